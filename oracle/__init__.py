@@ -1,0 +1,33 @@
+"""CPU FP64 oracle for the wall-corrected Rotne-Prager mobility and its consumers.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call, link
+or execute anything under ``oracle/``: only ``tests/``, the smoke check and the
+CPU-baseline leg of the benchmark use it.  It shares no code with the HIP
+library (no kernels, headers, helpers, tables or constant generators); the
+only common module is ``paper_1612_00474_amd.workloads``, which draws the
+seeded random inputs and holds none of the method's arithmetic.
+
+The oracle is written to be checked by eye against the paper (Balboa Usabiaga,
+Delmotte, Donev, "Brownian dynamics of confined suspensions of active
+microrollers", J. Chem. Phys. 146, 134104 (2017), arXiv:1612.00474):
+
+* ``green``       Blake's image solution for a Stokeslet above a no-slip wall
+                  (Sec. II.B, the Green's function entering eq. mobilityDifferential).
+* ``faxen``       The Faxen operators of eqs. mobilityDifferential and
+                  mobilityDifferentialTR applied symbolically (sympy) to the image part.
+* ``rpy``         Unbounded RPY translation-translation and translation-rotation
+                  tensors, including the overlapping-sphere forms (eq. mobilityOverlap).
+* ``mobility``    Wall regularisation M = B M~ B (App. A, eq. effMob), dense assembly,
+                  matrix-free and row-sampled products U = M F + M_C T.
+* ``lanczos``     Krylov/Lanczos approximation of M^{1/2} W with the stopping rule of
+                  Sec. II.C, and the dense symmetric square root.
+* ``stochastic``  Centred random finite difference (Sec. II.A) and the analytic
+                  divergence of M it estimates.
+* ``forces``      Soft steric potential (Sec. III, eq. soft_potential) plus gravity.
+* ``integrator``  Euler-Maruyama (eq. EM) and stochastic Adams-Bashforth (eq. AB) steps.
+* ``philox``      Philox4x64-10 counter-based generator (Salmon et al., SC'11) and the
+                  Box-Muller transform, for checking device-drawn noise.
+
+Every function is FP64.  Parity status of each function is listed in the module
+headers ("pinned by" lines name the independent checks in ``tests/``).
+"""

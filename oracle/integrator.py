@@ -1,0 +1,70 @@
+"""One Brownian dynamics time step: Euler-Maruyama or stochastic Adams-Bashforth.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Sec. II.A of the paper.  With u^n = M^n F^n + M_C^n T (deterministic velocity
+including the active torque term of Sec. III), g^n ~ M^{n 1/2} W^n (Lanczos,
+Sec. II.C) and D^n the centred RFD with W~^n:
+
+    EM  (eq. EM):  q^{n+1} = q^n + dt u^n + sqrt(2 kT dt) g^n + dt D^n
+    SAB (eq. AB):  q^{n+1} = q^n + dt (3/2 u^n - 1/2 u^{n-1}) + sqrt(2 kT dt) g^n + dt D^n
+
+The first SAB step has no u^{-1}; it takes u^{-1} = u^0, i.e. an EM step
+(reading: the paper does not say how the multistep scheme is started).
+u^n is returned so the caller can keep it for the next step.
+
+Pinned by (tests/test_oracle_integrator.py): with kT = 0 SAB is the
+two-step Adams-Bashforth method (second-order convergence on a deterministic
+two-sphere trajectory against a tight ODE solve) and EM is forward Euler
+(first order).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import forces as forces_mod
+from . import lanczos, mobility, stochastic
+
+
+def step(pos, u_prev, w, w_tilde, *, dt, delta, lanczos_tol, lanczos_max_iter=64,
+         scheme="sab", f_grav_z=-1.0, torque=(0.0, 1.0, 0.0), u0=1.0, b=0.1,
+         a=1.0, eta=1.0, kT=1.0, dense=None):
+    """Advance ``pos`` by one step.  Returns (new_pos, u_now, lanczos_iterations, eps, status).
+
+    ``u_prev``: previous deterministic velocity or None (first step).  ``w``,
+    ``w_tilde``: (n, 3) normal variates.  ``dense``: use dense matrices (default
+    for n <= 1500).
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    n = len(pos)
+    if dense is None:
+        dense = n <= 1500
+    F = forces_mod.forces(pos, a, u0, b, f_grav_z)
+    T = np.tile(np.asarray(torque, dtype=np.float64), (n, 1))
+    if dense:
+        M, MC = mobility.dense(pos, a, eta)
+        u = (M @ F.ravel() + MC @ T.ravel()).reshape(n, 3)
+        apply_m = lambda v: M @ v
+    else:
+        u = mobility.matvec(pos, F, T, a, eta)
+        apply_m = lambda v: mobility.matvec(pos, v.reshape(n, 3), None, a, eta).ravel()
+    g, iters, eps, status = lanczos.lanczos_sqrt(apply_m, np.asarray(w).ravel(),
+                                                 lanczos_tol, lanczos_max_iter)
+    drift = stochastic.rfd(pos, w_tilde, delta, a, eta, kT)
+    if scheme == "em" or u_prev is None:
+        det = u
+    else:
+        det = 1.5 * u - 0.5 * np.asarray(u_prev)
+    new = pos + dt * det + math.sqrt(2.0 * kT * dt) * g.reshape(n, 3) + dt * drift
+    return new, u, iters, eps, status
+
+
+def combine(pos, u, u_prev, g, drift, *, dt, kT=1.0, scheme="sab"):
+    """The update formula alone (eq. EM / eq. AB), given its ingredients."""
+    if scheme == "em" or u_prev is None:
+        det = u
+    else:
+        det = 1.5 * u - 0.5 * u_prev
+    return pos + dt * det + math.sqrt(2.0 * kT * dt) * g + dt * drift

@@ -1,0 +1,76 @@
+"""Krylov (Lanczos) approximation of M^{1/2} W and the dense symmetric square root.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Sec. II.C of the paper: m Lanczos iterations build the Krylov space
+K_m(M, W) = span{W, M W, ..., M^{m-1} W}; the noise is approximated in it as
+g_m = ||W|| V_m T_m^{1/2} e_1 (Ando et al.), with V_m the orthonormal Lanczos
+basis and T_m the tridiagonal projection of M.  The iteration stops when the
+relative change eps_m = ||g_m - g_{m-1}|| / ||g_{m-1}|| falls below the
+tolerance.  Readings where the paper is silent: the basis is fully
+re-orthogonalised against all previous vectors at every step (m is small);
+eps_m needs two iterates, so m >= 2 unless the Krylov space is invariant
+(beta_m = 0, where g_m is exact); the square root of T_m comes from its
+eigendecomposition T_m = Q Lambda Q^T.
+
+Pinned by (tests/test_oracle_lanczos.py): against the dense symmetric square
+root (``sqrtm_dense``) of the assembled mobility at tight tolerance; at m = 3N
+iterations the result is the exact M^{1/2} W; for one sphere the result equals
+the closed-form diagonal square root; the sample covariance of g over many W
+approaches M (fluctuation-dissipation, eq. BD).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+
+def lanczos_sqrt(apply_m, w, tol, max_iter=64, breakdown_rel=1e-14, notspd_rel=1e-12):
+    """Return (g, iterations, eps, status) with g ~ M^{1/2} w.
+
+    ``apply_m``: callable v -> M v on flat FP64 vectors.  ``status`` is "ok"
+    (eps < tol), "breakdown" (invariant Krylov space, g exact), "noconv"
+    (max_iter reached; g is the last iterate) or "notspd" (a Ritz value below
+    -notspd_rel * largest).
+    """
+    w = np.asarray(w, dtype=np.float64).ravel()
+    wn = np.linalg.norm(w)
+    if wn == 0.0:
+        return np.zeros_like(w), 0, 0.0, "ok"
+    V = [w / wn]
+    alphas, betas = [], []
+    g_prev = None
+    eps = np.inf
+    for m in range(1, max_iter + 1):
+        v = V[-1]
+        u = apply_m(v)
+        alpha = float(v @ u)
+        u = u - alpha * v
+        if m > 1:
+            u = u - betas[-1] * V[-2]
+        Vm = np.array(V)
+        u = u - Vm.T @ (Vm @ u)          # full re-orthogonalisation
+        beta = float(np.linalg.norm(u))
+        alphas.append(alpha)
+
+        lam, Q = scipy.linalg.eigh_tridiagonal(np.array(alphas), np.array(betas))
+        if lam.min() < -notspd_rel * max(lam.max(), 0.0):
+            return Vm.T @ (wn * Q @ (np.sqrt(np.maximum(lam, 0.0)) * Q[0])), m, eps, "notspd"
+        y = wn * Q @ (np.sqrt(np.maximum(lam, 0.0)) * Q[0])
+        g = Vm.T @ y
+        if g_prev is not None:
+            eps = float(np.linalg.norm(g - g_prev) / np.linalg.norm(g_prev))
+            if eps < tol:
+                return g, m, eps, "ok"
+        if beta <= breakdown_rel * max(abs(x) for x in alphas):
+            return g, m, (eps if g_prev is not None else 0.0), "breakdown"
+        betas.append(beta)
+        V.append(u / beta)
+        g_prev = g
+    return g, max_iter, eps, "noconv"
+
+
+def sqrtm_dense(M):
+    """Symmetric square root Q Lambda^{1/2} Q^T of a symmetric PSD matrix."""
+    lam, Q = np.linalg.eigh(np.asarray(M, dtype=np.float64))
+    return (Q * np.sqrt(np.maximum(lam, 0.0))) @ Q.T

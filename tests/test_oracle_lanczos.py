@@ -1,0 +1,75 @@
+"""Pins of the Lanczos square root (oracle/lanczos.py)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import faxen, lanczos, mobility
+from paper_1612_00474_amd import workloads as wl
+
+A = 1.0
+
+
+@pytest.fixture(scope="module")
+def c1():
+    inp = wl.make_inputs(wl.WORKLOADS["sheet256_rsa"], 0)
+    M, _ = mobility.dense(inp["pos"], A, 1.0)
+    return inp, M
+
+
+def test_matches_dense_symmetric_root(c1):
+    inp, M = c1
+    w = inp["w"].ravel()
+    g, m, eps, status = lanczos.lanczos_sqrt(lambda v: M @ v, w, 1e-6)
+    ref = lanczos.sqrtm_dense(M) @ w
+    assert status == "ok" and m < 30
+    assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= 1e-5
+    # fluctuation-dissipation in the mean-square: |g|^2 = w^T M w for the symmetric root
+    assert abs(g @ g - w @ M @ w) / (w @ M @ w) <= 1e-5
+
+
+def test_full_krylov_space_is_exact():
+    rng = np.random.default_rng(11)
+    pos = np.column_stack([rng.uniform(0, 5, 6), rng.uniform(0, 5, 6), rng.uniform(1.1, 3, 6)])
+    M, _ = mobility.dense(pos, A, 1.0)
+    w = rng.standard_normal(18)
+    g, m, eps, status = lanczos.lanczos_sqrt(lambda v: M @ v, w, 0.0, max_iter=18)
+    ref = lanczos.sqrtm_dense(M) @ w
+    assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= 1e-12
+
+
+def test_single_sphere_closed_form():
+    z = 1.8
+    pos = np.array([[0.3, 0.1, z]])
+    M, _ = mobility.dense(pos, A, 1.0)
+    h = z / A
+    mu_par = 1 - 9 / (16 * h) + 1 / (8 * h ** 3) - 1 / (16 * h ** 5)
+    mu_perp = 1 - 9 / (8 * h) + 1 / (2 * h ** 3) - 1 / (8 * h ** 5)
+    w = np.array([0.7, -1.2, 0.4])
+    ref = np.sqrt(np.array([mu_par, mu_par, mu_perp]) / (6 * math.pi * A)) * w
+    g, m, eps, status = lanczos.lanczos_sqrt(lambda v: M @ v, w, 1e-10)
+    assert status == "breakdown" and m <= 2
+    assert np.abs(g - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_covariance_is_mobility():
+    # fluctuation-dissipation (eq. BD): E[g g^T] = M
+    rng = np.random.default_rng(5)
+    pos = np.array([[0.0, 0.0, 1.5], [1.7, 0.6, 2.0]])
+    M, _ = mobility.dense(pos, A, 1.0)
+    K = 20000
+    G = np.empty((K, 6))
+    for k in range(K):
+        G[k] = lanczos.lanczos_sqrt(lambda v: M @ v, rng.standard_normal(6), 1e-12)[0]
+    C = G.T @ G / K
+    # standard error of each covariance entry ~ sqrt((M_ii M_jj + M_ij^2)/K)
+    se = np.sqrt((np.outer(np.diag(M), np.diag(M)) + M ** 2) / K)
+    assert np.all(np.abs(C - M) <= 5 * se)
+
+
+def test_non_convergence_and_status():
+    rng = np.random.default_rng(2)
+    pos = np.column_stack([rng.uniform(0, 8, 20), rng.uniform(0, 8, 20), rng.uniform(1.1, 3, 20)])
+    M, _ = mobility.dense(pos, A, 1.0)
+    g, m, eps, status = lanczos.lanczos_sqrt(lambda v: M @ v, rng.standard_normal(60), 1e-14, max_iter=3)
+    assert status == "noconv" and m == 3 and eps > 1e-14

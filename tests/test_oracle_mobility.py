@@ -1,0 +1,152 @@
+"""Pins of the wall-corrected mobility (oracle/faxen.py, oracle/mobility.py)."""
+import functools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from oracle import faxen, green, mobility
+from paper_1612_00474_amd import workloads as wl
+from tests.conftest import golden_rows
+from tests.quadrature import double_average
+
+A = 1.0
+
+
+@functools.lru_cache(maxsize=1)
+def _gimg_numeric():
+    X = sp.symbols("x1:4", real=True)
+    Y = sp.symbols("y1:4", real=True)
+    f = sp.lambdify((X, Y), list(green.blake_image(X, Y)), modules="numpy", cse=True)
+
+    def k(x, y):
+        vals = f(tuple(x), tuple(y))
+        return np.stack([np.broadcast_to(np.asarray(v, dtype=float), x.shape[1:]) for v in vals]).reshape(
+            (3, 3) + x.shape[1:])
+    return k
+
+
+PAIRS = [  # (q_i, q_j): clear of the wall; the third pair overlaps (|r| < 2a)
+    (np.array([0.0, 0.0, 1.5]), np.array([2.3, -1.1, 2.2])),
+    (np.array([0.4, 0.2, 3.0]), np.array([-5.0, 1.0, 1.2])),
+    (np.array([0.0, 0.0, 1.7]), np.array([0.9, 0.5, 2.4])),
+]
+
+
+@pytest.mark.parametrize("k", range(len(PAIRS)))
+def test_wall_tt_equals_double_surface_average_of_image(k):
+    qi, qj = PAIRS[k]
+    ref = double_average(_gimg_numeric(), qi, qj, A, 24)
+    got = faxen.wall_tt(qi[:, None], qj[:, None], A)[:, :, 0]
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", range(len(PAIRS)))
+def test_wall_tr_equals_double_surface_average_of_image(k):
+    qi, qj = PAIRS[k]
+    ref = double_average(_gimg_numeric(), qi, qj, A, 24, torque=True)
+    got = faxen.wall_tr(qi[:, None], qj[:, None], A)[:, :, 0]
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_self_mobility_matches_wall_series():
+    # mu(h) in units of 1/(6 pi eta a); compare Taylor coefficients in eps = a/h through eps^3
+    rows = golden_rows("wall_self_mobility_series.txt")
+    eps = sp.Symbol("eps", positive=True)
+    z = sp.Symbol("z", positive=True)
+    a = sp.Symbol("a", positive=True)
+    W = faxen.expressions()["Wself"]
+    for direction, idx in (("par", 0), ("perp", 8)):
+        mu = 1 + sp.Rational(3, 4) * a * W[idx]          # (6 pi eta a)/(8 pi eta) = 3a/4
+        mu = sp.simplify(mu.subs(z, a / eps))
+        ser = sp.series(mu, eps, 0, 4).removeO()
+        for d, order, num, den in rows:
+            if d == direction:
+                assert sp.Rational(int(num), int(den)) == ser.coeff(eps, int(order))
+
+
+def test_rolling_coupling_matches_far_field_result():
+    (num, den, power), = golden_rows("rolling_coupling.txt")
+    C = Fraction(int(num), int(den))
+    for h in (1.0, 1.7, 4.0):
+        Wtr = faxen.wall_tr_self(np.array(h), A)
+        Ux = Wtr[0, 1] / (8 * math.pi)          # velocity x per torque y (eta = 1)
+        expect = float(C) * (A / h) ** int(power) / (6 * math.pi * A ** 2)
+        assert abs(Ux - expect) <= 1e-14 * expect
+        assert abs(Wtr[1, 0] / (8 * math.pi) + expect) <= 1e-14 * expect
+        assert np.abs(Wtr[2]).max() == 0.0 and abs(Wtr[0, 0]) < 1e-18
+
+
+def test_pair_tends_to_self_block():
+    q = np.array([0.3, -0.2, 1.6])
+    self_tt = faxen.wall_tt_self(np.array(q[2]), A)
+    for e in (1e-4, 1e-6):
+        qj = q + e * np.array([0.6, 0.0, 0.8])
+        w = faxen.wall_tt(q[:, None], qj[:, None], A)[:, :, 0]
+        assert np.abs(w - self_tt).max() < 50 * e
+
+
+@pytest.fixture(scope="module")
+def c1_dense():
+    inp = wl.make_inputs(wl.WORKLOADS["sheet256_rsa"], 0)
+    return inp, mobility.dense(inp["pos"], A, 1.0)
+
+
+def test_dense_symmetric_positive_definite(c1_dense):
+    _, (M, _) = c1_dense
+    assert np.linalg.norm(M - M.T) / np.linalg.norm(M) <= 1e-14
+    assert np.linalg.eigvalsh(M).min() > 0.0
+
+
+def test_spd_with_overlaps_and_wall_overlaps():
+    rng = np.random.default_rng(7)
+    pos = np.column_stack([rng.uniform(0, 6, 60), rng.uniform(0, 6, 60), rng.uniform(0.2, 2.5, 60)])
+    pos[5, 2] = 0.0      # centre on the wall
+    pos[6, 2] = -0.3     # below the wall
+    pos[8, 2] = 1.5
+    pos[7] = pos[8] + np.array([0.0, 0.0, 1e-3])   # nearly coincident
+    pos[9, :2] = pos[10, :2]
+    pos[9, 2], pos[10, 2] = 0.4, 0.7              # coincident after clamping to z = a
+    M, MC = mobility.dense(pos, A, 1.0)
+    assert np.linalg.norm(M - M.T) / np.linalg.norm(M) <= 1e-14
+    lam = np.linalg.eigvalsh(M)
+    assert lam.min() > -1e-14 * lam.max()
+    for i in (5, 6):  # rows and columns vanish exactly on/below the wall (App. A)
+        assert np.all(M[3 * i:3 * i + 3] == 0.0) and np.all(M[:, 3 * i:3 * i + 3] == 0.0)
+        assert np.all(MC[3 * i:3 * i + 3] == 0.0) and np.all(MC[:, 3 * i:3 * i + 3] == 0.0)
+    # without exactly coincident (clamped) centres the nonzero part is positive definite
+    keep = np.ones(len(pos), bool)
+    keep[[5, 6, 9]] = False
+    Mk, _ = mobility.dense(pos[keep], A, 1.0)
+    lam = np.linalg.eigvalsh(Mk)
+    assert lam.min() > 1e-8 * lam.max()
+
+
+def test_wall_screening_decays_as_inverse_cube():
+    # Sec. II.C: pair interaction above a wall decays like 1/r^3 for r >> h
+    h = 1.5
+    rs = np.array([50.0, 100.0, 200.0, 400.0])
+    qi = np.tile(np.array([0.0, 0.0, h])[:, None], (1, rs.size))
+    qj = np.vstack([rs, np.zeros_like(rs), np.full_like(rs, h)])
+    tt, _ = mobility.pair_blocks(qi, qj, A, 1.0)
+    # the slowest component (parallel, along the separation) sets the decay; the
+    # transverse and normal components decay faster (1/r^5)
+    norm = np.sqrt((tt ** 2).sum(axis=(0, 1)))
+    assert abs(np.polyfit(np.log(rs), np.log(norm), 1)[0] + 3.0) < 0.02
+    assert abs(np.polyfit(np.log(rs), np.log(np.abs(tt[1, 1])), 1)[0] + 5.0) < 0.02
+    # without the wall part the decay is 1/r
+    from oracle import rpy
+    free = rpy.free_tt(qi - qj, A)[0, 0]
+    assert abs(np.polyfit(np.log(rs), np.log(free), 1)[0] + 1.0) < 0.01
+
+
+def test_matrix_free_equals_dense(c1_dense):
+    inp, (M, MC) = c1_dense
+    u_dense = (M @ inp["force"].ravel() + MC @ inp["torque"].ravel()).reshape(-1, 3)
+    u = mobility.matvec(inp["pos"], inp["force"], inp["torque"], A, 1.0)
+    assert np.abs(u - u_dense).max() <= 1e-15 * np.abs(u_dense).max() * 10
+    rows = np.array([0, 17, 255])
+    ur = mobility.matvec(inp["pos"], inp["force"], inp["torque"], A, 1.0, rows=rows, workers=2)
+    assert np.abs(ur - u_dense[rows]).max() <= 1e-14 * np.abs(u_dense).max()
