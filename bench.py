@@ -1,0 +1,168 @@
+"""Benchmark: Rotne-Prager-Blake Brownian dynamics steps at N = 65,536 on one MI355X.
+
+One "step" is one stochastic Adams-Bashforth step of the full hot path (paper, Sec. II):
+steric + gravity forces, the deterministic product u = M F + M_C T, the Lanczos Brownian
+increment M^{1/2} W (tolerance 1e-3), the centred random finite difference (two products)
+and the update.  Positions and noise are synthetic and resident on the GPU before the
+timed region starts (a uniform sheet at area fraction 0.4, heights in [1.1, 2.5]; noise
+drawn on the device from Philox).
+
+Prints ONE JSON line.  ``value`` is the pair interactions evaluated per second over the
+timed steps (every product counts N^2 ordered pairs); ``steps_per_s`` the step rate.
+The ``roofline`` object prices the dominant kernel (the float32 pair kernel) against the
+float32 vector-ALU peak; ``cpu_baseline`` times the FP64 CPU oracle on a sample of rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic operation count of one ordered pair in the pair kernel with a torque source:
+# the closed form in pair_tensor.h (FMA = 2, add/mul = 1, rsqrt = 1; Kahan compensation,
+# hi/lo reconstruction, index math and branches excluded).
+FLOPS_PER_PAIR_TORQUE = 190
+FLOPS_PER_PAIR_FORCE = 148
+PEAK_FP32_TFLOPS = 157.3     # 256 CU x 128 FP32 lanes (packed) x 2 x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sheet64k_mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=48)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, rows):
+    """Time the FP64 oracle's matrix-free product on `rows` target rows (all N sources)."""
+    import numpy as np
+    from oracle import mobility
+    from paper_1612_00474_amd import workloads as wl
+    inp = wl.make_inputs(w, 0)
+    sel = np.arange(rows)
+    mobility.matvec(inp["pos"][:64], inp["force"][:64], inp["torque"][:64])   # warm the tensors
+    t0 = time.perf_counter()
+    mobility.matvec(inp["pos"], inp["force"], inp["torque"], rows=sel)
+    dt = time.perf_counter() - t0
+    pairs = rows * w.n
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows} target rows x {w.n} sources of one product M F + M_C T "
+                      f"({pairs:.3e} pairs, {dt:.1f} s, single process)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
+              "this build has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1612_00474_amd import workloads as wl
+    w = wl.WORKLOADS[args.workload]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_rows)   # before the GPU is touched
+
+    import numpy as np
+    import torch
+    from paper_1612_00474_amd import Context, StepState
+
+    torch.cuda.init()
+    ctx = Context(0, a=w.a, eta=w.eta, kT=w.kT)
+    inp = wl.make_inputs(w, 0)
+    pos0 = torch.as_tensor(inp["pos"]).cuda()
+    F = torch.as_tensor(inp["force"]).cuda()
+    T = torch.as_tensor(inp["torque"]).cuda()
+    prec = w.precision
+    step_kw = dict(dt=w.dt, delta=w.delta, lanczos_tol=w.lanczos_tol, lanczos_max_iter=64,
+                   rfd_precision="fp64", f_grav_z=w.f_grav_z, torque=w.torque,
+                   steric_u0=w.steric_u0, steric_b=w.steric_b, seed=0, precision=prec)
+
+    # ---- kernel-only product throughput, mixed and float64 (pair kernel, HIP events) ----
+    def kernel_rate(precision, reps=3):
+        ctx.matvec(pos0, F, T, precision)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.timing_read()
+        for _ in range(reps):
+            ctx.matvec(pos0, F, T, precision)
+        ms, launches, pairs = ctx.timing_read()
+        ctx.timing(False)
+        return pairs / (ms * 1e-3), ms / launches
+
+    mixed_rate, mixed_ms = kernel_rate("mixed")
+    f64_rate, f64_ms = kernel_rate("fp64")
+
+    # ---- time steps ----------------------------------------------------------------------
+    state = StepState(pos0.clone())
+    iters = []
+    for _ in range(args.warmup):
+        iters.append(ctx.sab_step(state, **step_kw)[0])
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        iters.append(ctx.sab_step(state, **step_kw)[0])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_pair, launches, pairs = ctx.timing_read()
+    ctx.timing(False)
+    timed_iters = iters[args.warmup:]
+    n = w.n
+    products = sum(1 + m + 2 for m in timed_iters)
+    step_pairs = products * float(n) * n
+    value = step_pairs / elapsed
+
+    # dominant kernel: the float32 pair kernel of the timed steps (Lanczos products carry no
+    # torque; the deterministic product does); price its measured launches
+    flops = 0.0
+    for m in timed_iters:
+        flops += (FLOPS_PER_PAIR_TORQUE + m * FLOPS_PER_PAIR_FORCE + 2 * FLOPS_PER_PAIR_FORCE) * float(n) * n
+    achieved = flops / (ms_pair * 1e-3) / 1e12
+    line = {
+        "metric": "RPB matvec pair-interactions/s + BD steps/s at N=65,536, FP32-mixed vs FP64",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps_per_s": args.steps / elapsed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "area_fraction": 0.4, "z_range": [w.z_lo, w.z_hi],
+                   "scheme": "stochastic Adams-Bashforth", "dt": w.dt, "rfd_delta": w.delta,
+                   "lanczos_tol": w.lanczos_tol, "precision": prec, "rfd_precision": "fp64",
+                   "parallelism": "single GPU"},
+        "lanczos_iters": timed_iters,
+        "matvec_kernel_pairs_per_s": {"mixed": mixed_rate, "fp64": f64_rate,
+                                      "mixed_over_fp64": mixed_rate / f64_rate,
+                                      "ms_per_launch": {"mixed": mixed_ms, "fp64": f64_ms}},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "pair kernel (all products of the timed steps)",
+                     "kernel_ms_per_step": ms_pair / args.steps, "launches": launches},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * rpb.h -- C ABI of librpb: the wall-corrected Rotne-Prager ("Rotne-Prager-Blake")
+ * mobility of N equal spheres above a no-slip wall, and its three consumers, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Paper: F. Balboa Usabiaga, B. Delmotte, A. Donev, "Brownian dynamics of confined
+ * suspensions of active microrollers", J. Chem. Phys. 146, 134104 (2017), arXiv:1612.00474.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units are the caller's; reduced units a = eta = kT = 1 are typical.  The wall is
+ *    the plane z = 0 and the fluid fills z > 0.
+ *  - Every array argument is a DEVICE pointer to contiguous row-major [n][3] float64
+ *    (x, y, z per sphere), 8-byte aligned, owned by the caller.  The library never
+ *    frees or keeps them after the call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream).  Calls
+ *    that must read device scalars (Lanczos convergence, validation flags)
+ *    synchronise `stream` before returning; host out-parameters are valid on return.
+ *  - Return value: RPB_OK (0) or a negative rpb_status.  rpb_last_error() then holds
+ *    a message.  No C++ exception crosses this interface.
+ *  - n == 0 is a no-op that returns RPB_OK.  RPB_EINVAL for n < 0, a NULL required
+ *    pointer, a, eta or kT <= 0, an unknown precision, an output that overlaps an
+ *    input, or an argument outside the documented range.
+ *  - RPB_ENONFINITE when a position holds NaN or Inf (checked on the device before any
+ *    product is formed).
+ *  - One context per host thread; calls on one context must not overlap.  A context
+ *    owns its device workspace, which grows on demand (hipMalloc) and is released by
+ *    rpb_destroy().
+ *  - Results are deterministic: no floating-point atomics, fixed reduction orders.
+ */
+#ifndef RPB_H
+#define RPB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rpb_ctx rpb_ctx;     /* opaque: device, workspace, tuning table, timers */
+typedef void *rpb_stream_t;         /* a hipStream_t */
+
+typedef enum {
+  RPB_OK = 0,
+  RPB_EINVAL = -1,      /* invalid argument */
+  RPB_ENOMEM = -2,      /* device allocation failed */
+  RPB_EDEVICE = -3,     /* a HIP call failed (message in rpb_last_error) */
+  RPB_ENOCONV = -4,     /* Lanczos tolerance not reached within max_iter; output = last iterate */
+  RPB_ENOTSPD = -5,     /* a Ritz value of the Lanczos tridiagonal is negative */
+  RPB_ENONFINITE = -6   /* NaN or Inf in the positions */
+} rpb_status;
+
+typedef enum {
+  RPB_FP64 = 0,         /* pair terms and sums in float64 */
+  RPB_MIXED = 1         /* pair terms in float32 with compensated (Kahan) float32 sums per
+                           target, positions split into float32 hi/lo; vectors, Lanczos
+                           recurrence, eigensolve and norms stay float64 */
+} rpb_precision;
+
+typedef struct {
+  double a;             /* sphere radius (> 0) */
+  double eta;           /* fluid viscosity (> 0) */
+  double kT;            /* thermal energy k_B T (> 0) */
+  int precision;        /* rpb_precision */
+} rpb_params;
+
+/* Context ---------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+int rpb_create(int hip_device, rpb_ctx **out);
+/* Release the context and its device workspace (NULL is ignored). */
+void rpb_destroy(rpb_ctx *ctx);
+/* Message of the last failure on this context ("" if none).  Valid until the next call. */
+const char *rpb_last_error(const rpb_ctx *ctx);
+/* Library version string. */
+const char *rpb_version(void);
+
+/* Mobility product --------------------------------------------------------------------
+ *
+ * U = M F + M_C T for spheres at `pos`, with
+ *   M    the translation mobility (paper, Sec. II.B, eq. mobilityDifferential for separated
+ *        spheres, eq. mobilityOverlap for overlapping spheres: unbounded RPY part plus the
+ *        Faxen-applied image part of Blake's wall Green's function; self block included),
+ *   M_C  the translation-rotation mobility (Sec. III, eq. mobilityDifferentialTR),
+ * both regularised as M = B M~ B (App. A, eq. effMob): B_ii = H0(z_i/a) with
+ * H0(x) = clamp(x, 0, 1), and M~ evaluated with heights clamped to max(z, a).  The same
+ * B is applied to M_C, so spheres at or below the wall neither move nor move others.
+ * Direct O(N^2) summation over all ordered pairs (Sec. II.B).
+ *
+ * force, torque: [n][3] device arrays, either may be NULL (treated as zero; not both).
+ * vel_out: [n][3] device array, overwritten; must not overlap pos, force or torque.
+ */
+int rpb_mobility_matvec(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                        const double *force, const double *torque, double *vel_out,
+                        rpb_stream_t stream);
+
+/* Rows [row_begin, row_end) of the same product (all n spheres are sources).  vel_out
+ * then holds (row_end - row_begin) rows.  Concatenating the results of a partition of
+ * [0, n) gives rpb_mobility_matvec exactly (the per-GPU share of a row-sharded product). */
+int rpb_mobility_matvec_rows(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                             const double *force, const double *torque, int64_t row_begin,
+                             int64_t row_end, double *vel_out, rpb_stream_t stream);
+
+/* Brownian increment ------------------------------------------------------------------
+ *
+ * out ~ M^{1/2} w by the Krylov/Lanczos method of Ando et al. (paper, Sec. II.C): m Lanczos
+ * steps on K_m(M, w) with full re-orthogonalisation, T_m = Q L Q^T by an implicit-QL
+ * eigensolve on the device, g_m = |w| V_m Q L^{1/2} Q^T e_1.  Stops at the first m >= 2
+ * with eps_m = |g_m - g_{m-1}| / |g_{m-1}| < tol (evaluated in the orthonormal basis), or
+ * when the Krylov space is invariant (exact result, RPB_OK), or at max_iter
+ * (RPB_ENOCONV, out = g_max_iter).  Only M (not M_C) enters.
+ *
+ * w, out: [n][3] device arrays (out must not overlap pos or w).  tol > 0 (use a tiny tol
+ * with max_iter = m for a fixed number of steps).  1 <= max_iter <= 128.
+ * iters_out, eps_out: host pointers (may be NULL) for m and eps_m (0 when m = 1).
+ */
+int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                       const double *w, double tol, int max_iter, double *out,
+                       int *iters_out, double *eps_out, rpb_stream_t stream);
+
+/* Stochastic drift --------------------------------------------------------------------
+ *
+ * Centred random finite difference (paper, Sec. II.A, last term of eq. EM / eq. AB):
+ *   drift = (kT/delta) [ M(q + delta/2 w~) w~ - M(q - delta/2 w~) w~ ],
+ * equal in expectation to kT div_q . M up to O(delta^2).  delta > 0.
+ * The two products use `rfd_precision` (RPB_FP64 or RPB_MIXED); in float32 the
+ * difference of two O(1) products is divided by delta, so float64 is the default
+ * choice for small delta.
+ */
+int rfd_drift(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+              const double *w_tilde, double delta, int rfd_precision, double *drift_out,
+              rpb_stream_t stream);
+
+/* Forces --------------------------------------------------------------------------------
+ *
+ * Soft steric repulsion of the paper (Sec. III, eq. soft_potential) between all pairs
+ * (d = 2a, r = centre distance) and with the wall (d = a, r = z), plus gravity f_grav_z
+ * along z:  f(r) = U0/b for r < d, (U0/b) exp(-(r-d)/b) for r >= d, repulsive.  Pairs with
+ * r - d > 40 b are skipped (their force is below 4.3e-18 U0/b).  u0 >= 0, b > 0.
+ */
+int rpb_forces(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+               double f_grav_z, double u0, double b, double *force_out, rpb_stream_t stream);
+
+/* Counter-based normal variates: Philox4x64-10 (Salmon et al., SC'11) with key
+ * (seed, stream_id) and counter (block, step, 0, 0); block k gives variates 4k..4k+3;
+ * uniforms ((x >> 12) + 1/2) 2^-52, normals by Box-Muller on (u0,u1) and (u2,u3).
+ * out: `count` float64 values on the device. */
+int rpb_normals(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id,
+                uint64_t step, double *out, rpb_stream_t stream);
+
+/* Time step -------------------------------------------------------------------------------
+ *
+ * One step of eq. BD with the active torque term of Sec. III:
+ *   u^n     = M^n F^n + M_C^n T                         (forces from rpb_forces, T constant)
+ *   SAB (eq. AB): q^{n+1} = q^n + dt (3/2 u^n - 1/2 u^{n-1}) + sqrt(2 kT dt) g^n + dt D^n
+ *   EM  (eq. EM): q^{n+1} = q^n + dt u^n + sqrt(2 kT dt) g^n + dt D^n
+ * with g^n = lanczos_sqrt_apply(W^n) and D^n = rfd_drift(W~^n).  The first SAB step
+ * (have_prev == 0) is an EM step.  On return state->pos holds q^{n+1}, state->u_prev
+ * holds u^n, state->step is incremented and state->have_prev = 1.
+ */
+typedef struct {
+  double dt;            /* time step (> 0) */
+  double delta;         /* RFD length (> 0) */
+  double lanczos_tol;   /* Lanczos relative tolerance (> 0) */
+  int lanczos_max_iter; /* 1..128 */
+  int scheme;           /* 0 = stochastic Adams-Bashforth, 1 = Euler-Maruyama */
+  int rfd_precision;    /* rpb_precision of the two RFD products */
+  double f_grav_z;      /* gravity force on each sphere along z */
+  double torque[3];     /* constant torque on every sphere */
+  double steric_u0;     /* U0 of eq. soft_potential */
+  double steric_b;      /* b of eq. soft_potential */
+  uint64_t seed;        /* noise seed: W = normals(seed, 0, step), W~ = normals(seed, 1, step) */
+} rpb_sab_config;
+
+typedef struct {
+  int64_t n;            /* number of spheres */
+  double *pos;          /* [n][3] device, in/out */
+  double *u_prev;       /* [n][3] device, caller-owned storage for u^{n-1} (in/out) */
+  int64_t step;         /* step counter n (in/out) */
+  int have_prev;        /* 1 when u_prev holds u^{n-1} (in/out) */
+} rpb_sab_state;
+
+/* w, w_tilde: optional [n][3] device arrays of the normals W^n, W~^n; NULL draws them
+ * with rpb_normals(seed, 0 or 1, step).  iters_out / eps_out: optional host pointers for
+ * the Lanczos iteration count and last eps.  RPB_ENOCONV from Lanczos does not stop the
+ * step (the last iterate is used) but is returned after the update. */
+int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cfg, rpb_sab_state *state,
+             const double *w, const double *w_tilde, int *iters_out, double *eps_out,
+             rpb_stream_t stream);
+
+/* Timing ------------------------------------------------------------------------------------
+ *
+ * When enabled, the library brackets every launch of the O(N^2) pair kernel with HIP
+ * events on the stream it is launched on.  rpb_timing_read() synchronises, returns the
+ * summed kernel time in milliseconds, the number of launches and the number of ordered
+ * pair interactions they evaluated, and clears the record. */
+int rpb_timing_enable(rpb_ctx *ctx, int enable);
+int rpb_timing_read(rpb_ctx *ctx, double *ms_out, int64_t *launches_out, double *pairs_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPB_H */

@@ -1,0 +1,276 @@
+"""ctypes binding of librpb (include/rpb.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor dtypes,
+devices and shapes, passes raw device pointers and torch's current stream, and
+turns status codes into exceptions.  There is no CPU fallback: if the library
+is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librpb.so")
+
+RPB_OK, RPB_EINVAL, RPB_ENOMEM, RPB_EDEVICE, RPB_ENOCONV, RPB_ENOTSPD, RPB_ENONFINITE = (
+    0, -1, -2, -3, -4, -5, -6)
+STATUS_NAMES = {0: "RPB_OK", -1: "RPB_EINVAL", -2: "RPB_ENOMEM", -3: "RPB_EDEVICE",
+                -4: "RPB_ENOCONV", -5: "RPB_ENOTSPD", -6: "RPB_ENONFINITE"}
+RPB_FP64, RPB_MIXED = 0, 1
+PRECISIONS = {"fp64": RPB_FP64, "mixed": RPB_MIXED}
+
+# Every symbol include/rpb.h declares.
+EXPORTS = (
+    "rpb_create", "rpb_destroy", "rpb_last_error", "rpb_version",
+    "rpb_mobility_matvec", "rpb_mobility_matvec_rows", "lanczos_sqrt_apply", "rfd_drift",
+    "rpb_forces", "rpb_normals", "sab_step", "rpb_timing_enable", "rpb_timing_read",
+)
+
+
+class RpbParams(C.Structure):
+    _fields_ = [("a", C.c_double), ("eta", C.c_double), ("kT", C.c_double), ("precision", C.c_int)]
+
+
+class RpbSabConfig(C.Structure):
+    _fields_ = [("dt", C.c_double), ("delta", C.c_double), ("lanczos_tol", C.c_double),
+                ("lanczos_max_iter", C.c_int), ("scheme", C.c_int), ("rfd_precision", C.c_int),
+                ("f_grav_z", C.c_double), ("torque", C.c_double * 3), ("steric_u0", C.c_double),
+                ("steric_b", C.c_double), ("seed", C.c_uint64)]
+
+
+class RpbSabState(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("u_prev", C.c_void_p),
+                ("step", C.c_int64), ("have_prev", C.c_int)]
+
+
+class RpbError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librpb.so (raises if it is missing: build it with paper_1612_00474_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found; build it with `python -m paper_1612_00474_amd.build`")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    D = C.c_double
+    I64 = C.c_int64
+    pp = C.POINTER(RpbParams)
+    sig = {
+        "rpb_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
+        "rpb_destroy": (None, [P]),
+        "rpb_last_error": (C.c_char_p, [P]),
+        "rpb_version": (C.c_char_p, []),
+        "rpb_mobility_matvec": (C.c_int, [P, pp, I64, P, P, P, P, P]),
+        "rpb_mobility_matvec_rows": (C.c_int, [P, pp, I64, P, P, P, I64, I64, P, P]),
+        "lanczos_sqrt_apply": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, C.POINTER(C.c_int),
+                                         C.POINTER(D), P]),
+        "rfd_drift": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, P]),
+        "rpb_forces": (C.c_int, [P, pp, I64, P, D, D, D, P, P]),
+        "rpb_normals": (C.c_int, [P, I64, C.c_uint64, C.c_uint64, C.c_uint64, P, P]),
+        "sab_step": (C.c_int, [P, pp, C.POINTER(RpbSabConfig), C.POINTER(RpbSabState), P, P,
+                               C.POINTER(C.c_int), C.POINTER(D), P]),
+        "rpb_timing_enable": (C.c_int, [P, C.c_int]),
+        "rpb_timing_read": (C.c_int, [P, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _vec3(t, name, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dim() != 2 or t.shape[1] != 3:
+        raise ValueError(f"{name} must have shape (n, 3), got {tuple(t.shape)}")
+    if n is not None and t.shape[0] != n:
+        raise ValueError(f"{name} has {t.shape[0]} rows, expected {n}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One librpb context on one device (not thread-safe; one per host thread)."""
+
+    def __init__(self, device: int = 0, a: float = 1.0, eta: float = 1.0, kT: float = 1.0):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.rpb_create(device, C.byref(h))
+        if st != RPB_OK:
+            raise RpbError(st, f"rpb_create({device}) failed")
+        self.h = h
+        self.device = device
+        self.a, self.eta, self.kT = a, eta, kT
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rpb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self, precision="fp64"):
+        return RpbParams(self.a, self.eta, self.kT, PRECISIONS[precision] if isinstance(precision, str)
+                         else int(precision))
+
+    def _check(self, st, ok=(RPB_OK,)):
+        if st not in ok:
+            raise RpbError(st, self.lib.rpb_last_error(self.h).decode())
+        return st
+
+    def last_error(self) -> str:
+        return self.lib.rpb_last_error(self.h).decode()
+
+    # -- products ------------------------------------------------------------------------
+    def matvec(self, pos, force=None, torque=None, precision="fp64", out=None, rows=None):
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        if force is not None:
+            _vec3(force, "force", n)
+        if torque is not None:
+            _vec3(torque, "torque", n)
+        p = self.params(precision)
+        if rows is None:
+            if out is None:
+                out = torch.empty_like(pos)
+            _vec3(out, "out", n)
+            st = self.lib.rpb_mobility_matvec(self.h, C.byref(p), n, _ptr(pos), _ptr(force),
+                                              _ptr(torque), _ptr(out), _stream())
+        else:
+            r0, r1 = rows
+            if out is None:
+                out = torch.empty((r1 - r0, 3), dtype=torch.float64, device=pos.device)
+            _vec3(out, "out", r1 - r0)
+            st = self.lib.rpb_mobility_matvec_rows(self.h, C.byref(p), n, _ptr(pos), _ptr(force),
+                                                   _ptr(torque), r0, r1, _ptr(out), _stream())
+        self._check(st)
+        return out
+
+    def lanczos(self, pos, w, tol, max_iter=64, precision="fp64", out=None, allow_noconv=False):
+        """Returns (g, iterations, eps, status)."""
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        _vec3(w, "w", n)
+        if out is None:
+            out = torch.empty_like(pos)
+        p = self.params(precision)
+        it = C.c_int(0)
+        eps = C.c_double(0.0)
+        st = self.lib.lanczos_sqrt_apply(self.h, C.byref(p), n, _ptr(pos), _ptr(w), float(tol),
+                                         int(max_iter), _ptr(out), C.byref(it), C.byref(eps),
+                                         _stream())
+        self._check(st, (RPB_OK, RPB_ENOCONV) if allow_noconv else (RPB_OK,))
+        return out, it.value, eps.value, st
+
+    def rfd(self, pos, w_tilde, delta, precision="fp64", rfd_precision="fp64", out=None):
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        _vec3(w_tilde, "w_tilde", n)
+        if out is None:
+            out = torch.empty_like(pos)
+        p = self.params(precision)
+        st = self.lib.rfd_drift(self.h, C.byref(p), n, _ptr(pos), _ptr(w_tilde), float(delta),
+                                PRECISIONS[rfd_precision], _ptr(out), _stream())
+        self._check(st)
+        return out
+
+    def forces(self, pos, f_grav_z=-1.0, u0=1.0, b=0.1, out=None):
+        import torch
+        pos = _vec3(pos, "pos")
+        if out is None:
+            out = torch.empty_like(pos)
+        p = self.params("fp64")
+        st = self.lib.rpb_forces(self.h, C.byref(p), pos.shape[0], _ptr(pos), float(f_grav_z),
+                                 float(u0), float(b), _ptr(out), _stream())
+        self._check(st)
+        return out
+
+    def normals(self, count, seed, stream_id, step, device="cuda"):
+        import torch
+        out = torch.empty(count, dtype=torch.float64, device=device)
+        st = self.lib.rpb_normals(self.h, int(count), int(seed), int(stream_id), int(step),
+                                  _ptr(out), _stream())
+        self._check(st)
+        return out
+
+    # -- time step -----------------------------------------------------------------------
+    def sab_step(self, state, *, dt, delta, lanczos_tol, lanczos_max_iter=64, scheme="sab",
+                 rfd_precision="fp64", f_grav_z=-1.0, torque=(0.0, 1.0, 0.0), steric_u0=1.0,
+                 steric_b=0.1, seed=0, precision="fp64", w=None, w_tilde=None):
+        """Advance ``state`` (a StepState) by one step; returns (iterations, eps, status)."""
+        cfg = RpbSabConfig(dt, delta, lanczos_tol, lanczos_max_iter,
+                           0 if scheme == "sab" else 1, PRECISIONS[rfd_precision], f_grav_z,
+                           (C.c_double * 3)(*torque), steric_u0, steric_b, seed)
+        n = state.pos.shape[0]
+        if w is not None:
+            _vec3(w, "w", n)
+        if w_tilde is not None:
+            _vec3(w_tilde, "w_tilde", n)
+        s = RpbSabState(n, state.pos.data_ptr(), state.u_prev.data_ptr(), state.step,
+                        int(state.have_prev))
+        p = self.params(precision)
+        it = C.c_int(0)
+        eps = C.c_double(0.0)
+        st = self.lib.sab_step(self.h, C.byref(p), C.byref(cfg), C.byref(s), _ptr(w), _ptr(w_tilde),
+                               C.byref(it), C.byref(eps), _stream())
+        self._check(st, (RPB_OK, RPB_ENOCONV))
+        state.step = s.step
+        state.have_prev = bool(s.have_prev)
+        return it.value, eps.value, st
+
+    # -- timing --------------------------------------------------------------------------
+    def timing(self, enable: bool):
+        self._check(self.lib.rpb_timing_enable(self.h, int(enable)))
+
+    def timing_read(self):
+        """(milliseconds, launches, pair interactions) of the pair kernel since the last read."""
+        ms = C.c_double(0.0)
+        k = C.c_int64(0)
+        pairs = C.c_double(0.0)
+        self._check(self.lib.rpb_timing_read(self.h, C.byref(ms), C.byref(k), C.byref(pairs)))
+        return ms.value, k.value, pairs.value
+
+
+class StepState:
+    """Positions and the stored velocity u^{n-1} of a time-stepped suspension (device tensors)."""
+
+    def __init__(self, pos):
+        import torch
+        self.pos = _vec3(pos, "pos")
+        self.u_prev = torch.zeros_like(pos)
+        self.step = 0
+        self.have_prev = False

@@ -1,0 +1,165 @@
+// Context, workspace, error reporting and timing for librpb.
+#include <cstdarg>
+#include <cstring>
+
+#include "rpb_internal.h"
+
+namespace rpb {
+
+int fail(rpb_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+void *workspace(rpb_ctx *ctx, Slot slot, size_t bytes, int *status) {
+  DevBuf &b = ctx->ws[slot];
+  *status = RPB_OK;
+  if (bytes <= b.bytes && b.ptr) return b.ptr;
+  // growth: earlier work on any stream may still use the old buffer
+  if (b.ptr) {
+    if (hipDeviceSynchronize() != hipSuccess || hipFree(b.ptr) != hipSuccess) {
+      *status = fail(ctx, RPB_EDEVICE, "workspace release failed");
+      return nullptr;
+    }
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes < 4096 ? 4096 : bytes;
+  want = (want + 4095) & ~size_t(4095);
+  if (hipMalloc(&b.ptr, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.ptr = nullptr;
+    *status = fail(ctx, RPB_ENOMEM, "hipMalloc of %zu bytes failed (workspace slot %d)", want,
+                   int(slot));
+    return nullptr;
+  }
+  b.bytes = want;
+  return b.ptr;
+}
+
+int check_params(rpb_ctx *ctx, const rpb_params *p) {
+  if (!ctx) return RPB_EINVAL;
+  if (!p) return fail(ctx, RPB_EINVAL, "params is NULL");
+  if (!(p->a > 0.0) || !(p->eta > 0.0) || !(p->kT > 0.0))
+    return fail(ctx, RPB_EINVAL, "a, eta and kT must be positive (got %g, %g, %g)", p->a, p->eta,
+                p->kT);
+  if (p->precision != RPB_FP64 && p->precision != RPB_MIXED)
+    return fail(ctx, RPB_EINVAL, "unknown precision %d", p->precision);
+  return RPB_OK;
+}
+
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
+  if (!a || !b) return false;
+  const char *pa = static_cast<const char *>(a);
+  const char *pb = static_cast<const char *>(b);
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+int timing_begin(rpb_ctx *ctx, hipStream_t stream, hipEvent_t *start) {
+  *start = nullptr;
+  if (!ctx->timing) return RPB_OK;
+  hipEvent_t e;
+  if (!ctx->ev_pool.empty()) {
+    e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+  } else {
+    RPB_HIP(ctx, hipEventCreate(&e));
+  }
+  RPB_HIP(ctx, hipEventRecord(e, stream));
+  *start = e;
+  return RPB_OK;
+}
+
+int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs) {
+  if (!ctx->timing || !start) return RPB_OK;
+  hipEvent_t e;
+  if (!ctx->ev_pool.empty()) {
+    e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+  } else {
+    RPB_HIP(ctx, hipEventCreate(&e));
+  }
+  RPB_HIP(ctx, hipEventRecord(e, stream));
+  ctx->ev_start.push_back(start);
+  ctx->ev_stop.push_back(e);
+  ctx->ev_pairs.push_back(pairs);
+  return RPB_OK;
+}
+
+}  // namespace rpb
+
+using namespace rpb;
+
+extern "C" {
+
+const char *rpb_version(void) { return "librpb 0.1 (gfx950)"; }
+
+int rpb_create(int hip_device, rpb_ctx **out) {
+  if (!out) return RPB_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return RPB_EDEVICE;
+  if (hipSetDevice(hip_device) != hipSuccess) return RPB_EDEVICE;
+  rpb_ctx *c = new (std::nothrow) rpb_ctx();
+  if (!c) return RPB_ENOMEM;
+  c->device = hip_device;
+  if (hipHostMalloc(&c->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RPB_ENOMEM;
+  }
+  *out = c;
+  return RPB_OK;
+}
+
+void rpb_destroy(rpb_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto &b : ctx->ws)
+    if (b.ptr) (void)hipFree(b.ptr);
+  for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
+  for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  delete ctx;
+}
+
+const char *rpb_last_error(const rpb_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int rpb_timing_enable(rpb_ctx *ctx, int enable) {
+  if (!ctx) return RPB_EINVAL;
+  ctx->timing = enable != 0;
+  return RPB_OK;
+}
+
+int rpb_timing_read(rpb_ctx *ctx, double *ms_out, int64_t *launches_out, double *pairs_out) {
+  if (!ctx) return RPB_EINVAL;
+  double ms = 0.0, pairs = 0.0;
+  const size_t k = ctx->ev_start.size();
+  for (size_t i = 0; i < k; ++i) {
+    RPB_HIP(ctx, hipEventSynchronize(ctx->ev_stop[i]));
+    float t = 0.0f;
+    RPB_HIP(ctx, hipEventElapsedTime(&t, ctx->ev_start[i], ctx->ev_stop[i]));
+    ms += t;
+    pairs += ctx->ev_pairs[i];
+    ctx->ev_pool.push_back(ctx->ev_start[i]);
+    ctx->ev_pool.push_back(ctx->ev_stop[i]);
+  }
+  ctx->ev_start.clear();
+  ctx->ev_stop.clear();
+  ctx->ev_pairs.clear();
+  if (ms_out) *ms_out = ms;
+  if (launches_out) *launches_out = int64_t(k);
+  if (pairs_out) *pairs_out = pairs;
+  return RPB_OK;
+}
+
+}  // extern "C"

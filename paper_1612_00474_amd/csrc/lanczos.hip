@@ -1,0 +1,399 @@
+// Krylov/Lanczos approximation of M^{1/2} w (paper, Sec. II.C, method of Ando et al.).
+//
+// Everything but the O(N^2) products is float64 and O(N m):
+//   v_1 = w/|w|;  for m = 1, 2, ...:
+//     u = M v_m;  alpha_m = v_m . u;  u -= alpha_m v_m + beta_{m-1} v_{m-1};
+//     u -= V_m (V_m^T u)                       (full re-orthogonalisation)
+//     beta_m = |u|
+//     T_m = Q L Q^T (implicit QL, one wavefront), y_m = |w| Q L^{1/2} Q^T e_1
+//     eps_m = |y_m - (y_{m-1}, 0)| / |y_{m-1}|  (= |g_m - g_{m-1}|/|g_{m-1}| for orthonormal V)
+//     stop if eps_m < tol (m >= 2), or beta_m ~ 0 (invariant Krylov space, exact result)
+//     v_{m+1} = u / beta_m
+//   g = V_m y_m.
+// Reductions use a fixed number of blocks and a fixed tree, so results are bitwise
+// reproducible.  The host reads a 32-byte status record once per iteration.
+#include <algorithm>
+#include <cmath>
+
+#include "rpb_internal.h"
+
+namespace rpb {
+
+namespace {
+
+constexpr int kMaxKrylov = 64;      // largest m (the eigensolve keeps T_m in one wavefront)
+constexpr int kRedBlocks = 256;     // partial sums per reduction
+constexpr int kThreads = 256;
+
+// Device-side Lanczos scalars (lives at the start of the WS_SMALL slot).
+struct LzState {
+  double alpha[kMaxKrylov];
+  double beta[kMaxKrylov];
+  double y[kMaxKrylov];
+  double yprev[kMaxKrylov];
+  double h[kMaxKrylov];
+  double wnorm;
+  double scratch;
+  // status (read by the host every iteration)
+  double eps;
+  int m;
+  int reason;     // 0 running, 1 converged, 2 breakdown, 3 not SPD, 4 eigensolve failed
+};
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kThreads) void dot_partial(int64_t m, const double *__restrict__ a,
+                                                        const double *__restrict__ b,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kThreads)
+    acc += a[i] * b[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out = sum(part) (mode 0) or sqrt(sum(part)) (mode 1)
+__global__ __launch_bounds__(kThreads) void dot_finish(const double *__restrict__ part, int np,
+                                                       double *__restrict__ out, int mode) {
+  __shared__ double sh[kThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = mode == 1 ? sqrt(s) : s;
+}
+
+__global__ void scale_by_inverse(int64_t m, const double *__restrict__ x,
+                                 const double *__restrict__ d, double *__restrict__ y,
+                                 const LzState *__restrict__ st) {
+  if (st && st->reason != 0) return;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double s = d[0];
+  y[i] = s > 0.0 ? x[i] / s : 0.0;
+}
+
+// u -= alpha v + beta vprev
+__global__ void three_term(int64_t m, double *__restrict__ u, const double *__restrict__ v,
+                           const double *__restrict__ vprev, const double *__restrict__ alpha,
+                           const double *__restrict__ beta) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double x = u[i] - alpha[0] * v[i];
+  if (vprev) x -= beta[0] * vprev[i];
+  u[i] = x;
+}
+
+// part[k * gridDim.x + b] = partial dot of V_k and u over block b's share
+__global__ __launch_bounds__(kThreads) void reorth_dots(int64_t m, const double *__restrict__ V,
+                                                        const double *__restrict__ u,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int k = blockIdx.y;
+  const double *vk = V + int64_t(k) * m;
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kThreads)
+    acc += vk[i] * u[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[int64_t(k) * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void reorth_finish(int nvec, int np,
+                                                          const double *__restrict__ part,
+                                                          double *__restrict__ h) {
+  __shared__ double sh[kThreads];
+  for (int k = 0; k < nvec; ++k) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += kThreads) acc += part[int64_t(k) * np + i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) h[k] = s;
+  }
+}
+
+__global__ void reorth_update(int64_t m, int nvec, const double *__restrict__ V,
+                              const double *__restrict__ h, double *__restrict__ u) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double proj = 0.0;
+  for (int k = 0; k < nvec; ++k) proj += h[k] * V[int64_t(k) * m + i];
+  u[i] -= proj;
+}
+
+// out = V y (first nvec rows of V)
+__global__ void basis_combine(int64_t m, int nvec, const double *__restrict__ V,
+                              const double *__restrict__ y, double *__restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double acc = 0.0;
+  for (int k = 0; k < nvec; ++k) acc += y[k] * V[int64_t(k) * m + i];
+  out[i] = acc;
+}
+
+// Eigendecomposition of T_m by implicit QL with Wilkinson-type shifts (Bowdler, Martin,
+// Reinsch, Wilkinson 1968), then y_m = |w| Q L^{1/2} Q^T e_1, eps_m and the stop test.
+// One wavefront: lane k owns row k of the eigenvector matrix Z.  Every lane runs the same
+// scalar recurrence and stores the same values into the single LDS copy of (d, e); a
+// wavefront's LDS accesses complete in program order, so no barrier is needed until the
+// end, and the column rotations of Z touch only the lane's own row.
+__global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st) {
+  __shared__ double Z[kMaxKrylov * 64];   // Z[col * 64 + row]
+  __shared__ double Dg[kMaxKrylov];       // diagonal, becomes the eigenvalues
+  __shared__ double Eg[kMaxKrylov];       // subdiagonal e[i] couples i and i + 1
+  __shared__ double red[64];
+  const int lane = threadIdx.x;
+  for (int c = 0; c < m; ++c) Z[c * 64 + lane] = (c == lane) ? 1.0 : 0.0;
+  if (lane < m) {
+    Dg[lane] = st->alpha[lane];
+    Eg[lane] = (lane < m - 1) ? st->beta[lane] : 0.0;
+  }
+  __syncthreads();
+  int failed = 0;
+  for (int l = 0; l < m && !failed; ++l) {
+    int iter = 0;
+    for (;;) {
+      int mm = l;
+      for (; mm < m - 1; ++mm) {
+        const double dd = fabs(Dg[mm]) + fabs(Dg[(mm + 1)]);
+        if (fabs(Eg[mm]) + dd == dd) break;
+      }
+      if (mm == l) break;
+      if (++iter > 60) {
+        failed = 1;
+        break;
+      }
+      const double dl = Dg[l];
+      const double el = Eg[l];
+      double g = (Dg[(l + 1)] - dl) / (2.0 * el);
+      double r = sqrt(g * g + 1.0);
+      g = Dg[mm] - dl + el / (g + copysign(r, g));
+      double s = 1.0, c = 1.0, p = 0.0;
+      bool underflow = false;
+      for (int i = mm - 1; i >= l; --i) {
+        const double ei = Eg[i];
+        const double f = s * ei;
+        const double b = c * ei;
+        r = sqrt(f * f + g * g);
+        Eg[(i + 1)] = r;
+        if (r == 0.0) {
+          Dg[(i + 1)] -= p;
+          Eg[mm] = 0.0;
+          underflow = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = Dg[(i + 1)] - p;
+        r = (Dg[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        Dg[(i + 1)] = g + p;
+        g = c * r - b;
+        if (lane < m) {
+          const double z0 = Z[i * 64 + lane];
+          const double z1 = Z[(i + 1) * 64 + lane];
+          Z[(i + 1) * 64 + lane] = s * z0 + c * z1;
+          Z[i * 64 + lane] = c * z0 - s * z1;
+        }
+      }
+      if (underflow) continue;
+      Dg[l] -= p;
+      Eg[l] = g;
+      Eg[mm] = 0.0;
+    }
+  }
+  __syncthreads();
+  // eigenvalues (identical in every lane) and the first eigenvector components (row 0)
+  double lmax = 0.0, lmin = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double lam = Dg[k];
+    lmax = k == 0 ? lam : fmax(lmax, lam);
+    lmin = k == 0 ? lam : fmin(lmin, lam);
+  }
+  const double wn = st->wnorm;
+  double yr = 0.0;
+  if (lane < m) {
+    for (int k = 0; k < m; ++k)
+      yr += sqrt(fmax(Dg[k], 0.0)) * Z[k * 64 + 0] * Z[k * 64 + lane];
+    yr *= wn;
+  }
+  // eps_m in the orthonormal Krylov basis
+  const double yp = (lane < m - 1) ? st->yprev[lane] : 0.0;
+  const double diff = (lane < m) ? (yr - yp) : 0.0;
+  red[lane] = diff * diff;
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if (lane < s) red[lane] += red[lane + s];
+    __syncthreads();
+  }
+  const double num = red[0];
+  __syncthreads();
+  red[lane] = yp * yp;
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if (lane < s) red[lane] += red[lane + s];
+    __syncthreads();
+  }
+  const double den = red[0];
+  __syncthreads();
+  if (lane < m) {
+    st->y[lane] = yr;
+    st->yprev[lane] = yr;
+  }
+  if (lane == 0) {
+    double amax = 0.0;
+    for (int k = 0; k < m; ++k) amax = fmax(amax, fabs(st->alpha[k]));
+    const double eps = m >= 2 ? sqrt(num / den) : 0.0;
+    int reason = 0;
+    if (failed)
+      reason = 4;
+    else if (lmin < -1e-12 * fmax(lmax, 0.0))
+      reason = 3;
+    else if (m >= 2 && eps < tol)
+      reason = 1;
+    else if (st->beta[m - 1] <= 1e-14 * amax)
+      reason = 2;
+    st->eps = eps;
+    st->m = m;
+    st->reason = reason;
+  }
+}
+
+__global__ void lz_reset(LzState *st) {
+  const int t = threadIdx.x;
+  if (t < kMaxKrylov) {
+    st->alpha[t] = 0.0;
+    st->beta[t] = 0.0;
+    st->y[t] = 0.0;
+    st->yprev[t] = 0.0;
+    st->h[t] = 0.0;
+  }
+  if (t == 0) {
+    st->wnorm = 0.0;
+    st->eps = 0.0;
+    st->m = 0;
+    st->reason = 0;
+  }
+}
+
+inline unsigned nblk(int64_t m) { return unsigned((m + kThreads - 1) / kThreads); }
+
+int dot(rpb_ctx *ctx, int64_t m, const double *a, const double *b, double *part, double *out,
+        int mode, hipStream_t stream) {
+  dot_partial<<<kRedBlocks, kThreads, 0, stream>>>(m, a, b, part);
+  RPB_LAUNCHED(ctx);
+  dot_finish<<<1, kThreads, 0, stream>>>(part, kRedBlocks, out, mode);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+}  // namespace
+
+int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *w, double tol,
+                int max_iter, double *out, int *iters, double *eps_out, hipStream_t stream) {
+  const int64_t n = g.n;
+  const int64_t m3 = 3 * n;
+  int st;
+  double *V = static_cast<double *>(
+      workspace(ctx, WS_KRYLOV, size_t(max_iter) * size_t(m3) * sizeof(double), &st));
+  if (!V) return st;
+  double *u = static_cast<double *>(workspace(ctx, WS_VEC_A, size_t(m3) * sizeof(double), &st));
+  if (!u) return st;
+  double *part = static_cast<double *>(
+      workspace(ctx, WS_REDUCE, size_t(kRedBlocks) * kMaxKrylov * sizeof(double), &st));
+  if (!part) return st;
+  LzState *ls = static_cast<LzState *>(workspace(ctx, WS_SMALL, 1 << 16, &st));
+  if (!ls) return st;
+  LzState *host = static_cast<LzState *>(host_scratch(ctx));
+  static_assert(sizeof(LzState) <= 4096, "status must fit the pinned scratch");
+
+  lz_reset<<<1, 64, 0, stream>>>(ls);
+  RPB_LAUNCHED(ctx);
+  RPB_TRY(dot(ctx, m3, w, w, part, &ls->wnorm, 1, stream));
+  scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, w, &ls->wnorm, V, nullptr);
+  RPB_LAUNCHED(ctx);
+
+  int m = 0;
+  int reason = 0;
+  double eps = 0.0;
+  for (m = 1; m <= max_iter; ++m) {
+    double *vm = V + int64_t(m - 1) * m3;
+    const double *vprev = m > 1 ? V + int64_t(m - 2) * m3 : nullptr;
+    RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream));
+    RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[m - 1], 0, stream));
+    three_term<<<nblk(m3), kThreads, 0, stream>>>(m3, u, vm, vprev, &ls->alpha[m - 1],
+                                                   m > 1 ? &ls->beta[m - 2] : nullptr);
+    RPB_LAUNCHED(ctx);
+    {
+      const dim3 grid{unsigned(kRedBlocks), unsigned(m), 1u};
+      reorth_dots<<<grid, kThreads, 0, stream>>>(m3, V, u, part);
+      RPB_LAUNCHED(ctx);
+      reorth_finish<<<1, kThreads, 0, stream>>>(m, kRedBlocks, part, ls->h);
+      RPB_LAUNCHED(ctx);
+      reorth_update<<<nblk(m3), kThreads, 0, stream>>>(m3, m, V, ls->h, u);
+      RPB_LAUNCHED(ctx);
+    }
+    RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[m - 1], 1, stream));
+    tridiag_sqrt<<<1, 64, 0, stream>>>(m, tol, ls);
+    RPB_LAUNCHED(ctx);
+    if (m < max_iter) {
+      scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[m - 1],
+                                                           V + int64_t(m) * m3, ls);
+      RPB_LAUNCHED(ctx);
+    }
+    RPB_HIP(ctx, hipMemcpyAsync(host, ls, sizeof(LzState), hipMemcpyDeviceToHost, stream));
+    RPB_HIP(ctx, hipStreamSynchronize(stream));
+    reason = host->reason;
+    eps = host->eps;
+    if (reason != 0) break;
+  }
+  if (m > max_iter) m = max_iter;
+  basis_combine<<<nblk(m3), kThreads, 0, stream>>>(m3, m, V, ls->y, out);
+  RPB_LAUNCHED(ctx);
+  if (iters) *iters = m;
+  if (eps_out) *eps_out = eps;
+  if (reason == 4) return fail(ctx, RPB_EDEVICE, "tridiagonal eigensolve did not converge");
+  if (reason == 3) return fail(ctx, RPB_ENOTSPD, "negative Ritz value at m = %d", m);
+  if (reason == 0)
+    return fail(ctx, RPB_ENOCONV, "Lanczos: eps = %.3e > tol = %.3e after %d iterations", eps,
+                tol, m);
+  return RPB_OK;
+}
+
+}  // namespace rpb
+
+using namespace rpb;
+
+extern "C" int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                                  const double *w, double tol, int max_iter, double *out,
+                                  int *iters_out, double *eps_out, rpb_stream_t stream_) {
+  RPB_TRY(check_params(ctx, p));
+  if (n < 0) return fail(ctx, RPB_EINVAL, "n must be >= 0");
+  if (!(tol > 0.0)) return fail(ctx, RPB_EINVAL, "tol must be > 0");
+  if (max_iter < 1 || max_iter > kMaxKrylov)
+    return fail(ctx, RPB_EINVAL, "max_iter must be in [1, %d]", kMaxKrylov);
+  if (iters_out) *iters_out = 0;
+  if (eps_out) *eps_out = 0.0;
+  if (n == 0) return RPB_OK;
+  if (!pos || !w || !out) return fail(ctx, RPB_EINVAL, "pos, w and out must not be NULL");
+  const size_t nb = size_t(n) * 3 * sizeof(double);
+  if (overlaps(out, nb, pos, nb) || overlaps(out, nb, w, nb))
+    return fail(ctx, RPB_EINVAL, "out overlaps an input");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  RPB_HIP(ctx, hipSetDevice(ctx->device));
+  RPB_TRY(check_finite(ctx, pos, n, stream));
+  Packed g;
+  RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
+  return lanczos_run(ctx, p, g, w, tol, max_iter, out, iters_out, eps_out, stream);
+}

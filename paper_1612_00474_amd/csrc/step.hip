@@ -1,0 +1,135 @@
+// One Brownian dynamics step (paper, Sec. II.A: eq. EM and the stochastic Adams-Bashforth
+// scheme eq. AB; Sec. III for the constant driving torque and the soft potential).
+//
+//   F^n  = steric + gravity at q^n                       (forces.hip)
+//   u^n  = M^n F^n + M_C^n T                             (matvec.hip)
+//   g^n  ~ M^{n 1/2} W^n                                 (lanczos.hip)
+//   D^n  = (kT/delta)[M(q^n + delta/2 W~) - M(q^n - delta/2 W~)] W~   (stochastic.hip)
+//   q^{n+1} = q^n + dt (c0 u^n - c1 u^{n-1}) + sqrt(2 kT dt) g^n + dt D^n
+// with (c0, c1) = (3/2, 1/2) for SAB after the first step and (1, 0) for EM or the first
+// SAB step (no u^{-1} exists).  u^n is stored into the caller's u_prev for the next step.
+#include <cmath>
+
+#include "rpb_internal.h"
+
+namespace rpb {
+
+namespace {
+
+__global__ void fill_torque(int64_t n, double tx, double ty, double tz, double *__restrict__ t) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  t[3 * i] = tx;
+  t[3 * i + 1] = ty;
+  t[3 * i + 2] = tz;
+}
+
+__global__ void combine_kernel(int64_t m, double *__restrict__ pos, double *__restrict__ u_prev,
+                               const double *__restrict__ u, const double *__restrict__ g,
+                               const double *__restrict__ drift, double dt, double c0, double c1,
+                               double noise) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double ui = u[i];
+  const double det = c1 != 0.0 ? c0 * ui - c1 * u_prev[i] : c0 * ui;
+  pos[i] = pos[i] + dt * det + noise * g[i] + dt * drift[i];
+  u_prev[i] = ui;
+}
+
+inline unsigned nblk(int64_t m) { return unsigned((m + 255) / 256); }
+
+}  // namespace
+
+}  // namespace rpb
+
+using namespace rpb;
+
+extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cfg,
+                        rpb_sab_state *state, const double *w, const double *w_tilde,
+                        int *iters_out, double *eps_out, rpb_stream_t stream_) {
+  RPB_TRY(check_params(ctx, p));
+  if (!cfg || !state) return fail(ctx, RPB_EINVAL, "cfg and state must not be NULL");
+  if (!(cfg->dt > 0.0) || !(cfg->delta > 0.0) || !(cfg->lanczos_tol > 0.0))
+    return fail(ctx, RPB_EINVAL, "dt, delta and lanczos_tol must be > 0");
+  if (cfg->lanczos_max_iter < 1 || cfg->lanczos_max_iter > 64)
+    return fail(ctx, RPB_EINVAL, "lanczos_max_iter must be in [1, 64]");
+  if (cfg->scheme != 0 && cfg->scheme != 1) return fail(ctx, RPB_EINVAL, "unknown scheme");
+  if (cfg->rfd_precision != RPB_FP64 && cfg->rfd_precision != RPB_MIXED)
+    return fail(ctx, RPB_EINVAL, "unknown rfd_precision");
+  if (!(cfg->steric_u0 >= 0.0) || !(cfg->steric_b > 0.0))
+    return fail(ctx, RPB_EINVAL, "need steric_u0 >= 0 and steric_b > 0");
+  const int64_t n = state->n;
+  if (iters_out) *iters_out = 0;
+  if (eps_out) *eps_out = 0.0;
+  if (n < 0) return fail(ctx, RPB_EINVAL, "n must be >= 0");
+  if (n == 0) return RPB_OK;
+  if (!state->pos || !state->u_prev)
+    return fail(ctx, RPB_EINVAL, "state->pos and state->u_prev must not be NULL");
+  const size_t nb = size_t(n) * 3 * sizeof(double);
+  if (overlaps(state->pos, nb, state->u_prev, nb) || overlaps(state->pos, nb, w, nb) ||
+      overlaps(state->pos, nb, w_tilde, nb) || overlaps(state->u_prev, nb, w, nb) ||
+      overlaps(state->u_prev, nb, w_tilde, nb))
+    return fail(ctx, RPB_EINVAL, "state arrays overlap the noise arrays or each other");
+
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  RPB_HIP(ctx, hipSetDevice(ctx->device));
+  RPB_TRY(check_finite(ctx, state->pos, n, stream));
+  const int64_t m3 = 3 * n;
+  int st;
+  double *F = static_cast<double *>(workspace(ctx, WS_FORCE, nb, &st));
+  if (!F) return st;
+  double *T = static_cast<double *>(workspace(ctx, WS_TORQUE, nb, &st));
+  if (!T) return st;
+  double *u = static_cast<double *>(workspace(ctx, WS_VEC_F, nb, &st));
+  if (!u) return st;
+  double *g = static_cast<double *>(workspace(ctx, WS_VEC_G, nb, &st));
+  if (!g) return st;
+  double *drift = static_cast<double *>(workspace(ctx, WS_VEC_H, nb, &st));
+  if (!drift) return st;
+
+  // noise
+  const double *W = w;
+  const double *Wt = w_tilde;
+  if (!W) {
+    double *buf = static_cast<double *>(workspace(ctx, WS_NOISE_W, nb, &st));
+    if (!buf) return st;
+    RPB_TRY(normals_run(ctx, m3, cfg->seed, 0, uint64_t(state->step), buf, stream));
+    W = buf;
+  }
+  if (!Wt) {
+    double *buf = static_cast<double *>(workspace(ctx, WS_NOISE_WT, nb, &st));
+    if (!buf) return st;
+    RPB_TRY(normals_run(ctx, m3, cfg->seed, 1, uint64_t(state->step), buf, stream));
+    Wt = buf;
+  }
+
+  // deterministic velocity
+  RPB_TRY(forces_run(ctx, p, n, state->pos, cfg->f_grav_z, cfg->steric_u0, cfg->steric_b, F,
+                     stream));
+  fill_torque<<<nblk(n), 256, 0, stream>>>(n, cfg->torque[0], cfg->torque[1], cfg->torque[2], T);
+  RPB_LAUNCHED(ctx);
+  Packed geo;
+  RPB_TRY(pack_geometry(ctx, p, n, state->pos, WS_GEOM, &geo, stream));
+  RPB_TRY(matvec_packed(ctx, p, geo, F, T, 0, n, u, stream));
+
+  // Brownian increment (the last iterate is used if the tolerance is not met)
+  int iters = 0;
+  double eps = 0.0;
+  const int lz = lanczos_run(ctx, p, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter, g, &iters,
+                             &eps, stream);
+  if (lz != RPB_OK && lz != RPB_ENOCONV) return lz;
+
+  // stochastic drift
+  RPB_TRY(rfd_run(ctx, p, n, state->pos, Wt, cfg->delta, cfg->rfd_precision, drift, stream));
+
+  const bool ab = cfg->scheme == 0 && state->have_prev;
+  combine_kernel<<<nblk(m3), 256, 0, stream>>>(m3, state->pos, state->u_prev, u, g, drift,
+                                               cfg->dt, ab ? 1.5 : 1.0, ab ? 0.5 : 0.0,
+                                               std::sqrt(2.0 * p->kT * cfg->dt));
+  RPB_LAUNCHED(ctx);
+  state->step += 1;
+  state->have_prev = 1;
+  if (iters_out) *iters_out = iters;
+  if (eps_out) *eps_out = eps;
+  return lz;
+}

@@ -1,0 +1,91 @@
+"""GPU parity of lanczos_sqrt_apply against the FP64 oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lanczos, mobility
+from paper_1612_00474_amd import workloads as wl
+from tests.gpu_util import dev, host, rel2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_1612_00474_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    inp = wl.make_inputs(wl.WORKLOADS["sheet256_rsa"], 0)
+    M, _ = mobility.dense(inp["pos"])
+    return inp, M
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 9])
+def test_fixed_iterations_fp64(ctx, c1, m):
+    inp, M = c1
+    w = inp["w"]
+    ref, mref, _, _ = lanczos.lanczos_sqrt(lambda v: M @ v, w.ravel(), 1e-300, max_iter=m)
+    g, it, eps, st = ctx.lanczos(dev(inp["pos"]), dev(w), 1e-300, max_iter=m, allow_noconv=True)
+    assert it == m == mref
+    assert rel2(host(g).ravel(), ref) <= 1e-12
+
+
+def test_tolerance_run_matches_dense_root(ctx, c1):
+    inp, M = c1
+    w = inp["w"].ravel()
+    _, mref, eps_ref, _ = lanczos.lanczos_sqrt(lambda v: M @ v, w, 1e-6)
+    exact = lanczos.sqrtm_dense(M) @ w
+    for precision in ("fp64", "mixed"):
+        g, it, eps, st = ctx.lanczos(dev(inp["pos"]), dev(inp["w"]), 1e-6, precision=precision)
+        err = rel2(host(g).ravel(), exact)
+        print(f"lanczos {precision}: m = {it} (oracle {mref}), eps = {eps:.2e}, err vs dense root {err:.2e}")
+        assert err <= 1e-5
+        if precision == "fp64":
+            assert it == mref and abs(eps - eps_ref) <= 1e-9 * eps_ref
+
+
+def test_single_sphere_is_exact(ctx):
+    pos = np.array([[0.1, 0.2, 1.8]])
+    w = np.array([[0.7, -1.2, 0.4]])
+    h = 1.8
+    mu_par = 1 - 9 / (16 * h) + 1 / (8 * h ** 3) - 1 / (16 * h ** 5)
+    mu_perp = 1 - 9 / (8 * h) + 1 / (2 * h ** 3) - 1 / (8 * h ** 5)
+    ref = np.sqrt(np.array([mu_par, mu_par, mu_perp]) / (6 * math.pi)) * w[0]
+    g, it, eps, st = ctx.lanczos(dev(pos), dev(w), 1e-10)
+    assert it <= 2
+    assert np.abs(host(g)[0] - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_no_convergence_status(ctx, c1):
+    from paper_1612_00474_amd._lib import RPB_ENOCONV, RpbError
+    inp, _ = c1
+    with pytest.raises(RpbError) as e:
+        ctx.lanczos(dev(inp["pos"]), dev(inp["w"]), 1e-12, max_iter=3)
+    assert e.value.status == RPB_ENOCONV
+    g, it, eps, st = ctx.lanczos(dev(inp["pos"]), dev(inp["w"]), 1e-12, max_iter=3, allow_noconv=True)
+    assert st == RPB_ENOCONV and it == 3 and eps > 1e-12
+
+
+def test_full_size_properties(ctx):
+    # N = 16,384 (time-stepping sheet): the wall screens the interactions, so the tolerance
+    # 1e-3 is met in a few iterations (Sec. II.C); |g|^2 = w^T M w for the symmetric root.
+    inp = wl.make_inputs(wl.WORKLOADS["sheet16k_fp64"], 0)
+    P, W = dev(inp["pos"]), dev(inp["w"])
+    g, it, eps, st = ctx.lanczos(P, W, 1e-3)
+    Mw = host(ctx.matvec(P, W, None, "fp64"))
+    g = host(g)
+    wMw = float(np.sum(inp["w"] * Mw))
+    print(f"sheet16k: m = {it}, eps = {eps:.2e}, |g|^2 / w.Mw - 1 = {float(np.sum(g * g)) / wMw - 1:.2e}")
+    assert it <= 12 and eps < 1e-3
+    assert abs(float(np.sum(g * g)) / wMw - 1.0) <= 1e-3
+    # mixed and float64 agree at a fixed number of iterations
+    g64 = host(ctx.lanczos(P, W, 1e-300, max_iter=6, allow_noconv=True)[0])
+    g32 = host(ctx.lanczos(P, W, 1e-300, max_iter=6, precision="mixed", allow_noconv=True)[0])
+    assert rel2(g32, g64) <= 1e-5

@@ -1,0 +1,153 @@
+"""GPU parity of rpb_mobility_matvec against the FP64 oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mobility
+from paper_1612_00474_amd import workloads as wl
+from tests.gpu_util import awkward_config, dev, host, rel2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12     # relative 2-norm, float64 path
+MIXED_TOL = 1e-5     # relative 2-norm, float32 pair terms with Kahan sums
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_1612_00474_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return wl.make_inputs(wl.WORKLOADS["sheet256_rsa"], 0)
+
+
+@pytest.fixture(scope="module")
+def c1_ref(c1):
+    return mobility.dense_matvec(c1["pos"], c1["force"], c1["torque"])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_sheet256_parity(ctx, c1, c1_ref, precision, tol):
+    u = host(ctx.matvec(dev(c1["pos"]), dev(c1["force"]), dev(c1["torque"]), precision))
+    err = rel2(u, c1_ref)
+    print(f"sheet256 {precision}: rel2 = {err:.3e}")
+    assert err <= tol
+    assert np.abs(u - c1_ref).max() <= 10 * tol * np.abs(c1_ref).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_coherent_forcing(ctx, precision, tol):
+    # gravity-like F = (0, 0, -1) and the rollers' torque (0, 1, 0) on a wide sheet: the free
+    # and image parts cancel to O(h^2/r^3) at large r, which exposes float32 cancellation
+    pos = wl.sheet(2048, phi=0.4, seed=3)
+    F = np.tile([0.0, 0.0, -1.0], (len(pos), 1))
+    T = np.tile([0.0, 1.0, 0.0], (len(pos), 1))
+    rows = np.arange(0, 2048, 16)
+    ref = mobility.matvec(pos, F, T, rows=rows)
+    u = host(ctx.matvec(dev(pos), dev(F), dev(T), precision))[rows]
+    err = rel2(u, ref)
+    print(f"coherent {precision}: rel2 = {err:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 255, 256, 257, 300])
+def test_ragged_sizes_fp64(ctx, n):
+    rng = np.random.default_rng(n)
+    side = max(2.0, math.sqrt(n * math.pi / 0.4))
+    pos = np.column_stack([rng.uniform(0, side, n), rng.uniform(0, side, n), rng.uniform(0.8, 3, n)])
+    F = rng.standard_normal((n, 3))
+    T = rng.standard_normal((n, 3))
+    ref = mobility.dense_matvec(pos, F, T)
+    u = host(ctx.matvec(dev(pos), dev(F), dev(T), "fp64"))
+    assert rel2(u, ref) <= FP64_TOL
+    um = host(ctx.matvec(dev(pos), dev(F), dev(T), "mixed"))
+    assert rel2(um, ref) <= MIXED_TOL
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_wall_overlaps_and_coincident_spheres(ctx, precision, tol):
+    pos = awkward_config()
+    rng = np.random.default_rng(1)
+    F = rng.standard_normal(pos.shape)
+    T = rng.standard_normal(pos.shape)
+    ref = mobility.dense_matvec(pos, F, T)
+    u = host(ctx.matvec(dev(pos), dev(F), dev(T), precision))
+    assert rel2(u, ref) <= tol
+    # spheres on / below the wall do not move (App. A)
+    assert np.all(u[1] == 0.0) and np.all(u[2] == 0.0)
+
+
+def test_force_only_and_torque_only(ctx, c1, c1_ref):
+    pos = dev(c1["pos"])
+    uf = host(ctx.matvec(pos, dev(c1["force"]), None, "fp64"))
+    ut = host(ctx.matvec(pos, None, dev(c1["torque"]), "fp64"))
+    assert rel2(uf, mobility.dense_matvec(c1["pos"], c1["force"], None)) <= FP64_TOL
+    assert rel2(ut, mobility.dense_matvec(c1["pos"], None, c1["torque"])) <= FP64_TOL
+    assert rel2(uf + ut, c1_ref) <= FP64_TOL
+
+
+def test_row_shards_concatenate_bitwise(ctx):
+    pos = wl.sheet(5000, seed=2)
+    rng = np.random.default_rng(2)
+    F, T = dev(rng.standard_normal(pos.shape)), dev(rng.standard_normal(pos.shape))
+    P = dev(pos)
+    for precision in ("fp64", "mixed"):
+        full = host(ctx.matvec(P, F, T, precision))
+        cuts = [0, 1, 700, 2500, 4999, 5000]
+        parts = [host(ctx.matvec(P, F, T, precision, rows=(a, b))) for a, b in zip(cuts[:-1], cuts[1:])]
+        assert np.array_equal(np.vstack(parts), full)
+
+
+def test_deterministic(ctx, c1):
+    P, F, T = dev(c1["pos"]), dev(c1["force"]), dev(c1["torque"])
+    for precision in ("fp64", "mixed"):
+        a = host(ctx.matvec(P, F, T, precision))
+        b = host(ctx.matvec(P, F, T, precision))
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,nrows", [("sheet16k_fp64", 48), ("sheet64k_mixed", 24)])
+def test_full_size_row_sampled(ctx, name, nrows):
+    w = wl.WORKLOADS[name]
+    inp = wl.make_inputs(w, 0)
+    rows = np.random.default_rng(9).choice(w.n, nrows, replace=False)
+    ref = mobility.matvec(inp["pos"], inp["force"], inp["torque"], rows=rows)
+    P, F, T = dev(inp["pos"]), dev(inp["force"]), dev(inp["torque"])
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        u = host(ctx.matvec(P, F, T, precision))[rows]
+        err = rel2(u, ref)
+        print(f"{name} {precision}: rel2 = {err:.3e} over {nrows} sampled rows")
+        assert err <= tol
+
+
+def test_error_paths(ctx, c1):
+    import torch
+    from paper_1612_00474_amd._lib import RPB_EINVAL, RPB_ENONFINITE, RpbError
+    P, F = dev(c1["pos"]), dev(c1["force"])
+    with pytest.raises(RpbError) as e:
+        ctx.matvec(P, None, None)
+    assert e.value.status == RPB_EINVAL
+    with pytest.raises(RpbError) as e:
+        ctx.matvec(P, F, None, out=P)
+    assert e.value.status == RPB_EINVAL
+    bad = P.clone()
+    bad[3, 1] = float("nan")
+    with pytest.raises(RpbError) as e:
+        ctx.matvec(bad, F, None)
+    assert e.value.status == RPB_ENONFINITE
+    ctx.a = -1.0
+    try:
+        with pytest.raises(RpbError) as e:
+            ctx.matvec(P, F, None)
+        assert e.value.status == RPB_EINVAL
+    finally:
+        ctx.a = 1.0
+    empty = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    assert ctx.matvec(empty, empty, None).shape == (0, 3)

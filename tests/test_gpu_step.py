@@ -1,0 +1,86 @@
+"""GPU parity of sab_step (one stochastic Adams-Bashforth / Euler-Maruyama step) against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import integrator, philox
+from paper_1612_00474_amd import workloads as wl
+from tests.gpu_util import dev, host, rel2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+PHYS = dict(f_grav_z=-1.0, torque=(0.0, 1.0, 0.0))
+M_FIXED = 8   # fixed Lanczos iteration count so that both sides take the same Krylov space
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_1612_00474_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _setup(n=200, seed=0):
+    w = wl.Workload("step", n, wl.side_for_area_fraction(n, 0.4), 1.1, 2.5)
+    return wl.make_inputs(w, seed)
+
+
+def _oracle_step(pos, u_prev, W, Wt, scheme):
+    return integrator.step(pos, u_prev, W, Wt, dt=0.01, delta=1e-4, lanczos_tol=1e-300,
+                           lanczos_max_iter=M_FIXED, scheme=scheme, u0=1.0, b=0.1, **PHYS)
+
+
+@pytest.mark.parametrize("scheme", ["sab", "em"])
+def test_two_steps_match_oracle(ctx, scheme):
+    from paper_1612_00474_amd import StepState
+    inp = _setup()
+    rng = np.random.default_rng(3)
+    state = StepState(dev(inp["pos"]))
+    pos = inp["pos"].copy()
+    u_prev = None
+    for k in range(2):
+        W, Wt = rng.standard_normal(pos.shape), rng.standard_normal(pos.shape)
+        it, eps, st = ctx.sab_step(state, dt=0.01, delta=1e-4, lanczos_tol=1e-300,
+                                   lanczos_max_iter=M_FIXED, scheme=scheme, w=dev(W), w_tilde=dev(Wt),
+                                   steric_u0=1.0, steric_b=0.1, **PHYS)
+        new, u, mref, _, _ = _oracle_step(pos, u_prev, W, Wt, scheme)
+        got = host(state.pos)
+        err = rel2(got - pos, new - pos)
+        print(f"{scheme} step {k}: displacement rel2 = {err:.3e}")
+        assert it == mref == M_FIXED
+        assert err <= 1e-10
+        assert rel2(host(state.u_prev), u) <= 1e-12
+        # continue both trajectories from the device state (one-step parity)
+        pos = got.copy()
+        u_prev = host(state.u_prev).copy()
+    assert state.step == 2 and state.have_prev
+
+
+def test_device_noise_matches_oracle_generator(ctx):
+    from paper_1612_00474_amd import StepState
+    inp = _setup(n=120, seed=1)
+    state = StepState(dev(inp["pos"]))
+    state.step = 41
+    ctx.sab_step(state, dt=0.01, delta=1e-4, lanczos_tol=1e-300, lanczos_max_iter=M_FIXED, seed=99,
+                 steric_u0=1.0, steric_b=0.1, **PHYS)
+    n = len(inp["pos"])
+    W = philox.normals(3 * n, 99, 0, 41).reshape(n, 3)
+    Wt = philox.normals(3 * n, 99, 1, 41).reshape(n, 3)
+    new, *_ = _oracle_step(inp["pos"], None, W, Wt, "sab")
+    assert rel2(host(state.pos) - inp["pos"], new - inp["pos"]) <= 1e-10
+
+
+def test_mixed_precision_step(ctx):
+    from paper_1612_00474_amd import StepState
+    inp = _setup(n=256, seed=2)
+    rng = np.random.default_rng(8)
+    W, Wt = rng.standard_normal(inp["pos"].shape), rng.standard_normal(inp["pos"].shape)
+    state = StepState(dev(inp["pos"]))
+    ctx.sab_step(state, dt=0.01, delta=1e-4, lanczos_tol=1e-300, lanczos_max_iter=M_FIXED,
+                 precision="mixed", rfd_precision="fp64", w=dev(W), w_tilde=dev(Wt),
+                 steric_u0=1.0, steric_b=0.1, **PHYS)
+    new, *_ = _oracle_step(inp["pos"], None, W, Wt, "sab")
+    err = rel2(host(state.pos) - inp["pos"], new - inp["pos"])
+    print(f"mixed step: displacement rel2 = {err:.3e}")
+    assert err <= 1e-5
