@@ -23,13 +23,38 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic operation count of one ordered pair in the pair kernel with a torque source:
-# the closed form in pair_tensor.h (FMA = 2, add/mul = 1, rsqrt = 1; Kahan compensation,
-# hi/lo reconstruction, index math and branches excluded).
-FLOPS_PER_PAIR_TORQUE = 190
-FLOPS_PER_PAIR_FORCE = 148
-PEAK_FP32_TFLOPS = 157.3     # 256 CU x 128 FP32 lanes (packed) x 2 x 2.4 GHz
+# Algorithmic operation count of one ordered pair (the closed form evaluated by the pair
+# kernel: add/sub/mul = 1, FMA = 2, rsqrt = 1; the two separations x_i - x_j, y_i - y_j and
+# the three accumulations are included; float32 hi/lo reconstruction, Kahan compensation,
+# index math, selects and branches are not).  Far branch (|r| >= 2a), i.e. all but the few
+# overlapping pairs.
+FLOPS_PER_PAIR_FORCE = 106   # source carries a force only (Lanczos and RFD products)
+FLOPS_PER_PAIR_TORQUE = 147  # source carries a force and a torque (deterministic product)
+PEAK_FP32_TFLOPS = 157.3     # 256 CU x 128 FP32 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
+KIND_FP64_FORCE, KIND_FP64_TORQUE, KIND_MIXED_FORCE, KIND_MIXED_TORQUE = 0, 1, 2, 3
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1612_00474_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("matvec.hip", "pair_tensor.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    current = h.hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", "pair_kernels_sheet64k_hbm_traffic.md")
+    try:
+        with open(path) as f:
+            for line in f:
+                parts = line.rstrip("\n").split("\t")
+                if len(parts) == 3 and parts[0] == kernel and parts[2] == current:
+                    return float(parts[1])
+    except OSError:
+        pass
+    return None
 
 
 def parse():
@@ -118,7 +143,16 @@ def main():
         iters.append(ctx.sab_step(state, **step_kw)[0])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_pair, launches, pairs = ctx.timing_read()
+    kinds = {}
+    for name, kind, fpp in (("fp64_force", KIND_FP64_FORCE, FLOPS_PER_PAIR_FORCE),
+                            ("fp64_torque", KIND_FP64_TORQUE, FLOPS_PER_PAIR_TORQUE),
+                            ("mixed_force", KIND_MIXED_FORCE, FLOPS_PER_PAIR_FORCE),
+                            ("mixed_torque", KIND_MIXED_TORQUE, FLOPS_PER_PAIR_TORQUE)):
+        ms, k, pairs = ctx.timing_read(kind)
+        if k:
+            kinds[name] = {"launches": k, "ms_per_launch": ms / k,
+                           "pairs_per_s": pairs / (ms * 1e-3),
+                           "tflops": fpp * pairs / (ms * 1e-3) / 1e12}
     ctx.timing(False)
     timed_iters = iters[args.warmup:]
     n = w.n
@@ -126,12 +160,10 @@ def main():
     step_pairs = products * float(n) * n
     value = step_pairs / elapsed
 
-    # dominant kernel: the float32 pair kernel of the timed steps (Lanczos products carry no
-    # torque; the deterministic product does); price its measured launches
-    flops = 0.0
-    for m in timed_iters:
-        flops += (FLOPS_PER_PAIR_TORQUE + m * FLOPS_PER_PAIR_FORCE + 2 * FLOPS_PER_PAIR_FORCE) * float(n) * n
-    achieved = flops / (ms_pair * 1e-3) / 1e12
+    # dominant kernel: the pair kernel of the Lanczos products (most launches and most time)
+    dom = kinds["mixed_force" if prec == "mixed" else "fp64_force"]
+    peak = PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS
+    achieved = dom["tflops"]
     line = {
         "metric": "RPB matvec pair-interactions/s + BD steps/s at N=65,536, FP32-mixed vs FP64",
         "value": value,
@@ -154,10 +186,14 @@ def main():
         "matvec_kernel_pairs_per_s": {"mixed": mixed_rate, "fp64": f64_rate,
                                       "mixed_over_fp64": mixed_rate / f64_rate,
                                       "ms_per_launch": {"mixed": mixed_ms, "fp64": f64_ms}},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "pair kernel (all products of the timed steps)",
-                     "kernel_ms_per_step": ms_pair / args.steps, "launches": launches},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic("pair_kernel_mixed<false, 1>" if prec == "mixed"
+                                                 else "pair_kernel_f64<false, 2>"),
+                     "kernel": f"pair_kernel_{'mixed' if prec == 'mixed' else 'f64'}, force-only "
+                               f"products ({FLOPS_PER_PAIR_FORCE} flop/pair x {n}^2 pairs/launch)",
+                     "ms_per_launch": dom["ms_per_launch"], "launches": dom["launches"]},
+        "pair_kernels": kinds,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -111,7 +111,7 @@ int rpb_mobility_matvec_rows(rpb_ctx *ctx, const rpb_params *p, int64_t n, const
  * (RPB_ENOCONV, out = g_max_iter).  Only M (not M_C) enters.
  *
  * w, out: [n][3] device arrays (out must not overlap pos or w).  tol > 0 (use a tiny tol
- * with max_iter = m for a fixed number of steps).  1 <= max_iter <= 128.
+ * with max_iter = m for a fixed number of steps).  1 <= max_iter <= 64.
  * iters_out, eps_out: host pointers (may be NULL) for m and eps_m (0 when m = 1).
  */
 int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
@@ -193,9 +193,11 @@ int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cfg, rpb_s
  * When enabled, the library brackets every launch of the O(N^2) pair kernel with HIP
  * events on the stream it is launched on.  rpb_timing_read() synchronises, returns the
  * summed kernel time in milliseconds, the number of launches and the number of ordered
- * pair interactions they evaluated, and clears the record. */
+ * pair interactions of the launches of kernel variant `kind`, and removes them from the
+ * record.  kind = 2 * (precision == RPB_MIXED) + (torque present); kind = -1 takes all. */
 int rpb_timing_enable(rpb_ctx *ctx, int enable);
-int rpb_timing_read(rpb_ctx *ctx, double *ms_out, int64_t *launches_out, double *pairs_out);
+int rpb_timing_read(rpb_ctx *ctx, int kind, double *ms_out, int64_t *launches_out,
+                    double *pairs_out);
 
 #ifdef __cplusplus
 }

@@ -80,7 +80,7 @@ def load(path: str = LIB_PATH):
         "sab_step": (C.c_int, [P, pp, C.POINTER(RpbSabConfig), C.POINTER(RpbSabState), P, P,
                                C.POINTER(C.c_int), C.POINTER(D), P]),
         "rpb_timing_enable": (C.c_int, [P, C.c_int]),
-        "rpb_timing_read": (C.c_int, [P, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
+        "rpb_timing_read": (C.c_int, [P, C.c_int, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -256,12 +256,15 @@ class Context:
     def timing(self, enable: bool):
         self._check(self.lib.rpb_timing_enable(self.h, int(enable)))
 
-    def timing_read(self):
-        """(milliseconds, launches, pair interactions) of the pair kernel since the last read."""
+    def timing_read(self, kind=-1):
+        """(milliseconds, launches, pair interactions) of pair-kernel launches since the last read.
+
+        ``kind``: -1 for all launches, else 2 * (mixed) + (with torque)."""
         ms = C.c_double(0.0)
         k = C.c_int64(0)
         pairs = C.c_double(0.0)
-        self._check(self.lib.rpb_timing_read(self.h, C.byref(ms), C.byref(k), C.byref(pairs)))
+        self._check(self.lib.rpb_timing_read(self.h, int(kind), C.byref(ms), C.byref(k),
+                                             C.byref(pairs)))
         return ms.value, k.value, pairs.value
 
 

@@ -1,5 +1,6 @@
 // Context, workspace, error reporting and timing for librpb.
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 
 #include "rpb_internal.h"
@@ -77,7 +78,7 @@ int timing_begin(rpb_ctx *ctx, hipStream_t stream, hipEvent_t *start) {
   return RPB_OK;
 }
 
-int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs) {
+int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs, int kind) {
   if (!ctx->timing || !start) return RPB_OK;
   hipEvent_t e;
   if (!ctx->ev_pool.empty()) {
@@ -90,6 +91,7 @@ int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs)
   ctx->ev_start.push_back(start);
   ctx->ev_stop.push_back(e);
   ctx->ev_pairs.push_back(pairs);
+  ctx->ev_kind.push_back(kind);
   return RPB_OK;
 }
 
@@ -111,6 +113,12 @@ int rpb_create(int hip_device, rpb_ctx **out) {
   rpb_ctx *c = new (std::nothrow) rpb_ctx();
   if (!c) return RPB_ENOMEM;
   c->device = hip_device;
+  if (const char *v = getenv("RPB_TPT_F64")) c->tune.tpt_f64 = atoi(v) == 2 ? 2 : 1;
+  if (const char *v = getenv("RPB_TPT_MIXED")) c->tune.tpt_mixed = atoi(v) == 2 ? 2 : 1;
+  if (const char *v = getenv("RPB_TARGET_WGS")) {
+    const int w = atoi(v);
+    if (w >= 1 && w <= 1 << 20) c->tune.target_wgs = w;
+  }
   if (hipHostMalloc(&c->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return RPB_ENOMEM;
@@ -140,24 +148,37 @@ int rpb_timing_enable(rpb_ctx *ctx, int enable) {
   return RPB_OK;
 }
 
-int rpb_timing_read(rpb_ctx *ctx, double *ms_out, int64_t *launches_out, double *pairs_out) {
+int rpb_timing_read(rpb_ctx *ctx, int kind, double *ms_out, int64_t *launches_out,
+                    double *pairs_out) {
   if (!ctx) return RPB_EINVAL;
   double ms = 0.0, pairs = 0.0;
-  const size_t k = ctx->ev_start.size();
-  for (size_t i = 0; i < k; ++i) {
+  int64_t k = 0;
+  std::vector<hipEvent_t> keep_start, keep_stop;
+  std::vector<double> keep_pairs;
+  std::vector<int> keep_kind;
+  for (size_t i = 0; i < ctx->ev_start.size(); ++i) {
+    if (kind >= 0 && ctx->ev_kind[i] != kind) {
+      keep_start.push_back(ctx->ev_start[i]);
+      keep_stop.push_back(ctx->ev_stop[i]);
+      keep_pairs.push_back(ctx->ev_pairs[i]);
+      keep_kind.push_back(ctx->ev_kind[i]);
+      continue;
+    }
     RPB_HIP(ctx, hipEventSynchronize(ctx->ev_stop[i]));
     float t = 0.0f;
     RPB_HIP(ctx, hipEventElapsedTime(&t, ctx->ev_start[i], ctx->ev_stop[i]));
     ms += t;
     pairs += ctx->ev_pairs[i];
+    ++k;
     ctx->ev_pool.push_back(ctx->ev_start[i]);
     ctx->ev_pool.push_back(ctx->ev_stop[i]);
   }
-  ctx->ev_start.clear();
-  ctx->ev_stop.clear();
-  ctx->ev_pairs.clear();
+  ctx->ev_start.swap(keep_start);
+  ctx->ev_stop.swap(keep_stop);
+  ctx->ev_pairs.swap(keep_pairs);
+  ctx->ev_kind.swap(keep_kind);
   if (ms_out) *ms_out = ms;
-  if (launches_out) *launches_out = int64_t(k);
+  if (launches_out) *launches_out = k;
   if (pairs_out) *pairs_out = pairs;
   return RPB_OK;
 }

@@ -23,7 +23,6 @@ namespace rpb {
 namespace {
 
 constexpr int kBlock = 256;           // lanes per workgroup = targets per tile = sources per LDS tile
-constexpr int kTargetWorkgroups = 2048;
 
 struct GeomD {         // float64 geometry: x, y, z~ and H, n each
   const double *x, *y, *z, *h;
@@ -100,8 +99,10 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
   s = t;
 }
 
-// float64 pair kernel: partial[(chunk * 3 + comp) * nrows + row]
-template <bool TORQUE>
+// float64 pair kernel.  Workgroup = kBlock lanes x TPT targets per lane; the source chunk
+// blockIdx.y is streamed through LDS in tiles of kBlock.  Output:
+// partial[(chunk * 3 + comp) * nrows + row].
+template <bool TORQUE, int TPT>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g,
                                                           const double *__restrict__ src,
                                                           PairConsts<double> k,
@@ -111,15 +112,21 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g
   __shared__ double st[TORQUE ? 3 : 1][kBlock];
 
   const int tid = threadIdx.x;
-  const int64_t r = int64_t(blockIdx.x) * kBlock + tid;
-  const bool active = r < args.nrows;
-  const int64_t i = args.row0 + (active ? r : 0);
-  const double xi = g.x[i], yi = g.y[i], zi = g.z[i];
   const int64_t n = args.n;
+  int64_t r[TPT];
+  double xi[TPT], yi[TPT], zi[TPT], u[TPT][3];
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    r[q] = int64_t(blockIdx.x) * (kBlock * TPT) + q * kBlock + tid;
+    const int64_t i = args.row0 + (r[q] < args.nrows ? r[q] : 0);
+    xi[q] = g.x[i];
+    yi[q] = g.y[i];
+    zi[q] = g.z[i];
+    u[q][0] = u[q][1] = u[q][2] = 0.0;
+  }
   const int64_t jb = int64_t(blockIdx.y) * args.chunk;
   const int64_t je = min(n, jb + args.chunk);
 
-  double ux = 0.0, uy = 0.0, uz = 0.0;
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
@@ -140,26 +147,35 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g
     __syncthreads();
 #pragma unroll 2
     for (int j = 0; j < cnt; ++j) {
-      double ox, oy, oz;
-      pair_velocity<double, TORQUE>(xi - sx[j], yi - sy[j], zi, sz[j], sf[0][j], sf[1][j],
-                                    sf[2][j], TORQUE ? st[0][j] : 0.0,
-                                    TORQUE ? st[1][j] : 0.0, TORQUE ? st[2][j] : 0.0, k, ox,
-                                    oy, oz);
-      ux += ox;
-      uy += oy;
-      uz += oz;
+      const double xj = sx[j], yj = sy[j], zj = sz[j];
+      const double fx = sf[0][j], fy = sf[1][j], fz = sf[2][j];
+      const double tx = TORQUE ? st[0][j] : 0.0, ty = TORQUE ? st[1][j] : 0.0,
+                   tz = TORQUE ? st[2][j] : 0.0;
+#pragma unroll
+      for (int q = 0; q < TPT; ++q) {
+        double ox, oy, oz;
+        pair_velocity<double, TORQUE>(xi[q] - xj, yi[q] - yj, zi[q], zj, fx, fy, fz, tx, ty, tz,
+                                      k, ox, oy, oz);
+        u[q][0] += ox;
+        u[q][1] += oy;
+        u[q][2] += oz;
+      }
     }
   }
-  if (active) {
-    const int64_t base = int64_t(blockIdx.y) * 3 * args.nrows + r;
-    partial[base] = ux;
-    partial[base + args.nrows] = uy;
-    partial[base + 2 * args.nrows] = uz;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    if (r[q] < args.nrows) {
+      const int64_t base = int64_t(blockIdx.y) * 3 * args.nrows + r[q];
+      partial[base] = u[q][0];
+      partial[base + args.nrows] = u[q][1];
+      partial[base + 2 * args.nrows] = u[q][2];
+    }
   }
 }
 
-// mixed pair kernel: float32 pair terms, Kahan float32 sums, float64 partials
-template <bool TORQUE>
+// Mixed pair kernel: float32 pair terms, float32 sums over each LDS tile of kBlock sources,
+// tile sums added with Kahan compensation per target, float64 partials.
+template <bool TORQUE, int TPT>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF g,
                                                             const float *__restrict__ src,
                                                             PairConsts<float> k,
@@ -169,15 +185,25 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
   __shared__ float st[TORQUE ? 3 : 1][kBlock];
 
   const int tid = threadIdx.x;
-  const int64_t r = int64_t(blockIdx.x) * kBlock + tid;
-  const bool active = r < args.nrows;
-  const int64_t i = args.row0 + (active ? r : 0);
-  const float xih = g.xh[i], xil = g.xl[i], yih = g.yh[i], yil = g.yl[i], zi = g.z[i];
   const int64_t n = args.n;
+  int64_t r[TPT];
+  float xih[TPT], xil[TPT], yih[TPT], yil[TPT], zi[TPT];
+  float s[TPT][3], c[TPT][3];
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    r[q] = int64_t(blockIdx.x) * (kBlock * TPT) + q * kBlock + tid;
+    const int64_t i = args.row0 + (r[q] < args.nrows ? r[q] : 0);
+    xih[q] = g.xh[i];
+    xil[q] = g.xl[i];
+    yih[q] = g.yh[i];
+    yil[q] = g.yl[i];
+    zi[q] = g.z[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s[q][d] = c[q][d] = 0.f;
+  }
   const int64_t jb = int64_t(blockIdx.y) * args.chunk;
   const int64_t je = min(n, jb + args.chunk);
 
-  float sx = 0.f, cx = 0.f, sy_ = 0.f, cy = 0.f, szz = 0.f, cz = 0.f;
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
@@ -198,24 +224,39 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
       }
     }
     __syncthreads();
+    float a[TPT][3];
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) a[q][0] = a[q][1] = a[q][2] = 0.f;
 #pragma unroll 2
     for (int j = 0; j < cnt; ++j) {
-      const float dx = (xih - sxh[j]) + (xil - sxl[j]);
-      const float dy = (yih - syh[j]) + (yil - syl[j]);
-      float ox, oy, oz;
-      pair_velocity<float, TORQUE>(dx, dy, zi, sz[j], sf[0][j], sf[1][j], sf[2][j],
-                                   TORQUE ? st[0][j] : 0.f, TORQUE ? st[1][j] : 0.f,
-                                   TORQUE ? st[2][j] : 0.f, k, ox, oy, oz);
-      kahan_add(sx, cx, ox);
-      kahan_add(sy_, cy, oy);
-      kahan_add(szz, cz, oz);
+      const float xjh = sxh[j], xjl = sxl[j], yjh = syh[j], yjl = syl[j], zj = sz[j];
+      const float fx = sf[0][j], fy = sf[1][j], fz = sf[2][j];
+      const float tx = TORQUE ? st[0][j] : 0.f, ty = TORQUE ? st[1][j] : 0.f,
+                  tz = TORQUE ? st[2][j] : 0.f;
+#pragma unroll
+      for (int q = 0; q < TPT; ++q) {
+        const float dx = (xih[q] - xjh) + (xil[q] - xjl);
+        const float dy = (yih[q] - yjh) + (yil[q] - yjl);
+        float ox, oy, oz;
+        pair_velocity<float, TORQUE>(dx, dy, zi[q], zj, fx, fy, fz, tx, ty, tz, k, ox, oy, oz);
+        a[q][0] += ox;
+        a[q][1] += oy;
+        a[q][2] += oz;
+      }
     }
+#pragma unroll
+    for (int q = 0; q < TPT; ++q)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) kahan_add(s[q][d], c[q][d], a[q][d]);
   }
-  if (active) {
-    const int64_t base = int64_t(blockIdx.y) * 3 * args.nrows + r;
-    partial[base] = double(sx) - double(cx);
-    partial[base + args.nrows] = double(sy_) - double(cy);
-    partial[base + 2 * args.nrows] = double(szz) - double(cz);
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    if (r[q] < args.nrows) {
+      const int64_t base = int64_t(blockIdx.y) * 3 * args.nrows + r[q];
+      partial[base] = double(s[q][0]) - double(c[q][0]);
+      partial[base + args.nrows] = double(s[q][1]) - double(c[q][1]);
+      partial[base + 2 * args.nrows] = double(s[q][2]) - double(c[q][2]);
+    }
   }
 }
 
@@ -309,9 +350,12 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   // Source chunking: enough workgroups to fill the chip several times over.  The chunks
   // depend on n only (not on the row range), so every target sums its sources in the same
   // order whichever rows are requested: row shards concatenate to the full product bitwise.
-  const int64_t tiles = (nrows + kBlock - 1) / kBlock;
-  const int64_t tiles_full = (n + kBlock - 1) / kBlock;
-  int64_t nchunks = std::max<int64_t>(1, (kTargetWorkgroups + tiles_full - 1) / tiles_full);
+  const int tpt = f64 ? ctx->tune.tpt_f64 : ctx->tune.tpt_mixed;
+  const int64_t per_wg = int64_t(kBlock) * tpt;
+  const int64_t tiles = (nrows + per_wg - 1) / per_wg;
+  const int64_t tiles_full = (n + per_wg - 1) / per_wg;
+  int64_t nchunks =
+      std::max<int64_t>(1, (int64_t(ctx->tune.target_wgs) + tiles_full - 1) / tiles_full);
   int64_t chunk = (n + nchunks - 1) / nchunks;
   chunk = std::max<int64_t>(kBlock, (chunk + kBlock - 1) / kBlock * kBlock);
   nchunks = (n + chunk - 1) / chunk;
@@ -328,23 +372,32 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   RPB_TRY(timing_begin(ctx, stream, &t0));
   if (f64) {
     const auto k = make_pair_consts<double>(p->a);
-    if (has_t)
-      pair_kernel_f64<true><<<grid, kBlock, 0, stream>>>(args, geom_d(g),
-                                                        static_cast<const double *>(src), k, part);
+    const double *sv = static_cast<const double *>(src);
+    const GeomD gd = geom_d(g);
+    if (has_t && tpt == 2)
+      pair_kernel_f64<true, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else if (has_t)
+      pair_kernel_f64<true, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_f64<false, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
     else
-      pair_kernel_f64<false><<<grid, kBlock, 0, stream>>>(
-          args, geom_d(g), static_cast<const double *>(src), k, part);
+      pair_kernel_f64<false, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
   } else {
     const auto k = make_pair_consts<float>(p->a);
-    if (has_t)
-      pair_kernel_mixed<true><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src), k, part);
+    const float *sv = static_cast<const float *>(src);
+    const GeomF gf = geom_f(g);
+    if (has_t && tpt == 2)
+      pair_kernel_mixed<true, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+    else if (has_t)
+      pair_kernel_mixed<true, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_mixed<false, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
     else
-      pair_kernel_mixed<false><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src), k, part);
+      pair_kernel_mixed<false, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
   }
   RPB_LAUNCHED(ctx);
-  RPB_TRY(timing_end(ctx, stream, t0, double(nrows) * double(n)));
+  RPB_TRY(timing_end(ctx, stream, t0, double(nrows) * double(n),
+                     (f64 ? 0 : 2) + (has_t ? 1 : 0)));
 
   const double scale = 1.0 / (8.0 * M_PI * p->eta);
   reduce_partials<<<blocks_for(nrows, 256), 256, 0, stream>>>(nrows, int(nchunks), part,

@@ -2,8 +2,8 @@
 // applied to the source's force and torque.  Written once for float64 and float32.
 //
 // Geometry (heights already clamped to z~ = max(z, a), paper App. A eq. effMob):
-//   r = q~_i - q~_j                                   (direct separation)
-//   R = q~_i - (x_j, y_j, -z~_j),  e = R/|R|          (separation from the source image)
+//   r = q~_i - q~_j = (dx, dy, dz)                    (direct separation)
+//   R = q~_i - (x_j, y_j, -z~_j) = (dx, dy, Rz)       (separation from the source image)
 //
 // Unbounded part (Sec. II.B and Sec. III, the RPY forms to which the wall terms are added):
 //   |r| >= 2a:  (1/|r|)[(1 + 2a^2/(3r^2)) I + (1 - 2a^2/r^2) rr/r^2],  rotation: T x r / |r|^3
@@ -11,18 +11,27 @@
 //   (the |r| = 0 limit is the Stokes self-mobility 4/(3a) I and no rotation coupling).
 //
 // Wall part: the Faxen operators of eq. mobilityDifferential applied to the image system of
-// Blake's Green's function collapse, with A = a/|R|, hh = z~_j/|R| and ez = e_z, to
+// Blake's Green's function collapse, with e = R/|R|, X = a^2/|R|^2, Y = X^2, hh = z~_j/|R|,
+// ez = e_z, to
 //   8 pi eta W_tt = (1/|R|)[c1 I + c2 e e^T + c3 e z^T + c4 z e^T + c5 z z^T]
-//     c1 = -1 + A^2(2ez^2 - 2/3) + A^4(2/3 - 10/3 ez^2) - 2 ez hh + 2 hh^2
-//     c2 = -1 + A^2(2 - 10 ez^2) + A^4(70/3 ez^2 - 10/3) + 6 ez hh - 6 hh^2
-//     c3 = hh(2 - 12 ez^2) + 12 ez hh^2 + A^2(20 ez^3 - 4 ez) + A^4(40/3 ez - 140/3 ez^3)
-//     c4 = 2 hh - 20/3 A^4 ez
-//     c5 = -4 hh^2 - 4 A^2 ez^2 + A^4(20 ez^2 - 8/3)
+//     c1 = -1 + X(2ez^2 - 2/3) + Y(2/3 - 10/3 ez^2) - 2 ez hh + 2 hh^2
+//     c2 = -1 + X(2 - 10 ez^2) + Y(70/3 ez^2 - 10/3) + 6 ez hh - 6 hh^2
+//     c3 = hh(2 - 12 ez^2) + 12 ez hh^2 + X(20 ez^3 - 4 ez) + Y(40/3 ez - 140/3 ez^3)
+//     c4 = 2 hh - 20/3 Y ez
+//     c5 = -4 hh^2 - 4 X ez^2 + Y(20 ez^2 - 8/3)
 // and those of eq. mobilityDifferentialTR to
 //   8 pi eta W_tr T = (1/|R|^2)[ e x T + d2 (T x z) + (d3 e + d4 z) ((e x z) . T) ]
-//     d2 = 2 A^2 ez + 2 hh,  d3 = 10 A^2 ez - 6 ez + 6 hh,  d4 = -2 A^2.
+//     d2 = 2 X ez + 2 hh,  d3 = 10 X ez - 6 ez + 6 hh,  d4 = -2 X.
 // The same expressions hold at i = j (R = (0, 0, 2 z~_i)), where they reduce to the wall
 // self-mobility, so the self term needs no separate branch.
+//
+// Evaluation order (fewest operations): with t = hh (hh - ez), p = X(2 - 10/3 X) and
+// q = 20/3 Y, the coefficients are
+//     c1 = -1 + 2t - 2/3 (X - Y) + ez^2 p          c2 = -1 - 6t + p + ez^2 (q - 5p)
+//     c3 = 2hh + 12 ez t + ez[(q - 2p) + ez^2 (10p - 2q)]
+//     c4 = 2hh - ez q                               c5 = -4hh^2 - 4X ez^2 + Y(20 ez^2 - 8/3)
+// and since r and R share their horizontal part rho = (dx, dy), unbounded and wall terms
+// merge into one coefficient for F, one for rho and a z remainder.
 //
 // Every value here carries the factor 8 pi eta; the caller divides once per target.
 #pragma once
@@ -65,8 +74,8 @@ __device__ __forceinline__ double rsqrt_r(double x) {
   return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
 
-// Contribution of source j to the velocity of target i (8 pi eta units).
-// dx, dy: horizontal separation x_i - x_j, y_i - y_j; zi, zj: clamped heights.
+// Contribution of source j to the velocity of target i (8 pi eta units), stored into
+// (ox, oy, oz); the caller accumulates.  dx, dy: x_i - x_j, y_i - y_j; zi, zj: clamped heights;
 // f: the source's weighted force; t: its weighted torque (used when TORQUE).
 template <typename Real, bool TORQUE>
 __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj, Real fx, Real fy,
@@ -79,16 +88,16 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   const Real r2 = rho2 + dz * dz;
   const Real R2 = rho2 + Rz * Rz;
   const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
-  const Real invR = rsqrt_r(R2);
+  const Real iR = rsqrt_r(R2);
 
-  // unbounded RPY coefficients: U = cI F + cRR r (r.F) [+ cT T x r]
+  // unbounded RPY: cI F + cRR r (r.F) [+ cT T x r]
   Real cI, cRR, cT;
   if (r2 >= k.four_a2) {
     const Real ir2 = invr * invr;
     const Real s = k.a2 * ir2;
     cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
-    cRR = invr * ir2 * (Real(1) - Real(2) * s);
     cT = invr * ir2;
+    cRR = cT * (Real(1) - Real(2) * s);
   } else {
     const Real r = r2 * invr;
     cI = k.near_i - k.near_i_r * r;
@@ -97,46 +106,51 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   }
 
   // wall coefficients
-  const Real ex = dx * invR, ey = dy * invR, ez = Rz * invR;
-  const Real hh = zj * invR;
-  const Real A2 = k.a2 * invR * invR;
-  const Real A4 = A2 * A2;
+  const Real iR2 = iR * iR;
+  const Real X = k.a2 * iR2;
+  const Real Y = X * X;
+  const Real ez = Rz * iR;
+  const Real hh = zj * iR;
   const Real ez2 = ez * ez;
-  const Real hh2 = hh * hh;
-  const Real ezhh = ez * hh;
-  const Real c1 = Real(-1) + A2 * (Real(2) * ez2 - Real(2.0 / 3.0)) +
-                  A4 * (Real(2.0 / 3.0) - Real(10.0 / 3.0) * ez2) - Real(2) * ezhh + Real(2) * hh2;
-  const Real c2 = Real(-1) + A2 * (Real(2) - Real(10) * ez2) +
-                  A4 * (Real(70.0 / 3.0) * ez2 - Real(10.0 / 3.0)) + Real(6) * ezhh - Real(6) * hh2;
-  const Real c3 = hh * (Real(2) - Real(12) * ez2) + Real(12) * ezhh * hh +
-                  ez * (A2 * (Real(20) * ez2 - Real(4)) + A4 * (Real(40.0 / 3.0) - Real(140.0 / 3.0) * ez2));
-  const Real c4 = Real(2) * hh - Real(20.0 / 3.0) * A4 * ez;
-  const Real c5 = Real(-4) * hh2 - Real(4) * A2 * ez2 + A4 * (Real(20) * ez2 - Real(8.0 / 3.0));
+  const Real hme = hh - ez;
+  const Real t = hh * hme;
+  const Real p = X * (Real(2) - Real(10.0 / 3.0) * X);
+  const Real q = Real(20.0 / 3.0) * Y;
+  const Real hh2x = Real(2) * hh;
+  const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
+  const Real c2 = ez2 * (q - Real(5) * p) + (Real(-6) * t + (p - Real(1)));
+  const Real c3 = ez * ((q - Real(2) * p) + ez2 * (Real(10) * p - Real(2) * q)) +
+                  (Real(12) * (ez * t) + hh2x);
+  const Real c4 = hh2x - ez * q;
+  const Real c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
 
-  const Real rF = dx * fx + dy * fy + dz * fz;
-  const Real eF = ex * fx + ey * fy + ez * fz;
-  const Real cF = cI + invR * c1;
-  const Real ce = invR * (c2 * eF + c3 * fz);
-  const Real cz = invR * (c4 * eF + c5 * fz);
+  // apply to the force
+  const Real rhoF = dx * fx + dy * fy;
+  const Real rF = rhoF + dz * fz;
+  const Real eF = (rhoF + Rz * fz) * iR;
+  const Real G = c2 * eF + c3 * fz;              // coefficient of e   (times |R|)
+  const Real H = c4 * eF + c5 * fz;              // coefficient of z   (times |R|)
+  const Real A = cI + iR * c1;                   // coefficient of F
   const Real cr = cRR * rF;
-  ox = cF * fx + cr * dx + ce * ex;
-  oy = cF * fy + cr * dy + ce * ey;
-  oz = cF * fz + cr * dz + ce * ez + cz;
+  const Real B = cr + iR2 * G;                   // coefficient of rho
+  ox = A * fx + B * dx;
+  oy = A * fy + B * dy;
+  oz = A * fz + (cr * dz + iR * (G * ez + H));
 
   if (TORQUE) {
-    // unbounded: cT (T x r)
-    ox += cT * (ty * dz - tz * dy);
-    oy += cT * (tz * dx - tx * dz);
-    oz += cT * (tx * dy - ty * dx);
-    // wall: (1/|R|^2)[e x T + d2 (T x z) + (d3 e + d4 z) s],  s = (e x z) . T
-    const Real iR2 = invR * invR;
-    const Real s = ey * tx - ex * ty;
-    const Real d2 = Real(2) * (A2 * ez + hh);
-    const Real d3s = (Real(10) * A2 * ez - Real(6) * ez + Real(6) * hh) * s;
-    const Real d4s = Real(-2) * A2 * s;
-    ox += iR2 * (ey * tz - ez * ty + d2 * ty + d3s * ex);
-    oy += iR2 * (ez * tx - ex * tz - d2 * tx + d3s * ey);
-    oz += iR2 * (d3s * ez + d4s - s);
+    // r x T and R x T share their rho terms: kv = (dy tz, -dx tz, dx ty - dy tx)
+    const Real kx = dy * tz, ky = -(dx * tz), kz = dx * ty - dy * tx;
+    const Real iR3 = iR * iR2;
+    const Real al = iR3 - cT;                        // coefficient of kv
+    const Real xez = X * ez;
+    const Real d2 = Real(2) * xez + hh2x;
+    const Real d3 = Real(10) * xez + Real(6) * hme;
+    const Real s = -(kz * iR);                       // (e x z) . T
+    const Real be = cT * dz + (iR2 * d2 - iR3 * Rz);  // coefficient of (ty, -tx, 0)
+    const Real ga = iR3 * (s * d3);                  // coefficient of rho
+    ox += al * kx + (be * ty + ga * dx);
+    oy += al * ky + (ga * dy - be * tx);
+    oz += al * kz + (iR2 * s) * (d3 * ez - Real(2) * X);
   }
 }
 

@@ -44,8 +44,18 @@ struct DevBuf {
 
 }  // namespace rpb
 
+namespace rpb {
+// Launch shapes of the pair kernels (chosen by the tuner; defaults from measurements).
+struct Tuning {
+  int tpt_f64 = 2;          // targets per lane, float64 kernel (1 or 2)
+  int tpt_mixed = 1;        // targets per lane, mixed kernel (1 or 2)
+  int target_wgs = 4096;    // workgroups to aim for when splitting the sources into chunks
+};
+}  // namespace rpb
+
 struct rpb_ctx {
   int device = 0;
+  rpb::Tuning tune;
   std::string err;
   rpb::DevBuf ws[rpb::WS_NSLOTS];
   void *host_pinned = nullptr;          // small pinned host buffer for device scalars
@@ -53,6 +63,7 @@ struct rpb_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
   std::vector<double> ev_pairs;
+  std::vector<int> ev_kind;             // 2 * (precision == mixed) + (torque present)
   std::vector<hipEvent_t> ev_pool;
 };
 
@@ -98,7 +109,7 @@ int check_finite(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream)
 
 // Timing hooks around the pair kernel.
 int timing_begin(rpb_ctx *ctx, hipStream_t stream, hipEvent_t *start);
-int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs);
+int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs, int kind);
 
 // ---- mobility product (matvec.hip) ------------------------------------------------------
 
