@@ -188,13 +188,63 @@ int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cfg, rpb_s
              const double *w, const double *w_tilde, int *iters_out, double *eps_out,
              rpb_stream_t stream);
 
+/* Batched suspensions -----------------------------------------------------------------------
+ *
+ * nsys independent suspensions, concatenated: sphere i of system s is row offs[s] + i of
+ * every [n_total][3] device array, n_total = offs[nsys].  `offs` is a HOST array of nsys + 1
+ * non-decreasing int64 with offs[0] = 0 (empty systems allowed).  Spheres of different systems
+ * do not interact.  One persistent launch of the pair kernel serves all systems: work items
+ * (system, target tile, source chunk) are sorted by cost, largest first, and pulled from a
+ * device counter by a fixed grid of workgroups, so uneven sizes share the whole GPU.
+ * Each system's result equals the single-system call on its own rows (same arithmetic, the
+ * summation order over sources may differ).  1 <= nsys <= 4096 for the Lanczos and step
+ * calls. */
+int rpb_mobility_matvec_batched(rpb_ctx *ctx, const rpb_params *p, int32_t nsys,
+                                const int64_t *offs, const double *pos, const double *force,
+                                const double *torque, double *vel_out, rpb_stream_t stream);
+
+/* One Lanczos process per system (tolerance test per system; a converged system is frozen
+ * while the others continue).  iters_out, eps_out: optional HOST arrays of nsys entries.
+ * Returns RPB_ENOCONV if any system missed tol (its output is its last iterate). */
+int lanczos_sqrt_apply_batched(rpb_ctx *ctx, const rpb_params *p, int32_t nsys,
+                               const int64_t *offs, const double *pos, const double *w,
+                               double tol, int max_iter, double *out, int *iters_out,
+                               double *eps_out, rpb_stream_t stream);
+
+/* One SAB / EM step of every system (sab_step per system, all in the same launches).  The
+ * step number `step` selects the device noise (w / w_tilde NULL); have_prev = 0 makes it an
+ * EM step.  pos and u_prev ([n_total][3], device) are updated in place; the caller advances
+ * its step counter.  iters_out, eps_out: optional HOST arrays of nsys entries. */
+int sab_step_batched(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cfg, int32_t nsys,
+                     const int64_t *offs, double *pos, double *u_prev, int64_t step,
+                     int have_prev, const double *w, const double *w_tilde, int *iters_out,
+                     double *eps_out, rpb_stream_t stream);
+
+/* A batched step captured in a hipGraph.  Creation runs one warm-up step on scratch copies
+ * (the caller's arrays are not modified), then captures the step bound to `pos` and `u_prev`
+ * with the Lanczos budget cfg->lanczos_max_iter (converged systems are frozen on the device;
+ * no host synchronisation inside the step).  Each rpb_step_graph_launch advances pos, u_prev
+ * and the device step counter (starting at `step`, with `have_prev`) by one step on `stream`.
+ * The graph owns a private context and workspace; it must be destroyed before the arrays are
+ * freed.  rpb_step_graph_status synchronises `stream` and reports the step counter and the
+ * per-system Lanczos iterations / eps of the last step. */
+typedef struct rpb_graph rpb_graph;
+int rpb_step_graph_create(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cfg,
+                          int32_t nsys, const int64_t *offs, double *pos, double *u_prev,
+                          int64_t step, int have_prev, rpb_graph **out, rpb_stream_t stream);
+int rpb_step_graph_launch(rpb_graph *g, rpb_stream_t stream);
+int rpb_step_graph_status(rpb_graph *g, int64_t *step_out, int *iters_out, double *eps_out,
+                          rpb_stream_t stream);
+void rpb_step_graph_destroy(rpb_graph *g);
+
 /* Timing ------------------------------------------------------------------------------------
  *
  * When enabled, the library brackets every launch of the O(N^2) pair kernel with HIP
  * events on the stream it is launched on.  rpb_timing_read() synchronises, returns the
  * summed kernel time in milliseconds, the number of launches and the number of ordered
  * pair interactions of the launches of kernel variant `kind`, and removes them from the
- * record.  kind = 2 * (precision == RPB_MIXED) + (torque present); kind = -1 takes all. */
+ * record.  kind = 2 * (precision == RPB_MIXED) + (torque present), plus 4 for the batched
+ * kernel; kind = -1 takes all. */
 int rpb_timing_enable(rpb_ctx *ctx, int enable);
 int rpb_timing_read(rpb_ctx *ctx, int kind, double *ms_out, int64_t *launches_out,
                     double *pairs_out);

@@ -25,6 +25,9 @@ EXPORTS = (
     "rpb_create", "rpb_destroy", "rpb_last_error", "rpb_version",
     "rpb_mobility_matvec", "rpb_mobility_matvec_rows", "lanczos_sqrt_apply", "rfd_drift",
     "rpb_forces", "rpb_normals", "sab_step", "rpb_timing_enable", "rpb_timing_read",
+    "rpb_mobility_matvec_batched", "lanczos_sqrt_apply_batched", "sab_step_batched",
+    "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
+    "rpb_step_graph_destroy",
 )
 
 
@@ -81,6 +84,15 @@ def load(path: str = LIB_PATH):
                                C.POINTER(C.c_int), C.POINTER(D), P]),
         "rpb_timing_enable": (C.c_int, [P, C.c_int]),
         "rpb_timing_read": (C.c_int, [P, C.c_int, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
+        "rpb_mobility_matvec_batched": (C.c_int, [P, pp, C.c_int32, P, P, P, P, P, P]),
+        "lanczos_sqrt_apply_batched": (C.c_int, [P, pp, C.c_int32, P, P, P, D, C.c_int, P, P, P, P]),
+        "sab_step_batched": (C.c_int, [P, pp, C.POINTER(RpbSabConfig), C.c_int32, P, P, P, I64,
+                                       C.c_int, P, P, P, P, P]),
+        "rpb_step_graph_create": (C.c_int, [P, pp, C.POINTER(RpbSabConfig), C.c_int32, P, P, P,
+                                            I64, C.c_int, C.POINTER(C.c_void_p), P]),
+        "rpb_step_graph_launch": (C.c_int, [P, P]),
+        "rpb_step_graph_status": (C.c_int, [P, C.POINTER(I64), P, P, P]),
+        "rpb_step_graph_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -109,6 +121,27 @@ def _vec3(t, name, n=None):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t
+
+
+def _offsets(offs, n=None):
+    import numpy as np
+    o = np.ascontiguousarray(np.asarray(offs, dtype=np.int64))
+    if o.ndim != 1 or o.size < 2 or o[0] != 0 or np.any(np.diff(o) < 0):
+        raise ValueError("offs must be 1-D non-decreasing int64 prefix sums starting at 0")
+    if n is not None and o[-1] != n:
+        raise ValueError(f"offs[-1] = {o[-1]} but the arrays hold {n} spheres")
+    return o
+
+
+def _np_ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision, f_grav_z,
+                torque, steric_u0, steric_b, seed):
+    return RpbSabConfig(dt, delta, lanczos_tol, lanczos_max_iter, 0 if scheme == "sab" else 1,
+                        PRECISIONS[rfd_precision], f_grav_z, (C.c_double * 3)(*torque),
+                        steric_u0, steric_b, seed)
 
 
 def _stream():
@@ -227,6 +260,81 @@ class Context:
         self._check(st)
         return out
 
+    # -- batched suspensions -------------------------------------------------------------
+    def matvec_batched(self, pos, offs, force=None, torque=None, precision="fp64", out=None):
+        """Products of `len(offs) - 1` independent systems concatenated in `pos`."""
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        o = _offsets(offs, n)
+        if force is not None:
+            _vec3(force, "force", n)
+        if torque is not None:
+            _vec3(torque, "torque", n)
+        if out is None:
+            out = torch.empty_like(pos)
+        p = self.params(precision)
+        st = self.lib.rpb_mobility_matvec_batched(self.h, C.byref(p), o.size - 1, _np_ptr(o),
+                                                  _ptr(pos), _ptr(force), _ptr(torque), _ptr(out),
+                                                  _stream())
+        self._check(st)
+        return out
+
+    def lanczos_batched(self, pos, offs, w, tol, max_iter=64, precision="fp64", out=None,
+                        allow_noconv=False):
+        """Returns (g, iterations per system, eps per system, status)."""
+        import numpy as np
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        o = _offsets(offs, n)
+        _vec3(w, "w", n)
+        if out is None:
+            out = torch.empty_like(pos)
+        nsys = o.size - 1
+        it = np.zeros(nsys, dtype=np.int32)
+        eps = np.zeros(nsys, dtype=np.float64)
+        p = self.params(precision)
+        st = self.lib.lanczos_sqrt_apply_batched(self.h, C.byref(p), nsys, _np_ptr(o), _ptr(pos),
+                                                 _ptr(w), float(tol), int(max_iter), _ptr(out),
+                                                 _np_ptr(it), _np_ptr(eps), _stream())
+        self._check(st, (RPB_OK, RPB_ENOCONV) if allow_noconv else (RPB_OK,))
+        return out, it, eps, st
+
+    def sab_step_batched(self, pos, u_prev, offs, step, have_prev, *, dt, delta, lanczos_tol,
+                         lanczos_max_iter=64, scheme="sab", rfd_precision="fp64", f_grav_z=-1.0,
+                         torque=(0.0, 1.0, 0.0), steric_u0=1.0, steric_b=0.1, seed=0,
+                         precision="fp64", w=None, w_tilde=None):
+        """One step of every system; updates pos and u_prev in place.
+        Returns (iterations per system, eps per system, status)."""
+        import numpy as np
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        _vec3(u_prev, "u_prev", n)
+        o = _offsets(offs, n)
+        nsys = o.size - 1
+        cfg = _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision,
+                          f_grav_z, torque, steric_u0, steric_b, seed)
+        it = np.zeros(nsys, dtype=np.int32)
+        eps = np.zeros(nsys, dtype=np.float64)
+        p = self.params(precision)
+        st = self.lib.sab_step_batched(self.h, C.byref(p), C.byref(cfg), nsys, _np_ptr(o),
+                                       _ptr(pos), _ptr(u_prev), int(step), int(bool(have_prev)),
+                                       _ptr(w), _ptr(w_tilde), _np_ptr(it), _np_ptr(eps),
+                                       _stream())
+        self._check(st, (RPB_OK, RPB_ENOCONV))
+        return it, eps, st
+
+    def step_graph(self, pos, u_prev, offs, step=0, have_prev=False, *, dt, delta, lanczos_tol,
+                   lanczos_max_iter=16, scheme="sab", rfd_precision="fp64", f_grav_z=-1.0,
+                   torque=(0.0, 1.0, 0.0), steric_u0=1.0, steric_b=0.1, seed=0,
+                   precision="fp64"):
+        """A hipGraph of one batched step bound to pos / u_prev (see StepGraph)."""
+        return StepGraph(self, pos, u_prev, offs, step, have_prev,
+                         _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme,
+                                     rfd_precision, f_grav_z, torque, steric_u0, steric_b, seed),
+                         precision)
+
     # -- time step -----------------------------------------------------------------------
     def sab_step(self, state, *, dt, delta, lanczos_tol, lanczos_max_iter=64, scheme="sab",
                  rfd_precision="fp64", f_grav_z=-1.0, torque=(0.0, 1.0, 0.0), steric_u0=1.0,
@@ -277,3 +385,52 @@ class StepState:
         self.u_prev = torch.zeros_like(pos)
         self.step = 0
         self.have_prev = False
+
+
+class StepGraph:
+    """A captured batched SAB step: each launch() advances the bound arrays by one step."""
+
+    def __init__(self, ctx, pos, u_prev, offs, step, have_prev, cfg, precision):
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        _vec3(u_prev, "u_prev", n)
+        self.ctx = ctx
+        self.offs = _offsets(offs, n)
+        self.nsys = self.offs.size - 1
+        self._keep = (pos, u_prev)          # the graph writes into these tensors
+        self.cfg = cfg
+        p = ctx.params(precision)
+        h = C.c_void_p()
+        st = ctx.lib.rpb_step_graph_create(ctx.h, C.byref(p), C.byref(cfg), self.nsys,
+                                           _np_ptr(self.offs), _ptr(pos), _ptr(u_prev), int(step),
+                                           int(bool(have_prev)), C.byref(h), _stream())
+        ctx._check(st)
+        self.h = h
+
+    def launch(self):
+        st = self.ctx.lib.rpb_step_graph_launch(self.h, _stream())
+        if st != RPB_OK:
+            raise RpbError(st, "rpb_step_graph_launch failed")
+
+    def status(self):
+        """(device step counter, iterations per system, eps per system, status) of the last step."""
+        import numpy as np
+        step = C.c_int64(0)
+        it = np.zeros(self.nsys, dtype=np.int32)
+        eps = np.zeros(self.nsys, dtype=np.float64)
+        st = self.ctx.lib.rpb_step_graph_status(self.h, C.byref(step), _np_ptr(it), _np_ptr(eps),
+                                                _stream())
+        if st not in (RPB_OK, RPB_ENOCONV):
+            raise RpbError(st, "rpb_step_graph_status failed")
+        return step.value, it, eps, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rpb_step_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -115,11 +115,19 @@ int rpb_create(int hip_device, rpb_ctx **out) {
   c->device = hip_device;
   if (const char *v = getenv("RPB_TPT_F64")) c->tune.tpt_f64 = atoi(v) == 2 ? 2 : 1;
   if (const char *v = getenv("RPB_TPT_MIXED")) c->tune.tpt_mixed = atoi(v) == 2 ? 2 : 1;
+  if (const char *v = getenv("RPB_BATCH_CHUNK")) {
+    const int w = atoi(v);
+    if (w >= 256 && w <= 1 << 20 && w % 256 == 0) c->tune.batch_chunk = w;
+  }
+  if (const char *v = getenv("RPB_BATCH_WGS")) {
+    const int w = atoi(v);
+    if (w >= 1 && w <= 1 << 20) c->tune.batch_wgs = w;
+  }
   if (const char *v = getenv("RPB_TARGET_WGS")) {
     const int w = atoi(v);
     if (w >= 1 && w <= 1 << 20) c->tune.target_wgs = w;
   }
-  if (hipHostMalloc(&c->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&c->host_pinned, kHostScratchBytes, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return RPB_ENOMEM;
   }
@@ -137,6 +145,7 @@ void rpb_destroy(rpb_ctx *ctx) {
   for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
   delete ctx;
 }
 

@@ -39,6 +39,7 @@ struct LzState {
   int m;
   int reason;     // 0 running, 1 converged, 2 breakdown, 3 not SPD, 4 eigensolve failed
 };
+static_assert(sizeof(LzState) % 8 == 0, "LzState is an array of doubles and two ints");
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   const int t = threadIdx.x;
@@ -148,7 +149,7 @@ __global__ void basis_combine(int64_t m, int nvec, const double *__restrict__ V,
 // scalar recurrence and stores the same values into the single LDS copy of (d, e); a
 // wavefront's LDS accesses complete in program order, so no barrier is needed until the
 // end, and the column rotations of Z touch only the lane's own row.
-__global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st) {
+__device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   __shared__ double Z[kMaxKrylov * 64];   // Z[col * 64 + row]
   __shared__ double Dg[kMaxKrylov];       // diagonal, becomes the eigenvalues
   __shared__ double Eg[kMaxKrylov];       // subdiagonal e[i] couples i and i + 1
@@ -270,6 +271,10 @@ __global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *_
   }
 }
 
+__global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st) {
+  tridiag_body(m, tol, st);
+}
+
 __global__ void lz_reset(LzState *st) {
   const int t = threadIdx.x;
   if (t < kMaxKrylov) {
@@ -285,6 +290,157 @@ __global__ void lz_reset(LzState *st) {
     st->m = 0;
     st->reason = 0;
   }
+}
+
+// ---- batched Lanczos: one Krylov process per system, segments of the concatenated vectors ----
+//
+// System s owns elements [3 offs[s], 3 offs[s+1]) of every 3n vector and its own LzState.
+// done[s] != 0 freezes a system: every kernel skips it, so a system stops changing once its
+// own tolerance or breakdown test is met, whatever the others do.
+
+constexpr int kSegBlocks = 16;      // partial sums per system segment
+
+struct SegView {
+  const int64_t *offs;    // nsys + 1 (device)
+  const int *sys_of;      // sphere -> system (device)
+  LzState *st;            // nsys states
+  int *done;              // nsys flags
+};
+
+// part[s * kSegBlocks + b] = partial dot of a and b over system s
+__global__ __launch_bounds__(kThreads) void seg_dot_partial(SegView v, const double *__restrict__ a,
+                                                            const double *__restrict__ b,
+                                                            double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int s = blockIdx.y;
+  if (v.done[s]) return;
+  const int64_t e0 = 3 * v.offs[s], e1 = 3 * v.offs[s + 1];
+  double acc = 0.0;
+  for (int64_t i = e0 + int64_t(blockIdx.x) * kThreads + threadIdx.x; i < e1;
+       i += int64_t(kSegBlocks) * kThreads)
+    acc += a[i] * b[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[int64_t(s) * kSegBlocks + blockIdx.x] = r;
+}
+
+// st[s].<field at double offset `field`> = sum (mode 0) or sqrt(sum) (mode 1)
+__global__ __launch_bounds__(64) void seg_dot_finish(SegView v, const double *__restrict__ part,
+                                                     int field, int mode) {
+  const int s = blockIdx.x;
+  if (v.done[s] || threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int b = 0; b < kSegBlocks; ++b) acc += part[int64_t(s) * kSegBlocks + b];
+  reinterpret_cast<double *>(v.st + s)[field] = mode == 1 ? sqrt(acc) : acc;
+}
+
+// y = x / st[s].<field> on every live system (zero when the divisor is not positive)
+__global__ void seg_scale_by_inverse(SegView v, int64_t m, const double *__restrict__ x, int field,
+                                     double *__restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int s = v.sys_of[i / 3];
+  if (v.done[s]) return;
+  const double d = reinterpret_cast<const double *>(v.st + s)[field];
+  y[i] = d > 0.0 ? x[i] / d : 0.0;
+}
+
+__global__ void seg_three_term(SegView v, int64_t m, int k, double *__restrict__ u,
+                               const double *__restrict__ vk, const double *__restrict__ vprev) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int s = v.sys_of[i / 3];
+  if (v.done[s]) return;
+  double x = u[i] - v.st[s].alpha[k - 1] * vk[i];
+  if (vprev) x -= v.st[s].beta[k - 2] * vprev[i];
+  u[i] = x;
+}
+
+// part[(s * nvec + j) * kSegBlocks + b] = partial dot of V_j and u over system s
+__global__ __launch_bounds__(kThreads) void seg_reorth_dots(SegView v, int64_t m, int nvec,
+                                                            const double *__restrict__ V,
+                                                            const double *__restrict__ u,
+                                                            double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int s = blockIdx.z, j = blockIdx.y;
+  if (v.done[s]) return;
+  const int64_t e0 = 3 * v.offs[s], e1 = 3 * v.offs[s + 1];
+  const double *vj = V + int64_t(j) * m;
+  double acc = 0.0;
+  for (int64_t i = e0 + int64_t(blockIdx.x) * kThreads + threadIdx.x; i < e1;
+       i += int64_t(kSegBlocks) * kThreads)
+    acc += vj[i] * u[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t(s) * nvec + j) * kSegBlocks + blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(64) void seg_reorth_finish(SegView v, int nvec,
+                                                        const double *__restrict__ part) {
+  const int s = blockIdx.x;
+  if (v.done[s]) return;
+  for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < kSegBlocks; ++b) acc += part[(int64_t(s) * nvec + j) * kSegBlocks + b];
+    v.st[s].h[j] = acc;
+  }
+}
+
+__global__ void seg_reorth_update(SegView v, int64_t m, int nvec, const double *__restrict__ V,
+                                  double *__restrict__ u) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int s = v.sys_of[i / 3];
+  if (v.done[s]) return;
+  double proj = 0.0;
+  for (int j = 0; j < nvec; ++j) proj += v.st[s].h[j] * V[int64_t(j) * m + i];
+  u[i] -= proj;
+}
+
+__global__ __launch_bounds__(64) void tridiag_sqrt_batched(SegView v, int m, double tol) {
+  const int s = blockIdx.x;
+  if (v.done[s]) return;
+  tridiag_body(m, tol, v.st + s);
+  if (threadIdx.x == 0 && v.st[s].reason != 0) v.done[s] = 1;
+}
+
+// out = V_m y_m per system (m = the system's own iteration count)
+__global__ void seg_basis_combine(SegView v, int64_t m, const double *__restrict__ V,
+                                  double *__restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const LzState &st = v.st[v.sys_of[i / 3]];
+  double acc = 0.0;
+  for (int j = 0; j < st.m; ++j) acc += st.y[j] * V[int64_t(j) * m + i];
+  out[i] = acc;
+}
+
+__global__ void lz_reset_batched(SegView v, int nsys) {
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  LzState *st = v.st + s;
+  const int t = threadIdx.x;
+  if (t < kMaxKrylov) {
+    st->alpha[t] = 0.0;
+    st->beta[t] = 0.0;
+    st->y[t] = 0.0;
+    st->yprev[t] = 0.0;
+    st->h[t] = 0.0;
+  }
+  if (t == 0) {
+    st->wnorm = 0.0;
+    st->eps = 0.0;
+    st->m = 0;
+    st->reason = 0;
+    v.done[s] = 0;
+  }
+}
+
+// compact status record per system: (m, reason, eps)
+__global__ void lz_status_batched(SegView v, int nsys, LzStatus *__restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys) return;
+  out[s].m = v.st[s].m;
+  out[s].reason = v.st[s].reason;
+  out[s].eps = v.st[s].eps;
 }
 
 inline unsigned nblk(int64_t m) { return unsigned((m + kThreads - 1) / kThreads); }
@@ -313,10 +469,11 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   double *part = static_cast<double *>(
       workspace(ctx, WS_REDUCE, size_t(kRedBlocks) * kMaxKrylov * sizeof(double), &st));
   if (!part) return st;
-  LzState *ls = static_cast<LzState *>(workspace(ctx, WS_SMALL, 1 << 16, &st));
+  LzState *ls = static_cast<LzState *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
   if (!ls) return st;
   LzState *host = static_cast<LzState *>(host_scratch(ctx));
-  static_assert(sizeof(LzState) <= 4096, "status must fit the pinned scratch");
+  static_assert(sizeof(LzState) <= 4096 && sizeof(LzState) <= kSmallWorkCounter,
+                "status must fit the pinned scratch and the start of the small slot");
 
   lz_reset<<<1, 64, 0, stream>>>(ls);
   RPB_LAUNCHED(ctx);
@@ -371,6 +528,114 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   return RPB_OK;
 }
 
+
+int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
+                        const double *w, double tol, int max_iter, double *out, bool sync_each,
+                        LzStatus *status_host, hipStream_t stream) {
+  const int64_t n = g.n;
+  const int64_t m3 = 3 * n;
+  const int nsys = b.nsys;
+  int st;
+  double *V = static_cast<double *>(
+      workspace(ctx, WS_KRYLOV, size_t(max_iter) * size_t(m3) * sizeof(double), &st));
+  if (!V) return st;
+  double *u = static_cast<double *>(workspace(ctx, WS_VEC_A, size_t(m3) * sizeof(double), &st));
+  if (!u) return st;
+  double *part = static_cast<double *>(workspace(
+      ctx, WS_REDUCE, size_t(nsys) * kMaxKrylov * kSegBlocks * sizeof(double), &st));
+  if (!part) return st;
+  const size_t states_bytes = size_t(nsys) * sizeof(LzState);
+  const size_t status_off = (states_bytes + size_t(nsys) * sizeof(int) + 255) / 256 * 256;
+  char *lz = static_cast<char *>(
+      workspace(ctx, WS_LZBATCH, status_off + size_t(nsys) * sizeof(LzStatus), &st));
+  if (!lz) return st;
+  SegView v{b.offs, b.sys_of, reinterpret_cast<LzState *>(lz),
+            reinterpret_cast<int *>(lz + states_bytes)};
+  LzStatus *status_dev = reinterpret_cast<LzStatus *>(lz + status_off);
+  const unsigned ns = unsigned(nsys);
+  const int f_alpha = int(offsetof(LzState, alpha) / sizeof(double));
+  const int f_beta = int(offsetof(LzState, beta) / sizeof(double));
+  const int f_wnorm = int(offsetof(LzState, wnorm) / sizeof(double));
+  auto seg_dot = [&](const double *a, const double *c, int field, int mode) -> int {
+    seg_dot_partial<<<dim3{unsigned(kSegBlocks), ns, 1u}, kThreads, 0, stream>>>(v, a, c, part);
+    RPB_LAUNCHED(ctx);
+    seg_dot_finish<<<ns, 64, 0, stream>>>(v, part, field, mode);
+    RPB_LAUNCHED(ctx);
+    return RPB_OK;
+  };
+
+  lz_reset_batched<<<ns, 64, 0, stream>>>(v, nsys);
+  RPB_LAUNCHED(ctx);
+  RPB_TRY(seg_dot(w, w, f_wnorm, 1));
+  seg_scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(v, m3, w, f_wnorm, V);
+  RPB_LAUNCHED(ctx);
+  int *host_done = static_cast<int *>(host_scratch(ctx));
+  for (int k = 1; k <= max_iter; ++k) {
+    double *vk = V + int64_t(k - 1) * m3;
+    const double *vprev = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
+    RPB_TRY(matvec_batched(ctx, p, b, g, vk, nullptr, v.done, u, stream));
+    RPB_TRY(seg_dot(vk, u, f_alpha + k - 1, 0));
+    seg_three_term<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, u, vk, vprev);
+    RPB_LAUNCHED(ctx);
+    seg_reorth_dots<<<dim3{unsigned(kSegBlocks), unsigned(k), ns}, kThreads, 0, stream>>>(
+        v, m3, k, V, u, part);
+    RPB_LAUNCHED(ctx);
+    seg_reorth_finish<<<ns, 64, 0, stream>>>(v, k, part);
+    RPB_LAUNCHED(ctx);
+    seg_reorth_update<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, V, u);
+    RPB_LAUNCHED(ctx);
+    RPB_TRY(seg_dot(u, u, f_beta + k - 1, 1));
+    tridiag_sqrt_batched<<<ns, 64, 0, stream>>>(v, k, tol);
+    RPB_LAUNCHED(ctx);
+    if (k < max_iter) {
+      seg_scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(v, m3, u, f_beta + k - 1,
+                                                               V + int64_t(k) * m3);
+      RPB_LAUNCHED(ctx);
+    }
+    if (sync_each) {
+      RPB_HIP(ctx, hipMemcpyAsync(host_done, v.done, size_t(nsys) * sizeof(int),
+                                  hipMemcpyDeviceToHost, stream));
+      RPB_HIP(ctx, hipStreamSynchronize(stream));
+      bool all = true;
+      for (int s = 0; s < nsys && all; ++s) all = host_done[s] != 0;
+      if (all) break;
+    }
+  }
+  seg_basis_combine<<<nblk(m3), kThreads, 0, stream>>>(v, m3, V, out);
+  RPB_LAUNCHED(ctx);
+  lz_status_batched<<<(ns + 63) / 64, 64, 0, stream>>>(v, nsys, status_dev);
+  RPB_LAUNCHED(ctx);
+  if (status_host) {
+    RPB_HIP(ctx, hipMemcpyAsync(status_host, status_dev, size_t(nsys) * sizeof(LzStatus),
+                                hipMemcpyDeviceToHost, stream));
+    RPB_HIP(ctx, hipStreamSynchronize(stream));
+  }
+  return RPB_OK;
+}
+
+int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStream_t stream) {
+  const size_t states_bytes = size_t(nsys) * sizeof(LzState);
+  const size_t status_off = (states_bytes + size_t(nsys) * sizeof(int) + 255) / 256 * 256;
+  const DevBuf &b = ctx->ws[WS_LZBATCH];
+  if (!b.ptr || b.bytes < status_off + size_t(nsys) * sizeof(LzStatus))
+    return fail(ctx, RPB_EINVAL, "no batched Lanczos state");
+  RPB_HIP(ctx, hipMemcpyAsync(host, static_cast<char *>(b.ptr) + status_off,
+                              size_t(nsys) * sizeof(LzStatus), hipMemcpyDeviceToHost, stream));
+  RPB_HIP(ctx, hipStreamSynchronize(stream));
+  return RPB_OK;
+}
+
+int lanczos_status_code(rpb_ctx *ctx, const LzStatus *s, int nsys) {
+  int worst = RPB_OK;
+  for (int q = 0; q < nsys; ++q) {
+    if (s[q].reason == 4) return fail(ctx, RPB_EDEVICE, "tridiagonal eigensolve failed (system %d)", q);
+    if (s[q].reason == 3) worst = fail(ctx, RPB_ENOTSPD, "negative Ritz value (system %d)", q);
+    if (s[q].reason == 0 && worst == RPB_OK)
+      worst = fail(ctx, RPB_ENOCONV, "Lanczos tolerance not met (system %d, eps %.3e)", q, s[q].eps);
+  }
+  return worst;
+}
+
 }  // namespace rpb
 
 using namespace rpb;
@@ -396,4 +661,41 @@ extern "C" int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, 
   Packed g;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
   return lanczos_run(ctx, p, g, w, tol, max_iter, out, iters_out, eps_out, stream);
+}
+
+extern "C" int lanczos_sqrt_apply_batched(rpb_ctx *ctx, const rpb_params *p, int32_t nsys,
+                                          const int64_t *offs, const double *pos,
+                                          const double *w, double tol, int max_iter, double *out,
+                                          int *iters_out, double *eps_out, rpb_stream_t stream_) {
+  RPB_TRY(check_params(ctx, p));
+  RPB_TRY(check_offsets(ctx, nsys, offs));
+  if (nsys > kMaxBatchSystems)
+    return fail(ctx, RPB_EINVAL, "at most %d systems per batch", kMaxBatchSystems);
+  if (!(tol > 0.0)) return fail(ctx, RPB_EINVAL, "tol must be > 0");
+  if (max_iter < 1 || max_iter > kMaxKrylov)
+    return fail(ctx, RPB_EINVAL, "max_iter must be in [1, %d]", kMaxKrylov);
+  const int64_t n = offs[nsys];
+  for (int s = 0; s < nsys; ++s) {
+    if (iters_out) iters_out[s] = 0;
+    if (eps_out) eps_out[s] = 0.0;
+  }
+  if (n == 0) return RPB_OK;
+  if (!pos || !w || !out) return fail(ctx, RPB_EINVAL, "pos, w and out must not be NULL");
+  const size_t nb = size_t(n) * 3 * sizeof(double);
+  if (overlaps(out, nb, pos, nb) || overlaps(out, nb, w, nb))
+    return fail(ctx, RPB_EINVAL, "out overlaps an input");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  RPB_HIP(ctx, hipSetDevice(ctx->device));
+  RPB_TRY(check_finite(ctx, pos, n, stream));
+  Batch b;
+  RPB_TRY(prepare_batch(ctx, nsys, offs, p->precision, &b, stream));
+  Packed g;
+  RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
+  LzStatus *stat = static_cast<LzStatus *>(host_scratch(ctx));
+  RPB_TRY(lanczos_batched_run(ctx, p, b, g, w, tol, max_iter, out, true, stat, stream));
+  for (int s = 0; s < nsys; ++s) {
+    if (iters_out) iters_out[s] = stat[s].m;
+    if (eps_out) eps_out[s] = stat[s].eps;
+  }
+  return lanczos_status_code(ctx, stat, nsys);
 }

@@ -1,19 +1,24 @@
 // Matrix-free product U = M F + M_C T of the regularised Rotne-Prager-Blake mobility.
 //
 // Direct summation over all ordered pairs (paper, Sec. II.B): the pair tensor is evaluated
-// on the fly (pair_tensor.h) and never stored, so the kernel is bound by the vector ALUs,
+// on the fly (pair_tensor.h) and never stored, so the kernels are bound by the vector ALUs,
 // not by HBM.  Layout:
 //   pack_geometry   O(N)   AoS float64 positions -> SoA clamped heights, weights H0(z/a)
 //                          (App. A, eq. effMob); mixed precision splits x, y into
 //                          float32 hi + lo so that near-pair separations keep ~1e-7 accuracy
 //                          far from the origin.
 //   pack_vectors    O(N)   AoS float64 force/torque -> SoA H-weighted source vectors.
-//   pair_kernel     O(N^2) grid (target tile, source chunk); each workgroup stages source
-//                          tiles in LDS and every lane accumulates one target; float64
-//                          sums, or float32 sums with Kahan compensation.
+//   pair kernels    O(N^2) a workgroup owns a tile of targets (kBlock lanes x TPT targets per
+//                          lane) and streams a range of sources through LDS; float64 sums, or
+//                          float32 sums per LDS tile added with Kahan compensation.
+//                            * single system: grid (target tile, source chunk);
+//                            * batched systems: persistent workgroups pull (system, target
+//                              tile, source chunk) items, largest first, from a counter.
 //   reduce_partials O(N S) fixed-order sum over source chunks, times H_i / (8 pi eta).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <numeric>
 
 #include "pair_tensor.h"
 #include "rpb_internal.h"
@@ -22,7 +27,7 @@ namespace rpb {
 
 namespace {
 
-constexpr int kBlock = 256;           // lanes per workgroup = targets per tile = sources per LDS tile
+constexpr int kBlock = 256;   // lanes per workgroup = targets per tile row = sources per LDS tile
 
 struct GeomD {         // float64 geometry: x, y, z~ and H, n each
   const double *x, *y, *z, *h;
@@ -85,13 +90,6 @@ __global__ void pack_vectors(int64_t n, const double *__restrict__ h,
   }
 }
 
-struct PairArgs {
-  int64_t n;        // sources (and geometry size)
-  int64_t row0;     // first target
-  int64_t nrows;    // number of targets
-  int64_t chunk;    // sources per workgroup (multiple of kBlock)
-};
-
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
   const float y = v - c;
   const float t = s + y;
@@ -99,128 +97,132 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
   s = t;
 }
 
-// float64 pair kernel.  Workgroup = kBlock lanes x TPT targets per lane; the source chunk
-// blockIdx.y is streamed through LDS in tiles of kBlock.  Output:
-// partial[(chunk * 3 + comp) * nrows + row].
-template <bool TORQUE, int TPT>
-__global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g,
-                                                          const double *__restrict__ src,
-                                                          PairConsts<double> k,
-                                                          double *__restrict__ partial) {
-  __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
-  __shared__ double sf[3][kBlock];
-  __shared__ double st[TORQUE ? 3 : 1][kBlock];
+// ---- workgroup-level building blocks shared by the single and batched kernels ---------------
 
-  const int tid = threadIdx.x;
-  const int64_t n = args.n;
-  int64_t r[TPT];
-  double xi[TPT], yi[TPT], zi[TPT], u[TPT][3];
+template <bool TORQUE>
+struct LdsD {
+  double x[kBlock], y[kBlock], z[kBlock];
+  double f[3][kBlock];
+  double t[TORQUE ? 3 : 1][kBlock];
+};
+template <bool TORQUE>
+struct LdsF {
+  float xh[kBlock], xl[kBlock], yh[kBlock], yl[kBlock], z[kBlock];
+  float f[3][kBlock];
+  float t[TORQUE ? 3 : 1][kBlock];
+};
+
+template <int TPT>
+struct TargetsD {
+  double x[TPT], y[TPT], z[TPT];
+  double u[TPT][3];
+};
+template <int TPT>
+struct TargetsF {
+  float xh[TPT], xl[TPT], yh[TPT], yl[TPT], z[TPT];
+  float s[TPT][3], c[TPT][3];     // Kahan sum and compensation
+};
+
+// Load the lane's targets: rows first + q * kBlock + tid for q < TPT (row `safe` when out of
+// range, which keeps every load in bounds; such targets are never stored).
+template <int TPT>
+__device__ __forceinline__ void load_targets(const GeomD &g, int64_t first, int64_t end,
+                                             int64_t safe, TargetsD<TPT> &T) {
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
-    r[q] = int64_t(blockIdx.x) * (kBlock * TPT) + q * kBlock + tid;
-    const int64_t i = args.row0 + (r[q] < args.nrows ? r[q] : 0);
-    xi[q] = g.x[i];
-    yi[q] = g.y[i];
-    zi[q] = g.z[i];
-    u[q][0] = u[q][1] = u[q][2] = 0.0;
+    const int64_t r = first + q * kBlock + threadIdx.x;
+    const int64_t i = r < end ? r : safe;
+    T.x[q] = g.x[i];
+    T.y[q] = g.y[i];
+    T.z[q] = g.z[i];
+    T.u[q][0] = T.u[q][1] = T.u[q][2] = 0.0;
   }
-  const int64_t jb = int64_t(blockIdx.y) * args.chunk;
-  const int64_t je = min(n, jb + args.chunk);
+}
+template <int TPT>
+__device__ __forceinline__ void load_targets(const GeomF &g, int64_t first, int64_t end,
+                                             int64_t safe, TargetsF<TPT> &T) {
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int64_t r = first + q * kBlock + threadIdx.x;
+    const int64_t i = r < end ? r : safe;
+    T.xh[q] = g.xh[i];
+    T.xl[q] = g.xl[i];
+    T.yh[q] = g.yh[i];
+    T.yl[q] = g.yl[i];
+    T.z[q] = g.z[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) T.s[q][d] = T.c[q][d] = 0.f;
+  }
+}
 
+// Accumulate sources [jb, je) into the lane's targets.  `n` is the stride of the source
+// arrays.  Every lane of the workgroup must call this (it synchronises).
+template <bool TORQUE, int TPT>
+__device__ __forceinline__ void sources_f64(const GeomD &g, const double *__restrict__ src,
+                                            int64_t n, int64_t jb, int64_t je,
+                                            const PairConsts<double> &k, LdsD<TORQUE> &L,
+                                            TargetsD<TPT> &T) {
+  const int tid = threadIdx.x;
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
     if (tid < cnt) {
       const int64_t j = t0 + tid;
-      sx[tid] = g.x[j];
-      sy[tid] = g.y[j];
-      sz[tid] = g.z[j];
-      sf[0][tid] = src[j];
-      sf[1][tid] = src[n + j];
-      sf[2][tid] = src[2 * n + j];
+      L.x[tid] = g.x[j];
+      L.y[tid] = g.y[j];
+      L.z[tid] = g.z[j];
+      L.f[0][tid] = src[j];
+      L.f[1][tid] = src[n + j];
+      L.f[2][tid] = src[2 * n + j];
       if (TORQUE) {
-        st[0][tid] = src[3 * n + j];
-        st[1][tid] = src[4 * n + j];
-        st[2][tid] = src[5 * n + j];
+        L.t[0][tid] = src[3 * n + j];
+        L.t[1][tid] = src[4 * n + j];
+        L.t[2][tid] = src[5 * n + j];
       }
     }
     __syncthreads();
 #pragma unroll 2
     for (int j = 0; j < cnt; ++j) {
-      const double xj = sx[j], yj = sy[j], zj = sz[j];
-      const double fx = sf[0][j], fy = sf[1][j], fz = sf[2][j];
-      const double tx = TORQUE ? st[0][j] : 0.0, ty = TORQUE ? st[1][j] : 0.0,
-                   tz = TORQUE ? st[2][j] : 0.0;
+      const double xj = L.x[j], yj = L.y[j], zj = L.z[j];
+      const double fx = L.f[0][j], fy = L.f[1][j], fz = L.f[2][j];
+      const double tx = TORQUE ? L.t[0][j] : 0.0, ty = TORQUE ? L.t[1][j] : 0.0,
+                   tz = TORQUE ? L.t[2][j] : 0.0;
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
         double ox, oy, oz;
-        pair_velocity<double, TORQUE>(xi[q] - xj, yi[q] - yj, zi[q], zj, fx, fy, fz, tx, ty, tz,
-                                      k, ox, oy, oz);
-        u[q][0] += ox;
-        u[q][1] += oy;
-        u[q][2] += oz;
+        pair_velocity<double, TORQUE>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, tx, ty,
+                                      tz, k, ox, oy, oz);
+        T.u[q][0] += ox;
+        T.u[q][1] += oy;
+        T.u[q][2] += oz;
       }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    if (r[q] < args.nrows) {
-      const int64_t base = int64_t(blockIdx.y) * 3 * args.nrows + r[q];
-      partial[base] = u[q][0];
-      partial[base + args.nrows] = u[q][1];
-      partial[base + 2 * args.nrows] = u[q][2];
     }
   }
 }
 
-// Mixed pair kernel: float32 pair terms, float32 sums over each LDS tile of kBlock sources,
-// tile sums added with Kahan compensation per target, float64 partials.
 template <bool TORQUE, int TPT>
-__global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF g,
-                                                            const float *__restrict__ src,
-                                                            PairConsts<float> k,
-                                                            double *__restrict__ partial) {
-  __shared__ float sxh[kBlock], sxl[kBlock], syh[kBlock], syl[kBlock], sz[kBlock];
-  __shared__ float sf[3][kBlock];
-  __shared__ float st[TORQUE ? 3 : 1][kBlock];
-
+__device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__restrict__ src,
+                                              int64_t n, int64_t jb, int64_t je,
+                                              const PairConsts<float> &k, LdsF<TORQUE> &L,
+                                              TargetsF<TPT> &T) {
   const int tid = threadIdx.x;
-  const int64_t n = args.n;
-  int64_t r[TPT];
-  float xih[TPT], xil[TPT], yih[TPT], yil[TPT], zi[TPT];
-  float s[TPT][3], c[TPT][3];
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    r[q] = int64_t(blockIdx.x) * (kBlock * TPT) + q * kBlock + tid;
-    const int64_t i = args.row0 + (r[q] < args.nrows ? r[q] : 0);
-    xih[q] = g.xh[i];
-    xil[q] = g.xl[i];
-    yih[q] = g.yh[i];
-    yil[q] = g.yl[i];
-    zi[q] = g.z[i];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) s[q][d] = c[q][d] = 0.f;
-  }
-  const int64_t jb = int64_t(blockIdx.y) * args.chunk;
-  const int64_t je = min(n, jb + args.chunk);
-
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
     if (tid < cnt) {
       const int64_t j = t0 + tid;
-      sxh[tid] = g.xh[j];
-      sxl[tid] = g.xl[j];
-      syh[tid] = g.yh[j];
-      syl[tid] = g.yl[j];
-      sz[tid] = g.z[j];
-      sf[0][tid] = src[j];
-      sf[1][tid] = src[n + j];
-      sf[2][tid] = src[2 * n + j];
+      L.xh[tid] = g.xh[j];
+      L.xl[tid] = g.xl[j];
+      L.yh[tid] = g.yh[j];
+      L.yl[tid] = g.yl[j];
+      L.z[tid] = g.z[j];
+      L.f[0][tid] = src[j];
+      L.f[1][tid] = src[n + j];
+      L.f[2][tid] = src[2 * n + j];
       if (TORQUE) {
-        st[0][tid] = src[3 * n + j];
-        st[1][tid] = src[4 * n + j];
-        st[2][tid] = src[5 * n + j];
+        L.t[0][tid] = src[3 * n + j];
+        L.t[1][tid] = src[4 * n + j];
+        L.t[2][tid] = src[5 * n + j];
       }
     }
     __syncthreads();
@@ -229,16 +231,16 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
     for (int q = 0; q < TPT; ++q) a[q][0] = a[q][1] = a[q][2] = 0.f;
 #pragma unroll 2
     for (int j = 0; j < cnt; ++j) {
-      const float xjh = sxh[j], xjl = sxl[j], yjh = syh[j], yjl = syl[j], zj = sz[j];
-      const float fx = sf[0][j], fy = sf[1][j], fz = sf[2][j];
-      const float tx = TORQUE ? st[0][j] : 0.f, ty = TORQUE ? st[1][j] : 0.f,
-                  tz = TORQUE ? st[2][j] : 0.f;
+      const float xjh = L.xh[j], xjl = L.xl[j], yjh = L.yh[j], yjl = L.yl[j], zj = L.z[j];
+      const float fx = L.f[0][j], fy = L.f[1][j], fz = L.f[2][j];
+      const float tx = TORQUE ? L.t[0][j] : 0.f, ty = TORQUE ? L.t[1][j] : 0.f,
+                  tz = TORQUE ? L.t[2][j] : 0.f;
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
-        const float dx = (xih[q] - xjh) + (xil[q] - xjl);
-        const float dy = (yih[q] - yjh) + (yil[q] - yjl);
+        const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+        const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
         float ox, oy, oz;
-        pair_velocity<float, TORQUE>(dx, dy, zi[q], zj, fx, fy, fz, tx, ty, tz, k, ox, oy, oz);
+        pair_velocity<float, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, ox, oy, oz);
         a[q][0] += ox;
         a[q][1] += oy;
         a[q][2] += oz;
@@ -247,17 +249,79 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
 #pragma unroll
     for (int q = 0; q < TPT; ++q)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) kahan_add(s[q][d], c[q][d], a[q][d]);
+      for (int d = 0; d < 3; ++d) kahan_add(T.s[q][d], T.c[q][d], a[q][d]);
   }
+}
+
+// partial[(chunk * 3 + comp) * stride + (row - base_row)] for the lane's targets below `end`
+template <int TPT>
+__device__ __forceinline__ void store_partial(const TargetsD<TPT> &T, int64_t first, int64_t end,
+                                              int64_t chunk, int64_t stride, int64_t base_row,
+                                              double *__restrict__ partial) {
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
-    if (r[q] < args.nrows) {
-      const int64_t base = int64_t(blockIdx.y) * 3 * args.nrows + r[q];
-      partial[base] = double(s[q][0]) - double(c[q][0]);
-      partial[base + args.nrows] = double(s[q][1]) - double(c[q][1]);
-      partial[base + 2 * args.nrows] = double(s[q][2]) - double(c[q][2]);
+    const int64_t r = first + q * kBlock + threadIdx.x;
+    if (r < end) {
+      const int64_t o = chunk * 3 * stride + (r - base_row);
+      partial[o] = T.u[q][0];
+      partial[o + stride] = T.u[q][1];
+      partial[o + 2 * stride] = T.u[q][2];
     }
   }
+}
+template <int TPT>
+__device__ __forceinline__ void store_partial(const TargetsF<TPT> &T, int64_t first, int64_t end,
+                                              int64_t chunk, int64_t stride, int64_t base_row,
+                                              double *__restrict__ partial) {
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int64_t r = first + q * kBlock + threadIdx.x;
+    if (r < end) {
+      const int64_t o = chunk * 3 * stride + (r - base_row);
+      partial[o] = double(T.s[q][0]) - double(T.c[q][0]);
+      partial[o + stride] = double(T.s[q][1]) - double(T.c[q][1]);
+      partial[o + 2 * stride] = double(T.s[q][2]) - double(T.c[q][2]);
+    }
+  }
+}
+
+// ---- single system: grid (target tile, source chunk) -----------------------------------------
+
+struct PairArgs {
+  int64_t n;        // sources (and geometry size)
+  int64_t row0;     // first target
+  int64_t nrows;    // number of targets
+  int64_t chunk;    // sources per workgroup (multiple of kBlock)
+};
+
+template <bool TORQUE, int TPT>
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g,
+                                                          const double *__restrict__ src,
+                                                          PairConsts<double> k,
+                                                          double *__restrict__ partial) {
+  __shared__ LdsD<TORQUE> L;
+  TargetsD<TPT> T;
+  const int64_t first = args.row0 + int64_t(blockIdx.x) * (kBlock * TPT);
+  const int64_t end = args.row0 + args.nrows;
+  load_targets<TPT>(g, first, end, args.row0, T);
+  const int64_t jb = int64_t(blockIdx.y) * args.chunk;
+  sources_f64<TORQUE, TPT>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
+  store_partial<TPT>(T, first, end, blockIdx.y, args.nrows, args.row0, partial);
+}
+
+template <bool TORQUE, int TPT>
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF g,
+                                                            const float *__restrict__ src,
+                                                            PairConsts<float> k,
+                                                            double *__restrict__ partial) {
+  __shared__ LdsF<TORQUE> L;
+  TargetsF<TPT> T;
+  const int64_t first = args.row0 + int64_t(blockIdx.x) * (kBlock * TPT);
+  const int64_t end = args.row0 + args.nrows;
+  load_targets<TPT>(g, first, end, args.row0, T);
+  const int64_t jb = int64_t(blockIdx.y) * args.chunk;
+  sources_mixed<TORQUE, TPT>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
+  store_partial<TPT>(T, first, end, blockIdx.y, args.nrows, args.row0, partial);
 }
 
 __global__ void reduce_partials(int64_t nrows, int nchunks, const double *__restrict__ partial,
@@ -273,6 +337,95 @@ __global__ void reduce_partials(int64_t nrows, int nchunks, const double *__rest
   }
 }
 
+// ---- batched systems: persistent workgroups over a cost-ordered item list -------------------
+
+struct BatchArgs {
+  const int64_t *offs;   // nsys + 1 prefix sums (device)
+  const int4 *items;     // (system, target tile, source chunk, 0), largest first
+  int nitems;
+  int *counter;          // work counter (reset to 0 before the launch)
+  int64_t n;             // total spheres (stride of every array)
+  int64_t chunk;         // sources per item
+  const int *done;       // optional per-system flags: items of finished systems are skipped
+};
+
+// Pull the next item for the workgroup (-1 when the list is exhausted).  Every workgroup
+// keeps pulling until the counter passes nitems, so every wave reaches the exit.
+__device__ __forceinline__ int next_item(const BatchArgs &b, int *slot) {
+  __syncthreads();
+  if (threadIdx.x == 0) slot[0] = atomicAdd(b.counter, 1);
+  __syncthreads();
+  const int it = slot[0];
+  return it < b.nitems ? it : -1;
+}
+
+template <bool TORQUE, int TPT>
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64_batched(BatchArgs b, GeomD g,
+                                                                  const double *__restrict__ src,
+                                                                  PairConsts<double> k,
+                                                                  double *__restrict__ partial) {
+  __shared__ LdsD<TORQUE> L;
+  __shared__ int slot[1];
+  for (int it = next_item(b, slot); it >= 0; it = next_item(b, slot)) {
+    const int4 w = b.items[it];
+    if (b.done && b.done[w.x]) continue;
+    const int64_t s0 = b.offs[w.x], s1 = b.offs[w.x + 1];
+    TargetsD<TPT> T;
+    const int64_t first = s0 + int64_t(w.y) * (kBlock * TPT);
+    load_targets<TPT>(g, first, s1, s0, T);
+    const int64_t jb = s0 + int64_t(w.z) * b.chunk;
+    sources_f64<TORQUE, TPT>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
+    store_partial<TPT>(T, first, s1, w.z, b.n, 0, partial);
+  }
+}
+
+template <bool TORQUE, int TPT>
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_batched(BatchArgs b, GeomF g,
+                                                                    const float *__restrict__ src,
+                                                                    PairConsts<float> k,
+                                                                    double *__restrict__ partial) {
+  __shared__ LdsF<TORQUE> L;
+  __shared__ int slot[1];
+  for (int it = next_item(b, slot); it >= 0; it = next_item(b, slot)) {
+    const int4 w = b.items[it];
+    if (b.done && b.done[w.x]) continue;
+    const int64_t s0 = b.offs[w.x], s1 = b.offs[w.x + 1];
+    TargetsF<TPT> T;
+    const int64_t first = s0 + int64_t(w.y) * (kBlock * TPT);
+    load_targets<TPT>(g, first, s1, s0, T);
+    const int64_t jb = s0 + int64_t(w.z) * b.chunk;
+    sources_mixed<TORQUE, TPT>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
+    store_partial<TPT>(T, first, s1, w.z, b.n, 0, partial);
+  }
+}
+
+__global__ void reduce_partials_batched(int64_t n, const int *__restrict__ sys_of,
+                                        const int64_t *__restrict__ offs, int64_t chunk,
+                                        const int *__restrict__ done,
+                                        const double *__restrict__ partial,
+                                        const double *__restrict__ h, double scale,
+                                        double *__restrict__ vel) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int s = sys_of[r];
+  if (done && done[s]) return;
+  const int64_t nch = (offs[s + 1] - offs[s] + chunk - 1) / chunk;
+  const double w = scale * h[r];
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;
+    for (int64_t q = 0; q < nch; ++q) acc += partial[(q * 3 + c) * n + r];
+    vel[3 * r + c] = w * acc;
+  }
+}
+
+__global__ void fill_sys_of(int nsys, const int64_t *__restrict__ offs, int *__restrict__ sys_of) {
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  for (int64_t i = offs[s] + threadIdx.x; i < offs[s + 1]; i += blockDim.x) sys_of[i] = s;
+}
+
+__global__ void zero_int(int *p) { p[0] = 0; }
+
 __global__ void finite_flag(int64_t m, const double *__restrict__ v, int *__restrict__ flag) {
   int bad = 0;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
@@ -281,19 +434,36 @@ __global__ void finite_flag(int64_t m, const double *__restrict__ v, int *__rest
   if (bad) flag[0] = 1;   // benign race: every writer stores the same value
 }
 
-__global__ void zero_int(int *p) { p[0] = 0; }
-
 inline unsigned blocks_for(int64_t n, int threads) {
   return unsigned((n + threads - 1) / threads);
+}
+
+int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const double *torque,
+                 void **src, hipStream_t stream) {
+  const int64_t n = g.n;
+  const bool f64 = g.precision == RPB_FP64;
+  const size_t esz = f64 ? sizeof(double) : sizeof(float);
+  int st;
+  *src = workspace(ctx, WS_SRC, size_t(6 * n) * esz, &st);
+  if (!*src) return st;
+  const double *h = f64 ? geom_d(g).h : geom_f(g).h;
+  if (f64)
+    pack_vectors<double><<<blocks_for(n, 256), 256, 0, stream>>>(n, h, force, torque,
+                                                                 static_cast<double *>(*src));
+  else
+    pack_vectors<float><<<blocks_for(n, 256), 256, 0, stream>>>(n, h, force, torque,
+                                                                static_cast<float *>(*src));
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
 }
 
 }  // namespace
 
 int check_finite(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream) {
   int st;
-  int *flag = static_cast<int *>(workspace(ctx, WS_SMALL, 1 << 16, &st));
-  if (!flag) return st;
-  int *f = flag + (1 << 14) - 1;  // last int of the small slot's first 64 KiB
+  char *small = static_cast<char *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
+  if (!small) return st;
+  int *f = reinterpret_cast<int *>(small + kSmallFiniteFlag);
   zero_int<<<1, 1, 0, stream>>>(f);
   RPB_LAUNCHED(ctx);
   const int64_t m = 3 * n;
@@ -334,18 +504,9 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   if (nrows <= 0) return RPB_OK;
   const bool has_t = torque != nullptr;
   const bool f64 = g.precision == RPB_FP64;
-  const size_t esz = f64 ? sizeof(double) : sizeof(float);
-  int st;
-  void *src = workspace(ctx, WS_SRC, size_t(6 * n) * esz, &st);
-  if (!src) return st;
+  void *src;
+  RPB_TRY(pack_sources(ctx, g, force, torque, &src, stream));
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
-  if (f64)
-    pack_vectors<double><<<blocks_for(n, 256), 256, 0, stream>>>(n, h, force, torque,
-                                                                 static_cast<double *>(src));
-  else
-    pack_vectors<float><<<blocks_for(n, 256), 256, 0, stream>>>(n, h, force, torque,
-                                                                static_cast<float *>(src));
-  RPB_LAUNCHED(ctx);
 
   // Source chunking: enough workgroups to fill the chip several times over.  The chunks
   // depend on n only (not on the row range), so every target sums its sources in the same
@@ -362,6 +523,7 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   if (tiles > 0x7fffffff || nchunks > 65535)
     return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
 
+  int st;
   double *part = static_cast<double *>(
       workspace(ctx, WS_PART, size_t(nchunks) * 3 * size_t(nrows) * sizeof(double), &st));
   if (!part) return st;
@@ -403,6 +565,163 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   reduce_partials<<<blocks_for(nrows, 256), 256, 0, stream>>>(nrows, int(nchunks), part,
                                                               h + row0, scale, vel);
   RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+// ---- batched -----------------------------------------------------------------------------
+
+int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
+                  hipStream_t stream) {
+  const int tpt = precision == RPB_FP64 ? ctx->tune.tpt_f64 : ctx->tune.tpt_mixed;
+  const int64_t chunk = ctx->tune.batch_chunk;
+  b->nsys = nsys;
+  b->n = offs[nsys];
+  b->chunk = chunk;
+  b->tpt = tpt;
+  b->host_offs.assign(offs, offs + nsys + 1);
+  // work items, largest (targets x sources) first; ties keep (system, tile, chunk) order
+  std::vector<int4> items;
+  std::vector<double> cost;
+  const int64_t per = int64_t(kBlock) * tpt;
+  for (int s = 0; s < nsys; ++s) {
+    const int64_t ns = offs[s + 1] - offs[s];
+    for (int64_t t = 0; t * per < ns; ++t)
+      for (int64_t c = 0; c * chunk < ns; ++c) {
+        items.push_back(int4{s, int(t), int(c), 0});
+        cost.push_back(double(std::min(per, ns - t * per)) *
+                       double(std::min(chunk, ns - c * chunk)));
+      }
+  }
+  std::vector<size_t> order(items.size());
+  std::iota(order.begin(), order.end(), size_t(0));
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t c) { return cost[a] > cost[c]; });
+  int64_t max_chunks = 1;
+  for (int s = 0; s < nsys; ++s)
+    max_chunks = std::max<int64_t>(max_chunks, (offs[s + 1] - offs[s] + chunk - 1) / chunk);
+  b->nitems = int(items.size());
+  b->max_chunks = max_chunks;
+  std::vector<int2> tiles;
+  for (int s = 0; s < nsys; ++s)
+    for (int64_t t = 0; t * kBlock < offs[s + 1] - offs[s]; ++t) tiles.push_back(int2{s, int(t)});
+  b->ntiles = int(tiles.size());
+
+  // device copies: offs (nsys + 1 int64), items, sys_of (n int32); staged through pinned memory
+  const size_t offs_bytes = size_t(nsys + 1) * sizeof(int64_t);
+  const size_t items_bytes = std::max<size_t>(1, items.size()) * sizeof(int4);
+  const size_t offs_pad = (offs_bytes + 255) / 256 * 256;
+  const size_t items_pad = (items_bytes + 255) / 256 * 256;
+  const size_t tiles_bytes = std::max<size_t>(1, tiles.size()) * sizeof(int2);
+  const size_t tiles_pad = (tiles_bytes + 255) / 256 * 256;
+  const size_t sys_bytes = size_t(std::max<int64_t>(1, b->n)) * sizeof(int);
+  int st;
+  char *dev = static_cast<char *>(
+      workspace(ctx, WS_BATCH, offs_pad + items_pad + tiles_pad + sys_bytes, &st));
+  if (!dev) return st;
+  b->offs = reinterpret_cast<int64_t *>(dev);
+  b->items = reinterpret_cast<int4 *>(dev + offs_pad);
+  b->tiles = reinterpret_cast<int2 *>(dev + offs_pad + items_pad);
+  b->sys_of = reinterpret_cast<int *>(dev + offs_pad + items_pad + tiles_pad);
+  const size_t host_bytes = offs_pad + items_pad + tiles_pad;
+  // the pinned staging buffer may still feed an earlier copy
+  RPB_HIP(ctx, hipStreamSynchronize(stream));
+  if (ctx->batch_host_bytes < host_bytes) {
+    if (ctx->batch_host) RPB_HIP(ctx, hipHostFree(ctx->batch_host));
+    ctx->batch_host = nullptr;
+    ctx->batch_host_bytes = 0;
+    RPB_HIP(ctx, hipHostMalloc(&ctx->batch_host, host_bytes, hipHostMallocDefault));
+    ctx->batch_host_bytes = host_bytes;
+  }
+  char *hb = static_cast<char *>(ctx->batch_host);
+  std::memcpy(hb, offs, offs_bytes);
+  int4 *hi = reinterpret_cast<int4 *>(hb + offs_pad);
+  for (size_t q = 0; q < order.size(); ++q) hi[q] = items[order[q]];
+  int2 *ht = reinterpret_cast<int2 *>(hb + offs_pad + items_pad);
+  std::copy(tiles.begin(), tiles.end(), ht);
+  RPB_HIP(ctx, hipMemcpyAsync(b->offs, hb, offs_bytes, hipMemcpyHostToDevice, stream));
+  if (!items.empty())
+    RPB_HIP(ctx, hipMemcpyAsync(b->items, hi, items.size() * sizeof(int4), hipMemcpyHostToDevice,
+                                stream));
+  if (!tiles.empty())
+    RPB_HIP(ctx, hipMemcpyAsync(b->tiles, ht, tiles.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                stream));
+  fill_sys_of<<<unsigned(nsys), 256, 0, stream>>>(nsys, b->offs, b->sys_of);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
+                   const double *force, const double *torque, const int *done, double *vel,
+                   hipStream_t stream) {
+  const int64_t n = g.n;
+  if (n == 0 || b.nitems == 0) return RPB_OK;
+  const bool has_t = torque != nullptr;
+  const bool f64 = g.precision == RPB_FP64;
+  void *src;
+  RPB_TRY(pack_sources(ctx, g, force, torque, &src, stream));
+  const double *h = f64 ? geom_d(g).h : geom_f(g).h;
+  int st;
+  double *part = static_cast<double *>(
+      workspace(ctx, WS_PART, size_t(b.max_chunks) * 3 * size_t(n) * sizeof(double), &st));
+  if (!part) return st;
+  char *small = static_cast<char *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
+  if (!small) return st;
+  int *counter = reinterpret_cast<int *>(small + kSmallWorkCounter);
+  zero_int<<<1, 1, 0, stream>>>(counter);
+  RPB_LAUNCHED(ctx);
+
+  BatchArgs args{b.offs, b.items, b.nitems, counter, n, b.chunk, done};
+  const unsigned grid = unsigned(std::max(1, std::min(b.nitems, ctx->tune.batch_wgs)));
+  double pairs = 0.0;
+  for (int s = 0; s < b.nsys; ++s) {
+    const double ns = double(b.host_offs[s + 1] - b.host_offs[s]);
+    pairs += ns * ns;
+  }
+  hipEvent_t t0;
+  RPB_TRY(timing_begin(ctx, stream, &t0));
+  const int tpt = b.tpt;
+  if (f64) {
+    const auto k = make_pair_consts<double>(p->a);
+    const double *sv = static_cast<const double *>(src);
+    const GeomD gd = geom_d(g);
+    if (has_t && tpt == 2)
+      pair_kernel_f64_batched<true, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else if (has_t)
+      pair_kernel_f64_batched<true, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_f64_batched<false, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else
+      pair_kernel_f64_batched<false, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+  } else {
+    const auto k = make_pair_consts<float>(p->a);
+    const float *sv = static_cast<const float *>(src);
+    const GeomF gf = geom_f(g);
+    if (has_t && tpt == 2)
+      pair_kernel_mixed_batched<true, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+    else if (has_t)
+      pair_kernel_mixed_batched<true, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_mixed_batched<false, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+    else
+      pair_kernel_mixed_batched<false, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+  }
+  RPB_LAUNCHED(ctx);
+  RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
+  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  reduce_partials_batched<<<blocks_for(n, 256), 256, 0, stream>>>(n, b.sys_of, b.offs, b.chunk,
+                                                                 done, part, h, scale, vel);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+int check_offsets(rpb_ctx *ctx, int32_t nsys, const int64_t *offs) {
+  if (nsys < 1) return fail(ctx, RPB_EINVAL, "nsys must be >= 1");
+  if (!offs) return fail(ctx, RPB_EINVAL, "offs must not be NULL");
+  if (offs[0] != 0) return fail(ctx, RPB_EINVAL, "offs[0] must be 0");
+  for (int s = 0; s < nsys; ++s)
+    if (offs[s + 1] < offs[s]) return fail(ctx, RPB_EINVAL, "offs must be non-decreasing");
+  if (offs[nsys] > (int64_t(1) << 31) - 1)
+    return fail(ctx, RPB_EINVAL, "too many spheres for one batch");
   return RPB_OK;
 }
 
@@ -449,6 +768,29 @@ int rpb_mobility_matvec_rows(rpb_ctx *ctx, const rpb_params *p, int64_t n, const
                              const double *force, const double *torque, int64_t row_begin,
                              int64_t row_end, double *vel_out, rpb_stream_t stream) {
   return matvec_entry(ctx, p, n, pos, force, torque, row_begin, row_end, vel_out, stream);
+}
+
+int rpb_mobility_matvec_batched(rpb_ctx *ctx, const rpb_params *p, int32_t nsys,
+                                const int64_t *offs, const double *pos, const double *force,
+                                const double *torque, double *vel_out, rpb_stream_t stream_) {
+  RPB_TRY(check_params(ctx, p));
+  RPB_TRY(check_offsets(ctx, nsys, offs));
+  const int64_t n = offs[nsys];
+  if (n == 0) return RPB_OK;
+  if (!pos || !vel_out) return fail(ctx, RPB_EINVAL, "pos and vel_out must not be NULL");
+  if (!force && !torque) return fail(ctx, RPB_EINVAL, "force and torque are both NULL");
+  const size_t nb = size_t(n) * 3 * sizeof(double);
+  if (overlaps(vel_out, nb, pos, nb) || overlaps(vel_out, nb, force, nb) ||
+      overlaps(vel_out, nb, torque, nb))
+    return fail(ctx, RPB_EINVAL, "vel_out overlaps an input");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  RPB_HIP(ctx, hipSetDevice(ctx->device));
+  RPB_TRY(check_finite(ctx, pos, n, stream));
+  Batch b;
+  RPB_TRY(prepare_batch(ctx, nsys, offs, p->precision, &b, stream));
+  Packed g;
+  RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
+  return matvec_batched(ctx, p, b, g, force, torque, nullptr, vel_out, stream);
 }
 
 }  // extern "C"

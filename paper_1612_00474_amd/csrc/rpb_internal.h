@@ -34,8 +34,16 @@ enum Slot {
   WS_KRYLOV,        // Lanczos basis V (max_iter x 3n)
   WS_REDUCE,        // reduction partials
   WS_SMALL,         // small device scalars (Lanczos coefficients, status, flags)
+  WS_BATCH,         // batched products: offsets, work items, sphere -> system map
+  WS_LZBATCH,       // batched Lanczos: per-system scalars and status
   WS_NSLOTS
 };
+
+// Layout of the WS_SMALL slot.
+constexpr size_t kSmallBytes = 1 << 16;
+constexpr size_t kSmallWorkCounter = 8192;          // int: work counter of persistent kernels
+constexpr size_t kSmallFiniteFlag = kSmallBytes - 4; // int: non-finite input flag
+constexpr size_t kSmallStepState = 16384;           // int64 step, int have_prev (time step)
 
 struct DevBuf {
   void *ptr = nullptr;
@@ -50,6 +58,8 @@ struct Tuning {
   int tpt_f64 = 2;          // targets per lane, float64 kernel (1 or 2)
   int tpt_mixed = 1;        // targets per lane, mixed kernel (1 or 2)
   int target_wgs = 4096;    // workgroups to aim for when splitting the sources into chunks
+  int batch_chunk = 1024;   // sources per work item of the batched kernels (multiple of 256)
+  int batch_wgs = 2048;     // persistent workgroups of the batched kernels
 };
 }  // namespace rpb
 
@@ -59,6 +69,8 @@ struct rpb_ctx {
   std::string err;
   rpb::DevBuf ws[rpb::WS_NSLOTS];
   void *host_pinned = nullptr;          // small pinned host buffer for device scalars
+  void *batch_host = nullptr;           // pinned staging of batched offsets / work items
+  size_t batch_host_bytes = 0;
   // pair-kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -75,7 +87,8 @@ int fail(rpb_ctx *ctx, int code, const char *fmt, ...);
 // Device buffer of at least `bytes` for `slot` (grows; synchronises the device on growth).
 void *workspace(rpb_ctx *ctx, Slot slot, size_t bytes, int *status);
 
-// Pinned host scratch of at least 4 KiB.
+// Pinned host scratch (kHostScratchBytes).
+constexpr size_t kHostScratchBytes = 1 << 17;
 inline void *host_scratch(rpb_ctx *ctx) { return ctx->host_pinned; }
 
 #define RPB_HIP(ctx, call)                                                              \
@@ -131,7 +144,55 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
                   const double *torque, int64_t row0, int64_t nrows, double *vel,
                   hipStream_t stream);
 
+// ---- batched products (matvec.hip) -----------------------------------------------------
+
+// Work list of a batch of independent systems (built on the host, copied to the device).
+struct Batch {
+  int nsys = 0;
+  int64_t n = 0;                 // total spheres
+  int64_t chunk = 0;             // sources per work item
+  int tpt = 1;                   // targets per lane of the launch
+  int nitems = 0;
+  int64_t max_chunks = 0;        // source chunks of the largest system
+  std::vector<int64_t> host_offs;
+  int64_t *offs = nullptr;       // device
+  int4 *items = nullptr;         // device
+  int *sys_of = nullptr;         // device, n entries
+  int2 *tiles = nullptr;         // device: (system, 256-target tile) for the steric kernel
+  int ntiles = 0;
+};
+
+int check_offsets(rpb_ctx *ctx, int32_t nsys, const int64_t *offs);
+int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
+                  hipStream_t stream);
+// Batched product for packed geometry `g` (all systems); systems with done[s] != 0 are
+// skipped (their output rows are left untouched).  `done` may be NULL.
+int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
+                   const double *force, const double *torque, const int *done, double *vel,
+                   hipStream_t stream);
+
 // ---- vector kernels (lanczos.hip) -------------------------------------------------------
+constexpr int kMaxBatchSystems = 4096;   // per-system records must fit the pinned scratch
+
+// Per-system outcome of a batched Lanczos solve.
+struct LzStatus {
+  int m;          // iterations used
+  int reason;     // 0 not converged, 1 converged, 2 breakdown (exact), 3 not SPD, 4 solver failed
+  double eps;     // last relative change
+};
+
+// Batched Lanczos: one Krylov process per system of `b`.  sync_each = true reads the per-system
+// flags after every iteration and stops when all systems are done; false runs max_iter
+// iterations with device-side freezing only (no host synchronisation: capturable).
+// status_host (pinned, nsys records) is filled when not NULL (synchronises).
+int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
+                        const double *w, double tol, int max_iter, double *out, bool sync_each,
+                        LzStatus *status_host, hipStream_t stream);
+// Map per-system outcomes to a status code (first failure wins; ENOCONV when any missed tol).
+int lanczos_status_code(rpb_ctx *ctx, const LzStatus *s, int nsys);
+// Copy the per-system outcomes of the last batched solve (synchronises `stream`).
+int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStream_t stream);
+
 int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *w, double tol,
                 int max_iter, double *out, int *iters, double *eps, hipStream_t stream);
 
@@ -142,5 +203,33 @@ int normals_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id, 
                 double *out, hipStream_t stream);
 int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, double f_grav_z,
                double u0, double b, double *force, hipStream_t stream);
+// Steric forces within each system of a batch (no interaction across systems).
+int forces_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const double *pos,
+                       double f_grav_z, double u0, double b, double *force, hipStream_t stream);
+// Normals for the step number held on the device (*step_dev).
+int normals_devstep_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id,
+                        const int64_t *step_dev, double *out, hipStream_t stream);
+// RFD over a batch of systems.
+int rfd_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const double *pos,
+                    const double *wt, double delta, int rfd_precision, double *drift,
+                    hipStream_t stream);
+
+// ---- time step (step.hip) ---------------------------------------------------------------
+// Device record of a time-stepped batch: read by the noise and update kernels, advanced by
+// the last kernel of a step.
+struct StepRecord {
+  int64_t step;
+  int have_prev;
+};
+int set_step_state(rpb_ctx *ctx, void *step_state, int64_t step, int have_prev,
+                   hipStream_t stream);
+int check_step_config(rpb_ctx *ctx, const rpb_sab_config *cfg);
+// Enqueue one batched step without host synchronisation (capturable).  The step number and
+// the have-previous flag are read from the device record at `step_state` (int64 step, int
+// have_prev) and advanced at the end.
+int step_batched_enqueue(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cfg,
+                         const Batch &bt, double *pos, double *u_prev, const double *w,
+                         const double *w_tilde, void *step_state, bool sync_lanczos,
+                         LzStatus *status_host, hipStream_t stream);
 
 }  // namespace rpb

@@ -60,6 +60,26 @@ __global__ void normals_kernel(int64_t count, uint64_t seed, uint64_t stream_id,
     if (4 * b + q < count) out[4 * b + q] = v[q];
 }
 
+__global__ void normals_kernel_devstep(int64_t count, uint64_t seed, uint64_t stream_id,
+                                      const int64_t *__restrict__ step, double *__restrict__ out) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (4 * b >= count) return;
+  uint64_t x[4] = {uint64_t(b), uint64_t(step[0]), 0ull, 0ull};
+  philox4x64_10(x, seed, stream_id);
+  double v[4];
+#pragma unroll
+  for (int q = 0; q < 4; q += 2) {
+    const double rad = sqrt(-2.0 * log(to_uniform(x[q])));
+    double s, c;
+    sincospi(2.0 * to_uniform(x[q + 1]), &s, &c);
+    v[q] = rad * c;
+    v[q + 1] = rad * s;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (4 * b + q < count) out[4 * b + q] = v[q];
+}
+
 __global__ void shifted_pair(int64_t m, const double *__restrict__ q, const double *__restrict__ w,
                              double half_delta, double *__restrict__ qp, double *__restrict__ qm) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -110,6 +130,44 @@ int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, con
   RPB_TRY(pack_geometry(ctx, &q, n, qm, WS_GEOM2, &gm, stream));
   RPB_TRY(matvec_packed(ctx, &q, gp, wt, nullptr, 0, n, up, stream));
   RPB_TRY(matvec_packed(ctx, &q, gm, wt, nullptr, 0, n, um, stream));
+  scaled_difference<<<nblk(m), 256, 0, stream>>>(m, up, um, p->kT / delta, drift);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+int normals_devstep_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id,
+                        const int64_t *step_dev, double *out, hipStream_t stream) {
+  if (count <= 0) return RPB_OK;
+  const int64_t blocks = (count + 3) / 4;
+  normals_kernel_devstep<<<nblk(blocks), 256, 0, stream>>>(count, seed, stream_id, step_dev, out);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+int rfd_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const double *pos,
+                    const double *wt, double delta, int rfd_precision, double *drift,
+                    hipStream_t stream) {
+  const int64_t n = bt.n;
+  const int64_t m = 3 * n;
+  const size_t vb = size_t(m) * sizeof(double);
+  int st;
+  double *qp = static_cast<double *>(workspace(ctx, WS_VEC_B, vb, &st));
+  if (!qp) return st;
+  double *qm = static_cast<double *>(workspace(ctx, WS_VEC_C, vb, &st));
+  if (!qm) return st;
+  double *up = static_cast<double *>(workspace(ctx, WS_VEC_D, vb, &st));
+  if (!up) return st;
+  double *um = static_cast<double *>(workspace(ctx, WS_VEC_E, vb, &st));
+  if (!um) return st;
+  shifted_pair<<<nblk(m), 256, 0, stream>>>(m, pos, wt, 0.5 * delta, qp, qm);
+  RPB_LAUNCHED(ctx);
+  rpb_params q = *p;
+  q.precision = rfd_precision;
+  Packed gp, gm;
+  RPB_TRY(pack_geometry(ctx, &q, n, qp, WS_GEOM, &gp, stream));
+  RPB_TRY(pack_geometry(ctx, &q, n, qm, WS_GEOM2, &gm, stream));
+  RPB_TRY(matvec_batched(ctx, &q, bt, gp, wt, nullptr, nullptr, up, stream));
+  RPB_TRY(matvec_batched(ctx, &q, bt, gm, wt, nullptr, nullptr, um, stream));
   scaled_difference<<<nblk(m), 256, 0, stream>>>(m, up, um, p->kT / delta, drift);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
