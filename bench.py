@@ -106,6 +106,8 @@ def main():
 
     torch.cuda.init()
     ctx = Context(0, a=w.a, eta=w.eta, kT=w.kT)
+    if w.nsys > 1:
+        return bench_batched(args, w, ctx)
     inp = wl.make_inputs(w, 0)
     pos0 = torch.as_tensor(inp["pos"]).cuda()
     F = torch.as_tensor(inp["force"]).cuda()
@@ -114,6 +116,9 @@ def main():
     step_kw = dict(dt=w.dt, delta=w.delta, lanczos_tol=w.lanczos_tol, lanczos_max_iter=64,
                    rfd_precision="fp64", f_grav_z=w.f_grav_z, torque=w.torque,
                    steric_u0=w.steric_u0, steric_b=w.steric_b, seed=0, precision=prec)
+
+    # ---- launch shapes from the tuner (timed on this configuration, cached per size) -------
+    shapes = {prec_: ctx.autotune(pos0, None, prec_)[0] for prec_ in ("mixed", "fp64")}
 
     # ---- kernel-only product throughput, mixed and float64 (pair kernel, HIP events) ----
     def kernel_rate(precision, reps=3):
@@ -183,6 +188,7 @@ def main():
                    "lanczos_tol": w.lanczos_tol, "precision": prec, "rfd_precision": "fp64",
                    "parallelism": "single GPU"},
         "lanczos_iters": timed_iters,
+        "launch_shapes": shapes,
         "matvec_kernel_pairs_per_s": {"mixed": mixed_rate, "fp64": f64_rate,
                                       "mixed_over_fp64": mixed_rate / f64_rate,
                                       "ms_per_launch": {"mixed": mixed_ms, "fp64": f64_ms}},
@@ -195,6 +201,92 @@ def main():
                      "ms_per_launch": dom["ms_per_launch"], "launches": dom["launches"]},
         "pair_kernels": kinds,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+def bench_batched(args, w, ctx):
+    """Batched suspensions: one persistent launch per product, steps replayed from a hipGraph."""
+    import numpy as np
+    import torch
+    from paper_1612_00474_amd import workloads as wl
+
+    pos_np, offs = wl.make_batch(w, 0)
+    sizes = np.diff(offs)
+    n = int(offs[-1])
+    sum_sq = float(np.sum(sizes.astype(np.float64) ** 2))
+    pos0 = torch.as_tensor(pos_np).cuda()
+    F = torch.as_tensor(np.random.default_rng(0).standard_normal((n, 3))).cuda()
+    shapes = {prec_: ctx.autotune(pos0, offs, prec_)[0] for prec_ in ("mixed", "fp64")}
+
+    def kernel_rate(precision, reps=5):
+        ctx.matvec_batched(pos0, offs, F, None, precision)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.timing_read()
+        for _ in range(reps):
+            ctx.matvec_batched(pos0, offs, F, None, precision)
+        ms, k, pairs = ctx.timing_read()
+        ctx.timing(False)
+        return {"pairs_per_s": pairs / (ms * 1e-3), "ms_per_launch": ms / k,
+                "tflops": FLOPS_PER_PAIR_FORCE * pairs / (ms * 1e-3) / 1e12}
+
+    rates = {"mixed": kernel_rate("mixed"), "fp64": kernel_rate("fp64")}
+    budget = 16
+    kw = dict(dt=w.dt, delta=w.delta, lanczos_tol=w.lanczos_tol, lanczos_max_iter=budget,
+              rfd_precision="fp64", f_grav_z=w.f_grav_z, torque=w.torque, steric_u0=w.steric_u0,
+              steric_b=w.steric_b, seed=0, precision=w.precision)
+    P = pos0.clone()
+    U = torch.zeros_like(P)
+    graph = ctx.step_graph(P, U, offs, 0, False, **kw)
+    for _ in range(args.warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step, iters, eps, _ = graph.status()
+    graph.close()
+    # eager batched steps (host reads the Lanczos flags every iteration) for comparison
+    Pe = pos0.clone()
+    Ue = torch.zeros_like(Pe)
+    ctx.sab_step_batched(Pe, Ue, offs, 0, False, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.sab_step_batched(Pe, Ue, offs, k + 1, True, **kw)
+    torch.cuda.synchronize()
+    eager = time.perf_counter() - t1
+    pairs_step = float(np.sum(sizes.astype(np.float64) ** 2 * (3 + iters)))
+    dom = rates["mixed" if w.precision == "mixed" else "fp64"]
+    peak = PEAK_FP32_TFLOPS if w.precision == "mixed" else PEAK_FP64_TFLOPS
+    line = {
+        "metric": "RPB matvec pair-interactions/s + BD steps/s, batched suspensions",
+        "value": pairs_step * args.steps / elapsed,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps_per_s": args.steps / elapsed,
+        "eager_steps_per_s": args.steps / eager,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if w.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": w.name, "nsys": int(w.nsys), "n_total": n,
+                   "sizes": [int(x) for x in sizes], "sum_n_squared": sum_sq,
+                   "precision": w.precision, "rfd_precision": "fp64",
+                   "lanczos_tol": w.lanczos_tol, "lanczos_budget": budget,
+                   "graph": "one hipGraph launch per step", "parallelism": "single GPU"},
+        "lanczos_iters_last_step": [int(x) for x in iters],
+        "launch_shapes": shapes,
+        "batched_kernel": rates,
+        "roofline": {"bound": "alu", "achieved": dom["tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": dom["tflops"] / peak, "traffic": None,
+                     "kernel": f"batched pair kernel, force-only, {FLOPS_PER_PAIR_FORCE} flop/pair x "
+                               f"sum N_s^2 = {sum_sq:.4e} pairs/launch",
+                     "ms_per_launch": dom["ms_per_launch"]},
+        "cpu_baseline": None,
     }
     print(json.dumps(line))
     ctx.close()

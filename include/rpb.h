@@ -237,6 +237,33 @@ int rpb_step_graph_status(rpb_graph *g, int64_t *step_out, int *iters_out, doubl
                           rpb_stream_t stream);
 void rpb_step_graph_destroy(rpb_graph *g);
 
+/* Launch-shape tuning ---------------------------------------------------------------------
+ *
+ * One shape per precision.  tpt: targets per lane of the pair kernels (1 or 2); target_wgs:
+ * workgroups the single-system kernel aims for when splitting the sources into chunks;
+ * batch_chunk: sources per work item of the batched kernel (multiple of 256); batch_wgs:
+ * persistent workgroups of the batched kernel.  rpb_autotune times the candidates for
+ * p->precision on the given configuration (force-only products, `reps` launches each, HIP
+ * events on `stream`), keeps the fastest in the context and caches it per (precision,
+ * single/batched, floor(log2 n_total)); a cached shape is reused without timing
+ * (best_ms_out = -1 then).  Results depend on the shape only through the order of the
+ * floating-point summation. */
+typedef struct {
+  int tpt;
+  int target_wgs;
+  int batch_chunk;
+  int batch_wgs;
+} rpb_shape;
+typedef struct {
+  rpb_shape fp64;
+  rpb_shape mixed;
+} rpb_tuning;
+int rpb_get_tuning(const rpb_ctx *ctx, rpb_tuning *out);
+int rpb_set_tuning(rpb_ctx *ctx, const rpb_tuning *t);
+int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t *offs,
+                 const double *pos, int reps, rpb_tuning *out, double *best_ms_out,
+                 rpb_stream_t stream);
+
 /* Timing ------------------------------------------------------------------------------------
  *
  * When enabled, the library brackets every launch of the O(N^2) pair kernel with HIP

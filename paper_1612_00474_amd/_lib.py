@@ -27,7 +27,7 @@ EXPORTS = (
     "rpb_forces", "rpb_normals", "sab_step", "rpb_timing_enable", "rpb_timing_read",
     "rpb_mobility_matvec_batched", "lanczos_sqrt_apply_batched", "sab_step_batched",
     "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
-    "rpb_step_graph_destroy",
+    "rpb_step_graph_destroy", "rpb_get_tuning", "rpb_set_tuning", "rpb_autotune",
 )
 
 
@@ -40,6 +40,21 @@ class RpbSabConfig(C.Structure):
                 ("lanczos_max_iter", C.c_int), ("scheme", C.c_int), ("rfd_precision", C.c_int),
                 ("f_grav_z", C.c_double), ("torque", C.c_double * 3), ("steric_u0", C.c_double),
                 ("steric_b", C.c_double), ("seed", C.c_uint64)]
+
+
+class RpbShape(C.Structure):
+    _fields_ = [("tpt", C.c_int), ("target_wgs", C.c_int), ("batch_chunk", C.c_int),
+                ("batch_wgs", C.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class RpbTuning(C.Structure):
+    _fields_ = [("fp64", RpbShape), ("mixed", RpbShape)]
+
+    def as_dict(self):
+        return {"fp64": self.fp64.as_dict(), "mixed": self.mixed.as_dict()}
 
 
 class RpbSabState(C.Structure):
@@ -93,6 +108,10 @@ def load(path: str = LIB_PATH):
         "rpb_step_graph_launch": (C.c_int, [P, P]),
         "rpb_step_graph_status": (C.c_int, [P, C.POINTER(I64), P, P, P]),
         "rpb_step_graph_destroy": (None, [P]),
+        "rpb_get_tuning": (C.c_int, [P, C.POINTER(RpbTuning)]),
+        "rpb_set_tuning": (C.c_int, [P, C.POINTER(RpbTuning)]),
+        "rpb_autotune": (C.c_int, [P, pp, C.c_int32, P, P, C.c_int, C.POINTER(RpbTuning),
+                                   C.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -359,6 +378,30 @@ class Context:
         state.step = s.step
         state.have_prev = bool(s.have_prev)
         return it.value, eps.value, st
+
+    # -- tuning --------------------------------------------------------------------------
+    def tuning(self):
+        t = RpbTuning()
+        self._check(self.lib.rpb_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, precision, **kw):
+        """Change fields of one precision's launch shape (tpt, target_wgs, batch_chunk, batch_wgs)."""
+        cur = self.tuning()
+        cur[precision].update(kw)
+        t = RpbTuning(RpbShape(**cur["fp64"]), RpbShape(**cur["mixed"]))
+        self._check(self.lib.rpb_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, pos, offs=None, precision="mixed", reps=2):
+        """Time the launch-shape candidates on this configuration; returns (shape, best ms)."""
+        pos = _vec3(pos, "pos")
+        o = _offsets([0, pos.shape[0]] if offs is None else offs, pos.shape[0])
+        t = RpbTuning()
+        ms = C.c_double(0.0)
+        p = self.params(precision)
+        self._check(self.lib.rpb_autotune(self.h, C.byref(p), o.size - 1, _np_ptr(o), _ptr(pos),
+                                          int(reps), C.byref(t), C.byref(ms), _stream()))
+        return t.as_dict()[precision], ms.value
 
     # -- timing --------------------------------------------------------------------------
     def timing(self, enable: bool):

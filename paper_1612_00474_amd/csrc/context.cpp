@@ -113,19 +113,21 @@ int rpb_create(int hip_device, rpb_ctx **out) {
   rpb_ctx *c = new (std::nothrow) rpb_ctx();
   if (!c) return RPB_ENOMEM;
   c->device = hip_device;
-  if (const char *v = getenv("RPB_TPT_F64")) c->tune.tpt_f64 = atoi(v) == 2 ? 2 : 1;
-  if (const char *v = getenv("RPB_TPT_MIXED")) c->tune.tpt_mixed = atoi(v) == 2 ? 2 : 1;
-  if (const char *v = getenv("RPB_BATCH_CHUNK")) {
-    const int w = atoi(v);
-    if (w >= 256 && w <= 1 << 20 && w % 256 == 0) c->tune.batch_chunk = w;
-  }
-  if (const char *v = getenv("RPB_BATCH_WGS")) {
-    const int w = atoi(v);
-    if (w >= 1 && w <= 1 << 20) c->tune.batch_wgs = w;
-  }
-  if (const char *v = getenv("RPB_TARGET_WGS")) {
-    const int w = atoi(v);
-    if (w >= 1 && w <= 1 << 20) c->tune.target_wgs = w;
+  // launch-shape overrides for experiments: RPB_<FP64|MIXED>_<TPT|WGS|CHUNK|BWGS>
+  const char *pre[2] = {"RPB_FP64_", "RPB_MIXED_"};
+  for (int q = 0; q < 2; ++q) {
+    auto env = [&](const char *key, int lo, int hi, int mult, int *dst) {
+      const std::string name = std::string(pre[q]) + key;
+      if (const char *v = getenv(name.c_str())) {
+        const int w = atoi(v);
+        if (w >= lo && w <= hi && w % mult == 0) *dst = w;
+      }
+    };
+    Shape &sh = c->tune.s[q];
+    env("TPT", 1, 2, 1, &sh.tpt);
+    env("WGS", 1, 1 << 20, 1, &sh.target_wgs);
+    env("CHUNK", 256, 1 << 20, 256, &sh.batch_chunk);
+    env("BWGS", 1, 1 << 20, 1, &sh.batch_wgs);
   }
   if (hipHostMalloc(&c->host_pinned, kHostScratchBytes, hipHostMallocDefault) != hipSuccess) {
     delete c;

@@ -511,12 +511,13 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   // Source chunking: enough workgroups to fill the chip several times over.  The chunks
   // depend on n only (not on the row range), so every target sums its sources in the same
   // order whichever rows are requested: row shards concatenate to the full product bitwise.
-  const int tpt = f64 ? ctx->tune.tpt_f64 : ctx->tune.tpt_mixed;
+  const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
+  const int tpt = shape.tpt;
   const int64_t per_wg = int64_t(kBlock) * tpt;
   const int64_t tiles = (nrows + per_wg - 1) / per_wg;
   const int64_t tiles_full = (n + per_wg - 1) / per_wg;
   int64_t nchunks =
-      std::max<int64_t>(1, (int64_t(ctx->tune.target_wgs) + tiles_full - 1) / tiles_full);
+      std::max<int64_t>(1, (int64_t(shape.target_wgs) + tiles_full - 1) / tiles_full);
   int64_t chunk = (n + nchunks - 1) / nchunks;
   chunk = std::max<int64_t>(kBlock, (chunk + kBlock - 1) / kBlock * kBlock);
   nchunks = (n + chunk - 1) / chunk;
@@ -572,12 +573,14 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
 
 int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
                   hipStream_t stream) {
-  const int tpt = precision == RPB_FP64 ? ctx->tune.tpt_f64 : ctx->tune.tpt_mixed;
-  const int64_t chunk = ctx->tune.batch_chunk;
+  const Shape &shape = ctx->tune.s[precision == RPB_FP64 ? RPB_FP64 : RPB_MIXED];
+  const int tpt = shape.tpt;
+  const int64_t chunk = shape.batch_chunk;
   b->nsys = nsys;
   b->n = offs[nsys];
   b->chunk = chunk;
   b->tpt = tpt;
+  b->wgs = shape.batch_wgs;
   b->host_offs.assign(offs, offs + nsys + 1);
   // work items, largest (targets x sources) first; ties keep (system, tile, chunk) order
   std::vector<int4> items;
@@ -671,7 +674,7 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
   RPB_LAUNCHED(ctx);
 
   BatchArgs args{b.offs, b.items, b.nitems, counter, n, b.chunk, done};
-  const unsigned grid = unsigned(std::max(1, std::min(b.nitems, ctx->tune.batch_wgs)));
+  const unsigned grid = unsigned(std::max(1, std::min(b.nitems, b.wgs)));
   double pairs = 0.0;
   for (int s = 0; s < b.nsys; ++s) {
     const double ns = double(b.host_offs[s + 1] - b.host_offs[s]);

@@ -5,7 +5,9 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "rpb.h"
@@ -53,19 +55,23 @@ struct DevBuf {
 }  // namespace rpb
 
 namespace rpb {
-// Launch shapes of the pair kernels (chosen by the tuner; defaults from measurements).
+// Launch shape of a pair kernel (chosen by the tuner; defaults from measurements).
+struct Shape {
+  int tpt;          // targets per lane (1 or 2)
+  int target_wgs;   // workgroups to aim for when splitting the sources into chunks
+  int batch_chunk;  // sources per work item of the batched kernel (multiple of 256)
+  int batch_wgs;    // persistent workgroups of the batched kernel
+};
+// One shape per precision, indexed by rpb_precision (RPB_FP64 = 0, RPB_MIXED = 1).
 struct Tuning {
-  int tpt_f64 = 2;          // targets per lane, float64 kernel (1 or 2)
-  int tpt_mixed = 1;        // targets per lane, mixed kernel (1 or 2)
-  int target_wgs = 4096;    // workgroups to aim for when splitting the sources into chunks
-  int batch_chunk = 1024;   // sources per work item of the batched kernels (multiple of 256)
-  int batch_wgs = 2048;     // persistent workgroups of the batched kernels
+  Shape s[2] = {{2, 4096, 1024, 2048}, {1, 4096, 1024, 2048}};
 };
 }  // namespace rpb
 
 struct rpb_ctx {
   int device = 0;
   rpb::Tuning tune;
+  std::map<std::tuple<int, int, int>, rpb::Tuning> tune_cache;   // (precision, batched, log2 n)
   std::string err;
   rpb::DevBuf ws[rpb::WS_NSLOTS];
   void *host_pinned = nullptr;          // small pinned host buffer for device scalars
@@ -152,6 +158,7 @@ struct Batch {
   int64_t n = 0;                 // total spheres
   int64_t chunk = 0;             // sources per work item
   int tpt = 1;                   // targets per lane of the launch
+  int wgs = 1;                   // persistent workgroups of the launch
   int nitems = 0;
   int64_t max_chunks = 0;        // source chunks of the largest system
   std::vector<int64_t> host_offs;

@@ -140,3 +140,26 @@ def test_uneven_batch_rows_sampled(ctx):
         rows = rng.choice(b - a, 8, replace=False)
         ref = mobility.matvec(pos[a:b], F[a:b], None, rows=rows)
         assert rel2(u[a:b][rows], ref) <= 1e-5
+
+
+def test_autotune_picks_a_candidate_and_keeps_parity(ctx):
+    from paper_1612_00474_amd import Context
+    c = Context(0)
+    pos = wl.sheet(3000, seed=8)
+    rng = np.random.default_rng(8)
+    F = rng.standard_normal(pos.shape)
+    P, Fd = dev(pos), dev(F)
+    shape, ms = c.autotune(P, None, "mixed", reps=1)
+    assert shape["tpt"] in (1, 2) and shape["target_wgs"] in (2048, 4096, 8192, 16384) and ms > 0
+    shape2, ms2 = c.autotune(P, None, "mixed", reps=1)      # cached: no timing
+    assert shape2 == shape and ms2 == -1.0
+    ref = mobility.matvec(pos, F, None, rows=np.arange(0, 3000, 50))
+    assert rel2(host(c.matvec(P, Fd, None, "mixed"))[::50], ref) <= 1e-5
+    pos_b, offs, _ = _batch(seed=9)
+    shape_b, _ = c.autotune(dev(pos_b), offs, "fp64", reps=1)
+    assert shape_b["batch_chunk"] in (512, 1024, 2048) and shape_b["batch_wgs"] in (1024, 2048, 4096)
+    Fb = rng.standard_normal(pos_b.shape)
+    u = host(c.matvec_batched(dev(pos_b), offs, dev(Fb), None, "fp64"))
+    a, b = offs[4], offs[5]
+    assert rel2(u[a:b], mobility.dense_matvec(pos_b[a:b], Fb[a:b], None)) <= 1e-12
+    c.close()
