@@ -242,7 +242,9 @@ void rpb_step_graph_destroy(rpb_graph *g);
  * One shape per precision.  tpt: targets per lane of the pair kernels (1 or 2); target_wgs:
  * workgroups the single-system kernel aims for when splitting the sources into chunks;
  * batch_chunk: sources per work item of the batched kernel (multiple of 256); batch_wgs:
- * persistent workgroups of the batched kernel.  rpb_autotune times the candidates for
+ * persistent workgroups of the batched kernel; symmetric: whole-system products without
+ * torque use the symmetric tile-pair kernel (M_ij = M_ji^T: each unordered pair evaluated once,
+ * both directions applied).  rpb_autotune times the candidates for
  * p->precision on the given configuration (force-only products, `reps` launches each, HIP
  * events on `stream`), keeps the fastest in the context and caches it per (precision,
  * single/batched, floor(log2 n_total)); a cached shape is reused without timing
@@ -253,6 +255,7 @@ typedef struct {
   int target_wgs;
   int batch_chunk;
   int batch_wgs;
+  int symmetric;   /* 1: whole-system force-only products evaluate each unordered pair once */
 } rpb_shape;
 typedef struct {
   rpb_shape fp64;

@@ -44,7 +44,7 @@ class RpbSabConfig(C.Structure):
 
 class RpbShape(C.Structure):
     _fields_ = [("tpt", C.c_int), ("target_wgs", C.c_int), ("batch_chunk", C.c_int),
-                ("batch_wgs", C.c_int)]
+                ("batch_wgs", C.c_int), ("symmetric", C.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -386,7 +386,8 @@ class Context:
         return t.as_dict()
 
     def set_tuning(self, precision, **kw):
-        """Change fields of one precision's launch shape (tpt, target_wgs, batch_chunk, batch_wgs)."""
+        """Change fields of one precision's launch shape (tpt, target_wgs, batch_chunk,
+        batch_wgs, symmetric)."""
         cur = self.tuning()
         cur[precision].update(kw)
         t = RpbTuning(RpbShape(**cur["fp64"]), RpbShape(**cur["mixed"]))

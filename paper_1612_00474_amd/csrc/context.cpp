@@ -128,6 +128,7 @@ int rpb_create(int hip_device, rpb_ctx **out) {
     env("WGS", 1, 1 << 20, 1, &sh.target_wgs);
     env("CHUNK", 256, 1 << 20, 256, &sh.batch_chunk);
     env("BWGS", 1, 1 << 20, 1, &sh.batch_wgs);
+    env("SYM", 0, 1, 1, &sh.symmetric);
   }
   if (hipHostMalloc(&c->host_pinned, kHostScratchBytes, hipHostMallocDefault) != hipSuccess) {
     delete c;

@@ -337,6 +337,292 @@ __global__ void reduce_partials(int64_t nrows, int nchunks, const double *__rest
   }
 }
 
+// ---- single system, force-only sources: one evaluation per unordered pair ------------------
+//
+// The mobility matrix is symmetric, so a workgroup owning target tile I and source tile J > I
+// evaluates each pair (i, j) once (pair_velocity_sym) and produces both M_ij F_j (summed per
+// target in registers) and M_ij^T F_i = M_ji F_i (summed per source).  Within a wavefront the
+// sources are taken in blocks of 64 on a rotating schedule: at step k lane l works on source
+// (l + k) mod 64, and the per-source sums travel one lane down per step (DPP wave_rol:1), so
+// after 64 steps lane l holds the complete sum over the wavefront's targets for source
+// (l + 63) mod 64 without any cross-lane reduction.  The wavefronts' sums are added in LDS in
+// a fixed order.  Tile I gets slot (I, J) and tile J gets slot (J, I) of the partial array;
+// diagonal tiles are evaluated as ordered pairs into slot (I, I).  Every target thus receives
+// exactly nt partials, summed in slot order.
+
+struct SymArgs {
+  int64_t n;     // spheres
+  int64_t ts;    // tile size (kBlock * TPT)
+  int64_t nt;    // tiles
+};
+
+// v from lane (l + 1) mod 64 (DPP wave_rol:1)
+__device__ __forceinline__ float wave_rol1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double wave_rol1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), 0x134, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x134, 0xf, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
+// slot (T, P) of the symmetric partial array: partial[((T * nt + P) * 3 + comp) * ts + local]
+__device__ __forceinline__ int64_t sym_slot(const SymArgs &a, int64_t T, int64_t P, int comp,
+                                            int64_t local) {
+  return ((T * a.nt + P) * 3 + comp) * a.ts + local;
+}
+
+constexpr int kWaves = kBlock / 64;
+
+template <int TPT>
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
+                                                                const float *__restrict__ src,
+                                                                PairConsts<float> k,
+                                                                double *__restrict__ partial) {
+  const int64_t I = blockIdx.y, J = blockIdx.x;
+  if (J < I) return;
+  __shared__ LdsF<false> L;
+  __shared__ float col[kWaves][kBlock][3];
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int64_t n = a.n;
+  const int64_t first = I * a.ts;
+  TargetsF<TPT> T;
+  load_targets<TPT>(g, first, n, first, T);
+  const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
+  if (I == J) {
+    sources_mixed<false, TPT>(g, src, n, jb, je, k, L, T);
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int64_t local = q * kBlock + tid;
+      if (first + local < n)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          partial[sym_slot(a, I, I, d, local)] = double(T.s[q][d]) - double(T.c[q][d]);
+    }
+    return;
+  }
+  float gx[TPT], gy[TPT], gz[TPT];    // the targets' own weighted forces (zero when absent)
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int64_t r = first + q * kBlock + tid;
+    const bool on = r < n;
+    gx[q] = on ? src[r] : 0.f;
+    gy[q] = on ? src[n + r] : 0.f;
+    gz[q] = on ? src[2 * n + r] : 0.f;
+  }
+  for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
+    const int cnt = int(min<int64_t>(kBlock, je - t0));
+    __syncthreads();
+    if (tid < cnt) {
+      const int64_t j = t0 + tid;
+      L.xh[tid] = g.xh[j];
+      L.xl[tid] = g.xl[j];
+      L.yh[tid] = g.yh[j];
+      L.yl[tid] = g.yl[j];
+      L.z[tid] = g.z[j];
+      L.f[0][tid] = src[j];
+      L.f[1][tid] = src[n + j];
+      L.f[2][tid] = src[2 * n + j];
+    }
+    __syncthreads();
+    float acc[TPT][3];
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.f;
+    for (int blk = 0; blk < cnt; blk += 64) {
+      const int nb = min(64, cnt - blk);
+      float dx_ = 0.f, dy_ = 0.f, dz_ = 0.f;   // rotating per-source sums
+      for (int step = 0; step < 64; ++step) {
+        const int sl = (lane + step) & 63;
+        const bool valid = sl < nb;
+        const int j = blk + (valid ? sl : 0);
+        const float xjh = L.xh[j], xjl = L.xl[j], yjh = L.yh[j], yjl = L.yl[j], zj = L.z[j];
+        const float fx = valid ? L.f[0][j] : 0.f, fy = valid ? L.f[1][j] : 0.f,
+                    fz = valid ? L.f[2][j] : 0.f;
+        float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+          const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+          const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
+          float ox, oy, oz, px, py, pz;
+          pair_velocity_sym<float>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k, ox,
+                                   oy, oz, px, py, pz);
+          acc[q][0] += ox;
+          acc[q][1] += oy;
+          acc[q][2] += oz;
+          cx += px;
+          cy += py;
+          cz += pz;
+        }
+        if (step == 0) {
+          dx_ = cx;
+          dy_ = cy;
+          dz_ = cz;
+        } else {
+          dx_ = wave_rol1(dx_) + cx;
+          dy_ = wave_rol1(dy_) + cy;
+          dz_ = wave_rol1(dz_) + cz;
+        }
+      }
+      const int sl = (lane + 63) & 63;
+      if (sl < nb) {
+        col[wave][blk + sl][0] = dx_;
+        col[wave][blk + sl][1] = dy_;
+        col[wave][blk + sl][2] = dz_;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TPT; ++q)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) kahan_add(T.s[q][d], T.c[q][d], acc[q][d]);
+    __syncthreads();
+    if (tid < cnt) {
+      const int64_t l = t0 - jb + tid;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) v += double(col[w][tid][d]);
+        partial[sym_slot(a, J, I, d, l)] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int64_t local = q * kBlock + tid;
+    if (first + local < n)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        partial[sym_slot(a, I, J, d, local)] = double(T.s[q][d]) - double(T.c[q][d]);
+  }
+}
+
+template <int TPT>
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g,
+                                                              const double *__restrict__ src,
+                                                              PairConsts<double> k,
+                                                              double *__restrict__ partial) {
+  const int64_t I = blockIdx.y, J = blockIdx.x;
+  if (J < I) return;
+  __shared__ LdsD<false> L;
+  __shared__ double col[kWaves][kBlock][3];
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int64_t n = a.n;
+  const int64_t first = I * a.ts;
+  TargetsD<TPT> T;
+  load_targets<TPT>(g, first, n, first, T);
+  const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
+  if (I == J) {
+    sources_f64<false, TPT>(g, src, n, jb, je, k, L, T);
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int64_t local = q * kBlock + tid;
+      if (first + local < n)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, I, d, local)] = T.u[q][d];
+    }
+    return;
+  }
+  double gx[TPT], gy[TPT], gz[TPT];
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int64_t r = first + q * kBlock + tid;
+    const bool on = r < n;
+    gx[q] = on ? src[r] : 0.0;
+    gy[q] = on ? src[n + r] : 0.0;
+    gz[q] = on ? src[2 * n + r] : 0.0;
+  }
+  for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
+    const int cnt = int(min<int64_t>(kBlock, je - t0));
+    __syncthreads();
+    if (tid < cnt) {
+      const int64_t j = t0 + tid;
+      L.x[tid] = g.x[j];
+      L.y[tid] = g.y[j];
+      L.z[tid] = g.z[j];
+      L.f[0][tid] = src[j];
+      L.f[1][tid] = src[n + j];
+      L.f[2][tid] = src[2 * n + j];
+    }
+    __syncthreads();
+    for (int blk = 0; blk < cnt; blk += 64) {
+      const int nb = min(64, cnt - blk);
+      double dx_ = 0.0, dy_ = 0.0, dz_ = 0.0;
+      for (int step = 0; step < 64; ++step) {
+        const int sl = (lane + step) & 63;
+        const bool valid = sl < nb;
+        const int j = blk + (valid ? sl : 0);
+        const double xj = L.x[j], yj = L.y[j], zj = L.z[j];
+        const double fx = valid ? L.f[0][j] : 0.0, fy = valid ? L.f[1][j] : 0.0,
+                     fz = valid ? L.f[2][j] : 0.0;
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+          double ox, oy, oz, px, py, pz;
+          pair_velocity_sym<double>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, gx[q],
+                                    gy[q], gz[q], k, ox, oy, oz, px, py, pz);
+          T.u[q][0] += ox;
+          T.u[q][1] += oy;
+          T.u[q][2] += oz;
+          cx += px;
+          cy += py;
+          cz += pz;
+        }
+        if (step == 0) {
+          dx_ = cx;
+          dy_ = cy;
+          dz_ = cz;
+        } else {
+          dx_ = wave_rol1(dx_) + cx;
+          dy_ = wave_rol1(dy_) + cy;
+          dz_ = wave_rol1(dz_) + cz;
+        }
+      }
+      const int sl = (lane + 63) & 63;
+      if (sl < nb) {
+        col[wave][blk + sl][0] = dx_;
+        col[wave][blk + sl][1] = dy_;
+        col[wave][blk + sl][2] = dz_;
+      }
+    }
+    __syncthreads();
+    if (tid < cnt) {
+      const int64_t l = t0 - jb + tid;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) v += col[w][tid][d];
+        partial[sym_slot(a, J, I, d, l)] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int64_t local = q * kBlock + tid;
+    if (first + local < n)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, J, d, local)] = T.u[q][d];
+  }
+}
+
+__global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
+                                    const double *__restrict__ h, double scale,
+                                    double *__restrict__ vel) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= a.n) return;
+  const int64_t T = r / a.ts, local = r % a.ts;
+  const double w = scale * h[r];
+  for (int d = 0; d < 3; ++d) {
+    double s = 0.0;
+    for (int64_t P = 0; P < a.nt; ++P) s += partial[sym_slot(a, T, P, d, local)];
+    vel[3 * r + d] = w * s;
+  }
+}
+
 // ---- batched systems: persistent workgroups over a cost-ordered item list -------------------
 
 struct BatchArgs {
@@ -497,6 +783,45 @@ int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *po
   return RPB_OK;
 }
 
+// Force-only product of the whole system with one evaluation per unordered pair.
+int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
+                     const double *h, int tpt, double *vel, hipStream_t stream) {
+  const int64_t n = g.n;
+  const bool f64 = g.precision == RPB_FP64;
+  SymArgs a{n, int64_t(kBlock) * tpt, 0};
+  a.nt = (n + a.ts - 1) / a.ts;
+  if (a.nt > 65535)
+    return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
+  int st;
+  double *part = static_cast<double *>(workspace(
+      ctx, WS_PART, size_t(a.nt) * size_t(a.nt) * 3 * size_t(a.ts) * sizeof(double), &st));
+  if (!part) return st;
+  const dim3 grid{unsigned(a.nt), unsigned(a.nt), 1u};
+  hipEvent_t t0;
+  RPB_TRY(timing_begin(ctx, stream, &t0));
+  if (f64) {
+    const auto k = make_pair_consts<double>(p->a);
+    const double *sv = static_cast<const double *>(src);
+    if (tpt == 2)
+      pair_kernel_f64_sym<2><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
+    else
+      pair_kernel_f64_sym<1><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
+  } else {
+    const auto k = make_pair_consts<float>(p->a);
+    const float *sv = static_cast<const float *>(src);
+    if (tpt == 2)
+      pair_kernel_mixed_sym<2><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
+    else
+      pair_kernel_mixed_sym<1><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
+  }
+  RPB_LAUNCHED(ctx);
+  RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), f64 ? 0 : 2));
+  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  reduce_partials_sym<<<blocks_for(n, 256), 256, 0, stream>>>(a, part, h, scale, vel);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
 int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
                   const double *torque, int64_t row0, int64_t nrows, double *vel,
                   hipStream_t stream) {
@@ -513,6 +838,8 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   // order whichever rows are requested: row shards concatenate to the full product bitwise.
   const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
   const int tpt = shape.tpt;
+  if (!has_t && row0 == 0 && nrows == n && shape.symmetric)
+    return matvec_symmetric(ctx, p, g, src, h, tpt, vel, stream);
   const int64_t per_wg = int64_t(kBlock) * tpt;
   const int64_t tiles = (nrows + per_wg - 1) / per_wg;
   const int64_t tiles_full = (n + per_wg - 1) / per_wg;

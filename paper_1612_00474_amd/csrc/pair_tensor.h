@@ -154,4 +154,79 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   }
 }
 
+// Both directions of one unordered pair of force-only sources, from one evaluation of the
+// coefficients: the mobility matrix is symmetric, M_ji = M_ij^T (reciprocity of Blake's tensor;
+// the unbounded part depends on r r^T and |r| only), so
+//   (ox, oy, oz) = M_ij F_j   (velocity of i, 8 pi eta units)
+//   (px, py, pz) = M_ij^T F_i (velocity of j)
+// where M_ij^T swaps the roles of c3 and c4 (e z^T <-> z e^T).
+template <typename Real>
+__device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Real zj, Real fx,
+                                                  Real fy, Real fz, Real gx, Real gy, Real gz,
+                                                  const PairConsts<Real> &k, Real &ox, Real &oy,
+                                                  Real &oz, Real &px, Real &py, Real &pz) {
+  const Real dz = zi - zj;
+  const Real Rz = zi + zj;
+  const Real rho2 = dx * dx + dy * dy;
+  const Real r2 = rho2 + dz * dz;
+  const Real R2 = rho2 + Rz * Rz;
+  const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
+  const Real iR = rsqrt_r(R2);
+
+  Real cI, cRR;
+  if (r2 >= k.four_a2) {
+    const Real ir2 = invr * invr;
+    const Real s = k.a2 * ir2;
+    cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
+    cRR = invr * ir2 * (Real(1) - Real(2) * s);
+  } else {
+    const Real r = r2 * invr;
+    cI = k.near_i - k.near_i_r * r;
+    cRR = k.near_rr * invr;
+  }
+
+  const Real iR2 = iR * iR;
+  const Real X = k.a2 * iR2;
+  const Real Y = X * X;
+  const Real ez = Rz * iR;
+  const Real hh = zj * iR;
+  const Real ez2 = ez * ez;
+  const Real hme = hh - ez;
+  const Real t = hh * hme;
+  const Real p = X * (Real(2) - Real(10.0 / 3.0) * X);
+  const Real q = Real(20.0 / 3.0) * Y;
+  const Real hh2x = Real(2) * hh;
+  const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
+  const Real c2 = ez2 * (q - Real(5) * p) + (Real(-6) * t + (p - Real(1)));
+  const Real c3 = ez * ((q - Real(2) * p) + ez2 * (Real(10) * p - Real(2) * q)) +
+                  (Real(12) * (ez * t) + hh2x);
+  const Real c4 = hh2x - ez * q;
+  const Real c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
+  const Real A = cI + iR * c1;
+
+  // i <- j
+  const Real rhoF = dx * fx + dy * fy;
+  const Real rF = rhoF + dz * fz;
+  const Real eF = (rhoF + Rz * fz) * iR;
+  const Real G = c2 * eF + c3 * fz;
+  const Real H = c4 * eF + c5 * fz;
+  const Real cr = cRR * rF;
+  const Real B = cr + iR2 * G;
+  ox = A * fx + B * dx;
+  oy = A * fy + B * dy;
+  oz = A * fz + (cr * dz + iR * (G * ez + H));
+
+  // j <- i (transposed tensor)
+  const Real rhoG = dx * gx + dy * gy;
+  const Real rG = rhoG + dz * gz;
+  const Real eG = (rhoG + Rz * gz) * iR;
+  const Real G2 = c2 * eG + c4 * gz;
+  const Real H2 = c3 * eG + c5 * gz;
+  const Real cr2 = cRR * rG;
+  const Real B2 = cr2 + iR2 * G2;
+  px = A * gx + B2 * dx;
+  py = A * gy + B2 * dy;
+  pz = A * gz + (cr2 * dz + iR * (G2 * ez + H2));
+}
+
 }  // namespace rpb

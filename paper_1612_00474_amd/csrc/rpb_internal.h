@@ -61,10 +61,11 @@ struct Shape {
   int target_wgs;   // workgroups to aim for when splitting the sources into chunks
   int batch_chunk;  // sources per work item of the batched kernel (multiple of 256)
   int batch_wgs;    // persistent workgroups of the batched kernel
+  int symmetric;    // 1: whole-system force-only products evaluate each unordered pair once
 };
 // One shape per precision, indexed by rpb_precision (RPB_FP64 = 0, RPB_MIXED = 1).
 struct Tuning {
-  Shape s[2] = {{2, 4096, 1024, 2048}, {1, 4096, 1024, 2048}};
+  Shape s[2] = {{2, 4096, 1024, 2048, 1}, {1, 4096, 1024, 2048, 1}};
 };
 }  // namespace rpb
 

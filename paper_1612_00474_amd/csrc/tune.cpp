@@ -65,6 +65,7 @@ int rpb_get_tuning(const rpb_ctx *ctx, rpb_tuning *out) {
     dst[q]->target_wgs = ctx->tune.s[q].target_wgs;
     dst[q]->batch_chunk = ctx->tune.s[q].batch_chunk;
     dst[q]->batch_wgs = ctx->tune.s[q].batch_wgs;
+    dst[q]->symmetric = ctx->tune.s[q].symmetric;
   }
   return RPB_OK;
 }
@@ -76,11 +77,12 @@ int rpb_set_tuning(rpb_ctx *ctx, const rpb_tuning *t) {
     const rpb_shape &v = *src[q];
     if ((v.tpt != 1 && v.tpt != 2) || v.target_wgs < 1 || v.target_wgs > (1 << 20) ||
         v.batch_chunk < 256 || v.batch_chunk % 256 != 0 || v.batch_chunk > (1 << 20) ||
-        v.batch_wgs < 1 || v.batch_wgs > (1 << 20))
+        v.batch_wgs < 1 || v.batch_wgs > (1 << 20) || (v.symmetric != 0 && v.symmetric != 1))
       return fail(ctx, RPB_EINVAL, "tuning values out of range");
   }
   for (int q = 0; q < 2; ++q)
-    ctx->tune.s[q] = Shape{src[q]->tpt, src[q]->target_wgs, src[q]->batch_chunk, src[q]->batch_wgs};
+    ctx->tune.s[q] = Shape{src[q]->tpt, src[q]->target_wgs, src[q]->batch_chunk,
+                           src[q]->batch_wgs, src[q]->symmetric};
   return RPB_OK;
 }
 
@@ -113,10 +115,12 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
     for (int tpt : {1, 2}) {
       if (batched) {
         for (int chunk : {512, 1024, 2048})
-          for (int wgs : {1024, 2048, 4096}) cands.push_back(Shape{tpt, base.target_wgs, chunk, wgs});
+          for (int wgs : {1024, 2048, 4096})
+            cands.push_back(Shape{tpt, base.target_wgs, chunk, wgs, base.symmetric});
       } else {
+        cands.push_back(Shape{tpt, base.target_wgs, base.batch_chunk, base.batch_wgs, 1});
         for (int wgs : {2048, 4096, 8192, 16384})
-          cands.push_back(Shape{tpt, wgs, base.batch_chunk, base.batch_wgs});
+          cands.push_back(Shape{tpt, wgs, base.batch_chunk, base.batch_wgs, 0});
       }
     }
     int rc = RPB_OK;

@@ -151,3 +151,27 @@ def test_error_paths(ctx, c1):
         ctx.a = 1.0
     empty = torch.empty((0, 3), dtype=torch.float64, device="cuda")
     assert ctx.matvec(empty, empty, None).shape == (0, 3)
+
+
+@pytest.mark.parametrize("tpt", [1, 2])
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 300, 513, 1100])
+def test_symmetric_kernel_matches_oracle_and_ordered(ctx, n, tpt):
+    # force-only whole-system products take the symmetric tile-pair kernel (each unordered pair
+    # evaluated once); ragged tiles and partial 64-source blocks included
+    from paper_1612_00474_amd import Context
+    c = Context(0)
+    rng = np.random.default_rng(100 + n)
+    side = max(2.0, math.sqrt(n * math.pi / 0.4))
+    pos = np.column_stack([rng.uniform(0, side, n), rng.uniform(0, side, n), rng.uniform(0.8, 2.6, n)])
+    F = rng.standard_normal((n, 3))
+    ref = mobility.dense_matvec(pos, F, None)
+    P, Fd = dev(pos), dev(F)
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        c.set_tuning(precision, tpt=tpt, symmetric=1)
+        us = host(c.matvec(P, Fd, None, precision))
+        assert rel2(us, ref) <= tol, (precision, n, tpt)
+        assert np.array_equal(us, host(c.matvec(P, Fd, None, precision)))     # reproducible
+        c.set_tuning(precision, symmetric=0)
+        uo = host(c.matvec(P, Fd, None, precision))
+        assert rel2(us, uo) <= (1e-13 if precision == "fp64" else 2e-6)
+    c.close()
