@@ -376,13 +376,27 @@ __device__ __forceinline__ int64_t sym_slot(const SymArgs &a, int64_t T, int64_t
 
 constexpr int kWaves = kBlock / 64;
 
+// Tile pair (I, J), I <= J, of linear index L = I nt - I (I - 1) / 2 + (J - I): row I of the
+// upper triangle holds nt - I pairs.  Workgroups walk the triangle row by row.
+__device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, int64_t &J) {
+  const double b = double(2 * nt + 1);
+  int64_t i = int64_t((b - sqrt(b * b - 8.0 * double(L))) * 0.5);
+  auto start = [nt](int64_t r) { return r * nt - r * (r - 1) / 2; };
+  if (i < 0) i = 0;
+  if (i > nt - 1) i = nt - 1;
+  while (i > 0 && start(i) > L) --i;
+  while (i + 1 < nt && start(i + 1) <= L) ++i;
+  I = i;
+  J = i + (L - start(i));
+}
+
 template <int TPT>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
                                                                 const float *__restrict__ src,
                                                                 PairConsts<float> k,
                                                                 double *__restrict__ partial) {
-  const int64_t I = blockIdx.y, J = blockIdx.x;
-  if (J < I) return;
+  int64_t I, J;
+  tri_decode(blockIdx.x, a.nt, I, J);
   __shared__ LdsF<false> L;
   __shared__ float col[kWaves][kBlock][3];
   const int tid = threadIdx.x;
@@ -434,6 +448,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
     for (int blk = 0; blk < cnt; blk += 64) {
       const int nb = min(64, cnt - blk);
       float dx_ = 0.f, dy_ = 0.f, dz_ = 0.f;   // rotating per-source sums
+#pragma unroll 2
       for (int step = 0; step < 64; ++step) {
         const int sl = (lane + step) & 63;
         const bool valid = sl < nb;
@@ -456,15 +471,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
           cy += py;
           cz += pz;
         }
-        if (step == 0) {
-          dx_ = cx;
-          dy_ = cy;
-          dz_ = cz;
-        } else {
-          dx_ = wave_rol1(dx_) + cx;
-          dy_ = wave_rol1(dy_) + cy;
-          dz_ = wave_rol1(dz_) + cz;
-        }
+        dx_ = wave_rol1(dx_) + cx;    // the sums start at zero, so step 0 rotates zeros
+        dy_ = wave_rol1(dy_) + cy;
+        dz_ = wave_rol1(dz_) + cz;
       }
       const int sl = (lane + 63) & 63;
       if (sl < nb) {
@@ -504,8 +513,8 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
                                                               const double *__restrict__ src,
                                                               PairConsts<double> k,
                                                               double *__restrict__ partial) {
-  const int64_t I = blockIdx.y, J = blockIdx.x;
-  if (J < I) return;
+  int64_t I, J;
+  tri_decode(blockIdx.x, a.nt, I, J);
   __shared__ LdsD<false> L;
   __shared__ double col[kWaves][kBlock][3];
   const int tid = threadIdx.x;
@@ -551,6 +560,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
     for (int blk = 0; blk < cnt; blk += 64) {
       const int nb = min(64, cnt - blk);
       double dx_ = 0.0, dy_ = 0.0, dz_ = 0.0;
+#pragma unroll 2
       for (int step = 0; step < 64; ++step) {
         const int sl = (lane + step) & 63;
         const bool valid = sl < nb;
@@ -571,15 +581,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
           cy += py;
           cz += pz;
         }
-        if (step == 0) {
-          dx_ = cx;
-          dy_ = cy;
-          dz_ = cz;
-        } else {
-          dx_ = wave_rol1(dx_) + cx;
-          dy_ = wave_rol1(dy_) + cy;
-          dz_ = wave_rol1(dz_) + cz;
-        }
+        dx_ = wave_rol1(dx_) + cx;    // the sums start at zero, so step 0 rotates zeros
+        dy_ = wave_rol1(dy_) + cy;
+        dz_ = wave_rol1(dz_) + cz;
       }
       const int sl = (lane + 63) & 63;
       if (sl < nb) {
@@ -790,13 +794,13 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
   const bool f64 = g.precision == RPB_FP64;
   SymArgs a{n, int64_t(kBlock) * tpt, 0};
   a.nt = (n + a.ts - 1) / a.ts;
-  if (a.nt > 65535)
+  if (a.nt * (a.nt + 1) / 2 > 0x7fffffffll)
     return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
   int st;
   double *part = static_cast<double *>(workspace(
       ctx, WS_PART, size_t(a.nt) * size_t(a.nt) * 3 * size_t(a.ts) * sizeof(double), &st));
   if (!part) return st;
-  const dim3 grid{unsigned(a.nt), unsigned(a.nt), 1u};
+  const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2);
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
   if (f64) {
