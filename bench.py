@@ -57,6 +57,14 @@ def measured_traffic(kernel: str):
     return None
 
 
+def force_kernel_name(prec: str, shape: dict) -> str:
+    """rocprofv3 name of the pair kernel that a force-only product launches with `shape`."""
+    kind = "mixed" if prec == "mixed" else "f64"
+    if shape["symmetric"]:
+        return f"pair_kernel_{kind}_sym<{shape['tpt']}>"
+    return f"pair_kernel_{kind}<false, {shape['tpt']}>"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,9 +202,8 @@ def main():
                                       "ms_per_launch": {"mixed": mixed_ms, "fp64": f64_ms}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic("pair_kernel_mixed<false, 1>" if prec == "mixed"
-                                                 else "pair_kernel_f64<false, 2>"),
-                     "kernel": f"pair_kernel_{'mixed' if prec == 'mixed' else 'f64'}, force-only "
+                     "traffic": measured_traffic(force_kernel_name(prec, shapes[prec])),
+                     "kernel": f"{force_kernel_name(prec, shapes[prec])}, force-only "
                                f"products ({FLOPS_PER_PAIR_FORCE} flop/pair x {n}^2 pairs/launch)",
                      "ms_per_launch": dom["ms_per_launch"], "launches": dom["launches"]},
         "pair_kernels": kinds,

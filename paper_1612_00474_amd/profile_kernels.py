@@ -1,8 +1,10 @@
 """Kernel profiling driver (run under rocprofv3).
 
-Launches, on one synthetic sheet of N spheres, one plain device-to-device copy of known
-size (to calibrate the HBM byte counters FETCH_SIZE / WRITE_SIZE against a kernel whose
-traffic is known) followed by `--reps` launches of each pair-kernel variant:
+Tunes the launch shapes on one synthetic sheet of N spheres (as the benchmark does), then
+launches one plain device-to-device copy of known size (to calibrate the HBM byte counters
+FETCH_SIZE / WRITE_SIZE against a kernel whose traffic is known) followed by `--reps`
+launches of each pair-kernel variant and of the steric force kernel.  Only the dispatches
+after the copy count:
 
     rocprofv3 --kernel-trace --stats -d OUT -o run -- python -m paper_1612_00474_amd.profile_kernels
     rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch -- python -m paper_1612_00474_amd.profile_kernels
@@ -36,26 +38,34 @@ def main():
     from paper_1612_00474_amd import workloads as wl
 
     torch.cuda.init()
+    pos = torch.as_tensor(wl.sheet(args.n, seed=0)).cuda()
+    rng = np.random.default_rng(0)
+    F = torch.as_tensor(rng.standard_normal((args.n, 3))).cuda()
+    T = torch.as_tensor(rng.standard_normal((args.n, 3))).cuda()
+    ctx = Context(0)
+    offs = np.array([0, args.n], dtype=np.int64)
+    shapes = {prec: ctx.autotune(pos, offs, prec)[0] for prec in ("mixed", "fp64")}
+    torch.cuda.synchronize()
+
     nelem = args.copy_mib * (1 << 20) // 8
     src = torch.ones(nelem, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
 
-    pos = torch.as_tensor(wl.sheet(args.n, seed=0)).cuda()
-    rng = np.random.default_rng(0)
-    F = torch.as_tensor(rng.standard_normal((args.n, 3))).cuda()
-    T = torch.as_tensor(rng.standard_normal((args.n, 3))).cuda()
-    ctx = Context(0)
     launches = []
     for precision in ("mixed", "fp64"):
         for torque in (None, T):
             for _ in range(args.reps):
                 ctx.matvec(pos, F, torque, precision)
             launches.append({"precision": precision, "torque": torque is not None, "reps": args.reps})
+    for _ in range(args.reps):
+        ctx.forces(pos, f_grav_z=-1.0, u0=1.0, b=0.1)
+    launches.append({"kernel": "steric", "reps": args.reps})
     torch.cuda.synchronize()
     ctx.close()
-    print(json.dumps({"copy_bytes": nelem * 8, "n": args.n, "launches": launches}))
+    print(json.dumps({"copy_bytes": nelem * 8, "n": args.n, "shapes": shapes,
+                      "launches": launches}))
 
 
 if __name__ == "__main__":

@@ -58,6 +58,17 @@ def test_forces(ctx, c1):
         assert rel2(f, ref) <= 1e-12
 
 
+def test_forces_full_size_sampled_rows(ctx):
+    # the 65,536-sphere sheet: the sources are split over many workgroups; sampled rows
+    # (first, last, random) against the oracle's row evaluation
+    n = 65536
+    pos = wl.sheet(n, seed=0)
+    f = host(ctx.forces(dev(pos), -1.0, 1.0, 0.1))
+    rows = np.concatenate([[0, 1, n - 1], np.random.default_rng(3).choice(n, 45, replace=False)])
+    ref = forces.forces(pos, 1.0, 1.0, 0.1, -1.0, rows=rows)
+    assert rel2(f[rows], ref) <= 1e-12
+
+
 def test_normals_match_oracle_generator(ctx):
     for count, seed, stream, step in ((10, 0, 0, 0), (3 * 4097, 12345, 1, 77), (3, 2 ** 63 + 5, 0, 2 ** 40)):
         ref = philox.normals(count, seed, stream, step)
