@@ -187,14 +187,26 @@ __device__ __forceinline__ void sources_f64(const GeomD &g, const double *__rest
       const double fx = L.f[0][j], fy = L.f[1][j], fz = L.f[2][j];
       const double tx = TORQUE ? L.t[0][j] : 0.0, ty = TORQUE ? L.t[1][j] : 0.0,
                    tz = TORQUE ? L.t[2][j] : 0.0;
+      double o[TPT][3], r2[TPT];
+      bool close = false;
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
-        double ox, oy, oz;
-        pair_velocity<double, TORQUE>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, tx, ty,
-                                      tz, k, ox, oy, oz);
-        T.u[q][0] += ox;
-        T.u[q][1] += oy;
-        T.u[q][2] += oz;
+        pair_velocity<double, TORQUE, true>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, tx,
+                                            ty, tz, k, o[q][0], o[q][1], o[q][2], r2[q]);
+        close |= r2[q] < k.four_a2;
+      }
+      if (close) {   // rare: some lane holds a pair closer than 2a (or its own self pair)
+#pragma unroll
+        for (int q = 0; q < TPT; ++q)
+          if (r2[q] < k.four_a2)
+            pair_velocity<double, TORQUE>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, tx,
+                                          ty, tz, k, o[q][0], o[q][1], o[q][2], r2[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < TPT; ++q) {
+        T.u[q][0] += o[q][0];
+        T.u[q][1] += o[q][1];
+        T.u[q][2] += o[q][2];
       }
     }
   }
@@ -235,15 +247,32 @@ __device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__res
       const float fx = L.f[0][j], fy = L.f[1][j], fz = L.f[2][j];
       const float tx = TORQUE ? L.t[0][j] : 0.f, ty = TORQUE ? L.t[1][j] : 0.f,
                   tz = TORQUE ? L.t[2][j] : 0.f;
+      float o[TPT][3], r2[TPT];
+      bool close = false;
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
         const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
         const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-        float ox, oy, oz;
-        pair_velocity<float, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, ox, oy, oz);
-        a[q][0] += ox;
-        a[q][1] += oy;
-        a[q][2] += oz;
+        pair_velocity<float, TORQUE, true>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, o[q][0],
+                                           o[q][1], o[q][2], r2[q]);
+        close |= r2[q] < k.four_a2;
+      }
+      if (close) {   // rare: some lane holds a pair closer than 2a (or its own self pair)
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+          if (r2[q] < k.four_a2) {
+            const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+            const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
+            pair_velocity<float, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, o[q][0],
+                                         o[q][1], o[q][2], r2[q]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < TPT; ++q) {
+        a[q][0] += o[q][0];
+        a[q][1] += o[q][1];
+        a[q][2] += o[q][2];
       }
     }
 #pragma unroll
@@ -390,6 +419,102 @@ __device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, in
   J = i + (L - start(i));
 }
 
+// One rotation step: every lane evaluates its targets against source j (weighted force zero
+// when !valid), adds M_ij F_j into acc and passes the per-source sums cs one lane down after
+// adding M_ij^T F_i.  All pairs are first evaluated with the far-field (|r| >= 2a) form; if
+// any lane of the wavefront holds a closer pair (rare in a suspension) those pairs are
+// evaluated again with the complete form and replace the far-field values.
+template <int TPT>
+__device__ __forceinline__ void sym_step(const LdsF<false> &L, int j, bool valid,
+                                         const TargetsF<TPT> &T, const float (&gx)[TPT],
+                                         const float (&gy)[TPT], const float (&gz)[TPT],
+                                         const PairConsts<float> &k, float (&acc)[TPT][3],
+                                         float (&cs)[3]) {
+  const float xjh = L.xh[j], xjl = L.xl[j], yjh = L.yh[j], yjl = L.yl[j], zj = L.z[j];
+  const float fx = valid ? L.f[0][j] : 0.f, fy = valid ? L.f[1][j] : 0.f,
+              fz = valid ? L.f[2][j] : 0.f;
+  float o[TPT][6], r2[TPT];
+  bool close = false;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+    const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
+    pair_velocity_sym<float, true>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
+                                   o[q][0], o[q][1], o[q][2], o[q][3], o[q][4], o[q][5], r2[q]);
+    close |= r2[q] < k.four_a2;
+  }
+  if (close) {
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      if (r2[q] < k.four_a2) {
+        const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+        const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
+        float r2q;
+        pair_velocity_sym<float, false>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
+                                        o[q][0], o[q][1], o[q][2], o[q][3], o[q][4], o[q][5],
+                                        r2q);
+      }
+    }
+  }
+  float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    acc[q][0] += o[q][0];
+    acc[q][1] += o[q][1];
+    acc[q][2] += o[q][2];
+    cx += o[q][3];
+    cy += o[q][4];
+    cz += o[q][5];
+  }
+  cs[0] = wave_rol1(cs[0]) + cx;    // the sums start at zero, so the first step rotates zeros
+  cs[1] = wave_rol1(cs[1]) + cy;
+  cs[2] = wave_rol1(cs[2]) + cz;
+}
+
+template <int TPT>
+__device__ __forceinline__ void sym_step(const LdsD<false> &L, int j, bool valid,
+                                         const TargetsD<TPT> &T, const double (&gx)[TPT],
+                                         const double (&gy)[TPT], const double (&gz)[TPT],
+                                         const PairConsts<double> &k, double (&acc)[TPT][3],
+                                         double (&cs)[3]) {
+  const double xj = L.x[j], yj = L.y[j], zj = L.z[j];
+  const double fx = valid ? L.f[0][j] : 0.0, fy = valid ? L.f[1][j] : 0.0,
+               fz = valid ? L.f[2][j] : 0.0;
+  double o[TPT][6], r2[TPT];
+  bool close = false;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    pair_velocity_sym<double, true>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, gx[q],
+                                    gy[q], gz[q], k, o[q][0], o[q][1], o[q][2], o[q][3],
+                                    o[q][4], o[q][5], r2[q]);
+    close |= r2[q] < k.four_a2;
+  }
+  if (close) {
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      if (r2[q] < k.four_a2) {
+        double r2q;
+        pair_velocity_sym<double, false>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz,
+                                         gx[q], gy[q], gz[q], k, o[q][0], o[q][1], o[q][2],
+                                         o[q][3], o[q][4], o[q][5], r2q);
+      }
+    }
+  }
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    acc[q][0] += o[q][0];
+    acc[q][1] += o[q][1];
+    acc[q][2] += o[q][2];
+    cx += o[q][3];
+    cy += o[q][4];
+    cz += o[q][5];
+  }
+  cs[0] = wave_rol1(cs[0]) + cx;
+  cs[1] = wave_rol1(cs[1]) + cy;
+  cs[2] = wave_rol1(cs[2]) + cz;
+}
+
 template <int TPT>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
                                                                 const float *__restrict__ src,
@@ -447,39 +572,22 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
     for (int q = 0; q < TPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.f;
     for (int blk = 0; blk < cnt; blk += 64) {
       const int nb = min(64, cnt - blk);
-      float dx_ = 0.f, dy_ = 0.f, dz_ = 0.f;   // rotating per-source sums
+      float cs[3] = {0.f, 0.f, 0.f};   // rotating per-source sums
+      if (nb == 64) {
 #pragma unroll 2
-      for (int step = 0; step < 64; ++step) {
-        const int sl = (lane + step) & 63;
-        const bool valid = sl < nb;
-        const int j = blk + (valid ? sl : 0);
-        const float xjh = L.xh[j], xjl = L.xl[j], yjh = L.yh[j], yjl = L.yl[j], zj = L.z[j];
-        const float fx = valid ? L.f[0][j] : 0.f, fy = valid ? L.f[1][j] : 0.f,
-                    fz = valid ? L.f[2][j] : 0.f;
-        float cx = 0.f, cy = 0.f, cz = 0.f;
-#pragma unroll
-        for (int q = 0; q < TPT; ++q) {
-          const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
-          const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-          float ox, oy, oz, px, py, pz;
-          pair_velocity_sym<float>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k, ox,
-                                   oy, oz, px, py, pz);
-          acc[q][0] += ox;
-          acc[q][1] += oy;
-          acc[q][2] += oz;
-          cx += px;
-          cy += py;
-          cz += pz;
+        for (int step = 0; step < 64; ++step)
+          sym_step<TPT>(L, blk + ((lane + step) & 63), true, T, gx, gy, gz, k, acc, cs);
+      } else {
+        for (int step = 0; step < 64; ++step) {
+          const int sl = (lane + step) & 63;
+          sym_step<TPT>(L, blk + (sl < nb ? sl : 0), sl < nb, T, gx, gy, gz, k, acc, cs);
         }
-        dx_ = wave_rol1(dx_) + cx;    // the sums start at zero, so step 0 rotates zeros
-        dy_ = wave_rol1(dy_) + cy;
-        dz_ = wave_rol1(dz_) + cz;
       }
       const int sl = (lane + 63) & 63;
       if (sl < nb) {
-        col[wave][blk + sl][0] = dx_;
-        col[wave][blk + sl][1] = dy_;
-        col[wave][blk + sl][2] = dz_;
+        col[wave][blk + sl][0] = cs[0];
+        col[wave][blk + sl][1] = cs[1];
+        col[wave][blk + sl][2] = cs[2];
       }
     }
 #pragma unroll
@@ -559,37 +667,22 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
     __syncthreads();
     for (int blk = 0; blk < cnt; blk += 64) {
       const int nb = min(64, cnt - blk);
-      double dx_ = 0.0, dy_ = 0.0, dz_ = 0.0;
+      double cs[3] = {0.0, 0.0, 0.0};   // rotating per-source sums
+      if (nb == 64) {
 #pragma unroll 2
-      for (int step = 0; step < 64; ++step) {
-        const int sl = (lane + step) & 63;
-        const bool valid = sl < nb;
-        const int j = blk + (valid ? sl : 0);
-        const double xj = L.x[j], yj = L.y[j], zj = L.z[j];
-        const double fx = valid ? L.f[0][j] : 0.0, fy = valid ? L.f[1][j] : 0.0,
-                     fz = valid ? L.f[2][j] : 0.0;
-        double cx = 0.0, cy = 0.0, cz = 0.0;
-#pragma unroll
-        for (int q = 0; q < TPT; ++q) {
-          double ox, oy, oz, px, py, pz;
-          pair_velocity_sym<double>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, gx[q],
-                                    gy[q], gz[q], k, ox, oy, oz, px, py, pz);
-          T.u[q][0] += ox;
-          T.u[q][1] += oy;
-          T.u[q][2] += oz;
-          cx += px;
-          cy += py;
-          cz += pz;
+        for (int step = 0; step < 64; ++step)
+          sym_step<TPT>(L, blk + ((lane + step) & 63), true, T, gx, gy, gz, k, T.u, cs);
+      } else {
+        for (int step = 0; step < 64; ++step) {
+          const int sl = (lane + step) & 63;
+          sym_step<TPT>(L, blk + (sl < nb ? sl : 0), sl < nb, T, gx, gy, gz, k, T.u, cs);
         }
-        dx_ = wave_rol1(dx_) + cx;    // the sums start at zero, so step 0 rotates zeros
-        dy_ = wave_rol1(dy_) + cy;
-        dz_ = wave_rol1(dz_) + cz;
       }
       const int sl = (lane + 63) & 63;
       if (sl < nb) {
-        col[wave][blk + sl][0] = dx_;
-        col[wave][blk + sl][1] = dy_;
-        col[wave][blk + sl][2] = dz_;
+        col[wave][blk + sl][0] = cs[0];
+        col[wave][blk + sl][1] = cs[1];
+        col[wave][blk + sl][2] = cs[2];
       }
     }
     __syncthreads();

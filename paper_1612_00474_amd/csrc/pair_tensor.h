@@ -76,33 +76,45 @@ __device__ __forceinline__ double rsqrt_r(double x) {
 
 // Contribution of source j to the velocity of target i (8 pi eta units), stored into
 // (ox, oy, oz); the caller accumulates.  dx, dy: x_i - x_j, y_i - y_j; zi, zj: clamped heights;
-// f: the source's weighted force; t: its weighted torque (used when TORQUE).
-template <typename Real, bool TORQUE>
+// f: the source's weighted force; t: its weighted torque (used when TORQUE).  r2_out receives
+// |r|^2.  FAR_ONLY evaluates the |r| >= 2a form alone (cheaper; the caller must evaluate pairs
+// with |r|^2 < 4a^2 again with FAR_ONLY = false).
+template <typename Real, bool TORQUE, bool FAR_ONLY = false>
 __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj, Real fx, Real fy,
                                               Real fz, Real tx, Real ty, Real tz,
                                               const PairConsts<Real> &k, Real &ox, Real &oy,
-                                              Real &oz) {
+                                              Real &oz, Real &r2_out) {
   const Real dz = zi - zj;
   const Real Rz = zi + zj;
   const Real rho2 = dx * dx + dy * dy;
   const Real r2 = rho2 + dz * dz;
   const Real R2 = rho2 + Rz * Rz;
-  const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
   const Real iR = rsqrt_r(R2);
+  r2_out = r2;
 
   // unbounded RPY: cI F + cRR r (r.F) [+ cT T x r]
   Real cI, cRR, cT;
-  if (r2 >= k.four_a2) {
+  if (FAR_ONLY) {
+    const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
     const Real s = k.a2 * ir2;
     cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
     cT = invr * ir2;
     cRR = cT * (Real(1) - Real(2) * s);
   } else {
-    const Real r = r2 * invr;
-    cI = k.near_i - k.near_i_r * r;
-    cRR = k.near_rr * invr;
-    cT = k.near_t - k.near_t_r * r;
+    const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
+    if (r2 >= k.four_a2) {
+      const Real ir2 = invr * invr;
+      const Real s = k.a2 * ir2;
+      cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
+      cT = invr * ir2;
+      cRR = cT * (Real(1) - Real(2) * s);
+    } else {
+      const Real r = r2 * invr;
+      cI = k.near_i - k.near_i_r * r;
+      cRR = k.near_rr * invr;
+      cT = k.near_t - k.near_t_r * r;
+    }
   }
 
   // wall coefficients
@@ -160,29 +172,40 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
 //   (ox, oy, oz) = M_ij F_j   (velocity of i, 8 pi eta units)
 //   (px, py, pz) = M_ij^T F_i (velocity of j)
 // where M_ij^T swaps the roles of c3 and c4 (e z^T <-> z e^T).
-template <typename Real>
+template <typename Real, bool FAR_ONLY = false>
 __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Real zj, Real fx,
                                                   Real fy, Real fz, Real gx, Real gy, Real gz,
                                                   const PairConsts<Real> &k, Real &ox, Real &oy,
-                                                  Real &oz, Real &px, Real &py, Real &pz) {
+                                                  Real &oz, Real &px, Real &py, Real &pz,
+                                                  Real &r2_out) {
   const Real dz = zi - zj;
   const Real Rz = zi + zj;
   const Real rho2 = dx * dx + dy * dy;
   const Real r2 = rho2 + dz * dz;
   const Real R2 = rho2 + Rz * Rz;
-  const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
   const Real iR = rsqrt_r(R2);
+  r2_out = r2;
 
   Real cI, cRR;
-  if (r2 >= k.four_a2) {
+  if (FAR_ONLY) {
+    // valid for r2 >= (2a)^2 only: the caller re-evaluates closer pairs with FAR_ONLY = false
+    const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
     const Real s = k.a2 * ir2;
     cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
     cRR = invr * ir2 * (Real(1) - Real(2) * s);
   } else {
-    const Real r = r2 * invr;
-    cI = k.near_i - k.near_i_r * r;
-    cRR = k.near_rr * invr;
+    const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
+    if (r2 >= k.four_a2) {
+      const Real ir2 = invr * invr;
+      const Real s = k.a2 * ir2;
+      cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
+      cRR = invr * ir2 * (Real(1) - Real(2) * s);
+    } else {
+      const Real r = r2 * invr;
+      cI = k.near_i - k.near_i_r * r;
+      cRR = k.near_rr * invr;
+    }
   }
 
   const Real iR2 = iR * iR;
