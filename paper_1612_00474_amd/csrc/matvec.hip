@@ -187,26 +187,16 @@ __device__ __forceinline__ void sources_f64(const GeomD &g, const double *__rest
       const double fx = L.f[0][j], fy = L.f[1][j], fz = L.f[2][j];
       const double tx = TORQUE ? L.t[0][j] : 0.0, ty = TORQUE ? L.t[1][j] : 0.0,
                    tz = TORQUE ? L.t[2][j] : 0.0;
-      double o[TPT][3], r2[TPT];
-      bool close = false;
+      // pairs closer than 2a (rare) and the self pair take the complete form
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
-        pair_velocity<double, TORQUE, true>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, tx,
-                                            ty, tz, k, o[q][0], o[q][1], o[q][2], r2[q]);
-        close |= r2[q] < k.four_a2;
-      }
-      if (close) {   // rare: some lane holds a pair closer than 2a (or its own self pair)
-#pragma unroll
-        for (int q = 0; q < TPT; ++q)
-          if (r2[q] < k.four_a2)
-            pair_velocity<double, TORQUE>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, tx,
-                                          ty, tz, k, o[q][0], o[q][1], o[q][2], r2[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < TPT; ++q) {
-        T.u[q][0] += o[q][0];
-        T.u[q][1] += o[q][1];
-        T.u[q][2] += o[q][2];
+        const double dx = T.x[q] - xj, dy = T.y[q] - yj, dz = T.z[q] - zj;
+        if (dx * dx + dy * dy + dz * dz < k.four_a2)
+          pair_velocity<double, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, T.u[q][0],
+                                        T.u[q][1], T.u[q][2]);
+        else
+          pair_velocity<double, TORQUE, true>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
+                                              T.u[q][0], T.u[q][1], T.u[q][2]);
       }
     }
   }
@@ -247,32 +237,18 @@ __device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__res
       const float fx = L.f[0][j], fy = L.f[1][j], fz = L.f[2][j];
       const float tx = TORQUE ? L.t[0][j] : 0.f, ty = TORQUE ? L.t[1][j] : 0.f,
                   tz = TORQUE ? L.t[2][j] : 0.f;
-      float o[TPT][3], r2[TPT];
-      bool close = false;
+      // pairs closer than 2a (rare) and the self pair take the complete form
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
         const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
         const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-        pair_velocity<float, TORQUE, true>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, o[q][0],
-                                           o[q][1], o[q][2], r2[q]);
-        close |= r2[q] < k.four_a2;
-      }
-      if (close) {   // rare: some lane holds a pair closer than 2a (or its own self pair)
-#pragma unroll
-        for (int q = 0; q < TPT; ++q) {
-          if (r2[q] < k.four_a2) {
-            const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
-            const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-            pair_velocity<float, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, o[q][0],
-                                         o[q][1], o[q][2], r2[q]);
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < TPT; ++q) {
-        a[q][0] += o[q][0];
-        a[q][1] += o[q][1];
-        a[q][2] += o[q][2];
+        const float dz = T.z[q] - zj;
+        if (dx * dx + dy * dy + dz * dz < k.four_a2)
+          pair_velocity<float, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, a[q][0],
+                                       a[q][1], a[q][2]);
+        else
+          pair_velocity<float, TORQUE, true>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
+                                             a[q][0], a[q][1], a[q][2]);
       }
     }
 #pragma unroll
@@ -419,11 +395,10 @@ __device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, in
   J = i + (L - start(i));
 }
 
-// One rotation step: every lane evaluates its targets against source j (weighted force zero
-// when !valid), adds M_ij F_j into acc and passes the per-source sums cs one lane down after
-// adding M_ij^T F_i.  All pairs are first evaluated with the far-field (|r| >= 2a) form; if
-// any lane of the wavefront holds a closer pair (rare in a suspension) those pairs are
-// evaluated again with the complete form and replace the far-field values.
+// One rotation step: every lane passes its per-source sums cs one lane down, then evaluates
+// its targets against source j (weighted force zero when !valid), adding M_ij F_j into acc and
+// M_ij^T F_i into cs.  Pairs at least 2a apart use the far-field form alone; closer pairs (rare
+// in a suspension) the complete form, so each pair's value depends on its own geometry only.
 template <int TPT>
 __device__ __forceinline__ void sym_step(const LdsF<false> &L, int j, bool valid,
                                          const TargetsF<TPT> &T, const float (&gx)[TPT],
@@ -433,42 +408,21 @@ __device__ __forceinline__ void sym_step(const LdsF<false> &L, int j, bool valid
   const float xjh = L.xh[j], xjl = L.xl[j], yjh = L.yh[j], yjl = L.yl[j], zj = L.z[j];
   const float fx = valid ? L.f[0][j] : 0.f, fy = valid ? L.f[1][j] : 0.f,
               fz = valid ? L.f[2][j] : 0.f;
-  float o[TPT][6], r2[TPT];
-  bool close = false;
+  // the sums start at zero, so the first step rotates zeros
+#pragma unroll
+  for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
     const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
     const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-    pair_velocity_sym<float, true>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
-                                   o[q][0], o[q][1], o[q][2], o[q][3], o[q][4], o[q][5], r2[q]);
-    close |= r2[q] < k.four_a2;
+    const float dz = T.z[q] - zj;
+    if (dx * dx + dy * dy + dz * dz < k.four_a2)
+      pair_velocity_sym<float>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k, acc[q][0],
+                               acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
+    else
+      pair_velocity_sym<float, true>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
+                                     acc[q][0], acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
   }
-  if (close) {
-#pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-      if (r2[q] < k.four_a2) {
-        const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
-        const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-        float r2q;
-        pair_velocity_sym<float, false>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
-                                        o[q][0], o[q][1], o[q][2], o[q][3], o[q][4], o[q][5],
-                                        r2q);
-      }
-    }
-  }
-  float cx = 0.f, cy = 0.f, cz = 0.f;
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    acc[q][0] += o[q][0];
-    acc[q][1] += o[q][1];
-    acc[q][2] += o[q][2];
-    cx += o[q][3];
-    cy += o[q][4];
-    cz += o[q][5];
-  }
-  cs[0] = wave_rol1(cs[0]) + cx;    // the sums start at zero, so the first step rotates zeros
-  cs[1] = wave_rol1(cs[1]) + cy;
-  cs[2] = wave_rol1(cs[2]) + cz;
 }
 
 template <int TPT>
@@ -480,39 +434,18 @@ __device__ __forceinline__ void sym_step(const LdsD<false> &L, int j, bool valid
   const double xj = L.x[j], yj = L.y[j], zj = L.z[j];
   const double fx = valid ? L.f[0][j] : 0.0, fy = valid ? L.f[1][j] : 0.0,
                fz = valid ? L.f[2][j] : 0.0;
-  double o[TPT][6], r2[TPT];
-  bool close = false;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
-    pair_velocity_sym<double, true>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz, gx[q],
-                                    gy[q], gz[q], k, o[q][0], o[q][1], o[q][2], o[q][3],
-                                    o[q][4], o[q][5], r2[q]);
-    close |= r2[q] < k.four_a2;
+    const double dx = T.x[q] - xj, dy = T.y[q] - yj, dz = T.z[q] - zj;
+    if (dx * dx + dy * dy + dz * dz < k.four_a2)
+      pair_velocity_sym<double>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
+                                acc[q][0], acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
+    else
+      pair_velocity_sym<double, true>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
+                                      acc[q][0], acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
   }
-  if (close) {
-#pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-      if (r2[q] < k.four_a2) {
-        double r2q;
-        pair_velocity_sym<double, false>(T.x[q] - xj, T.y[q] - yj, T.z[q], zj, fx, fy, fz,
-                                         gx[q], gy[q], gz[q], k, o[q][0], o[q][1], o[q][2],
-                                         o[q][3], o[q][4], o[q][5], r2q);
-      }
-    }
-  }
-  double cx = 0.0, cy = 0.0, cz = 0.0;
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    acc[q][0] += o[q][0];
-    acc[q][1] += o[q][1];
-    acc[q][2] += o[q][2];
-    cx += o[q][3];
-    cy += o[q][4];
-    cz += o[q][5];
-  }
-  cs[0] = wave_rol1(cs[0]) + cx;
-  cs[1] = wave_rol1(cs[1]) + cy;
-  cs[2] = wave_rol1(cs[2]) + cz;
 }
 
 template <int TPT>

@@ -1,5 +1,6 @@
 // One ordered pair (target i, source j) of the regularised Rotne-Prager-Blake mobility,
-// applied to the source's force and torque.  Written once for float64 and float32.
+// applied to the source's force and torque and added to the target's running sum.  Written
+// once for float64 and float32.
 //
 // Geometry (heights already clamped to z~ = max(z, a), paper App. A eq. effMob):
 //   r = q~_i - q~_j = (dx, dy, dz)                    (direct separation)
@@ -74,23 +75,21 @@ __device__ __forceinline__ double rsqrt_r(double x) {
   return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
 
-// Contribution of source j to the velocity of target i (8 pi eta units), stored into
-// (ox, oy, oz); the caller accumulates.  dx, dy: x_i - x_j, y_i - y_j; zi, zj: clamped heights;
-// f: the source's weighted force; t: its weighted torque (used when TORQUE).  r2_out receives
-// |r|^2.  FAR_ONLY evaluates the |r| >= 2a form alone (cheaper; the caller must evaluate pairs
-// with |r|^2 < 4a^2 again with FAR_ONLY = false).
+// Contribution of source j to the velocity of target i (8 pi eta units), added to
+// (ox, oy, oz).  dx, dy: x_i - x_j, y_i - y_j; zi, zj: clamped heights; f: the source's weighted
+// force; t: its weighted torque (used when TORQUE).  FAR_ONLY evaluates the |r| >= 2a form
+// alone (cheaper; the caller routes pairs with |r|^2 < 4a^2 to FAR_ONLY = false).
 template <typename Real, bool TORQUE, bool FAR_ONLY = false>
 __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj, Real fx, Real fy,
                                               Real fz, Real tx, Real ty, Real tz,
                                               const PairConsts<Real> &k, Real &ox, Real &oy,
-                                              Real &oz, Real &r2_out) {
+                                              Real &oz) {
   const Real dz = zi - zj;
   const Real Rz = zi + zj;
   const Real rho2 = dx * dx + dy * dy;
   const Real r2 = rho2 + dz * dz;
   const Real R2 = rho2 + Rz * Rz;
   const Real iR = rsqrt_r(R2);
-  r2_out = r2;
 
   // unbounded RPY: cI F + cRR r (r.F) [+ cT T x r]
   Real cI, cRR, cT;
@@ -145,9 +144,13 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   const Real A = cI + iR * c1;                   // coefficient of F
   const Real cr = cRR * rF;
   const Real B = cr + iR2 * G;                   // coefficient of rho
-  ox = A * fx + B * dx;
-  oy = A * fy + B * dy;
-  oz = A * fz + (cr * dz + iR * (G * ez + H));
+  ox += A * fx;
+  ox += B * dx;
+  oy += A * fy;
+  oy += B * dy;
+  oz += A * fz;
+  oz += cr * dz;
+  oz += iR * (G * ez + H);
 
   if (TORQUE) {
     // r x T and R x T share their rho terms: kv = (dy tz, -dx tz, dx ty - dy tx)
@@ -160,35 +163,38 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
     const Real s = -(kz * iR);                       // (e x z) . T
     const Real be = cT * dz + (iR2 * d2 - iR3 * Rz);  // coefficient of (ty, -tx, 0)
     const Real ga = iR3 * (s * d3);                  // coefficient of rho
-    ox += al * kx + (be * ty + ga * dx);
-    oy += al * ky + (ga * dy - be * tx);
-    oz += al * kz + (iR2 * s) * (d3 * ez - Real(2) * X);
+    ox += al * kx;
+    ox += be * ty;
+    ox += ga * dx;
+    oy += al * ky;
+    oy += ga * dy;
+    oy -= be * tx;
+    oz += al * kz;
+    oz += (iR2 * s) * (d3 * ez - Real(2) * X);
   }
 }
 
 // Both directions of one unordered pair of force-only sources, from one evaluation of the
 // coefficients: the mobility matrix is symmetric, M_ji = M_ij^T (reciprocity of Blake's tensor;
 // the unbounded part depends on r r^T and |r| only), so
-//   (ox, oy, oz) = M_ij F_j   (velocity of i, 8 pi eta units)
-//   (px, py, pz) = M_ij^T F_i (velocity of j)
+//   (ox, oy, oz) += M_ij F_j   (velocity of i, 8 pi eta units)
+//   (px, py, pz) += M_ij^T F_i (velocity of j)
 // where M_ij^T swaps the roles of c3 and c4 (e z^T <-> z e^T).
 template <typename Real, bool FAR_ONLY = false>
 __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Real zj, Real fx,
                                                   Real fy, Real fz, Real gx, Real gy, Real gz,
                                                   const PairConsts<Real> &k, Real &ox, Real &oy,
-                                                  Real &oz, Real &px, Real &py, Real &pz,
-                                                  Real &r2_out) {
+                                                  Real &oz, Real &px, Real &py, Real &pz) {
   const Real dz = zi - zj;
   const Real Rz = zi + zj;
   const Real rho2 = dx * dx + dy * dy;
   const Real r2 = rho2 + dz * dz;
   const Real R2 = rho2 + Rz * Rz;
   const Real iR = rsqrt_r(R2);
-  r2_out = r2;
 
   Real cI, cRR;
   if (FAR_ONLY) {
-    // valid for r2 >= (2a)^2 only: the caller re-evaluates closer pairs with FAR_ONLY = false
+    // valid for r2 >= (2a)^2 only: the caller routes closer pairs to FAR_ONLY = false
     const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
     const Real s = k.a2 * ir2;
@@ -235,9 +241,13 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
   const Real H = c4 * eF + c5 * fz;
   const Real cr = cRR * rF;
   const Real B = cr + iR2 * G;
-  ox = A * fx + B * dx;
-  oy = A * fy + B * dy;
-  oz = A * fz + (cr * dz + iR * (G * ez + H));
+  ox += A * fx;
+  ox += B * dx;
+  oy += A * fy;
+  oy += B * dy;
+  oz += A * fz;
+  oz += cr * dz;
+  oz += iR * (G * ez + H);
 
   // j <- i (transposed tensor)
   const Real rhoG = dx * gx + dy * gy;
@@ -247,9 +257,13 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
   const Real H2 = c3 * eG + c5 * gz;
   const Real cr2 = cRR * rG;
   const Real B2 = cr2 + iR2 * G2;
-  px = A * gx + B2 * dx;
-  py = A * gy + B2 * dy;
-  pz = A * gz + (cr2 * dz + iR * (G2 * ez + H2));
+  px += A * gx;
+  px += B2 * dx;
+  py += A * gy;
+  py += B2 * dy;
+  pz += A * gz;
+  pz += cr2 * dz;
+  pz += iR * (G2 * ez + H2);
 }
 
 }  // namespace rpb
