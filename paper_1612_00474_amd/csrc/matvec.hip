@@ -399,15 +399,19 @@ __device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, in
 // its targets against source j (weighted force zero when !valid), adding M_ij F_j into acc and
 // M_ij^T F_i into cs.  Pairs at least 2a apart use the far-field form alone; closer pairs (rare
 // in a suspension) the complete form, so each pair's value depends on its own geometry only.
-template <int TPT>
-__device__ __forceinline__ void sym_step(const LdsF<false> &L, int j, bool valid,
-                                         const TargetsF<TPT> &T, const float (&gx)[TPT],
-                                         const float (&gy)[TPT], const float (&gz)[TPT],
+template <int TPT, bool TORQUE>
+__device__ __forceinline__ void sym_step(const LdsF<TORQUE> &L, int j, bool valid,
+                                         const TargetsF<TPT> &T, const float (&own)[TPT][6],
                                          const PairConsts<float> &k, float (&acc)[TPT][3],
                                          float (&cs)[3]) {
   const float xjh = L.xh[j], xjl = L.xl[j], yjh = L.yh[j], yjl = L.yl[j], zj = L.z[j];
   const float fx = valid ? L.f[0][j] : 0.f, fy = valid ? L.f[1][j] : 0.f,
               fz = valid ? L.f[2][j] : 0.f;
+  float tq[3] = {0.f, 0.f, 0.f};
+  if (TORQUE) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tq[c] = valid ? L.t[c][j] : 0.f;
+  }
   // the sums start at zero, so the first step rotates zeros
 #pragma unroll
   for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
@@ -417,45 +421,66 @@ __device__ __forceinline__ void sym_step(const LdsF<false> &L, int j, bool valid
     const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
     const float dz = T.z[q] - zj;
     if (dx * dx + dy * dy + dz * dz < k.four_a2)
-      pair_velocity_sym<float>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k, acc[q][0],
-                               acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
+      pair_velocity_sym<float, false, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                              own[q][1], own[q][2], k, acc[q][0], acc[q][1],
+                                              acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
     else
-      pair_velocity_sym<float, true>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
-                                     acc[q][0], acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
+      pair_velocity_sym<float, true, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                             own[q][1], own[q][2], k, acc[q][0], acc[q][1],
+                                             acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
   }
 }
 
-template <int TPT>
-__device__ __forceinline__ void sym_step(const LdsD<false> &L, int j, bool valid,
-                                         const TargetsD<TPT> &T, const double (&gx)[TPT],
-                                         const double (&gy)[TPT], const double (&gz)[TPT],
+template <int TPT, bool TORQUE>
+__device__ __forceinline__ void sym_step(const LdsD<TORQUE> &L, int j, bool valid,
+                                         const TargetsD<TPT> &T, const double (&own)[TPT][6],
                                          const PairConsts<double> &k, double (&acc)[TPT][3],
                                          double (&cs)[3]) {
   const double xj = L.x[j], yj = L.y[j], zj = L.z[j];
   const double fx = valid ? L.f[0][j] : 0.0, fy = valid ? L.f[1][j] : 0.0,
                fz = valid ? L.f[2][j] : 0.0;
+  double tq[3] = {0.0, 0.0, 0.0};
+  if (TORQUE) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tq[c] = valid ? L.t[c][j] : 0.0;
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
     const double dx = T.x[q] - xj, dy = T.y[q] - yj, dz = T.z[q] - zj;
     if (dx * dx + dy * dy + dz * dz < k.four_a2)
-      pair_velocity_sym<double>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
-                                acc[q][0], acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
+      pair_velocity_sym<double, false, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                               own[q][1], own[q][2], k, acc[q][0], acc[q][1],
+                                               acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
     else
-      pair_velocity_sym<double, true>(dx, dy, T.z[q], zj, fx, fy, fz, gx[q], gy[q], gz[q], k,
-                                      acc[q][0], acc[q][1], acc[q][2], cs[0], cs[1], cs[2]);
+      pair_velocity_sym<double, true, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                              own[q][1], own[q][2], k, acc[q][0], acc[q][1],
+                                              acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
   }
 }
 
-template <int TPT>
+// The targets' own weighted force and torque (zero for rows past the end).
+template <int TPT, typename Real>
+__device__ __forceinline__ void load_own(const Real *__restrict__ src, int64_t n, int64_t first,
+                                         bool torque, Real (&own)[TPT][6]) {
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int64_t r = first + q * kBlock + threadIdx.x;
+    const bool on = r < n;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) own[q][c] = on && (c < 3 || torque) ? src[c * n + r] : Real(0);
+  }
+}
+
+template <int TPT, bool TORQUE>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
                                                                 const float *__restrict__ src,
                                                                 PairConsts<float> k,
                                                                 double *__restrict__ partial) {
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  __shared__ LdsF<false> L;
+  __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
@@ -465,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_mixed<false, TPT>(g, src, n, jb, je, k, L, T);
+    sources_mixed<TORQUE, TPT>(g, src, n, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -476,15 +501,8 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
     }
     return;
   }
-  float gx[TPT], gy[TPT], gz[TPT];    // the targets' own weighted forces (zero when absent)
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int64_t r = first + q * kBlock + tid;
-    const bool on = r < n;
-    gx[q] = on ? src[r] : 0.f;
-    gy[q] = on ? src[n + r] : 0.f;
-    gz[q] = on ? src[2 * n + r] : 0.f;
-  }
+  float own[TPT][6];
+  load_own<TPT>(src, n, first, TORQUE, own);
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
@@ -495,9 +513,11 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
       L.yh[tid] = g.yh[j];
       L.yl[tid] = g.yl[j];
       L.z[tid] = g.z[j];
-      L.f[0][tid] = src[j];
-      L.f[1][tid] = src[n + j];
-      L.f[2][tid] = src[2 * n + j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        L.f[c][tid] = src[c * n + j];
+        if (TORQUE) L.t[c][tid] = src[(3 + c) * n + j];
+      }
     }
     __syncthreads();
     float acc[TPT][3];
@@ -509,11 +529,11 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
       if (nb == 64) {
 #pragma unroll 2
         for (int step = 0; step < 64; ++step)
-          sym_step<TPT>(L, blk + ((lane + step) & 63), true, T, gx, gy, gz, k, acc, cs);
+          sym_step<TPT, TORQUE>(L, blk + ((lane + step) & 63), true, T, own, k, acc, cs);
       } else {
         for (int step = 0; step < 64; ++step) {
           const int sl = (lane + step) & 63;
-          sym_step<TPT>(L, blk + (sl < nb ? sl : 0), sl < nb, T, gx, gy, gz, k, acc, cs);
+          sym_step<TPT, TORQUE>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, acc, cs);
         }
       }
       const int sl = (lane + 63) & 63;
@@ -549,14 +569,14 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
   }
 }
 
-template <int TPT>
+template <int TPT, bool TORQUE>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g,
                                                               const double *__restrict__ src,
                                                               PairConsts<double> k,
                                                               double *__restrict__ partial) {
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  __shared__ LdsD<false> L;
+  __shared__ LdsD<TORQUE> L;
   __shared__ double col[kWaves][kBlock][3];
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
@@ -566,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_f64<false, TPT>(g, src, n, jb, je, k, L, T);
+    sources_f64<TORQUE, TPT>(g, src, n, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -576,15 +596,8 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
     }
     return;
   }
-  double gx[TPT], gy[TPT], gz[TPT];
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int64_t r = first + q * kBlock + tid;
-    const bool on = r < n;
-    gx[q] = on ? src[r] : 0.0;
-    gy[q] = on ? src[n + r] : 0.0;
-    gz[q] = on ? src[2 * n + r] : 0.0;
-  }
+  double own[TPT][6];
+  load_own<TPT>(src, n, first, TORQUE, own);
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
@@ -593,9 +606,11 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
       L.x[tid] = g.x[j];
       L.y[tid] = g.y[j];
       L.z[tid] = g.z[j];
-      L.f[0][tid] = src[j];
-      L.f[1][tid] = src[n + j];
-      L.f[2][tid] = src[2 * n + j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        L.f[c][tid] = src[c * n + j];
+        if (TORQUE) L.t[c][tid] = src[(3 + c) * n + j];
+      }
     }
     __syncthreads();
     for (int blk = 0; blk < cnt; blk += 64) {
@@ -604,11 +619,11 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
       if (nb == 64) {
 #pragma unroll 2
         for (int step = 0; step < 64; ++step)
-          sym_step<TPT>(L, blk + ((lane + step) & 63), true, T, gx, gy, gz, k, T.u, cs);
+          sym_step<TPT, TORQUE>(L, blk + ((lane + step) & 63), true, T, own, k, T.u, cs);
       } else {
         for (int step = 0; step < 64; ++step) {
           const int sl = (lane + step) & 63;
-          sym_step<TPT>(L, blk + (sl < nb ? sl : 0), sl < nb, T, gx, gy, gz, k, T.u, cs);
+          sym_step<TPT, TORQUE>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, T.u, cs);
         }
       }
       const int sl = (lane + 63) & 63;
@@ -815,7 +830,7 @@ int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *po
 
 // Force-only product of the whole system with one evaluation per unordered pair.
 int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
-                     const double *h, int tpt, double *vel, hipStream_t stream) {
+                     bool torque, const double *h, int tpt, double *vel, hipStream_t stream) {
   const int64_t n = g.n;
   const bool f64 = g.precision == RPB_FP64;
   SymArgs a{n, int64_t(kBlock) * tpt, 0};
@@ -832,20 +847,28 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
   if (f64) {
     const auto k = make_pair_consts<double>(p->a);
     const double *sv = static_cast<const double *>(src);
-    if (tpt == 2)
-      pair_kernel_f64_sym<2><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
+    if (torque && tpt == 2)
+      pair_kernel_f64_sym<2, true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
+    else if (torque)
+      pair_kernel_f64_sym<1, true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_f64_sym<2, false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
     else
-      pair_kernel_f64_sym<1><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
+      pair_kernel_f64_sym<1, false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
   } else {
     const auto k = make_pair_consts<float>(p->a);
     const float *sv = static_cast<const float *>(src);
-    if (tpt == 2)
-      pair_kernel_mixed_sym<2><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
+    if (torque && tpt == 2)
+      pair_kernel_mixed_sym<2, true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
+    else if (torque)
+      pair_kernel_mixed_sym<1, true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_mixed_sym<2, false><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
     else
-      pair_kernel_mixed_sym<1><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
+      pair_kernel_mixed_sym<1, false><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
   }
   RPB_LAUNCHED(ctx);
-  RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), f64 ? 0 : 2));
+  RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), (f64 ? 0 : 2) + (torque ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta);
   reduce_partials_sym<<<blocks_for(n, 256), 256, 0, stream>>>(a, part, h, scale, vel);
   RPB_LAUNCHED(ctx);
@@ -868,8 +891,8 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   // order whichever rows are requested: row shards concatenate to the full product bitwise.
   const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
   const int tpt = shape.tpt;
-  if (!has_t && row0 == 0 && nrows == n && shape.symmetric)
-    return matvec_symmetric(ctx, p, g, src, h, tpt, vel, stream);
+  if (row0 == 0 && nrows == n && shape.symmetric)
+    return matvec_symmetric(ctx, p, g, src, has_t, h, tpt, vel, stream);
   const int64_t per_wg = int64_t(kBlock) * tpt;
   const int64_t tiles = (nrows + per_wg - 1) / per_wg;
   const int64_t tiles_full = (n + per_wg - 1) / per_wg;

@@ -174,17 +174,22 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   }
 }
 
-// Both directions of one unordered pair of force-only sources, from one evaluation of the
-// coefficients: the mobility matrix is symmetric, M_ji = M_ij^T (reciprocity of Blake's tensor;
-// the unbounded part depends on r r^T and |r| only), so
+// Both directions of one unordered pair, from one evaluation of the coefficients: the
+// mobility matrix is symmetric, M_ji = M_ij^T (reciprocity of Blake's tensor; the unbounded part
+// depends on r r^T and |r| only), so
 //   (ox, oy, oz) += M_ij F_j   (velocity of i, 8 pi eta units)
 //   (px, py, pz) += M_ij^T F_i (velocity of j)
-// where M_ij^T swaps the roles of c3 and c4 (e z^T <-> z e^T).
-template <typename Real, bool FAR_ONLY = false>
+// where M_ij^T swaps the roles of c3 and c4 (e z^T <-> z e^T).  With TORQUE the coupling terms
+// are added too, (o) += M^C_ij T_j and (p) += M^C_ji T_i (tq: T_j, uq: T_i).  M^C has no such
+// symmetry, but M^C_ji is the same expression with r -> -r and the image height hh = z~_j/|R|
+// replaced by z~_i/|R|, so everything else (|R|, e_z, X, the unbounded coefficient) is shared.
+template <typename Real, bool FAR_ONLY = false, bool TORQUE = false>
 __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Real zj, Real fx,
                                                   Real fy, Real fz, Real gx, Real gy, Real gz,
                                                   const PairConsts<Real> &k, Real &ox, Real &oy,
-                                                  Real &oz, Real &px, Real &py, Real &pz) {
+                                                  Real &oz, Real &px, Real &py, Real &pz,
+                                                  const Real *tq = nullptr,
+                                                  const Real *uq = nullptr) {
   const Real dz = zi - zj;
   const Real Rz = zi + zj;
   const Real rho2 = dx * dx + dy * dy;
@@ -192,25 +197,36 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
   const Real R2 = rho2 + Rz * Rz;
   const Real iR = rsqrt_r(R2);
 
-  Real cI, cRR;
+  Real cI, cRR, cT = Real(0);
   if (FAR_ONLY) {
     // valid for r2 >= (2a)^2 only: the caller routes closer pairs to FAR_ONLY = false
     const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
     const Real s = k.a2 * ir2;
     cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
-    cRR = invr * ir2 * (Real(1) - Real(2) * s);
+    if (TORQUE) {
+      cT = invr * ir2;
+      cRR = cT * (Real(1) - Real(2) * s);
+    } else {
+      cRR = invr * ir2 * (Real(1) - Real(2) * s);
+    }
   } else {
     const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
     if (r2 >= k.four_a2) {
       const Real ir2 = invr * invr;
       const Real s = k.a2 * ir2;
       cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
-      cRR = invr * ir2 * (Real(1) - Real(2) * s);
+      if (TORQUE) {
+        cT = invr * ir2;
+        cRR = cT * (Real(1) - Real(2) * s);
+      } else {
+        cRR = invr * ir2 * (Real(1) - Real(2) * s);
+      }
     } else {
       const Real r = r2 * invr;
       cI = k.near_i - k.near_i_r * r;
       cRR = k.near_rr * invr;
+      if (TORQUE) cT = k.near_t - k.near_t_r * r;
     }
   }
 
@@ -264,6 +280,48 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
   pz += A * gz;
   pz += cr2 * dz;
   pz += iR * (G2 * ez + H2);
+
+  if (TORQUE) {
+    const Real iR3 = iR * iR2;
+    const Real al = iR3 - cT;                 // coefficient of kv (both directions)
+    const Real xez = X * ez;
+    const Real be0 = iR2 * (Real(2) * xez) - iR3 * Rz;
+    const Real d30 = Real(10) * xez - Real(6) * ez;
+    const Real wz = d30 * ez - Real(2) * X;   // with the hh part of d3 added per direction
+    {  // i <- j: torque T_j, image height z~_j
+      const Real tx = tq[0], ty = tq[1], tz = tq[2];
+      const Real kx = dy * tz, ky = -(dx * tz), kz = dx * ty - dy * tx;
+      const Real d3 = d30 + Real(6) * hh;
+      const Real sv = -(kz * iR);
+      const Real be = cT * dz + (be0 + iR2 * hh2x);
+      const Real ga = iR3 * (sv * d3);
+      ox += al * kx;
+      ox += be * ty;
+      ox += ga * dx;
+      oy += al * ky;
+      oy += ga * dy;
+      oy -= be * tx;
+      oz += al * kz;
+      oz += (iR2 * sv) * (wz + Real(6) * hh * ez);
+    }
+    {  // j <- i: torque T_i, r -> -r, image height z~_i
+      const Real tx = uq[0], ty = uq[1], tz = uq[2];
+      const Real hi = zi * iR;
+      const Real kx = -(dy * tz), ky = dx * tz, kz = dy * tx - dx * ty;
+      const Real d3 = d30 + Real(6) * hi;
+      const Real sv = -(kz * iR);
+      const Real be = (be0 + iR2 * (Real(2) * hi)) - cT * dz;
+      const Real ga = iR3 * (sv * d3);
+      px += al * kx;
+      px += be * ty;
+      px -= ga * dx;
+      py += al * ky;
+      py -= ga * dy;
+      py -= be * tx;
+      pz += al * kz;
+      pz += (iR2 * sv) * (wz + Real(6) * hi * ez);
+    }
+  }
 }
 
 }  // namespace rpb

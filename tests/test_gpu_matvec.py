@@ -94,15 +94,25 @@ def test_force_only_and_torque_only(ctx, c1, c1_ref):
 
 
 def test_row_shards_concatenate_bitwise(ctx):
+    # row ranges use the ordered (target tile x source chunk) kernel, whose chunking depends on n
+    # only; the whole product matches them bitwise when it takes that kernel too, and the
+    # symmetric kernel's whole product within rounding
+    from paper_1612_00474_amd import Context
+    c = Context(0)
     pos = wl.sheet(5000, seed=2)
     rng = np.random.default_rng(2)
     F, T = dev(rng.standard_normal(pos.shape)), dev(rng.standard_normal(pos.shape))
     P = dev(pos)
     for precision in ("fp64", "mixed"):
-        full = host(ctx.matvec(P, F, T, precision))
+        c.set_tuning(precision, symmetric=0)
+        full = host(c.matvec(P, F, T, precision))
         cuts = [0, 1, 700, 2500, 4999, 5000]
-        parts = [host(ctx.matvec(P, F, T, precision, rows=(a, b))) for a, b in zip(cuts[:-1], cuts[1:])]
+        parts = [host(c.matvec(P, F, T, precision, rows=(a, b))) for a, b in zip(cuts[:-1], cuts[1:])]
         assert np.array_equal(np.vstack(parts), full)
+        c.set_tuning(precision, symmetric=1)
+        sym = host(c.matvec(P, F, T, precision))
+        assert rel2(sym, full) <= (1e-13 if precision == "fp64" else 2e-6)
+    c.close()
 
 
 def test_deterministic(ctx, c1):
@@ -153,25 +163,28 @@ def test_error_paths(ctx, c1):
     assert ctx.matvec(empty, empty, None).shape == (0, 3)
 
 
+@pytest.mark.parametrize("torque", [False, True])
 @pytest.mark.parametrize("tpt", [1, 2])
 @pytest.mark.parametrize("n", [2, 63, 64, 65, 300, 513, 1100])
-def test_symmetric_kernel_matches_oracle_and_ordered(ctx, n, tpt):
-    # force-only whole-system products take the symmetric tile-pair kernel (each unordered pair
-    # evaluated once); ragged tiles and partial 64-source blocks included
+def test_symmetric_kernel_matches_oracle_and_ordered(ctx, n, tpt, torque):
+    # whole-system products take the symmetric tile-pair kernel (each unordered pair evaluated
+    # once; with torques both coupling directions come from the shared geometry); ragged tiles
+    # and partial 64-source blocks included
     from paper_1612_00474_amd import Context
     c = Context(0)
     rng = np.random.default_rng(100 + n)
     side = max(2.0, math.sqrt(n * math.pi / 0.4))
     pos = np.column_stack([rng.uniform(0, side, n), rng.uniform(0, side, n), rng.uniform(0.8, 2.6, n)])
     F = rng.standard_normal((n, 3))
-    ref = mobility.dense_matvec(pos, F, None)
-    P, Fd = dev(pos), dev(F)
+    T = rng.standard_normal((n, 3)) if torque else None
+    ref = mobility.dense_matvec(pos, F, T)
+    P, Fd, Td = dev(pos), dev(F), (dev(T) if torque else None)
     for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
         c.set_tuning(precision, tpt=tpt, symmetric=1)
-        us = host(c.matvec(P, Fd, None, precision))
+        us = host(c.matvec(P, Fd, Td, precision))
         assert rel2(us, ref) <= tol, (precision, n, tpt)
-        assert np.array_equal(us, host(c.matvec(P, Fd, None, precision)))     # reproducible
+        assert np.array_equal(us, host(c.matvec(P, Fd, Td, precision)))     # reproducible
         c.set_tuning(precision, symmetric=0)
-        uo = host(c.matvec(P, Fd, None, precision))
+        uo = host(c.matvec(P, Fd, Td, precision))
         assert rel2(us, uo) <= (1e-13 if precision == "fp64" else 2e-6)
     c.close()
