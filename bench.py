@@ -35,9 +35,14 @@ PEAK_FP64_TFLOPS = 78.6
 KIND_FP64_FORCE, KIND_FP64_TORQUE, KIND_MIXED_FORCE, KIND_MIXED_TORQUE = 0, 1, 2, 3
 
 
-def measured_traffic(kernel: str):
+PROFILED_N = 65536   # sheet size of the committed counter summary
+
+
+def measured_traffic(kernel: str, n: int = PROFILED_N):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the kernel sources changed since the counters were taken."""
+    when the kernel sources changed since the counters were taken or `n` is another size."""
+    if n != PROFILED_N:
+        return None
     import hashlib
     csrc = os.path.join(ROOT, "paper_1612_00474_amd", "csrc")
     h = hashlib.sha256()
@@ -61,7 +66,7 @@ def force_kernel_name(prec: str, shape: dict) -> str:
     """rocprofv3 name of the pair kernel that a force-only product launches with `shape`."""
     kind = "mixed" if prec == "mixed" else "f64"
     if shape["symmetric"]:
-        return f"pair_kernel_{kind}_sym<{shape['tpt']}>"
+        return f"pair_kernel_{kind}_sym<{shape['tpt']}, false>"
     return f"pair_kernel_{kind}<false, {shape['tpt']}>"
 
 
@@ -77,19 +82,32 @@ def parse():
 
 
 def cpu_baseline(w, rows):
-    """Time the FP64 oracle's matrix-free product on `rows` target rows (all N sources)."""
+    """Time the FP64 oracle's matrix-free product on `rows` target rows (all N sources); for a
+    batch, on rows of its first system, sized to about the same number of pairs."""
     import numpy as np
     from oracle import mobility
     from paper_1612_00474_amd import workloads as wl
-    inp = wl.make_inputs(w, 0)
+    if w.nsys > 1:
+        pos_b, offs = wl.make_batch(w, 0)
+        n = int(offs[1])
+        pos = pos_b[:n]
+        rng = np.random.default_rng(0)
+        force, torque = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+        rows = min(n, max(1, rows * 65536 // n))
+        what = f"system 0 of the batch (N = {n})"
+    else:
+        inp = wl.make_inputs(w, 0)
+        pos, force, torque, n = inp["pos"], inp["force"], inp["torque"], w.n
+        rows = min(n, max(1, rows * 65536 // n))
+        what = f"{n} sources"
     sel = np.arange(rows)
-    mobility.matvec(inp["pos"][:64], inp["force"][:64], inp["torque"][:64])   # warm the tensors
+    mobility.matvec(pos[:64], force[:64], torque[:64])   # warm the tensors
     t0 = time.perf_counter()
-    mobility.matvec(inp["pos"], inp["force"], inp["torque"], rows=sel)
+    mobility.matvec(pos, force, torque, rows=sel)
     dt = time.perf_counter() - t0
-    pairs = rows * w.n
+    pairs = rows * n
     return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows} target rows x {w.n} sources of one product M F + M_C T "
+            "sample": f"{rows} target rows x {what}, one product M F + M_C T "
                       f"({pairs:.3e} pairs, {dt:.1f} s, single process)"}
 
 
@@ -115,7 +133,7 @@ def main():
     torch.cuda.init()
     ctx = Context(0, a=w.a, eta=w.eta, kT=w.kT)
     if w.nsys > 1:
-        return bench_batched(args, w, ctx)
+        return bench_batched(args, w, ctx, cpu)
     inp = wl.make_inputs(w, 0)
     pos0 = torch.as_tensor(inp["pos"]).cuda()
     F = torch.as_tensor(inp["force"]).cuda()
@@ -202,7 +220,7 @@ def main():
                                       "ms_per_launch": {"mixed": mixed_ms, "fp64": f64_ms}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(force_kernel_name(prec, shapes[prec])),
+                     "traffic": measured_traffic(force_kernel_name(prec, shapes[prec]), n),
                      "kernel": f"{force_kernel_name(prec, shapes[prec])}, force-only "
                                f"products ({FLOPS_PER_PAIR_FORCE} flop/pair x {n}^2 pairs/launch)",
                      "ms_per_launch": dom["ms_per_launch"], "launches": dom["launches"]},
@@ -213,7 +231,7 @@ def main():
     ctx.close()
 
 
-def bench_batched(args, w, ctx):
+def bench_batched(args, w, ctx, cpu):
     """Batched suspensions: one persistent launch per product, steps replayed from a hipGraph."""
     import numpy as np
     import torch
@@ -293,7 +311,7 @@ def bench_batched(args, w, ctx):
                      "kernel": f"batched pair kernel, force-only, {FLOPS_PER_PAIR_FORCE} flop/pair x "
                                f"sum N_s^2 = {sum_sq:.4e} pairs/launch",
                      "ms_per_launch": dom["ms_per_launch"]},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line))
     ctx.close()

@@ -69,9 +69,11 @@ WORKLOADS = {
     # Mixed precision at N = 65,536 (the headline size).
     "sheet64k_mixed": Workload("sheet64k_mixed", 65536, side_for_area_fraction(65536, PHI),
                                1.1, 2.5, precision="mixed", steps=10),
-    # 64 independent suspensions of uneven size.
+    # 64 independent suspensions of uneven size, float64 and mixed precision.
     "batch64_uneven": Workload("batch64_uneven", 0, 0.0, 1.1, 2.5, nsys=64,
                                n_lo=1024, n_hi=8192),
+    "batch64_uneven_mixed": Workload("batch64_uneven_mixed", 0, 0.0, 1.1, 2.5, nsys=64,
+                                     n_lo=1024, n_hi=8192, precision="mixed"),
     # Large sheet.
     "sheet256k_mixed": Workload("sheet256k_mixed", 262144, side_for_area_fraction(262144, PHI),
                                 1.1, 2.0, precision="mixed", steps=20, dt=0.005),
