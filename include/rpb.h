@@ -239,23 +239,28 @@ void rpb_step_graph_destroy(rpb_graph *g);
 
 /* Launch-shape tuning ---------------------------------------------------------------------
  *
- * One shape per precision.  tpt: targets per lane of the pair kernels (1 or 2); target_wgs:
- * workgroups the single-system kernel aims for when splitting the sources into chunks;
- * batch_chunk: sources per work item of the batched kernel (multiple of 256); batch_wgs:
- * persistent workgroups of the batched kernel; symmetric: whole-system products without
- * torque use the symmetric tile-pair kernel (M_ij = M_ji^T: each unordered pair evaluated once,
- * both directions applied).  rpb_autotune times the candidates for
+ * One shape per precision.  Single-system products: tpt, targets per lane of the pair kernels
+ * (1 or 2); target_wgs, workgroups the ordered kernel aims for when splitting the sources into
+ * chunks; symmetric, whole-system products use the symmetric tile-pair kernel (M_ij = M_ji^T:
+ * each unordered pair evaluated once, both directions applied; with torques both coupling
+ * directions come from the shared geometry).  Row ranges (rpb_mobility_matvec_rows) always
+ * take the ordered kernel.  Batched products: batch_tpt (1 or 2); batch_symmetric, the
+ * persistent kernel works on (system, tile pair) items of the symmetric kernel instead of
+ * (system, target tile, source chunk) items; batch_chunk, sources per ordered work item
+ * (multiple of 256); batch_wgs, persistent workgroups.  rpb_autotune times the candidates for
  * p->precision on the given configuration (force-only products, `reps` launches each, HIP
- * events on `stream`), keeps the fastest in the context and caches it per (precision,
- * single/batched, floor(log2 n_total)); a cached shape is reused without timing
- * (best_ms_out = -1 then).  Results depend on the shape only through the order of the
- * floating-point summation. */
+ * events on `stream`); nsys = 1 tunes the single-system fields, nsys > 1 the batched ones.
+ * The fastest is kept in the context and cached per (precision, single/batched,
+ * floor(log2 n_total)); a cached shape is reused without timing (best_ms_out = -1 then).
+ * Results depend on the shape only through the order of the floating-point summation. */
 typedef struct {
   int tpt;
   int target_wgs;
   int batch_chunk;
   int batch_wgs;
-  int symmetric;   /* 1: whole-system force-only products evaluate each unordered pair once */
+  int symmetric;        /* 1: whole-system products evaluate each unordered pair once */
+  int batch_tpt;
+  int batch_symmetric;  /* 1: batched products evaluate each unordered pair once */
 } rpb_shape;
 typedef struct {
   rpb_shape fp64;

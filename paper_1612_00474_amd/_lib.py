@@ -44,7 +44,8 @@ class RpbSabConfig(C.Structure):
 
 class RpbShape(C.Structure):
     _fields_ = [("tpt", C.c_int), ("target_wgs", C.c_int), ("batch_chunk", C.c_int),
-                ("batch_wgs", C.c_int), ("symmetric", C.c_int)]
+                ("batch_wgs", C.c_int), ("symmetric", C.c_int), ("batch_tpt", C.c_int),
+                ("batch_symmetric", C.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -172,6 +173,10 @@ class Context:
     """One librpb context on one device (not thread-safe; one per host thread)."""
 
     def __init__(self, device: int = 0, a: float = 1.0, eta: float = 1.0, kT: float = 1.0):
+        import torch
+        # torch owns the device memory and streams this library works on: its HIP runtime
+        # must be initialised before the library's first HIP call
+        torch.cuda.init()
         self.lib = load()
         h = C.c_void_p()
         st = self.lib.rpb_create(device, C.byref(h))
@@ -386,8 +391,8 @@ class Context:
         return t.as_dict()
 
     def set_tuning(self, precision, **kw):
-        """Change fields of one precision's launch shape (tpt, target_wgs, batch_chunk,
-        batch_wgs, symmetric)."""
+        """Change fields of one precision's launch shape (tpt, target_wgs, symmetric,
+        batch_tpt, batch_chunk, batch_wgs, batch_symmetric)."""
         cur = self.tuning()
         cur[precision].update(kw)
         t = RpbTuning(RpbShape(**cur["fp64"]), RpbShape(**cur["mixed"]))

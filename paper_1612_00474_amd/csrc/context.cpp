@@ -113,7 +113,8 @@ int rpb_create(int hip_device, rpb_ctx **out) {
   rpb_ctx *c = new (std::nothrow) rpb_ctx();
   if (!c) return RPB_ENOMEM;
   c->device = hip_device;
-  // launch-shape overrides for experiments: RPB_<FP64|MIXED>_<TPT|WGS|CHUNK|BWGS>
+  // launch-shape overrides for experiments:
+  // RPB_<FP64|MIXED>_<TPT|WGS|CHUNK|BWGS|SYM|BTPT|BSYM>
   const char *pre[2] = {"RPB_FP64_", "RPB_MIXED_"};
   for (int q = 0; q < 2; ++q) {
     auto env = [&](const char *key, int lo, int hi, int mult, int *dst) {
@@ -129,6 +130,8 @@ int rpb_create(int hip_device, rpb_ctx **out) {
     env("CHUNK", 256, 1 << 20, 256, &sh.batch_chunk);
     env("BWGS", 1, 1 << 20, 1, &sh.batch_wgs);
     env("SYM", 0, 1, 1, &sh.symmetric);
+    env("BTPT", 1, 2, 1, &sh.batch_tpt);
+    env("BSYM", 0, 1, 1, &sh.batch_symmetric);
   }
   if (hipHostMalloc(&c->host_pinned, kHostScratchBytes, hipHostMallocDefault) != hipSuccess) {
     delete c;

@@ -356,9 +356,10 @@ __global__ void reduce_partials(int64_t nrows, int nchunks, const double *__rest
 // exactly nt partials, summed in slot order.
 
 struct SymArgs {
-  int64_t n;     // spheres
-  int64_t ts;    // tile size (kBlock * TPT)
-  int64_t nt;    // tiles
+  int64_t n;       // spheres of the system
+  int64_t ts;      // tile size (kBlock * TPT)
+  int64_t nt;      // tiles
+  int64_t stride;  // stride of the source component arrays (all systems' spheres)
 };
 
 // v from lane (l + 1) mod 64 (DPP wave_rol:1)
@@ -462,26 +463,33 @@ __device__ __forceinline__ void sym_step(const LdsD<TORQUE> &L, int j, bool vali
 
 // The targets' own weighted force and torque (zero for rows past the end).
 template <int TPT, typename Real>
-__device__ __forceinline__ void load_own(const Real *__restrict__ src, int64_t n, int64_t first,
-                                         bool torque, Real (&own)[TPT][6]) {
+__device__ __forceinline__ void load_own(const Real *__restrict__ src, int64_t n, int64_t stride,
+                                         int64_t first, bool torque, Real (&own)[TPT][6]) {
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
     const int64_t r = first + q * kBlock + threadIdx.x;
     const bool on = r < n;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) own[q][c] = on && (c < 3 || torque) ? src[c * n + r] : Real(0);
+    for (int c = 0; c < 6; ++c)
+      own[q][c] = on && (c < 3 || torque) ? src[c * stride + r] : Real(0);
   }
 }
 
+inline __device__ GeomF offset_geom(const GeomF &g, int64_t s0) {
+  return {g.xh + s0, g.xl + s0, g.yh + s0, g.yl + s0, g.z + s0, g.h + s0};
+}
+inline __device__ GeomD offset_geom(const GeomD &g, int64_t s0) {
+  return {g.x + s0, g.y + s0, g.z + s0, g.h + s0};
+}
+
+// Tile pair (I, J), I <= J, of one system: `g`, `src` and `partial` already point at the
+// system's first sphere and first partial slot.  Every lane of the workgroup must call this.
 template <int TPT, bool TORQUE>
-__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
-                                                                const float *__restrict__ src,
-                                                                PairConsts<float> k,
-                                                                double *__restrict__ partial) {
-  int64_t I, J;
-  tri_decode(blockIdx.x, a.nt, I, J);
-  __shared__ LdsF<TORQUE> L;
-  __shared__ float col[kWaves][kBlock][3];
+__device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
+                                              const float *__restrict__ src,
+                                              const PairConsts<float> &k,
+                                              double *__restrict__ partial, int64_t I, int64_t J,
+                                              LdsF<TORQUE> &L, float (&col)[kWaves][kBlock][3]) {
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t n = a.n;
@@ -490,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_mixed<TORQUE, TPT>(g, src, n, jb, je, k, L, T);
+    sources_mixed<TORQUE, TPT>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -502,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
     return;
   }
   float own[TPT][6];
-  load_own<TPT>(src, n, first, TORQUE, own);
+  load_own<TPT>(src, n, a.stride, first, TORQUE, own);
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
@@ -515,8 +523,8 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
       L.z[tid] = g.z[j];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        L.f[c][tid] = src[c * n + j];
-        if (TORQUE) L.t[c][tid] = src[(3 + c) * n + j];
+        L.f[c][tid] = src[c * a.stride + j];
+        if (TORQUE) L.t[c][tid] = src[(3 + c) * a.stride + j];
       }
     }
     __syncthreads();
@@ -570,14 +578,11 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
 }
 
 template <int TPT, bool TORQUE>
-__global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g,
-                                                              const double *__restrict__ src,
-                                                              PairConsts<double> k,
-                                                              double *__restrict__ partial) {
-  int64_t I, J;
-  tri_decode(blockIdx.x, a.nt, I, J);
-  __shared__ LdsD<TORQUE> L;
-  __shared__ double col[kWaves][kBlock][3];
+__device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
+                                              const double *__restrict__ src,
+                                              const PairConsts<double> &k,
+                                              double *__restrict__ partial, int64_t I, int64_t J,
+                                              LdsD<TORQUE> &L, double (&col)[kWaves][kBlock][3]) {
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t n = a.n;
@@ -586,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_f64<TORQUE, TPT>(g, src, n, jb, je, k, L, T);
+    sources_f64<TORQUE, TPT>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -597,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
     return;
   }
   double own[TPT][6];
-  load_own<TPT>(src, n, first, TORQUE, own);
+  load_own<TPT>(src, n, a.stride, first, TORQUE, own);
   for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
     const int cnt = int(min<int64_t>(kBlock, je - t0));
     __syncthreads();
@@ -608,8 +613,8 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
       L.z[tid] = g.z[j];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        L.f[c][tid] = src[c * n + j];
-        if (TORQUE) L.t[c][tid] = src[(3 + c) * n + j];
+        L.f[c][tid] = src[c * a.stride + j];
+        if (TORQUE) L.t[c][tid] = src[(3 + c) * a.stride + j];
       }
     }
     __syncthreads();
@@ -652,6 +657,30 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
 #pragma unroll
       for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, J, d, local)] = T.u[q][d];
   }
+}
+
+template <int TPT, bool TORQUE>
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
+                                                                const float *__restrict__ src,
+                                                                PairConsts<float> k,
+                                                                double *__restrict__ partial) {
+  __shared__ LdsF<TORQUE> L;
+  __shared__ float col[kWaves][kBlock][3];
+  int64_t I, J;
+  tri_decode(blockIdx.x, a.nt, I, J);
+  sym_tile_pair<TPT, TORQUE>(a, g, src, k, partial, I, J, L, col);
+}
+
+template <int TPT, bool TORQUE>
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g,
+                                                              const double *__restrict__ src,
+                                                              PairConsts<double> k,
+                                                              double *__restrict__ partial) {
+  __shared__ LdsD<TORQUE> L;
+  __shared__ double col[kWaves][kBlock][3];
+  int64_t I, J;
+  tri_decode(blockIdx.x, a.nt, I, J);
+  sym_tile_pair<TPT, TORQUE>(a, g, src, k, partial, I, J, L, col);
 }
 
 __global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
@@ -749,6 +778,84 @@ __global__ void reduce_partials_batched(int64_t n, const int *__restrict__ sys_o
   }
 }
 
+// Symmetric batched product: items are (system, I, J) tile pairs with I <= J; system s owns the
+// partial slots from part_base[s] on, laid out as in the single-system symmetric kernel.
+struct SymBatchArgs {
+  const int64_t *offs;       // nsys + 1 prefix sums (device)
+  const int4 *items;         // (system, I, J, 0), largest first
+  int nitems;
+  int *counter;              // work counter (reset to 0 before the launch)
+  int64_t n;                 // total spheres (stride of the source arrays)
+  int64_t ts;                // tile size
+  const int64_t *part_base;  // first partial slot of each system
+  const int *done;           // optional per-system flags: items of finished systems are skipped
+};
+
+__device__ __forceinline__ SymArgs sym_args_of(const SymBatchArgs &b, int s) {
+  const int64_t ns = b.offs[s + 1] - b.offs[s];
+  return SymArgs{ns, b.ts, (ns + b.ts - 1) / b.ts, b.n};
+}
+
+__device__ __forceinline__ int next_sym_item(const SymBatchArgs &b, int *slot) {
+  __syncthreads();
+  if (threadIdx.x == 0) slot[0] = atomicAdd(b.counter, 1);
+  __syncthreads();
+  const int it = slot[0];
+  return it < b.nitems ? it : -1;
+}
+
+template <int TPT, bool TORQUE>
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
+    SymBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k,
+    double *__restrict__ partial) {
+  __shared__ LdsF<TORQUE> L;
+  __shared__ float col[kWaves][kBlock][3];
+  __shared__ int slot[1];
+  for (int it = next_sym_item(b, slot); it >= 0; it = next_sym_item(b, slot)) {
+    const int4 w = b.items[it];
+    if (b.done && b.done[w.x]) continue;
+    const int64_t s0 = b.offs[w.x];
+    sym_tile_pair<TPT, TORQUE>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
+                               partial + b.part_base[w.x], w.y, w.z, L, col);
+  }
+}
+
+template <int TPT, bool TORQUE>
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
+    SymBatchArgs b, GeomD g, const double *__restrict__ src, PairConsts<double> k,
+    double *__restrict__ partial) {
+  __shared__ LdsD<TORQUE> L;
+  __shared__ double col[kWaves][kBlock][3];
+  __shared__ int slot[1];
+  for (int it = next_sym_item(b, slot); it >= 0; it = next_sym_item(b, slot)) {
+    const int4 w = b.items[it];
+    if (b.done && b.done[w.x]) continue;
+    const int64_t s0 = b.offs[w.x];
+    sym_tile_pair<TPT, TORQUE>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
+                               partial + b.part_base[w.x], w.y, w.z, L, col);
+  }
+}
+
+__global__ void reduce_partials_sym_batched(SymBatchArgs b, const int *__restrict__ sys_of,
+                                            const double *__restrict__ partial,
+                                            const double *__restrict__ h, double scale,
+                                            double *__restrict__ vel) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= b.n) return;
+  const int s = sys_of[r];
+  if (b.done && b.done[s]) return;
+  const SymArgs a = sym_args_of(b, s);
+  const int64_t local = r - b.offs[s];
+  const int64_t T = local / a.ts, l = local % a.ts;
+  const double *base = partial + b.part_base[s];
+  const double w = scale * h[r];
+  for (int d = 0; d < 3; ++d) {
+    double acc = 0.0;
+    for (int64_t P = 0; P < a.nt; ++P) acc += base[sym_slot(a, T, P, d, l)];
+    vel[3 * r + d] = w * acc;
+  }
+}
+
 __global__ void fill_sys_of(int nsys, const int64_t *__restrict__ offs, int *__restrict__ sys_of) {
   const int s = blockIdx.x;
   if (s >= nsys) return;
@@ -833,7 +940,7 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
                      bool torque, const double *h, int tpt, double *vel, hipStream_t stream) {
   const int64_t n = g.n;
   const bool f64 = g.precision == RPB_FP64;
-  SymArgs a{n, int64_t(kBlock) * tpt, 0};
+  SymArgs a{n, int64_t(kBlock) * tpt, 0, n};
   a.nt = (n + a.ts - 1) / a.ts;
   if (a.nt * (a.nt + 1) / 2 > 0x7fffffffll)
     return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
@@ -954,27 +1061,44 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
 int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
                   hipStream_t stream) {
   const Shape &shape = ctx->tune.s[precision == RPB_FP64 ? RPB_FP64 : RPB_MIXED];
-  const int tpt = shape.tpt;
+  const int tpt = shape.batch_tpt;
   const int64_t chunk = shape.batch_chunk;
   b->nsys = nsys;
   b->n = offs[nsys];
   b->chunk = chunk;
   b->tpt = tpt;
   b->wgs = shape.batch_wgs;
+  b->symmetric = shape.batch_symmetric != 0;
   b->host_offs.assign(offs, offs + nsys + 1);
-  // work items, largest (targets x sources) first; ties keep (system, tile, chunk) order
+  // work items, largest (targets x sources) first; ties keep their generation order.
+  // Ordered: (system, target tile, source chunk); symmetric: (system, I, J) tile pairs, I <= J.
   std::vector<int4> items;
   std::vector<double> cost;
   const int64_t per = int64_t(kBlock) * tpt;
+  std::vector<int64_t> part_base(size_t(nsys), 0);
+  int64_t part_elems = 0;
   for (int s = 0; s < nsys; ++s) {
     const int64_t ns = offs[s + 1] - offs[s];
-    for (int64_t t = 0; t * per < ns; ++t)
-      for (int64_t c = 0; c * chunk < ns; ++c) {
-        items.push_back(int4{s, int(t), int(c), 0});
-        cost.push_back(double(std::min(per, ns - t * per)) *
-                       double(std::min(chunk, ns - c * chunk)));
-      }
+    if (b->symmetric) {
+      const int64_t nt = (ns + per - 1) / per;
+      part_base[s] = part_elems;
+      part_elems += nt * nt * 3 * per;
+      for (int64_t I = 0; I < nt; ++I)
+        for (int64_t J = I; J < nt; ++J) {
+          items.push_back(int4{s, int(I), int(J), 0});
+          cost.push_back(double(std::min(per, ns - I * per)) *
+                         double(std::min(per, ns - J * per)));
+        }
+    } else {
+      for (int64_t t = 0; t * per < ns; ++t)
+        for (int64_t c = 0; c * chunk < ns; ++c) {
+          items.push_back(int4{s, int(t), int(c), 0});
+          cost.push_back(double(std::min(per, ns - t * per)) *
+                         double(std::min(chunk, ns - c * chunk)));
+        }
+    }
   }
+  b->part_elems = part_elems;
   std::vector<size_t> order(items.size());
   std::iota(order.begin(), order.end(), size_t(0));
   std::stable_sort(order.begin(), order.end(),
@@ -989,8 +1113,9 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
     for (int64_t t = 0; t * kBlock < offs[s + 1] - offs[s]; ++t) tiles.push_back(int2{s, int(t)});
   b->ntiles = int(tiles.size());
 
-  // device copies: offs (nsys + 1 int64), items, sys_of (n int32); staged through pinned memory
-  const size_t offs_bytes = size_t(nsys + 1) * sizeof(int64_t);
+  // device copies: offs (nsys + 1 int64), part_base (nsys int64), items, tiles, sys_of (n int32);
+  // staged through pinned memory
+  const size_t offs_bytes = size_t(2 * nsys + 1) * sizeof(int64_t);
   const size_t items_bytes = std::max<size_t>(1, items.size()) * sizeof(int4);
   const size_t offs_pad = (offs_bytes + 255) / 256 * 256;
   const size_t items_pad = (items_bytes + 255) / 256 * 256;
@@ -1002,6 +1127,7 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
       workspace(ctx, WS_BATCH, offs_pad + items_pad + tiles_pad + sys_bytes, &st));
   if (!dev) return st;
   b->offs = reinterpret_cast<int64_t *>(dev);
+  b->part_base = b->offs + nsys + 1;
   b->items = reinterpret_cast<int4 *>(dev + offs_pad);
   b->tiles = reinterpret_cast<int2 *>(dev + offs_pad + items_pad);
   b->sys_of = reinterpret_cast<int *>(dev + offs_pad + items_pad + tiles_pad);
@@ -1016,7 +1142,9 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
     ctx->batch_host_bytes = host_bytes;
   }
   char *hb = static_cast<char *>(ctx->batch_host);
-  std::memcpy(hb, offs, offs_bytes);
+  std::memcpy(hb, offs, size_t(nsys + 1) * sizeof(int64_t));
+  std::memcpy(hb + size_t(nsys + 1) * sizeof(int64_t), part_base.data(),
+              size_t(nsys) * sizeof(int64_t));
   int4 *hi = reinterpret_cast<int4 *>(hb + offs_pad);
   for (size_t q = 0; q < order.size(); ++q) hi[q] = items[order[q]];
   int2 *ht = reinterpret_cast<int2 *>(hb + offs_pad + items_pad);
@@ -1033,6 +1161,62 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
   return RPB_OK;
 }
 
+namespace {
+
+int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
+                       const void *src, bool has_t, const int *done, int *counter, double *part,
+                       const double *h, double *vel, hipStream_t stream) {
+  const int64_t n = g.n;
+  const bool f64 = g.precision == RPB_FP64;
+  const int tpt = b.tpt;
+  SymBatchArgs args{b.offs, b.items, b.nitems, counter, n, int64_t(kBlock) * tpt, b.part_base,
+                    done};
+  const unsigned grid = unsigned(std::max(1, std::min(b.nitems, b.wgs)));
+  double pairs = 0.0;
+  for (int s = 0; s < b.nsys; ++s) {
+    const double ns = double(b.host_offs[s + 1] - b.host_offs[s]);
+    pairs += ns * ns;
+  }
+  hipEvent_t t0;
+  RPB_TRY(timing_begin(ctx, stream, &t0));
+  if (f64) {
+    const auto k = make_pair_consts<double>(p->a);
+    const double *sv = static_cast<const double *>(src);
+    const GeomD gd = geom_d(g);
+    if (has_t && tpt == 2)
+      pair_kernel_f64_sym_batched<2, true><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else if (has_t)
+      pair_kernel_f64_sym_batched<1, true><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_f64_sym_batched<2, false><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+    else
+      pair_kernel_f64_sym_batched<1, false><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+  } else {
+    const auto k = make_pair_consts<float>(p->a);
+    const float *sv = static_cast<const float *>(src);
+    const GeomF gf = geom_f(g);
+    if (has_t && tpt == 2)
+      pair_kernel_mixed_sym_batched<2, true><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+    else if (has_t)
+      pair_kernel_mixed_sym_batched<1, true><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
+    else if (tpt == 2)
+      pair_kernel_mixed_sym_batched<2, false><<<grid, kBlock, 0, stream>>>(args, gf, sv, k,
+                                                                           part);
+    else
+      pair_kernel_mixed_sym_batched<1, false><<<grid, kBlock, 0, stream>>>(args, gf, sv, k,
+                                                                           part);
+  }
+  RPB_LAUNCHED(ctx);
+  RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
+  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  reduce_partials_sym_batched<<<blocks_for(n, 256), 256, 0, stream>>>(args, b.sys_of, part, h,
+                                                                      scale, vel);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+}  // namespace
+
 int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
                    const double *force, const double *torque, const int *done, double *vel,
                    hipStream_t stream) {
@@ -1044,14 +1228,18 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
   RPB_TRY(pack_sources(ctx, g, force, torque, &src, stream));
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
   int st;
+  const size_t part_elems =
+      b.symmetric ? size_t(b.part_elems) : size_t(b.max_chunks) * 3 * size_t(n);
   double *part = static_cast<double *>(
-      workspace(ctx, WS_PART, size_t(b.max_chunks) * 3 * size_t(n) * sizeof(double), &st));
+      workspace(ctx, WS_PART, std::max<size_t>(1, part_elems) * sizeof(double), &st));
   if (!part) return st;
   char *small = static_cast<char *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
   if (!small) return st;
   int *counter = reinterpret_cast<int *>(small + kSmallWorkCounter);
   zero_int<<<1, 1, 0, stream>>>(counter);
   RPB_LAUNCHED(ctx);
+  if (b.symmetric) return matvec_batched_sym(ctx, p, b, g, src, has_t, done, counter, part, h,
+                                             vel, stream);
 
   BatchArgs args{b.offs, b.items, b.nitems, counter, n, b.chunk, done};
   const unsigned grid = unsigned(std::max(1, std::min(b.nitems, b.wgs)));

@@ -57,15 +57,17 @@ struct DevBuf {
 namespace rpb {
 // Launch shape of a pair kernel (chosen by the tuner; defaults from measurements).
 struct Shape {
-  int tpt;          // targets per lane (1 or 2)
-  int target_wgs;   // workgroups to aim for when splitting the sources into chunks
-  int batch_chunk;  // sources per work item of the batched kernel (multiple of 256)
-  int batch_wgs;    // persistent workgroups of the batched kernel
-  int symmetric;    // 1: whole-system force-only products evaluate each unordered pair once
+  int tpt;              // targets per lane (1 or 2)
+  int target_wgs;       // workgroups to aim for when splitting the sources into chunks
+  int batch_chunk;      // sources per ordered work item of the batched kernel (multiple of 256)
+  int batch_wgs;        // persistent workgroups of the batched kernel
+  int symmetric;        // 1: whole-system products evaluate each unordered pair once
+  int batch_tpt;        // targets per lane of the batched kernel
+  int batch_symmetric;  // 1: batched products evaluate each unordered pair once
 };
 // One shape per precision, indexed by rpb_precision (RPB_FP64 = 0, RPB_MIXED = 1).
 struct Tuning {
-  Shape s[2] = {{2, 4096, 1024, 2048, 1}, {1, 4096, 1024, 2048, 1}};
+  Shape s[2] = {{2, 4096, 1024, 2048, 1, 2, 1}, {2, 4096, 1024, 2048, 1, 2, 1}};
 };
 }  // namespace rpb
 
@@ -168,6 +170,9 @@ struct Batch {
   int *sys_of = nullptr;         // device, n entries
   int2 *tiles = nullptr;         // device: (system, 256-target tile) for the steric kernel
   int ntiles = 0;
+  bool symmetric = false;        // items are (system, I, J) tile pairs of the symmetric kernel
+  int64_t *part_base = nullptr;  // device, nsys entries: each system's first partial slot
+  int64_t part_elems = 0;        // partial doubles of the symmetric layout
 };
 
 int check_offsets(rpb_ctx *ctx, int32_t nsys, const int64_t *offs);

@@ -1,7 +1,8 @@
 // Launch-shape tuner for the pair kernels.
 //
-// Candidates (targets per lane, source split / work-item size, workgroup count) are timed with
-// HIP events on the caller's configuration and the fastest is kept in the context.  Results
+// Candidates (targets per lane, symmetric or ordered evaluation, source split / work-item size,
+// workgroup count) are timed with HIP events on the caller's configuration and the fastest is
+// kept in the context; single-system and batched products have fields of their own.  Results
 // are cached per (precision, single or batched, log2 of the sphere count), so a later call
 // with a similar problem reuses the choice without timing.
 #include <cmath>
@@ -61,11 +62,9 @@ int rpb_get_tuning(const rpb_ctx *ctx, rpb_tuning *out) {
   if (!ctx || !out) return RPB_EINVAL;
   rpb_shape *dst[2] = {&out->fp64, &out->mixed};
   for (int q = 0; q < 2; ++q) {
-    dst[q]->tpt = ctx->tune.s[q].tpt;
-    dst[q]->target_wgs = ctx->tune.s[q].target_wgs;
-    dst[q]->batch_chunk = ctx->tune.s[q].batch_chunk;
-    dst[q]->batch_wgs = ctx->tune.s[q].batch_wgs;
-    dst[q]->symmetric = ctx->tune.s[q].symmetric;
+    const Shape &v = ctx->tune.s[q];
+    *dst[q] = rpb_shape{v.tpt,       v.target_wgs, v.batch_chunk,    v.batch_wgs,
+                        v.symmetric, v.batch_tpt,  v.batch_symmetric};
   }
   return RPB_OK;
 }
@@ -77,12 +76,16 @@ int rpb_set_tuning(rpb_ctx *ctx, const rpb_tuning *t) {
     const rpb_shape &v = *src[q];
     if ((v.tpt != 1 && v.tpt != 2) || v.target_wgs < 1 || v.target_wgs > (1 << 20) ||
         v.batch_chunk < 256 || v.batch_chunk % 256 != 0 || v.batch_chunk > (1 << 20) ||
-        v.batch_wgs < 1 || v.batch_wgs > (1 << 20) || (v.symmetric != 0 && v.symmetric != 1))
+        v.batch_wgs < 1 || v.batch_wgs > (1 << 20) || (v.symmetric != 0 && v.symmetric != 1) ||
+        (v.batch_tpt != 1 && v.batch_tpt != 2) ||
+        (v.batch_symmetric != 0 && v.batch_symmetric != 1))
       return fail(ctx, RPB_EINVAL, "tuning values out of range");
   }
-  for (int q = 0; q < 2; ++q)
-    ctx->tune.s[q] = Shape{src[q]->tpt, src[q]->target_wgs, src[q]->batch_chunk,
-                           src[q]->batch_wgs, src[q]->symmetric};
+  for (int q = 0; q < 2; ++q) {
+    const rpb_shape &v = *src[q];
+    ctx->tune.s[q] = Shape{v.tpt,       v.target_wgs, v.batch_chunk,    v.batch_wgs,
+                           v.symmetric, v.batch_tpt,  v.batch_symmetric};
+  }
   return RPB_OK;
 }
 
@@ -114,13 +117,28 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
     std::vector<Shape> cands;
     for (int tpt : {1, 2}) {
       if (batched) {
-        for (int chunk : {512, 1024, 2048})
-          for (int wgs : {1024, 2048, 4096})
-            cands.push_back(Shape{tpt, base.target_wgs, chunk, wgs, base.symmetric});
+        for (int wgs : {1024, 2048, 4096}) {
+          Shape c = base;
+          c.batch_tpt = tpt;
+          c.batch_wgs = wgs;
+          c.batch_symmetric = 1;
+          cands.push_back(c);
+          c.batch_symmetric = 0;
+          for (int chunk : {512, 1024, 2048}) {
+            c.batch_chunk = chunk;
+            cands.push_back(c);
+          }
+        }
       } else {
-        cands.push_back(Shape{tpt, base.target_wgs, base.batch_chunk, base.batch_wgs, 1});
-        for (int wgs : {2048, 4096, 8192, 16384})
-          cands.push_back(Shape{tpt, wgs, base.batch_chunk, base.batch_wgs, 0});
+        Shape c = base;
+        c.tpt = tpt;
+        c.symmetric = 1;
+        cands.push_back(c);
+        c.symmetric = 0;
+        for (int wgs : {2048, 4096, 8192, 16384}) {
+          c.target_wgs = wgs;
+          cands.push_back(c);
+        }
       }
     }
     int rc = RPB_OK;

@@ -30,18 +30,25 @@ def _batch(sizes=SIZES, seed=0):
     return pos, offs, rng
 
 
+@pytest.mark.parametrize("sym,btpt", [(1, 1), (1, 2), (0, 1), (0, 2)])
+@pytest.mark.parametrize("torque", [False, True])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
-def test_batched_product_matches_oracle_per_system(ctx, precision, tol):
+def test_batched_product_matches_oracle_per_system(ctx, precision, tol, torque, sym, btpt):
+    # symmetric (system, tile pair) items and ordered (system, target tile, source chunk) items
+    from paper_1612_00474_amd import Context
+    c = Context(0)
+    c.set_tuning(precision, batch_symmetric=sym, batch_tpt=btpt, batch_chunk=256, batch_wgs=64)
     pos, offs, rng = _batch()
     F = rng.standard_normal(pos.shape)
-    T = rng.standard_normal(pos.shape)
-    u = host(ctx.matvec_batched(dev(pos), offs, dev(F), dev(T), precision))
+    T = rng.standard_normal(pos.shape) if torque else None
+    u = host(c.matvec_batched(dev(pos), offs, dev(F), dev(T) if torque else None, precision))
     for s in range(len(SIZES)):
         a, b = offs[s], offs[s + 1]
         if a == b:
             continue
-        ref = mobility.dense_matvec(pos[a:b], F[a:b], T[a:b])
+        ref = mobility.dense_matvec(pos[a:b], F[a:b], None if T is None else T[a:b])
         assert rel2(u[a:b], ref) <= tol, (s, precision)
+    c.close()
 
 
 def test_batched_equals_single_calls(ctx):
