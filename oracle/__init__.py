@@ -25,6 +25,8 @@ microrollers", J. Chem. Phys. 146, 134104 (2017), arXiv:1612.00474):
                   divergence of M it estimates.
 * ``forces``      Soft steric potential (Sec. III, eq. soft_potential) plus gravity.
 * ``integrator``  Euler-Maruyama (eq. EM) and stochastic Adams-Bashforth (eq. AB) steps.
+* ``equilibrium`` The Gibbs-Boltzmann density of a lone sphere's height (App. B check) and
+                  the density a drift-free scheme would leave invariant instead.
 * ``philox``      Philox4x64-10 counter-based generator (Salmon et al., SC'11) and the
                   Box-Muller transform, for checking device-drawn noise.
 
