@@ -131,6 +131,16 @@ int rfd_drift(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
               const double *w_tilde, double delta, int rfd_precision, double *drift_out,
               rpb_stream_t stream);
 
+/* One-sided random finite difference (Sec. II.A: the paper allows a one-sided difference in
+ * place of the centred one):
+ *   drift = (kT/delta) [ M(q + delta w~) w~ - M(q) w~ ],
+ * equal in expectation to kT div_q . M up to O(delta); its truncation/round-off balance is
+ * delta/a ~ eps^{1/2} against eps^{1/3} for the centred form.  Arguments and errors as for
+ * rfd_drift. */
+int rfd_drift_one_sided(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                        const double *w_tilde, double delta, int rfd_precision,
+                        double *drift_out, rpb_stream_t stream);
+
 /* Forces --------------------------------------------------------------------------------
  *
  * Soft steric repulsion of the paper (Sec. III, eq. soft_potential) between all pairs
@@ -154,7 +164,7 @@ int rpb_normals(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id,
  *   u^n     = M^n F^n + M_C^n T                         (forces from rpb_forces, T constant)
  *   SAB (eq. AB): q^{n+1} = q^n + dt (3/2 u^n - 1/2 u^{n-1}) + sqrt(2 kT dt) g^n + dt D^n
  *   EM  (eq. EM): q^{n+1} = q^n + dt u^n + sqrt(2 kT dt) g^n + dt D^n
- * with g^n = lanczos_sqrt_apply(W^n) and D^n = rfd_drift(W~^n).  The first SAB step
+ * with g^n = lanczos_sqrt_apply(W^n) and D^n = rfd_drift(W~^n) (or rfd_drift_one_sided).  The first SAB step
  * (have_prev == 0) is an EM step.  On return state->pos holds q^{n+1}, state->u_prev
  * holds u^n, state->step is incremented and state->have_prev = 1.
  */
@@ -165,6 +175,7 @@ typedef struct {
   int lanczos_max_iter; /* 1..128 */
   int scheme;           /* 0 = stochastic Adams-Bashforth, 1 = Euler-Maruyama */
   int rfd_precision;    /* rpb_precision of the two RFD products */
+  int rfd_scheme;       /* 0 = centred RFD (rfd_drift), 1 = one-sided (rfd_drift_one_sided) */
   double f_grav_z;      /* gravity force on each sphere along z */
   double torque[3];     /* constant torque on every sphere */
   double steric_u0;     /* U0 of eq. soft_potential */

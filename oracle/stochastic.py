@@ -21,7 +21,8 @@ divergence is z-hat times d/dz of the perpendicular self-mobility
 (1/(6 pi eta a^2))(9/(8h^2) - 3/(2h^4) + 5/(8h^6)), h = z/a, and for 0 < z < a it
 is z-hat (2z/a^2)(1/4)/(6 pi eta a); the deterministic central difference
 summed over all 3N unit directions matches ``divergence`` to O(delta^2); the
-sample mean of the RFD over many W~ matches it within its standard error.
+sample mean of the RFD (centred and one-sided) over many W~ matches it within its standard
+error.
 """
 from __future__ import annotations
 
@@ -41,6 +42,18 @@ def rfd(pos, w_tilde, delta, a=1.0, eta=1.0, kT=1.0, rows=None, workers=1):
     up = mobility.matvec(qp, wt, None, a, eta, rows=rows, workers=workers)
     um = mobility.matvec(qm, wt, None, a, eta, rows=rows, workers=workers)
     return (kT / delta) * (up - um)
+
+
+def rfd_one_sided(pos, w_tilde, delta, a=1.0, eta=1.0, kT=1.0, rows=None, workers=1):
+    """One-sided random finite difference (kT/delta)[M(q + delta W~)W~ - M(q)W~], shape (n, 3).
+
+    Sec. II.A allows a one-sided difference in place of the centred one; it equals
+    kT (div . M) in expectation up to O(delta)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    wt = np.asarray(w_tilde, dtype=np.float64).reshape(pos.shape)
+    up = mobility.matvec(pos + delta * wt, wt, None, a, eta, rows=rows, workers=workers)
+    u0 = mobility.matvec(pos, wt, None, a, eta, rows=rows, workers=workers)
+    return (kT / delta) * (up - u0)
 
 
 def divergence(pos, a=1.0, eta=1.0):

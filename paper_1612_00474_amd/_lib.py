@@ -24,6 +24,7 @@ PRECISIONS = {"fp64": RPB_FP64, "mixed": RPB_MIXED}
 EXPORTS = (
     "rpb_create", "rpb_destroy", "rpb_last_error", "rpb_version",
     "rpb_mobility_matvec", "rpb_mobility_matvec_rows", "lanczos_sqrt_apply", "rfd_drift",
+    "rfd_drift_one_sided",
     "rpb_forces", "rpb_normals", "sab_step", "rpb_timing_enable", "rpb_timing_read",
     "rpb_mobility_matvec_batched", "lanczos_sqrt_apply_batched", "sab_step_batched",
     "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
@@ -38,7 +39,7 @@ class RpbParams(C.Structure):
 class RpbSabConfig(C.Structure):
     _fields_ = [("dt", C.c_double), ("delta", C.c_double), ("lanczos_tol", C.c_double),
                 ("lanczos_max_iter", C.c_int), ("scheme", C.c_int), ("rfd_precision", C.c_int),
-                ("f_grav_z", C.c_double), ("torque", C.c_double * 3), ("steric_u0", C.c_double),
+                ("rfd_scheme", C.c_int), ("f_grav_z", C.c_double), ("torque", C.c_double * 3), ("steric_u0", C.c_double),
                 ("steric_b", C.c_double), ("seed", C.c_uint64)]
 
 
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
         "lanczos_sqrt_apply": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, C.POINTER(C.c_int),
                                          C.POINTER(D), P]),
         "rfd_drift": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, P]),
+        "rfd_drift_one_sided": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, P]),
         "rpb_forces": (C.c_int, [P, pp, I64, P, D, D, D, P, P]),
         "rpb_normals": (C.c_int, [P, I64, C.c_uint64, C.c_uint64, C.c_uint64, P, P]),
         "sab_step": (C.c_int, [P, pp, C.POINTER(RpbSabConfig), C.POINTER(RpbSabState), P, P,
@@ -157,11 +159,16 @@ def _np_ptr(a):
     return C.c_void_p(a.ctypes.data)
 
 
+RFD_SCHEMES = {"centred": 0, "one_sided": 1}
+
+
 def _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision, f_grav_z,
-                torque, steric_u0, steric_b, seed):
+                torque, steric_u0, steric_b, seed, rfd_scheme="centred"):
+    if scheme not in ("sab", "em"):
+        raise ValueError(f"scheme must be 'sab' or 'em', not {scheme!r}")
     return RpbSabConfig(dt, delta, lanczos_tol, lanczos_max_iter, 0 if scheme == "sab" else 1,
-                        PRECISIONS[rfd_precision], f_grav_z, (C.c_double * 3)(*torque),
-                        steric_u0, steric_b, seed)
+                        PRECISIONS[rfd_precision], RFD_SCHEMES[rfd_scheme], f_grav_z,
+                        (C.c_double * 3)(*torque), steric_u0, steric_b, seed)
 
 
 def _stream():
@@ -252,7 +259,8 @@ class Context:
         self._check(st, (RPB_OK, RPB_ENOCONV) if allow_noconv else (RPB_OK,))
         return out, it.value, eps.value, st
 
-    def rfd(self, pos, w_tilde, delta, precision="fp64", rfd_precision="fp64", out=None):
+    def rfd(self, pos, w_tilde, delta, precision="fp64", rfd_precision="fp64", out=None,
+            rfd_scheme="centred"):
         import torch
         pos = _vec3(pos, "pos")
         n = pos.shape[0]
@@ -260,8 +268,9 @@ class Context:
         if out is None:
             out = torch.empty_like(pos)
         p = self.params(precision)
-        st = self.lib.rfd_drift(self.h, C.byref(p), n, _ptr(pos), _ptr(w_tilde), float(delta),
-                                PRECISIONS[rfd_precision], _ptr(out), _stream())
+        fn = {"centred": self.lib.rfd_drift, "one_sided": self.lib.rfd_drift_one_sided}[rfd_scheme]
+        st = fn(self.h, C.byref(p), n, _ptr(pos), _ptr(w_tilde), float(delta),
+                PRECISIONS[rfd_precision], _ptr(out), _stream())
         self._check(st)
         return out
 
@@ -328,7 +337,7 @@ class Context:
     def sab_step_batched(self, pos, u_prev, offs, step, have_prev, *, dt, delta, lanczos_tol,
                          lanczos_max_iter=64, scheme="sab", rfd_precision="fp64", f_grav_z=-1.0,
                          torque=(0.0, 1.0, 0.0), steric_u0=1.0, steric_b=0.1, seed=0,
-                         precision="fp64", w=None, w_tilde=None):
+                         precision="fp64", w=None, w_tilde=None, rfd_scheme="centred"):
         """One step of every system; updates pos and u_prev in place.
         Returns (iterations per system, eps per system, status)."""
         import numpy as np
@@ -338,7 +347,7 @@ class Context:
         o = _offsets(offs, n)
         nsys = o.size - 1
         cfg = _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision,
-                          f_grav_z, torque, steric_u0, steric_b, seed)
+                          f_grav_z, torque, steric_u0, steric_b, seed, rfd_scheme)
         it = np.zeros(nsys, dtype=np.int32)
         eps = np.zeros(nsys, dtype=np.float64)
         p = self.params(precision)
@@ -352,21 +361,22 @@ class Context:
     def step_graph(self, pos, u_prev, offs, step=0, have_prev=False, *, dt, delta, lanczos_tol,
                    lanczos_max_iter=16, scheme="sab", rfd_precision="fp64", f_grav_z=-1.0,
                    torque=(0.0, 1.0, 0.0), steric_u0=1.0, steric_b=0.1, seed=0,
-                   precision="fp64"):
+                   precision="fp64", rfd_scheme="centred"):
         """A hipGraph of one batched step bound to pos / u_prev (see StepGraph)."""
         return StepGraph(self, pos, u_prev, offs, step, have_prev,
                          _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme,
-                                     rfd_precision, f_grav_z, torque, steric_u0, steric_b, seed),
+                                     rfd_precision, f_grav_z, torque, steric_u0, steric_b, seed,
+                                     rfd_scheme),
                          precision)
 
     # -- time step -----------------------------------------------------------------------
     def sab_step(self, state, *, dt, delta, lanczos_tol, lanczos_max_iter=64, scheme="sab",
                  rfd_precision="fp64", f_grav_z=-1.0, torque=(0.0, 1.0, 0.0), steric_u0=1.0,
-                 steric_b=0.1, seed=0, precision="fp64", w=None, w_tilde=None):
+                 steric_b=0.1, seed=0, precision="fp64", w=None, w_tilde=None,
+                 rfd_scheme="centred"):
         """Advance ``state`` (a StepState) by one step; returns (iterations, eps, status)."""
-        cfg = RpbSabConfig(dt, delta, lanczos_tol, lanczos_max_iter,
-                           0 if scheme == "sab" else 1, PRECISIONS[rfd_precision], f_grav_z,
-                           (C.c_double * 3)(*torque), steric_u0, steric_b, seed)
+        cfg = _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision,
+                          f_grav_z, torque, steric_u0, steric_b, seed, rfd_scheme)
         n = state.pos.shape[0]
         if w is not None:
             _vec3(w, "w", n)

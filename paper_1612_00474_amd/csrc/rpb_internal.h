@@ -211,7 +211,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
 
 // ---- RFD / RNG / forces / step ----------------------------------------------------------
 int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, const double *wt,
-            double delta, int rfd_precision, double *drift, hipStream_t stream);
+            double delta, int rfd_precision, bool one_sided, double *drift, hipStream_t stream);
 int normals_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id, uint64_t step,
                 double *out, hipStream_t stream);
 int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, double f_grav_z,
@@ -224,8 +224,8 @@ int normals_devstep_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t str
                         const int64_t *step_dev, double *out, hipStream_t stream);
 // RFD over a batch of systems.
 int rfd_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const double *pos,
-                    const double *wt, double delta, int rfd_precision, double *drift,
-                    hipStream_t stream);
+                    const double *wt, double delta, int rfd_precision, bool one_sided,
+                    double *drift, hipStream_t stream);
 
 // ---- time step (step.hip) ---------------------------------------------------------------
 // Device record of a time-stepped batch: read by the noise and update kernels, advanced by

@@ -106,7 +106,8 @@ int step_batched_enqueue(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config
   RPB_TRY(matvec_batched(ctx, p, bt, geo, F, T, nullptr, u, stream));
   RPB_TRY(lanczos_batched_run(ctx, p, bt, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter, g,
                               sync_lanczos, status_host, stream));
-  RPB_TRY(rfd_batched_run(ctx, p, bt, pos, Wt, cfg->delta, cfg->rfd_precision, drift, stream));
+  RPB_TRY(rfd_batched_run(ctx, p, bt, pos, Wt, cfg->delta, cfg->rfd_precision,
+                          cfg->rfd_scheme == 1, drift, stream));
   combine_kernel_dev<<<nblk(m3), 256, 0, stream>>>(m3, pos, u_prev, u, g, drift, cfg->dt,
                                                    cfg->scheme, rec, std::sqrt(2.0 * p->kT * cfg->dt));
   RPB_LAUNCHED(ctx);
@@ -131,6 +132,8 @@ int check_step_config(rpb_ctx *ctx, const rpb_sab_config *cfg) {
   if (cfg->scheme != 0 && cfg->scheme != 1) return fail(ctx, RPB_EINVAL, "unknown scheme");
   if (cfg->rfd_precision != RPB_FP64 && cfg->rfd_precision != RPB_MIXED)
     return fail(ctx, RPB_EINVAL, "unknown rfd_precision");
+  if (cfg->rfd_scheme != 0 && cfg->rfd_scheme != 1)
+    return fail(ctx, RPB_EINVAL, "unknown rfd_scheme");
   if (!(cfg->steric_u0 >= 0.0) || !(cfg->steric_b > 0.0))
     return fail(ctx, RPB_EINVAL, "need steric_u0 >= 0 and steric_b > 0");
   return RPB_OK;
@@ -145,15 +148,7 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
                         int *iters_out, double *eps_out, rpb_stream_t stream_) {
   RPB_TRY(check_params(ctx, p));
   if (!cfg || !state) return fail(ctx, RPB_EINVAL, "cfg and state must not be NULL");
-  if (!(cfg->dt > 0.0) || !(cfg->delta > 0.0) || !(cfg->lanczos_tol > 0.0))
-    return fail(ctx, RPB_EINVAL, "dt, delta and lanczos_tol must be > 0");
-  if (cfg->lanczos_max_iter < 1 || cfg->lanczos_max_iter > 64)
-    return fail(ctx, RPB_EINVAL, "lanczos_max_iter must be in [1, 64]");
-  if (cfg->scheme != 0 && cfg->scheme != 1) return fail(ctx, RPB_EINVAL, "unknown scheme");
-  if (cfg->rfd_precision != RPB_FP64 && cfg->rfd_precision != RPB_MIXED)
-    return fail(ctx, RPB_EINVAL, "unknown rfd_precision");
-  if (!(cfg->steric_u0 >= 0.0) || !(cfg->steric_b > 0.0))
-    return fail(ctx, RPB_EINVAL, "need steric_u0 >= 0 and steric_b > 0");
+  RPB_TRY(check_step_config(ctx, cfg));
   const int64_t n = state->n;
   if (iters_out) *iters_out = 0;
   if (eps_out) *eps_out = 0.0;
@@ -216,7 +211,8 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   if (lz != RPB_OK && lz != RPB_ENOCONV) return lz;
 
   // stochastic drift
-  RPB_TRY(rfd_run(ctx, p, n, state->pos, Wt, cfg->delta, cfg->rfd_precision, drift, stream));
+  RPB_TRY(rfd_run(ctx, p, n, state->pos, Wt, cfg->delta, cfg->rfd_precision,
+                  cfg->rfd_scheme == 1, drift, stream));
 
   const bool ab = cfg->scheme == 0 && state->have_prev;
   combine_kernel<<<nblk(m3), 256, 0, stream>>>(m3, state->pos, state->u_prev, u, g, drift,

@@ -80,12 +80,15 @@ __global__ void normals_kernel_devstep(int64_t count, uint64_t seed, uint64_t st
     if (4 * b + q < count) out[4 * b + q] = v[q];
 }
 
+// q+ = q + sp w, q- = q - sm w: (delta/2, delta/2) for the centred difference, (delta, 0) for
+// the one-sided one (q- = q exactly).
 __global__ void shifted_pair(int64_t m, const double *__restrict__ q, const double *__restrict__ w,
-                             double half_delta, double *__restrict__ qp, double *__restrict__ qm) {
+                             double sp, double sm, double *__restrict__ qp,
+                             double *__restrict__ qm) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  qp[i] = q[i] + half_delta * w[i];
-  qm[i] = q[i] - half_delta * w[i];
+  qp[i] = q[i] + sp * w[i];
+  qm[i] = q[i] - sm * w[i];
 }
 
 __global__ void scaled_difference(int64_t m, const double *__restrict__ a,
@@ -109,7 +112,7 @@ int normals_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id, 
 }
 
 int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, const double *wt,
-            double delta, int rfd_precision, double *drift, hipStream_t stream) {
+            double delta, int rfd_precision, bool one_sided, double *drift, hipStream_t stream) {
   const int64_t m = 3 * n;
   const size_t vb = size_t(m) * sizeof(double);
   int st;
@@ -121,7 +124,8 @@ int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, con
   if (!up) return st;
   double *um = static_cast<double *>(workspace(ctx, WS_VEC_E, vb, &st));
   if (!um) return st;
-  shifted_pair<<<nblk(m), 256, 0, stream>>>(m, pos, wt, 0.5 * delta, qp, qm);
+  shifted_pair<<<nblk(m), 256, 0, stream>>>(m, pos, wt, one_sided ? delta : 0.5 * delta,
+                                             one_sided ? 0.0 : 0.5 * delta, qp, qm);
   RPB_LAUNCHED(ctx);
   rpb_params q = *p;
   q.precision = rfd_precision;
@@ -145,8 +149,8 @@ int normals_devstep_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t str
 }
 
 int rfd_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const double *pos,
-                    const double *wt, double delta, int rfd_precision, double *drift,
-                    hipStream_t stream) {
+                    const double *wt, double delta, int rfd_precision, bool one_sided,
+                    double *drift, hipStream_t stream) {
   const int64_t n = bt.n;
   const int64_t m = 3 * n;
   const size_t vb = size_t(m) * sizeof(double);
@@ -159,7 +163,8 @@ int rfd_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const do
   if (!up) return st;
   double *um = static_cast<double *>(workspace(ctx, WS_VEC_E, vb, &st));
   if (!um) return st;
-  shifted_pair<<<nblk(m), 256, 0, stream>>>(m, pos, wt, 0.5 * delta, qp, qm);
+  shifted_pair<<<nblk(m), 256, 0, stream>>>(m, pos, wt, one_sided ? delta : 0.5 * delta,
+                                             one_sided ? 0.0 : 0.5 * delta, qp, qm);
   RPB_LAUNCHED(ctx);
   rpb_params q = *p;
   q.precision = rfd_precision;
@@ -177,11 +182,11 @@ int rfd_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const do
 
 using namespace rpb;
 
-extern "C" {
+namespace {
 
-int rfd_drift(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
-              const double *w_tilde, double delta, int rfd_precision, double *drift_out,
-              rpb_stream_t stream_) {
+int rfd_entry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+              const double *w_tilde, double delta, int rfd_precision, bool one_sided,
+              double *drift_out, rpb_stream_t stream_) {
   RPB_TRY(check_params(ctx, p));
   if (n < 0) return fail(ctx, RPB_EINVAL, "n must be >= 0");
   if (!(delta > 0.0)) return fail(ctx, RPB_EINVAL, "delta must be > 0");
@@ -196,7 +201,23 @@ int rfd_drift(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   RPB_HIP(ctx, hipSetDevice(ctx->device));
   RPB_TRY(check_finite(ctx, pos, n, stream));
-  return rfd_run(ctx, p, n, pos, w_tilde, delta, rfd_precision, drift_out, stream);
+  return rfd_run(ctx, p, n, pos, w_tilde, delta, rfd_precision, one_sided, drift_out, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rfd_drift(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+              const double *w_tilde, double delta, int rfd_precision, double *drift_out,
+              rpb_stream_t stream) {
+  return rfd_entry(ctx, p, n, pos, w_tilde, delta, rfd_precision, false, drift_out, stream);
+}
+
+int rfd_drift_one_sided(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                        const double *w_tilde, double delta, int rfd_precision,
+                        double *drift_out, rpb_stream_t stream) {
+  return rfd_entry(ctx, p, n, pos, w_tilde, delta, rfd_precision, true, drift_out, stream);
 }
 
 int rpb_normals(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id, uint64_t step,

@@ -19,8 +19,9 @@ BURN, STEPS, EVERY = 5000, 8000, 20
 KS_TOL = 0.01                       # measured 0.0013-0.0014; a missing drift: 0.09
 
 
-@pytest.mark.parametrize("scheme", ["sab", "em"])
-def test_single_sphere_heights_follow_boltzmann(scheme):
+@pytest.mark.parametrize("scheme,rfd", [("sab", "centred"), ("em", "centred"),
+                                        ("sab", "one_sided")])
+def test_single_sphere_heights_follow_boltzmann(scheme, rfd):
     require_gpu()
     import torch
     from paper_1612_00474_amd import Context
@@ -33,7 +34,7 @@ def test_single_sphere_heights_follow_boltzmann(scheme):
     graph = ctx.step_graph(P, U, offs, 0, False, dt=DT, delta=1e-4, lanczos_tol=1e-8,
                            lanczos_max_iter=4, scheme=scheme, f_grav_z=FG,
                            torque=(0.0, 0.0, 0.0), steric_u0=U0, steric_b=B, seed=5,
-                           precision="fp64")
+                           precision="fp64", rfd_scheme=rfd)
     for _ in range(BURN):
         graph.launch()
     samples = []
@@ -51,7 +52,7 @@ def test_single_sphere_heights_follow_boltzmann(scheme):
     p = eq.boltzmann_density(h, A, U0, B, FG, KT)
     ks = eq.ks_distance(heights, h, eq.cdf(h, p))
     mean_ref = float(np.trapezoid(h * p, h))
-    print(f"{scheme}: KS distance {ks:.4f}, mean height {heights.mean():.4f} "
+    print(f"{scheme}/{rfd}: KS distance {ks:.4f}, mean height {heights.mean():.4f} "
           f"(Boltzmann {mean_ref:.4f}), Lanczos iterations {sorted(set(iters.tolist()))}")
     assert ks < KS_TOL
     assert abs(heights.mean() - mean_ref) < 0.01

@@ -26,13 +26,15 @@ def _setup(n=200, seed=0):
     return wl.make_inputs(w, seed)
 
 
-def _oracle_step(pos, u_prev, W, Wt, scheme):
+def _oracle_step(pos, u_prev, W, Wt, scheme, rfd="centred"):
     return integrator.step(pos, u_prev, W, Wt, dt=0.01, delta=1e-4, lanczos_tol=1e-300,
-                           lanczos_max_iter=M_FIXED, scheme=scheme, u0=1.0, b=0.1, **PHYS)
+                           lanczos_max_iter=M_FIXED, scheme=scheme, u0=1.0, b=0.1, rfd=rfd,
+                           **PHYS)
 
 
-@pytest.mark.parametrize("scheme", ["sab", "em"])
-def test_two_steps_match_oracle(ctx, scheme):
+@pytest.mark.parametrize("scheme,rfd", [("sab", "centred"), ("em", "centred"),
+                                        ("sab", "one_sided"), ("em", "one_sided")])
+def test_two_steps_match_oracle(ctx, scheme, rfd):
     from paper_1612_00474_amd import StepState
     inp = _setup()
     rng = np.random.default_rng(3)
@@ -43,11 +45,11 @@ def test_two_steps_match_oracle(ctx, scheme):
         W, Wt = rng.standard_normal(pos.shape), rng.standard_normal(pos.shape)
         it, eps, st = ctx.sab_step(state, dt=0.01, delta=1e-4, lanczos_tol=1e-300,
                                    lanczos_max_iter=M_FIXED, scheme=scheme, w=dev(W), w_tilde=dev(Wt),
-                                   steric_u0=1.0, steric_b=0.1, **PHYS)
-        new, u, mref, _, _ = _oracle_step(pos, u_prev, W, Wt, scheme)
+                                   steric_u0=1.0, steric_b=0.1, rfd_scheme=rfd, **PHYS)
+        new, u, mref, _, _ = _oracle_step(pos, u_prev, W, Wt, scheme, rfd)
         got = host(state.pos)
         err = rel2(got - pos, new - pos)
-        print(f"{scheme} step {k}: displacement rel2 = {err:.3e}")
+        print(f"{scheme}/{rfd} step {k}: displacement rel2 = {err:.3e}")
         assert it == mref == M_FIXED
         assert err <= 1e-10
         assert rel2(host(state.u_prev), u) <= 1e-12

@@ -33,6 +33,15 @@ def test_rfd_fp64(ctx, c1):
     assert err <= 1e-10
 
 
+def test_rfd_one_sided_fp64(ctx, c1):
+    # (kT/delta)[M(q + delta w~) w~ - M(q) w~]: same rounding amplification as the centred form
+    for pos in (c1["pos"], awkward_config()):
+        wt = np.random.default_rng(5).standard_normal(pos.shape)
+        ref = stochastic.rfd_one_sided(pos, wt, 1e-4)
+        d = host(ctx.rfd(dev(pos), dev(wt), 1e-4, rfd_scheme="one_sided"))
+        assert rel2(d, ref) <= 1e-10
+
+
 def test_rfd_awkward_config(ctx):
     pos = awkward_config()
     wt = np.random.default_rng(4).standard_normal(pos.shape)

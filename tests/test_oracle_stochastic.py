@@ -59,6 +59,29 @@ def test_rfd_mean_matches_divergence():
     assert np.all(np.abs(mean - d) <= 4.5 * se + 1e-12)
 
 
+def test_one_sided_rfd_mean_matches_divergence():
+    # one-sided difference: unbiased up to O(delta) (Sec. II.A)
+    pos = _config()[:3]
+    rng = np.random.default_rng(10)
+    K = 1200
+    samples = np.array([stochastic.rfd_one_sided(pos, rng.standard_normal(pos.shape), 1e-4,
+                                                 A).ravel() for _ in range(K)])
+    mean = samples.mean(0)
+    se = samples.std(0) / math.sqrt(K)
+    d = stochastic.divergence(pos, A, 1.0).ravel()
+    assert np.all(np.abs(mean - d) <= 4.5 * se + 1e-3 * np.abs(d).max())
+
+
+def test_one_sided_and_centred_rfd_agree_to_first_order_in_delta():
+    # (kT/delta)[M(q+delta w)w - M(q)w] - centred = (delta/2) w.grad(M w) + O(delta^2): halving
+    # delta halves the gap
+    pos = _config()[:5]
+    wt = np.random.default_rng(4).standard_normal(pos.shape)
+    gap = [np.linalg.norm(stochastic.rfd_one_sided(pos, wt, d, A) - stochastic.rfd(pos, wt, d, A))
+           for d in (2e-3, 1e-3)]
+    assert gap[1] == pytest.approx(gap[0] / 2, rel=0.02)
+
+
 def test_rfd_scales_with_kT():
     pos = _config()
     wt = np.random.default_rng(1).standard_normal(pos.shape)
