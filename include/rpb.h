@@ -62,6 +62,10 @@ typedef struct {
   double eta;           /* fluid viscosity (> 0) */
   double kT;            /* thermal energy k_B T (> 0) */
   int precision;        /* rpb_precision */
+  int wall;             /* 1: no-slip wall at z = 0 (Rotne-Prager-Blake tensors, heights clamped
+                           and weighted as in App. A, soft wall repulsion in rpb_forces);
+                           0: free space (unbounded RPY tensors of Sec. II.B alone, no
+                           clamping, no wall force), the contrast of Sec. II.C / Fig. 1 */
 } rpb_params;
 
 /* Context ---------------------------------------------------------------------------- */

@@ -35,8 +35,9 @@ def force_magnitude(r, d, u0, b):
     return np.where(r < d, u0 / b, (u0 / b) * np.exp(-(r - d) / b))
 
 
-def forces(pos, a=1.0, u0=1.0, b=0.1, f_grav_z=-1.0, rows=None):
-    """Total force on each sphere (or on ``rows``), shape (n, 3) / (len(rows), 3)."""
+def forces(pos, a=1.0, u0=1.0, b=0.1, f_grav_z=-1.0, rows=None, wall=True):
+    """Total force on each sphere (or on ``rows``), shape (n, 3) / (len(rows), 3).
+    ``wall=False``: no wall repulsion (free space)."""
     pos = np.asarray(pos, dtype=np.float64)
     n = len(pos)
     rows = np.arange(n) if rows is None else np.asarray(rows)
@@ -48,5 +49,7 @@ def forces(pos, a=1.0, u0=1.0, b=0.1, f_grav_z=-1.0, rows=None):
         f = force_magnitude(rn[ok], 2.0 * a, u0, b)
         out[k] = np.sum((f / rn[ok])[:, None] * r[ok], axis=0)
     z = pos[rows, 2]
-    out[:, 2] += force_magnitude(z, a, u0, b) + f_grav_z
+    if wall:
+        out[:, 2] += force_magnitude(z, a, u0, b)
+    out[:, 2] += f_grav_z
     return out

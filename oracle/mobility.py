@@ -19,6 +19,9 @@ Definitions (paper, Sec. II.B, Sec. III and App. A):
 Velocity of the spheres: U = M F + M_C T (the deterministic drift of eq. BD with
 the active term of Sec. III).
 
+Free space (``wall=False``, the contrast drawn in Sec. II.C): the unbounded RPY
+blocks alone, unclamped heights and H = 1.
+
 Pinned by (tests/test_oracle_mobility.py): symmetry and positive definiteness of
 dense M (eigvalsh), zero rows for spheres at or below the wall, the textbook wall
 self-mobility series, the 1/r^3 decay of the screened pair interaction for
@@ -35,26 +38,34 @@ import numpy as np
 from . import faxen, rpy
 
 
-def regularize(pos, a):
-    """Clamped positions q~ = (x, y, max(z, a)) and weights H0(z/a) (App. A, eq. effMob)."""
+def regularize(pos, a, wall=True):
+    """Clamped positions q~ = (x, y, max(z, a)) and weights H0(z/a) (App. A, eq. effMob).
+
+    Free space (``wall=False``): no clamping, H = 1."""
     pos = np.asarray(pos, dtype=np.float64)
     qt = pos.copy()
+    if not wall:
+        return qt, np.ones(len(pos))
     qt[:, 2] = np.maximum(pos[:, 2], a)
     H = np.clip(pos[:, 2] / a, 0.0, 1.0)
     return qt, H
 
 
-def pair_blocks(qi, qj, a, eta):
+def pair_blocks(qi, qj, a, eta, wall=True):
     """Translation and translation-rotation blocks M~_ij, M~C_ij of clamped positions.
 
     ``qi``, ``qj``: arrays (3, n) of targets and sources (already clamped).
-    Returns (tt, tr), each (3, 3, n), in mobility units.
+    Returns (tt, tr), each (3, 3, n), in mobility units.  ``wall=False``: the unbounded
+    RPY blocks alone (free space).
     """
     qi = np.asarray(qi, dtype=np.float64)
     qj = np.asarray(qj, dtype=np.float64)
     r = qi - qj
-    tt = rpy.free_tt(r, a) + faxen.wall_tt(qi, qj, a)
-    tr = rpy.free_tr(r, a) + faxen.wall_tr(qi, qj, a)
+    tt = rpy.free_tt(r, a)
+    tr = rpy.free_tr(r, a)
+    if wall:
+        tt = tt + faxen.wall_tt(qi, qj, a)
+        tr = tr + faxen.wall_tr(qi, qj, a)
     s = 1.0 / (8.0 * math.pi * eta)
     return tt * s, tr * s
 
@@ -62,9 +73,9 @@ def pair_blocks(qi, qj, a, eta):
 _PAIR_CHUNK = 1 << 17
 
 
-def dense(pos, a=1.0, eta=1.0):
+def dense(pos, a=1.0, eta=1.0, wall=True):
     """Dense (3N, 3N) matrices M and M_C (FP64).  Practical for N up to ~2000."""
-    qt, H = regularize(pos, a)
+    qt, H = regularize(pos, a, wall)
     n = len(qt)
     M = np.zeros((n, 3, n, 3))
     MC = np.zeros((n, 3, n, 3))
@@ -74,7 +85,7 @@ def dense(pos, a=1.0, eta=1.0):
     for s in range(0, I.size, _PAIR_CHUNK):
         ii = I[s:s + _PAIR_CHUNK]
         jj = J[s:s + _PAIR_CHUNK]
-        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta)
+        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta, wall)
         w = H[ii] * H[jj]
         M[ii, :, jj, :] = (tt * w).transpose(2, 0, 1)
         MC[ii, :, jj, :] = (tr * w).transpose(2, 0, 1)
@@ -82,7 +93,7 @@ def dense(pos, a=1.0, eta=1.0):
 
 
 def _rows_product(args):
-    rows, qt, H, force, torque, a, eta = args
+    rows, qt, H, force, torque, a, eta, wall = args
     n = len(qt)
     out = np.zeros((len(rows), 3))
     step = max(1, _PAIR_CHUNK // n)
@@ -90,7 +101,7 @@ def _rows_product(args):
         blk = rows[s:s + step]
         ii = np.repeat(blk, n)
         jj = np.tile(np.arange(n), len(blk))
-        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta)
+        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta, wall)
         acc = np.zeros((3, len(ii)))
         if force is not None:
             acc += np.einsum("abk,kb->ak", tt, force[jj])
@@ -101,14 +112,14 @@ def _rows_product(args):
     return out
 
 
-def matvec(pos, force=None, torque=None, a=1.0, eta=1.0, rows=None, workers=1):
+def matvec(pos, force=None, torque=None, a=1.0, eta=1.0, rows=None, workers=1, wall=True):
     """U = M F + M_C T by direct summation over all sources (matrix-free).
 
     ``rows``: optional indices of the target spheres to evaluate (row sampling);
     the result then has shape (len(rows), 3).  ``workers`` > 1 splits the targets
     over a pool of forked processes.
     """
-    qt, H = regularize(pos, a)
+    qt, H = regularize(pos, a, wall)
     n = len(qt)
     force = None if force is None else np.asarray(force, dtype=np.float64)
     torque = None if torque is None else np.asarray(torque, dtype=np.float64)
@@ -116,18 +127,19 @@ def matvec(pos, force=None, torque=None, a=1.0, eta=1.0, rows=None, workers=1):
     if rows.size == 0:
         return np.zeros((0, 3))
     if workers <= 1:
-        return _rows_product((rows, qt, H, force, torque, a, eta))
+        return _rows_product((rows, qt, H, force, torque, a, eta, wall))
     # compile the lambdified tensors before forking so the children inherit them
-    pair_blocks(qt[:1].T, qt[:1].T, a, eta)
+    pair_blocks(qt[:1].T, qt[:1].T, a, eta, wall)
     parts = np.array_split(rows, min(workers * 4, rows.size))
     with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
-        res = list(ex.map(_rows_product, [(p, qt, H, force, torque, a, eta) for p in parts]))
+        res = list(ex.map(_rows_product, [(p, qt, H, force, torque, a, eta, wall)
+                                          for p in parts]))
     return np.vstack(res)
 
 
-def dense_matvec(pos, force=None, torque=None, a=1.0, eta=1.0):
+def dense_matvec(pos, force=None, torque=None, a=1.0, eta=1.0, wall=True):
     """U = M F + M_C T through the dense matrices (small N)."""
-    M, MC = dense(pos, a, eta)
+    M, MC = dense(pos, a, eta, wall)
     n = len(pos)
     u = np.zeros(3 * n)
     if force is not None:

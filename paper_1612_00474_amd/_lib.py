@@ -33,7 +33,8 @@ EXPORTS = (
 
 
 class RpbParams(C.Structure):
-    _fields_ = [("a", C.c_double), ("eta", C.c_double), ("kT", C.c_double), ("precision", C.c_int)]
+    _fields_ = [("a", C.c_double), ("eta", C.c_double), ("kT", C.c_double), ("precision", C.c_int),
+                ("wall", C.c_int)]
 
 
 class RpbSabConfig(C.Structure):
@@ -179,7 +180,8 @@ def _stream():
 class Context:
     """One librpb context on one device (not thread-safe; one per host thread)."""
 
-    def __init__(self, device: int = 0, a: float = 1.0, eta: float = 1.0, kT: float = 1.0):
+    def __init__(self, device: int = 0, a: float = 1.0, eta: float = 1.0, kT: float = 1.0,
+                 wall: bool = True):
         import torch
         # torch owns the device memory and streams this library works on: its HIP runtime
         # must be initialised before the library's first HIP call
@@ -192,6 +194,7 @@ class Context:
         self.h = h
         self.device = device
         self.a, self.eta, self.kT = a, eta, kT
+        self.wall = wall          # False: free space (unbounded RPY, no wall force)
 
     def close(self):
         if getattr(self, "h", None):
@@ -206,7 +209,7 @@ class Context:
 
     def params(self, precision="fp64"):
         return RpbParams(self.a, self.eta, self.kT, PRECISIONS[precision] if isinstance(precision, str)
-                         else int(precision))
+                         else int(precision), int(bool(self.wall)))
 
     def _check(self, st, ok=(RPB_OK,)):
         if st not in ok:

@@ -53,6 +53,7 @@ int check_params(rpb_ctx *ctx, const rpb_params *p) {
                 p->kT);
   if (p->precision != RPB_FP64 && p->precision != RPB_MIXED)
     return fail(ctx, RPB_EINVAL, "unknown precision %d", p->precision);
+  if (p->wall != 0 && p->wall != 1) return fail(ctx, RPB_EINVAL, "wall must be 0 or 1");
   return RPB_OK;
 }
 

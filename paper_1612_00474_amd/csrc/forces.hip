@@ -1,8 +1,9 @@
 // Soft steric forces plus gravity (paper, Sec. III, eq. soft_potential).
 //
 // U(r) = U0 + U0 (d - r)/b for r < d and U0 exp(-(r - d)/b) for r >= d, with d = 2a and r
-// the centre distance for sphere pairs, d = a and r = z for the wall; the force is -grad U,
-// magnitude U0/b or (U0/b) exp(-(r - d)/b), repulsive.  Gravity adds f_g along z.  Pairs
+// the centre distance for sphere pairs, d = a and r = z for the wall (absent in free space);
+// the force is -grad U, magnitude U0/b or (U0/b) exp(-(r - d)/b), repulsive.  Gravity adds
+// f_g along z.  Pairs
 // farther than d + 40 b are skipped (their force is below 4.3e-18 U0/b).  Brute-force
 // O(N^2) distance tests over LDS tiles, float64 throughout, unclamped positions; the sources
 // are split over workgroups and the chunk sums added in a fixed order (deterministic).
@@ -77,7 +78,7 @@ __device__ __forceinline__ void steric_accumulate(const double *__restrict__ pos
 template <int KT, bool FINAL>
 __device__ __forceinline__ void steric_tile(const double *__restrict__ pos, int64_t t0, int64_t t1,
                                             int64_t s0, int64_t s1, double a, double u0, double b,
-                                            double f_grav_z, double *__restrict__ out) {
+                                            double f_grav_z, int wall, double *__restrict__ out) {
   __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
   const int tid = threadIdx.x;
   double f[KT][3], tq[KT][3];
@@ -100,7 +101,8 @@ __device__ __forceinline__ void steric_tile(const double *__restrict__ pos, int6
       if (FINAL) {
         const double zi = tq[q][2];
         const double fmax_ = u0 / b;
-        fz += (zi < a ? fmax_ : fmax_ * exp(-(zi - a) / b)) + f_grav_z;
+        if (wall) fz += zi < a ? fmax_ : fmax_ * exp(-(zi - a) / b);
+        fz += f_grav_z;
       }
       out[3 * i] = f[q][0];
       out[3 * i + 1] = f[q][1];
@@ -115,11 +117,12 @@ template <int KT, bool FINAL>
 __global__ __launch_bounds__(kBlock) void steric_kernel(int64_t n, int64_t chunk,
                                                         const double *__restrict__ pos, double a,
                                                         double u0, double b, double f_grav_z,
-                                                        double *__restrict__ out) {
+                                                        int wall, double *__restrict__ out) {
   const int64_t t0 = int64_t(blockIdx.x) * kBlock * KT;
   const int64_t s0 = int64_t(blockIdx.y) * chunk;
   const int64_t s1 = min(n, s0 + chunk);
-  steric_tile<KT, FINAL>(pos, t0, n, s0, s1, a, u0, b, f_grav_z, out + 3 * n * blockIdx.y);
+  steric_tile<KT, FINAL>(pos, t0, n, s0, s1, a, u0, b, f_grav_z, wall,
+                         out + 3 * n * blockIdx.y);
 }
 
 // Sums the chunk partials in chunk order, then adds the wall force and gravity.
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void steric_finish(int64_t n, int nchunks,
                                                         const double *__restrict__ pos,
                                                         const double *__restrict__ part, double a,
                                                         double u0, double b, double f_grav_z,
-                                                        double *__restrict__ force) {
+                                                        int wall, double *__restrict__ force) {
   const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;   // element of the (n, 3) array
   if (e >= 3 * n) return;
   double acc = 0.0;
@@ -135,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void steric_finish(int64_t n, int nchunks,
   if (e % 3 == 2) {
     const double z = pos[e];
     const double fmax_ = u0 / b;
-    acc += (z < a ? fmax_ : fmax_ * exp(-(z - a) / b)) + f_grav_z;
+    if (wall) acc += z < a ? fmax_ : fmax_ * exp(-(z - a) / b);
+    acc += f_grav_z;
   }
   force[e] = acc;
 }
@@ -145,11 +149,12 @@ __global__ __launch_bounds__(kBlock) void steric_kernel_batched(const int64_t *_
                                                                 const int2 *__restrict__ tiles,
                                                                 const double *__restrict__ pos,
                                                                 double a, double u0, double b,
-                                                                double f_grav_z,
+                                                                double f_grav_z, int wall,
                                                                 double *__restrict__ force) {
   const int2 tl = tiles[blockIdx.x];
   const int64_t s0 = offs[tl.x], s1 = offs[tl.x + 1];
-  steric_tile<1, true>(pos, s0 + int64_t(tl.y) * kBlock, s1, s0, s1, a, u0, b, f_grav_z, force);
+  steric_tile<1, true>(pos, s0 + int64_t(tl.y) * kBlock, s1, s0, s1, a, u0, b, f_grav_z, wall,
+                       force);
 }
 
 }  // namespace
@@ -157,8 +162,8 @@ __global__ __launch_bounds__(kBlock) void steric_kernel_batched(const int64_t *_
 int forces_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const double *pos,
                        double f_grav_z, double u0, double b, double *force, hipStream_t stream) {
   if (bt.ntiles <= 0) return RPB_OK;
-  steric_kernel_batched<<<unsigned(bt.ntiles), kBlock, 0, stream>>>(bt.offs, bt.tiles, pos, p->a,
-                                                                    u0, b, f_grav_z, force);
+  steric_kernel_batched<<<unsigned(bt.ntiles), kBlock, 0, stream>>>(
+      bt.offs, bt.tiles, pos, p->a, u0, b, f_grav_z, p->wall, force);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
@@ -177,7 +182,7 @@ int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, 
   if (tiles > 0x7fffffff) return fail(ctx, RPB_EINVAL, "too many spheres");
   if (nchunks == 1) {
     steric_kernel<kTargets, true><<<dim3{unsigned(tiles), 1u, 1u}, kBlock, 0, stream>>>(
-        n, chunk, pos, p->a, u0, b, f_grav_z, force);
+        n, chunk, pos, p->a, u0, b, f_grav_z, p->wall, force);
     RPB_LAUNCHED(ctx);
     return RPB_OK;
   }
@@ -186,11 +191,11 @@ int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, 
       workspace(ctx, WS_PART, size_t(nchunks) * 3 * size_t(n) * sizeof(double), &st));
   if (!part) return st;
   steric_kernel<kTargets, false><<<dim3{unsigned(tiles), unsigned(nchunks), 1u}, kBlock, 0,
-                                   stream>>>(n, chunk, pos, p->a, u0, b, f_grav_z, part);
+                                   stream>>>(n, chunk, pos, p->a, u0, b, f_grav_z, p->wall, part);
   RPB_LAUNCHED(ctx);
   const int64_t elems = 3 * n;
   steric_finish<<<unsigned((elems + kBlock - 1) / kBlock), kBlock, 0, stream>>>(
-      n, int(nchunks), pos, part, p->a, u0, b, f_grav_z, force);
+      n, int(nchunks), pos, part, p->a, u0, b, f_grav_z, p->wall, force);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #include "pair_tensor.h"
 #include "rpb_internal.h"
@@ -51,19 +52,20 @@ inline size_t geom_bytes(int64_t n, int precision) {
                                : size_t(n) * sizeof(double) + size_t(5 * n) * sizeof(float);
 }
 
-__global__ void pack_geometry_f64(int64_t n, const double *__restrict__ pos, double a,
+// With a wall: z~ = max(z, a) and H = clamp(z/a, 0, 1) (App. A); in free space: z~ = z, H = 1.
+__global__ void pack_geometry_f64(int64_t n, const double *__restrict__ pos, double a, int wall,
                                   double *__restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double z = pos[3 * i + 2];
   out[i] = pos[3 * i];
   out[n + i] = pos[3 * i + 1];
-  out[2 * n + i] = fmax(z, a);
-  out[3 * n + i] = fmin(fmax(z / a, 0.0), 1.0);
+  out[2 * n + i] = wall ? fmax(z, a) : z;
+  out[3 * n + i] = wall ? fmin(fmax(z / a, 0.0), 1.0) : 1.0;
 }
 
 __global__ void pack_geometry_mixed(int64_t n, const double *__restrict__ pos, double a,
-                                    double *__restrict__ hout, float *__restrict__ f) {
+                                    int wall, double *__restrict__ hout, float *__restrict__ f) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
@@ -72,8 +74,8 @@ __global__ void pack_geometry_mixed(int64_t n, const double *__restrict__ pos, d
   f[n + i] = float(x - double(xh));
   f[2 * n + i] = yh;
   f[3 * n + i] = float(y - double(yh));
-  f[4 * n + i] = float(fmax(z, a));
-  hout[i] = fmin(fmax(z / a, 0.0), 1.0);
+  f[4 * n + i] = float(wall ? fmax(z, a) : z);
+  hout[i] = wall ? fmin(fmax(z / a, 0.0), 1.0) : 1.0;
 }
 
 // Source vectors, H-weighted, structure of arrays: [fx | fy | fz | tx | ty | tz] (n each).
@@ -157,7 +159,7 @@ __device__ __forceinline__ void load_targets(const GeomF &g, int64_t first, int6
 
 // Accumulate sources [jb, je) into the lane's targets.  `n` is the stride of the source
 // arrays.  Every lane of the workgroup must call this (it synchronises).
-template <bool TORQUE, int TPT>
+template <bool TORQUE, int TPT, bool WALL>
 __device__ __forceinline__ void sources_f64(const GeomD &g, const double *__restrict__ src,
                                             int64_t n, int64_t jb, int64_t je,
                                             const PairConsts<double> &k, LdsD<TORQUE> &L,
@@ -192,17 +194,17 @@ __device__ __forceinline__ void sources_f64(const GeomD &g, const double *__rest
       for (int q = 0; q < TPT; ++q) {
         const double dx = T.x[q] - xj, dy = T.y[q] - yj, dz = T.z[q] - zj;
         if (dx * dx + dy * dy + dz * dz < k.four_a2)
-          pair_velocity<double, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, T.u[q][0],
+          pair_velocity<double, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, T.u[q][0],
                                         T.u[q][1], T.u[q][2]);
         else
-          pair_velocity<double, TORQUE, true>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
+          pair_velocity<double, TORQUE, true, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
                                               T.u[q][0], T.u[q][1], T.u[q][2]);
       }
     }
   }
 }
 
-template <bool TORQUE, int TPT>
+template <bool TORQUE, int TPT, bool WALL>
 __device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__restrict__ src,
                                               int64_t n, int64_t jb, int64_t je,
                                               const PairConsts<float> &k, LdsF<TORQUE> &L,
@@ -244,10 +246,10 @@ __device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__res
         const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
         const float dz = T.z[q] - zj;
         if (dx * dx + dy * dy + dz * dz < k.four_a2)
-          pair_velocity<float, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, a[q][0],
+          pair_velocity<float, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, a[q][0],
                                        a[q][1], a[q][2]);
         else
-          pair_velocity<float, TORQUE, true>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
+          pair_velocity<float, TORQUE, true, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
                                              a[q][0], a[q][1], a[q][2]);
       }
     }
@@ -299,7 +301,7 @@ struct PairArgs {
   int64_t chunk;    // sources per workgroup (multiple of kBlock)
 };
 
-template <bool TORQUE, int TPT>
+template <bool TORQUE, int TPT, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g,
                                                           const double *__restrict__ src,
                                                           PairConsts<double> k,
@@ -310,11 +312,11 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g
   const int64_t end = args.row0 + args.nrows;
   load_targets<TPT>(g, first, end, args.row0, T);
   const int64_t jb = int64_t(blockIdx.y) * args.chunk;
-  sources_f64<TORQUE, TPT>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
+  sources_f64<TORQUE, TPT, WALL>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
   store_partial<TPT>(T, first, end, blockIdx.y, args.nrows, args.row0, partial);
 }
 
-template <bool TORQUE, int TPT>
+template <bool TORQUE, int TPT, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF g,
                                                             const float *__restrict__ src,
                                                             PairConsts<float> k,
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
   const int64_t end = args.row0 + args.nrows;
   load_targets<TPT>(g, first, end, args.row0, T);
   const int64_t jb = int64_t(blockIdx.y) * args.chunk;
-  sources_mixed<TORQUE, TPT>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
+  sources_mixed<TORQUE, TPT, WALL>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
   store_partial<TPT>(T, first, end, blockIdx.y, args.nrows, args.row0, partial);
 }
 
@@ -400,7 +402,7 @@ __device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, in
 // its targets against source j (weighted force zero when !valid), adding M_ij F_j into acc and
 // M_ij^T F_i into cs.  Pairs at least 2a apart use the far-field form alone; closer pairs (rare
 // in a suspension) the complete form, so each pair's value depends on its own geometry only.
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __device__ __forceinline__ void sym_step(const LdsF<TORQUE> &L, int j, bool valid,
                                          const TargetsF<TPT> &T, const float (&own)[TPT][6],
                                          const PairConsts<float> &k, float (&acc)[TPT][3],
@@ -422,17 +424,17 @@ __device__ __forceinline__ void sym_step(const LdsF<TORQUE> &L, int j, bool vali
     const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
     const float dz = T.z[q] - zj;
     if (dx * dx + dy * dy + dz * dz < k.four_a2)
-      pair_velocity_sym<float, false, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+      pair_velocity_sym<float, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
                                               own[q][1], own[q][2], k, acc[q][0], acc[q][1],
                                               acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
     else
-      pair_velocity_sym<float, true, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+      pair_velocity_sym<float, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
                                              own[q][1], own[q][2], k, acc[q][0], acc[q][1],
                                              acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
   }
 }
 
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __device__ __forceinline__ void sym_step(const LdsD<TORQUE> &L, int j, bool valid,
                                          const TargetsD<TPT> &T, const double (&own)[TPT][6],
                                          const PairConsts<double> &k, double (&acc)[TPT][3],
@@ -451,11 +453,11 @@ __device__ __forceinline__ void sym_step(const LdsD<TORQUE> &L, int j, bool vali
   for (int q = 0; q < TPT; ++q) {
     const double dx = T.x[q] - xj, dy = T.y[q] - yj, dz = T.z[q] - zj;
     if (dx * dx + dy * dy + dz * dz < k.four_a2)
-      pair_velocity_sym<double, false, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+      pair_velocity_sym<double, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
                                                own[q][1], own[q][2], k, acc[q][0], acc[q][1],
                                                acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
     else
-      pair_velocity_sym<double, true, TORQUE>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+      pair_velocity_sym<double, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
                                               own[q][1], own[q][2], k, acc[q][0], acc[q][1],
                                               acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
   }
@@ -484,7 +486,7 @@ inline __device__ GeomD offset_geom(const GeomD &g, int64_t s0) {
 
 // Tile pair (I, J), I <= J, of one system: `g`, `src` and `partial` already point at the
 // system's first sphere and first partial slot.  Every lane of the workgroup must call this.
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
                                               const float *__restrict__ src,
                                               const PairConsts<float> &k,
@@ -498,7 +500,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_mixed<TORQUE, TPT>(g, src, a.stride, jb, je, k, L, T);
+    sources_mixed<TORQUE, TPT, WALL>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -537,11 +539,11 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
       if (nb == 64) {
 #pragma unroll 2
         for (int step = 0; step < 64; ++step)
-          sym_step<TPT, TORQUE>(L, blk + ((lane + step) & 63), true, T, own, k, acc, cs);
+          sym_step<TPT, TORQUE, WALL>(L, blk + ((lane + step) & 63), true, T, own, k, acc, cs);
       } else {
         for (int step = 0; step < 64; ++step) {
           const int sl = (lane + step) & 63;
-          sym_step<TPT, TORQUE>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, acc, cs);
+          sym_step<TPT, TORQUE, WALL>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, acc, cs);
         }
       }
       const int sl = (lane + 63) & 63;
@@ -577,7 +579,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
   }
 }
 
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
                                               const double *__restrict__ src,
                                               const PairConsts<double> &k,
@@ -591,7 +593,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_f64<TORQUE, TPT>(g, src, a.stride, jb, je, k, L, T);
+    sources_f64<TORQUE, TPT, WALL>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -624,11 +626,11 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
       if (nb == 64) {
 #pragma unroll 2
         for (int step = 0; step < 64; ++step)
-          sym_step<TPT, TORQUE>(L, blk + ((lane + step) & 63), true, T, own, k, T.u, cs);
+          sym_step<TPT, TORQUE, WALL>(L, blk + ((lane + step) & 63), true, T, own, k, T.u, cs);
       } else {
         for (int step = 0; step < 64; ++step) {
           const int sl = (lane + step) & 63;
-          sym_step<TPT, TORQUE>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, T.u, cs);
+          sym_step<TPT, TORQUE, WALL>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, T.u, cs);
         }
       }
       const int sl = (lane + 63) & 63;
@@ -659,7 +661,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
   }
 }
 
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
                                                                 const float *__restrict__ src,
                                                                 PairConsts<float> k,
@@ -668,10 +670,10 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
   __shared__ float col[kWaves][kBlock][3];
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE>(a, g, src, k, partial, I, J, L, col);
+  sym_tile_pair<TPT, TORQUE, WALL>(a, g, src, k, partial, I, J, L, col);
 }
 
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g,
                                                               const double *__restrict__ src,
                                                               PairConsts<double> k,
@@ -680,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
   __shared__ double col[kWaves][kBlock][3];
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE>(a, g, src, k, partial, I, J, L, col);
+  sym_tile_pair<TPT, TORQUE, WALL>(a, g, src, k, partial, I, J, L, col);
 }
 
 __global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
@@ -719,7 +721,7 @@ __device__ __forceinline__ int next_item(const BatchArgs &b, int *slot) {
   return it < b.nitems ? it : -1;
 }
 
-template <bool TORQUE, int TPT>
+template <bool TORQUE, int TPT, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_batched(BatchArgs b, GeomD g,
                                                                   const double *__restrict__ src,
                                                                   PairConsts<double> k,
@@ -734,12 +736,12 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_batched(BatchArgs b, G
     const int64_t first = s0 + int64_t(w.y) * (kBlock * TPT);
     load_targets<TPT>(g, first, s1, s0, T);
     const int64_t jb = s0 + int64_t(w.z) * b.chunk;
-    sources_f64<TORQUE, TPT>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
+    sources_f64<TORQUE, TPT, WALL>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
     store_partial<TPT>(T, first, s1, w.z, b.n, 0, partial);
   }
 }
 
-template <bool TORQUE, int TPT>
+template <bool TORQUE, int TPT, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_batched(BatchArgs b, GeomF g,
                                                                     const float *__restrict__ src,
                                                                     PairConsts<float> k,
@@ -754,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_batched(BatchArgs b,
     const int64_t first = s0 + int64_t(w.y) * (kBlock * TPT);
     load_targets<TPT>(g, first, s1, s0, T);
     const int64_t jb = s0 + int64_t(w.z) * b.chunk;
-    sources_mixed<TORQUE, TPT>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
+    sources_mixed<TORQUE, TPT, WALL>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
     store_partial<TPT>(T, first, s1, w.z, b.n, 0, partial);
   }
 }
@@ -804,7 +806,7 @@ __device__ __forceinline__ int next_sym_item(const SymBatchArgs &b, int *slot) {
   return it < b.nitems ? it : -1;
 }
 
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
     SymBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k,
     double *__restrict__ partial) {
@@ -815,12 +817,12 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
-    sym_tile_pair<TPT, TORQUE>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
+    sym_tile_pair<TPT, TORQUE, WALL>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
                                partial + b.part_base[w.x], w.y, w.z, L, col);
   }
 }
 
-template <int TPT, bool TORQUE>
+template <int TPT, bool TORQUE, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
     SymBatchArgs b, GeomD g, const double *__restrict__ src, PairConsts<double> k,
     double *__restrict__ partial) {
@@ -831,7 +833,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
-    sym_tile_pair<TPT, TORQUE>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
+    sym_tile_pair<TPT, TORQUE, WALL>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
                                partial + b.part_base[w.x], w.y, w.z, L, col);
   }
 }
@@ -874,6 +876,33 @@ __global__ void finite_flag(int64_t m, const double *__restrict__ v, int *__rest
 
 inline unsigned blocks_for(int64_t n, int threads) {
   return unsigned((n + threads - 1) / threads);
+}
+
+// Calls fn(torque, tpt, wall) with the three as std::integral_constant values, so each
+// launch site names its kernel template once.
+template <typename Fn>
+void with_variant(bool torque, int tpt, bool wall, Fn &&fn) {
+  using T1 = std::true_type;
+  using T0 = std::false_type;
+  using P2 = std::integral_constant<int, 2>;
+  using P1 = std::integral_constant<int, 1>;
+  auto by_wall = [&](auto t, auto q) {
+    if (wall)
+      fn(t, q, T1{});
+    else
+      fn(t, q, T0{});
+  };
+  if (torque) {
+    if (tpt == 2)
+      by_wall(T1{}, P2{});
+    else
+      by_wall(T1{}, P1{});
+  } else {
+    if (tpt == 2)
+      by_wall(T0{}, P2{});
+    else
+      by_wall(T0{}, P1{});
+  }
 }
 
 int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const double *torque,
@@ -924,12 +953,12 @@ int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *po
   out->precision = p->precision;
   out->geom = buf;
   if (p->precision == RPB_FP64) {
-    pack_geometry_f64<<<blocks_for(n, 256), 256, 0, stream>>>(n, pos, p->a,
+    pack_geometry_f64<<<blocks_for(n, 256), 256, 0, stream>>>(n, pos, p->a, p->wall,
                                                               static_cast<double *>(buf));
   } else {
     double *h = static_cast<double *>(buf);
     pack_geometry_mixed<<<blocks_for(n, 256), 256, 0, stream>>>(
-        n, pos, p->a, h, reinterpret_cast<float *>(h + n));
+        n, pos, p->a, p->wall, h, reinterpret_cast<float *>(h + n));
   }
   RPB_LAUNCHED(ctx);
   return RPB_OK;
@@ -951,29 +980,16 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
   const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2);
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
-  if (f64) {
-    const auto k = make_pair_consts<double>(p->a);
-    const double *sv = static_cast<const double *>(src);
-    if (torque && tpt == 2)
-      pair_kernel_f64_sym<2, true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
-    else if (torque)
-      pair_kernel_f64_sym<1, true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_f64_sym<2, false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
+  with_variant(torque, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
+    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
+    constexpr int kP = decltype(P)::value;
+    if (f64)
+      pair_kernel_f64_sym<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
+          a, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a), part);
     else
-      pair_kernel_f64_sym<1, false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), sv, k, part);
-  } else {
-    const auto k = make_pair_consts<float>(p->a);
-    const float *sv = static_cast<const float *>(src);
-    if (torque && tpt == 2)
-      pair_kernel_mixed_sym<2, true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
-    else if (torque)
-      pair_kernel_mixed_sym<1, true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_mixed_sym<2, false><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
-    else
-      pair_kernel_mixed_sym<1, false><<<grid, kBlock, 0, stream>>>(a, geom_f(g), sv, k, part);
-  }
+      pair_kernel_mixed_sym<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
+          a, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+  });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), (f64 ? 0 : 2) + (torque ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta);
@@ -1020,31 +1036,17 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   const dim3 grid{unsigned(tiles), unsigned(nchunks), 1u};
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
-  if (f64) {
-    const auto k = make_pair_consts<double>(p->a);
-    const double *sv = static_cast<const double *>(src);
-    const GeomD gd = geom_d(g);
-    if (has_t && tpt == 2)
-      pair_kernel_f64<true, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-    else if (has_t)
-      pair_kernel_f64<true, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_f64<false, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+  with_variant(has_t, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
+    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
+    constexpr int kP = decltype(P)::value;
+    if (f64)
+      pair_kernel_f64<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
+          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a),
+          part);
     else
-      pair_kernel_f64<false, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-  } else {
-    const auto k = make_pair_consts<float>(p->a);
-    const float *sv = static_cast<const float *>(src);
-    const GeomF gf = geom_f(g);
-    if (has_t && tpt == 2)
-      pair_kernel_mixed<true, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else if (has_t)
-      pair_kernel_mixed<true, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_mixed<false, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else
-      pair_kernel_mixed<false, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-  }
+      pair_kernel_mixed<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
+          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+  });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(nrows) * double(n),
                      (f64 ? 0 : 2) + (has_t ? 1 : 0)));
@@ -1179,33 +1181,17 @@ int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const 
   }
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
-  if (f64) {
-    const auto k = make_pair_consts<double>(p->a);
-    const double *sv = static_cast<const double *>(src);
-    const GeomD gd = geom_d(g);
-    if (has_t && tpt == 2)
-      pair_kernel_f64_sym_batched<2, true><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-    else if (has_t)
-      pair_kernel_f64_sym_batched<1, true><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_f64_sym_batched<2, false><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+  with_variant(has_t, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
+    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
+    constexpr int kP = decltype(P)::value;
+    if (f64)
+      pair_kernel_f64_sym_batched<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
+          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a),
+          part);
     else
-      pair_kernel_f64_sym_batched<1, false><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-  } else {
-    const auto k = make_pair_consts<float>(p->a);
-    const float *sv = static_cast<const float *>(src);
-    const GeomF gf = geom_f(g);
-    if (has_t && tpt == 2)
-      pair_kernel_mixed_sym_batched<2, true><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else if (has_t)
-      pair_kernel_mixed_sym_batched<1, true><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_mixed_sym_batched<2, false><<<grid, kBlock, 0, stream>>>(args, gf, sv, k,
-                                                                           part);
-    else
-      pair_kernel_mixed_sym_batched<1, false><<<grid, kBlock, 0, stream>>>(args, gf, sv, k,
-                                                                           part);
-  }
+      pair_kernel_mixed_sym_batched<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
+          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+  });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta);
@@ -1251,31 +1237,17 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
   const int tpt = b.tpt;
-  if (f64) {
-    const auto k = make_pair_consts<double>(p->a);
-    const double *sv = static_cast<const double *>(src);
-    const GeomD gd = geom_d(g);
-    if (has_t && tpt == 2)
-      pair_kernel_f64_batched<true, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-    else if (has_t)
-      pair_kernel_f64_batched<true, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_f64_batched<false, 2><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
+  with_variant(has_t, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
+    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
+    constexpr int kP = decltype(P)::value;
+    if (f64)
+      pair_kernel_f64_batched<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
+          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a),
+          part);
     else
-      pair_kernel_f64_batched<false, 1><<<grid, kBlock, 0, stream>>>(args, gd, sv, k, part);
-  } else {
-    const auto k = make_pair_consts<float>(p->a);
-    const float *sv = static_cast<const float *>(src);
-    const GeomF gf = geom_f(g);
-    if (has_t && tpt == 2)
-      pair_kernel_mixed_batched<true, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else if (has_t)
-      pair_kernel_mixed_batched<true, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else if (tpt == 2)
-      pair_kernel_mixed_batched<false, 2><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-    else
-      pair_kernel_mixed_batched<false, 1><<<grid, kBlock, 0, stream>>>(args, gf, sv, k, part);
-  }
+      pair_kernel_mixed_batched<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
+          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+  });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta);

@@ -34,6 +34,8 @@
 // and since r and R share their horizontal part rho = (dx, dy), unbounded and wall terms
 // merge into one coefficient for F, one for rho and a z remainder.
 //
+// With WALL = false (free space) only the unbounded tensors are applied.
+//
 // Every value here carries the factor 8 pi eta; the caller divides once per target.
 #pragma once
 
@@ -79,7 +81,7 @@ __device__ __forceinline__ double rsqrt_r(double x) {
 // (ox, oy, oz).  dx, dy: x_i - x_j, y_i - y_j; zi, zj: clamped heights; f: the source's weighted
 // force; t: its weighted torque (used when TORQUE).  FAR_ONLY evaluates the |r| >= 2a form
 // alone (cheaper; the caller routes pairs with |r|^2 < 4a^2 to FAR_ONLY = false).
-template <typename Real, bool TORQUE, bool FAR_ONLY = false>
+template <typename Real, bool TORQUE, bool FAR_ONLY = false, bool WALL = true>
 __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj, Real fx, Real fy,
                                               Real fz, Real tx, Real ty, Real tz,
                                               const PairConsts<Real> &k, Real &ox, Real &oy,
@@ -114,6 +116,22 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
       cRR = k.near_rr * invr;
       cT = k.near_t - k.near_t_r * r;
     }
+  }
+
+  if (!WALL) {   // free space: the unbounded RPY tensors alone
+    const Real cr = cRR * (dx * fx + dy * fy + dz * fz);
+    ox += cI * fx;
+    ox += cr * dx;
+    oy += cI * fy;
+    oy += cr * dy;
+    oz += cI * fz;
+    oz += cr * dz;
+    if (TORQUE) {   // cT T x r
+      ox += cT * (ty * dz - tz * dy);
+      oy += cT * (tz * dx - tx * dz);
+      oz += cT * (tx * dy - ty * dx);
+    }
+    return;
   }
 
   // wall coefficients
@@ -183,7 +201,7 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
 // are added too, (o) += M^C_ij T_j and (p) += M^C_ji T_i (tq: T_j, uq: T_i).  M^C has no such
 // symmetry, but M^C_ji is the same expression with r -> -r and the image height hh = z~_j/|R|
 // replaced by z~_i/|R|, so everything else (|R|, e_z, X, the unbounded coefficient) is shared.
-template <typename Real, bool FAR_ONLY = false, bool TORQUE = false>
+template <typename Real, bool FAR_ONLY = false, bool TORQUE = false, bool WALL = true>
 __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Real zj, Real fx,
                                                   Real fy, Real fz, Real gx, Real gy, Real gz,
                                                   const PairConsts<Real> &k, Real &ox, Real &oy,
@@ -228,6 +246,32 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
       cRR = k.near_rr * invr;
       if (TORQUE) cT = k.near_t - k.near_t_r * r;
     }
+  }
+
+  if (!WALL) {   // free space: the unbounded RPY tensors alone (r -> -r for j <- i)
+    const Real cr = cRR * (dx * fx + dy * fy + dz * fz);
+    const Real cr2 = cRR * (dx * gx + dy * gy + dz * gz);
+    ox += cI * fx;
+    ox += cr * dx;
+    oy += cI * fy;
+    oy += cr * dy;
+    oz += cI * fz;
+    oz += cr * dz;
+    px += cI * gx;
+    px += cr2 * dx;
+    py += cI * gy;
+    py += cr2 * dy;
+    pz += cI * gz;
+    pz += cr2 * dz;
+    if (TORQUE) {   // cT T_j x r into o, cT T_i x (-r) into p
+      ox += cT * (tq[1] * dz - tq[2] * dy);
+      oy += cT * (tq[2] * dx - tq[0] * dz);
+      oz += cT * (tq[0] * dy - tq[1] * dx);
+      px -= cT * (uq[1] * dz - uq[2] * dy);
+      py -= cT * (uq[2] * dx - uq[0] * dz);
+      pz -= cT * (uq[0] * dy - uq[1] * dx);
+    }
+    return;
   }
 
   const Real iR2 = iR * iR;

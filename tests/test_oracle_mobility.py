@@ -150,3 +150,50 @@ def test_matrix_free_equals_dense(c1_dense):
     rows = np.array([0, 17, 255])
     ur = mobility.matvec(inp["pos"], inp["force"], inp["torque"], A, 1.0, rows=rows, workers=2)
     assert np.abs(ur - u_dense[rows]).max() <= 1e-14 * np.abs(u_dense).max()
+
+
+# ---- free space (wall = False): the unbounded RPY tensors alone ---------------------------
+
+def _free_config():
+    # overlapping pairs and spheres at and below z = 0: no wall, so nothing is clamped
+    return np.array([[0.0, 0.0, 1.3], [1.5, 0.4, 1.9], [0.8, -1.1, 0.6], [3.5, 1.0, -2.4],
+                     [2.6, -0.5, 0.0], [0.2, 0.3, 1.0]])
+
+
+def test_free_space_self_block_is_stokes_drag():
+    for z in (-3.0, 0.0, 0.4, 2.0):
+        M, _ = mobility.dense(np.array([[0.1, 0.2, z]]), 1.3, 0.7, wall=False)
+        assert np.allclose(M, np.eye(3) / (6 * math.pi * 0.7 * 1.3), rtol=1e-14, atol=0)
+
+
+def test_free_space_is_translation_invariant_and_spd():
+    pos = _free_config()
+    M0, C0 = mobility.dense(pos, wall=False)
+    M1, C1 = mobility.dense(pos + np.array([3.0, -7.0, 11.0]), wall=False)
+    assert np.allclose(M0, M1, rtol=1e-13, atol=1e-16)
+    assert np.allclose(C0, C1, rtol=1e-13, atol=1e-16)
+    assert np.allclose(M0, M0.T, rtol=0, atol=1e-15)
+    assert np.linalg.eigvalsh(M0).min() > 0.0
+    # the wall breaks the invariance
+    W0, _ = mobility.dense(pos + np.array([0.0, 0.0, 5.0]))
+    W1, _ = mobility.dense(pos + np.array([0.0, 0.0, 9.0]))
+    assert np.abs(W0 - W1).max() > 1e-3
+
+
+def test_wall_mobility_tends_to_free_space_far_from_the_wall():
+    # the image part of the self term decays like a/h (-9/16 a/h parallel, -9/8 a/h normal)
+    pos = _free_config() + np.array([0.0, 0.0, 3.0])
+    free, _ = mobility.dense(pos, wall=False)
+    for lift in (1e3, 1e4):
+        wall, _ = mobility.dense(pos + np.array([0.0, 0.0, lift]))
+        gap = np.abs(wall - free).max() / np.abs(free).max()
+        assert gap < 2.0 / lift
+
+
+def test_free_space_matrix_free_product_matches_dense():
+    pos = _free_config()
+    rng = np.random.default_rng(3)
+    F, T = rng.standard_normal(pos.shape), rng.standard_normal(pos.shape)
+    M, MC = mobility.dense(pos, wall=False)
+    ref = (M @ F.ravel() + MC @ T.ravel()).reshape(-1, 3)
+    assert np.allclose(mobility.matvec(pos, F, T, wall=False), ref, rtol=1e-13, atol=1e-16)

@@ -88,3 +88,14 @@ def test_rfd_scales_with_kT():
     d1 = stochastic.rfd(pos, wt, 1e-4, A, 1.0, 1.0)
     d2 = stochastic.rfd(pos, wt, 1e-4, A, 1.0, 2.5)
     assert np.allclose(d2, 2.5 * d1, rtol=1e-14, atol=0)
+
+
+def test_free_space_rfd_mean_vanishes():
+    # the unbounded RPY tensor is divergence-free (both branches), so the drift has mean zero
+    pos = _config()[:3]
+    rng = np.random.default_rng(12)
+    K = 800
+    samples = np.array([stochastic.rfd(pos, rng.standard_normal(pos.shape), 1e-4, A,
+                                       wall=False).ravel() for _ in range(K)])
+    se = samples.std(0) / math.sqrt(K)
+    assert np.all(np.abs(samples.mean(0)) <= 4.5 * se + 1e-12)
