@@ -122,6 +122,17 @@ int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, const doubl
                        const double *w, double tol, int max_iter, double *out,
                        int *iters_out, double *eps_out, rpb_stream_t stream);
 
+/* Block-diagonal preconditioned Lanczos (the preconditioning tried in Sec. II.C): with L the
+ * diagonal whose square is the diagonal of the self blocks M_ii (the wall self-mobilities
+ * mu_par, mu_par, mu_perp times H_i^2; L = 1 where H_i = 0), Lanczos runs on
+ * B = L^-1 M L^-1 and returns out = L B^{1/2} w.  That is a square root of M in the sense
+ * out out^T ~ M over w (covariance L B L = M), not the symmetric root M^{1/2} w, so it is a
+ * valid Brownian increment.  The stopping test applies to the B-space iterates.  Arguments,
+ * errors and iteration semantics as for lanczos_sqrt_apply. */
+int lanczos_sqrt_apply_precond(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                               const double *w, double tol, int max_iter, double *out,
+                               int *iters_out, double *eps_out, rpb_stream_t stream);
+
 /* Stochastic drift --------------------------------------------------------------------
  *
  * Centred random finite difference (paper, Sec. II.A, last term of eq. EM / eq. AB):
@@ -180,6 +191,7 @@ typedef struct {
   int scheme;           /* 0 = stochastic Adams-Bashforth, 1 = Euler-Maruyama */
   int rfd_precision;    /* rpb_precision of the two RFD products */
   int rfd_scheme;       /* 0 = centred RFD (rfd_drift), 1 = one-sided (rfd_drift_one_sided) */
+  int lanczos_precond;  /* 1: block-diagonal preconditioned Lanczos (lanczos_sqrt_apply_precond) */
   double f_grav_z;      /* gravity force on each sphere along z */
   double torque[3];     /* constant torque on every sphere */
   double steric_u0;     /* U0 of eq. soft_potential */

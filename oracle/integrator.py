@@ -30,11 +30,13 @@ from . import lanczos, mobility, stochastic
 
 def step(pos, u_prev, w, w_tilde, *, dt, delta, lanczos_tol, lanczos_max_iter=64,
          scheme="sab", f_grav_z=-1.0, torque=(0.0, 1.0, 0.0), u0=1.0, b=0.1,
-         a=1.0, eta=1.0, kT=1.0, dense=None, rfd="centred", wall=True):
+         a=1.0, eta=1.0, kT=1.0, dense=None, rfd="centred", wall=True,
+         lanczos_precond=False):
     """Advance ``pos`` by one step.  Returns (new_pos, u_now, lanczos_iterations, eps, status).
 
     ``u_prev``: previous deterministic velocity or None (first step).  ``rfd``: "centred"
-    or "one_sided" random finite difference for the drift.  ``wall=False``: free space.  ``w``,
+    or "one_sided" random finite difference for the drift.  ``wall=False``: free space.
+    ``lanczos_precond``: block-diagonal preconditioned Lanczos for the noise.  ``w``,
     ``w_tilde``: (n, 3) normal variates.  ``dense``: use dense matrices (default
     for n <= 1500).
     """
@@ -52,8 +54,13 @@ def step(pos, u_prev, w, w_tilde, *, dt, delta, lanczos_tol, lanczos_max_iter=64
         u = mobility.matvec(pos, F, T, a, eta, wall=wall)
         apply_m = lambda v: mobility.matvec(pos, v.reshape(n, 3), None, a, eta,
                                             wall=wall).ravel()
-    g, iters, eps, status = lanczos.lanczos_sqrt(apply_m, np.asarray(w).ravel(),
-                                                 lanczos_tol, lanczos_max_iter)
+    if lanczos_precond:
+        scale = lanczos.block_diagonal_scale(pos, a, eta, wall)
+        g, iters, eps, status = lanczos.lanczos_sqrt_precond(apply_m, scale, np.asarray(w).ravel(),
+                                                             lanczos_tol, lanczos_max_iter)
+    else:
+        g, iters, eps, status = lanczos.lanczos_sqrt(apply_m, np.asarray(w).ravel(),
+                                                     lanczos_tol, lanczos_max_iter)
     rfd_fn = stochastic.rfd if rfd == "centred" else stochastic.rfd_one_sided
     drift = rfd_fn(pos, w_tilde, delta, a, eta, kT, wall=wall)
     if scheme == "em" or u_prev is None:

@@ -17,7 +17,9 @@ Pinned by (tests/test_oracle_lanczos.py): against the dense symmetric square
 root (``sqrtm_dense``) of the assembled mobility at tight tolerance; at m = 3N
 iterations the result is the exact M^{1/2} W; for one sphere the result equals
 the closed-form diagonal square root; the sample covariance of g over many W
-approaches M (fluctuation-dissipation, eq. BD).
+approaches M (fluctuation-dissipation, eq. BD).  The preconditioned variant at
+m = 3N equals L B^{1/2} W with (L B^{1/2})(L B^{1/2})^T = M, and its scale reproduces the
+wall self-mobility series.
 """
 from __future__ import annotations
 
@@ -74,3 +76,30 @@ def sqrtm_dense(M):
     """Symmetric square root Q Lambda^{1/2} Q^T of a symmetric PSD matrix."""
     lam, Q = np.linalg.eigh(np.asarray(M, dtype=np.float64))
     return (Q * np.sqrt(np.maximum(lam, 0.0))) @ Q.T
+
+
+def block_diagonal_scale(pos, a=1.0, eta=1.0, wall=True):
+    """L with L^2 = the diagonal of the self blocks M_ii, flat (3N,).
+
+    With the wall each self block is diagonal, diag(mu_par, mu_par, mu_perp) times H_i^2
+    (App. A); a sphere at or below the wall (H = 0) keeps L = 1, so its zero rows of M stay
+    zero rows of B.  The blocks are read off the dense oracle matrix of each lone sphere.
+    """
+    from . import mobility
+    pos = np.asarray(pos, dtype=np.float64)
+    out = np.ones(3 * len(pos))
+    for i, q in enumerate(pos):
+        M, _ = mobility.dense(q[None, :], a, eta, wall)
+        d = np.diag(M)
+        out[3 * i:3 * i + 3] = np.where(d > 0.0, np.sqrt(np.where(d > 0.0, d, 1.0)), 1.0)
+    return out
+
+
+def lanczos_sqrt_precond(apply_m, scale, w, tol, max_iter=64):
+    """Square-root preconditioned Lanczos (the preconditioning Sec. II.C tried): with
+    P = L L^T block diagonal (here diagonal, L = diag(scale)), run Lanczos on
+    B = L^-1 M L^-T and return g = L B^{1/2} w, whose covariance over w is L B L^T = M.
+    The stopping test is applied to the B-space iterates.  Returns (g, m, eps, status)."""
+    scale = np.asarray(scale, dtype=np.float64)
+    y, m, eps, status = lanczos_sqrt(lambda v: apply_m(v / scale) / scale, w, tol, max_iter)
+    return scale * y, m, eps, status

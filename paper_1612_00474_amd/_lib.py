@@ -24,7 +24,7 @@ PRECISIONS = {"fp64": RPB_FP64, "mixed": RPB_MIXED}
 EXPORTS = (
     "rpb_create", "rpb_destroy", "rpb_last_error", "rpb_version",
     "rpb_mobility_matvec", "rpb_mobility_matvec_rows", "lanczos_sqrt_apply", "rfd_drift",
-    "rfd_drift_one_sided",
+    "rfd_drift_one_sided", "lanczos_sqrt_apply_precond",
     "rpb_forces", "rpb_normals", "sab_step", "rpb_timing_enable", "rpb_timing_read",
     "rpb_mobility_matvec_batched", "lanczos_sqrt_apply_batched", "sab_step_batched",
     "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
@@ -40,7 +40,8 @@ class RpbParams(C.Structure):
 class RpbSabConfig(C.Structure):
     _fields_ = [("dt", C.c_double), ("delta", C.c_double), ("lanczos_tol", C.c_double),
                 ("lanczos_max_iter", C.c_int), ("scheme", C.c_int), ("rfd_precision", C.c_int),
-                ("rfd_scheme", C.c_int), ("f_grav_z", C.c_double), ("torque", C.c_double * 3), ("steric_u0", C.c_double),
+                ("rfd_scheme", C.c_int), ("lanczos_precond", C.c_int), ("f_grav_z", C.c_double),
+                ("torque", C.c_double * 3), ("steric_u0", C.c_double),
                 ("steric_b", C.c_double), ("seed", C.c_uint64)]
 
 
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH):
         "rpb_mobility_matvec_rows": (C.c_int, [P, pp, I64, P, P, P, I64, I64, P, P]),
         "lanczos_sqrt_apply": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, C.POINTER(C.c_int),
                                          C.POINTER(D), P]),
+        "lanczos_sqrt_apply_precond": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P,
+                                                 C.POINTER(C.c_int), C.POINTER(D), P]),
         "rfd_drift": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, P]),
         "rfd_drift_one_sided": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, P]),
         "rpb_forces": (C.c_int, [P, pp, I64, P, D, D, D, P, P]),
@@ -164,12 +167,13 @@ RFD_SCHEMES = {"centred": 0, "one_sided": 1}
 
 
 def _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision, f_grav_z,
-                torque, steric_u0, steric_b, seed, rfd_scheme="centred"):
+                torque, steric_u0, steric_b, seed, rfd_scheme="centred", lanczos_precond=False):
     if scheme not in ("sab", "em"):
         raise ValueError(f"scheme must be 'sab' or 'em', not {scheme!r}")
     return RpbSabConfig(dt, delta, lanczos_tol, lanczos_max_iter, 0 if scheme == "sab" else 1,
-                        PRECISIONS[rfd_precision], RFD_SCHEMES[rfd_scheme], f_grav_z,
-                        (C.c_double * 3)(*torque), steric_u0, steric_b, seed)
+                        PRECISIONS[rfd_precision], RFD_SCHEMES[rfd_scheme],
+                        int(bool(lanczos_precond)), f_grav_z, (C.c_double * 3)(*torque),
+                        steric_u0, steric_b, seed)
 
 
 def _stream():
@@ -245,8 +249,9 @@ class Context:
         self._check(st)
         return out
 
-    def lanczos(self, pos, w, tol, max_iter=64, precision="fp64", out=None, allow_noconv=False):
-        """Returns (g, iterations, eps, status)."""
+    def lanczos(self, pos, w, tol, max_iter=64, precision="fp64", out=None, allow_noconv=False,
+                precond=False):
+        """Returns (g, iterations, eps, status); precond: block-diagonal preconditioned form."""
         import torch
         pos = _vec3(pos, "pos")
         n = pos.shape[0]
@@ -256,9 +261,9 @@ class Context:
         p = self.params(precision)
         it = C.c_int(0)
         eps = C.c_double(0.0)
-        st = self.lib.lanczos_sqrt_apply(self.h, C.byref(p), n, _ptr(pos), _ptr(w), float(tol),
-                                         int(max_iter), _ptr(out), C.byref(it), C.byref(eps),
-                                         _stream())
+        fn = self.lib.lanczos_sqrt_apply_precond if precond else self.lib.lanczos_sqrt_apply
+        st = fn(self.h, C.byref(p), n, _ptr(pos), _ptr(w), float(tol), int(max_iter), _ptr(out),
+                C.byref(it), C.byref(eps), _stream())
         self._check(st, (RPB_OK, RPB_ENOCONV) if allow_noconv else (RPB_OK,))
         return out, it.value, eps.value, st
 
@@ -340,7 +345,8 @@ class Context:
     def sab_step_batched(self, pos, u_prev, offs, step, have_prev, *, dt, delta, lanczos_tol,
                          lanczos_max_iter=64, scheme="sab", rfd_precision="fp64", f_grav_z=-1.0,
                          torque=(0.0, 1.0, 0.0), steric_u0=1.0, steric_b=0.1, seed=0,
-                         precision="fp64", w=None, w_tilde=None, rfd_scheme="centred"):
+                         precision="fp64", w=None, w_tilde=None, rfd_scheme="centred",
+                         lanczos_precond=False):
         """One step of every system; updates pos and u_prev in place.
         Returns (iterations per system, eps per system, status)."""
         import numpy as np
@@ -350,7 +356,8 @@ class Context:
         o = _offsets(offs, n)
         nsys = o.size - 1
         cfg = _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision,
-                          f_grav_z, torque, steric_u0, steric_b, seed, rfd_scheme)
+                          f_grav_z, torque, steric_u0, steric_b, seed, rfd_scheme,
+                          lanczos_precond)
         it = np.zeros(nsys, dtype=np.int32)
         eps = np.zeros(nsys, dtype=np.float64)
         p = self.params(precision)
@@ -364,22 +371,23 @@ class Context:
     def step_graph(self, pos, u_prev, offs, step=0, have_prev=False, *, dt, delta, lanczos_tol,
                    lanczos_max_iter=16, scheme="sab", rfd_precision="fp64", f_grav_z=-1.0,
                    torque=(0.0, 1.0, 0.0), steric_u0=1.0, steric_b=0.1, seed=0,
-                   precision="fp64", rfd_scheme="centred"):
+                   precision="fp64", rfd_scheme="centred", lanczos_precond=False):
         """A hipGraph of one batched step bound to pos / u_prev (see StepGraph)."""
         return StepGraph(self, pos, u_prev, offs, step, have_prev,
                          _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme,
                                      rfd_precision, f_grav_z, torque, steric_u0, steric_b, seed,
-                                     rfd_scheme),
+                                     rfd_scheme, lanczos_precond),
                          precision)
 
     # -- time step -----------------------------------------------------------------------
     def sab_step(self, state, *, dt, delta, lanczos_tol, lanczos_max_iter=64, scheme="sab",
                  rfd_precision="fp64", f_grav_z=-1.0, torque=(0.0, 1.0, 0.0), steric_u0=1.0,
                  steric_b=0.1, seed=0, precision="fp64", w=None, w_tilde=None,
-                 rfd_scheme="centred"):
+                 rfd_scheme="centred", lanczos_precond=False):
         """Advance ``state`` (a StepState) by one step; returns (iterations, eps, status)."""
         cfg = _sab_config(dt, delta, lanczos_tol, lanczos_max_iter, scheme, rfd_precision,
-                          f_grav_z, torque, steric_u0, steric_b, seed, rfd_scheme)
+                          f_grav_z, torque, steric_u0, steric_b, seed, rfd_scheme,
+                          lanczos_precond)
         n = state.pos.shape[0]
         if w is not None:
             _vec3(w, "w", n)

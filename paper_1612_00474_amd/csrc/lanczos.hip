@@ -443,6 +443,18 @@ __global__ void lz_status_batched(SegView v, int nsys, LzStatus *__restrict__ ou
   out[s].eps = v.st[s].eps;
 }
 
+// y = x / s, or x /= s in place when y == x (square-root preconditioning)
+__global__ void divide_by(int64_t m, const double *__restrict__ x, const double *__restrict__ s,
+                          double *y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < m) y[i] = x[i] / s[i];
+}
+
+__global__ void multiply_by(int64_t m, double *x, const double *__restrict__ s) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < m) x[i] *= s[i];
+}
+
 inline unsigned nblk(int64_t m) { return unsigned((m + kThreads - 1) / kThreads); }
 
 int dot(rpb_ctx *ctx, int64_t m, const double *a, const double *b, double *part, double *out,
@@ -457,10 +469,18 @@ int dot(rpb_ctx *ctx, int64_t m, const double *a, const double *b, double *part,
 }  // namespace
 
 int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *w, double tol,
-                int max_iter, double *out, int *iters, double *eps_out, hipStream_t stream) {
+                int max_iter, bool precond, double *out, int *iters, double *eps_out,
+                hipStream_t stream) {
   const int64_t n = g.n;
   const int64_t m3 = 3 * n;
   int st;
+  double *L = nullptr, *t = nullptr;
+  if (precond) {
+    L = static_cast<double *>(workspace(ctx, WS_PRECOND, size_t(2 * m3) * sizeof(double), &st));
+    if (!L) return st;
+    t = L + m3;
+    RPB_TRY(block_diag_scale(ctx, p, g, L, stream));
+  }
   double *V = static_cast<double *>(
       workspace(ctx, WS_KRYLOV, size_t(max_iter) * size_t(m3) * sizeof(double), &st));
   if (!V) return st;
@@ -487,7 +507,15 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   for (m = 1; m <= max_iter; ++m) {
     double *vm = V + int64_t(m - 1) * m3;
     const double *vprev = m > 1 ? V + int64_t(m - 2) * m3 : nullptr;
-    RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream));
+    if (precond) {   // u = L^-1 M L^-1 vm
+      divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, vm, L, t);
+      RPB_LAUNCHED(ctx);
+      RPB_TRY(matvec_packed(ctx, p, g, t, nullptr, 0, n, u, stream));
+      divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
+      RPB_LAUNCHED(ctx);
+    } else {
+      RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream));
+    }
     RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[m - 1], 0, stream));
     three_term<<<nblk(m3), kThreads, 0, stream>>>(m3, u, vm, vprev, &ls->alpha[m - 1],
                                                    m > 1 ? &ls->beta[m - 2] : nullptr);
@@ -518,6 +546,10 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   if (m > max_iter) m = max_iter;
   basis_combine<<<nblk(m3), kThreads, 0, stream>>>(m3, m, V, ls->y, out);
   RPB_LAUNCHED(ctx);
+  if (precond) {
+    multiply_by<<<nblk(m3), kThreads, 0, stream>>>(m3, out, L);
+    RPB_LAUNCHED(ctx);
+  }
   if (iters) *iters = m;
   if (eps_out) *eps_out = eps;
   if (reason == 4) return fail(ctx, RPB_EDEVICE, "tridiagonal eigensolve did not converge");
@@ -530,12 +562,19 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
 
 
 int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
-                        const double *w, double tol, int max_iter, double *out, bool sync_each,
-                        LzStatus *status_host, hipStream_t stream) {
+                        const double *w, double tol, int max_iter, bool precond, double *out,
+                        bool sync_each, LzStatus *status_host, hipStream_t stream) {
   const int64_t n = g.n;
   const int64_t m3 = 3 * n;
   const int nsys = b.nsys;
   int st;
+  double *L = nullptr, *t = nullptr;
+  if (precond) {
+    L = static_cast<double *>(workspace(ctx, WS_PRECOND, size_t(2 * m3) * sizeof(double), &st));
+    if (!L) return st;
+    t = L + m3;
+    RPB_TRY(block_diag_scale(ctx, p, g, L, stream));
+  }
   double *V = static_cast<double *>(
       workspace(ctx, WS_KRYLOV, size_t(max_iter) * size_t(m3) * sizeof(double), &st));
   if (!V) return st;
@@ -573,7 +612,15 @@ int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const
   for (int k = 1; k <= max_iter; ++k) {
     double *vk = V + int64_t(k - 1) * m3;
     const double *vprev = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
-    RPB_TRY(matvec_batched(ctx, p, b, g, vk, nullptr, v.done, u, stream));
+    if (precond) {   // u = L^-1 M L^-1 vk (rows of finished systems are not used)
+      divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, vk, L, t);
+      RPB_LAUNCHED(ctx);
+      RPB_TRY(matvec_batched(ctx, p, b, g, t, nullptr, v.done, u, stream));
+      divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
+      RPB_LAUNCHED(ctx);
+    } else {
+      RPB_TRY(matvec_batched(ctx, p, b, g, vk, nullptr, v.done, u, stream));
+    }
     RPB_TRY(seg_dot(vk, u, f_alpha + k - 1, 0));
     seg_three_term<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, u, vk, vprev);
     RPB_LAUNCHED(ctx);
@@ -603,6 +650,10 @@ int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const
   }
   seg_basis_combine<<<nblk(m3), kThreads, 0, stream>>>(v, m3, V, out);
   RPB_LAUNCHED(ctx);
+  if (precond) {
+    multiply_by<<<nblk(m3), kThreads, 0, stream>>>(m3, out, L);
+    RPB_LAUNCHED(ctx);
+  }
   lz_status_batched<<<(ns + 63) / 64, 64, 0, stream>>>(v, nsys, status_dev);
   RPB_LAUNCHED(ctx);
   if (status_host) {
@@ -640,9 +691,11 @@ int lanczos_status_code(rpb_ctx *ctx, const LzStatus *s, int nsys) {
 
 using namespace rpb;
 
-extern "C" int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
-                                  const double *w, double tol, int max_iter, double *out,
-                                  int *iters_out, double *eps_out, rpb_stream_t stream_) {
+namespace {
+
+int lanczos_entry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                  const double *w, double tol, int max_iter, bool precond, double *out,
+                  int *iters_out, double *eps_out, rpb_stream_t stream_) {
   RPB_TRY(check_params(ctx, p));
   if (n < 0) return fail(ctx, RPB_EINVAL, "n must be >= 0");
   if (!(tol > 0.0)) return fail(ctx, RPB_EINVAL, "tol must be > 0");
@@ -660,7 +713,22 @@ extern "C" int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, 
   RPB_TRY(check_finite(ctx, pos, n, stream));
   Packed g;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
-  return lanczos_run(ctx, p, g, w, tol, max_iter, out, iters_out, eps_out, stream);
+  return lanczos_run(ctx, p, g, w, tol, max_iter, precond, out, iters_out, eps_out, stream);
+}
+
+}  // namespace
+
+extern "C" int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                                  const double *w, double tol, int max_iter, double *out,
+                                  int *iters_out, double *eps_out, rpb_stream_t stream) {
+  return lanczos_entry(ctx, p, n, pos, w, tol, max_iter, false, out, iters_out, eps_out, stream);
+}
+
+extern "C" int lanczos_sqrt_apply_precond(rpb_ctx *ctx, const rpb_params *p, int64_t n,
+                                          const double *pos, const double *w, double tol,
+                                          int max_iter, double *out, int *iters_out,
+                                          double *eps_out, rpb_stream_t stream) {
+  return lanczos_entry(ctx, p, n, pos, w, tol, max_iter, true, out, iters_out, eps_out, stream);
 }
 
 extern "C" int lanczos_sqrt_apply_batched(rpb_ctx *ctx, const rpb_params *p, int32_t nsys,
@@ -692,7 +760,7 @@ extern "C" int lanczos_sqrt_apply_batched(rpb_ctx *ctx, const rpb_params *p, int
   Packed g;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
   LzStatus *stat = static_cast<LzStatus *>(host_scratch(ctx));
-  RPB_TRY(lanczos_batched_run(ctx, p, b, g, w, tol, max_iter, out, true, stat, stream));
+  RPB_TRY(lanczos_batched_run(ctx, p, b, g, w, tol, max_iter, false, out, true, stat, stream));
   for (int s = 0; s < nsys; ++s) {
     if (iters_out) iters_out[s] = stat[s].m;
     if (eps_out) eps_out[s] = stat[s].eps;

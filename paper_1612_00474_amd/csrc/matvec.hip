@@ -878,6 +878,24 @@ inline unsigned blocks_for(int64_t n, int threads) {
   return unsigned((n + threads - 1) / threads);
 }
 
+// L with L^2 = diag(M_ii): the self pair (r = 0, R = (0, 0, 2 z~)) applied to e_x and e_z, in
+// float64 whatever the product precision; H = 0 keeps L = 1.
+template <bool WALL, typename Geom>
+__global__ void self_scale(int64_t n, Geom g, PairConsts<double> k, double inv8pieta,
+                           double *__restrict__ scale) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double z = double(g.z[i]), w = g.h[i] * g.h[i] * inv8pieta;
+  double px = 0.0, py = 0.0, pz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+  pair_velocity<double, false, false, WALL>(0.0, 0.0, z, z, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, k, px,
+                                            py, pz);
+  pair_velocity<double, false, false, WALL>(0.0, 0.0, z, z, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, k, nx,
+                                            ny, nz);
+  const double dpar = w * px, dperp = w * nz;
+  scale[3 * i] = scale[3 * i + 1] = dpar > 0.0 ? sqrt(dpar) : 1.0;
+  scale[3 * i + 2] = dperp > 0.0 ? sqrt(dperp) : 1.0;
+}
+
 // Calls fn(torque, tpt, wall) with the three as std::integral_constant values, so each
 // launch site names its kernel template once.
 template <typename Fn>
@@ -959,6 +977,28 @@ int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *po
     double *h = static_cast<double *>(buf);
     pack_geometry_mixed<<<blocks_for(n, 256), 256, 0, stream>>>(
         n, pos, p->a, p->wall, h, reinterpret_cast<float *>(h + n));
+  }
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+int block_diag_scale(rpb_ctx *ctx, const rpb_params *p, const Packed &g, double *scale,
+                     hipStream_t stream) {
+  const int64_t n = g.n;
+  if (n == 0) return RPB_OK;
+  const auto k = make_pair_consts<double>(p->a);
+  const double inv = 1.0 / (8.0 * M_PI * p->eta);
+  const unsigned nb = blocks_for(n, 256);
+  if (g.precision == RPB_FP64) {
+    if (p->wall)
+      self_scale<true><<<nb, 256, 0, stream>>>(n, geom_d(g), k, inv, scale);
+    else
+      self_scale<false><<<nb, 256, 0, stream>>>(n, geom_d(g), k, inv, scale);
+  } else {
+    if (p->wall)
+      self_scale<true><<<nb, 256, 0, stream>>>(n, geom_f(g), k, inv, scale);
+    else
+      self_scale<false><<<nb, 256, 0, stream>>>(n, geom_f(g), k, inv, scale);
   }
   RPB_LAUNCHED(ctx);
   return RPB_OK;

@@ -38,6 +38,7 @@ enum Slot {
   WS_SMALL,         // small device scalars (Lanczos coefficients, status, flags)
   WS_BATCH,         // batched products: offsets, work items, sphere -> system map
   WS_LZBATCH,       // batched Lanczos: per-system scalars and status
+  WS_PRECOND,       // block-diagonal preconditioner: L (3n) and a scaled vector (3n)
   WS_NSLOTS
 };
 
@@ -199,15 +200,22 @@ struct LzStatus {
 // iterations with device-side freezing only (no host synchronisation: capturable).
 // status_host (pinned, nsys records) is filled when not NULL (synchronises).
 int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
-                        const double *w, double tol, int max_iter, double *out, bool sync_each,
-                        LzStatus *status_host, hipStream_t stream);
+                        const double *w, double tol, int max_iter, bool precond, double *out,
+                        bool sync_each, LzStatus *status_host, hipStream_t stream);
+// L (3n, float64) with L^2 = the diagonal of the self blocks M_ii of the packed geometry
+// (1 where H = 0).
+int block_diag_scale(rpb_ctx *ctx, const rpb_params *p, const Packed &g, double *scale,
+                     hipStream_t stream);
 // Map per-system outcomes to a status code (first failure wins; ENOCONV when any missed tol).
 int lanczos_status_code(rpb_ctx *ctx, const LzStatus *s, int nsys);
 // Copy the per-system outcomes of the last batched solve (synchronises `stream`).
 int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStream_t stream);
 
+// precond: square-root preconditioning with the self-block diagonal (block_diag_scale):
+// Lanczos on B = L^-1 M L^-1, result L B^{1/2} w.
 int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *w, double tol,
-                int max_iter, double *out, int *iters, double *eps, hipStream_t stream);
+                int max_iter, bool precond, double *out, int *iters, double *eps,
+                hipStream_t stream);
 
 // ---- RFD / RNG / forces / step ----------------------------------------------------------
 int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, const double *wt,

@@ -104,8 +104,8 @@ int step_batched_enqueue(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config
   Packed geo;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &geo, stream));
   RPB_TRY(matvec_batched(ctx, p, bt, geo, F, T, nullptr, u, stream));
-  RPB_TRY(lanczos_batched_run(ctx, p, bt, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter, g,
-                              sync_lanczos, status_host, stream));
+  RPB_TRY(lanczos_batched_run(ctx, p, bt, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter,
+                              cfg->lanczos_precond != 0, g, sync_lanczos, status_host, stream));
   RPB_TRY(rfd_batched_run(ctx, p, bt, pos, Wt, cfg->delta, cfg->rfd_precision,
                           cfg->rfd_scheme == 1, drift, stream));
   combine_kernel_dev<<<nblk(m3), 256, 0, stream>>>(m3, pos, u_prev, u, g, drift, cfg->dt,
@@ -134,6 +134,8 @@ int check_step_config(rpb_ctx *ctx, const rpb_sab_config *cfg) {
     return fail(ctx, RPB_EINVAL, "unknown rfd_precision");
   if (cfg->rfd_scheme != 0 && cfg->rfd_scheme != 1)
     return fail(ctx, RPB_EINVAL, "unknown rfd_scheme");
+  if (cfg->lanczos_precond != 0 && cfg->lanczos_precond != 1)
+    return fail(ctx, RPB_EINVAL, "lanczos_precond must be 0 or 1");
   if (!(cfg->steric_u0 >= 0.0) || !(cfg->steric_b > 0.0))
     return fail(ctx, RPB_EINVAL, "need steric_u0 >= 0 and steric_b > 0");
   return RPB_OK;
@@ -206,8 +208,8 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   // Brownian increment (the last iterate is used if the tolerance is not met)
   int iters = 0;
   double eps = 0.0;
-  const int lz = lanczos_run(ctx, p, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter, g, &iters,
-                             &eps, stream);
+  const int lz = lanczos_run(ctx, p, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter,
+                             cfg->lanczos_precond != 0, g, &iters, &eps, stream);
   if (lz != RPB_OK && lz != RPB_ENOCONV) return lz;
 
   // stochastic drift

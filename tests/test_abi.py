@@ -40,3 +40,32 @@ def test_binding_loads_and_matches_header():
     for name in _lib.EXPORTS:
         assert hasattr(lib, name)
     assert lib.rpb_version().decode().startswith("librpb")
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    # every field offset and struct size of the binding's mirrors, against gcc on rpb.h
+    import ctypes as C
+    from paper_1612_00474_amd import _lib
+    structs = {"rpb_params": _lib.RpbParams, "rpb_sab_config": _lib.RpbSabConfig,
+               "rpb_shape": _lib.RpbShape, "rpb_tuning": _lib.RpbTuning,
+               "rpb_sab_state": _lib.RpbSabState}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rpb.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        cname, what, value = line.split()
+        py = structs[cname]
+        expect = C.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert int(value) == expect, (cname, what)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in structs.values())

@@ -89,3 +89,30 @@ def test_full_size_properties(ctx):
     g64 = host(ctx.lanczos(P, W, 1e-300, max_iter=6, allow_noconv=True)[0])
     g32 = host(ctx.lanczos(P, W, 1e-300, max_iter=6, precision="mixed", allow_noconv=True)[0])
     assert rel2(g32, g64) <= 1e-5
+
+
+@pytest.mark.parametrize("m", [1, 3, 7])
+def test_preconditioned_fixed_iterations_fp64(ctx, c1, m):
+    # square-root preconditioning: Lanczos on B = L^-1 M L^-1, result L B^{1/2} w
+    inp, M = c1
+    pos = inp["pos"].copy()
+    pos[5, 2] = 0.7                      # one sphere below z = a (H < 1 scales its L)
+    Mp, _ = mobility.dense(pos)
+    L = lanczos.block_diagonal_scale(pos)
+    w = inp["w"]
+    ref, mref, _, _ = lanczos.lanczos_sqrt_precond(lambda v: Mp @ v, L, w.ravel(), 1e-300, m)
+    g, it, eps, st = ctx.lanczos(dev(pos), dev(w), 1e-300, max_iter=m, allow_noconv=True,
+                                 precond=True)
+    assert it == m == mref
+    assert rel2(host(g).ravel(), ref) <= 1e-12
+
+
+def test_preconditioned_tolerance_run_is_a_root_of_m(ctx, c1):
+    inp, M = c1
+    L = lanczos.block_diagonal_scale(inp["pos"])
+    S = L[:, None] * lanczos.sqrtm_dense(M / np.outer(L, L))      # S S^T = M
+    w = inp["w"].ravel()
+    for precision, tol in (("fp64", 1e-5), ("mixed", 1e-4)):
+        g, it, eps, st = ctx.lanczos(dev(inp["pos"]), dev(inp["w"]), 1e-6, precision=precision,
+                                     precond=True)
+        assert rel2(host(g).ravel(), S @ w) <= tol, precision

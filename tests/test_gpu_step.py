@@ -59,6 +59,22 @@ def test_two_steps_match_oracle(ctx, scheme, rfd):
     assert state.step == 2 and state.have_prev
 
 
+def test_preconditioned_step_matches_oracle(ctx):
+    from paper_1612_00474_amd import StepState
+    inp = _setup()
+    rng = np.random.default_rng(8)
+    W, Wt = rng.standard_normal(inp["pos"].shape), rng.standard_normal(inp["pos"].shape)
+    state = StepState(dev(inp["pos"]))
+    it, eps, st = ctx.sab_step(state, dt=0.01, delta=1e-4, lanczos_tol=1e-300,
+                               lanczos_max_iter=M_FIXED, w=dev(W), w_tilde=dev(Wt), steric_u0=1.0,
+                               steric_b=0.1, lanczos_precond=True, **PHYS)
+    new, u, m, _, _ = integrator.step(inp["pos"], None, W, Wt, dt=0.01, delta=1e-4,
+                                      lanczos_tol=1e-300, lanczos_max_iter=M_FIXED, u0=1.0, b=0.1,
+                                      lanczos_precond=True, **PHYS)
+    assert it == m == M_FIXED
+    assert rel2(host(state.pos) - inp["pos"], new - inp["pos"]) <= 1e-10
+
+
 def test_device_noise_matches_oracle_generator(ctx):
     from paper_1612_00474_amd import StepState
     inp = _setup(n=120, seed=1)

@@ -6,6 +6,7 @@ import pytest
 
 from oracle import faxen, lanczos, mobility
 from paper_1612_00474_amd import workloads as wl
+from tests.conftest import golden_rows
 
 A = 1.0
 
@@ -73,3 +74,34 @@ def test_non_convergence_and_status():
     M, _ = mobility.dense(pos, A, 1.0)
     g, m, eps, status = lanczos.lanczos_sqrt(lambda v: M @ v, rng.standard_normal(60), 1e-14, max_iter=3)
     assert status == "noconv" and m == 3 and eps > 1e-14
+
+
+def test_preconditioned_root_is_a_square_root_of_m(c1):
+    # square-root preconditioning: S = L B^{1/2} with B = L^-1 M L^-T satisfies S S^T = M
+    pos = c1[0]["pos"][:40].copy()
+    pos[3, 2] = 0.6                      # one sphere below z = a (H < 1)
+    M, _ = mobility.dense(pos)
+    L = lanczos.block_diagonal_scale(pos)
+    B = M / np.outer(L, L)
+    S = L[:, None] * lanczos.sqrtm_dense(B)
+    assert np.allclose(S @ S.T, M, rtol=0, atol=1e-14 * np.abs(M).max())
+    # the self blocks of B are the identity (L^2 is their diagonal)
+    for i in range(len(pos)):
+        assert np.allclose(B[3 * i:3 * i + 3, 3 * i:3 * i + 3], np.eye(3), atol=1e-14)
+    w = np.random.default_rng(3).standard_normal(3 * len(pos))
+    g, m, eps, st = lanczos.lanczos_sqrt_precond(lambda v: M @ v, L, w, 1e-300, 3 * len(pos))
+    assert np.allclose(g, S @ w, rtol=0, atol=1e-10 * np.abs(S @ w).max())
+
+
+def test_block_diagonal_scale_follows_the_wall_self_mobility():
+    # L^2 (6 pi eta a) = 1 - 9/16 eps + 1/8 eps^3 (parallel), 1 - 9/8 eps + 1/2 eps^3 (normal)
+    # through O(eps^3) (golden fixture), eps = a/h; zero weight below the wall keeps L = 1
+    coef = {}
+    for dn, o, num, den in golden_rows("wall_self_mobility_series.txt"):
+        coef.setdefault(dn, {})[int(o)] = int(num) / int(den)
+    h = 30.0
+    L = lanczos.block_diagonal_scale(np.array([[0.0, 0.0, h], [1.0, 1.0, -0.5]]))
+    for k, dn in ((0, "par"), (2, "perp")):
+        series = sum(c * (1.0 / h) ** o for o, c in coef[dn].items())
+        assert abs(L[k] ** 2 * 6 * np.pi - series) <= 2.0 / h ** 4
+    assert np.all(L[3:] == 1.0)
