@@ -66,6 +66,13 @@ typedef struct {
                            and weighted as in App. A, soft wall repulsion in rpb_forces);
                            0: free space (unbounded RPY tensors of Sec. II.B alone, no
                            clamping, no wall force), the contrast of Sec. II.C / Fig. 1 */
+  double lx, ly;        /* both > 0: pseudo-periodic boundaries in x and y with these box
+                           lengths (App. B): pair forces by the minimum image convention,
+                           hydrodynamics summed over the minimum image and its images in the
+                           eight neighbour cells; both 0: unbounded.  Single-system calls only
+                           (the batched entry points return RPB_EINVAL); rpb_forces needs
+                           lx, ly > 2 (2a + 40 b) so that the minimum image holds every pair
+                           within its cutoff. */
 } rpb_params;
 
 /* Context ---------------------------------------------------------------------------- */

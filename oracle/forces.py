@@ -35,15 +35,19 @@ def force_magnitude(r, d, u0, b):
     return np.where(r < d, u0 / b, (u0 / b) * np.exp(-(r - d) / b))
 
 
-def forces(pos, a=1.0, u0=1.0, b=0.1, f_grav_z=-1.0, rows=None, wall=True):
+def forces(pos, a=1.0, u0=1.0, b=0.1, f_grav_z=-1.0, rows=None, wall=True, box=None):
     """Total force on each sphere (or on ``rows``), shape (n, 3) / (len(rows), 3).
-    ``wall=False``: no wall repulsion (free space)."""
+    ``wall=False``: no wall repulsion (free space).  ``box=(L_x, L_y)``: pair separations
+    by the minimum image convention (App. B)."""
     pos = np.asarray(pos, dtype=np.float64)
     n = len(pos)
     rows = np.arange(n) if rows is None else np.asarray(rows)
     out = np.zeros((len(rows), 3))
     for k, i in enumerate(rows):
         r = pos[i] - pos
+        if box is not None:
+            for c, length in enumerate(box):
+                r[:, c] -= length * np.round(r[:, c] / length)
         rn = np.sqrt(np.sum(r * r, axis=1))
         ok = (np.arange(n) != i) & (rn > 0.0)
         f = force_magnitude(rn[ok], 2.0 * a, u0, b)

@@ -31,12 +31,13 @@ from . import lanczos, mobility, stochastic
 def step(pos, u_prev, w, w_tilde, *, dt, delta, lanczos_tol, lanczos_max_iter=64,
          scheme="sab", f_grav_z=-1.0, torque=(0.0, 1.0, 0.0), u0=1.0, b=0.1,
          a=1.0, eta=1.0, kT=1.0, dense=None, rfd="centred", wall=True,
-         lanczos_precond=False):
+         lanczos_precond=False, box=None):
     """Advance ``pos`` by one step.  Returns (new_pos, u_now, lanczos_iterations, eps, status).
 
     ``u_prev``: previous deterministic velocity or None (first step).  ``rfd``: "centred"
     or "one_sided" random finite difference for the drift.  ``wall=False``: free space.
-    ``lanczos_precond``: block-diagonal preconditioned Lanczos for the noise.  ``w``,
+    ``lanczos_precond``: block-diagonal preconditioned Lanczos for the noise.
+    ``box=(L_x, L_y)``: pseudo-periodic boundary conditions (App. B).  ``w``,
     ``w_tilde``: (n, 3) normal variates.  ``dense``: use dense matrices (default
     for n <= 1500).
     """
@@ -44,16 +45,16 @@ def step(pos, u_prev, w, w_tilde, *, dt, delta, lanczos_tol, lanczos_max_iter=64
     n = len(pos)
     if dense is None:
         dense = n <= 1500
-    F = forces_mod.forces(pos, a, u0, b, f_grav_z, wall=wall)
+    F = forces_mod.forces(pos, a, u0, b, f_grav_z, wall=wall, box=box)
     T = np.tile(np.asarray(torque, dtype=np.float64), (n, 1))
     if dense:
-        M, MC = mobility.dense(pos, a, eta, wall)
+        M, MC = mobility.dense(pos, a, eta, wall, box)
         u = (M @ F.ravel() + MC @ T.ravel()).reshape(n, 3)
         apply_m = lambda v: M @ v
     else:
-        u = mobility.matvec(pos, F, T, a, eta, wall=wall)
+        u = mobility.matvec(pos, F, T, a, eta, wall=wall, box=box)
         apply_m = lambda v: mobility.matvec(pos, v.reshape(n, 3), None, a, eta,
-                                            wall=wall).ravel()
+                                            wall=wall, box=box).ravel()
     if lanczos_precond:
         scale = lanczos.block_diagonal_scale(pos, a, eta, wall)
         g, iters, eps, status = lanczos.lanczos_sqrt_precond(apply_m, scale, np.asarray(w).ravel(),
@@ -62,7 +63,7 @@ def step(pos, u_prev, w, w_tilde, *, dt, delta, lanczos_tol, lanczos_max_iter=64
         g, iters, eps, status = lanczos.lanczos_sqrt(apply_m, np.asarray(w).ravel(),
                                                      lanczos_tol, lanczos_max_iter)
     rfd_fn = stochastic.rfd if rfd == "centred" else stochastic.rfd_one_sided
-    drift = rfd_fn(pos, w_tilde, delta, a, eta, kT, wall=wall)
+    drift = rfd_fn(pos, w_tilde, delta, a, eta, kT, wall=wall, box=box)
     if scheme == "em" or u_prev is None:
         det = u
     else:

@@ -22,6 +22,10 @@ the active term of Sec. III).
 Free space (``wall=False``, the contrast drawn in Sec. II.C): the unbounded RPY
 blocks alone, unclamped heights and H = 1.
 
+Pseudo-periodic boundary conditions (``box=(L_x, L_y)``, App. B): each pair block is the
+sum over the source's minimum image and its images in the eight neighbour cells, so M
+depends on the positions modulo the box only.
+
 Pinned by (tests/test_oracle_mobility.py): symmetry and positive definiteness of
 dense M (eigvalsh), zero rows for spheres at or below the wall, the textbook wall
 self-mobility series, the 1/r^3 decay of the screened pair interaction for
@@ -51,15 +55,38 @@ def regularize(pos, a, wall=True):
     return qt, H
 
 
-def pair_blocks(qi, qj, a, eta, wall=True):
+def image_offsets(box):
+    """Horizontal offsets (k_x L_x, k_y L_y, 0) of the unit cell and its eight neighbours."""
+    lx, ly = box
+    return [np.array([kx * lx, ky * ly, 0.0]) for kx in (-1, 0, 1) for ky in (-1, 0, 1)]
+
+
+def minimum_image(qi, qj, box):
+    """Sources moved by whole box lengths so that x_i - x_j and y_i - y_j lie in
+    [-L/2, L/2] (the minimum image convention of App. B).  Arrays (3, n)."""
+    qj = np.array(qj, dtype=np.float64, copy=True)
+    for c, length in enumerate(box):
+        qj[c] += length * np.round((qi[c] - qj[c]) / length)
+    return qj
+
+
+def pair_blocks(qi, qj, a, eta, wall=True, box=None):
     """Translation and translation-rotation blocks M~_ij, M~C_ij of clamped positions.
 
     ``qi``, ``qj``: arrays (3, n) of targets and sources (already clamped).
     Returns (tt, tr), each (3, 3, n), in mobility units.  ``wall=False``: the unbounded
-    RPY blocks alone (free space).
+    RPY blocks alone (free space).  ``box=(L_x, L_y)``: pseudo-periodic boundary conditions
+    of App. B, the sum over the source's minimum image and its eight neighbour-cell images.
     """
     qi = np.asarray(qi, dtype=np.float64)
     qj = np.asarray(qj, dtype=np.float64)
+    if box is not None:
+        qw = minimum_image(qi, qj, box)
+        tt, tr = 0.0, 0.0
+        for off in image_offsets(box):
+            t1, t2 = pair_blocks(qi, qw + off[:, None], a, eta, wall)
+            tt, tr = tt + t1, tr + t2
+        return tt, tr
     r = qi - qj
     tt = rpy.free_tt(r, a)
     tr = rpy.free_tr(r, a)
@@ -73,7 +100,7 @@ def pair_blocks(qi, qj, a, eta, wall=True):
 _PAIR_CHUNK = 1 << 17
 
 
-def dense(pos, a=1.0, eta=1.0, wall=True):
+def dense(pos, a=1.0, eta=1.0, wall=True, box=None):
     """Dense (3N, 3N) matrices M and M_C (FP64).  Practical for N up to ~2000."""
     qt, H = regularize(pos, a, wall)
     n = len(qt)
@@ -85,7 +112,7 @@ def dense(pos, a=1.0, eta=1.0, wall=True):
     for s in range(0, I.size, _PAIR_CHUNK):
         ii = I[s:s + _PAIR_CHUNK]
         jj = J[s:s + _PAIR_CHUNK]
-        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta, wall)
+        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta, wall, box)
         w = H[ii] * H[jj]
         M[ii, :, jj, :] = (tt * w).transpose(2, 0, 1)
         MC[ii, :, jj, :] = (tr * w).transpose(2, 0, 1)
@@ -93,7 +120,7 @@ def dense(pos, a=1.0, eta=1.0, wall=True):
 
 
 def _rows_product(args):
-    rows, qt, H, force, torque, a, eta, wall = args
+    rows, qt, H, force, torque, a, eta, wall, box = args
     n = len(qt)
     out = np.zeros((len(rows), 3))
     step = max(1, _PAIR_CHUNK // n)
@@ -101,7 +128,7 @@ def _rows_product(args):
         blk = rows[s:s + step]
         ii = np.repeat(blk, n)
         jj = np.tile(np.arange(n), len(blk))
-        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta, wall)
+        tt, tr = pair_blocks(qt[ii].T, qt[jj].T, a, eta, wall, box)
         acc = np.zeros((3, len(ii)))
         if force is not None:
             acc += np.einsum("abk,kb->ak", tt, force[jj])
@@ -112,7 +139,8 @@ def _rows_product(args):
     return out
 
 
-def matvec(pos, force=None, torque=None, a=1.0, eta=1.0, rows=None, workers=1, wall=True):
+def matvec(pos, force=None, torque=None, a=1.0, eta=1.0, rows=None, workers=1, wall=True,
+           box=None):
     """U = M F + M_C T by direct summation over all sources (matrix-free).
 
     ``rows``: optional indices of the target spheres to evaluate (row sampling);
@@ -127,19 +155,19 @@ def matvec(pos, force=None, torque=None, a=1.0, eta=1.0, rows=None, workers=1, w
     if rows.size == 0:
         return np.zeros((0, 3))
     if workers <= 1:
-        return _rows_product((rows, qt, H, force, torque, a, eta, wall))
+        return _rows_product((rows, qt, H, force, torque, a, eta, wall, box))
     # compile the lambdified tensors before forking so the children inherit them
     pair_blocks(qt[:1].T, qt[:1].T, a, eta, wall)
     parts = np.array_split(rows, min(workers * 4, rows.size))
     with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
-        res = list(ex.map(_rows_product, [(p, qt, H, force, torque, a, eta, wall)
+        res = list(ex.map(_rows_product, [(p, qt, H, force, torque, a, eta, wall, box)
                                           for p in parts]))
     return np.vstack(res)
 
 
-def dense_matvec(pos, force=None, torque=None, a=1.0, eta=1.0, wall=True):
+def dense_matvec(pos, force=None, torque=None, a=1.0, eta=1.0, wall=True, box=None):
     """U = M F + M_C T through the dense matrices (small N)."""
-    M, MC = dense(pos, a, eta, wall)
+    M, MC = dense(pos, a, eta, wall, box)
     n = len(pos)
     u = np.zeros(3 * n)
     if force is not None:

@@ -33,19 +33,20 @@ import numpy as np
 from . import faxen, mobility, rpy
 
 
-def rfd(pos, w_tilde, delta, a=1.0, eta=1.0, kT=1.0, rows=None, workers=1, wall=True):
+def rfd(pos, w_tilde, delta, a=1.0, eta=1.0, kT=1.0, rows=None, workers=1, wall=True,
+        box=None):
     """Centred random finite difference (kT/delta)[M(q+)W~ - M(q-)W~], shape (n, 3)."""
     pos = np.asarray(pos, dtype=np.float64)
     wt = np.asarray(w_tilde, dtype=np.float64).reshape(pos.shape)
     qp = pos + 0.5 * delta * wt
     qm = pos - 0.5 * delta * wt
-    up = mobility.matvec(qp, wt, None, a, eta, rows=rows, workers=workers, wall=wall)
-    um = mobility.matvec(qm, wt, None, a, eta, rows=rows, workers=workers, wall=wall)
+    up = mobility.matvec(qp, wt, None, a, eta, rows=rows, workers=workers, wall=wall, box=box)
+    um = mobility.matvec(qm, wt, None, a, eta, rows=rows, workers=workers, wall=wall, box=box)
     return (kT / delta) * (up - um)
 
 
 def rfd_one_sided(pos, w_tilde, delta, a=1.0, eta=1.0, kT=1.0, rows=None, workers=1,
-                  wall=True):
+                  wall=True, box=None):
     """One-sided random finite difference (kT/delta)[M(q + delta W~)W~ - M(q)W~], shape (n, 3).
 
     Sec. II.A allows a one-sided difference in place of the centred one; it equals
@@ -53,8 +54,8 @@ def rfd_one_sided(pos, w_tilde, delta, a=1.0, eta=1.0, kT=1.0, rows=None, worker
     pos = np.asarray(pos, dtype=np.float64)
     wt = np.asarray(w_tilde, dtype=np.float64).reshape(pos.shape)
     up = mobility.matvec(pos + delta * wt, wt, None, a, eta, rows=rows, workers=workers,
-                         wall=wall)
-    u0 = mobility.matvec(pos, wt, None, a, eta, rows=rows, workers=workers, wall=wall)
+                         wall=wall, box=box)
+    u0 = mobility.matvec(pos, wt, None, a, eta, rows=rows, workers=workers, wall=wall, box=box)
     return (kT / delta) * (up - u0)
 
 

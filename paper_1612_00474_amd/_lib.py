@@ -34,7 +34,7 @@ EXPORTS = (
 
 class RpbParams(C.Structure):
     _fields_ = [("a", C.c_double), ("eta", C.c_double), ("kT", C.c_double), ("precision", C.c_int),
-                ("wall", C.c_int)]
+                ("wall", C.c_int), ("lx", C.c_double), ("ly", C.c_double)]
 
 
 class RpbSabConfig(C.Structure):
@@ -185,7 +185,7 @@ class Context:
     """One librpb context on one device (not thread-safe; one per host thread)."""
 
     def __init__(self, device: int = 0, a: float = 1.0, eta: float = 1.0, kT: float = 1.0,
-                 wall: bool = True):
+                 wall: bool = True, box=None):
         import torch
         # torch owns the device memory and streams this library works on: its HIP runtime
         # must be initialised before the library's first HIP call
@@ -199,6 +199,7 @@ class Context:
         self.device = device
         self.a, self.eta, self.kT = a, eta, kT
         self.wall = wall          # False: free space (unbounded RPY, no wall force)
+        self.box = box            # (L_x, L_y): pseudo-periodic boundaries, single systems
 
     def close(self):
         if getattr(self, "h", None):
@@ -212,8 +213,9 @@ class Context:
             pass
 
     def params(self, precision="fp64"):
+        lx, ly = self.box if self.box is not None else (0.0, 0.0)
         return RpbParams(self.a, self.eta, self.kT, PRECISIONS[precision] if isinstance(precision, str)
-                         else int(precision), int(bool(self.wall)))
+                         else int(precision), int(bool(self.wall)), float(lx), float(ly))
 
     def _check(self, st, ok=(RPB_OK,)):
         if st not in ok:

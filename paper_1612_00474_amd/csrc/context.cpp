@@ -1,4 +1,5 @@
 // Context, workspace, error reporting and timing for librpb.
+#include <cmath>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
@@ -54,6 +55,9 @@ int check_params(rpb_ctx *ctx, const rpb_params *p) {
   if (p->precision != RPB_FP64 && p->precision != RPB_MIXED)
     return fail(ctx, RPB_EINVAL, "unknown precision %d", p->precision);
   if (p->wall != 0 && p->wall != 1) return fail(ctx, RPB_EINVAL, "wall must be 0 or 1");
+  const bool box = p->lx > 0.0 && p->ly > 0.0 && std::isfinite(p->lx) && std::isfinite(p->ly);
+  if (!box && !(p->lx == 0.0 && p->ly == 0.0))
+    return fail(ctx, RPB_EINVAL, "box lengths must both be positive and finite, or both 0");
   return RPB_OK;
 }
 

@@ -3,10 +3,10 @@
 // U(r) = U0 + U0 (d - r)/b for r < d and U0 exp(-(r - d)/b) for r >= d, with d = 2a and r
 // the centre distance for sphere pairs, d = a and r = z for the wall (absent in free space);
 // the force is -grad U, magnitude U0/b or (U0/b) exp(-(r - d)/b), repulsive.  Gravity adds
-// f_g along z.  Pairs
-// farther than d + 40 b are skipped (their force is below 4.3e-18 U0/b).  Brute-force
-// O(N^2) distance tests over LDS tiles, float64 throughout, unclamped positions; the sources
-// are split over workgroups and the chunk sums added in a fixed order (deterministic).
+// f_g along z.  Pairs farther than d + 40 b are skipped (their force is below 4.3e-18 U0/b).
+// Brute-force O(N^2) distance tests over LDS tiles, float64 throughout, unclamped positions,
+// minimum-image separations in a pseudo-periodic box (App. B); the sources are split over
+// workgroups and the chunk sums added in a fixed order (deterministic).
 #include <algorithm>
 #include <cmath>
 
@@ -24,9 +24,9 @@ constexpr int kMinWorkgroups = 2048;   // source chunks are added until the grid
 template <int KT>
 __device__ __forceinline__ void steric_accumulate(const double *__restrict__ pos, int64_t t0,
                                                   int64_t t1, int64_t s0, int64_t s1, double a,
-                                                  double u0, double b, double (&f)[KT][3],
-                                                  const double (&tq)[KT][3], double *sx,
-                                                  double *sy, double *sz) {
+                                                  double u0, double b, double lx, double ly,
+                                                  double (&f)[KT][3], const double (&tq)[KT][3],
+                                                  double *sx, double *sy, double *sz) {
   const int tid = threadIdx.x;
   const double d = 2.0 * a;
   const double cut = d + 40.0 * b;
@@ -51,6 +51,10 @@ __device__ __forceinline__ void steric_accumulate(const double *__restrict__ pos
       for (int q = 0; q < KT; ++q) {
         dx[q] = tq[q][0] - xj;
         dy[q] = tq[q][1] - yj;
+        if (lx > 0.0) {   // pseudo-periodic box: minimum image
+          dx[q] -= lx * rint(dx[q] / lx);
+          dy[q] -= ly * rint(dy[q] / ly);
+        }
         dz[q] = tq[q][2] - zj;
         r2[q] = dx[q] * dx[q] + dy[q] * dy[q] + dz[q] * dz[q];
         hit |= r2[q] < cut2;
@@ -78,7 +82,8 @@ __device__ __forceinline__ void steric_accumulate(const double *__restrict__ pos
 template <int KT, bool FINAL>
 __device__ __forceinline__ void steric_tile(const double *__restrict__ pos, int64_t t0, int64_t t1,
                                             int64_t s0, int64_t s1, double a, double u0, double b,
-                                            double f_grav_z, int wall, double *__restrict__ out) {
+                                            double lx, double ly, double f_grav_z, int wall,
+                                            double *__restrict__ out) {
   __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
   const int tid = threadIdx.x;
   double f[KT][3], tq[KT][3];
@@ -92,7 +97,7 @@ __device__ __forceinline__ void steric_tile(const double *__restrict__ pos, int6
       f[q][c] = 0.0;
     }
   }
-  steric_accumulate<KT>(pos, t0, t1, s0, s1, a, u0, b, f, tq, sx, sy, sz);
+  steric_accumulate<KT>(pos, t0, t1, s0, s1, a, u0, b, lx, ly, f, tq, sx, sy, sz);
 #pragma unroll
   for (int q = 0; q < KT; ++q) {
     const int64_t i = t0 + q * kBlock + tid;
@@ -116,12 +121,13 @@ __device__ __forceinline__ void steric_tile(const double *__restrict__ pos, int6
 template <int KT, bool FINAL>
 __global__ __launch_bounds__(kBlock) void steric_kernel(int64_t n, int64_t chunk,
                                                         const double *__restrict__ pos, double a,
-                                                        double u0, double b, double f_grav_z,
-                                                        int wall, double *__restrict__ out) {
+                                                        double u0, double b, double lx, double ly,
+                                                        double f_grav_z, int wall,
+                                                        double *__restrict__ out) {
   const int64_t t0 = int64_t(blockIdx.x) * kBlock * KT;
   const int64_t s0 = int64_t(blockIdx.y) * chunk;
   const int64_t s1 = min(n, s0 + chunk);
-  steric_tile<KT, FINAL>(pos, t0, n, s0, s1, a, u0, b, f_grav_z, wall,
+  steric_tile<KT, FINAL>(pos, t0, n, s0, s1, a, u0, b, lx, ly, f_grav_z, wall,
                          out + 3 * n * blockIdx.y);
 }
 
@@ -153,8 +159,8 @@ __global__ __launch_bounds__(kBlock) void steric_kernel_batched(const int64_t *_
                                                                 double *__restrict__ force) {
   const int2 tl = tiles[blockIdx.x];
   const int64_t s0 = offs[tl.x], s1 = offs[tl.x + 1];
-  steric_tile<1, true>(pos, s0 + int64_t(tl.y) * kBlock, s1, s0, s1, a, u0, b, f_grav_z, wall,
-                       force);
+  steric_tile<1, true>(pos, s0 + int64_t(tl.y) * kBlock, s1, s0, s1, a, u0, b, 0.0, 0.0, f_grav_z,
+                       wall, force);
 }
 
 }  // namespace
@@ -171,6 +177,10 @@ int forces_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const
 int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, double f_grav_z,
                double u0, double b, double *force, hipStream_t stream) {
   if (n <= 0) return RPB_OK;
+  const double cut = 2.0 * p->a + 40.0 * b;
+  if (p->lx > 0.0 && (p->lx <= 2.0 * cut || p->ly <= 2.0 * cut))
+    return fail(ctx, RPB_EINVAL, "box %g x %g too small for the minimum image (need > %g)", p->lx,
+                p->ly, 2.0 * cut);
   constexpr int kTargets = 2;
   const int64_t per = int64_t(kBlock) * kTargets;
   const int64_t tiles = (n + per - 1) / per;
@@ -182,7 +192,7 @@ int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, 
   if (tiles > 0x7fffffff) return fail(ctx, RPB_EINVAL, "too many spheres");
   if (nchunks == 1) {
     steric_kernel<kTargets, true><<<dim3{unsigned(tiles), 1u, 1u}, kBlock, 0, stream>>>(
-        n, chunk, pos, p->a, u0, b, f_grav_z, p->wall, force);
+        n, chunk, pos, p->a, u0, b, p->lx, p->ly, f_grav_z, p->wall, force);
     RPB_LAUNCHED(ctx);
     return RPB_OK;
   }
@@ -191,7 +201,8 @@ int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, 
       workspace(ctx, WS_PART, size_t(nchunks) * 3 * size_t(n) * sizeof(double), &st));
   if (!part) return st;
   steric_kernel<kTargets, false><<<dim3{unsigned(tiles), unsigned(nchunks), 1u}, kBlock, 0,
-                                   stream>>>(n, chunk, pos, p->a, u0, b, f_grav_z, p->wall, part);
+                                   stream>>>(n, chunk, pos, p->a, u0, b, p->lx, p->ly, f_grav_z,
+                                             p->wall, part);
   RPB_LAUNCHED(ctx);
   const int64_t elems = 3 * n;
   steric_finish<<<unsigned((elems + kBlock - 1) / kBlock), kBlock, 0, stream>>>(

@@ -737,6 +737,8 @@ extern "C" int lanczos_sqrt_apply_batched(rpb_ctx *ctx, const rpb_params *p, int
                                           int *iters_out, double *eps_out, rpb_stream_t stream_) {
   RPB_TRY(check_params(ctx, p));
   RPB_TRY(check_offsets(ctx, nsys, offs));
+  if (p->lx > 0.0)
+    return fail(ctx, RPB_EINVAL, "pseudo-periodic boundaries are supported for single systems");
   if (nsys > kMaxBatchSystems)
     return fail(ctx, RPB_EINVAL, "at most %d systems per batch", kMaxBatchSystems);
   if (!(tol > 0.0)) return fail(ctx, RPB_EINVAL, "tol must be > 0");

@@ -159,7 +159,7 @@ __device__ __forceinline__ void load_targets(const GeomF &g, int64_t first, int6
 
 // Accumulate sources [jb, je) into the lane's targets.  `n` is the stride of the source
 // arrays.  Every lane of the workgroup must call this (it synchronises).
-template <bool TORQUE, int TPT, bool WALL>
+template <bool TORQUE, int TPT, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sources_f64(const GeomD &g, const double *__restrict__ src,
                                             int64_t n, int64_t jb, int64_t je,
                                             const PairConsts<double> &k, LdsD<TORQUE> &L,
@@ -192,19 +192,21 @@ __device__ __forceinline__ void sources_f64(const GeomD &g, const double *__rest
       // pairs closer than 2a (rare) and the self pair take the complete form
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
-        const double dx = T.x[q] - xj, dy = T.y[q] - yj, dz = T.z[q] - zj;
-        if (dx * dx + dy * dy + dz * dz < k.four_a2)
-          pair_velocity<double, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, T.u[q][0],
-                                        T.u[q][1], T.u[q][2]);
-        else
-          pair_velocity<double, TORQUE, true, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
-                                              T.u[q][0], T.u[q][1], T.u[q][2]);
+        for_images<PERIODIC>(T.x[q] - xj, T.y[q] - yj, k, [&](double dx, double dy) {
+          const double dz = T.z[q] - zj;
+          if (dx * dx + dy * dy + dz * dz < k.four_a2)
+            pair_velocity<double, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty,
+                                                       tz, k, T.u[q][0], T.u[q][1], T.u[q][2]);
+          else
+            pair_velocity<double, TORQUE, true, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty,
+                                                      tz, k, T.u[q][0], T.u[q][1], T.u[q][2]);
+        });
       }
     }
   }
 }
 
-template <bool TORQUE, int TPT, bool WALL>
+template <bool TORQUE, int TPT, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__restrict__ src,
                                               int64_t n, int64_t jb, int64_t je,
                                               const PairConsts<float> &k, LdsF<TORQUE> &L,
@@ -242,15 +244,17 @@ __device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__res
       // pairs closer than 2a (rare) and the self pair take the complete form
 #pragma unroll
       for (int q = 0; q < TPT; ++q) {
-        const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
-        const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-        const float dz = T.z[q] - zj;
-        if (dx * dx + dy * dy + dz * dz < k.four_a2)
-          pair_velocity<float, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k, a[q][0],
-                                       a[q][1], a[q][2]);
-        else
-          pair_velocity<float, TORQUE, true, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz, k,
-                                             a[q][0], a[q][1], a[q][2]);
+        const float dx0 = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+        const float dy0 = (T.yh[q] - yjh) + (T.yl[q] - yjl);
+        for_images<PERIODIC>(dx0, dy0, k, [&](float dx, float dy) {
+          const float dz = T.z[q] - zj;
+          if (dx * dx + dy * dy + dz * dz < k.four_a2)
+            pair_velocity<float, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz,
+                                                      k, a[q][0], a[q][1], a[q][2]);
+          else
+            pair_velocity<float, TORQUE, true, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz,
+                                                     k, a[q][0], a[q][1], a[q][2]);
+        });
       }
     }
 #pragma unroll
@@ -301,7 +305,7 @@ struct PairArgs {
   int64_t chunk;    // sources per workgroup (multiple of kBlock)
 };
 
-template <bool TORQUE, int TPT, bool WALL>
+template <bool TORQUE, int TPT, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g,
                                                           const double *__restrict__ src,
                                                           PairConsts<double> k,
@@ -312,11 +316,12 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g
   const int64_t end = args.row0 + args.nrows;
   load_targets<TPT>(g, first, end, args.row0, T);
   const int64_t jb = int64_t(blockIdx.y) * args.chunk;
-  sources_f64<TORQUE, TPT, WALL>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
+  sources_f64<TORQUE, TPT, WALL, PERIODIC>(g, src, args.n, jb, min(args.n, jb + args.chunk), k,
+                                           L, T);
   store_partial<TPT>(T, first, end, blockIdx.y, args.nrows, args.row0, partial);
 }
 
-template <bool TORQUE, int TPT, bool WALL>
+template <bool TORQUE, int TPT, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF g,
                                                             const float *__restrict__ src,
                                                             PairConsts<float> k,
@@ -327,7 +332,8 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
   const int64_t end = args.row0 + args.nrows;
   load_targets<TPT>(g, first, end, args.row0, T);
   const int64_t jb = int64_t(blockIdx.y) * args.chunk;
-  sources_mixed<TORQUE, TPT, WALL>(g, src, args.n, jb, min(args.n, jb + args.chunk), k, L, T);
+  sources_mixed<TORQUE, TPT, WALL, PERIODIC>(g, src, args.n, jb, min(args.n, jb + args.chunk), k,
+                                             L, T);
   store_partial<TPT>(T, first, end, blockIdx.y, args.nrows, args.row0, partial);
 }
 
@@ -402,7 +408,7 @@ __device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, in
 // its targets against source j (weighted force zero when !valid), adding M_ij F_j into acc and
 // M_ij^T F_i into cs.  Pairs at least 2a apart use the far-field form alone; closer pairs (rare
 // in a suspension) the complete form, so each pair's value depends on its own geometry only.
-template <int TPT, bool TORQUE, bool WALL>
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sym_step(const LdsF<TORQUE> &L, int j, bool valid,
                                          const TargetsF<TPT> &T, const float (&own)[TPT][6],
                                          const PairConsts<float> &k, float (&acc)[TPT][3],
@@ -420,21 +426,25 @@ __device__ __forceinline__ void sym_step(const LdsF<TORQUE> &L, int j, bool vali
   for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
-    const float dx = (T.xh[q] - xjh) + (T.xl[q] - xjl);
-    const float dy = (T.yh[q] - yjh) + (T.yl[q] - yjl);
-    const float dz = T.z[q] - zj;
-    if (dx * dx + dy * dy + dz * dz < k.four_a2)
-      pair_velocity_sym<float, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
-                                              own[q][1], own[q][2], k, acc[q][0], acc[q][1],
-                                              acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
-    else
-      pair_velocity_sym<float, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
-                                             own[q][1], own[q][2], k, acc[q][0], acc[q][1],
-                                             acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
+    const float dx0 = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+    const float dy0 = (T.yh[q] - yjh) + (T.yl[q] - yjl);
+    for_images<PERIODIC>(dx0, dy0, k, [&](float dx, float dy) {
+      const float dz = T.z[q] - zj;
+      if (dx * dx + dy * dy + dz * dz < k.four_a2)
+        pair_velocity_sym<float, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                                      own[q][1], own[q][2], k, acc[q][0],
+                                                      acc[q][1], acc[q][2], cs[0], cs[1], cs[2],
+                                                      tq, own[q] + 3);
+      else
+        pair_velocity_sym<float, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                                     own[q][1], own[q][2], k, acc[q][0],
+                                                     acc[q][1], acc[q][2], cs[0], cs[1], cs[2], tq,
+                                                     own[q] + 3);
+    });
   }
 }
 
-template <int TPT, bool TORQUE, bool WALL>
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sym_step(const LdsD<TORQUE> &L, int j, bool valid,
                                          const TargetsD<TPT> &T, const double (&own)[TPT][6],
                                          const PairConsts<double> &k, double (&acc)[TPT][3],
@@ -451,15 +461,19 @@ __device__ __forceinline__ void sym_step(const LdsD<TORQUE> &L, int j, bool vali
   for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
 #pragma unroll
   for (int q = 0; q < TPT; ++q) {
-    const double dx = T.x[q] - xj, dy = T.y[q] - yj, dz = T.z[q] - zj;
-    if (dx * dx + dy * dy + dz * dz < k.four_a2)
-      pair_velocity_sym<double, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
-                                               own[q][1], own[q][2], k, acc[q][0], acc[q][1],
-                                               acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
-    else
-      pair_velocity_sym<double, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
-                                              own[q][1], own[q][2], k, acc[q][0], acc[q][1],
-                                              acc[q][2], cs[0], cs[1], cs[2], tq, own[q] + 3);
+    for_images<PERIODIC>(T.x[q] - xj, T.y[q] - yj, k, [&](double dx, double dy) {
+      const double dz = T.z[q] - zj;
+      if (dx * dx + dy * dy + dz * dz < k.four_a2)
+        pair_velocity_sym<double, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                                       own[q][1], own[q][2], k, acc[q][0],
+                                                       acc[q][1], acc[q][2], cs[0], cs[1], cs[2],
+                                                       tq, own[q] + 3);
+      else
+        pair_velocity_sym<double, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
+                                                      own[q][1], own[q][2], k, acc[q][0],
+                                                      acc[q][1], acc[q][2], cs[0], cs[1], cs[2],
+                                                      tq, own[q] + 3);
+    });
   }
 }
 
@@ -486,7 +500,7 @@ inline __device__ GeomD offset_geom(const GeomD &g, int64_t s0) {
 
 // Tile pair (I, J), I <= J, of one system: `g`, `src` and `partial` already point at the
 // system's first sphere and first partial slot.  Every lane of the workgroup must call this.
-template <int TPT, bool TORQUE, bool WALL>
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
                                               const float *__restrict__ src,
                                               const PairConsts<float> &k,
@@ -500,7 +514,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_mixed<TORQUE, TPT, WALL>(g, src, a.stride, jb, je, k, L, T);
+    sources_mixed<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -539,11 +553,13 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
       if (nb == 64) {
 #pragma unroll 2
         for (int step = 0; step < 64; ++step)
-          sym_step<TPT, TORQUE, WALL>(L, blk + ((lane + step) & 63), true, T, own, k, acc, cs);
+          sym_step<TPT, TORQUE, WALL, PERIODIC>(L, blk + ((lane + step) & 63), true, T, own, k,
+                                                acc, cs);
       } else {
         for (int step = 0; step < 64; ++step) {
           const int sl = (lane + step) & 63;
-          sym_step<TPT, TORQUE, WALL>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, acc, cs);
+          sym_step<TPT, TORQUE, WALL, PERIODIC>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k,
+                                                acc, cs);
         }
       }
       const int sl = (lane + 63) & 63;
@@ -579,7 +595,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
   }
 }
 
-template <int TPT, bool TORQUE, bool WALL>
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
                                               const double *__restrict__ src,
                                               const PairConsts<double> &k,
@@ -593,7 +609,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
   load_targets<TPT>(g, first, n, first, T);
   const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
   if (I == J) {
-    sources_f64<TORQUE, TPT, WALL>(g, src, a.stride, jb, je, k, L, T);
+    sources_f64<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -626,11 +642,13 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
       if (nb == 64) {
 #pragma unroll 2
         for (int step = 0; step < 64; ++step)
-          sym_step<TPT, TORQUE, WALL>(L, blk + ((lane + step) & 63), true, T, own, k, T.u, cs);
+          sym_step<TPT, TORQUE, WALL, PERIODIC>(L, blk + ((lane + step) & 63), true, T, own, k,
+                                                T.u, cs);
       } else {
         for (int step = 0; step < 64; ++step) {
           const int sl = (lane + step) & 63;
-          sym_step<TPT, TORQUE, WALL>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k, T.u, cs);
+          sym_step<TPT, TORQUE, WALL, PERIODIC>(L, blk + (sl < nb ? sl : 0), sl < nb, T, own, k,
+                                                T.u, cs);
         }
       }
       const int sl = (lane + 63) & 63;
@@ -661,7 +679,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
   }
 }
 
-template <int TPT, bool TORQUE, bool WALL>
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
                                                                 const float *__restrict__ src,
                                                                 PairConsts<float> k,
@@ -670,10 +688,10 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
   __shared__ float col[kWaves][kBlock][3];
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE, WALL>(a, g, src, k, partial, I, J, L, col);
+  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, L, col);
 }
 
-template <int TPT, bool TORQUE, bool WALL>
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g,
                                                               const double *__restrict__ src,
                                                               PairConsts<double> k,
@@ -682,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
   __shared__ double col[kWaves][kBlock][3];
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE, WALL>(a, g, src, k, partial, I, J, L, col);
+  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, L, col);
 }
 
 __global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
@@ -736,7 +754,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_batched(BatchArgs b, G
     const int64_t first = s0 + int64_t(w.y) * (kBlock * TPT);
     load_targets<TPT>(g, first, s1, s0, T);
     const int64_t jb = s0 + int64_t(w.z) * b.chunk;
-    sources_f64<TORQUE, TPT, WALL>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
+    sources_f64<TORQUE, TPT, WALL, false>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
     store_partial<TPT>(T, first, s1, w.z, b.n, 0, partial);
   }
 }
@@ -756,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_batched(BatchArgs b,
     const int64_t first = s0 + int64_t(w.y) * (kBlock * TPT);
     load_targets<TPT>(g, first, s1, s0, T);
     const int64_t jb = s0 + int64_t(w.z) * b.chunk;
-    sources_mixed<TORQUE, TPT, WALL>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
+    sources_mixed<TORQUE, TPT, WALL, false>(g, src, b.n, jb, min(s1, jb + b.chunk), k, L, T);
     store_partial<TPT>(T, first, s1, w.z, b.n, 0, partial);
   }
 }
@@ -817,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
-    sym_tile_pair<TPT, TORQUE, WALL>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
+    sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
                                partial + b.part_base[w.x], w.y, w.z, L, col);
   }
 }
@@ -833,7 +851,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
-    sym_tile_pair<TPT, TORQUE, WALL>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
+    sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
                                partial + b.part_base[w.x], w.y, w.z, L, col);
   }
 }
@@ -896,19 +914,25 @@ __global__ void self_scale(int64_t n, Geom g, PairConsts<double> k, double inv8p
   scale[3 * i + 2] = dperp > 0.0 ? sqrt(dperp) : 1.0;
 }
 
-// Calls fn(torque, tpt, wall) with the three as std::integral_constant values, so each
-// launch site names its kernel template once.
+// Calls fn(torque, tpt, wall, periodic) with the four as std::integral_constant values, so
+// each launch site names its kernel template once.
 template <typename Fn>
-void with_variant(bool torque, int tpt, bool wall, Fn &&fn) {
+void with_variant(bool torque, int tpt, bool wall, bool periodic, Fn &&fn) {
   using T1 = std::true_type;
   using T0 = std::false_type;
   using P2 = std::integral_constant<int, 2>;
   using P1 = std::integral_constant<int, 1>;
+  auto by_box = [&](auto t, auto q, auto w) {
+    if (periodic)
+      fn(t, q, w, T1{});
+    else
+      fn(t, q, w, T0{});
+  };
   auto by_wall = [&](auto t, auto q) {
     if (wall)
-      fn(t, q, T1{});
+      by_box(t, q, T1{});
     else
-      fn(t, q, T0{});
+      by_box(t, q, T0{});
   };
   if (torque) {
     if (tpt == 2)
@@ -922,6 +946,8 @@ void with_variant(bool torque, int tpt, bool wall, Fn &&fn) {
       by_wall(T0{}, P1{});
   }
 }
+
+inline bool periodic(const rpb_params *p) { return p->lx > 0.0; }
 
 int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const double *torque,
                  void **src, hipStream_t stream) {
@@ -1020,15 +1046,17 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
   const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2);
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
-  with_variant(torque, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
-    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
+  with_variant(torque, tpt, p->wall != 0, periodic(p), [&](auto T, auto P, auto W, auto B) {
+    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value, kB = decltype(B)::value;
     constexpr int kP = decltype(P)::value;
     if (f64)
-      pair_kernel_f64_sym<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
-          a, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a), part);
+      pair_kernel_f64_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
+          a, geom_d(g), static_cast<const double *>(src),
+          make_pair_consts<double>(p->a, p->lx, p->ly), part);
     else
-      pair_kernel_mixed_sym<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
-          a, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+      pair_kernel_mixed_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
+          a, geom_f(g), static_cast<const float *>(src),
+          make_pair_consts<float>(p->a, p->lx, p->ly), part);
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), (f64 ? 0 : 2) + (torque ? 1 : 0)));
@@ -1076,16 +1104,17 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   const dim3 grid{unsigned(tiles), unsigned(nchunks), 1u};
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
-  with_variant(has_t, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
-    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
+  with_variant(has_t, tpt, p->wall != 0, periodic(p), [&](auto T, auto P, auto W, auto B) {
+    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value, kB = decltype(B)::value;
     constexpr int kP = decltype(P)::value;
     if (f64)
-      pair_kernel_f64<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a),
-          part);
+      pair_kernel_f64<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
+          args, geom_d(g), static_cast<const double *>(src),
+          make_pair_consts<double>(p->a, p->lx, p->ly), part);
     else
-      pair_kernel_mixed<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+      pair_kernel_mixed<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
+          args, geom_f(g), static_cast<const float *>(src),
+          make_pair_consts<float>(p->a, p->lx, p->ly), part);
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(nrows) * double(n),
@@ -1221,7 +1250,7 @@ int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const 
   }
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
-  with_variant(has_t, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
+  with_variant(has_t, tpt, p->wall != 0, false, [&](auto T, auto P, auto W, auto) {
     constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
     constexpr int kP = decltype(P)::value;
     if (f64)
@@ -1277,7 +1306,7 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
   const int tpt = b.tpt;
-  with_variant(has_t, tpt, p->wall != 0, [&](auto T, auto P, auto W) {
+  with_variant(has_t, tpt, p->wall != 0, false, [&](auto T, auto P, auto W, auto) {
     constexpr bool kT = decltype(T)::value, kW = decltype(W)::value;
     constexpr int kP = decltype(P)::value;
     if (f64)
@@ -1358,6 +1387,8 @@ int rpb_mobility_matvec_batched(rpb_ctx *ctx, const rpb_params *p, int32_t nsys,
                                 const double *torque, double *vel_out, rpb_stream_t stream_) {
   RPB_TRY(check_params(ctx, p));
   RPB_TRY(check_offsets(ctx, nsys, offs));
+  if (p->lx > 0.0)
+    return fail(ctx, RPB_EINVAL, "pseudo-periodic boundaries are supported for single systems");
   const int64_t n = offs[nsys];
   if (n == 0) return RPB_OK;
   if (!pos || !vel_out) return fail(ctx, RPB_EINVAL, "pos and vel_out must not be NULL");

@@ -52,11 +52,18 @@ struct PairConsts {
   Real near_rr;     // 4/(3a) * 3/(32a)
   Real near_t;      // 1/(2a^3)
   Real near_t_r;    // 1/(2a^3) * 3/(8a)
+  Real lx, ly;      // pseudo-periodic box (used by the PERIODIC kernels only)
+  Real ilx, ily;    // 1/lx, 1/ly
 };
 
 template <typename Real>
-__host__ __device__ inline PairConsts<Real> make_pair_consts(double a) {
+__host__ __device__ inline PairConsts<Real> make_pair_consts(double a, double lx = 0.0,
+                                                              double ly = 0.0) {
   PairConsts<Real> k;
+  k.lx = Real(lx);
+  k.ly = Real(ly);
+  k.ilx = lx > 0.0 ? Real(1.0 / lx) : Real(0);
+  k.ily = ly > 0.0 ? Real(1.0 / ly) : Real(0);
   k.a2 = Real(a * a);
   k.four_a2 = Real(4.0 * a * a);
   k.near_i = Real(4.0 / (3.0 * a));
@@ -366,6 +373,26 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
       pz += (iR2 * sv) * (wz + Real(6) * hi * ez);
     }
   }
+}
+
+__device__ __forceinline__ float round_nearest(float x) { return __builtin_rintf(x); }
+__device__ __forceinline__ double round_nearest(double x) { return __builtin_rint(x); }
+
+// Calls f(dx', dy') for the pair separation: once as given, or, with pseudo-periodic
+// boundaries (App. B), for the minimum image (|dx|, |dy| <= L/2) and its images in the eight
+// neighbour cells.
+template <bool PERIODIC, typename Real, typename F>
+__device__ __forceinline__ void for_images(Real dx, Real dy, const PairConsts<Real> &k, F &&f) {
+  if (!PERIODIC) {
+    f(dx, dy);
+    return;
+  }
+  dx -= k.lx * round_nearest(dx * k.ilx);
+  dy -= k.ly * round_nearest(dy * k.ily);
+#pragma unroll
+  for (int ix = -1; ix <= 1; ++ix)
+#pragma unroll
+    for (int iy = -1; iy <= 1; ++iy) f(dx + Real(ix) * k.lx, dy + Real(iy) * k.ly);
 }
 
 }  // namespace rpb

@@ -236,6 +236,8 @@ extern "C" int sab_step_batched(rpb_ctx *ctx, const rpb_params *p, const rpb_sab
   RPB_TRY(check_params(ctx, p));
   RPB_TRY(check_step_config(ctx, cfg));
   RPB_TRY(check_offsets(ctx, nsys, offs));
+  if (p->lx > 0.0)
+    return fail(ctx, RPB_EINVAL, "pseudo-periodic boundaries are supported for single systems");
   if (nsys > kMaxBatchSystems)
     return fail(ctx, RPB_EINVAL, "at most %d systems per batch", kMaxBatchSystems);
   const int64_t n = offs[nsys];

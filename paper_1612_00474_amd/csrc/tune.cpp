@@ -94,6 +94,8 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
                  rpb_stream_t stream_) {
   RPB_TRY(check_params(ctx, p));
   RPB_TRY(check_offsets(ctx, nsys, offs));
+  if (nsys > 1 && p->lx > 0.0)
+    return fail(ctx, RPB_EINVAL, "pseudo-periodic boundaries are supported for single systems");
   if (reps < 1 || reps > 100) return fail(ctx, RPB_EINVAL, "reps must be in [1, 100]");
   const int64_t n = offs[nsys];
   if (n == 0) return fail(ctx, RPB_EINVAL, "nothing to tune");

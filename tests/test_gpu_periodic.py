@@ -1,0 +1,90 @@
+"""Pseudo-periodic boundary conditions (App. B: forces by the minimum image convention,
+hydrodynamics over the unit cell and its eight neighbour cells): GPU parity against the
+oracle's box option, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import forces, integrator, mobility
+from tests.gpu_util import dev, host, rel2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+BOX = (40.0, 30.0)
+FP64_TOL, MIXED_TOL = 1e-12, 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_1612_00474_amd import Context
+    c = Context(0, box=BOX)
+    yield c
+    c.close()
+
+
+def _boxed(n, seed):
+    rng = np.random.default_rng(seed)
+    pos = np.column_stack([rng.uniform(0, BOX[0], n), rng.uniform(0, BOX[1], n),
+                           rng.uniform(1.05, 2.5, n)])
+    pos[0] = [0.4, 15.0, 1.3]                  # a pair across the x edge
+    pos[1] = [BOX[0] - 0.7, 15.6, 1.5]
+    pos[2] = [10.0, -0.3, 1.2]                 # a pair across the y edge, one outside the box
+    pos[3] = [10.5, BOX[1] + 0.5, 1.4]
+    pos[4, 0] += 2 * BOX[0]                    # far outside: only its image matters
+    pos[5, 2] = 0.7                            # below z = a
+    return pos
+
+
+@pytest.mark.parametrize("sym", [1, 0])
+@pytest.mark.parametrize("n", [6, 257])
+def test_periodic_product_matches_oracle(ctx, n, sym):
+    pos = _boxed(n, 60 + n)
+    rng = np.random.default_rng(n)
+    F, T = rng.standard_normal(pos.shape), rng.standard_normal(pos.shape)
+    for torque in (None, T):
+        ref = mobility.dense_matvec(pos, F, torque, box=BOX)
+        for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+            ctx.set_tuning(precision, symmetric=sym)
+            u = host(ctx.matvec(dev(pos), dev(F), None if torque is None else dev(torque),
+                                precision))
+            assert rel2(u, ref) <= tol, (n, sym, precision, torque is None)
+
+
+def test_periodic_forces_match_oracle(ctx):
+    pos = _boxed(300, 9)
+    ref = forces.forces(pos, 1.0, 1.0, 0.1, -1.0, box=BOX)
+    f = host(ctx.forces(dev(pos), -1.0, 1.0, 0.1))
+    assert rel2(f, ref) <= 1e-12
+
+
+def test_periodic_step_matches_oracle(ctx):
+    from paper_1612_00474_amd import StepState
+    pos = _boxed(80, 10)
+    rng = np.random.default_rng(10)
+    W, Wt = rng.standard_normal(pos.shape), rng.standard_normal(pos.shape)
+    state = StepState(dev(pos))
+    it, eps, st = ctx.sab_step(state, dt=0.01, delta=1e-4, lanczos_tol=1e-300,
+                               lanczos_max_iter=6, w=dev(W), w_tilde=dev(Wt), steric_u0=1.0,
+                               steric_b=0.1)
+    new, u, m, _, _ = integrator.step(pos, None, W, Wt, dt=0.01, delta=1e-4,
+                                      lanczos_tol=1e-300, lanczos_max_iter=6, u0=1.0, b=0.1,
+                                      box=BOX)
+    assert it == m == 6
+    assert rel2(host(state.pos) - pos, new - pos) <= 1e-10
+    assert rel2(host(state.u_prev), u) <= 1e-12
+
+
+def test_periodic_rejections(ctx):
+    from paper_1612_00474_amd import Context, RpbError
+    pos = dev(_boxed(20, 11))
+    F = dev(np.ones((20, 3)))
+    with pytest.raises(RpbError):
+        ctx.matvec_batched(pos, [0, 10, 20], F, None, "fp64")
+    small = Context(0, box=(10.0, 30.0))      # 10 < 2 (2a + 40 b) = 12
+    with pytest.raises(RpbError):
+        small.forces(pos, -1.0, 1.0, 0.1)
+    small.close()
+    bad = Context(0, box=(10.0, 0.0))
+    with pytest.raises(RpbError):
+        bad.matvec(pos, F, None)
+    bad.close()

@@ -197,3 +197,55 @@ def test_free_space_matrix_free_product_matches_dense():
     M, MC = mobility.dense(pos, wall=False)
     ref = (M @ F.ravel() + MC @ T.ravel()).reshape(-1, 3)
     assert np.allclose(mobility.matvec(pos, F, T, wall=False), ref, rtol=1e-13, atol=1e-16)
+
+
+# ---- pseudo-periodic boundary conditions (App. B): minimum image + 8 neighbour cells ------
+
+BOX = (9.0, 7.5)
+
+
+def _box_config():
+    rng = np.random.default_rng(17)
+    pos = np.column_stack([rng.uniform(0, BOX[0], 7), rng.uniform(0, BOX[1], 7),
+                           rng.uniform(1.05, 2.5, 7)])
+    pos[1, :2] = pos[0, :2] + [1.2, 0.9]       # an overlapping pair
+    pos[2, 2] = 0.8                            # a sphere below z = a
+    return pos
+
+
+def test_periodic_mobility_depends_on_positions_modulo_the_box():
+    pos = _box_config()
+    M, MC = mobility.dense(pos, box=BOX)
+    moved = pos.copy()
+    moved[:, 0] += 3.3                         # common shift
+    moved[:, 1] -= 1.1
+    moved[3, 0] += 2 * BOX[0]                  # whole-box jumps of single spheres
+    moved[5, 1] -= BOX[1]
+    M2, MC2 = mobility.dense(moved, box=BOX)
+    assert np.allclose(M2, M, rtol=1e-12, atol=1e-15)
+    assert np.allclose(MC2, MC, rtol=1e-12, atol=1e-15)
+    assert np.allclose(M, M.T, rtol=0, atol=1e-15)
+
+
+def test_periodic_images_decay_like_the_screened_interaction():
+    # the eight neighbour cells add O(L^-3) (wall-screened far field, Sec. II.C): doubling the
+    # box divides the difference from the unbounded sheet by about 8
+    pos = _box_config()[:4] - np.array([4.5, 3.75, 0.0])
+    pos[:, :2] *= 0.4
+    free, _ = mobility.dense(pos)
+    gaps = []
+    for L in (40.0, 80.0):
+        M, _ = mobility.dense(pos, box=(L, L))
+        gaps.append(np.abs(M - free).max())
+    assert 6.0 < gaps[0] / gaps[1] < 10.5
+
+
+def test_periodic_forces_use_the_minimum_image():
+    from oracle import forces
+    pair = np.array([[0.3, 2.0, 1.5], [BOX[0] - 0.6, 2.4, 1.7]])
+    near = pair.copy()
+    near[1, 0] -= BOX[0]                       # the same pair, unwrapped
+    fp = forces.forces(pair, 1.0, 1.0, 0.1, -1.0, box=BOX)
+    fn = forces.forces(near, 1.0, 1.0, 0.1, -1.0)
+    assert np.allclose(fp, fn, rtol=1e-14, atol=1e-14)
+    assert np.abs(fp[:, 0]).max() > 1.0        # they do repel
