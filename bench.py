@@ -65,9 +65,11 @@ def measured_traffic(kernel: str, n: int = PROFILED_N):
 def force_kernel_name(prec: str, shape: dict) -> str:
     """rocprofv3 name of the pair kernel that a force-only product launches with `shape`."""
     kind = "mixed" if prec == "mixed" else "f64"
+    # template arguments: (targets per lane, torque, wall, periodic) for the symmetric kernel,
+    # (torque, targets per lane, wall, periodic) for the ordered one
     if shape["symmetric"]:
-        return f"pair_kernel_{kind}_sym<{shape['tpt']}, false>"
-    return f"pair_kernel_{kind}<false, {shape['tpt']}>"
+        return f"pair_kernel_{kind}_sym<{shape['tpt']}, false, true, false>"
+    return f"pair_kernel_{kind}<false, {shape['tpt']}, true, false>"
 
 
 def parse():
