@@ -370,14 +370,17 @@ struct SymArgs {
   int64_t stride;  // stride of the source component arrays (all systems' spheres)
 };
 
-// v from lane (l + 1) mod 64 (DPP wave_rol:1)
+// v from lane (l + 1) mod 64 (DPP wave_rol:1).  Every lane has a source lane, so the "old"
+// operand is never used; passing v itself lets the move be done in place.
 __device__ __forceinline__ float wave_rol1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xf, 0xf, false));
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x134, 0xf, 0xf, false));
 }
 __device__ __forceinline__ double wave_rol1(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), 0x134, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x134, 0xf, 0xf, false);
+  const int l = int(b & 0xffffffffll), h = int(b >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(l, l, 0x134, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(h, h, 0x134, 0xf, 0xf, false);
   return __longlong_as_double((static_cast<long long>(hi) << 32) |
                               static_cast<long long>(static_cast<unsigned>(lo)));
 }

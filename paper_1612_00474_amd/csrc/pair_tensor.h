@@ -29,7 +29,7 @@
 // Evaluation order (fewest operations): with t = hh (hh - ez), p = X(2 - 10/3 X) and
 // q = 20/3 Y, the coefficients are
 //     c1 = -1 + 2t - 2/3 (X - Y) + ez^2 p          c2 = -1 - 6t + p + ez^2 (q - 5p)
-//     c3 = 2hh + 12 ez t + ez[(q - 2p) + ez^2 (10p - 2q)]
+//     c3 = 2hh + 12 ez t + ez[(q - 2p) - 2 ez^2 (q - 5p)]
 //     c4 = 2hh - ez q                               c5 = -4hh^2 - 4X ez^2 + Y(20 ez^2 - 8/3)
 // and since r and R share their horizontal part rho = (dx, dy), unbounded and wall terms
 // merge into one coefficient for F, one for rho and a z remainder.
@@ -154,9 +154,9 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   const Real q = Real(20.0 / 3.0) * Y;
   const Real hh2x = Real(2) * hh;
   const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
-  const Real c2 = ez2 * (q - Real(5) * p) + (Real(-6) * t + (p - Real(1)));
-  const Real c3 = ez * ((q - Real(2) * p) + ez2 * (Real(10) * p - Real(2) * q)) +
-                  (Real(12) * (ez * t) + hh2x);
+  const Real m1 = ez2 * (q - Real(5) * p);   // shared by c2 and c3 (10p - 2q = -2(q - 5p))
+  const Real c2 = m1 + (Real(-6) * t + (p - Real(1)));
+  const Real c3 = ez * ((q - Real(2) * p) + Real(-2) * m1) + (Real(12) * (ez * t) + hh2x);
   const Real c4 = hh2x - ez * q;
   const Real c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
 
@@ -293,9 +293,9 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
   const Real q = Real(20.0 / 3.0) * Y;
   const Real hh2x = Real(2) * hh;
   const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
-  const Real c2 = ez2 * (q - Real(5) * p) + (Real(-6) * t + (p - Real(1)));
-  const Real c3 = ez * ((q - Real(2) * p) + ez2 * (Real(10) * p - Real(2) * q)) +
-                  (Real(12) * (ez * t) + hh2x);
+  const Real m1 = ez2 * (q - Real(5) * p);   // shared by c2 and c3 (10p - 2q = -2(q - 5p))
+  const Real c2 = m1 + (Real(-6) * t + (p - Real(1)));
+  const Real c3 = ez * ((q - Real(2) * p) + Real(-2) * m1) + (Real(12) * (ez * t) + hh2x);
   const Real c4 = hh2x - ez * q;
   const Real c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
   const Real A = cI + iR * c1;

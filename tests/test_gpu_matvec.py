@@ -123,11 +123,13 @@ def test_deterministic(ctx, c1):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,nrows", [("sheet16k_fp64", 48), ("sheet64k_mixed", 24)])
+@pytest.mark.parametrize("name,nrows", [("sheet16k_fp64", 48), ("sheet64k_mixed", 24),
+                                        ("sheet256k_mixed", 6)])
 def test_full_size_row_sampled(ctx, name, nrows):
     w = wl.WORKLOADS[name]
     inp = wl.make_inputs(w, 0)
     rows = np.random.default_rng(9).choice(w.n, nrows, replace=False)
+    rows[0] = w.n - 1                          # the last sphere (ragged last tile)
     ref = mobility.matvec(inp["pos"], inp["force"], inp["torque"], rows=rows)
     P, F, T = dev(inp["pos"]), dev(inp["force"]), dev(inp["torque"])
     for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
