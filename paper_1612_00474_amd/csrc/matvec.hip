@@ -706,18 +706,28 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
   sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, L, col);
 }
 
+// One thread per (component, row): four independent partial sums over the slots (P mod 4),
+// combined in a fixed order, so the memory system sees four loads in flight per thread.
 __global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
                                     const double *__restrict__ h, double scale,
                                     double *__restrict__ vel) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= a.n) return;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= 3 * a.n) return;
+  const int d = int(e / a.n);
+  const int64_t r = e - int64_t(d) * a.n;
   const int64_t T = r / a.ts, local = r % a.ts;
-  const double w = scale * h[r];
-  for (int d = 0; d < 3; ++d) {
-    double s = 0.0;
-    for (int64_t P = 0; P < a.nt; ++P) s += partial[sym_slot(a, T, P, d, local)];
-    vel[3 * r + d] = w * s;
+  const double *base = partial + sym_slot(a, T, 0, d, local);
+  const int64_t stride = 3 * a.ts;   // slot (T, P) to (T, P + 1)
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t P = 0;
+  for (; P + 4 <= a.nt; P += 4) {
+    s0 += base[P * stride];
+    s1 += base[(P + 1) * stride];
+    s2 += base[(P + 2) * stride];
+    s3 += base[(P + 3) * stride];
   }
+  for (; P < a.nt; ++P) s0 += base[P * stride];
+  vel[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
 }
 
 // ---- batched systems: persistent workgroups over a cost-ordered item list -------------------
@@ -863,20 +873,27 @@ __global__ void reduce_partials_sym_batched(SymBatchArgs b, const int *__restric
                                             const double *__restrict__ partial,
                                             const double *__restrict__ h, double scale,
                                             double *__restrict__ vel) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= b.n) return;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // (component, row)
+  if (e >= 3 * b.n) return;
+  const int d = int(e / b.n);
+  const int64_t r = e - int64_t(d) * b.n;
   const int s = sys_of[r];
   if (b.done && b.done[s]) return;
   const SymArgs a = sym_args_of(b, s);
   const int64_t local = r - b.offs[s];
-  const int64_t T = local / a.ts, l = local % a.ts;
-  const double *base = partial + b.part_base[s];
-  const double w = scale * h[r];
-  for (int d = 0; d < 3; ++d) {
-    double acc = 0.0;
-    for (int64_t P = 0; P < a.nt; ++P) acc += base[sym_slot(a, T, P, d, l)];
-    vel[3 * r + d] = w * acc;
+  const int64_t T = local / a.ts;
+  const double *base = partial + b.part_base[s] + sym_slot(a, T, 0, d, local % a.ts);
+  const int64_t stride = 3 * a.ts;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t P = 0;
+  for (; P + 4 <= a.nt; P += 4) {
+    s0 += base[P * stride];
+    s1 += base[(P + 1) * stride];
+    s2 += base[(P + 2) * stride];
+    s3 += base[(P + 3) * stride];
   }
+  for (; P < a.nt; ++P) s0 += base[P * stride];
+  vel[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
 }
 
 __global__ void fill_sys_of(int nsys, const int64_t *__restrict__ offs, int *__restrict__ sys_of) {
@@ -1064,7 +1081,7 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), (f64 ? 0 : 2) + (torque ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta);
-  reduce_partials_sym<<<blocks_for(n, 256), 256, 0, stream>>>(a, part, h, scale, vel);
+  reduce_partials_sym<<<blocks_for(3 * n, 256), 256, 0, stream>>>(a, part, h, scale, vel);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
@@ -1267,8 +1284,8 @@ int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const 
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta);
-  reduce_partials_sym_batched<<<blocks_for(n, 256), 256, 0, stream>>>(args, b.sys_of, part, h,
-                                                                      scale, vel);
+  reduce_partials_sym_batched<<<blocks_for(3 * n, 256), 256, 0, stream>>>(args, b.sys_of, part,
+                                                                          h, scale, vel);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
