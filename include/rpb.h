@@ -186,9 +186,10 @@ int rpb_normals(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id,
  *   u^n     = M^n F^n + M_C^n T                         (forces from rpb_forces, T constant)
  *   SAB (eq. AB): q^{n+1} = q^n + dt (3/2 u^n - 1/2 u^{n-1}) + sqrt(2 kT dt) g^n + dt D^n
  *   EM  (eq. EM): q^{n+1} = q^n + dt u^n + sqrt(2 kT dt) g^n + dt D^n
- * with g^n = lanczos_sqrt_apply(W^n) and D^n = rfd_drift(W~^n) (or rfd_drift_one_sided).  The first SAB step
- * (have_prev == 0) is an EM step.  On return state->pos holds q^{n+1}, state->u_prev
- * holds u^n, state->step is incremented and state->have_prev = 1.
+ * with g^n = lanczos_sqrt_apply(W^n) (or lanczos_sqrt_apply_precond) and D^n = rfd_drift(W~^n)
+ * (or rfd_drift_one_sided).  The first SAB step (have_prev == 0) is an EM step.  On return
+ * state->pos holds q^{n+1}, state->u_prev holds u^n, state->step is incremented and
+ * state->have_prev = 1.
  */
 typedef struct {
   double dt;            /* time step (> 0) */

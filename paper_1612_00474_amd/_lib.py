@@ -82,6 +82,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not found; build it with `python -m paper_1612_00474_amd.build`")
+    # torch first: its HIP runtime is then the one the library's libamdhip64 dependency binds
+    # to (a second copy of the runtime in the process would not see the device state torch
+    # sets up)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P = C.c_void_p
     D = C.c_double

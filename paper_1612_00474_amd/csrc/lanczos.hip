@@ -679,10 +679,12 @@ int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStrea
 int lanczos_status_code(rpb_ctx *ctx, const LzStatus *s, int nsys) {
   int worst = RPB_OK;
   for (int q = 0; q < nsys; ++q) {
-    if (s[q].reason == 4) return fail(ctx, RPB_EDEVICE, "tridiagonal eigensolve failed (system %d)", q);
+    if (s[q].reason == 4)
+      return fail(ctx, RPB_EDEVICE, "tridiagonal eigensolve failed (system %d)", q);
     if (s[q].reason == 3) worst = fail(ctx, RPB_ENOTSPD, "negative Ritz value (system %d)", q);
     if (s[q].reason == 0 && worst == RPB_OK)
-      worst = fail(ctx, RPB_ENOCONV, "Lanczos tolerance not met (system %d, eps %.3e)", q, s[q].eps);
+      worst = fail(ctx, RPB_ENOCONV, "Lanczos tolerance not met (system %d, eps %.3e)", q,
+                   s[q].eps);
   }
   return worst;
 }

@@ -8,7 +8,8 @@
 //
 // Unbounded part (Sec. II.B and Sec. III, the RPY forms to which the wall terms are added):
 //   |r| >= 2a:  (1/|r|)[(1 + 2a^2/(3r^2)) I + (1 - 2a^2/r^2) rr/r^2],  rotation: T x r / |r|^3
-//   |r| <  2a:  (4/(3a))[(1 - 9|r|/(32a)) I + (3/(32a)) rr/|r|],      rotation: (1 - 3|r|/(8a))/(2a^3) T x r
+//   |r| <  2a:  (4/(3a))[(1 - 9|r|/(32a)) I + (3/(32a)) rr/|r|],
+//               rotation: (1 - 3|r|/(8a))/(2a^3) T x r
 //   (the |r| = 0 limit is the Stokes self-mobility 4/(3a) I and no rotation coupling).
 //
 // Wall part: the Faxen operators of eq. mobilityDifferential applied to the image system of

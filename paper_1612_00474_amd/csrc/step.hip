@@ -109,7 +109,8 @@ int step_batched_enqueue(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config
   RPB_TRY(rfd_batched_run(ctx, p, bt, pos, Wt, cfg->delta, cfg->rfd_precision,
                           cfg->rfd_scheme == 1, drift, stream));
   combine_kernel_dev<<<nblk(m3), 256, 0, stream>>>(m3, pos, u_prev, u, g, drift, cfg->dt,
-                                                   cfg->scheme, rec, std::sqrt(2.0 * p->kT * cfg->dt));
+                                                   cfg->scheme, rec,
+                                                   std::sqrt(2.0 * p->kT * cfg->dt));
   RPB_LAUNCHED(ctx);
   advance_step_record<<<1, 1, 0, stream>>>(rec);
   RPB_LAUNCHED(ctx);

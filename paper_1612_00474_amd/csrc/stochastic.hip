@@ -92,7 +92,8 @@ __global__ void shifted_pair(int64_t m, const double *__restrict__ q, const doub
 }
 
 __global__ void scaled_difference(int64_t m, const double *__restrict__ a,
-                                  const double *__restrict__ b, double s, double *__restrict__ out) {
+                                  const double *__restrict__ b, double s,
+                                  double *__restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= m) return;
   out[i] = s * (a[i] - b[i]);

@@ -22,7 +22,8 @@ int time_candidate(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_
                    const double *pos, int reps, hipStream_t stream, double *ms_out) {
   const int64_t n = offs[nsys];
   int st;
-  double *vel = static_cast<double *>(workspace(ctx, WS_VEC_A, size_t(3 * n) * sizeof(double), &st));
+  double *vel =
+      static_cast<double *>(workspace(ctx, WS_VEC_A, size_t(3 * n) * sizeof(double), &st));
   if (!vel) return st;
   Packed g;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));

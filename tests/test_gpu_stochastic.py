@@ -83,3 +83,49 @@ def test_normals_match_oracle_generator(ctx):
         ref = philox.normals(count, seed, stream, step)
         got = host(ctx.normals(count, seed, stream, step))
         assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_variant_error_paths(ctx, c1):
+    # the one-sided RFD, the preconditioned Lanczos and the step options reject bad input
+    # like their plain forms
+    import ctypes as C
+    import torch
+    from paper_1612_00474_amd._lib import RPB_EINVAL, RPB_ENONFINITE, RpbError, _sab_config
+    P, Wt = dev(c1["pos"]), dev(c1["w_tilde"])
+    with pytest.raises(RpbError) as e:
+        ctx.rfd(P, Wt, -1e-4, rfd_scheme="one_sided")
+    assert e.value.status == RPB_EINVAL
+    with pytest.raises(RpbError) as e:
+        ctx.rfd(P, Wt, 1e-4, rfd_scheme="one_sided", out=Wt)
+    assert e.value.status == RPB_EINVAL
+    bad = P.clone()
+    bad[0, 2] = float("inf")
+    with pytest.raises(RpbError) as e:
+        ctx.rfd(bad, Wt, 1e-4, rfd_scheme="one_sided")
+    assert e.value.status == RPB_ENONFINITE
+    with pytest.raises(RpbError) as e:
+        ctx.lanczos(P, Wt, 1e-3, max_iter=0, precond=True)
+    assert e.value.status == RPB_EINVAL
+    with pytest.raises(RpbError) as e:
+        ctx.lanczos(bad, Wt, 1e-3, precond=True)
+    assert e.value.status == RPB_ENONFINITE
+    # out-of-range step options through the raw ABI
+    from paper_1612_00474_amd import StepState
+    from paper_1612_00474_amd._lib import RpbSabState, _stream
+    state = StepState(P.clone())
+    for field, value in (("rfd_scheme", 2), ("lanczos_precond", 3), ("scheme", 5)):
+        cfg = _sab_config(0.01, 1e-4, 1e-3, 8, "sab", "fp64", -1.0, (0.0, 1.0, 0.0), 1.0, 0.1, 0)
+        setattr(cfg, field, value)
+        s = RpbSabState(state.pos.shape[0], state.pos.data_ptr(), state.u_prev.data_ptr(), 0, 0)
+        p = ctx.params("fp64")
+        st = ctx.lib.sab_step(ctx.h, C.byref(p), C.byref(cfg), C.byref(s), None, None, None, None,
+                              _stream())
+        assert st == RPB_EINVAL, field
+    # a wall flag other than 0 or 1
+    p = ctx.params("fp64")
+    p.wall = 2
+    out = torch.empty_like(P)
+    st = ctx.lib.rpb_mobility_matvec(ctx.h, C.byref(p), P.shape[0], C.c_void_p(P.data_ptr()),
+                                     C.c_void_p(Wt.data_ptr()), None, C.c_void_p(out.data_ptr()),
+                                     _stream())
+    assert st == RPB_EINVAL
