@@ -21,36 +21,11 @@
 #include <numeric>
 #include <type_traits>
 
-#include "pair_tensor.h"
-#include "rpb_internal.h"
+#include "pair_common.h"
 
 namespace rpb {
 
 namespace {
-
-constexpr int kBlock = 256;   // lanes per workgroup = targets per tile row = sources per LDS tile
-
-struct GeomD {         // float64 geometry: x, y, z~ and H, n each
-  const double *x, *y, *z, *h;
-};
-struct GeomF {         // mixed geometry: float32 hi/lo x, y, float32 z~, float64 H
-  const float *xh, *xl, *yh, *yl, *z;
-  const double *h;
-};
-
-inline GeomD geom_d(const Packed &g) {
-  const double *b = static_cast<const double *>(g.geom);
-  return {b, b + g.n, b + 2 * g.n, b + 3 * g.n};
-}
-inline GeomF geom_f(const Packed &g) {
-  const double *h = static_cast<const double *>(g.geom);
-  const float *f = reinterpret_cast<const float *>(h + g.n);
-  return {f, f + g.n, f + 2 * g.n, f + 3 * g.n, f + 4 * g.n, h};
-}
-inline size_t geom_bytes(int64_t n, int precision) {
-  return precision == RPB_FP64 ? size_t(4 * n) * sizeof(double)
-                               : size_t(n) * sizeof(double) + size_t(5 * n) * sizeof(float);
-}
 
 // With a wall: z~ = max(z, a) and H = clamp(z/a, 0, 1) (App. A); in free space: z~ = z, H = 1.
 __global__ void pack_geometry_f64(int64_t n, const double *__restrict__ pos, double a, int wall,
@@ -92,12 +67,6 @@ __global__ void pack_vectors(int64_t n, const double *__restrict__ h,
   }
 }
 
-__device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
-  const float y = v - c;
-  const float t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
 
 // ---- workgroup-level building blocks shared by the single and batched kernels ---------------
 
@@ -362,50 +331,6 @@ __global__ void reduce_partials(int64_t nrows, int nchunks, const double *__rest
 // a fixed order.  Tile I gets slot (I, J) and tile J gets slot (J, I) of the partial array;
 // diagonal tiles are evaluated as ordered pairs into slot (I, I).  Every target thus receives
 // exactly nt partials, summed in slot order.
-
-struct SymArgs {
-  int64_t n;       // spheres of the system
-  int64_t ts;      // tile size (kBlock * TPT)
-  int64_t nt;      // tiles
-  int64_t stride;  // stride of the source component arrays (all systems' spheres)
-};
-
-// v from lane (l + 1) mod 64 (DPP wave_rol:1).  Every lane has a source lane, so the "old"
-// operand is never used; passing v itself lets the move be done in place.
-__device__ __forceinline__ float wave_rol1(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x134, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double wave_rol1(double v) {
-  const long long b = __double_as_longlong(v);
-  const int l = int(b & 0xffffffffll), h = int(b >> 32);
-  const int lo = __builtin_amdgcn_update_dpp(l, l, 0x134, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(h, h, 0x134, 0xf, 0xf, false);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              static_cast<long long>(static_cast<unsigned>(lo)));
-}
-
-// slot (T, P) of the symmetric partial array: partial[((T * nt + P) * 3 + comp) * ts + local]
-__device__ __forceinline__ int64_t sym_slot(const SymArgs &a, int64_t T, int64_t P, int comp,
-                                            int64_t local) {
-  return ((T * a.nt + P) * 3 + comp) * a.ts + local;
-}
-
-constexpr int kWaves = kBlock / 64;
-
-// Tile pair (I, J), I <= J, of linear index L = I nt - I (I - 1) / 2 + (J - I): row I of the
-// upper triangle holds nt - I pairs.  Workgroups walk the triangle row by row.
-__device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, int64_t &J) {
-  const double b = double(2 * nt + 1);
-  int64_t i = int64_t((b - sqrt(b * b - 8.0 * double(L))) * 0.5);
-  auto start = [nt](int64_t r) { return r * nt - r * (r - 1) / 2; };
-  if (i < 0) i = 0;
-  if (i > nt - 1) i = nt - 1;
-  while (i > 0 && start(i) > L) --i;
-  while (i + 1 < nt && start(i + 1) <= L) ++i;
-  I = i;
-  J = i + (L - start(i));
-}
 
 // One rotation step: every lane passes its per-source sums cs one lane down, then evaluates
 // its targets against source j (weighted force zero when !valid), adding M_ij F_j into acc and
@@ -912,9 +837,6 @@ __global__ void finite_flag(int64_t m, const double *__restrict__ v, int *__rest
   if (bad) flag[0] = 1;   // benign race: every writer stores the same value
 }
 
-inline unsigned blocks_for(int64_t n, int threads) {
-  return unsigned((n + threads - 1) / threads);
-}
 
 // L with L^2 = diag(M_ii): the self pair (r = 0, R = (0, 0, 2 z~)) applied to e_x and e_z, in
 // float64 whatever the product precision; H = 0 keeps L = 1.

@@ -200,28 +200,33 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   }
 }
 
-// Both directions of one unordered pair, from one evaluation of the coefficients: the
-// mobility matrix is symmetric, M_ji = M_ij^T (reciprocity of Blake's tensor; the unbounded part
-// depends on r r^T and |r| only), so
-//   (ox, oy, oz) += M_ij F_j   (velocity of i, 8 pi eta units)
-//   (px, py, pz) += M_ij^T F_i (velocity of j)
-// where M_ij^T swaps the roles of c3 and c4 (e z^T <-> z e^T).  With TORQUE the coupling terms
-// are added too, (o) += M^C_ij T_j and (p) += M^C_ji T_i (tq: T_j, uq: T_i).  M^C has no such
-// symmetry, but M^C_ji is the same expression with r -> -r and the image height hh = z~_j/|R|
-// replaced by z~_i/|R|, so everything else (|R|, e_z, X, the unbounded coefficient) is shared.
-template <typename Real, bool FAR_ONLY = false, bool TORQUE = false, bool WALL = true>
-__device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Real zj, Real fx,
-                                                  Real fy, Real fz, Real gx, Real gy, Real gz,
-                                                  const PairConsts<Real> &k, Real &ox, Real &oy,
-                                                  Real &oz, Real &px, Real &py, Real &pz,
-                                                  const Real *tq = nullptr,
-                                                  const Real *uq = nullptr) {
+// Coefficients of one unordered pair, shared by both directions (and by every source vector
+// of a multi-vector product): the mobility matrix is symmetric, M_ji = M_ij^T (reciprocity of
+// Blake's tensor; the unbounded part depends on r r^T and |r| only).
+template <typename Real>
+struct SymCoef {
+  Real dx, dy, dz, Rz;   // r = (dx, dy, dz), R_z = z~_i + z~_j
+  Real iR, iR2, ez;      // 1/|R|, 1/|R|^2, e_z
+  Real cI, cRR, cT;      // unbounded: cI F + cRR r (r.F), rotation cT T x r
+  Real A;                // cI + c1/|R| (coefficient of F)
+  Real c2, c3, c4, c5;   // wall basis
+  Real X, hh;            // a^2/|R|^2, z~_j/|R| (torque coupling)
+};
+
+template <typename Real, bool FAR_ONLY, bool TORQUE, bool WALL>
+__device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real zj,
+                                                 const PairConsts<Real> &k, SymCoef<Real> &c) {
   const Real dz = zi - zj;
   const Real Rz = zi + zj;
   const Real rho2 = dx * dx + dy * dy;
   const Real r2 = rho2 + dz * dz;
   const Real R2 = rho2 + Rz * Rz;
   const Real iR = rsqrt_r(R2);
+  c.dx = dx;
+  c.dy = dy;
+  c.dz = dz;
+  c.Rz = Rz;
+  c.iR = iR;
 
   Real cI, cRR, cT = Real(0);
   if (FAR_ONLY) {
@@ -255,32 +260,10 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
       if (TORQUE) cT = k.near_t - k.near_t_r * r;
     }
   }
-
-  if (!WALL) {   // free space: the unbounded RPY tensors alone (r -> -r for j <- i)
-    const Real cr = cRR * (dx * fx + dy * fy + dz * fz);
-    const Real cr2 = cRR * (dx * gx + dy * gy + dz * gz);
-    ox += cI * fx;
-    ox += cr * dx;
-    oy += cI * fy;
-    oy += cr * dy;
-    oz += cI * fz;
-    oz += cr * dz;
-    px += cI * gx;
-    px += cr2 * dx;
-    py += cI * gy;
-    py += cr2 * dy;
-    pz += cI * gz;
-    pz += cr2 * dz;
-    if (TORQUE) {   // cT T_j x r into o, cT T_i x (-r) into p
-      ox += cT * (tq[1] * dz - tq[2] * dy);
-      oy += cT * (tq[2] * dx - tq[0] * dz);
-      oz += cT * (tq[0] * dy - tq[1] * dx);
-      px -= cT * (uq[1] * dz - uq[2] * dy);
-      py -= cT * (uq[2] * dx - uq[0] * dz);
-      pz -= cT * (uq[0] * dy - uq[1] * dx);
-    }
-    return;
-  }
+  c.cI = cI;
+  c.cRR = cRR;
+  c.cT = cT;
+  if (!WALL) return;
 
   const Real iR2 = iR * iR;
   const Real X = k.a2 * iR2;
@@ -295,85 +278,178 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
   const Real hh2x = Real(2) * hh;
   const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
   const Real m1 = ez2 * (q - Real(5) * p);   // shared by c2 and c3 (10p - 2q = -2(q - 5p))
-  const Real c2 = m1 + (Real(-6) * t + (p - Real(1)));
-  const Real c3 = ez * ((q - Real(2) * p) + Real(-2) * m1) + (Real(12) * (ez * t) + hh2x);
-  const Real c4 = hh2x - ez * q;
-  const Real c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
-  const Real A = cI + iR * c1;
+  c.c2 = m1 + (Real(-6) * t + (p - Real(1)));
+  c.c3 = ez * ((q - Real(2) * p) + Real(-2) * m1) + (Real(12) * (ez * t) + hh2x);
+  c.c4 = hh2x - ez * q;
+  c.c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
+  c.A = cI + iR * c1;
+  c.iR2 = iR2;
+  c.ez = ez;
+  c.X = X;
+  c.hh = hh;
+}
 
+// (o) += M_ij f (velocity of i from source j's force f) and (p) += M_ij^T g (velocity of j from
+// target i's force g), 8 pi eta units; M_ij^T swaps the roles of c3 and c4 (e z^T <-> z e^T).
+template <typename Real, bool WALL>
+__device__ __forceinline__ void sym_apply(const SymCoef<Real> &c, Real fx, Real fy, Real fz,
+                                          Real gx, Real gy, Real gz, Real &ox, Real &oy,
+                                          Real &oz, Real &px, Real &py, Real &pz) {
+  const Real dx = c.dx, dy = c.dy, dz = c.dz;
+  if (!WALL) {   // free space: the unbounded RPY tensors alone (r -> -r for j <- i)
+    const Real cr = c.cRR * (dx * fx + dy * fy + dz * fz);
+    const Real cr2 = c.cRR * (dx * gx + dy * gy + dz * gz);
+    ox += c.cI * fx;
+    ox += cr * dx;
+    oy += c.cI * fy;
+    oy += cr * dy;
+    oz += c.cI * fz;
+    oz += cr * dz;
+    px += c.cI * gx;
+    px += cr2 * dx;
+    py += c.cI * gy;
+    py += cr2 * dy;
+    pz += c.cI * gz;
+    pz += cr2 * dz;
+    return;
+  }
   // i <- j
   const Real rhoF = dx * fx + dy * fy;
   const Real rF = rhoF + dz * fz;
-  const Real eF = (rhoF + Rz * fz) * iR;
-  const Real G = c2 * eF + c3 * fz;
-  const Real H = c4 * eF + c5 * fz;
-  const Real cr = cRR * rF;
-  const Real B = cr + iR2 * G;
-  ox += A * fx;
+  const Real eF = (rhoF + c.Rz * fz) * c.iR;
+  const Real G = c.c2 * eF + c.c3 * fz;
+  const Real H = c.c4 * eF + c.c5 * fz;
+  const Real cr = c.cRR * rF;
+  const Real B = cr + c.iR2 * G;
+  ox += c.A * fx;
   ox += B * dx;
-  oy += A * fy;
+  oy += c.A * fy;
   oy += B * dy;
-  oz += A * fz;
+  oz += c.A * fz;
   oz += cr * dz;
-  oz += iR * (G * ez + H);
+  oz += c.iR * (G * c.ez + H);
 
   // j <- i (transposed tensor)
   const Real rhoG = dx * gx + dy * gy;
   const Real rG = rhoG + dz * gz;
-  const Real eG = (rhoG + Rz * gz) * iR;
-  const Real G2 = c2 * eG + c4 * gz;
-  const Real H2 = c3 * eG + c5 * gz;
-  const Real cr2 = cRR * rG;
-  const Real B2 = cr2 + iR2 * G2;
-  px += A * gx;
+  const Real eG = (rhoG + c.Rz * gz) * c.iR;
+  const Real G2 = c.c2 * eG + c.c4 * gz;
+  const Real H2 = c.c3 * eG + c.c5 * gz;
+  const Real cr2 = c.cRR * rG;
+  const Real B2 = cr2 + c.iR2 * G2;
+  px += c.A * gx;
   px += B2 * dx;
-  py += A * gy;
+  py += c.A * gy;
   py += B2 * dy;
-  pz += A * gz;
+  pz += c.A * gz;
   pz += cr2 * dz;
-  pz += iR * (G2 * ez + H2);
+  pz += c.iR * (G2 * c.ez + H2);
+}
 
-  if (TORQUE) {
-    const Real iR3 = iR * iR2;
-    const Real al = iR3 - cT;                 // coefficient of kv (both directions)
-    const Real xez = X * ez;
-    const Real be0 = iR2 * (Real(2) * xez) - iR3 * Rz;
-    const Real d30 = Real(10) * xez - Real(6) * ez;
-    const Real wz = d30 * ez - Real(2) * X;   // with the hh part of d3 added per direction
-    {  // i <- j: torque T_j, image height z~_j
-      const Real tx = tq[0], ty = tq[1], tz = tq[2];
-      const Real kx = dy * tz, ky = -(dx * tz), kz = dx * ty - dy * tx;
-      const Real d3 = d30 + Real(6) * hh;
-      const Real sv = -(kz * iR);
-      const Real be = cT * dz + (be0 + iR2 * hh2x);
-      const Real ga = iR3 * (sv * d3);
-      ox += al * kx;
-      ox += be * ty;
-      ox += ga * dx;
-      oy += al * ky;
-      oy += ga * dy;
-      oy -= be * tx;
-      oz += al * kz;
-      oz += (iR2 * sv) * (wz + Real(6) * hh * ez);
-    }
-    {  // j <- i: torque T_i, r -> -r, image height z~_i
-      const Real tx = uq[0], ty = uq[1], tz = uq[2];
-      const Real hi = zi * iR;
-      const Real kx = -(dy * tz), ky = dx * tz, kz = dy * tx - dx * ty;
-      const Real d3 = d30 + Real(6) * hi;
-      const Real sv = -(kz * iR);
-      const Real be = (be0 + iR2 * (Real(2) * hi)) - cT * dz;
-      const Real ga = iR3 * (sv * d3);
-      px += al * kx;
-      px += be * ty;
-      px -= ga * dx;
-      py += al * ky;
-      py -= ga * dy;
-      py -= be * tx;
-      pz += al * kz;
-      pz += (iR2 * sv) * (wz + Real(6) * hi * ez);
-    }
+// The coupling terms of both directions, (o) += M^C_ij T_j and (p) += M^C_ji T_i (tq: T_j,
+// uq: T_i).  M^C has no symmetry, but M^C_ji is the same expression with r -> -r and the image
+// height hh = z~_j/|R| replaced by z~_i/|R|, so everything else (|R|, e_z, X, the unbounded
+// coefficient) is shared.
+template <typename Real, bool WALL>
+__device__ __forceinline__ void sym_apply_torque(const SymCoef<Real> &c, Real zi, const Real *tq,
+                                                 const Real *uq, Real &ox, Real &oy, Real &oz,
+                                                 Real &px, Real &py, Real &pz) {
+  const Real dx = c.dx, dy = c.dy, dz = c.dz, cT = c.cT;
+  if (!WALL) {   // cT T_j x r into o, cT T_i x (-r) into p
+    ox += cT * (tq[1] * dz - tq[2] * dy);
+    oy += cT * (tq[2] * dx - tq[0] * dz);
+    oz += cT * (tq[0] * dy - tq[1] * dx);
+    px -= cT * (uq[1] * dz - uq[2] * dy);
+    py -= cT * (uq[2] * dx - uq[0] * dz);
+    pz -= cT * (uq[0] * dy - uq[1] * dx);
+    return;
   }
+  const Real iR = c.iR, iR2 = c.iR2, ez = c.ez, X = c.X, Rz = c.Rz;
+  const Real iR3 = iR * iR2;
+  const Real al = iR3 - cT;                 // coefficient of kv (both directions)
+  const Real xez = X * ez;
+  const Real be0 = iR2 * (Real(2) * xez) - iR3 * Rz;
+  const Real d30 = Real(10) * xez - Real(6) * ez;
+  const Real wz = d30 * ez - Real(2) * X;   // with the hh part of d3 added per direction
+  {  // i <- j: torque T_j, image height z~_j
+    const Real hh = c.hh;
+    const Real tx = tq[0], ty = tq[1], tz = tq[2];
+    const Real kx = dy * tz, ky = -(dx * tz), kz = dx * ty - dy * tx;
+    const Real d3 = d30 + Real(6) * hh;
+    const Real sv = -(kz * iR);
+    const Real be = cT * dz + (be0 + iR2 * (Real(2) * hh));
+    const Real ga = iR3 * (sv * d3);
+    ox += al * kx;
+    ox += be * ty;
+    ox += ga * dx;
+    oy += al * ky;
+    oy += ga * dy;
+    oy -= be * tx;
+    oz += al * kz;
+    oz += (iR2 * sv) * (wz + Real(6) * hh * ez);
+  }
+  {  // j <- i: torque T_i, r -> -r, image height z~_i
+    const Real tx = uq[0], ty = uq[1], tz = uq[2];
+    const Real hi = zi * iR;
+    const Real kx = -(dy * tz), ky = dx * tz, kz = dy * tx - dx * ty;
+    const Real d3 = d30 + Real(6) * hi;
+    const Real sv = -(kz * iR);
+    const Real be = (be0 + iR2 * (Real(2) * hi)) - cT * dz;
+    const Real ga = iR3 * (sv * d3);
+    px += al * kx;
+    px += be * ty;
+    px -= ga * dx;
+    py += al * ky;
+    py -= ga * dy;
+    py -= be * tx;
+    pz += al * kz;
+    pz += (iR2 * sv) * (wz + Real(6) * hi * ez);
+  }
+}
+
+// One direction only: (o) += M_ij f.
+template <typename Real, bool WALL>
+__device__ __forceinline__ void sym_apply_one(const SymCoef<Real> &c, Real fx, Real fy, Real fz,
+                                              Real &ox, Real &oy, Real &oz) {
+  const Real dx = c.dx, dy = c.dy, dz = c.dz;
+  if (!WALL) {
+    const Real cr = c.cRR * (dx * fx + dy * fy + dz * fz);
+    ox += c.cI * fx;
+    ox += cr * dx;
+    oy += c.cI * fy;
+    oy += cr * dy;
+    oz += c.cI * fz;
+    oz += cr * dz;
+    return;
+  }
+  const Real rhoF = dx * fx + dy * fy;
+  const Real rF = rhoF + dz * fz;
+  const Real eF = (rhoF + c.Rz * fz) * c.iR;
+  const Real G = c.c2 * eF + c.c3 * fz;
+  const Real H = c.c4 * eF + c.c5 * fz;
+  const Real cr = c.cRR * rF;
+  const Real B = cr + c.iR2 * G;
+  ox += c.A * fx;
+  ox += B * dx;
+  oy += c.A * fy;
+  oy += B * dy;
+  oz += c.A * fz;
+  oz += cr * dz;
+  oz += c.iR * (G * c.ez + H);
+}
+
+// Both directions of one unordered pair (force and, with TORQUE, torque sources).
+template <typename Real, bool FAR_ONLY = false, bool TORQUE = false, bool WALL = true>
+__device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Real zj, Real fx,
+                                                  Real fy, Real fz, Real gx, Real gy, Real gz,
+                                                  const PairConsts<Real> &k, Real &ox, Real &oy,
+                                                  Real &oz, Real &px, Real &py, Real &pz,
+                                                  const Real *tq = nullptr,
+                                                  const Real *uq = nullptr) {
+  SymCoef<Real> c;
+  sym_coefficients<Real, FAR_ONLY, TORQUE, WALL>(dx, dy, zi, zj, k, c);
+  sym_apply<Real, WALL>(c, fx, fy, fz, gx, gy, gz, ox, oy, oz, px, py, pz);
+  if (TORQUE) sym_apply_torque<Real, WALL>(c, zi, tq, uq, ox, oy, oz, px, py, pz);
 }
 
 __device__ __forceinline__ float round_nearest(float x) { return __builtin_rintf(x); }
