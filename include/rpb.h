@@ -255,6 +255,30 @@ int sab_step_batched(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cf
                      int have_prev, const double *w, const double *w_tilde, int *iters_out,
                      double *eps_out, rpb_stream_t stream);
 
+/* Several source vectors, one configuration ------------------------------------------------
+ *
+ * vel[v] = M force[v] for v < nvec: force and vel are [nvec][n][3] float64 device arrays
+ * (vector-major), pos [n][3].  The products the Lanczos method needs (Sec. IV) for several
+ * independent noise vectors of one configuration share the pair coefficients: each unordered
+ * pair's coefficients are evaluated once and applied to four vectors in the same launch
+ * (the symmetric tile-pair kernel, diagonal tiles as ordered pairs).  Forces only (no
+ * torques), wall or free space, no pseudo-periodic box (RPB_EINVAL).  Each result agrees with
+ * rpb_mobility_matvec on that vector to rounding (summation order differs).  The partial sums
+ * take 3 n^2 / 8 bytes of device workspace per launch; beyond 32 GiB (n above about 300,000)
+ * the call falls back to one single-vector product per vector. */
+int rpb_mobility_matvec_multi(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                              int32_t nvec, const double *force, double *vel,
+                              rpb_stream_t stream);
+
+/* nvec independent Lanczos processes (Sec. II.C) for M^{1/2} w[v], one configuration: every
+ * Krylov iteration takes one multi-vector product of the processes still running; a process
+ * stops on its own tolerance test.  w, out: [nvec][n][3] device; iters_out, eps_out: optional
+ * HOST arrays of nvec entries; 0 <= nvec <= 4096.  Returns RPB_ENOCONV if any process missed
+ * tol (its output is its last iterate). */
+int lanczos_sqrt_apply_multi(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                             int32_t nvec, const double *w, double tol, int max_iter,
+                             double *out, int *iters_out, double *eps_out, rpb_stream_t stream);
+
 /* A batched step captured in a hipGraph.  Creation runs one warm-up step on scratch copies
  * (the caller's arrays are not modified), then captures the step bound to `pos` and `u_prev`
  * with the Lanczos budget cfg->lanczos_max_iter (converged systems are frozen on the device;
@@ -314,7 +338,8 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
  * summed kernel time in milliseconds, the number of launches and the number of ordered
  * pair interactions of the launches of kernel variant `kind`, and removes them from the
  * record.  kind = 2 * (precision == RPB_MIXED) + (torque present), plus 4 for the batched
- * kernel; kind = -1 takes all. */
+ * kernel; 8 + 2 * (precision == RPB_MIXED) for the multi-vector kernel, whose pair count is
+ * n^2 times the vectors of the launch; kind = -1 takes all. */
 int rpb_timing_enable(rpb_ctx *ctx, int enable);
 int rpb_timing_read(rpb_ctx *ctx, int kind, double *ms_out, int64_t *launches_out,
                     double *pairs_out);

@@ -29,6 +29,7 @@ EXPORTS = (
     "rpb_mobility_matvec_batched", "lanczos_sqrt_apply_batched", "sab_step_batched",
     "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
     "rpb_step_graph_destroy", "rpb_get_tuning", "rpb_set_tuning", "rpb_autotune",
+    "rpb_mobility_matvec_multi", "lanczos_sqrt_apply_multi",
 )
 
 
@@ -123,6 +124,9 @@ def load(path: str = LIB_PATH):
         "rpb_set_tuning": (C.c_int, [P, C.POINTER(RpbTuning)]),
         "rpb_autotune": (C.c_int, [P, pp, C.c_int32, P, P, C.c_int, C.POINTER(RpbTuning),
                                    C.POINTER(D), P]),
+        "rpb_mobility_matvec_multi": (C.c_int, [P, pp, I64, P, C.c_int32, P, P, P]),
+        "lanczos_sqrt_apply_multi": (C.c_int, [P, pp, I64, P, C.c_int32, P, D, C.c_int, P, P,
+                                               P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -307,6 +311,57 @@ class Context:
         self._check(st)
         return out
 
+    # -- several vectors, one configuration --------------------------------------------
+    def _vecs(self, t, name, n):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a float64 GPU tensor")
+        if t.dim() != 3 or t.shape[1] != n or t.shape[2] != 3 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous (nvec, {n}, 3) tensor, got "
+                             f"{tuple(t.shape)}")
+        return t
+
+    def matvec_multi(self, pos, force, precision="fp64", out=None):
+        """M F_v for every vector F_v = force[v] of shape (n, 3) (forces only)."""
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        self._vecs(force, "force", n)
+        if out is None:
+            out = torch.empty_like(force)
+        self._vecs(out, "out", n)
+        if out.shape[0] != force.shape[0]:
+            raise ValueError("out and force must hold the same number of vectors")
+        p = self.params(precision)
+        st = self.lib.rpb_mobility_matvec_multi(self.h, C.byref(p), n, _ptr(pos), force.shape[0],
+                                                _ptr(force), _ptr(out), _stream())
+        self._check(st)
+        return out
+
+    def lanczos_multi(self, pos, w, tol, max_iter=64, precision="fp64", out=None,
+                      allow_noconv=False):
+        """M^{1/2} w[v] for every vector; returns (g, iterations per vector, eps per vector,
+        status)."""
+        import numpy as np
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        self._vecs(w, "w", n)
+        if out is None:
+            out = torch.empty_like(w)
+        self._vecs(out, "out", n)
+        if out.shape[0] != w.shape[0]:
+            raise ValueError("out and w must hold the same number of vectors")
+        nvec = w.shape[0]
+        it = np.zeros(max(nvec, 1), dtype=np.int32)
+        eps = np.zeros(max(nvec, 1), dtype=np.float64)
+        p = self.params(precision)
+        st = self.lib.lanczos_sqrt_apply_multi(self.h, C.byref(p), n, _ptr(pos), nvec, _ptr(w),
+                                               float(tol), int(max_iter), _ptr(out), _np_ptr(it),
+                                               _np_ptr(eps), _stream())
+        self._check(st, (RPB_OK, RPB_ENOCONV) if allow_noconv else (RPB_OK,))
+        return out, it[:nvec], eps[:nvec], st
+
     # -- batched suspensions -------------------------------------------------------------
     def matvec_batched(self, pos, offs, force=None, torque=None, precision="fp64", out=None):
         """Products of `len(offs) - 1` independent systems concatenated in `pos`."""
@@ -443,7 +498,8 @@ class Context:
     def timing_read(self, kind=-1):
         """(milliseconds, launches, pair interactions) of pair-kernel launches since the last read.
 
-        ``kind``: -1 for all launches, else 2 * (mixed) + (with torque)."""
+        ``kind``: -1 for all launches, else 2 * (mixed) + (with torque), plus 4 for the
+        batched kernel; 8 + 2 * (mixed) for the multi-vector kernel."""
         ms = C.c_double(0.0)
         k = C.c_int64(0)
         pairs = C.c_double(0.0)

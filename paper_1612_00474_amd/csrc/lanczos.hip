@@ -14,6 +14,7 @@
 // reproducible.  The host reads a 32-byte status record once per iteration.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "rpb_internal.h"
 
@@ -561,20 +562,18 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
 }
 
 
-int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
-                        const double *w, double tol, int max_iter, bool precond, double *out,
-                        bool sync_each, LzStatus *status_host, hipStream_t stream) {
-  const int64_t n = g.n;
-  const int64_t m3 = 3 * n;
+namespace {
+
+// One Krylov process per segment (system) of `b`; product(src, done_dev, done_host, dst) writes
+// dst = M src for every segment not yet done (done_host: the flags as of the last host read,
+// NULL when unknown).  L (nullable): preconditioner scale, 3 b.n entries, with scratch t.
+template <typename Product>
+int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, const double *w,
+                     double tol, int max_iter, Product &&product, double *out, bool sync_each,
+                     LzStatus *status_host, hipStream_t stream) {
+  const int64_t m3 = 3 * b.n;
   const int nsys = b.nsys;
   int st;
-  double *L = nullptr, *t = nullptr;
-  if (precond) {
-    L = static_cast<double *>(workspace(ctx, WS_PRECOND, size_t(2 * m3) * sizeof(double), &st));
-    if (!L) return st;
-    t = L + m3;
-    RPB_TRY(block_diag_scale(ctx, p, g, L, stream));
-  }
   double *V = static_cast<double *>(
       workspace(ctx, WS_KRYLOV, size_t(max_iter) * size_t(m3) * sizeof(double), &st));
   if (!V) return st;
@@ -609,17 +608,18 @@ int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const
   seg_scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(v, m3, w, f_wnorm, V);
   RPB_LAUNCHED(ctx);
   int *host_done = static_cast<int *>(host_scratch(ctx));
+  const int *known = nullptr;   // host copy of the flags, once read
   for (int k = 1; k <= max_iter; ++k) {
     double *vk = V + int64_t(k - 1) * m3;
     const double *vprev = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
-    if (precond) {   // u = L^-1 M L^-1 vk (rows of finished systems are not used)
+    if (L) {   // u = L^-1 M L^-1 vk (rows of finished systems are not used)
       divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, vk, L, t);
       RPB_LAUNCHED(ctx);
-      RPB_TRY(matvec_batched(ctx, p, b, g, t, nullptr, v.done, u, stream));
+      RPB_TRY(product(t, v.done, known, u));
       divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
       RPB_LAUNCHED(ctx);
     } else {
-      RPB_TRY(matvec_batched(ctx, p, b, g, vk, nullptr, v.done, u, stream));
+      RPB_TRY(product(vk, v.done, known, u));
     }
     RPB_TRY(seg_dot(vk, u, f_alpha + k - 1, 0));
     seg_three_term<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, u, vk, vprev);
@@ -646,11 +646,12 @@ int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const
       bool all = true;
       for (int s = 0; s < nsys && all; ++s) all = host_done[s] != 0;
       if (all) break;
+      known = host_done;
     }
   }
   seg_basis_combine<<<nblk(m3), kThreads, 0, stream>>>(v, m3, V, out);
   RPB_LAUNCHED(ctx);
-  if (precond) {
+  if (L) {
     multiply_by<<<nblk(m3), kThreads, 0, stream>>>(m3, out, L);
     RPB_LAUNCHED(ctx);
   }
@@ -662,6 +663,27 @@ int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const
     RPB_HIP(ctx, hipStreamSynchronize(stream));
   }
   return RPB_OK;
+}
+
+}  // namespace
+
+int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
+                        const double *w, double tol, int max_iter, bool precond, double *out,
+                        bool sync_each, LzStatus *status_host, hipStream_t stream) {
+  const int64_t m3 = 3 * b.n;
+  double *L = nullptr, *t = nullptr;
+  if (precond) {
+    int st;
+    L = static_cast<double *>(workspace(ctx, WS_PRECOND, size_t(2 * m3) * sizeof(double), &st));
+    if (!L) return st;
+    t = L + m3;
+    RPB_TRY(block_diag_scale(ctx, p, g, L, stream));
+  }
+  auto product = [&](const double *src, const int *done_dev, const int *, double *dst) {
+    return matvec_batched(ctx, p, b, g, src, nullptr, done_dev, dst, stream);
+  };
+  return lanczos_segments(ctx, b, L, t, w, tol, max_iter, product, out, sync_each, status_host,
+                          stream);
 }
 
 int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStream_t stream) {
@@ -770,4 +792,50 @@ extern "C" int lanczos_sqrt_apply_batched(rpb_ctx *ctx, const rpb_params *p, int
     if (eps_out) eps_out[s] = stat[s].eps;
   }
   return lanczos_status_code(ctx, stat, nsys);
+}
+
+extern "C" int lanczos_sqrt_apply_multi(rpb_ctx *ctx, const rpb_params *p, int64_t n,
+                                        const double *pos, int32_t nvec, const double *w,
+                                        double tol, int max_iter, double *out, int *iters_out,
+                                        double *eps_out, rpb_stream_t stream_) {
+  RPB_TRY(check_params(ctx, p));
+  if (n < 0) return fail(ctx, RPB_EINVAL, "n must be >= 0");
+  if (nvec < 0 || nvec > kMaxBatchSystems)
+    return fail(ctx, RPB_EINVAL, "nvec must be in [0, %d]", kMaxBatchSystems);
+  if (p->lx > 0.0)
+    return fail(ctx, RPB_EINVAL, "pseudo-periodic boundaries are not supported for "
+                                 "multi-vector products");
+  if (!(tol > 0.0)) return fail(ctx, RPB_EINVAL, "tol must be > 0");
+  if (max_iter < 1 || max_iter > kMaxKrylov)
+    return fail(ctx, RPB_EINVAL, "max_iter must be in [1, %d]", kMaxKrylov);
+  for (int s = 0; s < nvec; ++s) {
+    if (iters_out) iters_out[s] = 0;
+    if (eps_out) eps_out[s] = 0.0;
+  }
+  if (n == 0 || nvec == 0) return RPB_OK;
+  if (!pos || !w || !out) return fail(ctx, RPB_EINVAL, "pos, w and out must not be NULL");
+  const size_t pb = size_t(n) * 3 * sizeof(double), vb = pb * size_t(nvec);
+  if (overlaps(out, vb, pos, pb) || overlaps(out, vb, w, vb))
+    return fail(ctx, RPB_EINVAL, "out overlaps an input");
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  RPB_HIP(ctx, hipSetDevice(ctx->device));
+  RPB_TRY(check_finite(ctx, pos, n, stream));
+  // vector v is segment v of a batch of nvec segments of n spheres each
+  std::vector<int64_t> offs(size_t(nvec) + 1);
+  for (int s = 0; s <= nvec; ++s) offs[size_t(s)] = int64_t(s) * n;
+  Batch b;
+  RPB_TRY(prepare_batch(ctx, nvec, offs.data(), p->precision, &b, stream, false));
+  Packed g;
+  RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
+  auto product = [&](const double *src, const int *, const int *done_host, double *dst) {
+    return matvec_multi(ctx, p, g, nvec, done_host, src, dst, stream);
+  };
+  LzStatus *stat = static_cast<LzStatus *>(host_scratch(ctx));
+  RPB_TRY(lanczos_segments(ctx, b, nullptr, nullptr, w, tol, max_iter, product, out, true, stat,
+                           stream));
+  for (int s = 0; s < nvec; ++s) {
+    if (iters_out) iters_out[s] = stat[s].m;
+    if (eps_out) eps_out[s] = stat[s].eps;
+  }
+  return lanczos_status_code(ctx, stat, nvec);
 }

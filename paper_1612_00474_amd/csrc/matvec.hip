@@ -1072,7 +1072,7 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
 // ---- batched -----------------------------------------------------------------------------
 
 int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
-                  hipStream_t stream) {
+                  hipStream_t stream, bool work_items) {
   const Shape &shape = ctx->tune.s[precision == RPB_FP64 ? RPB_FP64 : RPB_MIXED];
   const int tpt = shape.batch_tpt;
   const int64_t chunk = shape.batch_chunk;
@@ -1090,7 +1090,7 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
   const int64_t per = int64_t(kBlock) * tpt;
   std::vector<int64_t> part_base(size_t(nsys), 0);
   int64_t part_elems = 0;
-  for (int s = 0; s < nsys; ++s) {
+  for (int s = 0; s < nsys && work_items; ++s) {
     const int64_t ns = offs[s + 1] - offs[s];
     if (b->symmetric) {
       const int64_t nt = (ns + per - 1) / per;
@@ -1122,7 +1122,7 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
   b->nitems = int(items.size());
   b->max_chunks = max_chunks;
   std::vector<int2> tiles;
-  for (int s = 0; s < nsys; ++s)
+  for (int s = 0; s < nsys && work_items; ++s)
     for (int64_t t = 0; t * kBlock < offs[s + 1] - offs[s]; ++t) tiles.push_back(int2{s, int(t)});
   b->ntiles = int(tiles.size());
 

@@ -177,13 +177,22 @@ struct Batch {
 };
 
 int check_offsets(rpb_ctx *ctx, int32_t nsys, const int64_t *offs);
+// work_items = false builds the offsets and the sphere -> system map only (for segment-wise
+// vector kernels), no pair or steric work items.
 int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
-                  hipStream_t stream);
+                  hipStream_t stream, bool work_items = true);
 // Batched product for packed geometry `g` (all systems); systems with done[s] != 0 are
 // skipped (their output rows are left untouched).  `done` may be NULL.
 int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
                    const double *force, const double *torque, const int *done, double *vel,
                    hipStream_t stream);
+
+// ---- multi-vector products (multi.hip) --------------------------------------------------
+
+// vel[v] = M force[v] for the nvec vectors force[v] ([n][3] float64 each, v-major) of packed
+// geometry `g`; vectors with done[v] != 0 (host array, nullable) are skipped.
+int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, const int *done,
+                 const double *force, double *vel, hipStream_t stream);
 
 // ---- vector kernels (lanczos.hip) -------------------------------------------------------
 constexpr int kMaxBatchSystems = 4096;   // per-system records must fit the pinned scratch
