@@ -211,6 +211,10 @@ struct SymCoef {
   Real A;                // cI + c1/|R| (coefficient of F)
   Real c2, c3, c4, c5;   // wall basis
   Real X, hh;            // a^2/|R|^2, z~_j/|R| (torque coupling)
+  // The wall tensor applied to F, with s = dx F_x + dy F_y:
+  //   u_x,y = A F_x,y + (b1 s + b2 F_z) (dx, dy),   u_z = A F_z + z1 s + z2 F_z,
+  // and its transpose swaps b2 and z1.
+  Real b1, b2, z1, z2;
 };
 
 template <typename Real, bool FAR_ONLY, bool TORQUE, bool WALL>
@@ -283,6 +287,18 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
   c.c4 = hh2x - ez * q;
   c.c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
   c.A = cI + iR * c1;
+  // Expanding the basis {I, e e^T, e z^T, z e^T, z z^T} (e = R/|R|) and the unbounded r r^T
+  // term over (dx, dy, dz): with w = c2 R_z/|R|^3,
+  //   b1 = cRR + c2/|R|^3,  b2 = cRR dz + w + c3/|R|^2,  z1 = cRR dz + w + c4/|R|^2,
+  //   z2 = cRR dz^2 + w R_z + (c3 + c4) R_z/|R|^2 + c5/|R|.
+  const Real iR3 = iR * iR2;
+  const Real w = (c.c2 * iR3) * Rz;
+  const Real crdz = cRR * dz;
+  const Real base = crdz + w;
+  c.b1 = c.c2 * iR3 + cRR;
+  c.b2 = c.c3 * iR2 + base;
+  c.z1 = c.c4 * iR2 + base;
+  c.z2 = crdz * dz + (w * Rz + ((c.c3 + c.c4) * iR2 * Rz + c.c5 * iR));
   c.iR2 = iR2;
   c.ez = ez;
   c.X = X;
@@ -314,36 +330,26 @@ __device__ __forceinline__ void sym_apply(const SymCoef<Real> &c, Real fx, Real 
     return;
   }
   // i <- j
-  const Real rhoF = dx * fx + dy * fy;
-  const Real rF = rhoF + dz * fz;
-  const Real eF = (rhoF + c.Rz * fz) * c.iR;
-  const Real G = c.c2 * eF + c.c3 * fz;
-  const Real H = c.c4 * eF + c.c5 * fz;
-  const Real cr = c.cRR * rF;
-  const Real B = cr + c.iR2 * G;
+  const Real s = dx * fx + dy * fy;
+  const Real B = c.b1 * s + c.b2 * fz;
   ox += c.A * fx;
   ox += B * dx;
   oy += c.A * fy;
   oy += B * dy;
   oz += c.A * fz;
-  oz += cr * dz;
-  oz += c.iR * (G * c.ez + H);
+  oz += c.z1 * s;
+  oz += c.z2 * fz;
 
-  // j <- i (transposed tensor)
-  const Real rhoG = dx * gx + dy * gy;
-  const Real rG = rhoG + dz * gz;
-  const Real eG = (rhoG + c.Rz * gz) * c.iR;
-  const Real G2 = c.c2 * eG + c.c4 * gz;
-  const Real H2 = c.c3 * eG + c.c5 * gz;
-  const Real cr2 = c.cRR * rG;
-  const Real B2 = cr2 + c.iR2 * G2;
+  // j <- i (transposed tensor: b2 and z1 swap)
+  const Real s2 = dx * gx + dy * gy;
+  const Real B2 = c.b1 * s2 + c.z1 * gz;
   px += c.A * gx;
   px += B2 * dx;
   py += c.A * gy;
   py += B2 * dy;
   pz += c.A * gz;
-  pz += cr2 * dz;
-  pz += c.iR * (G2 * c.ez + H2);
+  pz += c.b2 * s2;
+  pz += c.z2 * gz;
 }
 
 // The coupling terms of both directions, (o) += M^C_ij T_j and (p) += M^C_ji T_i (tq: T_j,
@@ -422,20 +428,15 @@ __device__ __forceinline__ void sym_apply_one(const SymCoef<Real> &c, Real fx, R
     oz += cr * dz;
     return;
   }
-  const Real rhoF = dx * fx + dy * fy;
-  const Real rF = rhoF + dz * fz;
-  const Real eF = (rhoF + c.Rz * fz) * c.iR;
-  const Real G = c.c2 * eF + c.c3 * fz;
-  const Real H = c.c4 * eF + c.c5 * fz;
-  const Real cr = c.cRR * rF;
-  const Real B = cr + c.iR2 * G;
+  const Real s = dx * fx + dy * fy;
+  const Real B = c.b1 * s + c.b2 * fz;
   ox += c.A * fx;
   ox += B * dx;
   oy += c.A * fy;
   oy += B * dy;
   oz += c.A * fz;
-  oz += cr * dz;
-  oz += c.iR * (G * c.ez + H);
+  oz += c.z1 * s;
+  oz += c.z2 * fz;
 }
 
 // Both directions of one unordered pair (force and, with TORQUE, torque sources).
