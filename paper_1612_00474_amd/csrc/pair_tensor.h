@@ -209,7 +209,6 @@ struct SymCoef {
   Real iR, iR2, ez;      // 1/|R|, 1/|R|^2, e_z
   Real cI, cRR, cT;      // unbounded: cI F + cRR r (r.F), rotation cT T x r
   Real A;                // cI + c1/|R| (coefficient of F)
-  Real c2, c3, c4, c5;   // wall basis
   Real X, hh;            // a^2/|R|^2, z~_j/|R| (torque coupling)
   // The wall tensor applied to F, with s = dx F_x + dy F_y:
   //   u_x,y = A F_x,y + (b1 s + b2 F_z) (dx, dy),   u_z = A F_z + z1 s + z2 F_z,
@@ -269,36 +268,40 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
   c.cT = cT;
   if (!WALL) return;
 
+  // Wall tensor in the basis {I, e e^T, e z^T, z e^T, z z^T}, e = R/|R|, with X = a^2/|R|^2,
+  // Y = X^2, h = z~_j/|R|, t = h (h - e_z), p = 2X - 10Y/3, q = 20Y/3, m = e_z^2 (q - 5p):
+  //   c1 = e_z^2 p + 2t - 2(X - Y)/3 - 1,  c2 = m - 6t + p - 1,
+  //   c3 = e_z (q - 2p - 2m) + 12 e_z t + 2h,  c4 = 2h - e_z q,
+  //   c5 = Y (20 e_z^2 - 8/3) - 4 (h^2 + X e_z^2).
+  // Expanded over (dx, dy, dz) together with the unbounded r r^T term, only these enter:
+  //   A = cI + c1/|R|,  b1 = cRR + c2/|R|^3,  b2 = cRR dz + (c2 e_z + c3)/|R|^2,
+  //   z1 = cRR dz + (c2 e_z + c4)/|R|^2,  z2 = cRR dz^2 + (c2 e_z^2 + (c3 + c4) e_z + c5)/|R|,
+  // and with g = m - 6t + p, u = e_z (g - q):
+  //   c2 e_z + c3 = 2h - e_z - u,  c2 e_z + c4 = 2h - e_z + u,
+  //   c2 e_z^2 + (c3 + c4) e_z + c5 = e_z^2 (6t - m + 70Y/3 - 6X - 1) - 4t - 8Y/3.
   const Real iR2 = iR * iR;
   const Real X = k.a2 * iR2;
   const Real Y = X * X;
   const Real ez = Rz * iR;
   const Real hh = zj * iR;
   const Real ez2 = ez * ez;
-  const Real hme = hh - ez;
-  const Real t = hh * hme;
+  const Real t = hh * (hh - ez);
   const Real p = X * (Real(2) - Real(10.0 / 3.0) * X);
   const Real q = Real(20.0 / 3.0) * Y;
-  const Real hh2x = Real(2) * hh;
+  const Real m = ez2 * (q - Real(5) * p);
   const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
-  const Real m1 = ez2 * (q - Real(5) * p);   // shared by c2 and c3 (10p - 2q = -2(q - 5p))
-  c.c2 = m1 + (Real(-6) * t + (p - Real(1)));
-  c.c3 = ez * ((q - Real(2) * p) + Real(-2) * m1) + (Real(12) * (ez * t) + hh2x);
-  c.c4 = hh2x - ez * q;
-  c.c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
+  const Real g = m + (Real(-6) * t + p);
+  const Real u = ez * (g - q);
+  const Real h2e = Real(2) * hh - ez;
+  const Real bx = ez2 * ((Real(6) * t - m) + (Real(70.0 / 3.0) * Y - (Real(6) * X + Real(1)))) -
+                  (Real(4) * t + Real(8.0 / 3.0) * Y);
   c.A = cI + iR * c1;
-  // Expanding the basis {I, e e^T, e z^T, z e^T, z z^T} (e = R/|R|) and the unbounded r r^T
-  // term over (dx, dy, dz): with w = c2 R_z/|R|^3,
-  //   b1 = cRR + c2/|R|^3,  b2 = cRR dz + w + c3/|R|^2,  z1 = cRR dz + w + c4/|R|^2,
-  //   z2 = cRR dz^2 + w R_z + (c3 + c4) R_z/|R|^2 + c5/|R|.
   const Real iR3 = iR * iR2;
-  const Real w = (c.c2 * iR3) * Rz;
   const Real crdz = cRR * dz;
-  const Real base = crdz + w;
-  c.b1 = c.c2 * iR3 + cRR;
-  c.b2 = c.c3 * iR2 + base;
-  c.z1 = c.c4 * iR2 + base;
-  c.z2 = crdz * dz + (w * Rz + ((c.c3 + c.c4) * iR2 * Rz + c.c5 * iR));
+  c.b1 = (g - Real(1)) * iR3 + cRR;
+  c.b2 = (h2e - u) * iR2 + crdz;
+  c.z1 = (h2e + u) * iR2 + crdz;
+  c.z2 = crdz * dz + bx * iR;
   c.iR2 = iR2;
   c.ez = ez;
   c.X = X;
