@@ -33,6 +33,7 @@ FLOPS_PER_PAIR_TORQUE = 147  # source carries a force and a torque (deterministi
 PEAK_FP32_TFLOPS = 157.3     # 256 CU x 128 FP32 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
 KIND_FP64_FORCE, KIND_FP64_TORQUE, KIND_MIXED_FORCE, KIND_MIXED_TORQUE = 0, 1, 2, 3
+KIND_MULTI_FP64, KIND_MULTI_MIXED = 8, 10   # multi-vector kernel (pairs counted per vector)
 
 
 PROFILED_N = 65536   # sheet size of the committed counter summary
@@ -46,7 +47,7 @@ def measured_traffic(kernel: str, n: int = PROFILED_N):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1612_00474_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("matvec.hip", "pair_tensor.h"):
+    for name in ("matvec.hip", "multi.hip", "pair_common.h", "pair_tensor.h"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     current = h.hexdigest()[:16]
@@ -163,6 +164,28 @@ def main():
     mixed_rate, mixed_ms = kernel_rate("mixed")
     f64_rate, f64_ms = kernel_rate("fp64")
 
+    # ---- multi-vector product: four force vectors of this configuration per launch -------
+    FF = torch.as_tensor(np.random.default_rng(7).standard_normal((4, w.n, 3))).cuda()
+
+    def multi_rate(precision, reps=3):
+        kind = KIND_MULTI_MIXED if precision == "mixed" else KIND_MULTI_FP64
+        one = KIND_MIXED_FORCE if precision == "mixed" else KIND_FP64_FORCE
+        ctx.matvec_multi(pos0, FF, precision)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.timing_read()
+        for _ in range(reps):
+            ctx.matvec_multi(pos0, FF, precision)
+            ctx.matvec(pos0, FF[0], None, precision)
+        ms, launches, pairs = ctx.timing_read(kind)
+        ms1, launches1, pairs1 = ctx.timing_read(one)
+        ctx.timing(False)
+        rate, rate1 = pairs / (ms * 1e-3), pairs1 / (ms1 * 1e-3)
+        return {"vector_pairs_per_s": rate, "ms_per_launch": ms / launches,
+                "single_vector_pairs_per_s": rate1, "speedup_per_vector": rate / rate1}
+
+    multi = {"vectors_per_launch": 4, "mixed": multi_rate("mixed"), "fp64": multi_rate("fp64")}
+
     # ---- time steps ----------------------------------------------------------------------
     state = StepState(pos0.clone())
     iters = []
@@ -227,6 +250,7 @@ def main():
                                f"products ({FLOPS_PER_PAIR_FORCE} flop/pair x {n}^2 pairs/launch)",
                      "ms_per_launch": dom["ms_per_launch"], "launches": dom["launches"]},
         "pair_kernels": kinds,
+        "multi_vector_product": multi,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

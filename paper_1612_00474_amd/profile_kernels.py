@@ -3,8 +3,8 @@
 Tunes the launch shapes on one synthetic sheet of N spheres (as the benchmark does), then
 launches one plain device-to-device copy of known size (to calibrate the HBM byte counters
 FETCH_SIZE / WRITE_SIZE against a kernel whose traffic is known) followed by `--reps`
-launches of each pair-kernel variant and of the steric force kernel.  Only the dispatches
-after the copy count:
+launches of each pair-kernel variant, of the multi-vector kernel (four vectors per launch)
+and of the steric force kernel.  Only the dispatches after the copy count:
 
     rocprofv3 --kernel-trace --stats -d OUT -o run -- python -m paper_1612_00474_amd.profile_kernels
     rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch -- python -m paper_1612_00474_amd.profile_kernels
@@ -59,6 +59,11 @@ def main():
             for _ in range(args.reps):
                 ctx.matvec(pos, F, torque, precision)
             launches.append({"precision": precision, "torque": torque is not None, "reps": args.reps})
+    FF = torch.as_tensor(rng.standard_normal((4, args.n, 3))).cuda()
+    for precision in ("mixed", "fp64"):
+        for _ in range(args.reps):
+            ctx.matvec_multi(pos, FF, precision)
+        launches.append({"precision": precision, "multi_vector": 4, "reps": args.reps})
     for _ in range(args.reps):
         ctx.forces(pos, f_grav_z=-1.0, u0=1.0, b=0.1)
     launches.append({"kernel": "steric", "reps": args.reps})
