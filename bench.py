@@ -209,6 +209,12 @@ def main():
             kinds[name] = {"launches": k, "ms_per_launch": ms / k,
                            "pairs_per_s": pairs / (ms * 1e-3),
                            "tflops": fpp * pairs / (ms * 1e-3) / 1e12}
+    # the two-vector launch of each step: M F + M_C T together with the first Lanczos product
+    for name, kind in (("fp64_two_vector", KIND_MULTI_FP64), ("mixed_two_vector", KIND_MULTI_MIXED)):
+        ms, k, pairs = ctx.timing_read(kind)
+        if k:
+            kinds[name] = {"launches": k, "ms_per_launch": ms / k,
+                           "vector_pairs_per_s": pairs / (ms * 1e-3)}
     ctx.timing(False)
     timed_iters = iters[args.warmup:]
     n = w.n

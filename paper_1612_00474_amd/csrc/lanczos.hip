@@ -471,7 +471,7 @@ int dot(rpb_ctx *ctx, int64_t m, const double *a, const double *b, double *part,
 
 int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *w, double tol,
                 int max_iter, bool precond, double *out, int *iters, double *eps_out,
-                hipStream_t stream) {
+                hipStream_t stream, const double *mw) {
   const int64_t n = g.n;
   const int64_t m3 = 3 * n;
   int st;
@@ -513,6 +513,9 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
       RPB_LAUNCHED(ctx);
       RPB_TRY(matvec_packed(ctx, p, g, t, nullptr, 0, n, u, stream));
       divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
+      RPB_LAUNCHED(ctx);
+    } else if (m == 1 && mw) {   // M v_1 = (M w) / |w| from the caller's product
+      scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, mw, &ls->wnorm, u, nullptr);
       RPB_LAUNCHED(ctx);
     } else {
       RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream));

@@ -24,39 +24,54 @@ namespace rpb {
 
 namespace {
 
-constexpr int kMulti = 4;            // source vectors per launch (fewer: zero vectors pad)
-constexpr int kMultiC = 3 * kMulti;  // source components per sphere
+constexpr int kMulti = 4;   // source vectors per launch of the plain multi-vector product
 // Largest partial buffer of one launch; larger systems use the single-vector product per vector.
 constexpr size_t kMaxMultiPartialBytes = size_t(32) << 30;
 
-struct VecIds {
-  int v[kMulti];   // vector of each launch slot, -1 for a zero vector
+// Source rows of a launch of K vectors: forces of slots 0..K-1 (3 each), then, with TQ, the
+// torque of slot 0.
+template <int K, bool TQ>
+constexpr int src_rows() { return 3 * K + (TQ ? 3 : 0); }
+
+template <int K>
+struct SrcPtrs {
+  const double *p[K];   // [n][3] source vector of each launch slot, NULL for a zero vector
+};
+template <int K>
+struct OutPtrs {
+  double *p[K];         // [n][3] result of each slot, NULL: not stored
 };
 
-template <typename Real>
-__global__ void pack_multi(int64_t n, VecIds ids, const double *__restrict__ h,
-                           const double *__restrict__ f, Real *__restrict__ out) {
+// src[e n + i]: e = 3 k + c holds H_i F_k(i, c); with a torque, e = 3 K + c holds H_i T(i, c)
+// for slot 0.
+template <int K, typename Real>
+__global__ void pack_multi(int64_t n, SrcPtrs<K> in, const double *__restrict__ h,
+                           const double *__restrict__ torque, Real *__restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double w = h[i];
 #pragma unroll
-  for (int k = 0; k < kMulti; ++k) {
-    const int v = ids.v[k];
+  for (int k = 0; k < K; ++k) {
+    const double *f = in.p[k];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      out[(k * 3 + c) * n + i] = v >= 0 ? Real(w * f[(int64_t(v) * n + i) * 3 + c]) : Real(0);
+    for (int c = 0; c < 3; ++c) out[(k * 3 + c) * n + i] = f ? Real(w * f[3 * i + c]) : Real(0);
   }
+  if (torque)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[(3 * K + c) * n + i] = Real(w * torque[3 * i + c]);
 }
 
+template <int K, bool TQ>
 struct MultiLdsF {
   float xh[kBlock], xl[kBlock], yh[kBlock], yl[kBlock], z[kBlock];
-  float f[kMultiC][kBlock];
-  float col[kWaves][kMultiC][64];   // per-wavefront sums for one 64-source block
+  float f[src_rows<K, TQ>()][kBlock];
+  float col[kWaves][3 * K][64];   // per-wavefront sums for one 64-source block
 };
+template <int K, bool TQ>
 struct MultiLdsD {
   double x[kBlock], y[kBlock], z[kBlock];
-  double f[kMultiC][kBlock];
-  double col[kWaves][kMultiC][64];
+  double f[src_rows<K, TQ>()][kBlock];
+  double col[kWaves][3 * K][64];
 };
 
 struct TgtF {
@@ -72,25 +87,29 @@ __device__ __forceinline__ TgtF target_of(const GeomF &g, int64_t i) {
 __device__ __forceinline__ TgtD target_of(const GeomD &g, int64_t i) {
   return {g.x[i], g.y[i], g.z[i]};
 }
-__device__ __forceinline__ void stage(MultiLdsF &L, const GeomF &g, int64_t j, int s) {
+template <typename Lds>
+__device__ __forceinline__ void stage(Lds &L, const GeomF &g, int64_t j, int s) {
   L.xh[s] = g.xh[j];
   L.xl[s] = g.xl[j];
   L.yh[s] = g.yh[j];
   L.yl[s] = g.yl[j];
   L.z[s] = g.z[j];
 }
-__device__ __forceinline__ void stage(MultiLdsD &L, const GeomD &g, int64_t j, int s) {
+template <typename Lds>
+__device__ __forceinline__ void stage(Lds &L, const GeomD &g, int64_t j, int s) {
   L.x[s] = g.x[j];
   L.y[s] = g.y[j];
   L.z[s] = g.z[j];
 }
 // In-plane separation r_i - r_j (mixed: hi and lo parts subtracted separately).
-__device__ __forceinline__ void separation(const TgtF &t, const MultiLdsF &L, int j, float &dx,
+template <typename Lds>
+__device__ __forceinline__ void separation(const TgtF &t, const Lds &L, int j, float &dx,
                                            float &dy) {
   dx = (t.xh - L.xh[j]) + (t.xl - L.xl[j]);
   dy = (t.yh - L.yh[j]) + (t.yl - L.yl[j]);
 }
-__device__ __forceinline__ void separation(const TgtD &t, const MultiLdsD &L, int j, double &dx,
+template <typename Lds>
+__device__ __forceinline__ void separation(const TgtD &t, const Lds &L, int j, double &dx,
                                            double &dy) {
   dx = t.x - L.x[j];
   dy = t.y - L.y[j];
@@ -98,38 +117,43 @@ __device__ __forceinline__ void separation(const TgtD &t, const MultiLdsD &L, in
 
 // Coefficients of pair (i, j): the far-field form alone for pairs at least 2a apart, the
 // complete form for closer ones (including the self pair, r = 0).
-template <bool WALL, typename Real>
+template <bool TQ, bool WALL, typename Real>
 __device__ __forceinline__ void multi_coefficients(Real dx, Real dy, Real zi, Real zj,
                                                    const PairConsts<Real> &k, SymCoef<Real> &c) {
   const Real dz = zi - zj;
   if (dx * dx + dy * dy + dz * dz < k.four_a2)
-    sym_coefficients<Real, false, false, WALL>(dx, dy, zi, zj, k, c);
+    sym_coefficients<Real, false, TQ, WALL>(dx, dy, zi, zj, k, c);
   else
-    sym_coefficients<Real, true, false, WALL>(dx, dy, zi, zj, k, c);
+    sym_coefficients<Real, true, TQ, WALL>(dx, dy, zi, zj, k, c);
 }
 
 // One rotation step of an off-diagonal tile pair: the lane's target i against source j for
-// every vector, M_ij F_j into acc and M_ji F_i into the rotating sums cs (weighted forces zero
-// when !valid).
-template <bool WALL, typename Real, typename Tgt, typename Lds>
+// every vector, M_ij F_j into acc and M_ji F_i into the rotating sums cs (weighted sources
+// zero when !valid); with TQ, slot 0 adds the coupling M^C_ij T_j and M^C_ji T_i.
+template <int K, bool TQ, bool WALL, typename Real, typename Tgt, typename Lds>
 __device__ __forceinline__ void multi_step(const Lds &L, int j, bool valid, const Tgt &t,
-                                           const Real (&own)[kMultiC], const PairConsts<Real> &k,
-                                           Real (&acc)[kMultiC], Real (&cs)[kMultiC]) {
+                                           const Real (&own)[src_rows<K, TQ>()],
+                                           const PairConsts<Real> &k, Real (&acc)[3 * K],
+                                           Real (&cs)[3 * K]) {
+  constexpr int R = src_rows<K, TQ>();
   Real dx, dy;
   separation(t, L, j, dx, dy);
   const Real zj = L.z[j];
-  Real f[kMultiC];
+  Real f[R];
 #pragma unroll
-  for (int e = 0; e < kMultiC; ++e) f[e] = valid ? L.f[e][j] : Real(0);
+  for (int e = 0; e < R; ++e) f[e] = valid ? L.f[e][j] : Real(0);
 #pragma unroll
-  for (int e = 0; e < kMultiC; ++e) cs[e] = wave_rol1(cs[e]);
+  for (int e = 0; e < 3 * K; ++e) cs[e] = wave_rol1(cs[e]);
   SymCoef<Real> c;
-  multi_coefficients<WALL>(dx, dy, t.z, zj, k, c);
+  multi_coefficients<TQ, WALL>(dx, dy, t.z, zj, k, c);
 #pragma unroll
-  for (int v = 0; v < kMulti; ++v)
+  for (int v = 0; v < K; ++v)
     sym_apply<Real, WALL>(c, f[3 * v], f[3 * v + 1], f[3 * v + 2], own[3 * v], own[3 * v + 1],
                           own[3 * v + 2], acc[3 * v], acc[3 * v + 1], acc[3 * v + 2], cs[3 * v],
                           cs[3 * v + 1], cs[3 * v + 2]);
+  if (TQ)
+    sym_apply_torque<Real, WALL>(c, t.z, f + 3 * K, own + 3 * K, acc[0], acc[1], acc[2], cs[0],
+                                 cs[1], cs[2]);
 }
 
 // partial[(((v nt + T) nt + P) 3 + comp) kBlock + local]: tile pair (T, P)'s sums for the rows
@@ -140,12 +164,13 @@ __device__ __forceinline__ int64_t multi_slot(const SymArgs &a, int v, int64_t T
 }
 
 // Tile pair (I, J), I <= J.  Every lane of the workgroup must call this (it synchronises).
-template <bool WALL, typename Real, typename Geom, typename Lds>
+template <int K, bool TQ, bool WALL, typename Real, typename Geom, typename Lds>
 __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
                                                 const Real *__restrict__ src,
                                                 const PairConsts<Real> &k,
                                                 double *__restrict__ partial, int64_t I,
                                                 int64_t J, Lds &L) {
+  constexpr int R = src_rows<K, TQ>();
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t n = a.n;
@@ -157,47 +182,53 @@ __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
   if (tid < cnt) {
     stage(L, g, jb + tid, tid);
 #pragma unroll
-    for (int e = 0; e < kMultiC; ++e) L.f[e][tid] = src[e * a.stride + jb + tid];
+    for (int e = 0; e < R; ++e) L.f[e][tid] = src[e * a.stride + jb + tid];
   }
   __syncthreads();
-  Real acc[kMultiC];
+  Real acc[3 * K];
 #pragma unroll
-  for (int e = 0; e < kMultiC; ++e) acc[e] = Real(0);
+  for (int e = 0; e < 3 * K; ++e) acc[e] = Real(0);
   if (I == J) {   // ordered pairs of the diagonal tile, self pair included
     for (int j = 0; j < cnt; ++j) {
       Real dx, dy;
       separation(t, L, j, dx, dy);
       SymCoef<Real> c;
-      multi_coefficients<WALL>(dx, dy, t.z, L.z[j], k, c);
+      multi_coefficients<TQ, WALL>(dx, dy, t.z, L.z[j], k, c);
 #pragma unroll
-      for (int v = 0; v < kMulti; ++v)
+      for (int v = 0; v < K; ++v)
         sym_apply_one<Real, WALL>(c, L.f[3 * v][j], L.f[3 * v + 1][j], L.f[3 * v + 2][j],
                                   acc[3 * v], acc[3 * v + 1], acc[3 * v + 2]);
+      if (TQ) {   // one direction: the target's own torque does not enter
+        const Real tq[3] = {L.f[3 * K][j], L.f[3 * K + 1][j], L.f[3 * K + 2][j]};
+        const Real none[3] = {Real(0), Real(0), Real(0)};
+        Real px = Real(0), py = Real(0), pz = Real(0);
+        sym_apply_torque<Real, WALL>(c, t.z, tq, none, acc[0], acc[1], acc[2], px, py, pz);
+      }
     }
   } else {
-    Real own[kMultiC];
+    Real own[R];
 #pragma unroll
-    for (int e = 0; e < kMultiC; ++e) own[e] = on ? src[e * a.stride + i] : Real(0);
+    for (int e = 0; e < R; ++e) own[e] = on ? src[e * a.stride + i] : Real(0);
     for (int blk = 0; blk < cnt; blk += 64) {
       const int nb = min(64, cnt - blk);
-      Real cs[kMultiC];
+      Real cs[3 * K];
 #pragma unroll
-      for (int e = 0; e < kMultiC; ++e) cs[e] = Real(0);
+      for (int e = 0; e < 3 * K; ++e) cs[e] = Real(0);
       if (nb == 64) {
         for (int step = 0; step < 64; ++step)
-          multi_step<WALL>(L, blk + ((lane + step) & 63), true, t, own, k, acc, cs);
+          multi_step<K, TQ, WALL>(L, blk + ((lane + step) & 63), true, t, own, k, acc, cs);
       } else {
         for (int step = 0; step < 64; ++step) {
           const int sl = (lane + step) & 63;
-          multi_step<WALL>(L, blk + (sl < nb ? sl : 0), sl < nb, t, own, k, acc, cs);
+          multi_step<K, TQ, WALL>(L, blk + (sl < nb ? sl : 0), sl < nb, t, own, k, acc, cs);
         }
       }
       // after 64 rotations lane l holds the sums of source (l + 63) mod 64
       const int sl = (lane + 63) & 63;
 #pragma unroll
-      for (int e = 0; e < kMultiC; ++e) L.col[wave][e][sl] = cs[e];
+      for (int e = 0; e < 3 * K; ++e) L.col[wave][e][sl] = cs[e];
       __syncthreads();
-      for (int e0 = tid; e0 < kMultiC * 64; e0 += kBlock) {
+      for (int e0 = tid; e0 < 3 * K * 64; e0 += kBlock) {
         const int e = e0 / 64, s = e0 % 64;
         if (s < nb) {
           double sum = 0.0;
@@ -211,46 +242,46 @@ __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
   }
   if (on)
 #pragma unroll
-    for (int e = 0; e < kMultiC; ++e)
+    for (int e = 0; e < 3 * K; ++e)
       partial[multi_slot(a, e / 3, I, J, e % 3, tid)] = double(acc[e]);
 }
 
-template <bool WALL>
+template <int K, bool TQ, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi(SymArgs a, GeomF g,
                                                                   const float *__restrict__ src,
                                                                   PairConsts<float> k,
                                                                   double *__restrict__ partial) {
-  __shared__ MultiLdsF L;
+  __shared__ MultiLdsF<K, TQ> L;
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  multi_tile_pair<WALL>(a, g, src, k, partial, I, J, L);
+  multi_tile_pair<K, TQ, WALL>(a, g, src, k, partial, I, J, L);
 }
 
-template <bool WALL>
+template <int K, bool TQ, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_multi(SymArgs a, GeomD g,
                                                                 const double *__restrict__ src,
                                                                 PairConsts<double> k,
                                                                 double *__restrict__ partial) {
-  __shared__ MultiLdsD L;
+  __shared__ MultiLdsD<K, TQ> L;
   int64_t I, J;
   tri_decode(blockIdx.x, a.nt, I, J);
-  multi_tile_pair<WALL>(a, g, src, k, partial, I, J, L);
+  multi_tile_pair<K, TQ, WALL>(a, g, src, k, partial, I, J, L);
 }
 
 // One thread per (vector slot, component, row); four independent partial sums over the
-// slots (P mod 4), combined in a fixed order.
-__global__ void reduce_multi(SymArgs a, VecIds ids, const double *__restrict__ partial,
-                             const double *__restrict__ h, double scale,
-                             double *__restrict__ vel) {
+// slots (P mod 4), combined in a fixed order.  Slot v's result goes to out.p[v] ([n][3]).
+template <int K>
+__global__ void reduce_multi(SymArgs a, OutPtrs<K> out, const double *__restrict__ partial,
+                             const double *__restrict__ h, double scale) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t per = 3 * a.n;
-  if (e >= kMulti * per) return;
+  if (e >= K * per) return;
   const int v = int(e / per);
   const int64_t rem = e - int64_t(v) * per;
   const int d = int(rem / a.n);
   const int64_t r = rem - int64_t(d) * a.n;
-  const int id = ids.v[v];
-  if (id < 0) return;
+  double *dst = out.p[v];
+  if (!dst) return;
   const int64_t T = r / kBlock, local = r % kBlock;
   const double *base = partial + multi_slot(a, v, T, 0, d, local);
   const int64_t stride = 3 * kBlock;   // slot (T, P) to (T, P + 1)
@@ -263,7 +294,72 @@ __global__ void reduce_multi(SymArgs a, VecIds ids, const double *__restrict__ p
     s3 += base[(P + 3) * stride];
   }
   for (; P < a.nt; ++P) s0 += base[P * stride];
-  vel[(int64_t(id) * a.n + r) * 3 + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
+  dst[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
+}
+
+size_t multi_partial_bytes(int K, int64_t nt) {
+  return size_t(K) * size_t(nt) * size_t(nt) * 3 * size_t(kBlock) * sizeof(double);
+}
+
+// One launch of K vectors: sources in.p[k] (slot 0 with torque `torque` when TQ), results to
+// out.p[k].
+template <int K, bool TQ>
+int multi_launch(rpb_ctx *ctx, const rpb_params *p, const Packed &g, SrcPtrs<K> in,
+                 const double *torque, OutPtrs<K> out, hipStream_t stream) {
+  const int64_t n = g.n;
+  const bool f64 = g.precision == RPB_FP64;
+  SymArgs a{n, kBlock, (n + kBlock - 1) / kBlock, n};
+  int st;
+  double *part =
+      static_cast<double *>(workspace(ctx, WS_PART, multi_partial_bytes(K, a.nt), &st));
+  if (!part) return st;
+  const size_t esz = f64 ? sizeof(double) : sizeof(float);
+  void *src = workspace(ctx, WS_SRC, size_t(src_rows<K, TQ>()) * size_t(n) * esz, &st);
+  if (!src) return st;
+  const double *h = f64 ? geom_d(g).h : geom_f(g).h;
+  const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2);
+  int used = 0;
+  for (int s = 0; s < K; ++s) used += in.p[s] != nullptr || (s == 0 && TQ);
+  const double *tq = TQ ? torque : nullptr;
+  if (f64)
+    pack_multi<K, double><<<blocks_for(n, 256), 256, 0, stream>>>(n, in, h, tq,
+                                                                 static_cast<double *>(src));
+  else
+    pack_multi<K, float><<<blocks_for(n, 256), 256, 0, stream>>>(n, in, h, tq,
+                                                                static_cast<float *>(src));
+  RPB_LAUNCHED(ctx);
+  hipEvent_t t0;
+  RPB_TRY(timing_begin(ctx, stream, &t0));
+  const bool wall = p->wall != 0;
+  if (f64) {
+    const auto k = make_pair_consts<double>(p->a);
+    const auto *s = static_cast<const double *>(src);
+    if (wall)
+      pair_kernel_f64_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
+    else
+      pair_kernel_f64_multi<K, TQ, false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
+  } else {
+    const auto k = make_pair_consts<float>(p->a);
+    const auto *s = static_cast<const float *>(src);
+    if (wall)
+      pair_kernel_mixed_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), s, k, part);
+    else
+      pair_kernel_mixed_multi<K, TQ, false><<<grid, kBlock, 0, stream>>>(a, geom_f(g), s, k,
+                                                                         part);
+  }
+  RPB_LAUNCHED(ctx);
+  RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n) * used, 8 + (f64 ? 0 : 2)));
+  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  reduce_multi<K><<<blocks_for(int64_t(K) * 3 * n, 256), 256, 0, stream>>>(a, out, part, h,
+                                                                            scale);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
+// One launch can hold the problem (grid and partial-buffer limits).
+bool multi_fits(int K, int64_t n) {
+  const int64_t nt = (n + kBlock - 1) / kBlock;
+  return nt * (nt + 1) / 2 <= 0x7fffffffll && multi_partial_bytes(K, nt) <= kMaxMultiPartialBytes;
 }
 
 }  // namespace
@@ -278,65 +374,40 @@ int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, c
   std::vector<int> ids;
   for (int v = 0; v < nvec; ++v)
     if (!done || !done[v]) ids.push_back(v);
-  const bool f64 = g.precision == RPB_FP64;
-  SymArgs a{n, kBlock, (n + kBlock - 1) / kBlock, n};
-  const size_t part_bytes =
-      size_t(kMulti) * size_t(a.nt) * size_t(a.nt) * 3 * size_t(kBlock) * sizeof(double);
-  if (a.nt * (a.nt + 1) / 2 > 0x7fffffffll || part_bytes > kMaxMultiPartialBytes) {
+  if (!multi_fits(kMulti, n)) {
     // too large for one launch: one single-vector product per vector
     for (int v : ids)
       RPB_TRY(matvec_packed(ctx, p, g, force + size_t(v) * 3 * n, nullptr, 0, n,
                             vel + size_t(v) * 3 * n, stream));
     return RPB_OK;
   }
-  int st;
-  double *part = static_cast<double *>(workspace(ctx, WS_PART, part_bytes, &st));
-  if (!part) return st;
-  const size_t esz = f64 ? sizeof(double) : sizeof(float);
-  void *src = workspace(ctx, WS_SRC, size_t(kMultiC) * size_t(n) * esz, &st);
-  if (!src) return st;
-  const double *h = f64 ? geom_d(g).h : geom_f(g).h;
-  const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2);
-  const double scale = 1.0 / (8.0 * M_PI * p->eta);
-  const bool wall = p->wall != 0;
   for (size_t g0 = 0; g0 < ids.size(); g0 += kMulti) {
-    VecIds vi;
-    int used = 0;
+    SrcPtrs<kMulti> in;
+    OutPtrs<kMulti> out;
     for (int s = 0; s < kMulti; ++s) {
-      vi.v[s] = g0 + s < ids.size() ? ids[g0 + s] : -1;
-      used += vi.v[s] >= 0;
+      const bool on = g0 + s < ids.size();
+      const size_t off = on ? size_t(ids[g0 + s]) * 3 * n : 0;
+      in.p[s] = on ? force + off : nullptr;
+      out.p[s] = on ? vel + off : nullptr;
     }
-    if (f64)
-      pack_multi<double><<<blocks_for(n, 256), 256, 0, stream>>>(n, vi, h, force,
-                                                                static_cast<double *>(src));
-    else
-      pack_multi<float><<<blocks_for(n, 256), 256, 0, stream>>>(n, vi, h, force,
-                                                               static_cast<float *>(src));
-    RPB_LAUNCHED(ctx);
-    hipEvent_t t0;
-    RPB_TRY(timing_begin(ctx, stream, &t0));
-    if (f64) {
-      const auto k = make_pair_consts<double>(p->a);
-      const auto *s = static_cast<const double *>(src);
-      if (wall)
-        pair_kernel_f64_multi<true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
-      else
-        pair_kernel_f64_multi<false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
-    } else {
-      const auto k = make_pair_consts<float>(p->a);
-      const auto *s = static_cast<const float *>(src);
-      if (wall)
-        pair_kernel_mixed_multi<true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), s, k, part);
-      else
-        pair_kernel_mixed_multi<false><<<grid, kBlock, 0, stream>>>(a, geom_f(g), s, k, part);
-    }
-    RPB_LAUNCHED(ctx);
-    RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n) * used, 8 + (f64 ? 0 : 2)));
-    reduce_multi<<<blocks_for(int64_t(kMulti) * 3 * n, 256), 256, 0, stream>>>(a, vi, part, h,
-                                                                               scale, vel);
-    RPB_LAUNCHED(ctx);
+    RPB_TRY((multi_launch<kMulti, false>(ctx, p, g, in, nullptr, out, stream)));
   }
   return RPB_OK;
+}
+
+bool matvec_pair_supported(const rpb_params *p, int64_t n) {
+  return p->lx <= 0.0 && n > 0 && multi_fits(2, n);
+}
+
+int matvec_pair(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
+                const double *torque, const double *w, double *u_force, double *u_w,
+                hipStream_t stream) {
+  if (!matvec_pair_supported(p, g.n))
+    return fail(ctx, RPB_EINVAL, "two-vector product not available for this configuration");
+  const SrcPtrs<2> in{{force, w}};
+  const OutPtrs<2> out{{u_force, u_w}};
+  if (torque) return multi_launch<2, true>(ctx, p, g, in, torque, out, stream);
+  return multi_launch<2, false>(ctx, p, g, in, nullptr, out, stream);
 }
 
 }  // namespace rpb

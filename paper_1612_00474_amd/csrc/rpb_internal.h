@@ -193,6 +193,13 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
 // geometry `g`; vectors with done[v] != 0 (host array, nullable) are skipped.
 int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, const int *done,
                  const double *force, double *vel, hipStream_t stream);
+// u_force = M force + M_C torque and u_w = M w in one launch (the pair coefficients shared);
+// torque nullable.  Available when matvec_pair_supported(p, n) (no box, partials within the
+// workspace limit).
+bool matvec_pair_supported(const rpb_params *p, int64_t n);
+int matvec_pair(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
+                const double *torque, const double *w, double *u_force, double *u_w,
+                hipStream_t stream);
 
 // ---- vector kernels (lanczos.hip) -------------------------------------------------------
 constexpr int kMaxBatchSystems = 4096;   // per-system records must fit the pinned scratch
@@ -221,10 +228,11 @@ int lanczos_status_code(rpb_ctx *ctx, const LzStatus *s, int nsys);
 int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStream_t stream);
 
 // precond: square-root preconditioning with the self-block diagonal (block_diag_scale):
-// Lanczos on B = L^-1 M L^-1, result L B^{1/2} w.
+// Lanczos on B = L^-1 M L^-1, result L B^{1/2} w.  mw (nullable, only without precond): the
+// product M w computed by the caller, which then replaces the first iteration's product.
 int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *w, double tol,
                 int max_iter, bool precond, double *out, int *iters, double *eps,
-                hipStream_t stream);
+                hipStream_t stream, const double *mw = nullptr);
 
 // ---- RFD / RNG / forces / step ----------------------------------------------------------
 int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, const double *wt,

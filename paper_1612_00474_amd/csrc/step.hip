@@ -204,13 +204,22 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   RPB_LAUNCHED(ctx);
   Packed geo;
   RPB_TRY(pack_geometry(ctx, p, n, state->pos, WS_GEOM, &geo, stream));
-  RPB_TRY(matvec_packed(ctx, p, geo, F, T, 0, n, u, stream));
+  // M F + M_C T and the first Lanczos product M W share the configuration: one two-vector
+  // launch evaluates each pair's coefficients once for both
+  double *mw = nullptr;
+  if (cfg->lanczos_precond == 0 && matvec_pair_supported(p, n)) {
+    mw = static_cast<double *>(workspace(ctx, WS_VEC_B, nb, &st));
+    if (!mw) return st;
+    RPB_TRY(matvec_pair(ctx, p, geo, F, T, W, u, mw, stream));
+  } else {
+    RPB_TRY(matvec_packed(ctx, p, geo, F, T, 0, n, u, stream));
+  }
 
   // Brownian increment (the last iterate is used if the tolerance is not met)
   int iters = 0;
   double eps = 0.0;
   const int lz = lanczos_run(ctx, p, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter,
-                             cfg->lanczos_precond != 0, g, &iters, &eps, stream);
+                             cfg->lanczos_precond != 0, g, &iters, &eps, stream, mw);
   if (lz != RPB_OK && lz != RPB_ENOCONV) return lz;
 
   // stochastic drift
