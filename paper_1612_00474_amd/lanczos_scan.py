@@ -7,9 +7,11 @@ tolerance does not grow with N; in free space (unscreened 1/r interactions) it d
 driver measures both on the synthetic sheets (area fraction 0.4, heights uniform in
 [1.1, 2.5]) for several N and tolerances, with the same noise vector in every mode.  Sec. II.C
 also reports that a block-diagonal preconditioner (wall self-terms) gives only a very small
-improvement; the second mode measures that:
+improvement; the second mode measures that.  ``--recipe sedimented`` uses instead the
+configuration of the paper's convergence study (area fraction 0.25, heights with an
+exponential profile of mean 1.6a, no overlaps; ``workloads.sedimented_sheet``):
 
-    python -m paper_1612_00474_amd.lanczos_scan [--sizes 1024 4096 16384 65536]
+    python -m paper_1612_00474_amd.lanczos_scan [--sizes 1024 4096 16384 65536] [--recipe sedimented]
 
 Prints one JSON line per (N, mode) and a final summary line.
 """
@@ -30,6 +32,7 @@ def main():
     ap.add_argument("--sizes", type=int, nargs="+", default=[1024, 4096, 16384, 65536])
     ap.add_argument("--tols", type=float, nargs="+", default=[1e-3, 1e-5])
     ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--recipe", choices=["sheet", "sedimented"], default="sheet")
     args = ap.parse_args()
 
     import numpy as np
@@ -44,10 +47,11 @@ def main():
              "free space": (Context(0, wall=False), False)}
     rows = []
     for n in args.sizes:
-        pos = torch.as_tensor(wl.sheet(n, seed=0)).cuda()
+        host = wl.sheet(n, seed=0) if args.recipe == "sheet" else wl.sedimented_sheet(n, seed=0)
+        pos = torch.as_tensor(host).cuda()
         w = torch.as_tensor(np.random.default_rng(1).standard_normal((n, 3))).cuda()
         for mode, (ctx, precond) in modes.items():
-            row = {"n": n, "mode": mode, "precision": args.precision}
+            row = {"n": n, "mode": mode, "recipe": args.recipe, "precision": args.precision}
             for tol in args.tols:
                 g, it, eps, st = ctx.lanczos(pos, w, tol, max_iter=64, precision=args.precision,
                                              allow_noconv=True, precond=precond)

@@ -151,3 +151,45 @@ def sheet(n: int, z_lo: float = 1.1, z_hi: float = 2.5, phi: float = PHI, seed: 
     """A uniform sheet of ``n`` spheres at area fraction ``phi`` (positions only)."""
     s = substreams(seed)
     return sample_positions(n, side_for_area_fraction(n, phi), z_lo, z_hi, rng=s[STREAM_POS])
+
+
+def sedimented_sheet(n: int, phi: float = 0.25, h_mean: float = 1.6, h_min: float = 1.1,
+                     seed: int = 0, a: float = 1.0) -> np.ndarray:
+    """A sedimented-looking sheet: x, y at projected area fraction ``phi``, heights
+    h_min + Exp(h_mean - h_min) (mean ``h_mean``, the exponential profile of a gravitational
+    height over the wall), no two centres closer than 2a (random sequential addition on a
+    cell grid).  Stands in for the equilibrium states of the Lanczos convergence study
+    (phi = 0.25, characteristic height 1.6a)."""
+    rng = substreams(seed)[STREAM_POS]
+    side = side_for_area_fraction(n, phi, a)
+    d2 = (2.0 * a) ** 2
+    cell = 2.0 * a
+    nc = max(1, int(side // cell))
+    grid = {}
+    out = np.empty((n, 3))
+    k = tries = 0
+    while k < n:
+        tries += 1
+        if tries > 200 * n + 1000:
+            raise RuntimeError("random sequential addition did not place all spheres")
+        x, y = rng.uniform(0.0, side, 2)
+        z = h_min + rng.exponential(h_mean - h_min)
+        cx, cy = int(x / side * nc) % nc, int(y / side * nc) % nc
+        ok = True
+        for ix in (cx - 1, cx, cx + 1):
+            for iy in (cy - 1, cy, cy + 1):
+                for j in grid.get((ix % nc, iy % nc), ()):
+                    q = out[j]
+                    if (q[0] - x) ** 2 + (q[1] - y) ** 2 + (q[2] - z) ** 2 < d2:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if not ok:
+            continue
+        out[k] = (x, y, z)
+        grid.setdefault((cx, cy), []).append(k)
+        k += 1
+    return out
