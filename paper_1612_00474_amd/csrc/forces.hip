@@ -4,9 +4,13 @@
 // the centre distance for sphere pairs, d = a and r = z for the wall (absent in free space);
 // the force is -grad U, magnitude U0/b or (U0/b) exp(-(r - d)/b), repulsive.  Gravity adds
 // f_g along z.  Pairs farther than d + 40 b are skipped (their force is below 4.3e-18 U0/b).
-// Brute-force O(N^2) distance tests over LDS tiles, float64 throughout, unclamped positions,
-// minimum-image separations in a pseudo-periodic box (App. B); the sources are split over
-// workgroups and the chunk sums added in a fixed order (deterministic).
+// Float64 throughout, unclamped positions, minimum-image separations in a pseudo-periodic box
+// (App. B).  Two ways to find the pairs:
+//   * cell list (default): spheres binned into cubic cells of side >= d + 40 b, cells hashed
+//     to buckets, buckets filled and then sorted by sphere index, each target visiting the 27
+//     neighbouring cells in a fixed order: O(N) work, deterministic sums;
+//   * all pairs over LDS tiles (a pseudo-periodic box with fewer than three cells per side):
+//     the sources split over workgroups and the chunk sums added in a fixed order.
 #include <algorithm>
 #include <cmath>
 
@@ -150,28 +154,294 @@ __global__ __launch_bounds__(kBlock) void steric_finish(int64_t n, int nchunks,
   force[e] = acc;
 }
 
-// One workgroup per (system, tile of kBlock targets) item, against all of the system's spheres.
-__global__ __launch_bounds__(kBlock) void steric_kernel_batched(const int64_t *__restrict__ offs,
-                                                                const int2 *__restrict__ tiles,
-                                                                const double *__restrict__ pos,
-                                                                double a, double u0, double b,
-                                                                double f_grav_z, int wall,
-                                                                double *__restrict__ force) {
-  const int2 tl = tiles[blockIdx.x];
-  const int64_t s0 = offs[tl.x], s1 = offs[tl.x + 1];
-  steric_tile<1, true>(pos, s0 + int64_t(tl.y) * kBlock, s1, s0, s1, a, u0, b, 0.0, 0.0, f_grav_z,
-                       wall, force);
+// ---- cell list ------------------------------------------------------------------------
+
+struct CellArgs {
+  double cs;            // cell side along z (and x, y without a box), >= the cutoff
+  double csx, csy;      // cell sides along x, y in a box (lx / ncx, ly / ncy)
+  double lx, ly;        // box (0: none)
+  int ncx, ncy;         // cells per box side (0: none)
+  uint32_t mask;        // buckets - 1 (a power of two minus one)
+};
+
+__device__ __forceinline__ int clamp_cell(double v) {
+  return int(fmin(fmax(floor(v), -1073741824.0), 1073741823.0));
+}
+
+// Cell of a position (x, y wrapped into the box when there is one).
+__device__ __forceinline__ int3 cell_of(double x, double y, double z, const CellArgs &c) {
+  int cx, cy;
+  if (c.ncx > 0) {
+    const double xw = x - c.lx * floor(x / c.lx), yw = y - c.ly * floor(y / c.ly);
+    cx = min(max(int(xw / c.csx), 0), c.ncx - 1);
+    cy = min(max(int(yw / c.csy), 0), c.ncy - 1);
+  } else {
+    cx = clamp_cell(x / c.cs);
+    cy = clamp_cell(y / c.cs);
+  }
+  return make_int3(cx, cy, clamp_cell(z / c.cs));
+}
+
+__device__ __forceinline__ uint32_t bucket_of(int3 q, int sys, uint32_t mask) {
+  const uint32_t h = (uint32_t(q.x) * 73856093u) ^ (uint32_t(q.y) * 19349663u) ^
+                     (uint32_t(q.z) * 83492791u) ^ (uint32_t(sys) * 2654435761u);
+  return h & mask;
+}
+
+__global__ void cells_clear(int64_t nb, int *__restrict__ count) {
+  const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (h < nb) count[h] = 0;
+}
+
+// Cell (and system) of every sphere; bucket occupancy counts.
+__global__ void cells_count(int64_t n, const double *__restrict__ pos,
+                            const int *__restrict__ sys_of, CellArgs c, int4 *__restrict__ cell,
+                            uint32_t *__restrict__ bucket, int *__restrict__ count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int3 q = cell_of(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], c);
+  const int sys = sys_of ? sys_of[i] : 0;
+  const uint32_t b = bucket_of(q, sys, c.mask);
+  cell[i] = make_int4(q.x, q.y, q.z, sys);
+  bucket[i] = b;
+  atomicAdd(count + b, 1);
+}
+
+// Exclusive prefix sum of the bucket counts into start, in three passes over blocks of kBlock
+// buckets (block sums, their scan, then each block's own scan); clears the fill cursors.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *tmp) {
+  const int tid = threadIdx.x;
+  tmp[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int add = tid >= off ? tmp[tid - off] : 0;
+    __syncthreads();
+    tmp[tid] += add;
+    __syncthreads();
+  }
+  const int incl = tmp[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void cells_block_sums(int64_t nb,
+                                                           const int *__restrict__ count,
+                                                           int *__restrict__ bsum) {
+  __shared__ int tmp[kBlock];
+  const int64_t h = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int v = h < nb ? count[h] : 0;
+  const int ex = block_exclusive_scan(v, tmp);
+  if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = ex + v;
+}
+
+// One workgroup: exclusive scan of the nblk block sums in place (nblk <= kBlock * per).
+__global__ __launch_bounds__(kBlock) void cells_scan_sums(int nblk, int *__restrict__ bsum) {
+  __shared__ int tmp[kBlock];
+  const int per = (nblk + kBlock - 1) / kBlock;
+  const int b0 = min(nblk, int(threadIdx.x) * per), b1 = min(nblk, b0 + per);
+  int s = 0;
+  for (int k = b0; k < b1; ++k) s += bsum[k];
+  int run = block_exclusive_scan(s, tmp);
+  for (int k = b0; k < b1; ++k) {
+    const int v = bsum[k];
+    bsum[k] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void cells_block_scan(int64_t nb,
+                                                           const int *__restrict__ count,
+                                                           const int *__restrict__ bsum,
+                                                           int *__restrict__ start,
+                                                           int *__restrict__ cursor) {
+  __shared__ int tmp[kBlock];
+  const int64_t h = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int v = h < nb ? count[h] : 0;
+  const int ex = block_exclusive_scan(v, tmp);
+  if (h < nb) {
+    start[h] = bsum[blockIdx.x] + ex;
+    cursor[h] = 0;
+  }
+}
+
+__global__ void cells_fill(int64_t n, const uint32_t *__restrict__ bucket,
+                           const int *__restrict__ start, int *__restrict__ cursor,
+                           int *__restrict__ list) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t b = bucket[i];
+  list[start[b] + atomicAdd(cursor + b, 1)] = int(i);
+}
+
+// Sort every bucket's entries by sphere index (heap sort: O(k log k) however full a bucket
+// is), so that the order in which a target meets its neighbours depends on the input only.
+__global__ void cells_sort(int64_t nb, const int *__restrict__ start, const int *__restrict__ count,
+                           int *__restrict__ list) {
+  const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (h >= nb) return;
+  int *a = list + start[h];
+  const int k = count[h];
+  if (k < 2) return;
+  if (k <= 16) {   // insertion sort for the usual few entries
+    for (int u = 1; u < k; ++u) {
+      const int v = a[u];
+      int w = u - 1;
+      while (w >= 0 && a[w] > v) {
+        a[w + 1] = a[w];
+        --w;
+      }
+      a[w + 1] = v;
+    }
+    return;
+  }
+  auto sift = [a](int root, int end) {
+    while (true) {
+      int child = 2 * root + 1;
+      if (child >= end) return;
+      if (child + 1 < end && a[child + 1] > a[child]) ++child;
+      if (a[root] >= a[child]) return;
+      const int t = a[root];
+      a[root] = a[child];
+      a[child] = t;
+      root = child;
+    }
+  };
+  for (int r = k / 2 - 1; r >= 0; --r) sift(r, k);
+  for (int end = k - 1; end > 0; --end) {
+    const int t = a[0];
+    a[0] = a[end];
+    a[end] = t;
+    sift(0, end);
+  }
+}
+
+// One thread per target: the 27 neighbouring cells in a fixed order, each bucket's spheres
+// of that cell (and system) in index order; then the wall force and gravity.
+__global__ void steric_cells(int64_t n, const double *__restrict__ pos, CellArgs c,
+                             const int4 *__restrict__ cell, const int *__restrict__ start,
+                             const int *__restrict__ count, const int *__restrict__ list,
+                             double a, double u0, double b, double f_grav_z, int wall,
+                             double *__restrict__ force) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = 2.0 * a;
+  const double cut = d + 40.0 * b;
+  const double cut2 = cut * cut;
+  const double fmax_ = u0 / b;
+  const double inv_b = 1.0 / b;
+  const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  const int4 me = cell[i];
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int oz = -1; oz <= 1; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        int3 q = make_int3(me.x + ox, me.y + oy, me.z + oz);
+        if (c.ncx > 0) {
+          q.x = (q.x + c.ncx) % c.ncx;
+          q.y = (q.y + c.ncy) % c.ncy;
+        }
+        const uint32_t h = bucket_of(q, me.w, c.mask);
+        const int s0 = start[h], s1 = s0 + count[h];
+        for (int s = s0; s < s1; ++s) {
+          const int j = list[s];
+          const int4 cj = cell[j];
+          if (cj.x != q.x || cj.y != q.y || cj.z != q.z || cj.w != me.w || j == i) continue;
+          double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1];
+          const double dz = zi - pos[3 * j + 2];
+          if (c.lx > 0.0) {   // minimum image
+            dx -= c.lx * rint(dx / c.lx);
+            dy -= c.ly * rint(dy / c.ly);
+          }
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 < cut2 && r2 > 0.0) {
+            const double r = sqrt(r2);
+            const double fm = r < d ? fmax_ : fmax_ * exp(-(r - d) * inv_b);
+            const double sc = fm / r;
+            fx += sc * dx;
+            fy += sc * dy;
+            fz += sc * dz;
+          }
+        }
+      }
+  if (wall) fz += zi < a ? fmax_ : fmax_ * exp(-(zi - a) / b);
+  fz += f_grav_z;
+  force[3 * i] = fx;
+  force[3 * i + 1] = fy;
+  force[3 * i + 2] = fz;
+}
+
+// Cell side and layout for cutoff `cut`; false when a box holds fewer than three cells per
+// side (the neighbour cells would then wrap onto each other).
+bool cell_args(double cut, double lx, double ly, int64_t n, CellArgs *c) {
+  c->cs = cut;
+  c->lx = lx;
+  c->ly = ly;
+  c->ncx = c->ncy = 0;
+  c->csx = c->csy = cut;
+  if (lx > 0.0) {
+    const double nx = std::floor(lx / cut), ny = std::floor(ly / cut);
+    if (nx < 3.0 || ny < 3.0) return false;
+    c->ncx = int(std::min(nx, 65536.0));
+    c->ncy = int(std::min(ny, 65536.0));
+    c->csx = lx / c->ncx;
+    c->csy = ly / c->ncy;
+  }
+  uint64_t nb = 1024;
+  while (nb < uint64_t(2 * n)) nb <<= 1;
+  c->mask = uint32_t(nb - 1);
+  return true;
+}
+
+// Forces of all spheres (sys_of: sphere -> system map of a batch, NULL for one system).
+int steric_cell_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                    const int *sys_of, const CellArgs &c, double f_grav_z, double u0, double b,
+                    double *force, hipStream_t stream) {
+  const int64_t nb = int64_t(c.mask) + 1;
+  const size_t cell_bytes = (size_t(n) * sizeof(int4) + 255) / 256 * 256;
+  const size_t n_bytes = (size_t(n) * sizeof(int) + 255) / 256 * 256;
+  const size_t nb_bytes = (size_t(nb) * sizeof(int) + 255) / 256 * 256;
+  int st;
+  const int64_t nblk = (nb + kBlock - 1) / kBlock;
+  const size_t blk_bytes = (size_t(nblk) * sizeof(int) + 255) / 256 * 256;
+  char *w = static_cast<char *>(
+      workspace(ctx, WS_CELLS, cell_bytes + 2 * n_bytes + 3 * nb_bytes + blk_bytes, &st));
+  if (!w) return st;
+  int4 *cell = reinterpret_cast<int4 *>(w);
+  uint32_t *bucket = reinterpret_cast<uint32_t *>(w + cell_bytes);
+  int *list = reinterpret_cast<int *>(w + cell_bytes + n_bytes);
+  int *count = reinterpret_cast<int *>(w + cell_bytes + 2 * n_bytes);
+  int *start = count + nb_bytes / sizeof(int);
+  int *cursor = start + nb_bytes / sizeof(int);
+  int *bsum = cursor + nb_bytes / sizeof(int);
+  const unsigned gn = unsigned((n + kBlock - 1) / kBlock), gb = unsigned((nb + kBlock - 1) / kBlock);
+  cells_clear<<<gb, kBlock, 0, stream>>>(nb, count);
+  RPB_LAUNCHED(ctx);
+  cells_count<<<gn, kBlock, 0, stream>>>(n, pos, sys_of, c, cell, bucket, count);
+  RPB_LAUNCHED(ctx);
+  cells_block_sums<<<gb, kBlock, 0, stream>>>(nb, count, bsum);
+  RPB_LAUNCHED(ctx);
+  cells_scan_sums<<<1, kBlock, 0, stream>>>(int(gb), bsum);
+  RPB_LAUNCHED(ctx);
+  cells_block_scan<<<gb, kBlock, 0, stream>>>(nb, count, bsum, start, cursor);
+  RPB_LAUNCHED(ctx);
+  cells_fill<<<gn, kBlock, 0, stream>>>(n, bucket, start, cursor, list);
+  RPB_LAUNCHED(ctx);
+  cells_sort<<<gb, kBlock, 0, stream>>>(nb, start, count, list);
+  RPB_LAUNCHED(ctx);
+  steric_cells<<<gn, kBlock, 0, stream>>>(n, pos, c, cell, start, count, list, p->a, u0, b,
+                                          f_grav_z, p->wall, force);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
 }
 
 }  // namespace
 
 int forces_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const double *pos,
                        double f_grav_z, double u0, double b, double *force, hipStream_t stream) {
-  if (bt.ntiles <= 0) return RPB_OK;
-  steric_kernel_batched<<<unsigned(bt.ntiles), kBlock, 0, stream>>>(
-      bt.offs, bt.tiles, pos, p->a, u0, b, f_grav_z, p->wall, force);
-  RPB_LAUNCHED(ctx);
-  return RPB_OK;
+  if (bt.n <= 0) return RPB_OK;
+  CellArgs c;
+  cell_args(2.0 * p->a + 40.0 * b, 0.0, 0.0, bt.n, &c);
+  return steric_cell_run(ctx, p, bt.n, pos, bt.sys_of, c, f_grav_z, u0, b, force, stream);
 }
 
 int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, double f_grav_z,
@@ -181,6 +451,10 @@ int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, 
   if (p->lx > 0.0 && (p->lx <= 2.0 * cut || p->ly <= 2.0 * cut))
     return fail(ctx, RPB_EINVAL, "box %g x %g too small for the minimum image (need > %g)", p->lx,
                 p->ly, 2.0 * cut);
+  CellArgs c;
+  if (cell_args(cut, p->lx, p->ly, n, &c))
+    return steric_cell_run(ctx, p, n, pos, nullptr, c, f_grav_z, u0, b, force, stream);
+  // a box with fewer than three cells per side: all pairs
   constexpr int kTargets = 2;
   const int64_t per = int64_t(kBlock) * kTargets;
   const int64_t tiles = (n + per - 1) / per;

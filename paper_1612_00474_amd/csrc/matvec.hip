@@ -1121,30 +1121,23 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
     max_chunks = std::max<int64_t>(max_chunks, (offs[s + 1] - offs[s] + chunk - 1) / chunk);
   b->nitems = int(items.size());
   b->max_chunks = max_chunks;
-  std::vector<int2> tiles;
-  for (int s = 0; s < nsys && work_items; ++s)
-    for (int64_t t = 0; t * kBlock < offs[s + 1] - offs[s]; ++t) tiles.push_back(int2{s, int(t)});
-  b->ntiles = int(tiles.size());
 
-  // device copies: offs (nsys + 1 int64), part_base (nsys int64), items, tiles, sys_of (n int32);
+  // device copies: offs (nsys + 1 int64), part_base (nsys int64), items, sys_of (n int32);
   // staged through pinned memory
   const size_t offs_bytes = size_t(2 * nsys + 1) * sizeof(int64_t);
   const size_t items_bytes = std::max<size_t>(1, items.size()) * sizeof(int4);
   const size_t offs_pad = (offs_bytes + 255) / 256 * 256;
   const size_t items_pad = (items_bytes + 255) / 256 * 256;
-  const size_t tiles_bytes = std::max<size_t>(1, tiles.size()) * sizeof(int2);
-  const size_t tiles_pad = (tiles_bytes + 255) / 256 * 256;
   const size_t sys_bytes = size_t(std::max<int64_t>(1, b->n)) * sizeof(int);
   int st;
   char *dev = static_cast<char *>(
-      workspace(ctx, WS_BATCH, offs_pad + items_pad + tiles_pad + sys_bytes, &st));
+      workspace(ctx, WS_BATCH, offs_pad + items_pad + sys_bytes, &st));
   if (!dev) return st;
   b->offs = reinterpret_cast<int64_t *>(dev);
   b->part_base = b->offs + nsys + 1;
   b->items = reinterpret_cast<int4 *>(dev + offs_pad);
-  b->tiles = reinterpret_cast<int2 *>(dev + offs_pad + items_pad);
-  b->sys_of = reinterpret_cast<int *>(dev + offs_pad + items_pad + tiles_pad);
-  const size_t host_bytes = offs_pad + items_pad + tiles_pad;
+  b->sys_of = reinterpret_cast<int *>(dev + offs_pad + items_pad);
+  const size_t host_bytes = offs_pad + items_pad;
   // the pinned staging buffer may still feed an earlier copy
   RPB_HIP(ctx, hipStreamSynchronize(stream));
   if (ctx->batch_host_bytes < host_bytes) {
@@ -1160,14 +1153,9 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
               size_t(nsys) * sizeof(int64_t));
   int4 *hi = reinterpret_cast<int4 *>(hb + offs_pad);
   for (size_t q = 0; q < order.size(); ++q) hi[q] = items[order[q]];
-  int2 *ht = reinterpret_cast<int2 *>(hb + offs_pad + items_pad);
-  std::copy(tiles.begin(), tiles.end(), ht);
   RPB_HIP(ctx, hipMemcpyAsync(b->offs, hb, offs_bytes, hipMemcpyHostToDevice, stream));
   if (!items.empty())
     RPB_HIP(ctx, hipMemcpyAsync(b->items, hi, items.size() * sizeof(int4), hipMemcpyHostToDevice,
-                                stream));
-  if (!tiles.empty())
-    RPB_HIP(ctx, hipMemcpyAsync(b->tiles, ht, tiles.size() * sizeof(int2), hipMemcpyHostToDevice,
                                 stream));
   fill_sys_of<<<unsigned(nsys), 256, 0, stream>>>(nsys, b->offs, b->sys_of);
   RPB_LAUNCHED(ctx);

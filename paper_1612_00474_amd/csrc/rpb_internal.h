@@ -39,6 +39,7 @@ enum Slot {
   WS_BATCH,         // batched products: offsets, work items, sphere -> system map
   WS_LZBATCH,       // batched Lanczos: per-system scalars and status
   WS_PRECOND,       // block-diagonal preconditioner: L (3n) and a scaled vector (3n)
+  WS_CELLS,         // steric cell list: cells, buckets, sorted lists, bucket counts and starts
   WS_NSLOTS
 };
 
@@ -169,8 +170,6 @@ struct Batch {
   int64_t *offs = nullptr;       // device
   int4 *items = nullptr;         // device
   int *sys_of = nullptr;         // device, n entries
-  int2 *tiles = nullptr;         // device: (system, 256-target tile) for the steric kernel
-  int ntiles = 0;
   bool symmetric = false;        // items are (system, I, J) tile pairs of the symmetric kernel
   int64_t *part_base = nullptr;  // device, nsys entries: each system's first partial slot
   int64_t part_elems = 0;        // partial doubles of the symmetric layout
@@ -178,7 +177,7 @@ struct Batch {
 
 int check_offsets(rpb_ctx *ctx, int32_t nsys, const int64_t *offs);
 // work_items = false builds the offsets and the sphere -> system map only (for segment-wise
-// vector kernels), no pair or steric work items.
+// vector kernels), no pair work items.
 int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
                   hipStream_t stream, bool work_items = true);
 // Batched product for packed geometry `g` (all systems); systems with done[s] != 0 are

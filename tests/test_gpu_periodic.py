@@ -88,3 +88,19 @@ def test_periodic_rejections(ctx):
     with pytest.raises(RpbError):
         bad.matvec(pos, F, None)
     bad.close()
+
+
+def test_periodic_forces_small_box(ctx):
+    # a box with fewer than three cells of the steric cutoff per side takes the all-pairs path
+    from paper_1612_00474_amd import Context
+    small_box = (14.0, 13.0)
+    c = Context(0, box=small_box)
+    try:
+        rng = np.random.default_rng(31)
+        pos = np.column_stack([rng.uniform(-3.0, 17.0, 40), rng.uniform(-2.0, 15.0, 40),
+                               rng.uniform(1.05, 2.5, 40)])
+        ref = forces.forces(pos, 1.0, 1.0, 0.1, -1.0, box=small_box)
+        f = host(c.forces(dev(pos), -1.0, 1.0, 0.1))
+        assert rel2(f, ref) <= 1e-12
+    finally:
+        c.close()

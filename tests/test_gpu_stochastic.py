@@ -129,3 +129,19 @@ def test_variant_error_paths(ctx, c1):
                                      C.c_void_p(Wt.data_ptr()), None, C.c_void_p(out.data_ptr()),
                                      _stream())
     assert st == RPB_EINVAL
+
+
+def test_forces_crowded_cells_tall_columns_negative_coordinates(ctx):
+    # the cell list: a heavily overlapping cluster (buckets of hundreds of spheres), a column
+    # spanning many cells in z, spheres at negative x, y; against the oracle and reproducible
+    rng = np.random.default_rng(21)
+    cluster = rng.uniform(0.0, 2.0, (300, 3)) + np.array([5.0, 5.0, 1.0])
+    column = np.column_stack([20.0 + rng.uniform(0.0, 0.5, 60), np.full(60, 20.0),
+                              np.linspace(1.0, 40.0, 60)])
+    spread = rng.uniform([-50.0, -50.0, 0.5], [50.0, 50.0, 3.0], (400, 3))
+    pos = np.vstack([cluster, column, spread])
+    ref = forces.forces(pos, 1.0, 1.0, 0.1, -1.0)
+    P = dev(pos)
+    f = host(ctx.forces(P, -1.0, 1.0, 0.1))
+    assert rel2(f, ref) <= 1e-12
+    assert np.array_equal(f, host(ctx.forces(P, -1.0, 1.0, 0.1)))
