@@ -27,43 +27,45 @@ namespace rpb {
 
 namespace {
 
-// With a wall: z~ = max(z, a) and H = clamp(z/a, 0, 1) (App. A); in free space: z~ = z, H = 1.
+// Positions in units of a.  With a wall: z~ = max(z, a) and H = clamp(z/a, 0, 1) (App. A); in
+// free space: z~ = z, H = 1.
 __global__ void pack_geometry_f64(int64_t n, const double *__restrict__ pos, double a, int wall,
                                   double *__restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double z = pos[3 * i + 2];
-  out[i] = pos[3 * i];
-  out[n + i] = pos[3 * i + 1];
-  out[2 * n + i] = wall ? fmax(z, a) : z;
-  out[3 * n + i] = wall ? fmin(fmax(z / a, 0.0), 1.0) : 1.0;
+  const double z = pos[3 * i + 2] / a;
+  out[i] = pos[3 * i] / a;
+  out[n + i] = pos[3 * i + 1] / a;
+  out[2 * n + i] = wall ? fmax(z, 1.0) : z;
+  out[3 * n + i] = wall ? fmin(fmax(z, 0.0), 1.0) : 1.0;
 }
 
 __global__ void pack_geometry_mixed(int64_t n, const double *__restrict__ pos, double a,
                                     int wall, double *__restrict__ hout, float *__restrict__ f) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  const double x = pos[3 * i] / a, y = pos[3 * i + 1] / a, z = pos[3 * i + 2] / a;
   const float xh = float(x), yh = float(y);
   f[i] = xh;
   f[n + i] = float(x - double(xh));
   f[2 * n + i] = yh;
   f[3 * n + i] = float(y - double(yh));
-  f[4 * n + i] = float(wall ? fmax(z, a) : z);
-  hout[i] = wall ? fmin(fmax(z / a, 0.0), 1.0) : 1.0;
+  f[4 * n + i] = float(wall ? fmax(z, 1.0) : z);
+  hout[i] = wall ? fmin(fmax(z, 0.0), 1.0) : 1.0;
 }
 
-// Source vectors, H-weighted, structure of arrays: [fx | fy | fz | tx | ty | tz] (n each).
+// Source vectors, H-weighted, structure of arrays: [fx | fy | fz | tx | ty | tz] (n each); the
+// torques divided by a (lengths in units of a).
 template <typename Real>
 __global__ void pack_vectors(int64_t n, const double *__restrict__ h,
                              const double *__restrict__ force, const double *__restrict__ torque,
-                             Real *__restrict__ out) {
+                             double inv_a, Real *__restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double w = h[i];
   for (int c = 0; c < 3; ++c) {
     out[c * n + i] = force ? Real(w * force[3 * i + c]) : Real(0);
-    if (torque) out[(3 + c) * n + i] = Real(w * torque[3 * i + c]);
+    if (torque) out[(3 + c) * n + i] = Real(w * inv_a * torque[3 * i + c]);
   }
 }
 
@@ -163,7 +165,7 @@ __device__ __forceinline__ void sources_f64(const GeomD &g, const double *__rest
       for (int q = 0; q < TPT; ++q) {
         for_images<PERIODIC>(T.x[q] - xj, T.y[q] - yj, k, [&](double dx, double dy) {
           const double dz = T.z[q] - zj;
-          if (dx * dx + dy * dy + dz * dz < k.four_a2)
+          if (dx * dx + dy * dy + dz * dz < kFourA2)
             pair_velocity<double, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty,
                                                        tz, k, T.u[q][0], T.u[q][1], T.u[q][2]);
           else
@@ -217,7 +219,7 @@ __device__ __forceinline__ void sources_mixed(const GeomF &g, const float *__res
         const float dy0 = (T.yh[q] - yjh) + (T.yl[q] - yjl);
         for_images<PERIODIC>(dx0, dy0, k, [&](float dx, float dy) {
           const float dz = T.z[q] - zj;
-          if (dx * dx + dy * dy + dz * dz < k.four_a2)
+          if (dx * dx + dy * dy + dz * dz < float(kFourA2))
             pair_velocity<float, TORQUE, false, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, tx, ty, tz,
                                                       k, a[q][0], a[q][1], a[q][2]);
           else
@@ -358,7 +360,7 @@ __device__ __forceinline__ void sym_step(const LdsF<TORQUE> &L, int j, bool vali
     const float dy0 = (T.yh[q] - yjh) + (T.yl[q] - yjl);
     for_images<PERIODIC>(dx0, dy0, k, [&](float dx, float dy) {
       const float dz = T.z[q] - zj;
-      if (dx * dx + dy * dy + dz * dz < k.four_a2)
+      if (dx * dx + dy * dy + dz * dz < float(kFourA2))
         pair_velocity_sym<float, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
                                                       own[q][1], own[q][2], k, acc[q][0],
                                                       acc[q][1], acc[q][2], cs[0], cs[1], cs[2],
@@ -391,7 +393,7 @@ __device__ __forceinline__ void sym_step(const LdsD<TORQUE> &L, int j, bool vali
   for (int q = 0; q < TPT; ++q) {
     for_images<PERIODIC>(T.x[q] - xj, T.y[q] - yj, k, [&](double dx, double dy) {
       const double dz = T.z[q] - zj;
-      if (dx * dx + dy * dy + dz * dz < k.four_a2)
+      if (dx * dx + dy * dy + dz * dz < kFourA2)
         pair_velocity_sym<double, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, own[q][0],
                                                        own[q][1], own[q][2], k, acc[q][0],
                                                        acc[q][1], acc[q][2], cs[0], cs[1], cs[2],
@@ -901,11 +903,11 @@ int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const doubl
   if (!*src) return st;
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
   if (f64)
-    pack_vectors<double><<<blocks_for(n, 256), 256, 0, stream>>>(n, h, force, torque,
-                                                                 static_cast<double *>(*src));
+    pack_vectors<double><<<blocks_for(n, 256), 256, 0, stream>>>(
+        n, h, force, torque, 1.0 / g.a, static_cast<double *>(*src));
   else
-    pack_vectors<float><<<blocks_for(n, 256), 256, 0, stream>>>(n, h, force, torque,
-                                                                static_cast<float *>(*src));
+    pack_vectors<float><<<blocks_for(n, 256), 256, 0, stream>>>(
+        n, h, force, torque, 1.0 / g.a, static_cast<float *>(*src));
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
@@ -936,6 +938,7 @@ int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *po
   void *buf = workspace(ctx, slot, geom_bytes(n, p->precision), &st);
   if (!buf) return st;
   out->n = n;
+  out->a = p->a;
   out->precision = p->precision;
   out->geom = buf;
   if (p->precision == RPB_FP64) {
@@ -954,8 +957,8 @@ int block_diag_scale(rpb_ctx *ctx, const rpb_params *p, const Packed &g, double 
                      hipStream_t stream) {
   const int64_t n = g.n;
   if (n == 0) return RPB_OK;
-  const auto k = make_pair_consts<double>(p->a);
-  const double inv = 1.0 / (8.0 * M_PI * p->eta);
+  const auto k = make_pair_consts<double>();
+  const double inv = 1.0 / (8.0 * M_PI * p->eta * p->a);
   const unsigned nb = blocks_for(n, 256);
   if (g.precision == RPB_FP64) {
     if (p->wall)
@@ -994,15 +997,15 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
     if (f64)
       pair_kernel_f64_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
           a, geom_d(g), static_cast<const double *>(src),
-          make_pair_consts<double>(p->a, p->lx, p->ly), part);
+          make_pair_consts<double>(p->lx / p->a, p->ly / p->a), part);
     else
       pair_kernel_mixed_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
           a, geom_f(g), static_cast<const float *>(src),
-          make_pair_consts<float>(p->a, p->lx, p->ly), part);
+          make_pair_consts<float>(p->lx / p->a, p->ly / p->a), part);
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), (f64 ? 0 : 2) + (torque ? 1 : 0)));
-  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   reduce_partials_sym<<<blocks_for(3 * n, 256), 256, 0, stream>>>(a, part, h, scale, vel);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
@@ -1052,17 +1055,17 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
     if (f64)
       pair_kernel_f64<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
           args, geom_d(g), static_cast<const double *>(src),
-          make_pair_consts<double>(p->a, p->lx, p->ly), part);
+          make_pair_consts<double>(p->lx / p->a, p->ly / p->a), part);
     else
       pair_kernel_mixed<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
           args, geom_f(g), static_cast<const float *>(src),
-          make_pair_consts<float>(p->a, p->lx, p->ly), part);
+          make_pair_consts<float>(p->lx / p->a, p->ly / p->a), part);
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(nrows) * double(n),
                      (f64 ? 0 : 2) + (has_t ? 1 : 0)));
 
-  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   reduce_partials<<<blocks_for(nrows, 256), 256, 0, stream>>>(nrows, int(nchunks), part,
                                                               h + row0, scale, vel);
   RPB_LAUNCHED(ctx);
@@ -1185,15 +1188,15 @@ int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const 
     constexpr int kP = decltype(P)::value;
     if (f64)
       pair_kernel_f64_sym_batched<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a),
+          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(),
           part);
     else
       pair_kernel_mixed_sym_batched<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(), part);
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
-  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   reduce_partials_sym_batched<<<blocks_for(3 * n, 256), 256, 0, stream>>>(args, b.sys_of, part,
                                                                           h, scale, vel);
   RPB_LAUNCHED(ctx);
@@ -1241,15 +1244,15 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
     constexpr int kP = decltype(P)::value;
     if (f64)
       pair_kernel_f64_batched<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(p->a),
+          args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(),
           part);
     else
       pair_kernel_mixed_batched<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(p->a), part);
+          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(), part);
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
-  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   reduce_partials_batched<<<blocks_for(n, 256), 256, 0, stream>>>(n, b.sys_of, b.offs, b.chunk,
                                                                  done, part, h, scale, vel);
   RPB_LAUNCHED(ctx);

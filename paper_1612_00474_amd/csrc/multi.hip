@@ -42,11 +42,12 @@ struct OutPtrs {
   double *p[K];         // [n][3] result of each slot, NULL: not stored
 };
 
-// src[e n + i]: e = 3 k + c holds H_i F_k(i, c); with a torque, e = 3 K + c holds H_i T(i, c)
+// src[e n + i]: e = 3 k + c holds H_i F_k(i, c); with a torque, e = 3 K + c holds H_i T(i, c)/a
 // for slot 0.
 template <int K, typename Real>
 __global__ void pack_multi(int64_t n, SrcPtrs<K> in, const double *__restrict__ h,
-                           const double *__restrict__ torque, Real *__restrict__ out) {
+                           const double *__restrict__ torque, double inv_a,
+                           Real *__restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double w = h[i];
@@ -58,7 +59,7 @@ __global__ void pack_multi(int64_t n, SrcPtrs<K> in, const double *__restrict__ 
   }
   if (torque)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out[(3 * K + c) * n + i] = Real(w * torque[3 * i + c]);
+    for (int c = 0; c < 3; ++c) out[(3 * K + c) * n + i] = Real(w * inv_a * torque[3 * i + c]);
 }
 
 template <int K, bool TQ>
@@ -121,7 +122,7 @@ template <bool TQ, bool WALL, typename Real>
 __device__ __forceinline__ void multi_coefficients(Real dx, Real dy, Real zi, Real zj,
                                                    const PairConsts<Real> &k, SymCoef<Real> &c) {
   const Real dz = zi - zj;
-  if (dx * dx + dy * dy + dz * dz < k.four_a2)
+  if (dx * dx + dy * dy + dz * dz < Real(kFourA2))
     sym_coefficients<Real, false, TQ, WALL>(dx, dy, zi, zj, k, c);
   else
     sym_coefficients<Real, true, TQ, WALL>(dx, dy, zi, zj, k, c);
@@ -322,24 +323,24 @@ int multi_launch(rpb_ctx *ctx, const rpb_params *p, const Packed &g, SrcPtrs<K> 
   for (int s = 0; s < K; ++s) used += in.p[s] != nullptr || (s == 0 && TQ);
   const double *tq = TQ ? torque : nullptr;
   if (f64)
-    pack_multi<K, double><<<blocks_for(n, 256), 256, 0, stream>>>(n, in, h, tq,
+    pack_multi<K, double><<<blocks_for(n, 256), 256, 0, stream>>>(n, in, h, tq, 1.0 / g.a,
                                                                  static_cast<double *>(src));
   else
-    pack_multi<K, float><<<blocks_for(n, 256), 256, 0, stream>>>(n, in, h, tq,
+    pack_multi<K, float><<<blocks_for(n, 256), 256, 0, stream>>>(n, in, h, tq, 1.0 / g.a,
                                                                 static_cast<float *>(src));
   RPB_LAUNCHED(ctx);
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
   const bool wall = p->wall != 0;
   if (f64) {
-    const auto k = make_pair_consts<double>(p->a);
+    const auto k = make_pair_consts<double>();
     const auto *s = static_cast<const double *>(src);
     if (wall)
       pair_kernel_f64_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
     else
       pair_kernel_f64_multi<K, TQ, false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
   } else {
-    const auto k = make_pair_consts<float>(p->a);
+    const auto k = make_pair_consts<float>();
     const auto *s = static_cast<const float *>(src);
     if (wall)
       pair_kernel_mixed_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), s, k, part);
@@ -349,7 +350,7 @@ int multi_launch(rpb_ctx *ctx, const rpb_params *p, const Packed &g, SrcPtrs<K> 
   }
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n) * used, 8 + (f64 ? 0 : 2)));
-  const double scale = 1.0 / (8.0 * M_PI * p->eta);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   reduce_multi<K><<<blocks_for(int64_t(K) * 3 * n, 256), 256, 0, stream>>>(a, out, part, h,
                                                                             scale);
   RPB_LAUNCHED(ctx);

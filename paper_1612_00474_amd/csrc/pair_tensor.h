@@ -2,6 +2,9 @@
 // applied to the source's force and torque and added to the target's running sum.  Written
 // once for float64 and float32.
 //
+// All lengths are in units of the radius a (the formulas below keep a for reference; the code
+// takes a = 1, see PairConsts).
+//
 // Geometry (heights already clamped to z~ = max(z, a), paper App. A eq. effMob):
 //   r = q~_i - q~_j = (dx, dy, dz)                    (direct separation)
 //   R = q~_i - (x_j, y_j, -z~_j) = (dx, dy, Rz)       (separation from the source image)
@@ -37,41 +40,38 @@
 //
 // With WALL = false (free space) only the unbounded tensors are applied.
 //
-// Every value here carries the factor 8 pi eta; the caller divides once per target.
+// Every value here carries the factor 8 pi eta a (8 pi eta a^2 for the torque coupling); the
+// caller divides once per target.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace rpb {
 
+// Lengths are in units of the sphere radius a (the packed geometry is divided by a), so the
+// tensors take a = 1: M(r; a) = M(r/a; 1)/a and M_C(r; a) = M_C(r/a; 1)/a^2, and the caller
+// applies 1/(8 pi eta a) per target and divides the torques by a.
 template <typename Real>
 struct PairConsts {
-  Real a2;          // a^2
-  Real four_a2;     // (2a)^2, branch point
-  Real near_i;      // 4/(3a)
-  Real near_i_r;    // 4/(3a) * 9/(32a)
-  Real near_rr;     // 4/(3a) * 3/(32a)
-  Real near_t;      // 1/(2a^3)
-  Real near_t_r;    // 1/(2a^3) * 3/(8a)
-  Real lx, ly;      // pseudo-periodic box (used by the PERIODIC kernels only)
+  Real lx, ly;      // pseudo-periodic box in units of a (used by the PERIODIC kernels only)
   Real ilx, ily;    // 1/lx, 1/ly
 };
 
+// Overlap branch (r < 2, units of a): cI = 4/3 - (3/8) r, cRR = (1/8)/r, cT = 1/2 - (3/16) r.
+constexpr double kNearI = 4.0 / 3.0;
+constexpr double kNearIR = 3.0 / 8.0;
+constexpr double kNearRR = 1.0 / 8.0;
+constexpr double kNearT = 0.5;
+constexpr double kNearTR = 3.0 / 16.0;
+constexpr double kFourA2 = 4.0;   // (2a)^2, the branch point
+
 template <typename Real>
-__host__ __device__ inline PairConsts<Real> make_pair_consts(double a, double lx = 0.0,
-                                                              double ly = 0.0) {
+__host__ __device__ inline PairConsts<Real> make_pair_consts(double lx = 0.0, double ly = 0.0) {
   PairConsts<Real> k;
   k.lx = Real(lx);
   k.ly = Real(ly);
   k.ilx = lx > 0.0 ? Real(1.0 / lx) : Real(0);
   k.ily = ly > 0.0 ? Real(1.0 / ly) : Real(0);
-  k.a2 = Real(a * a);
-  k.four_a2 = Real(4.0 * a * a);
-  k.near_i = Real(4.0 / (3.0 * a));
-  k.near_i_r = Real(4.0 / (3.0 * a) * 9.0 / (32.0 * a));
-  k.near_rr = Real(4.0 / (3.0 * a) * 3.0 / (32.0 * a));
-  k.near_t = Real(1.0 / (2.0 * a * a * a));
-  k.near_t_r = Real(1.0 / (2.0 * a * a * a) * 3.0 / (8.0 * a));
   return k;
 }
 
@@ -106,23 +106,23 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   if (FAR_ONLY) {
     const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
-    const Real s = k.a2 * ir2;
+    const Real s = ir2;
     cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
     cT = invr * ir2;
     cRR = cT * (Real(1) - Real(2) * s);
   } else {
     const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
-    if (r2 >= k.four_a2) {
+    if (r2 >= Real(kFourA2)) {
       const Real ir2 = invr * invr;
-      const Real s = k.a2 * ir2;
+      const Real s = ir2;
       cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
       cT = invr * ir2;
       cRR = cT * (Real(1) - Real(2) * s);
     } else {
       const Real r = r2 * invr;
-      cI = k.near_i - k.near_i_r * r;
-      cRR = k.near_rr * invr;
-      cT = k.near_t - k.near_t_r * r;
+      cI = Real(kNearI) - Real(kNearIR) * r;
+      cRR = Real(kNearRR) * invr;
+      cT = Real(kNearT) - Real(kNearTR) * r;
     }
   }
 
@@ -144,7 +144,7 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
 
   // wall coefficients
   const Real iR2 = iR * iR;
-  const Real X = k.a2 * iR2;
+  const Real X = iR2;
   const Real Y = X * X;
   const Real ez = Rz * iR;
   const Real hh = zj * iR;
@@ -236,7 +236,7 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
     // valid for r2 >= (2a)^2 only: the caller routes closer pairs to FAR_ONLY = false
     const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
-    const Real s = k.a2 * ir2;
+    const Real s = ir2;
     cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
     if (TORQUE) {
       cT = invr * ir2;
@@ -246,9 +246,9 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
     }
   } else {
     const Real invr = r2 > Real(0) ? rsqrt_r(r2) : Real(0);
-    if (r2 >= k.four_a2) {
+    if (r2 >= Real(kFourA2)) {
       const Real ir2 = invr * invr;
-      const Real s = k.a2 * ir2;
+      const Real s = ir2;
       cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
       if (TORQUE) {
         cT = invr * ir2;
@@ -258,9 +258,9 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
       }
     } else {
       const Real r = r2 * invr;
-      cI = k.near_i - k.near_i_r * r;
-      cRR = k.near_rr * invr;
-      if (TORQUE) cT = k.near_t - k.near_t_r * r;
+      cI = Real(kNearI) - Real(kNearIR) * r;
+      cRR = Real(kNearRR) * invr;
+      if (TORQUE) cT = Real(kNearT) - Real(kNearTR) * r;
     }
   }
   c.cI = cI;
@@ -280,7 +280,7 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
   //   c2 e_z + c3 = 2h - e_z - u,  c2 e_z + c4 = 2h - e_z + u,
   //   c2 e_z^2 + (c3 + c4) e_z + c5 = e_z^2 (6t - m + 70Y/3 - 6X - 1) - 4t - 8Y/3.
   const Real iR2 = iR * iR;
-  const Real X = k.a2 * iR2;
+  const Real X = iR2;
   const Real Y = X * X;
   const Real ez = Rz * iR;
   const Real hh = zj * iR;

@@ -140,6 +140,7 @@ int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs,
 // Geometry of one configuration, packed once and reused by several products.
 struct Packed {
   int64_t n = 0;
+  double a = 1.0;         // radius: the packed lengths are in units of a
   int precision = RPB_FP64;
   void *geom = nullptr;   // precision-dependent structure-of-arrays
 };
