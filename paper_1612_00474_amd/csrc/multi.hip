@@ -396,15 +396,21 @@ int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, c
   return RPB_OK;
 }
 
-bool matvec_pair_supported(const rpb_params *p, int64_t n) {
-  return p->lx <= 0.0 && n > 0 && multi_fits(2, n);
+bool matvec_first_supported(const rpb_params *p, int64_t n) {
+  return p->lx <= 0.0 && n > 0 && multi_fits(3, n);
 }
 
-int matvec_pair(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
-                const double *torque, const double *w, double *u_force, double *u_w,
-                hipStream_t stream) {
-  if (!matvec_pair_supported(p, g.n))
-    return fail(ctx, RPB_EINVAL, "two-vector product not available for this configuration");
+int matvec_first(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
+                 const double *torque, const double *w, const double *w3, double *u_force,
+                 double *u_w, double *u_w3, hipStream_t stream) {
+  if (!matvec_first_supported(p, g.n))
+    return fail(ctx, RPB_EINVAL, "joint product not available for this configuration");
+  if (w3) {
+    const SrcPtrs<3> in{{force, w, w3}};
+    const OutPtrs<3> out{{u_force, u_w, u_w3}};
+    if (torque) return multi_launch<3, true>(ctx, p, g, in, torque, out, stream);
+    return multi_launch<3, false>(ctx, p, g, in, nullptr, out, stream);
+  }
   const SrcPtrs<2> in{{force, w}};
   const OutPtrs<2> out{{u_force, u_w}};
   if (torque) return multi_launch<2, true>(ctx, p, g, in, torque, out, stream);

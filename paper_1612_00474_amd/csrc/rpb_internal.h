@@ -193,13 +193,14 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
 // geometry `g`; vectors with done[v] != 0 (host array, nullable) are skipped.
 int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, const int *done,
                  const double *force, double *vel, hipStream_t stream);
-// u_force = M force + M_C torque and u_w = M w in one launch (the pair coefficients shared);
-// torque nullable.  Available when matvec_pair_supported(p, n) (no box, partials within the
+// The products of a step at its own configuration in one launch (the pair coefficients shared):
+// u_force = M force + M_C torque, u_w = M w and, when w3 is not NULL, u_w3 = M w3; torque
+// nullable.  Available when matvec_first_supported(p, n) (no box, partials within the
 // workspace limit).
-bool matvec_pair_supported(const rpb_params *p, int64_t n);
-int matvec_pair(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
-                const double *torque, const double *w, double *u_force, double *u_w,
-                hipStream_t stream);
+bool matvec_first_supported(const rpb_params *p, int64_t n);
+int matvec_first(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
+                 const double *torque, const double *w, const double *w3, double *u_force,
+                 double *u_w, double *u_w3, hipStream_t stream);
 
 // ---- vector kernels (lanczos.hip) -------------------------------------------------------
 constexpr int kMaxBatchSystems = 4096;   // per-system records must fit the pinned scratch
@@ -235,8 +236,10 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
                 hipStream_t stream, const double *mw = nullptr);
 
 // ---- RFD / RNG / forces / step ----------------------------------------------------------
+// base (one-sided only, nullable): M(q) w~ already computed in rfd_precision by the caller.
 int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, const double *wt,
-            double delta, int rfd_precision, bool one_sided, double *drift, hipStream_t stream);
+            double delta, int rfd_precision, bool one_sided, double *drift, hipStream_t stream,
+            const double *base = nullptr);
 int normals_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id, uint64_t step,
                 double *out, hipStream_t stream);
 int forces_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, double f_grav_z,

@@ -204,13 +204,19 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   RPB_LAUNCHED(ctx);
   Packed geo;
   RPB_TRY(pack_geometry(ctx, p, n, state->pos, WS_GEOM, &geo, stream));
-  // M F + M_C T and the first Lanczos product M W share the configuration: one two-vector
-  // launch evaluates each pair's coefficients once for both
-  double *mw = nullptr;
-  if (cfg->lanczos_precond == 0 && matvec_pair_supported(p, n)) {
+  // M F + M_C T, the first Lanczos product M W and, for the one-sided RFD in the step's own
+  // precision, its product M W~ at q share the configuration: one launch evaluates each pair's
+  // coefficients once for all of them
+  double *mw = nullptr, *mwt = nullptr;
+  const bool one_sided = cfg->rfd_scheme == 1;
+  if (cfg->lanczos_precond == 0 && matvec_first_supported(p, n)) {
     mw = static_cast<double *>(workspace(ctx, WS_VEC_B, nb, &st));
     if (!mw) return st;
-    RPB_TRY(matvec_pair(ctx, p, geo, F, T, W, u, mw, stream));
+    if (one_sided && cfg->rfd_precision == p->precision) {
+      mwt = static_cast<double *>(workspace(ctx, WS_VEC_E, nb, &st));   // rfd_run's q- product
+      if (!mwt) return st;
+    }
+    RPB_TRY(matvec_first(ctx, p, geo, F, T, W, mwt ? Wt : nullptr, u, mw, mwt, stream));
   } else {
     RPB_TRY(matvec_packed(ctx, p, geo, F, T, 0, n, u, stream));
   }
@@ -223,8 +229,8 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   if (lz != RPB_OK && lz != RPB_ENOCONV) return lz;
 
   // stochastic drift
-  RPB_TRY(rfd_run(ctx, p, n, state->pos, Wt, cfg->delta, cfg->rfd_precision,
-                  cfg->rfd_scheme == 1, drift, stream));
+  RPB_TRY(rfd_run(ctx, p, n, state->pos, Wt, cfg->delta, cfg->rfd_precision, one_sided, drift,
+                  stream, mwt));
 
   const bool ab = cfg->scheme == 0 && state->have_prev;
   combine_kernel<<<nblk(m3), 256, 0, stream>>>(m3, state->pos, state->u_prev, u, g, drift,

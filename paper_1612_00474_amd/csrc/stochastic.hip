@@ -113,7 +113,8 @@ int normals_run(rpb_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream_id, 
 }
 
 int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, const double *wt,
-            double delta, int rfd_precision, bool one_sided, double *drift, hipStream_t stream) {
+            double delta, int rfd_precision, bool one_sided, double *drift, hipStream_t stream,
+            const double *base) {
   const int64_t m = 3 * n;
   const size_t vb = size_t(m) * sizeof(double);
   int st;
@@ -132,10 +133,13 @@ int rfd_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, con
   q.precision = rfd_precision;
   Packed gp, gm;
   RPB_TRY(pack_geometry(ctx, &q, n, qp, WS_GEOM, &gp, stream));
-  RPB_TRY(pack_geometry(ctx, &q, n, qm, WS_GEOM2, &gm, stream));
   RPB_TRY(matvec_packed(ctx, &q, gp, wt, nullptr, 0, n, up, stream));
-  RPB_TRY(matvec_packed(ctx, &q, gm, wt, nullptr, 0, n, um, stream));
-  scaled_difference<<<nblk(m), 256, 0, stream>>>(m, up, um, p->kT / delta, drift);
+  if (!(one_sided && base)) {   // the product at q- (= q when one-sided)
+    RPB_TRY(pack_geometry(ctx, &q, n, qm, WS_GEOM2, &gm, stream));
+    RPB_TRY(matvec_packed(ctx, &q, gm, wt, nullptr, 0, n, um, stream));
+    base = um;
+  }
+  scaled_difference<<<nblk(m), 256, 0, stream>>>(m, up, base, p->kT / delta, drift);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }

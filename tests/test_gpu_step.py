@@ -104,10 +104,16 @@ def test_mixed_precision_step(ctx):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("precision,tol_u,tol_x", [("fp64", 1e-12, 1e-10), ("mixed", 1e-5, 1e-5)])
-def test_step_products_over_several_tiles(ctx, precision, tol_u, tol_x):
-    # N = 700: three tiles of the two-vector launch that evaluates M F + M_C T (with the
-    # rollers' torque) together with the first Lanczos product M W, ragged last tile included
+@pytest.mark.parametrize("precision,rfd_precision,rfd,tol_u,tol_x", [
+    ("fp64", "fp64", "centred", 1e-12, 1e-10),
+    ("mixed", "fp64", "centred", 1e-5, 1e-5),
+    ("fp64", "fp64", "one_sided", 1e-12, 1e-10),
+    ("mixed", "mixed", "one_sided", 1e-5, 2e-3)])
+def test_step_products_over_several_tiles(ctx, precision, rfd_precision, rfd, tol_u, tol_x):
+    # N = 700: three tiles of the launch that evaluates M F + M_C T (with the rollers' torque)
+    # together with the first Lanczos product M W and, for the one-sided RFD in the step's own
+    # precision, M W~ at q; ragged last tile included.  Mixed RFD: float32 products differenced
+    # over delta = 1e-4 (a-priori ~1e-3 relative in the drift, a small part of the displacement)
     from paper_1612_00474_amd import StepState
     inp = _setup(n=700, seed=4)
     rng = np.random.default_rng(12)
@@ -115,11 +121,12 @@ def test_step_products_over_several_tiles(ctx, precision, tol_u, tol_x):
     state = StepState(dev(inp["pos"]))
     it, eps, st = ctx.sab_step(state, dt=0.01, delta=1e-4, lanczos_tol=1e-300,
                                lanczos_max_iter=M_FIXED, precision=precision,
-                               rfd_precision="fp64", w=dev(W), w_tilde=dev(Wt), steric_u0=1.0,
-                               steric_b=0.1, **PHYS)
-    new, u, mref, _, _ = _oracle_step(inp["pos"], None, W, Wt, "sab")
+                               rfd_precision=rfd_precision, rfd_scheme=rfd, w=dev(W),
+                               w_tilde=dev(Wt), steric_u0=1.0, steric_b=0.1, **PHYS)
+    new, u, mref, _, _ = _oracle_step(inp["pos"], None, W, Wt, "sab", rfd)
     err_u = rel2(host(state.u_prev), u)
     err_x = rel2(host(state.pos) - inp["pos"], new - inp["pos"])
-    print(f"{precision} step N=700: u rel2 = {err_u:.3e}, displacement rel2 = {err_x:.3e}")
+    print(f"{precision}/{rfd_precision} {rfd} step N=700: u rel2 = {err_u:.3e}, "
+          f"displacement rel2 = {err_x:.3e}")
     assert it == mref == M_FIXED
     assert err_u <= tol_u and err_x <= tol_x
