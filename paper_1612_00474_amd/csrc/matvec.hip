@@ -1,20 +1,23 @@
 // Matrix-free product U = M F + M_C T of the regularised Rotne-Prager-Blake mobility.
 //
-// Direct summation over all ordered pairs (paper, Sec. II.B): the pair tensor is evaluated
-// on the fly (pair_tensor.h) and never stored, so the kernels are bound by the vector ALUs,
-// not by HBM.  Layout:
-//   pack_geometry   O(N)   AoS float64 positions -> SoA clamped heights, weights H0(z/a)
-//                          (App. A, eq. effMob); mixed precision splits x, y into
-//                          float32 hi + lo so that near-pair separations keep ~1e-7 accuracy
-//                          far from the origin.
-//   pack_vectors    O(N)   AoS float64 force/torque -> SoA H-weighted source vectors.
-//   pair kernels    O(N^2) a workgroup owns a tile of targets (kBlock lanes x TPT targets per
-//                          lane) and streams a range of sources through LDS; float64 sums, or
-//                          float32 sums per LDS tile added with Kahan compensation.
-//                            * single system: grid (target tile, source chunk);
-//                            * batched systems: persistent workgroups pull (system, target
-//                              tile, source chunk) items, largest first, from a counter.
-//   reduce_partials O(N S) fixed-order sum over source chunks, times H_i / (8 pi eta).
+// Direct summation over all pairs (paper, Sec. II.B): the pair tensor is evaluated on the fly
+// (pair_tensor.h) and never stored, so the kernels are bound by the vector ALUs, not by HBM.
+// Layout:
+//   pack_geometry   O(N)   AoS float64 positions -> SoA lengths in units of a, clamped heights,
+//                          weights H0(z/a) (App. A, eq. effMob); mixed precision splits x, y
+//                          into float32 hi + lo so that near-pair separations keep ~1e-7
+//                          accuracy far from the origin.
+//   pack_vectors    O(N)   AoS float64 force/torque -> SoA H-weighted source vectors (torques
+//                          divided by a).
+//   pair kernels    O(N^2) * whole system: the symmetric tile-pair kernel, one evaluation
+//                            per unordered pair applied in both directions (M_ji = M_ij^T);
+//                          * row ranges: a workgroup owns a tile of targets (kBlock lanes x
+//                            TPT targets per lane) and streams a chunk of sources through LDS;
+//                          * batched systems: persistent workgroups pull (system, tile pair)
+//                            or (system, target tile, source chunk) items, largest first.
+//                          Float64 sums, or float32 sums per LDS tile added with Kahan
+//                          compensation.
+//   reduce_partials O(N S) fixed-order sum of the partials, times H_i / (8 pi eta a).
 #include <algorithm>
 #include <cmath>
 #include <cstring>

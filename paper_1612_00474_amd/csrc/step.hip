@@ -2,12 +2,14 @@
 // scheme eq. AB; Sec. III for the constant driving torque and the soft potential).
 //
 //   F^n  = steric + gravity at q^n                       (forces.hip)
-//   u^n  = M^n F^n + M_C^n T                             (matvec.hip)
+//   u^n  = M^n F^n + M_C^n T                             (matvec.hip, multi.hip)
 //   g^n  ~ M^{n 1/2} W^n                                 (lanczos.hip)
 //   D^n  = (kT/delta)[M(q^n + delta/2 W~) - M(q^n - delta/2 W~)] W~   (stochastic.hip)
 //   q^{n+1} = q^n + dt (c0 u^n - c1 u^{n-1}) + sqrt(2 kT dt) g^n + dt D^n
 // with (c0, c1) = (3/2, 1/2) for SAB after the first step and (1, 0) for EM or the first
 // SAB step (no u^{-1} exists).  u^n is stored into the caller's u_prev for the next step.
+// The products at q^n (u^n, the first Lanczos product M W^n and, for a one-sided RFD in the
+// step's precision, M W~) share one multi-vector launch.
 #include <cmath>
 
 #include "rpb_internal.h"
