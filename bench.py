@@ -39,18 +39,28 @@ KIND_MULTI_FP64, KIND_MULTI_MIXED = 8, 10   # multi-vector kernel (pairs counted
 PROFILED_N = 65536   # sheet size of the committed counter summary
 
 
+def kernel_source_hash() -> str:
+    """sha256[:16] of the pair-kernel sources with comments and blank lines removed (so that
+    editing a comment does not void the recorded counters)."""
+    import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_1612_00474_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("matvec.hip", "multi.hip", "pair_common.h", "pair_tensor.h"):
+        with open(os.path.join(csrc, name)) as f:
+            for line in f:
+                code = re.sub(r"//.*$", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel: str, n: int = PROFILED_N):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
     when the kernel sources changed since the counters were taken or `n` is another size."""
     if n != PROFILED_N:
         return None
-    import hashlib
-    csrc = os.path.join(ROOT, "paper_1612_00474_amd", "csrc")
-    h = hashlib.sha256()
-    for name in ("matvec.hip", "multi.hip", "pair_common.h", "pair_tensor.h"):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(f.read())
-    current = h.hexdigest()[:16]
+    current = kernel_source_hash()
     path = os.path.join(ROOT, "profiles", "pair_kernels_sheet64k_hbm_traffic.md")
     try:
         with open(path) as f:
