@@ -432,7 +432,23 @@ __global__ void lz_reset_batched(SegView v, int nsys) {
     st->m = 0;
     st->reason = 0;
     v.done[s] = 0;
+    if (s == 0) v.done[nsys] = 0;
   }
+}
+
+// done[nsys] = 1 once every system is done: later launches of the persistent product kernel
+// return at once instead of walking their work list.
+__global__ __launch_bounds__(256) void seg_all_done(SegView v, int nsys) {
+  __shared__ int any[256];
+  int open = 0;
+  for (int s = threadIdx.x; s < nsys; s += 256) open |= v.done[s] == 0;
+  any[threadIdx.x] = open;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (int(threadIdx.x) < off) any[threadIdx.x] |= any[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) v.done[nsys] = any[0] ? 0 : 1;
 }
 
 // compact status record per system: (m, reason, eps)
@@ -586,7 +602,7 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
       ctx, WS_REDUCE, size_t(nsys) * kMaxKrylov * kSegBlocks * sizeof(double), &st));
   if (!part) return st;
   const size_t states_bytes = size_t(nsys) * sizeof(LzState);
-  const size_t status_off = (states_bytes + size_t(nsys) * sizeof(int) + 255) / 256 * 256;
+  const size_t status_off = (states_bytes + size_t(nsys + 1) * sizeof(int) + 255) / 256 * 256;
   char *lz = static_cast<char *>(
       workspace(ctx, WS_LZBATCH, status_off + size_t(nsys) * sizeof(LzStatus), &st));
   if (!lz) return st;
@@ -636,6 +652,8 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
     RPB_LAUNCHED(ctx);
     RPB_TRY(seg_dot(u, u, f_beta + k - 1, 1));
     tridiag_sqrt_batched<<<ns, 64, 0, stream>>>(v, k, tol);
+    RPB_LAUNCHED(ctx);
+    seg_all_done<<<1, 256, 0, stream>>>(v, nsys);
     RPB_LAUNCHED(ctx);
     if (k < max_iter) {
       seg_scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(v, m3, u, f_beta + k - 1,
@@ -691,7 +709,7 @@ int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const
 
 int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStream_t stream) {
   const size_t states_bytes = size_t(nsys) * sizeof(LzState);
-  const size_t status_off = (states_bytes + size_t(nsys) * sizeof(int) + 255) / 256 * 256;
+  const size_t status_off = (states_bytes + size_t(nsys + 1) * sizeof(int) + 255) / 256 * 256;
   const DevBuf &b = ctx->ws[WS_LZBATCH];
   if (!b.ptr || b.bytes < status_off + size_t(nsys) * sizeof(LzStatus))
     return fail(ctx, RPB_EINVAL, "no batched Lanczos state");

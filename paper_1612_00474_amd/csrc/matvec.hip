@@ -670,6 +670,7 @@ struct BatchArgs {
   int64_t n;             // total spheres (stride of every array)
   int64_t chunk;         // sources per item
   const int *done;       // optional per-system flags: items of finished systems are skipped
+  const int *all_done;   // optional: nonzero once every system is done (the launch returns)
 };
 
 // Pull the next item for the workgroup (-1 when the list is exhausted).  Every workgroup
@@ -689,6 +690,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_batched(BatchArgs b, G
                                                                   double *__restrict__ partial) {
   __shared__ LdsD<TORQUE> L;
   __shared__ int slot[1];
+  if (b.all_done && *b.all_done) return;
   for (int it = next_item(b, slot); it >= 0; it = next_item(b, slot)) {
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
@@ -709,6 +711,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_batched(BatchArgs b,
                                                                     double *__restrict__ partial) {
   __shared__ LdsF<TORQUE> L;
   __shared__ int slot[1];
+  if (b.all_done && *b.all_done) return;
   for (int it = next_item(b, slot); it >= 0; it = next_item(b, slot)) {
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
@@ -752,6 +755,7 @@ struct SymBatchArgs {
   int64_t ts;                // tile size
   const int64_t *part_base;  // first partial slot of each system
   const int *done;           // optional per-system flags: items of finished systems are skipped
+  const int *all_done;       // optional: nonzero once every system is done (the launch returns)
 };
 
 __device__ __forceinline__ SymArgs sym_args_of(const SymBatchArgs &b, int s) {
@@ -774,6 +778,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
   __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
   __shared__ int slot[1];
+  if (b.all_done && *b.all_done) return;
   for (int it = next_sym_item(b, slot); it >= 0; it = next_sym_item(b, slot)) {
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
@@ -790,6 +795,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
   __shared__ LdsD<TORQUE> L;
   __shared__ double col[kWaves][kBlock][3];
   __shared__ int slot[1];
+  if (b.all_done && *b.all_done) return;
   for (int it = next_sym_item(b, slot); it >= 0; it = next_sym_item(b, slot)) {
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
@@ -1177,7 +1183,7 @@ int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const 
   const bool f64 = g.precision == RPB_FP64;
   const int tpt = b.tpt;
   SymBatchArgs args{b.offs, b.items, b.nitems, counter, n, int64_t(kBlock) * tpt, b.part_base,
-                    done};
+                    done, done ? done + b.nsys : nullptr};
   const unsigned grid = unsigned(std::max(1, std::min(b.nitems, b.wgs)));
   double pairs = 0.0;
   for (int s = 0; s < b.nsys; ++s) {
@@ -1232,7 +1238,8 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
   if (b.symmetric) return matvec_batched_sym(ctx, p, b, g, src, has_t, done, counter, part, h,
                                              vel, stream);
 
-  BatchArgs args{b.offs, b.items, b.nitems, counter, n, b.chunk, done};
+  BatchArgs args{b.offs, b.items, b.nitems, counter, n, b.chunk, done,
+                 done ? done + b.nsys : nullptr};
   const unsigned grid = unsigned(std::max(1, std::min(b.nitems, b.wgs)));
   double pairs = 0.0;
   for (int s = 0; s < b.nsys; ++s) {

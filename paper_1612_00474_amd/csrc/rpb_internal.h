@@ -182,7 +182,8 @@ int check_offsets(rpb_ctx *ctx, int32_t nsys, const int64_t *offs);
 int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision, Batch *b,
                   hipStream_t stream, bool work_items = true);
 // Batched product for packed geometry `g` (all systems); systems with done[s] != 0 are
-// skipped (their output rows are left untouched).  `done` may be NULL.
+// skipped (their output rows are left untouched), and the launch returns at once when
+// done[nsys] != 0 (every system done).  `done` (nsys + 1 flags) may be NULL.
 int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
                    const double *force, const double *torque, const int *done, double *vel,
                    hipStream_t stream);
