@@ -306,7 +306,8 @@ void rpb_step_graph_destroy(rpb_graph *g);
  * chunks; symmetric, whole-system products use the symmetric tile-pair kernel (M_ij = M_ji^T:
  * each unordered pair evaluated once, both directions applied; with torques both coupling
  * directions come from the shared geometry).  Row ranges (rpb_mobility_matvec_rows) always
- * take the ordered kernel.  Batched products: batch_tpt (1 or 2); batch_symmetric, the
+ * take the ordered kernel, and so do systems whose symmetric partial sums would exceed 32 GiB
+ * (3 n^2 / (256 tpt) doubles: above about 840,000 spheres at tpt = 2).  Batched products: batch_tpt (1 or 2); batch_symmetric, the
  * persistent kernel works on (system, tile pair) items of the symmetric kernel instead of
  * (system, target tile, source chunk) items; batch_chunk, sources per ordered work item
  * (multiple of 256); batch_wgs, persistent workgroups.  rpb_autotune times the candidates for

@@ -984,7 +984,15 @@ int block_diag_scale(rpb_ctx *ctx, const rpb_params *p, const Packed &g, double 
   return RPB_OK;
 }
 
-// Force-only product of the whole system with one evaluation per unordered pair.
+// Partial buffer of the symmetric kernel, nt^2 slots of 3 ts doubles, about 3 n^2/ts doubles.
+// Larger systems take the ordered kernel, whose partials grow as O(n).
+constexpr size_t kMaxSymPartialBytes = size_t(32) << 30;
+inline size_t sym_partial_bytes(int64_t n, int64_t ts) {
+  const int64_t nt = (n + ts - 1) / ts;
+  return size_t(nt) * size_t(nt) * 3 * size_t(ts) * sizeof(double);
+}
+
+// Whole-system product with one evaluation per unordered pair.
 int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
                      bool torque, const double *h, int tpt, double *vel, hipStream_t stream) {
   const int64_t n = g.n;
@@ -1036,7 +1044,8 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   // order whichever rows are requested: row shards concatenate to the full product bitwise.
   const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
   const int tpt = shape.tpt;
-  if (row0 == 0 && nrows == n && shape.symmetric)
+  if (row0 == 0 && nrows == n && shape.symmetric &&
+      sym_partial_bytes(n, int64_t(kBlock) * tpt) <= kMaxSymPartialBytes)
     return matvec_symmetric(ctx, p, g, src, has_t, h, tpt, vel, stream);
   const int64_t per_wg = int64_t(kBlock) * tpt;
   const int64_t tiles = (nrows + per_wg - 1) / per_wg;
@@ -1094,6 +1103,12 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
   b->tpt = tpt;
   b->wgs = shape.batch_wgs;
   b->symmetric = shape.batch_symmetric != 0;
+  if (b->symmetric) {   // the partial buffer must stay within the limit of the symmetric kernel
+    size_t bytes = 0;
+    for (int s = 0; s < nsys; ++s)
+      bytes += sym_partial_bytes(offs[s + 1] - offs[s], int64_t(kBlock) * tpt);
+    if (bytes > kMaxSymPartialBytes) b->symmetric = false;
+  }
   b->host_offs.assign(offs, offs + nsys + 1);
   // work items, largest (targets x sources) first; ties keep their generation order.
   // Ordered: (system, target tile, source chunk); symmetric: (system, I, J) tile pairs, I <= J.
