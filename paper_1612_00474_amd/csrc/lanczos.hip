@@ -586,10 +586,11 @@ namespace {
 // One Krylov process per segment (system) of `b`; product(src, done_dev, done_host, dst) writes
 // dst = M src for every segment not yet done (done_host: the flags as of the last host read,
 // NULL when unknown).  L (nullable): preconditioner scale, 3 b.n entries, with scratch t.
+// mw (nullable, not with L): M w computed by the caller, used for the first iteration.
 template <typename Product>
 int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, const double *w,
                      double tol, int max_iter, Product &&product, double *out, bool sync_each,
-                     LzStatus *status_host, hipStream_t stream) {
+                     LzStatus *status_host, hipStream_t stream, const double *mw = nullptr) {
   const int64_t m3 = 3 * b.n;
   const int nsys = b.nsys;
   int st;
@@ -636,6 +637,9 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
       RPB_LAUNCHED(ctx);
       RPB_TRY(product(t, v.done, known, u));
       divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
+      RPB_LAUNCHED(ctx);
+    } else if (k == 1 && mw) {   // M v_1 = (M w) / |w| per system, from the caller's product
+      seg_scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(v, m3, mw, f_wnorm, u);
       RPB_LAUNCHED(ctx);
     } else {
       RPB_TRY(product(vk, v.done, known, u));
@@ -690,7 +694,8 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
 
 int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
                         const double *w, double tol, int max_iter, bool precond, double *out,
-                        bool sync_each, LzStatus *status_host, hipStream_t stream) {
+                        bool sync_each, LzStatus *status_host, hipStream_t stream,
+                        const double *mw) {
   const int64_t m3 = 3 * b.n;
   double *L = nullptr, *t = nullptr;
   if (precond) {
@@ -704,7 +709,7 @@ int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const
     return matvec_batched(ctx, p, b, g, src, nullptr, done_dev, dst, stream);
   };
   return lanczos_segments(ctx, b, L, t, w, tol, max_iter, product, out, sync_each, status_host,
-                          stream);
+                          stream, precond ? nullptr : mw);
 }
 
 int lanczos_batched_status_copy(rpb_ctx *ctx, int nsys, LzStatus *host, hipStream_t stream) {

@@ -424,13 +424,6 @@ __device__ __forceinline__ void load_own(const Real *__restrict__ src, int64_t n
   }
 }
 
-inline __device__ GeomF offset_geom(const GeomF &g, int64_t s0) {
-  return {g.xh + s0, g.xl + s0, g.yh + s0, g.yl + s0, g.z + s0, g.h + s0};
-}
-inline __device__ GeomD offset_geom(const GeomD &g, int64_t s0) {
-  return {g.x + s0, g.y + s0, g.z + s0, g.h + s0};
-}
-
 // Tile pair (I, J), I <= J, of one system: `g`, `src` and `partial` already point at the
 // system's first sphere and first partial slot.  Every lane of the workgroup must call this.
 template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>

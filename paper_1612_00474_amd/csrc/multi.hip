@@ -16,6 +16,7 @@
 //   reduce_multi  O(N^2/256) fixed-order sum of the tile partials, times H_i / (8 pi eta).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "pair_common.h"
@@ -32,6 +33,8 @@ constexpr size_t kMaxMultiPartialBytes = size_t(32) << 30;
 // torque of slot 0.
 template <int K, bool TQ>
 constexpr int src_rows() { return 3 * K + (TQ ? 3 : 0); }
+
+__global__ void zero_counter(int *c) { c[0] = 0; }
 
 template <int K>
 struct SrcPtrs {
@@ -363,6 +366,161 @@ bool multi_fits(int K, int64_t n) {
   return nt * (nt + 1) / 2 <= 0x7fffffffll && multi_partial_bytes(K, nt) <= kMaxMultiPartialBytes;
 }
 
+// ---- batches of independent systems ------------------------------------------------------
+
+struct MultiBatchArgs {
+  const int64_t *offs;   // nsys + 1 sphere prefix sums
+  const int64_t *cum;    // nsys + 1: first work item of each system, cum[nsys] = all items
+  const int64_t *base;   // nsys + 1: first partial double of each system
+  int nsys;
+  int64_t n;             // total spheres (stride of the source arrays)
+  int *counter;          // work counter (reset to 0 before the launch)
+};
+
+// Item and partial offsets of every system (one workgroup): system s has nt (nt + 1)/2 tile
+// pairs of the upper triangle and K nt^2 3 kBlock partial doubles, nt = ceil(n_s / kBlock).
+__global__ __launch_bounds__(kBlock) void multi_batch_setup(int nsys, int K,
+                                                            const int64_t *__restrict__ offs,
+                                                            int64_t *__restrict__ cum,
+                                                            int64_t *__restrict__ base) {
+  __shared__ int64_t pi[kBlock + 1], pe[kBlock + 1];
+  const int tid = threadIdx.x;
+  const int per = (nsys + kBlock - 1) / kBlock;
+  const int s0 = min(nsys, tid * per), s1 = min(nsys, s0 + per);
+  int64_t ci = 0, ce = 0;
+  for (int s = s0; s < s1; ++s) {
+    const int64_t nt = (offs[s + 1] - offs[s] + kBlock - 1) / kBlock;
+    ci += nt * (nt + 1) / 2;
+    ce += int64_t(K) * nt * nt * 3 * kBlock;
+  }
+  pi[tid] = ci;
+  pe[tid] = ce;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t ri = 0, re = 0;
+    for (int t = 0; t < kBlock; ++t) {
+      const int64_t vi = pi[t], ve = pe[t];
+      pi[t] = ri;
+      pe[t] = re;
+      ri += vi;
+      re += ve;
+    }
+    pi[kBlock] = ri;
+    pe[kBlock] = re;
+  }
+  __syncthreads();
+  ci = pi[tid];
+  ce = pe[tid];
+  for (int s = s0; s < s1; ++s) {
+    cum[s] = ci;
+    base[s] = ce;
+    const int64_t nt = (offs[s + 1] - offs[s] + kBlock - 1) / kBlock;
+    ci += nt * (nt + 1) / 2;
+    ce += int64_t(K) * nt * nt * 3 * kBlock;
+  }
+  if (tid == 0) {
+    cum[nsys] = pi[kBlock];
+    base[nsys] = pe[kBlock];
+  }
+}
+
+// Next work item of the workgroup: (system, I, J), or false once the list is exhausted.  Every
+// workgroup keeps pulling until the counter passes the item count, so every wave exits.
+__device__ __forceinline__ bool next_multi_item(const MultiBatchArgs &b, int *slot, int &sys,
+                                                int64_t &I, int64_t &J) {
+  __syncthreads();
+  if (threadIdx.x == 0) slot[0] = atomicAdd(b.counter, 1);
+  __syncthreads();
+  const int64_t it = slot[0];
+  if (it >= b.cum[b.nsys]) return false;
+  int lo = 0, hi = b.nsys - 1;   // the last system with cum <= it (empty systems own no item)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (b.cum[mid] <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  sys = lo;
+  const int64_t nt = (b.offs[lo + 1] - b.offs[lo] + kBlock - 1) / kBlock;
+  tri_decode(it - b.cum[lo], nt, I, J);
+  return true;
+}
+
+__device__ __forceinline__ SymArgs multi_args_of(const MultiBatchArgs &b, int s) {
+  const int64_t ns = b.offs[s + 1] - b.offs[s];
+  return SymArgs{ns, kBlock, (ns + kBlock - 1) / kBlock, b.n};
+}
+
+template <int K, bool TQ, bool WALL>
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi_batched(
+    MultiBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k,
+    double *__restrict__ partial) {
+  __shared__ MultiLdsF<K, TQ> L;
+  __shared__ int slot[1];
+  int s;
+  int64_t I, J;
+  while (next_multi_item(b, slot, s, I, J)) {
+    const int64_t s0 = b.offs[s];
+    multi_tile_pair<K, TQ, WALL>(multi_args_of(b, s), offset_geom(g, s0), src + s0, k,
+                                 partial + b.base[s], I, J, L);
+  }
+}
+
+template <int K, bool TQ, bool WALL>
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64_multi_batched(
+    MultiBatchArgs b, GeomD g, const double *__restrict__ src, PairConsts<double> k,
+    double *__restrict__ partial) {
+  __shared__ MultiLdsD<K, TQ> L;
+  __shared__ int slot[1];
+  int s;
+  int64_t I, J;
+  while (next_multi_item(b, slot, s, I, J)) {
+    const int64_t s0 = b.offs[s];
+    multi_tile_pair<K, TQ, WALL>(multi_args_of(b, s), offset_geom(g, s0), src + s0, k,
+                                 partial + b.base[s], I, J, L);
+  }
+}
+
+template <int K>
+__global__ void reduce_multi_batched(MultiBatchArgs b, const int *__restrict__ sys_of,
+                                     OutPtrs<K> out, const double *__restrict__ partial,
+                                     const double *__restrict__ h, double scale) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = 3 * b.n;
+  if (e >= K * per) return;
+  const int v = int(e / per);
+  const int64_t rem = e - int64_t(v) * per;
+  const int d = int(rem / b.n);
+  const int64_t r = rem - int64_t(d) * b.n;
+  double *dst = out.p[v];
+  if (!dst) return;
+  const int s = sys_of[r];
+  const SymArgs a = multi_args_of(b, s);
+  const int64_t local = r - b.offs[s];
+  const double *p0 = partial + b.base[s] + multi_slot(a, v, local / kBlock, 0, d, local % kBlock);
+  const int64_t stride = 3 * kBlock;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t P = 0;
+  for (; P + 4 <= a.nt; P += 4) {
+    s0 += p0[P * stride];
+    s1 += p0[(P + 1) * stride];
+    s2 += p0[(P + 2) * stride];
+    s3 += p0[(P + 3) * stride];
+  }
+  for (; P < a.nt; ++P) s0 += p0[P * stride];
+  dst[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
+}
+
+size_t multi_batch_partial_bytes(int K, const Batch &bt) {
+  size_t bytes = 0;
+  for (int s = 0; s < bt.nsys; ++s) {
+    const int64_t nt = (bt.host_offs[s + 1] - bt.host_offs[s] + kBlock - 1) / kBlock;
+    bytes += size_t(K) * size_t(nt) * size_t(nt) * 3 * size_t(kBlock) * sizeof(double);
+  }
+  return bytes;
+}
+
 }  // namespace
 
 int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, const int *done,
@@ -415,6 +573,92 @@ int matvec_first(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doubl
   const OutPtrs<2> out{{u_force, u_w}};
   if (torque) return multi_launch<2, true>(ctx, p, g, in, torque, out, stream);
   return multi_launch<2, false>(ctx, p, g, in, nullptr, out, stream);
+}
+
+bool matvec_first_batched_supported(const rpb_params *p, const Batch &bt) {
+  return p->lx <= 0.0 && bt.n > 0 && bt.nsys > 0 &&
+         multi_batch_partial_bytes(2, bt) <= kMaxMultiPartialBytes;
+}
+
+int matvec_first_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const Packed &g,
+                         const double *force, const double *torque, const double *w,
+                         double *u_force, double *u_w, hipStream_t stream) {
+  if (!matvec_first_batched_supported(p, bt))
+    return fail(ctx, RPB_EINVAL, "joint batched product not available for this batch");
+  constexpr int K = 2;
+  const int64_t n = g.n;
+  const bool f64 = g.precision == RPB_FP64;
+  int st;
+  const size_t meta_bytes = size_t(2 * (bt.nsys + 1)) * sizeof(int64_t);
+  int64_t *meta = static_cast<int64_t *>(workspace(ctx, WS_MBATCH, meta_bytes, &st));
+  if (!meta) return st;
+  double *part = static_cast<double *>(
+      workspace(ctx, WS_PART, std::max<size_t>(8, multi_batch_partial_bytes(K, bt)), &st));
+  if (!part) return st;
+  const size_t esz = f64 ? sizeof(double) : sizeof(float);
+  const bool tq = torque != nullptr;
+  void *src = workspace(ctx, WS_SRC, size_t(3 * K + 3) * size_t(n) * esz, &st);
+  if (!src) return st;
+  char *small = static_cast<char *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
+  if (!small) return st;
+  int *counter = reinterpret_cast<int *>(small + kSmallWorkCounter);
+  MultiBatchArgs args{bt.offs, meta, meta + bt.nsys + 1, bt.nsys, n, counter};
+  multi_batch_setup<<<1, kBlock, 0, stream>>>(bt.nsys, K, bt.offs, meta, meta + bt.nsys + 1);
+  RPB_LAUNCHED(ctx);
+  const double *h = f64 ? geom_d(g).h : geom_f(g).h;
+  const SrcPtrs<K> in{{force, w}};
+  if (f64)
+    pack_multi<K, double><<<blocks_for(n, 256), 256, 0, stream>>>(
+        n, in, h, torque, 1.0 / g.a, static_cast<double *>(src));
+  else
+    pack_multi<K, float><<<blocks_for(n, 256), 256, 0, stream>>>(
+        n, in, h, torque, 1.0 / g.a, static_cast<float *>(src));
+  RPB_LAUNCHED(ctx);
+  zero_counter<<<1, 1, 0, stream>>>(counter);
+  RPB_LAUNCHED(ctx);
+  const unsigned grid = unsigned(std::max(1, bt.wgs));
+  hipEvent_t t0;
+  RPB_TRY(timing_begin(ctx, stream, &t0));
+  const bool wall = p->wall != 0;
+  auto launch = [&](auto TQ) {
+    constexpr bool kTQ = decltype(TQ)::value;
+    if (f64) {
+      const auto k = make_pair_consts<double>();
+      const auto *s = static_cast<const double *>(src);
+      if (wall)
+        pair_kernel_f64_multi_batched<K, kTQ, true><<<grid, kBlock, 0, stream>>>(args, geom_d(g),
+                                                                                 s, k, part);
+      else
+        pair_kernel_f64_multi_batched<K, kTQ, false><<<grid, kBlock, 0, stream>>>(
+            args, geom_d(g), s, k, part);
+    } else {
+      const auto k = make_pair_consts<float>();
+      const auto *s = static_cast<const float *>(src);
+      if (wall)
+        pair_kernel_mixed_multi_batched<K, kTQ, true><<<grid, kBlock, 0, stream>>>(
+            args, geom_f(g), s, k, part);
+      else
+        pair_kernel_mixed_multi_batched<K, kTQ, false><<<grid, kBlock, 0, stream>>>(
+            args, geom_f(g), s, k, part);
+    }
+  };
+  if (tq)
+    launch(std::true_type{});
+  else
+    launch(std::false_type{});
+  RPB_LAUNCHED(ctx);
+  double pairs = 0.0;
+  for (int q = 0; q < bt.nsys; ++q) {
+    const double ns = double(bt.host_offs[q + 1] - bt.host_offs[q]);
+    pairs += ns * ns;
+  }
+  RPB_TRY(timing_end(ctx, stream, t0, K * pairs, 8 + (f64 ? 0 : 2)));
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
+  const OutPtrs<K> out{{u_force, u_w}};
+  reduce_multi_batched<K><<<blocks_for(int64_t(K) * 3 * n, 256), 256, 0, stream>>>(
+      args, bt.sys_of, out, part, h, scale);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
 }
 
 }  // namespace rpb

@@ -35,6 +35,14 @@ inline size_t geom_bytes(int64_t n, int precision) {
                                : size_t(n) * sizeof(double) + size_t(5 * n) * sizeof(float);
 }
 
+// The geometry of a batch's system starting at sphere s0.
+inline __device__ GeomF offset_geom(const GeomF &g, int64_t s0) {
+  return {g.xh + s0, g.xl + s0, g.yh + s0, g.yl + s0, g.z + s0, g.h + s0};
+}
+inline __device__ GeomD offset_geom(const GeomD &g, int64_t s0) {
+  return {g.x + s0, g.y + s0, g.z + s0, g.h + s0};
+}
+
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
   const float y = v - c;
   const float t = s + y;

@@ -40,6 +40,7 @@ enum Slot {
   WS_LZBATCH,       // batched Lanczos: per-system scalars and status
   WS_PRECOND,       // block-diagonal preconditioner: L (3n) and a scaled vector (3n)
   WS_CELLS,         // steric cell list: cells, buckets, sorted lists, bucket counts and starts
+  WS_MBATCH,        // batched multi-vector products: per-system item and partial offsets
   WS_NSLOTS
 };
 
@@ -203,6 +204,13 @@ int matvec_first(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doubl
                  const double *torque, const double *w, const double *w3, double *u_force,
                  double *u_w, double *u_w3, hipStream_t stream);
 
+// Batched form of matvec_first with two vectors (u_force = M force + M_C torque, u_w = M w per
+// system), one persistent launch; available when matvec_first_batched_supported(p, bt).
+bool matvec_first_batched_supported(const rpb_params *p, const Batch &bt);
+int matvec_first_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const Packed &g,
+                         const double *force, const double *torque, const double *w,
+                         double *u_force, double *u_w, hipStream_t stream);
+
 // ---- vector kernels (lanczos.hip) -------------------------------------------------------
 constexpr int kMaxBatchSystems = 4096;   // per-system records must fit the pinned scratch
 
@@ -217,9 +225,12 @@ struct LzStatus {
 // flags after every iteration and stops when all systems are done; false runs max_iter
 // iterations with device-side freezing only (no host synchronisation: capturable).
 // status_host (pinned, nsys records) is filled when not NULL (synchronises).
+// mw (nullable, ignored with precond): M w computed by the caller for every system, used for
+// the first iteration.
 int lanczos_batched_run(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
                         const double *w, double tol, int max_iter, bool precond, double *out,
-                        bool sync_each, LzStatus *status_host, hipStream_t stream);
+                        bool sync_each, LzStatus *status_host, hipStream_t stream,
+                        const double *mw = nullptr);
 // L (3n, float64) with L^2 = the diagonal of the self blocks M_ii of the packed geometry
 // (1 where H = 0).
 int block_diag_scale(rpb_ctx *ctx, const rpb_params *p, const Packed &g, double *scale,

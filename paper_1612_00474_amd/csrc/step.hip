@@ -105,9 +105,18 @@ int step_batched_enqueue(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config
   RPB_LAUNCHED(ctx);
   Packed geo;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &geo, stream));
-  RPB_TRY(matvec_batched(ctx, p, bt, geo, F, T, nullptr, u, stream));
+  // M F + M_C T and the first Lanczos product M W of every system in one persistent launch
+  double *mw = nullptr;
+  if (cfg->lanczos_precond == 0 && matvec_first_batched_supported(p, bt)) {
+    mw = static_cast<double *>(workspace(ctx, WS_VEC_B, nb, &st));
+    if (!mw) return st;
+    RPB_TRY(matvec_first_batched(ctx, p, bt, geo, F, T, W, u, mw, stream));
+  } else {
+    RPB_TRY(matvec_batched(ctx, p, bt, geo, F, T, nullptr, u, stream));
+  }
   RPB_TRY(lanczos_batched_run(ctx, p, bt, geo, W, cfg->lanczos_tol, cfg->lanczos_max_iter,
-                              cfg->lanczos_precond != 0, g, sync_lanczos, status_host, stream));
+                              cfg->lanczos_precond != 0, g, sync_lanczos, status_host, stream,
+                              mw));
   RPB_TRY(rfd_batched_run(ctx, p, bt, pos, Wt, cfg->delta, cfg->rfd_precision,
                           cfg->rfd_scheme == 1, drift, stream));
   combine_kernel_dev<<<nblk(m3), 256, 0, stream>>>(m3, pos, u_prev, u, g, drift, cfg->dt,

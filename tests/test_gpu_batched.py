@@ -110,6 +110,34 @@ def test_batched_step_matches_oracle(ctx):
         assert rel2(host(U)[a:b], u) <= 1e-12
 
 
+@pytest.mark.parametrize("precision,tol_u,tol_x", [("fp64", 1e-12, 1e-10), ("mixed", 1e-5, 1e-5)])
+def test_batched_step_over_several_tiles(ctx, precision, tol_u, tol_x):
+    # systems of several 256-sphere tiles (ragged), an empty and a one-sphere system: the joint
+    # persistent launch of M F + M_C T (rollers' torque) and the first Lanczos product M W
+    sizes = [300, 0, 700, 1, 257]
+    pos, offs, rng = _batch(sizes, seed=6)
+    W, Wt = rng.standard_normal(pos.shape), rng.standard_normal(pos.shape)
+    P, U = dev(pos), dev(np.zeros_like(pos))
+    phys = dict(f_grav_z=-1.0, torque=(0.0, 1.0, 0.0))
+    it, eps, st = ctx.sab_step_batched(P, U, offs, 0, False, dt=0.01, delta=1e-4,
+                                       lanczos_tol=1e-300, lanczos_max_iter=6, w=dev(W),
+                                       w_tilde=dev(Wt), steric_u0=1.0, steric_b=0.1,
+                                       precision=precision, rfd_precision="fp64", **phys)
+    got, gu = host(P), host(U)
+    for s in range(len(sizes)):
+        a, b = offs[s], offs[s + 1]
+        if a == b:
+            continue
+        new, u, m, _, _ = integrator.step(pos[a:b], None, W[a:b], Wt[a:b], dt=0.01, delta=1e-4,
+                                          lanczos_tol=1e-300, lanczos_max_iter=6, u0=1.0, b=0.1,
+                                          **phys)
+        # float32 products cannot show the exact breakdown (beta ~ 1e-14 max|alpha|) of the
+        # one-sphere system, whose Krylov space is exhausted after its 3 dimensions
+        assert it[s] == m if precision == "fp64" else it[s] <= 6
+        assert rel2(gu[a:b], u) <= tol_u, (s, precision)
+        assert rel2(got[a:b] - pos[a:b], new - pos[a:b]) <= tol_x, (s, precision)
+
+
 def test_graph_replays_match_eager_steps(ctx):
     import torch
     pos, offs, rng = _batch([200, 900, 31, 450], seed=5)
