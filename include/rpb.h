@@ -171,7 +171,7 @@ int rfd_drift_one_sided(rpb_ctx *ctx, const rpb_params *p, int64_t n, const doub
  * r - d > 40 b are skipped (their force is below 4.3e-18 U0/b).  u0 >= 0, b > 0.
  * The pairs are found with a cell list (cells of side >= 2a + 40 b, O(N) work); a box with
  * fewer than three such cells per side takes an all-pairs search.  Results are bitwise
- * reproducible.  The workspace grows by about 50 bytes per sphere.
+ * reproducible.  The workspace grows by about 100 bytes per sphere.
  */
 int rpb_forces(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
                double f_grav_z, double u0, double b, double *force_out, rpb_stream_t stream);

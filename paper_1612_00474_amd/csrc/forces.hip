@@ -315,11 +315,26 @@ __global__ void cells_sort(int64_t nb, const int *__restrict__ start, const int 
   }
 }
 
+// Positions and cells in bucket order (sorted slot s holds sphere list[s]), so that a target
+// reads each neighbouring bucket as one contiguous range.
+__global__ void cells_gather(int64_t n, const int *__restrict__ list,
+                             const double *__restrict__ pos, const int4 *__restrict__ cell,
+                             double4 *__restrict__ spos, int4 *__restrict__ scell) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int j = list[s];
+  spos[s] = make_double4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], 0.0);
+  int4 q = cell[j];
+  q.w = j;   // the system is implied by the bucket check below; keep the index for j != i
+  scell[s] = q;
+}
+
 // One thread per target: the 27 neighbouring cells in a fixed order, each bucket's spheres
 // of that cell (and system) in index order; then the wall force and gravity.
 __global__ void steric_cells(int64_t n, const double *__restrict__ pos, CellArgs c,
                              const int4 *__restrict__ cell, const int *__restrict__ start,
-                             const int *__restrict__ count, const int *__restrict__ list,
+                             const int *__restrict__ count, const double4 *__restrict__ spos,
+                             const int4 *__restrict__ scell, const int *__restrict__ sys_of,
                              double a, double u0, double b, double f_grav_z, int wall,
                              double *__restrict__ force) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -343,11 +358,12 @@ __global__ void steric_cells(int64_t n, const double *__restrict__ pos, CellArgs
         const uint32_t h = bucket_of(q, me.w, c.mask);
         const int s0 = start[h], s1 = s0 + count[h];
         for (int s = s0; s < s1; ++s) {
-          const int j = list[s];
-          const int4 cj = cell[j];
-          if (cj.x != q.x || cj.y != q.y || cj.z != q.z || cj.w != me.w || j == i) continue;
-          double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1];
-          const double dz = zi - pos[3 * j + 2];
+          const int4 cj = scell[s];   // (cell x, y, z, sphere index)
+          if (cj.x != q.x || cj.y != q.y || cj.z != q.z || cj.w == i) continue;
+          if (sys_of && sys_of[cj.w] != me.w) continue;
+          const double4 pj = spos[s];
+          double dx = xi - pj.x, dy = yi - pj.y;
+          const double dz = zi - pj.z;
           if (c.lx > 0.0) {   // minimum image
             dx -= c.lx * rint(dx / c.lx);
             dy -= c.ly * rint(dy / c.ly);
@@ -403,8 +419,9 @@ int steric_cell_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *
   int st;
   const int64_t nblk = (nb + kBlock - 1) / kBlock;
   const size_t blk_bytes = (size_t(nblk) * sizeof(int) + 255) / 256 * 256;
-  char *w = static_cast<char *>(
-      workspace(ctx, WS_CELLS, cell_bytes + 2 * n_bytes + 3 * nb_bytes + blk_bytes, &st));
+  const size_t spos_bytes = (size_t(n) * sizeof(double4) + 255) / 256 * 256;
+  char *w = static_cast<char *>(workspace(
+      ctx, WS_CELLS, 2 * cell_bytes + spos_bytes + 2 * n_bytes + 3 * nb_bytes + blk_bytes, &st));
   if (!w) return st;
   int4 *cell = reinterpret_cast<int4 *>(w);
   uint32_t *bucket = reinterpret_cast<uint32_t *>(w + cell_bytes);
@@ -413,6 +430,9 @@ int steric_cell_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *
   int *start = count + nb_bytes / sizeof(int);
   int *cursor = start + nb_bytes / sizeof(int);
   int *bsum = cursor + nb_bytes / sizeof(int);
+  char *tail = reinterpret_cast<char *>(bsum) + blk_bytes;
+  int4 *scell = reinterpret_cast<int4 *>(tail);
+  double4 *spos = reinterpret_cast<double4 *>(tail + cell_bytes);
   const unsigned gn = unsigned((n + kBlock - 1) / kBlock), gb = unsigned((nb + kBlock - 1) / kBlock);
   cells_clear<<<gb, kBlock, 0, stream>>>(nb, count);
   RPB_LAUNCHED(ctx);
@@ -428,8 +448,10 @@ int steric_cell_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *
   RPB_LAUNCHED(ctx);
   cells_sort<<<gb, kBlock, 0, stream>>>(nb, start, count, list);
   RPB_LAUNCHED(ctx);
-  steric_cells<<<gn, kBlock, 0, stream>>>(n, pos, c, cell, start, count, list, p->a, u0, b,
-                                          f_grav_z, p->wall, force);
+  cells_gather<<<gn, kBlock, 0, stream>>>(n, list, pos, cell, spos, scell);
+  RPB_LAUNCHED(ctx);
+  steric_cells<<<gn, kBlock, 0, stream>>>(n, pos, c, cell, start, count, spos, scell, sys_of,
+                                          p->a, u0, b, f_grav_z, p->wall, force);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
