@@ -431,14 +431,17 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
                                               const float *__restrict__ src,
                                               const PairConsts<float> &k,
                                               double *__restrict__ partial, int64_t I, int64_t J,
-                                              LdsF<TORQUE> &L, float (&col)[kWaves][kBlock][3]) {
+                                              int64_t h, LdsF<TORQUE> &L,
+                                              float (&col)[kWaves][kBlock][3]) {
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t n = a.n;
   const int64_t first = I * a.ts;
   TargetsF<TPT> T;
   load_targets<TPT>(g, first, n, first, T);
-  const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
+  // source part h of tile J
+  const int64_t jt = J * a.ts, part = a.ts / a.nsplit;
+  const int64_t jb = jt + h * part, je = min(n, jb + part);
   if (I == J) {
     sources_mixed<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
@@ -447,7 +450,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
       if (first + local < n)
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          partial[sym_slot(a, I, I, d, local)] = double(T.s[q][d]) - double(T.c[q][d]);
+          partial[sym_slot(a, I, I, d, local, h)] = double(T.s[q][d]) - double(T.c[q][d]);
     }
     return;
   }
@@ -501,7 +504,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
       for (int d = 0; d < 3; ++d) kahan_add(T.s[q][d], T.c[q][d], acc[q][d]);
     __syncthreads();
     if (tid < cnt) {
-      const int64_t l = t0 - jb + tid;
+      const int64_t l = t0 - jt + tid;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         double v = 0.0;
@@ -517,7 +520,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
     if (first + local < n)
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        partial[sym_slot(a, I, J, d, local)] = double(T.s[q][d]) - double(T.c[q][d]);
+        partial[sym_slot(a, I, J, d, local, h)] = double(T.s[q][d]) - double(T.c[q][d]);
   }
 }
 
@@ -526,14 +529,17 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
                                               const double *__restrict__ src,
                                               const PairConsts<double> &k,
                                               double *__restrict__ partial, int64_t I, int64_t J,
-                                              LdsD<TORQUE> &L, double (&col)[kWaves][kBlock][3]) {
+                                              int64_t h, LdsD<TORQUE> &L,
+                                              double (&col)[kWaves][kBlock][3]) {
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t n = a.n;
   const int64_t first = I * a.ts;
   TargetsD<TPT> T;
   load_targets<TPT>(g, first, n, first, T);
-  const int64_t jb = J * a.ts, je = min(n, jb + a.ts);
+  // source part h of tile J
+  const int64_t jt = J * a.ts, part = a.ts / a.nsplit;
+  const int64_t jb = jt + h * part, je = min(n, jb + part);
   if (I == J) {
     sources_f64<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
@@ -541,7 +547,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
       const int64_t local = q * kBlock + tid;
       if (first + local < n)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, I, d, local)] = T.u[q][d];
+        for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, I, d, local, h)] = T.u[q][d];
     }
     return;
   }
@@ -586,7 +592,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
     }
     __syncthreads();
     if (tid < cnt) {
-      const int64_t l = t0 - jb + tid;
+      const int64_t l = t0 - jt + tid;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         double v = 0.0;
@@ -601,7 +607,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
     const int64_t local = q * kBlock + tid;
     if (first + local < n)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, J, d, local)] = T.u[q][d];
+      for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, J, d, local, h)] = T.u[q][d];
   }
 }
 
@@ -613,8 +619,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
   __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
   int64_t I, J;
-  tri_decode(blockIdx.x, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, L, col);
+  tri_decode(blockIdx.x / a.nsplit, a.nt, I, J);
+  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, blockIdx.x % a.nsplit,
+                                             L, col);
 }
 
 template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
@@ -625,12 +632,14 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
   __shared__ LdsD<TORQUE> L;
   __shared__ double col[kWaves][kBlock][3];
   int64_t I, J;
-  tri_decode(blockIdx.x, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, L, col);
+  tri_decode(blockIdx.x / a.nsplit, a.nt, I, J);
+  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, blockIdx.x % a.nsplit,
+                                             L, col);
 }
 
 // One thread per (component, row): four independent partial sums over the slots (P mod 4),
-// combined in a fixed order, so the memory system sees four loads in flight per thread.
+// combined in a fixed order, so the memory system sees four loads in flight per thread.  With
+// source parts (nsplit > 1) the row side T <= P holds one slot per part.
 __global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
                                     const double *__restrict__ h, double scale,
                                     double *__restrict__ vel) {
@@ -640,17 +649,16 @@ __global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partia
   const int64_t r = e - int64_t(d) * a.n;
   const int64_t T = r / a.ts, local = r % a.ts;
   const double *base = partial + sym_slot(a, T, 0, d, local);
-  const int64_t stride = 3 * a.ts;   // slot (T, P) to (T, P + 1)
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t P = 0;
-  for (; P + 4 <= a.nt; P += 4) {
-    s0 += base[P * stride];
-    s1 += base[(P + 1) * stride];
-    s2 += base[(P + 2) * stride];
-    s3 += base[(P + 3) * stride];
+  const int64_t ph = 3 * a.ts;             // slot (T, P, h) to (T, P, h + 1)
+  const int64_t stride = a.nsplit * ph;    // slot (T, P, 0) to (T, P + 1, 0)
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t P = 0; P < a.nt; ++P) {
+    double v = base[P * stride];
+    if (P >= T)
+      for (int64_t q = 1; q < a.nsplit; ++q) v += base[P * stride + q * ph];
+    s[P & 3] += v;
   }
-  for (; P < a.nt; ++P) s0 += base[P * stride];
-  vel[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
+  vel[3 * r + d] = scale * h[r] * ((s[0] + s[1]) + (s[2] + s[3]));
 }
 
 // ---- batched systems: persistent workgroups over a cost-ordered item list -------------------
@@ -777,7 +785,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
     sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
-                               partial + b.part_base[w.x], w.y, w.z, L, col);
+                               partial + b.part_base[w.x], w.y, w.z, 0, L, col);
   }
 }
 
@@ -794,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
     sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
-                               partial + b.part_base[w.x], w.y, w.z, L, col);
+                               partial + b.part_base[w.x], w.y, w.z, 0, L, col);
   }
 }
 
@@ -977,12 +985,22 @@ int block_diag_scale(rpb_ctx *ctx, const rpb_params *p, const Packed &g, double 
   return RPB_OK;
 }
 
-// Partial buffer of the symmetric kernel, nt^2 slots of 3 ts doubles, about 3 n^2/ts doubles.
-// Larger systems take the ordered kernel, whose partials grow as O(n).
-constexpr size_t kMaxSymPartialBytes = size_t(32) << 30;
-inline size_t sym_partial_bytes(int64_t n, int64_t ts) {
+// Small systems have few tile pairs: their sources are split into parts (each of at least
+// 128 spheres, one workgroup per part) until the grid has about kSplitWorkgroups workgroups.
+constexpr int64_t kSplitWorkgroups = 4096;
+inline int64_t sym_nsplit(int64_t n, int64_t ts) {
   const int64_t nt = (n + ts - 1) / ts;
-  return size_t(nt) * size_t(nt) * 3 * size_t(ts) * sizeof(double);
+  int64_t q = 1;
+  while (nt * (nt + 1) / 2 * q < kSplitWorkgroups && ts / (2 * q) >= 128) q *= 2;
+  return q;
+}
+
+// Partial buffer of the symmetric kernel, nt^2 nsplit slots of 3 ts doubles.  Larger systems
+// take the ordered kernel, whose partials grow as O(n).
+constexpr size_t kMaxSymPartialBytes = size_t(32) << 30;
+inline size_t sym_partial_bytes(int64_t n, int64_t ts, int64_t nsplit = 1) {
+  const int64_t nt = (n + ts - 1) / ts;
+  return size_t(nt) * size_t(nt) * size_t(nsplit) * 3 * size_t(ts) * sizeof(double);
 }
 
 // Whole-system product with one evaluation per unordered pair.
@@ -992,13 +1010,14 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
   const bool f64 = g.precision == RPB_FP64;
   SymArgs a{n, int64_t(kBlock) * tpt, 0, n};
   a.nt = (n + a.ts - 1) / a.ts;
-  if (a.nt * (a.nt + 1) / 2 > 0x7fffffffll)
+  a.nsplit = sym_nsplit(n, a.ts);
+  if (a.nt * (a.nt + 1) / 2 * a.nsplit > 0x7fffffffll)
     return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
   int st;
-  double *part = static_cast<double *>(workspace(
-      ctx, WS_PART, size_t(a.nt) * size_t(a.nt) * 3 * size_t(a.ts) * sizeof(double), &st));
+  double *part = static_cast<double *>(
+      workspace(ctx, WS_PART, sym_partial_bytes(n, a.ts, a.nsplit), &st));
   if (!part) return st;
-  const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2);
+  const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2 * a.nsplit);
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
   with_variant(torque, tpt, p->wall != 0, periodic(p), [&](auto T, auto P, auto W, auto B) {
@@ -1038,7 +1057,8 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
   const int tpt = shape.tpt;
   if (row0 == 0 && nrows == n && shape.symmetric &&
-      sym_partial_bytes(n, int64_t(kBlock) * tpt) <= kMaxSymPartialBytes)
+      sym_partial_bytes(n, int64_t(kBlock) * tpt, sym_nsplit(n, int64_t(kBlock) * tpt)) <=
+          kMaxSymPartialBytes)
     return matvec_symmetric(ctx, p, g, src, has_t, h, tpt, vel, stream);
   const int64_t per_wg = int64_t(kBlock) * tpt;
   const int64_t tiles = (nrows + per_wg - 1) / per_wg;

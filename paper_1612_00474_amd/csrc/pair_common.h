@@ -51,10 +51,11 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
 }
 
 struct SymArgs {
-  int64_t n;       // spheres of the system
-  int64_t ts;      // tile size (kBlock * TPT)
-  int64_t nt;      // tiles
-  int64_t stride;  // stride of the source component arrays (all systems' spheres)
+  int64_t n;           // spheres of the system
+  int64_t ts;          // tile size (kBlock * TPT)
+  int64_t nt;          // tiles
+  int64_t stride;      // stride of the source component arrays (all systems' spheres)
+  int64_t nsplit = 1;  // workgroups per tile pair, each taking one part of the source tile
 };
 
 // v from lane (l + 1) mod 64 (DPP wave_rol:1).  Every lane has a source lane, so the "old"
@@ -72,10 +73,13 @@ __device__ __forceinline__ double wave_rol1(double v) {
                               static_cast<long long>(static_cast<unsigned>(lo)));
 }
 
-// slot (T, P) of the symmetric partial array: partial[((T * nt + P) * 3 + comp) * ts + local]
+// slot (T, P, h) of the symmetric partial array:
+// partial[(((T * nt + P) * nsplit + h) * 3 + comp) * ts + local].  Tile T's rows get the sums
+// over source part h of tile P in slot (T, P, h) when T <= P, and the column sums of the
+// tile pair (P, T) in slot (T, P, 0) when T > P.
 __device__ __forceinline__ int64_t sym_slot(const SymArgs &a, int64_t T, int64_t P, int comp,
-                                            int64_t local) {
-  return ((T * a.nt + P) * 3 + comp) * a.ts + local;
+                                            int64_t local, int64_t h = 0) {
+  return (((T * a.nt + P) * a.nsplit + h) * 3 + comp) * a.ts + local;
 }
 
 constexpr int kWaves = kBlock / 64;
