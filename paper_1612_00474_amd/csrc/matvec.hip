@@ -757,11 +757,12 @@ struct SymBatchArgs {
   const int64_t *part_base;  // first partial slot of each system
   const int *done;           // optional per-system flags: items of finished systems are skipped
   const int *all_done;       // optional: nonzero once every system is done (the launch returns)
+  int64_t nsplit;            // source parts per tile pair (items (system, I, J, part))
 };
 
 __device__ __forceinline__ SymArgs sym_args_of(const SymBatchArgs &b, int s) {
   const int64_t ns = b.offs[s + 1] - b.offs[s];
-  return SymArgs{ns, b.ts, (ns + b.ts - 1) / b.ts, b.n};
+  return SymArgs{ns, b.ts, (ns + b.ts - 1) / b.ts, b.n, b.nsplit};
 }
 
 __device__ __forceinline__ int next_sym_item(const SymBatchArgs &b, int *slot) {
@@ -785,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
     sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
-                               partial + b.part_base[w.x], w.y, w.z, 0, L, col);
+                               partial + b.part_base[w.x], w.y, w.z, w.w, L, col);
   }
 }
 
@@ -802,7 +803,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
     sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
-                               partial + b.part_base[w.x], w.y, w.z, 0, L, col);
+                               partial + b.part_base[w.x], w.y, w.z, w.w, L, col);
   }
 }
 
@@ -820,17 +821,16 @@ __global__ void reduce_partials_sym_batched(SymBatchArgs b, const int *__restric
   const int64_t local = r - b.offs[s];
   const int64_t T = local / a.ts;
   const double *base = partial + b.part_base[s] + sym_slot(a, T, 0, d, local % a.ts);
-  const int64_t stride = 3 * a.ts;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t P = 0;
-  for (; P + 4 <= a.nt; P += 4) {
-    s0 += base[P * stride];
-    s1 += base[(P + 1) * stride];
-    s2 += base[(P + 2) * stride];
-    s3 += base[(P + 3) * stride];
+  const int64_t ph = 3 * a.ts;             // slot (T, P, h) to (T, P, h + 1)
+  const int64_t stride = a.nsplit * ph;    // slot (T, P, 0) to (T, P + 1, 0)
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t P = 0; P < a.nt; ++P) {
+    double v = base[P * stride];
+    if (P >= T)
+      for (int64_t q = 1; q < a.nsplit; ++q) v += base[P * stride + q * ph];
+    acc[P & 3] += v;
   }
-  for (; P < a.nt; ++P) s0 += base[P * stride];
-  vel[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
+  vel[3 * r + d] = scale * h[r] * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 __global__ void fill_sys_of(int nsys, const int64_t *__restrict__ offs, int *__restrict__ sys_of) {
@@ -1116,32 +1116,47 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
   b->tpt = tpt;
   b->wgs = shape.batch_wgs;
   b->symmetric = shape.batch_symmetric != 0;
-  if (b->symmetric) {   // the partial buffer must stay within the limit of the symmetric kernel
+  const int64_t per = int64_t(kBlock) * tpt;
+  // symmetric items are split into source parts (of at least 128 spheres) until there are
+  // about four items per persistent workgroup, for balance at the end of the launch; the
+  // partial buffer must stay within the limit of the symmetric kernel
+  b->nsplit = 1;
+  if (b->symmetric) {
+    int64_t pairs = 0;
+    for (int s = 0; s < nsys; ++s) {
+      const int64_t nt = (offs[s + 1] - offs[s] + per - 1) / per;
+      pairs += nt * (nt + 1) / 2;
+    }
+    while (pairs * b->nsplit < 4 * int64_t(b->wgs) && per / (2 * b->nsplit) >= 128) b->nsplit *= 2;
     size_t bytes = 0;
-    for (int s = 0; s < nsys; ++s)
-      bytes += sym_partial_bytes(offs[s + 1] - offs[s], int64_t(kBlock) * tpt);
-    if (bytes > kMaxSymPartialBytes) b->symmetric = false;
+    for (int s = 0; s < nsys; ++s) bytes += sym_partial_bytes(offs[s + 1] - offs[s], per, b->nsplit);
+    if (bytes > kMaxSymPartialBytes) {
+      b->symmetric = false;
+      b->nsplit = 1;
+    }
   }
   b->host_offs.assign(offs, offs + nsys + 1);
   // work items, largest (targets x sources) first; ties keep their generation order.
-  // Ordered: (system, target tile, source chunk); symmetric: (system, I, J) tile pairs, I <= J.
+  // Ordered: (system, target tile, source chunk); symmetric: (system, I, J, part), I <= J.
   std::vector<int4> items;
   std::vector<double> cost;
-  const int64_t per = int64_t(kBlock) * tpt;
   std::vector<int64_t> part_base(size_t(nsys), 0);
   int64_t part_elems = 0;
+  const int64_t part_len = per / b->nsplit;
   for (int s = 0; s < nsys && work_items; ++s) {
     const int64_t ns = offs[s + 1] - offs[s];
     if (b->symmetric) {
       const int64_t nt = (ns + per - 1) / per;
       part_base[s] = part_elems;
-      part_elems += nt * nt * 3 * per;
+      part_elems += nt * nt * b->nsplit * 3 * per;
       for (int64_t I = 0; I < nt; ++I)
-        for (int64_t J = I; J < nt; ++J) {
-          items.push_back(int4{s, int(I), int(J), 0});
-          cost.push_back(double(std::min(per, ns - I * per)) *
-                         double(std::min(per, ns - J * per)));
-        }
+        for (int64_t J = I; J < nt; ++J)
+          for (int64_t q = 0; q < b->nsplit; ++q) {
+            const int64_t j0 = J * per + q * part_len;
+            items.push_back(int4{s, int(I), int(J), int(q)});
+            cost.push_back(double(std::min(per, ns - I * per)) *
+                           double(std::max<int64_t>(0, std::min(part_len, ns - j0))));
+          }
     } else {
       for (int64_t t = 0; t * per < ns; ++t)
         for (int64_t c = 0; c * chunk < ns; ++c) {
@@ -1210,8 +1225,8 @@ int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const 
   const int64_t n = g.n;
   const bool f64 = g.precision == RPB_FP64;
   const int tpt = b.tpt;
-  SymBatchArgs args{b.offs, b.items, b.nitems, counter, n, int64_t(kBlock) * tpt, b.part_base,
-                    done, done ? done + b.nsys : nullptr};
+  SymBatchArgs args{b.offs,      b.items, b.nitems, counter, n, int64_t(kBlock) * tpt,
+                    b.part_base, done,    done ? done + b.nsys : nullptr, b.nsplit};
   const unsigned grid = unsigned(std::max(1, std::min(b.nitems, b.wgs)));
   double pairs = 0.0;
   for (int s = 0; s < b.nsys; ++s) {

@@ -172,7 +172,8 @@ struct Batch {
   int64_t *offs = nullptr;       // device
   int4 *items = nullptr;         // device
   int *sys_of = nullptr;         // device, n entries
-  bool symmetric = false;        // items are (system, I, J) tile pairs of the symmetric kernel
+  bool symmetric = false;        // items are (system, I, J, part) of the symmetric kernel
+  int nsplit = 1;                // source parts per symmetric tile pair
   int64_t *part_base = nullptr;  // device, nsys entries: each system's first partial slot
   int64_t part_elems = 0;        // partial doubles of the symmetric layout
 };
