@@ -1,19 +1,23 @@
 // Products of one configuration's mobility with several source vectors, U_k = M F_k.
 //
-// The Lanczos method (Sec. IV) needs only products with M, and several independent Krylov
+// The Lanczos method (Sec. II.C) needs only products with M, and several independent Krylov
 // processes on the same configuration (several noise vectors) need products with the same
-// matrix.  The pair coefficients of the regularised Rotne-Prager-Blake tensor (App. A) depend
-// on the geometry alone, so one evaluation serves every vector: about half the work of a
-// symmetric pair update is the coefficients, the rest is applying them to a vector.
+// matrix; so do the products a time step takes at its own configuration (M F + M_C T, the
+// first Lanczos product M W and, for a one-sided RFD, M W~).  The pair coefficients of the
+// regularised Rotne-Prager-Blake tensor (App. A) depend on the geometry alone, so one
+// evaluation serves every vector: about half the work of a symmetric pair update is the
+// coefficients, the rest is applying them to a vector.
 //
 // Layout: the symmetric tile-pair scheme of the single-vector product, one target per lane
-// (tile = kBlock spheres), kMulti vectors per launch:
+// (tile = kBlock spheres), K = 2, 3 or 4 vectors per launch, the first optionally with a torque:
 //   pack_multi    O(N K)    AoS float64 vectors -> SoA H-weighted sources src[(k 3 + c) n + i]
 //   pair kernel   O(N^2)    tile pair (I, J), I <= J, per workgroup: M_IJ F_J into the rows of
 //                           I (lane sums), M_JI F_I into the rows of J (rotating per-source sums
 //                           added across the workgroup's wavefronts in LDS); diagonal tiles as
-//                           ordered pairs.  Each pair's coefficients are computed once.
-//   reduce_multi  O(N^2/256) fixed-order sum of the tile partials, times H_i / (8 pi eta).
+//                           ordered pairs.  Each pair's coefficients are computed once.  Batches
+//                           of systems: persistent workgroups map a work-item number to
+//                           (system, I, J).
+//   reduce_multi  O(N^2/256) fixed-order sum of the tile partials, times H_i / (8 pi eta a).
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
