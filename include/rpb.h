@@ -261,7 +261,7 @@ int sab_step_batched(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cf
 /* Several source vectors, one configuration ------------------------------------------------
  *
  * vel[v] = M force[v] for v < nvec: force and vel are [nvec][n][3] float64 device arrays
- * (vector-major), pos [n][3].  The products the Lanczos method needs (Sec. IV) for several
+ * (vector-major), pos [n][3].  The products the Lanczos method needs (Sec. II.C) for several
  * independent noise vectors of one configuration share the pair coefficients: each unordered
  * pair's coefficients are evaluated once and applied to four vectors in the same launch
  * (the symmetric tile-pair kernel, diagonal tiles as ordered pairs).  Forces only (no
