@@ -55,6 +55,55 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+class ClockSampler:
+    """Samples the GPU shader clock (the active level of the sysfs pp_dpm_sclk table) from a
+    background thread while the timed steps run; best effort, empty where it is not readable."""
+
+    def __init__(self, period=0.05):
+        import glob
+        import threading
+        self.paths = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+        self.period = period
+        self.mhz = []
+        self._stop = threading.Event()
+        self._thread = threading.Thread(target=self._run, daemon=True)
+
+    def _read(self):
+        for path in self.paths:
+            try:
+                with open(path) as f:
+                    for line in f:
+                        if line.rstrip().endswith("*"):
+                            return float(line.split(":")[1].strip().split("Mhz")[0].split("MHz")[0])
+            except (OSError, ValueError, IndexError):
+                continue
+        return None
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = self._read()
+            if v is not None:
+                self.mhz.append(v)
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        if self.paths:
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self._thread.is_alive():
+            self._thread.join()
+
+    def summary(self):
+        if not self.mhz:
+            return None
+        v = sorted(self.mhz)
+        return {"sclk_mhz_median": v[len(v) // 2], "sclk_mhz_min": v[0], "sclk_mhz_max": v[-1],
+                "samples": len(v), "source": "pp_dpm_sclk during the timed steps"}
+
+
 def measured_traffic(kernel: str, n: int = PROFILED_N):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
     when the kernel sources changed since the counters were taken or `n` is another size."""
@@ -204,11 +253,12 @@ def main():
     torch.cuda.synchronize()
     ctx.timing(True)
     ctx.timing_read()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        iters.append(ctx.sab_step(state, **step_kw)[0])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with ClockSampler() as clocks:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            iters.append(ctx.sab_step(state, **step_kw)[0])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     kinds = {}
     for name, kind, fpp in (("fp64_force", KIND_FP64_FORCE, FLOPS_PER_PAIR_FORCE),
                             ("fp64_torque", KIND_FP64_TORQUE, FLOPS_PER_PAIR_TORQUE),
@@ -267,6 +317,7 @@ def main():
                      "ms_per_launch": dom["ms_per_launch"], "launches": dom["launches"]},
         "pair_kernels": kinds,
         "multi_vector_product": multi,
+        "gpu_clock": clocks.summary(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
@@ -310,11 +361,12 @@ def bench_batched(args, w, ctx, cpu):
     for _ in range(args.warmup):
         graph.launch()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        graph.launch()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with ClockSampler() as clocks:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.launch()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     step, iters, eps, _ = graph.status()
     graph.close()
     # eager batched steps (host reads the Lanczos flags every iteration) for comparison
@@ -348,6 +400,7 @@ def bench_batched(args, w, ctx, cpu):
         "lanczos_iters_last_step": [int(x) for x in iters],
         "launch_shapes": shapes,
         "batched_kernel": rates,
+        "gpu_clock": clocks.summary(),
         "roofline": {"bound": "alu", "achieved": dom["tflops"], "peak": peak, "unit": "TFLOP/s",
                      "frac": dom["tflops"] / peak, "traffic": None,
                      "kernel": f"batched pair kernel, force-only, {FLOPS_PER_PAIR_FORCE} flop/pair x "
