@@ -100,6 +100,19 @@ int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs,
   return RPB_OK;
 }
 
+void timing_discard(rpb_ctx *ctx, size_t first) {
+  for (size_t i = first; i < ctx->ev_start.size(); ++i) {
+    ctx->ev_pool.push_back(ctx->ev_start[i]);
+    ctx->ev_pool.push_back(ctx->ev_stop[i]);
+  }
+  if (first < ctx->ev_start.size()) {
+    ctx->ev_start.resize(first);
+    ctx->ev_stop.resize(first);
+    ctx->ev_pairs.resize(first);
+    ctx->ev_kind.resize(first);
+  }
+}
+
 }  // namespace rpb
 
 using namespace rpb;
@@ -155,6 +168,8 @@ void rpb_destroy(rpb_ctx *ctx) {
   for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
   for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (auto e : ctx->lz_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
   delete ctx;

@@ -14,6 +14,7 @@
 // reproducible.  The host reads a 32-byte status record once per iteration.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <vector>
 
 #include "rpb_internal.h"
@@ -41,6 +42,55 @@ struct LzState {
   int reason;     // 0 running, 1 converged, 2 breakdown, 3 not SPD, 4 eigensolve failed
 };
 static_assert(sizeof(LzState) % 8 == 0, "LzState is an array of doubles and two ints");
+static_assert(sizeof(LzState) <= kSmallWorkCounter, "LzState must fit the start of the small slot");
+static_assert(size_t(kMaxBatchSystems) * sizeof(LzStatus) <= kHostLzRingOffset,
+              "per-system records must stay below the status ring");
+
+// Host copies of the status words (eps, m, reason) of two consecutive iterations.
+struct LzRingSlot {
+  double eps;
+  int m;
+  int reason;
+};
+struct LzRing {
+  LzRingSlot slot[2];
+};
+static_assert(sizeof(LzRingSlot) == sizeof(double) + 2 * sizeof(int) &&
+                  offsetof(LzState, reason) - offsetof(LzState, eps) ==
+                      offsetof(LzRingSlot, reason) - offsetof(LzRingSlot, eps),
+              "the ring slot mirrors the status words of LzState");
+
+LzRing *lz_ring(rpb_ctx *ctx) {
+  return reinterpret_cast<LzRing *>(static_cast<char *>(host_scratch(ctx)) + kHostLzRingOffset);
+}
+
+// Waits for every ring copy still in flight (a previous call's last copy may target a slot
+// this call is about to reuse, possibly from another stream).
+int lz_ring_fence(rpb_ctx *ctx) {
+  for (int q = 0; q < 2; ++q) {
+    if (!ctx->lz_live[q]) continue;
+    RPB_HIP(ctx, hipEventSynchronize(ctx->lz_ev[q]));
+    ctx->lz_live[q] = false;
+  }
+  return RPB_OK;
+}
+
+// Enqueues the copy of the status words into ring slot q and marks it with event q.
+int lz_ring_post(rpb_ctx *ctx, LzRing *ring, int q, const double *status, hipStream_t stream) {
+  if (!ctx->lz_ev[q]) RPB_HIP(ctx, hipEventCreateWithFlags(&ctx->lz_ev[q], hipEventDisableTiming));
+  RPB_HIP(ctx, hipMemcpyAsync(&ring->slot[q], status, sizeof(LzRingSlot), hipMemcpyDeviceToHost,
+                              stream));
+  RPB_HIP(ctx, hipEventRecord(ctx->lz_ev[q], stream));
+  ctx->lz_live[q] = true;
+  return RPB_OK;
+}
+
+// Blocks until the copy into ring slot q has landed.
+int lz_ring_wait(rpb_ctx *ctx, int q) {
+  RPB_HIP(ctx, hipEventSynchronize(ctx->lz_ev[q]));
+  ctx->lz_live[q] = false;
+  return RPB_OK;
+}
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   const int t = threadIdx.x;
@@ -272,7 +322,10 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   }
 }
 
+// A process that has stopped (reason != 0) keeps its state: an iteration enqueued after the
+// stop leaves y, eps, m and reason as they are.
 __global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st) {
+  if (st->reason != 0) return;
   tridiag_body(m, tol, st);
 }
 
@@ -508,9 +561,14 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   if (!part) return st;
   LzState *ls = static_cast<LzState *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
   if (!ls) return st;
-  LzState *host = static_cast<LzState *>(host_scratch(ctx));
-  static_assert(sizeof(LzState) <= 4096 && sizeof(LzState) <= kSmallWorkCounter,
-                "status must fit the pinned scratch and the start of the small slot");
+  // The host reads the status of iteration m only after iteration m + 1 has been enqueued,
+  // so the device never idles while the host decides.  Every kernel of an iteration enqueued
+  // after the stop leaves the result unchanged: the product's kernels return at once while
+  // ls->reason is nonzero, tridiag_sqrt keeps y, eps and reason, and the other kernels touch
+  // only u, V's next column and entries of alpha and beta past the last iteration.
+  RPB_TRY(lz_ring_fence(ctx));
+  LzRing *ring = lz_ring(ctx);
+  const int *stopped = &ls->reason;
 
   lz_reset<<<1, 64, 0, stream>>>(ls);
   RPB_LAUNCHED(ctx);
@@ -518,52 +576,64 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, w, &ls->wnorm, V, nullptr);
   RPB_LAUNCHED(ctx);
 
-  int m = 0;
+  int m = 0;           // iterations whose result counts
   int reason = 0;
   double eps = 0.0;
-  for (m = 1; m <= max_iter; ++m) {
-    double *vm = V + int64_t(m - 1) * m3;
-    const double *vprev = m > 1 ? V + int64_t(m - 2) * m3 : nullptr;
+  size_t mark[2] = {0, 0};   // first timing record of each iteration in flight
+  bool stop = false;
+  for (int k = 1; k <= max_iter && !stop; ++k) {
+    mark[k & 1] = ctx->ev_start.size();
+    double *vm = V + int64_t(k - 1) * m3;
+    const double *vprev = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
     if (precond) {   // u = L^-1 M L^-1 vm
       divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, vm, L, t);
       RPB_LAUNCHED(ctx);
-      RPB_TRY(matvec_packed(ctx, p, g, t, nullptr, 0, n, u, stream));
+      RPB_TRY(matvec_packed(ctx, p, g, t, nullptr, 0, n, u, stream, stopped));
       divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
       RPB_LAUNCHED(ctx);
-    } else if (m == 1 && mw) {   // M v_1 = (M w) / |w| from the caller's product
+    } else if (k == 1 && mw) {   // M v_1 = (M w) / |w| from the caller's product
       scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, mw, &ls->wnorm, u, nullptr);
       RPB_LAUNCHED(ctx);
     } else {
-      RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream));
+      RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream, stopped));
     }
-    RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[m - 1], 0, stream));
-    three_term<<<nblk(m3), kThreads, 0, stream>>>(m3, u, vm, vprev, &ls->alpha[m - 1],
-                                                   m > 1 ? &ls->beta[m - 2] : nullptr);
+    RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
+    three_term<<<nblk(m3), kThreads, 0, stream>>>(m3, u, vm, vprev, &ls->alpha[k - 1],
+                                                   k > 1 ? &ls->beta[k - 2] : nullptr);
     RPB_LAUNCHED(ctx);
     {
-      const dim3 grid{unsigned(kRedBlocks), unsigned(m), 1u};
+      const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
       reorth_dots<<<grid, kThreads, 0, stream>>>(m3, V, u, part);
       RPB_LAUNCHED(ctx);
-      reorth_finish<<<1, kThreads, 0, stream>>>(m, kRedBlocks, part, ls->h);
+      reorth_finish<<<1, kThreads, 0, stream>>>(k, kRedBlocks, part, ls->h);
       RPB_LAUNCHED(ctx);
-      reorth_update<<<nblk(m3), kThreads, 0, stream>>>(m3, m, V, ls->h, u);
+      reorth_update<<<nblk(m3), kThreads, 0, stream>>>(m3, k, V, ls->h, u);
       RPB_LAUNCHED(ctx);
     }
-    RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[m - 1], 1, stream));
-    tridiag_sqrt<<<1, 64, 0, stream>>>(m, tol, ls);
+    RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[k - 1], 1, stream));
+    tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls);
     RPB_LAUNCHED(ctx);
-    if (m < max_iter) {
-      scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[m - 1],
-                                                           V + int64_t(m) * m3, ls);
+    if (k < max_iter) {
+      scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
+                                                           V + int64_t(k) * m3, ls);
       RPB_LAUNCHED(ctx);
     }
-    RPB_HIP(ctx, hipMemcpyAsync(host, ls, sizeof(LzState), hipMemcpyDeviceToHost, stream));
-    RPB_HIP(ctx, hipStreamSynchronize(stream));
-    reason = host->reason;
-    eps = host->eps;
-    if (reason != 0) break;
+    RPB_TRY(lz_ring_post(ctx, ring, k & 1, &ls->eps, stream));
+    // the status of the previous iteration (or of this one, after the last)
+    for (int q = k > 1 ? k - 1 : k; q <= k; ++q) {
+      if (q == k && k < max_iter) break;
+      RPB_TRY(lz_ring_wait(ctx, q & 1));
+      m = q;
+      reason = ring->slot[q & 1].reason;
+      eps = ring->slot[q & 1].eps;
+      if (reason != 0) {
+        // iteration q + 1, if enqueued, did no work: drop its pair-kernel timing records
+        if (q < k) timing_discard(ctx, mark[k & 1]);
+        stop = true;
+        break;
+      }
+    }
   }
-  if (m > max_iter) m = max_iter;
   basis_combine<<<nblk(m3), kThreads, 0, stream>>>(m3, m, V, ls->y, out);
   RPB_LAUNCHED(ctx);
   if (precond) {

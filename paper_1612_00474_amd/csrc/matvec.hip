@@ -62,7 +62,8 @@ __global__ void pack_geometry_mixed(int64_t n, const double *__restrict__ pos, d
 template <typename Real>
 __global__ void pack_vectors(int64_t n, const double *__restrict__ h,
                              const double *__restrict__ force, const double *__restrict__ torque,
-                             double inv_a, Real *__restrict__ out) {
+                             double inv_a, Real *__restrict__ out, const int *__restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double w = h[i];
@@ -277,6 +278,7 @@ struct PairArgs {
   int64_t row0;     // first target
   int64_t nrows;    // number of targets
   int64_t chunk;    // sources per workgroup (multiple of kBlock)
+  const int *skip;  // optional device flag: the launch does nothing while it is nonzero
 };
 
 template <bool TORQUE, int TPT, bool WALL, bool PERIODIC>
@@ -284,6 +286,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g
                                                           const double *__restrict__ src,
                                                           PairConsts<double> k,
                                                           double *__restrict__ partial) {
+  if (args.skip && *args.skip) return;
   __shared__ LdsD<TORQUE> L;
   TargetsD<TPT> T;
   const int64_t first = args.row0 + int64_t(blockIdx.x) * (kBlock * TPT);
@@ -300,6 +303,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
                                                             const float *__restrict__ src,
                                                             PairConsts<float> k,
                                                             double *__restrict__ partial) {
+  if (args.skip && *args.skip) return;
   __shared__ LdsF<TORQUE> L;
   TargetsF<TPT> T;
   const int64_t first = args.row0 + int64_t(blockIdx.x) * (kBlock * TPT);
@@ -313,7 +317,8 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF
 
 __global__ void reduce_partials(int64_t nrows, int nchunks, const double *__restrict__ partial,
                                 const double *__restrict__ h, double scale,
-                                double *__restrict__ vel) {
+                                double *__restrict__ vel, const int *__restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const double w = scale * h[r];
@@ -616,6 +621,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF
                                                                 const float *__restrict__ src,
                                                                 PairConsts<float> k,
                                                                 double *__restrict__ partial) {
+  if (a.skip && *a.skip) return;
   __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
   int64_t I, J;
@@ -629,6 +635,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
                                                               const double *__restrict__ src,
                                                               PairConsts<double> k,
                                                               double *__restrict__ partial) {
+  if (a.skip && *a.skip) return;
   __shared__ LdsD<TORQUE> L;
   __shared__ double col[kWaves][kBlock][3];
   int64_t I, J;
@@ -643,6 +650,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
 __global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
                                     const double *__restrict__ h, double scale,
                                     double *__restrict__ vel) {
+  if (a.skip && *a.skip) return;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= 3 * a.n) return;
   const int d = int(e / a.n);
@@ -904,7 +912,7 @@ void with_variant(bool torque, int tpt, bool wall, bool periodic, Fn &&fn) {
 inline bool periodic(const rpb_params *p) { return p->lx > 0.0; }
 
 int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const double *torque,
-                 void **src, hipStream_t stream) {
+                 void **src, hipStream_t stream, const int *skip = nullptr) {
   const int64_t n = g.n;
   const bool f64 = g.precision == RPB_FP64;
   const size_t esz = f64 ? sizeof(double) : sizeof(float);
@@ -914,10 +922,10 @@ int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const doubl
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
   if (f64)
     pack_vectors<double><<<blocks_for(n, 256), 256, 0, stream>>>(
-        n, h, force, torque, 1.0 / g.a, static_cast<double *>(*src));
+        n, h, force, torque, 1.0 / g.a, static_cast<double *>(*src), skip);
   else
     pack_vectors<float><<<blocks_for(n, 256), 256, 0, stream>>>(
-        n, h, force, torque, 1.0 / g.a, static_cast<float *>(*src));
+        n, h, force, torque, 1.0 / g.a, static_cast<float *>(*src), skip);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
@@ -1005,10 +1013,12 @@ inline size_t sym_partial_bytes(int64_t n, int64_t ts, int64_t nsplit = 1) {
 
 // Whole-system product with one evaluation per unordered pair.
 int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
-                     bool torque, const double *h, int tpt, double *vel, hipStream_t stream) {
+                     bool torque, const double *h, int tpt, double *vel, hipStream_t stream,
+                     const int *skip) {
   const int64_t n = g.n;
   const bool f64 = g.precision == RPB_FP64;
   SymArgs a{n, int64_t(kBlock) * tpt, 0, n};
+  a.skip = skip;
   a.nt = (n + a.ts - 1) / a.ts;
   a.nsplit = sym_nsplit(n, a.ts);
   if (a.nt * (a.nt + 1) / 2 * a.nsplit > 0x7fffffffll)
@@ -1042,13 +1052,13 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
 
 int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
                   const double *torque, int64_t row0, int64_t nrows, double *vel,
-                  hipStream_t stream) {
+                  hipStream_t stream, const int *skip) {
   const int64_t n = g.n;
   if (nrows <= 0) return RPB_OK;
   const bool has_t = torque != nullptr;
   const bool f64 = g.precision == RPB_FP64;
   void *src;
-  RPB_TRY(pack_sources(ctx, g, force, torque, &src, stream));
+  RPB_TRY(pack_sources(ctx, g, force, torque, &src, stream, skip));
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
 
   // Source chunking: enough workgroups to fill the chip several times over.  The chunks
@@ -1059,7 +1069,7 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   if (row0 == 0 && nrows == n && shape.symmetric &&
       sym_partial_bytes(n, int64_t(kBlock) * tpt, sym_nsplit(n, int64_t(kBlock) * tpt)) <=
           kMaxSymPartialBytes)
-    return matvec_symmetric(ctx, p, g, src, has_t, h, tpt, vel, stream);
+    return matvec_symmetric(ctx, p, g, src, has_t, h, tpt, vel, stream, skip);
   const int64_t per_wg = int64_t(kBlock) * tpt;
   const int64_t tiles = (nrows + per_wg - 1) / per_wg;
   const int64_t tiles_full = (n + per_wg - 1) / per_wg;
@@ -1076,7 +1086,7 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
       workspace(ctx, WS_PART, size_t(nchunks) * 3 * size_t(nrows) * sizeof(double), &st));
   if (!part) return st;
 
-  PairArgs args{n, row0, nrows, chunk};
+  PairArgs args{n, row0, nrows, chunk, skip};
   const dim3 grid{unsigned(tiles), unsigned(nchunks), 1u};
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
@@ -1098,7 +1108,7 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
 
   const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   reduce_partials<<<blocks_for(nrows, 256), 256, 0, stream>>>(nrows, int(nchunks), part,
-                                                              h + row0, scale, vel);
+                                                              h + row0, scale, vel, skip);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }

@@ -56,6 +56,7 @@ struct SymArgs {
   int64_t nt;          // tiles
   int64_t stride;      // stride of the source component arrays (all systems' spheres)
   int64_t nsplit = 1;  // workgroups per tile pair, each taking one part of the source tile
+  const int *skip = nullptr;   // optional device flag: the launch does nothing while it is nonzero
 };
 
 // v from lane (l + 1) mod 64 (DPP wave_rol:1).  Every lane has a source lane, so the "old"

@@ -89,6 +89,10 @@ struct rpb_ctx {
   std::vector<double> ev_pairs;
   std::vector<int> ev_kind;             // 2 * (precision == mixed) + (torque present)
   std::vector<hipEvent_t> ev_pool;
+  // Lanczos status ring (two slots in the upper half of the pinned scratch) and the events
+  // that mark each slot's copy as landed; `lz_live` is set while a copy may be in flight
+  hipEvent_t lz_ev[2] = {nullptr, nullptr};
+  bool lz_live[2] = {false, false};
 };
 
 namespace rpb {
@@ -99,8 +103,11 @@ int fail(rpb_ctx *ctx, int code, const char *fmt, ...);
 // Device buffer of at least `bytes` for `slot` (grows; synchronises the device on growth).
 void *workspace(rpb_ctx *ctx, Slot slot, size_t bytes, int *status);
 
-// Pinned host scratch (kHostScratchBytes).
+// Pinned host scratch (kHostScratchBytes).  The lower half holds device scalars and
+// per-system records copied back by one call and read before it returns; the upper half
+// holds the Lanczos status ring, whose last copy may still land after the call returns.
 constexpr size_t kHostScratchBytes = 1 << 17;
+constexpr size_t kHostLzRingOffset = kHostScratchBytes / 2;
 inline void *host_scratch(rpb_ctx *ctx) { return ctx->host_pinned; }
 
 #define RPB_HIP(ctx, call)                                                              \
@@ -135,6 +142,8 @@ int check_finite(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream)
 // Timing hooks around the pair kernel.
 int timing_begin(rpb_ctx *ctx, hipStream_t stream, hipEvent_t *start);
 int timing_end(rpb_ctx *ctx, hipStream_t stream, hipEvent_t start, double pairs, int kind);
+// Drops the timing records from index `first` on (launches that turned out to do no work).
+void timing_discard(rpb_ctx *ctx, size_t first);
 
 // ---- mobility product (matvec.hip) ------------------------------------------------------
 
@@ -151,11 +160,12 @@ int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *po
                   Packed *out, hipStream_t stream);
 
 // vel[r] for rows [row0, row0 + nrows) of U = M F + M_C T for packed geometry `g`.
-// force / torque are [n][3] float64 device arrays (nullable, not both).  `scale_out`
-// multiplies the result (1 for plain products).
+// force / torque are [n][3] float64 device arrays (nullable, not both).  `skip` (nullable)
+// is a device flag read by every kernel of the product when it runs: while it is nonzero
+// they return at once and `vel` keeps its contents.
 int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
                   const double *torque, int64_t row0, int64_t nrows, double *vel,
-                  hipStream_t stream);
+                  hipStream_t stream, const int *skip = nullptr);
 
 // ---- batched products (matvec.hip) -----------------------------------------------------
 
