@@ -106,8 +106,11 @@ int rpb_mobility_matvec(rpb_ctx *ctx, const rpb_params *p, int64_t n, const doub
                         rpb_stream_t stream);
 
 /* Rows [row_begin, row_end) of the same product (all n spheres are sources).  vel_out
- * then holds (row_end - row_begin) rows.  Concatenating the results of a partition of
- * [0, n) gives rpb_mobility_matvec exactly (the per-GPU share of a row-sharded product). */
+ * then holds (row_end - row_begin) rows: the per-GPU share of a row-sharded product.  Row
+ * ranges take the ordered kernel (target tiles x source chunks, chunking fixed by n), so
+ * the results of any partition of [0, n) concatenate bitwise to one another and to a
+ * whole-system product taken with that kernel; the default whole-system product (one
+ * evaluation per unordered pair, other summation order) agrees with them to rounding. */
 int rpb_mobility_matvec_rows(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
                              const double *force, const double *torque, int64_t row_begin,
                              int64_t row_end, double *vel_out, rpb_stream_t stream);
@@ -198,7 +201,7 @@ typedef struct {
   double dt;            /* time step (> 0) */
   double delta;         /* RFD length (> 0) */
   double lanczos_tol;   /* Lanczos relative tolerance (> 0) */
-  int lanczos_max_iter; /* 1..128 */
+  int lanczos_max_iter; /* 1..64 */
   int scheme;           /* 0 = stochastic Adams-Bashforth, 1 = Euler-Maruyama */
   int rfd_precision;    /* rpb_precision of the two RFD products */
   int rfd_scheme;       /* 0 = centred RFD (rfd_drift), 1 = one-sided (rfd_drift_one_sided) */
@@ -343,7 +346,9 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
  * pair interactions of the launches of kernel variant `kind`, and removes them from the
  * record.  kind = 2 * (precision == RPB_MIXED) + (torque present), plus 4 for the batched
  * kernel; 8 + 2 * (precision == RPB_MIXED) for the multi-vector kernel, whose pair count is
- * n^2 times the vectors of the launch; kind = -1 takes all. */
+ * n^2 times the vectors of the launch; kind = -1 takes all.  A single-system Lanczos solve
+ * enqueues one iteration past its stop before it reads the stop flag; that iteration's
+ * launches return at once and are dropped from the record. */
 int rpb_timing_enable(rpb_ctx *ctx, int enable);
 int rpb_timing_read(rpb_ctx *ctx, int kind, double *ms_out, int64_t *launches_out,
                     double *pairs_out);

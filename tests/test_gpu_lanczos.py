@@ -116,3 +116,29 @@ def test_preconditioned_tolerance_run_is_a_root_of_m(ctx, c1):
         g, it, eps, st = ctx.lanczos(dev(inp["pos"]), dev(inp["w"]), 1e-6, precision=precision,
                                      precond=True)
         assert rel2(host(g).ravel(), S @ w) <= tol, precision
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_stop_read_one_iteration_late_changes_nothing(ctx, c1, precond):
+    # The solve enqueues one iteration past its stop before the host reads the stop flag; that
+    # iteration must leave the result alone and must not count as a pair-kernel launch.  A run
+    # capped at the same m never enqueues past its last iteration, so the two agree bitwise.
+    import torch
+    inp, _ = c1
+    P, W = dev(inp["pos"]), dev(inp["w"])
+    for precision in ("fp64", "mixed"):
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.timing_read()
+        g, it, eps, st = ctx.lanczos(P, W, 1e-6, precision=precision, precond=precond)
+        _, launches, _ = ctx.timing_read()
+        ctx.timing(False)
+        assert 2 <= it < 64
+        assert launches == it, (precision, it, launches)
+        capped, it2, eps2, _ = ctx.lanczos(P, W, 1e-6, max_iter=it, precision=precision,
+                                           precond=precond)
+        assert it2 == it and eps2 == eps
+        assert torch.equal(g, capped), precision
+        # back to back: the previous solve's last status copy cannot leak into this one
+        again, it3, eps3, _ = ctx.lanczos(P, W, 1e-6, precision=precision, precond=precond)
+        assert it3 == it and eps3 == eps and torch.equal(g, again)
