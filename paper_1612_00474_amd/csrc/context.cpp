@@ -170,6 +170,7 @@ void rpb_destroy(rpb_ctx *ctx) {
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (auto e : ctx->lz_ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->fin_ev) (void)hipEventDestroy(ctx->fin_ev);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
   delete ctx;

@@ -173,8 +173,8 @@ __device__ __forceinline__ int3 cell_of(double x, double y, double z, const Cell
   int cx, cy;
   if (c.ncx > 0) {
     const double xw = x - c.lx * floor(x / c.lx), yw = y - c.ly * floor(y / c.ly);
-    cx = min(max(int(xw / c.csx), 0), c.ncx - 1);
-    cy = min(max(int(yw / c.csy), 0), c.ncy - 1);
+    cx = min(max(clamp_cell(xw / c.csx), 0), c.ncx - 1);
+    cy = min(max(clamp_cell(yw / c.csy), 0), c.ncy - 1);
   } else {
     cx = clamp_cell(x / c.cs);
     cy = clamp_cell(y / c.cs);

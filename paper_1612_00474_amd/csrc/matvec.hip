@@ -950,6 +950,39 @@ int check_finite(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream)
   return RPB_OK;
 }
 
+int check_finite_begin(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream) {
+  if (ctx->fin_live) {   // a copy left in flight by a call that failed before its _end
+    RPB_HIP(ctx, hipEventSynchronize(ctx->fin_ev));
+    ctx->fin_live = false;
+  }
+  int st;
+  char *small = static_cast<char *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
+  if (!small) return st;
+  int *f = reinterpret_cast<int *>(small + kSmallFiniteFlag);
+  zero_int<<<1, 1, 0, stream>>>(f);
+  RPB_LAUNCHED(ctx);
+  const int64_t m = 3 * n;
+  const unsigned nb = unsigned(std::min<int64_t>(1024, (m + 255) / 256));
+  finite_flag<<<nb, 256, 0, stream>>>(m, pos, f);
+  RPB_LAUNCHED(ctx);
+  if (!ctx->fin_ev) RPB_HIP(ctx, hipEventCreateWithFlags(&ctx->fin_ev, hipEventDisableTiming));
+  int *host = reinterpret_cast<int *>(static_cast<char *>(host_scratch(ctx)) + kHostFiniteOffset);
+  RPB_HIP(ctx, hipMemcpyAsync(host, f, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RPB_HIP(ctx, hipEventRecord(ctx->fin_ev, stream));
+  ctx->fin_live = true;
+  return RPB_OK;
+}
+
+int check_finite_end(rpb_ctx *ctx) {
+  if (!ctx->fin_live) return fail(ctx, RPB_EDEVICE, "position check was not started");
+  RPB_HIP(ctx, hipEventSynchronize(ctx->fin_ev));
+  ctx->fin_live = false;
+  const int *host =
+      reinterpret_cast<const int *>(static_cast<char *>(host_scratch(ctx)) + kHostFiniteOffset);
+  if (host[0]) return fail(ctx, RPB_ENONFINITE, "positions contain NaN or Inf");
+  return RPB_OK;
+}
+
 int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, Slot slot,
                   Packed *out, hipStream_t stream) {
   int st;

@@ -93,6 +93,9 @@ struct rpb_ctx {
   // that mark each slot's copy as landed; `lz_live` is set while a copy may be in flight
   hipEvent_t lz_ev[2] = {nullptr, nullptr};
   bool lz_live[2] = {false, false};
+  // deferred position check (check_finite_begin / _end): its flag's copy and event
+  hipEvent_t fin_ev = nullptr;
+  bool fin_live = false;
 };
 
 namespace rpb {
@@ -108,6 +111,7 @@ void *workspace(rpb_ctx *ctx, Slot slot, size_t bytes, int *status);
 // holds the Lanczos status ring, whose last copy may still land after the call returns.
 constexpr size_t kHostScratchBytes = 1 << 17;
 constexpr size_t kHostLzRingOffset = kHostScratchBytes / 2;
+constexpr size_t kHostFiniteOffset = kHostLzRingOffset + 1024;   // deferred position check
 inline void *host_scratch(rpb_ctx *ctx) { return ctx->host_pinned; }
 
 #define RPB_HIP(ctx, call)                                                              \
@@ -138,6 +142,12 @@ int check_params(rpb_ctx *ctx, const rpb_params *p);
 bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes);
 // Checks that every position is finite (synchronises `stream`).
 int check_finite(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream);
+// The same check in two halves: _begin enqueues it and the copy of its flag to pinned host
+// memory; _end waits for that copy only (not for work enqueued after it) and returns
+// RPB_ENONFINITE if a position is NaN or Inf.  Work enqueued between the two may see those
+// values, so it must not index memory by position value, and must write only workspace.
+int check_finite_begin(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream);
+int check_finite_end(rpb_ctx *ctx);
 
 // Timing hooks around the pair kernel.
 int timing_begin(rpb_ctx *ctx, hipStream_t stream, hipEvent_t *start);

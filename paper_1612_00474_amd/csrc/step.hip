@@ -178,7 +178,11 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
 
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   RPB_HIP(ctx, hipSetDevice(ctx->device));
-  RPB_TRY(check_finite(ctx, state->pos, n, stream));
+  // The position check is read back only once the noise, the forces and the first product
+  // are enqueued, so the device goes on from the previous call's work without a pause.
+  // Those kernels index memory by sphere, tile and hashed (clamped) cell, never by a raw
+  // position value, and write only workspace; the state changes after the check has passed.
+  RPB_TRY(check_finite_begin(ctx, state->pos, n, stream));
   const int64_t m3 = 3 * n;
   int st;
   double *F = static_cast<double *>(workspace(ctx, WS_FORCE, nb, &st));
@@ -231,6 +235,8 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   } else {
     RPB_TRY(matvec_packed(ctx, p, geo, F, T, 0, n, u, stream));
   }
+
+  RPB_TRY(check_finite_end(ctx));
 
   // Brownian increment (the last iterate is used if the tolerance is not met)
   int iters = 0;

@@ -130,3 +130,39 @@ def test_step_products_over_several_tiles(ctx, precision, rfd_precision, rfd, to
           f"displacement rel2 = {err_x:.3e}")
     assert it == mref == M_FIXED
     assert err_u <= tol_u and err_x <= tol_x
+
+
+@pytest.mark.parametrize("box", [None, "periodic"])
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_non_finite_position_leaves_state_alone(box, bad):
+    # the step reads its position check back only after the forces (cell list) and the first
+    # product are enqueued; a NaN or Inf must still end in RPB_ENONFINITE with the state as it
+    # was, and the next good step must run normally
+    import torch
+    from paper_1612_00474_amd import Context, StepState
+    from paper_1612_00474_amd._lib import RPB_ENONFINITE, RpbError
+    require_gpu()
+    inp = _setup(n=300, seed=4)
+    side = wl.side_for_area_fraction(300, 0.4)
+    c = Context(0, box=(side, side)) if box else Context(0)
+    try:
+        kw = dict(dt=0.01, delta=1e-4, lanczos_tol=1e-4, **PHYS)
+        for precision in ("fp64", "mixed"):
+            state = StepState(dev(inp["pos"]))
+            c.sab_step(state, precision=precision, **kw)
+            good_pos, good_u = state.pos.clone(), state.u_prev.clone()
+            for row, comp in ((0, 2), (150, 0), (299, 1)):
+                state.pos[row, comp] = bad
+                before = state.pos.clone()
+                with pytest.raises(RpbError) as e:
+                    c.sab_step(state, precision=precision, **kw)
+                assert e.value.status == RPB_ENONFINITE
+                assert np.array_equal(host(state.pos), host(before), equal_nan=True)
+                assert torch.equal(state.u_prev, good_u)
+                assert state.step == 1 and state.have_prev
+                state.pos.copy_(good_pos)
+            it, _, _ = c.sab_step(state, precision=precision, **kw)
+            assert it >= 2 and state.step == 2
+            assert torch.isfinite(state.pos).all() and torch.isfinite(state.u_prev).all()
+    finally:
+        c.close()
