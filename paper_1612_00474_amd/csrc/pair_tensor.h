@@ -470,9 +470,11 @@ __device__ __forceinline__ void for_images(Real dx, Real dy, const PairConsts<Re
   }
   dx -= k.lx * round_nearest(dx * k.ilx);
   dy -= k.ly * round_nearest(dy * k.ily);
-#pragma unroll
+  // Kept as a loop: nine inlined copies of the pair code (times the callers' own unrolling)
+  // would exhaust the vector registers and leave one wavefront per SIMD.
+#pragma unroll 1
   for (int ix = -1; ix <= 1; ++ix)
-#pragma unroll
+#pragma unroll 1
     for (int iy = -1; iy <= 1; ++iy) f(dx + Real(ix) * k.lx, dy + Real(iy) * k.ly);
 }
 
