@@ -375,44 +375,48 @@ __device__ __forceinline__ void sym_apply_torque(const SymCoef<Real> &c, Real zi
   }
   const Real iR = c.iR, iR2 = c.iR2, ez = c.ez, X = c.X, Rz = c.Rz;
   const Real iR3 = iR * iR2;
-  const Real al = iR3 - cT;                 // coefficient of kv (both directions)
+  const Real iR4 = iR2 * iR2;
+  const Real al = iR3 - cT;                 // coefficient of k (both directions)
   const Real xez = X * ez;
   const Real be0 = iR2 * (Real(2) * xez) - iR3 * Rz;
   const Real d30 = Real(10) * xez - Real(6) * ez;
-  const Real wz = d30 * ez - Real(2) * X;   // with the hh part of d3 added per direction
-  {  // i <- j: torque T_j, image height z~_j
+  const Real wz = d30 * ez - Real(2) * X;   // with the image-height part added per direction
+  const Real iR2x2 = Real(2) * iR2;
+  const Real ez6 = Real(6) * ez;
+  // Per direction, with k = (r_x, r_y, 0) x T = (r_y T_z, -r_x T_z, K):
+  //   u_x,y += al k_x,y + be (T_y, -T_x) + ga (r_x, r_y),   u_z += K (al - (wz + 6 h e_z)/|R|^3),
+  //   be = 2h/|R|^2 + be0 + cT r_z,   ga = -K (d30 + 6h)/|R|^4,   h = image height / |R|.
+  {  // i <- j: torque T_j, r = (dx, dy, dz), image height z~_j
     const Real hh = c.hh;
     const Real tx = tq[0], ty = tq[1], tz = tq[2];
-    const Real kx = dy * tz, ky = -(dx * tz), kz = dx * ty - dy * tx;
-    const Real d3 = d30 + Real(6) * hh;
-    const Real sv = -(kz * iR);
-    const Real be = cT * dz + (be0 + iR2 * (Real(2) * hh));
-    const Real ga = iR3 * (sv * d3);
-    ox += al * kx;
+    const Real K = dx * ty - dy * tx;
+    const Real P = al * tz;
+    const Real be = iR2x2 * hh + (cT * dz + be0);
+    const Real ga = -K * (iR4 * (Real(6) * hh + d30));
+    const Real cz = al - iR3 * (hh * ez6 + wz);
+    ox += P * dy;
     ox += be * ty;
     ox += ga * dx;
-    oy += al * ky;
+    oy -= P * dx;
     oy += ga * dy;
     oy -= be * tx;
-    oz += al * kz;
-    oz += (iR2 * sv) * (wz + Real(6) * hh * ez);
+    oz += K * cz;
   }
   {  // j <- i: torque T_i, r -> -r, image height z~_i
-    const Real tx = uq[0], ty = uq[1], tz = uq[2];
     const Real hi = zi * iR;
-    const Real kx = -(dy * tz), ky = dx * tz, kz = dy * tx - dx * ty;
-    const Real d3 = d30 + Real(6) * hi;
-    const Real sv = -(kz * iR);
-    const Real be = (be0 + iR2 * (Real(2) * hi)) - cT * dz;
-    const Real ga = iR3 * (sv * d3);
-    px += al * kx;
+    const Real tx = uq[0], ty = uq[1], tz = uq[2];
+    const Real K = dy * tx - dx * ty;
+    const Real P = al * tz;
+    const Real be = iR2x2 * hi + (be0 - cT * dz);
+    const Real ga = -K * (iR4 * (Real(6) * hi + d30));
+    const Real cz = al - iR3 * (hi * ez6 + wz);
+    px -= P * dy;
     px += be * ty;
     px -= ga * dx;
-    py += al * ky;
+    py += P * dx;
     py -= ga * dy;
     py -= be * tx;
-    pz += al * kz;
-    pz += (iR2 * sv) * (wz + Real(6) * hi * ez);
+    pz += K * cz;
   }
 }
 
