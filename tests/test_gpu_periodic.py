@@ -104,3 +104,60 @@ def test_periodic_forces_small_box(ctx):
         assert rel2(f, ref) <= 1e-12
     finally:
         c.close()
+
+
+def test_periodic_product_several_tiles():
+    # 1,100 spheres: several 256- or 512-sphere tiles and a ragged last one, so the symmetric
+    # kernel's off-diagonal tile pairs (one image loop serving both directions) are exercised
+    require_gpu()
+    from paper_1612_00474_amd import Context
+    box = (90.0, 70.0)
+    rng = np.random.default_rng(21)
+    n = 1100
+    pos = np.column_stack([rng.uniform(0, box[0], n), rng.uniform(0, box[1], n),
+                           rng.uniform(1.05, 2.5, n)])
+    pos[0] = [0.3, 35.0, 1.3]                  # pairs across both edges
+    pos[n - 1] = [box[0] - 0.6, 35.4, 1.6]
+    pos[1] = [20.0, 0.2, 1.2]
+    pos[n - 2] = [20.5, box[1] - 0.4, 1.4]
+    pos[2, 0] -= 3 * box[0]                    # far outside the box
+    pos[3, 2] = 0.6                            # below z = a
+    F, T = rng.standard_normal(pos.shape), rng.standard_normal(pos.shape)
+    rows = np.concatenate([np.arange(6), rng.choice(n, 40, replace=False), [n - 2, n - 1]])
+    c = Context(0, box=box)
+    try:
+        for torque in (None, T):
+            ref = mobility.matvec(pos, F, torque, rows=rows, box=box)
+            for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+                for tpt, sym in ((1, 1), (2, 1), (1, 0), (2, 0)):
+                    c.set_tuning(precision, tpt=tpt, symmetric=sym)
+                    u = host(c.matvec(dev(pos), dev(F), None if torque is None else dev(torque),
+                                      precision))[rows]
+                    err = rel2(u, ref)
+                    assert err <= tol, (tpt, sym, precision, torque is None, err)
+    finally:
+        c.close()
+
+
+def test_periodic_full_size_row_sampled():
+    # the 65,536-sphere sheet in a box of its own side, force-only products as the benchmark
+    # times them (launch shape from the tuner), against the oracle on sampled rows
+    require_gpu()
+    from paper_1612_00474_amd import Context
+    from paper_1612_00474_amd import workloads as wl
+    w = wl.WORKLOADS["sheet64k_mixed"]
+    inp = wl.make_inputs(w, 0)
+    box = (w.side, w.side)
+    rows = np.random.default_rng(17).choice(w.n, 3, replace=False)
+    rows[0] = w.n - 1
+    ref = mobility.matvec(inp["pos"], inp["force"], None, rows=rows, box=box)
+    c = Context(0, box=box)
+    try:
+        P, F = dev(inp["pos"]), dev(inp["force"])
+        for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+            c.autotune(P, None, precision)
+            err = rel2(host(c.matvec(P, F, None, precision))[rows], ref)
+            print(f"periodic sheet64k {precision}: rel2 = {err:.3e} over {len(rows)} rows")
+            assert err <= tol
+    finally:
+        c.close()
