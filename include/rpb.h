@@ -338,6 +338,18 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
                  const double *pos, int reps, rpb_tuning *out, double *best_ms_out,
                  rpb_stream_t stream);
 
+/* Output check (debug aid) ---------------------------------------------------------------------
+ *
+ * Off by default.  When enabled on a context, rpb_mobility_matvec, rpb_mobility_matvec_rows,
+ * rpb_mobility_matvec_batched, lanczos_sqrt_apply (and its preconditioned form), rfd_drift,
+ * rfd_drift_one_sided and sab_step scan their result (the velocity, the increment, the drift,
+ * the new positions) for NaN or Inf once it is computed, synchronise the stream and return
+ * RPB_ENONFINITE if one is found.  The result is left as computed (for sab_step the state has
+ * advanced).  Inputs other than positions (forces, torques, noise) are not checked, so this is
+ * how a non-finite force shows up.  Costs one pass over the result and a synchronisation per
+ * call.  Returns RPB_EINVAL for a NULL context. */
+int rpb_output_check_enable(rpb_ctx *ctx, int enable);
+
 /* Timing ------------------------------------------------------------------------------------
  *
  * When enabled, the library brackets every launch of the O(N^2) pair kernel with HIP

@@ -29,7 +29,7 @@ EXPORTS = (
     "rpb_mobility_matvec_batched", "lanczos_sqrt_apply_batched", "sab_step_batched",
     "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
     "rpb_step_graph_destroy", "rpb_get_tuning", "rpb_set_tuning", "rpb_autotune",
-    "rpb_mobility_matvec_multi", "lanczos_sqrt_apply_multi",
+    "rpb_mobility_matvec_multi", "lanczos_sqrt_apply_multi", "rpb_output_check_enable",
 )
 
 
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "sab_step": (C.c_int, [P, pp, C.POINTER(RpbSabConfig), C.POINTER(RpbSabState), P, P,
                                C.POINTER(C.c_int), C.POINTER(D), P]),
         "rpb_timing_enable": (C.c_int, [P, C.c_int]),
+        "rpb_output_check_enable": (C.c_int, [P, C.c_int]),
         "rpb_timing_read": (C.c_int, [P, C.c_int, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
         "rpb_mobility_matvec_batched": (C.c_int, [P, pp, C.c_int32, P, P, P, P, P, P]),
         "lanczos_sqrt_apply_batched": (C.c_int, [P, pp, C.c_int32, P, P, P, D, C.c_int, P, P, P, P]),
@@ -490,6 +491,10 @@ class Context:
         self._check(self.lib.rpb_autotune(self.h, C.byref(p), o.size - 1, _np_ptr(o), _ptr(pos),
                                           int(reps), C.byref(t), C.byref(ms), _stream()))
         return t.as_dict()[precision], ms.value
+
+    def output_check(self, enable: bool):
+        """Scan each result for NaN / Inf and raise (RPB_ENONFINITE) if one is found."""
+        self._check(self.lib.rpb_output_check_enable(self.h, int(enable)))
 
     # -- timing --------------------------------------------------------------------------
     def timing(self, enable: bool):

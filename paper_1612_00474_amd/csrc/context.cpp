@@ -178,6 +178,12 @@ void rpb_destroy(rpb_ctx *ctx) {
 
 const char *rpb_last_error(const rpb_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
+int rpb_output_check_enable(rpb_ctx *ctx, int enable) {
+  if (!ctx) return RPB_EINVAL;
+  ctx->check_output = enable != 0;
+  return RPB_OK;
+}
+
 int rpb_timing_enable(rpb_ctx *ctx, int enable) {
   if (!ctx) return RPB_EINVAL;
   ctx->timing = enable != 0;

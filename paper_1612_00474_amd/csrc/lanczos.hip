@@ -833,7 +833,11 @@ int lanczos_entry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *po
   RPB_TRY(check_finite(ctx, pos, n, stream));
   Packed g;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
-  return lanczos_run(ctx, p, g, w, tol, max_iter, precond, out, iters_out, eps_out, stream);
+  const int lz =
+      lanczos_run(ctx, p, g, w, tol, max_iter, precond, out, iters_out, eps_out, stream);
+  if (lz != RPB_OK && lz != RPB_ENOCONV) return lz;
+  RPB_TRY(check_output(ctx, out, 3 * n, stream, "the Brownian increment"));
+  return lz;
 }
 
 }  // namespace

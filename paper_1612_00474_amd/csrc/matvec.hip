@@ -950,6 +950,24 @@ int check_finite(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream)
   return RPB_OK;
 }
 
+int check_output(rpb_ctx *ctx, const double *v, int64_t m, hipStream_t stream, const char *what) {
+  if (!ctx->check_output || m <= 0) return RPB_OK;
+  int st;
+  char *small = static_cast<char *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
+  if (!small) return st;
+  int *f = reinterpret_cast<int *>(small + kSmallFiniteFlag);
+  zero_int<<<1, 1, 0, stream>>>(f);
+  RPB_LAUNCHED(ctx);
+  const unsigned nb = unsigned(std::min<int64_t>(1024, (m + 255) / 256));
+  finite_flag<<<nb, 256, 0, stream>>>(m, v, f);
+  RPB_LAUNCHED(ctx);
+  int *host = static_cast<int *>(host_scratch(ctx));
+  RPB_HIP(ctx, hipMemcpyAsync(host, f, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RPB_HIP(ctx, hipStreamSynchronize(stream));
+  if (host[0]) return fail(ctx, RPB_ENONFINITE, "%s contains NaN or Inf", what);
+  return RPB_OK;
+}
+
 int check_finite_begin(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream) {
   if (ctx->fin_live) {   // a copy left in flight by a call that failed before its _end
     RPB_HIP(ctx, hipEventSynchronize(ctx->fin_ev));
@@ -1392,7 +1410,8 @@ int matvec_entry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos
   RPB_TRY(check_finite(ctx, pos, n, stream));
   Packed g;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
-  return matvec_packed(ctx, p, g, force, torque, row0, row1 - row0, vel, stream);
+  RPB_TRY(matvec_packed(ctx, p, g, force, torque, row0, row1 - row0, vel, stream));
+  return check_output(ctx, vel, 3 * (row1 - row0), stream, "the velocity");
 }
 
 }  // namespace
@@ -1433,7 +1452,8 @@ int rpb_mobility_matvec_batched(rpb_ctx *ctx, const rpb_params *p, int32_t nsys,
   RPB_TRY(prepare_batch(ctx, nsys, offs, p->precision, &b, stream));
   Packed g;
   RPB_TRY(pack_geometry(ctx, p, n, pos, WS_GEOM, &g, stream));
-  return matvec_batched(ctx, p, b, g, force, torque, nullptr, vel_out, stream);
+  RPB_TRY(matvec_batched(ctx, p, b, g, force, torque, nullptr, vel_out, stream));
+  return check_output(ctx, vel_out, 3 * n, stream, "the velocity");
 }
 
 }  // extern "C"

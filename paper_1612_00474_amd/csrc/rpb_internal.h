@@ -96,6 +96,8 @@ struct rpb_ctx {
   // deferred position check (check_finite_begin / _end): its flag's copy and event
   hipEvent_t fin_ev = nullptr;
   bool fin_live = false;
+  // opt-in scan of each entry point's output for NaN / Inf (rpb_output_check_enable)
+  bool check_output = false;
 };
 
 namespace rpb {
@@ -148,6 +150,9 @@ int check_finite(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream)
 // values, so it must not index memory by position value, and must write only workspace.
 int check_finite_begin(rpb_ctx *ctx, const double *pos, int64_t n, hipStream_t stream);
 int check_finite_end(rpb_ctx *ctx);
+// With ctx->check_output set: scan m values at v for NaN / Inf on `stream`, synchronise, and
+// return RPB_ENONFINITE naming `what` if one is found; RPB_OK at once otherwise.
+int check_output(rpb_ctx *ctx, const double *v, int64_t m, hipStream_t stream, const char *what);
 
 // Timing hooks around the pair kernel.
 int timing_begin(rpb_ctx *ctx, hipStream_t stream, hipEvent_t *start);

@@ -258,6 +258,7 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   state->have_prev = 1;
   if (iters_out) *iters_out = iters;
   if (eps_out) *eps_out = eps;
+  RPB_TRY(check_output(ctx, state->pos, m3, stream, "the new positions"));
   return lz;
 }
 

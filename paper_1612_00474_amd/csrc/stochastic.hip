@@ -206,7 +206,8 @@ int rfd_entry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   RPB_HIP(ctx, hipSetDevice(ctx->device));
   RPB_TRY(check_finite(ctx, pos, n, stream));
-  return rfd_run(ctx, p, n, pos, w_tilde, delta, rfd_precision, one_sided, drift_out, stream);
+  RPB_TRY(rfd_run(ctx, p, n, pos, w_tilde, delta, rfd_precision, one_sided, drift_out, stream));
+  return check_output(ctx, drift_out, 3 * n, stream, "the drift");
 }
 
 }  // namespace

@@ -190,3 +190,35 @@ def test_symmetric_kernel_matches_oracle_and_ordered(ctx, n, tpt, torque):
         uo = host(c.matvec(P, Fd, Td, precision))
         assert rel2(us, uo) <= (1e-13 if precision == "fp64" else 2e-6)
     c.close()
+
+
+def test_output_check(ctx, c1):
+    # rpb_output_check_enable: results are scanned for NaN / Inf (only positions are checked
+    # on input, so a NaN force is how a non-finite result arises)
+    from paper_1612_00474_amd._lib import RPB_ENONFINITE, RpbError
+    P, F, Wt = dev(c1["pos"]), dev(c1["force"]), dev(c1["w_tilde"])
+    bad = F.clone()
+    bad[7, 2] = float("nan")
+    assert np.isnan(host(ctx.matvec(P, bad, None))).any()      # off by default
+    ctx.output_check(True)
+    try:
+        for precision in ("fp64", "mixed"):
+            assert np.isfinite(host(ctx.matvec(P, F, None, precision))).all()
+            with pytest.raises(RpbError) as e:
+                ctx.matvec(P, bad, None, precision)
+            assert e.value.status == RPB_ENONFINITE
+        n = P.shape[0]
+        offs = np.array([0, 100, n], dtype=np.int64)
+        ctx.matvec_batched(P, offs, F)
+        with pytest.raises(RpbError) as e:
+            ctx.matvec_batched(P, offs, bad)
+        assert e.value.status == RPB_ENONFINITE
+        assert np.isfinite(host(ctx.rfd(P, Wt, 1e-4))).all()
+        badw = Wt.clone()
+        badw[3, 0] = float("inf")
+        with pytest.raises(RpbError) as e:
+            ctx.rfd(P, badw, 1e-4)
+        assert e.value.status == RPB_ENONFINITE
+    finally:
+        ctx.output_check(False)
+    assert np.isnan(host(ctx.matvec(P, bad, None))).any()      # off again
