@@ -194,6 +194,14 @@ __global__ void basis_combine(int64_t m, int nvec, const double *__restrict__ V,
   out[i] = acc;
 }
 
+// 1/sqrt(x) for x > 0: hardware estimate, then one third-order Newton step on
+// e = 1 - x y^2, y (1 + e/2 + 3e^2/8) = y (1 - e)^{-1/2} + O(e^3).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
 // Eigendecomposition of T_m by implicit QL with Wilkinson-type shifts (Bowdler, Martin,
 // Reinsch, Wilkinson 1968), then y_m = |w| Q L^{1/2} Q^T e_1, eps_m and the stop test.
 // One wavefront: lane k owns row k of the eigenvector matrix Z.  Every lane runs the same
@@ -231,36 +239,46 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
       double g = (Dg[(l + 1)] - dl) / (2.0 * el);
       double r = sqrt(g * g + 1.0);
       g = Dg[mm] - dl + el / (g + copysign(r, g));
+      // One sweep of plane rotations from (mm - 1, mm) down to (l, l + 1).  d[i + 1] (not yet
+      // rewritten in this sweep) and column i + 1 of this lane's row of Z are carried in
+      // registers from one rotation to the next, so the LDS loads of e[i], d[i] and column i
+      // do not wait on the previous rotation's stores.  The rotation is formed from
+      // 1/sqrt(f^2 + g^2): r = h2 / sqrt(h2), s = f / r, c = g / r.
       double s = 1.0, c = 1.0, p = 0.0;
       bool underflow = false;
+      double dhi = Dg[mm];
+      double zhi = (lane < m) ? Z[mm * 64 + lane] : 0.0;
       for (int i = mm - 1; i >= l; --i) {
         const double ei = Eg[i];
+        const double di = Dg[i];
+        const double zi = (lane < m) ? Z[i * 64 + lane] : 0.0;
         const double f = s * ei;
         const double b = c * ei;
-        r = sqrt(f * f + g * g);
-        Eg[(i + 1)] = r;
-        if (r == 0.0) {
-          Dg[(i + 1)] -= p;
+        const double h2 = f * f + g * g;
+        if (h2 == 0.0) {
+          Eg[(i + 1)] = 0.0;
+          Dg[(i + 1)] = dhi - p;
+          if (lane < m) Z[(i + 1) * 64 + lane] = zhi;
           Eg[mm] = 0.0;
           underflow = true;
           break;
         }
-        s = f / r;
-        c = g / r;
-        g = Dg[(i + 1)] - p;
-        r = (Dg[i] - g) * s + 2.0 * c * b;
+        const double inv = rsqrt_f64(h2);
+        Eg[(i + 1)] = h2 * inv;
+        s = f * inv;
+        c = g * inv;
+        g = dhi - p;
+        r = (di - g) * s + 2.0 * c * b;
         p = s * r;
         Dg[(i + 1)] = g + p;
         g = c * r - b;
-        if (lane < m) {
-          const double z0 = Z[i * 64 + lane];
-          const double z1 = Z[(i + 1) * 64 + lane];
-          Z[(i + 1) * 64 + lane] = s * z0 + c * z1;
-          Z[i * 64 + lane] = c * z0 - s * z1;
-        }
+        if (lane < m) Z[(i + 1) * 64 + lane] = s * zi + c * zhi;
+        zhi = c * zi - s * zhi;
+        dhi = di;
       }
       if (underflow) continue;
-      Dg[l] -= p;
+      if (lane < m) Z[l * 64 + lane] = zhi;
+      Dg[l] = dhi - p;
       Eg[l] = g;
       Eg[mm] = 0.0;
     }
