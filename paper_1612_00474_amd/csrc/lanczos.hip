@@ -13,6 +13,7 @@
 // Reductions use a fixed number of blocks and a fixed tree, so results are bitwise
 // reproducible.  The host reads a 32-byte status record once per iteration.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstddef>
 #include <vector>
@@ -163,16 +164,15 @@ __global__ __launch_bounds__(kThreads) void reorth_dots(int64_t m, const double 
   if (threadIdx.x == 0) part[int64_t(k) * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void reorth_finish(int nvec, int np,
-                                                          const double *__restrict__ part,
+// h[k] = sum of the np partials of V_k . u; one workgroup per basis vector k
+__global__ __launch_bounds__(kThreads) void reorth_finish(int np, const double *__restrict__ part,
                                                           double *__restrict__ h) {
   __shared__ double sh[kThreads];
-  for (int k = 0; k < nvec; ++k) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < np; i += kThreads) acc += part[int64_t(k) * np + i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) h[k] = s;
-  }
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[int64_t(k) * np + i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) h[k] = s;
 }
 
 __global__ void reorth_update(int64_t m, int nvec, const double *__restrict__ V,
@@ -224,11 +224,15 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   for (int l = 0; l < m && !failed; ++l) {
     int iter = 0;
     for (;;) {
-      int mm = l;
-      for (; mm < m - 1; ++mm) {
-        const double dd = fabs(Dg[mm]) + fabs(Dg[(mm + 1)]);
-        if (fabs(Eg[mm]) + dd == dd) break;
+      // smallest mm >= l whose e[mm] is negligible next to its diagonal neighbours (m - 1 if
+      // none): every lane tests one index and the wavefront takes the lowest hit
+      bool small = false;
+      if (lane >= l && lane < m - 1) {
+        const double dd = fabs(Dg[lane]) + fabs(Dg[lane + 1]);
+        small = fabs(Eg[lane]) + dd == dd;
       }
+      const unsigned long long hits = __ballot(small);
+      const int mm = hits ? __builtin_ctzll(hits) : m - 1;
       if (mm == l) break;
       if (++iter > 60) {
         failed = 1;
@@ -285,11 +289,14 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   }
   __syncthreads();
   // eigenvalues (identical in every lane) and the first eigenvector components (row 0)
-  double lmax = 0.0, lmin = 0.0;
-  for (int k = 0; k < m; ++k) {
-    const double lam = Dg[k];
-    lmax = k == 0 ? lam : fmax(lmax, lam);
-    lmin = k == 0 ? lam : fmin(lmin, lam);
+  // largest and smallest eigenvalue and largest |alpha|, reduced across the wavefront
+  double lmax = lane < m ? Dg[lane] : -DBL_MAX;
+  double lmin = lane < m ? Dg[lane] : DBL_MAX;
+  double amax = lane < m ? fabs(st->alpha[lane]) : 0.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    lmax = fmax(lmax, __shfl_xor(lmax, off));
+    lmin = fmin(lmin, __shfl_xor(lmin, off));
+    amax = fmax(amax, __shfl_xor(amax, off));
   }
   const double wn = st->wnorm;
   double yr = 0.0;
@@ -322,8 +329,6 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
     st->yprev[lane] = yr;
   }
   if (lane == 0) {
-    double amax = 0.0;
-    for (int k = 0; k < m; ++k) amax = fmax(amax, fabs(st->alpha[k]));
     const double eps = m >= 2 ? sqrt(num / den) : 0.0;
     int reason = 0;
     if (failed)
@@ -623,7 +628,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
       const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
       reorth_dots<<<grid, kThreads, 0, stream>>>(m3, V, u, part);
       RPB_LAUNCHED(ctx);
-      reorth_finish<<<1, kThreads, 0, stream>>>(k, kRedBlocks, part, ls->h);
+      reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
       RPB_LAUNCHED(ctx);
       reorth_update<<<nblk(m3), kThreads, 0, stream>>>(m3, k, V, ls->h, u);
       RPB_LAUNCHED(ctx);
