@@ -288,7 +288,6 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
     }
   }
   __syncthreads();
-  // eigenvalues (identical in every lane) and the first eigenvector components (row 0)
   // largest and smallest eigenvalue and largest |alpha|, reduced across the wavefront
   double lmax = lane < m ? Dg[lane] : -DBL_MAX;
   double lmin = lane < m ? Dg[lane] : DBL_MAX;
@@ -298,6 +297,8 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
     lmin = fmin(lmin, __shfl_xor(lmin, off));
     amax = fmax(amax, __shfl_xor(amax, off));
   }
+  // y_m = |w| Q L^{1/2} Q^T e_1: lane r forms row r from the eigenvalues (identical in every
+  // lane) and the first row of the eigenvector matrix
   const double wn = st->wnorm;
   double yr = 0.0;
   if (lane < m) {
