@@ -16,7 +16,11 @@ u^n is returned so the caller can keep it for the next step.
 Pinned by (tests/test_oracle_integrator.py): with kT = 0 SAB is the
 two-step Adams-Bashforth method (second-order convergence on a deterministic
 two-sphere trajectory against a tight ODE solve) and EM is forward Euler
-(first order).
+(first order).  At kT > 0, for one sphere above the wall with no force: the noise
+term alone equals sqrt(2 kT dt) (6 pi eta a)^{-1/2} diag(sqrt mu_par, sqrt mu_par,
+sqrt mu_perp) W (the textbook wall self-mobilities), and the drift term alone,
+with W~ = z-hat, equals dt kT d/dz of the perpendicular self-mobility; both schemes
+give the same stochastic terms, and they add.
 """
 from __future__ import annotations
 
@@ -71,11 +75,3 @@ def step(pos, u_prev, w, w_tilde, *, dt, delta, lanczos_tol, lanczos_max_iter=64
     new = pos + dt * det + math.sqrt(2.0 * kT * dt) * g.reshape(n, 3) + dt * drift
     return new, u, iters, eps, status
 
-
-def combine(pos, u, u_prev, g, drift, *, dt, kT=1.0, scheme="sab"):
-    """The update formula alone (eq. EM / eq. AB), given its ingredients."""
-    if scheme == "em" or u_prev is None:
-        det = u
-    else:
-        det = 1.5 * u - 0.5 * u_prev
-    return pos + dt * det + math.sqrt(2.0 * kT * dt) * g + dt * drift

@@ -29,7 +29,10 @@ depends on the positions modulo the box only.
 Pinned by (tests/test_oracle_mobility.py): symmetry and positive definiteness of
 dense M (eigvalsh), zero rows for spheres at or below the wall, the textbook wall
 self-mobility series, the 1/r^3 decay of the screened pair interaction for
-r >> h (Sec. II.C), quadrature of the integral definition.
+r >> h (Sec. II.C), quadrature of the integral definition.  The box option: invariance
+under whole-box moves and common shifts, O(L^-3) decay of the image terms, and equality
+with the unbounded mobility of the system copied into the 3 x 3 cells around the unit
+cell, each source's nine copies summed (App. B's image set).
 """
 from __future__ import annotations
 

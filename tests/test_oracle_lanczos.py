@@ -105,3 +105,25 @@ def test_block_diagonal_scale_follows_the_wall_self_mobility():
         series = sum(c * (1.0 / h) ** o for o, c in coef[dn].items())
         assert abs(L[k] ** 2 * 6 * np.pi - series) <= 2.0 / h ** 4
     assert np.all(L[3:] == 1.0)
+
+
+def _not_spd_fixture():
+    rows = golden_rows("periodic_not_spd.txt")
+    box = tuple(float(x) for x in rows[0][1:])
+    m = int(rows[1][1])
+    pos = np.array([[float(x) for x in r[1:]] for r in rows if r[0] == "pos"])
+    w = np.array([[float(x) for x in r[1:]] for r in rows if r[0] == "w"]).ravel()
+    return box, m, pos, w
+
+
+def test_periodic_not_spd_fixture():
+    # App. B: the truncated image sum keeps M symmetric but not always positive definite; the
+    # stored crowded configuration has a negative eigenvalue, and Lanczos reports it as soon as
+    # a Ritz value falls below -1e-12 times the largest
+    box, m, pos, w = _not_spd_fixture()
+    M, _ = mobility.dense(pos, box=box)
+    assert np.abs(M - M.T).max() <= 1e-15 * np.abs(M).max()
+    lam = np.linalg.eigvalsh(M)
+    assert lam[0] < -1e-3 * lam[-1]
+    g, mo, eps, status = lanczos.lanczos_sqrt(lambda v: M @ v, w, 1e-300, 64)
+    assert status == "notspd" and mo == m

@@ -249,3 +249,27 @@ def test_periodic_forces_use_the_minimum_image():
     fn = forces.forces(near, 1.0, 1.0, 0.1, -1.0)
     assert np.allclose(fp, fn, rtol=1e-14, atol=1e-14)
     assert np.abs(fp[:, 0]).max() > 1.0        # they do repel
+
+
+def test_periodic_image_set_is_the_nine_cell_replica():
+    # App. B: a pair's hydrodynamic block is the sum over the source's minimum image and its
+    # images in the eight neighbour cells (a sphere also feels its own eight images).  Built
+    # here without the box option: copy every sphere into the 3 x 3 cells around the unit cell,
+    # assemble the unbounded (wall) mobility of the 9N spheres, and sum each original target's
+    # column blocks over the nine copies of each source.  The spheres sit in a corner of side
+    # below L/2, so every pair's minimum image is the pair itself.
+    box = (12.0, 10.0)
+    rng = np.random.default_rng(23)
+    n = 5
+    pos = np.column_stack([rng.uniform(0, 5.0, n), rng.uniform(0, 4.5, n),
+                           rng.uniform(1.05, 2.5, n)])
+    pos[1, :2] = pos[0, :2] + [1.1, 0.7]       # an overlapping pair
+    pos[2, 2] = 0.7                            # a sphere below z = a
+    M, MC = mobility.dense(pos, box=box)
+    cells = [(kx, ky) for kx in (-1, 0, 1) for ky in (-1, 0, 1)]
+    reps = np.concatenate([pos + np.array([kx * box[0], ky * box[1], 0.0]) for kx, ky in cells])
+    Mr, MCr = mobility.dense(reps)
+    home = cells.index((0, 0))
+    for big, small in ((Mr, M), (MCr, MC)):
+        ref = big.reshape(9, n, 3, 9, n, 3)[home].sum(axis=2).reshape(3 * n, 3 * n)
+        assert np.abs(small - ref).max() <= 1e-14 * np.abs(ref).max()
