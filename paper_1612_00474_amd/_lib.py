@@ -261,8 +261,10 @@ class Context:
         return out
 
     def lanczos(self, pos, w, tol, max_iter=64, precision="fp64", out=None, allow_noconv=False,
-                precond=False):
-        """Returns (g, iterations, eps, status); precond: block-diagonal preconditioned form."""
+                precond=False, allow_notspd=False):
+        """Returns (g, iterations, eps, status); precond: block-diagonal preconditioned form.
+        allow_noconv / allow_notspd: return RPB_ENOCONV / RPB_ENOTSPD (with the last iterate)
+        instead of raising."""
         import torch
         pos = _vec3(pos, "pos")
         n = pos.shape[0]
@@ -275,7 +277,9 @@ class Context:
         fn = self.lib.lanczos_sqrt_apply_precond if precond else self.lib.lanczos_sqrt_apply
         st = fn(self.h, C.byref(p), n, _ptr(pos), _ptr(w), float(tol), int(max_iter), _ptr(out),
                 C.byref(it), C.byref(eps), _stream())
-        self._check(st, (RPB_OK, RPB_ENOCONV) if allow_noconv else (RPB_OK,))
+        ok = (RPB_OK,) + ((RPB_ENOCONV,) if allow_noconv else ()) + (
+            (RPB_ENOTSPD,) if allow_notspd else ())
+        self._check(st, ok)
         return out, it.value, eps.value, st
 
     def rfd(self, pos, w_tilde, delta, precision="fp64", rfd_precision="fp64", out=None,

@@ -85,6 +85,9 @@ __global__ void normals_kernel_devstep(int64_t count, uint64_t seed, uint64_t st
 __global__ void shifted_pair(int64_t m, const double *__restrict__ q, const double *__restrict__ w,
                              double sp, double sm, double *__restrict__ qp,
                              double *__restrict__ qm) {
+  // q +- s w with the product rounded before the sum (no fused multiply-add): the positions
+  // then carry the rounding of the difference as it is written, which the drift divides by delta
+#pragma clang fp contract(off)
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= m) return;
   qp[i] = q[i] + sp * w[i];

@@ -35,3 +35,23 @@ def awkward_config(n=40, seed=5):
     pos[3, 2], pos[4, 2] = 0.5, 0.8     # identical after clamping to z = a
     pos[5] = pos[6] + np.array([0.3, 0.0, 0.0])
     return pos
+
+
+ELEMENT_FACTOR = 10.0
+
+
+def close(got, ref, tol, factor=ELEMENT_FACTOR):
+    """Relative 2-norm error within tol AND every element within factor * tol of the largest
+    reference magnitude (so that a few bad elements cannot hide inside the norm)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = float(np.abs(ref).max()) if ref.size else 0.0
+    emax = float(np.abs(got - ref).max()) if ref.size else 0.0
+    return rel2(got, ref) <= tol and emax <= factor * tol * scale
+
+
+def max_element(got, ref):
+    """Largest element error relative to the largest reference magnitude."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(got - ref).max() / np.abs(ref).max())

@@ -6,7 +6,7 @@ import pytest
 
 from oracle import mobility
 from paper_1612_00474_amd import workloads as wl
-from tests.gpu_util import awkward_config, dev, host, rel2, require_gpu
+from tests.gpu_util import max_element, close, awkward_config, dev, host, rel2, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +38,7 @@ def test_sheet256_parity(ctx, c1, c1_ref, precision, tol):
     u = host(ctx.matvec(dev(c1["pos"]), dev(c1["force"]), dev(c1["torque"]), precision))
     err = rel2(u, c1_ref)
     print(f"sheet256 {precision}: rel2 = {err:.3e}")
-    assert err <= tol
+    assert err <= tol and max_element(u, c1_ref) <= 10 * tol
     assert np.abs(u - c1_ref).max() <= 10 * tol * np.abs(c1_ref).max()
 
 
@@ -54,7 +54,7 @@ def test_coherent_forcing(ctx, precision, tol):
     u = host(ctx.matvec(dev(pos), dev(F), dev(T), precision))[rows]
     err = rel2(u, ref)
     print(f"coherent {precision}: rel2 = {err:.3e}")
-    assert err <= tol
+    assert err <= tol and max_element(u, ref) <= 10 * tol
 
 
 @pytest.mark.parametrize("n", [1, 2, 7, 255, 256, 257, 300])
@@ -66,9 +66,9 @@ def test_ragged_sizes_fp64(ctx, n):
     T = rng.standard_normal((n, 3))
     ref = mobility.dense_matvec(pos, F, T)
     u = host(ctx.matvec(dev(pos), dev(F), dev(T), "fp64"))
-    assert rel2(u, ref) <= FP64_TOL
+    assert close(u, ref, FP64_TOL)
     um = host(ctx.matvec(dev(pos), dev(F), dev(T), "mixed"))
-    assert rel2(um, ref) <= MIXED_TOL
+    assert close(um, ref, MIXED_TOL)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
@@ -79,7 +79,7 @@ def test_wall_overlaps_and_coincident_spheres(ctx, precision, tol):
     T = rng.standard_normal(pos.shape)
     ref = mobility.dense_matvec(pos, F, T)
     u = host(ctx.matvec(dev(pos), dev(F), dev(T), precision))
-    assert rel2(u, ref) <= tol
+    assert close(u, ref, tol)
     # spheres on / below the wall do not move (App. A)
     assert np.all(u[1] == 0.0) and np.all(u[2] == 0.0)
 
@@ -88,9 +88,9 @@ def test_force_only_and_torque_only(ctx, c1, c1_ref):
     pos = dev(c1["pos"])
     uf = host(ctx.matvec(pos, dev(c1["force"]), None, "fp64"))
     ut = host(ctx.matvec(pos, None, dev(c1["torque"]), "fp64"))
-    assert rel2(uf, mobility.dense_matvec(c1["pos"], c1["force"], None)) <= FP64_TOL
-    assert rel2(ut, mobility.dense_matvec(c1["pos"], None, c1["torque"])) <= FP64_TOL
-    assert rel2(uf + ut, c1_ref) <= FP64_TOL
+    assert close(uf, mobility.dense_matvec(c1["pos"], c1["force"], None), FP64_TOL)
+    assert close(ut, mobility.dense_matvec(c1["pos"], None, c1["torque"]), FP64_TOL)
+    assert close(uf + ut, c1_ref, FP64_TOL)
 
 
 def test_row_shards_concatenate_bitwise(ctx):
@@ -111,7 +111,7 @@ def test_row_shards_concatenate_bitwise(ctx):
         assert np.array_equal(np.vstack(parts), full)
         c.set_tuning(precision, symmetric=1)
         sym = host(c.matvec(P, F, T, precision))
-        assert rel2(sym, full) <= (1e-13 if precision == "fp64" else 2e-6)
+        assert close(sym, full, (1e-13 if precision == "fp64" else 2e-6))
     c.close()
 
 
@@ -123,20 +123,29 @@ def test_deterministic(ctx, c1):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,nrows", [("sheet16k_fp64", 48), ("sheet64k_mixed", 24),
-                                        ("sheet256k_mixed", 6)])
+@pytest.mark.parametrize("name,nrows", [("sheet16k_fp64", 64), ("sheet64k_mixed", 256),
+                                        ("sheet256k_mixed", 1024)])
 def test_full_size_row_sampled(ctx, name, nrows):
+    # the 16,384-sphere sheet against the oracle computed here; the two larger sheets against
+    # the oracle's values stored by tests/golden/make_sheet_rows.py (256 and 1,024 rows)
+    from tests.conftest import golden_sheet_rows
     w = wl.WORKLOADS[name]
     inp = wl.make_inputs(w, 0)
-    rows = np.random.default_rng(9).choice(w.n, nrows, replace=False)
-    rows[0] = w.n - 1                          # the last sphere (ragged last tile)
-    ref = mobility.matvec(inp["pos"], inp["force"], inp["torque"], rows=rows)
+    if name == "sheet16k_fp64":
+        rows = np.random.default_rng(9).choice(w.n, nrows, replace=False)
+        rows[0] = w.n - 1                      # the last sphere (ragged last tile)
+        ref = mobility.matvec(inp["pos"], inp["force"], inp["torque"], rows=rows)
+    else:
+        fname = {"sheet64k_mixed": "sheet64k_rows.txt", "sheet256k_mixed": "sheet256k_rows.txt"}
+        rows, ref = golden_sheet_rows(fname[name], inp)["u"]
+        assert len(rows) == nrows and rows[0] == w.n - 1
     P, F, T = dev(inp["pos"]), dev(inp["force"]), dev(inp["torque"])
     for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
         u = host(ctx.matvec(P, F, T, precision))[rows]
         err = rel2(u, ref)
-        print(f"{name} {precision}: rel2 = {err:.3e} over {nrows} sampled rows")
-        assert err <= tol
+        emax = max_element(u, ref)
+        print(f"{name} {precision}: rel2 = {err:.3e}, max element {emax:.3e} over {nrows} rows")
+        assert err <= tol and emax <= 10 * tol
 
 
 def test_error_paths(ctx, c1):
@@ -184,11 +193,11 @@ def test_symmetric_kernel_matches_oracle_and_ordered(ctx, n, tpt, torque):
     for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
         c.set_tuning(precision, tpt=tpt, symmetric=1)
         us = host(c.matvec(P, Fd, Td, precision))
-        assert rel2(us, ref) <= tol, (precision, n, tpt)
+        assert close(us, ref, tol), (precision, n, tpt)
         assert np.array_equal(us, host(c.matvec(P, Fd, Td, precision)))     # reproducible
         c.set_tuning(precision, symmetric=0)
         uo = host(c.matvec(P, Fd, Td, precision))
-        assert rel2(us, uo) <= (1e-13 if precision == "fp64" else 2e-6)
+        assert close(us, uo, (1e-13 if precision == "fp64" else 2e-6))
     c.close()
 
 

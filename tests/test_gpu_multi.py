@@ -8,7 +8,7 @@ import pytest
 
 from oracle import lanczos, mobility
 from paper_1612_00474_amd import workloads as wl
-from tests.gpu_util import dev, host, rel2, require_gpu
+from tests.gpu_util import max_element, close, dev, host, rel2, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +47,10 @@ def test_multi_matches_oracle_per_vector(ctx, n, nvec, wall):
     for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
         u = host(c.matvec_multi(P, Fd, precision))
         for v in range(nvec):
-            assert rel2(u[v], ref[v]) <= tol, (precision, n, v)
+            assert close(u[v], ref[v], tol), (precision, n, v)
         # agrees with the single-vector product to rounding
         one = np.stack([host(c.matvec(P, dev(F[v]), None, precision)) for v in range(nvec)])
-        assert rel2(u, one) <= (1e-13 if precision == "fp64" else 2e-6)
+        assert close(u, one, (1e-13 if precision == "fp64" else 2e-6))
         assert np.array_equal(u, host(c.matvec_multi(P, Fd, precision)))   # reproducible
     if not wall:
         c.close()
@@ -66,7 +66,7 @@ def test_multi_overlaps_and_self_pairs(ctx):
     M, _ = mobility.dense(pos)
     u = host(ctx.matvec_multi(dev(pos), dev(F), "fp64"))
     for v in range(3):
-        assert rel2(u[v], (M @ F[v].ravel()).reshape(n, 3)) <= FP64_TOL
+        assert close(u[v], (M @ F[v].ravel()).reshape(n, 3), FP64_TOL)
 
 
 def test_multi_full_size_row_sampled(ctx):
@@ -84,7 +84,7 @@ def test_multi_full_size_row_sampled(ctx):
             ref = mobility.matvec(inp["pos"], F[v], None, rows=rows)
             err = rel2(u[v][rows], ref)
             print(f"multi N=65536 {precision} vector {v}: rel2 = {err:.3e} over 12 rows")
-            assert err <= tol
+            assert err <= tol and max_element(u[v][rows], ref) <= 10 * tol
 
 
 def test_multi_error_paths(ctx):
@@ -139,7 +139,7 @@ def test_lanczos_multi_fixed_iterations(ctx, c1, m):
     for v in range(6):
         ref, mref, _, _ = lanczos.lanczos_sqrt(lambda x: M @ x, W[v].ravel(), 1e-300, max_iter=m)
         assert it[v] == m == mref
-        assert rel2(g[v].ravel(), ref) <= 1e-12
+        assert close(g[v].ravel(), ref, 1e-12)
 
 
 def test_lanczos_multi_tolerance_per_vector(ctx, c1):
@@ -160,7 +160,7 @@ def test_lanczos_multi_tolerance_per_vector(ctx, c1):
             _, mref, eps_ref, _ = lanczos.lanczos_sqrt(lambda x: M @ x, W[v].ravel(), 1e-6)
             err = rel2(g[v].ravel(), root @ W[v].ravel())
             print(f"lanczos multi {precision} v{v}: m = {it[v]} (oracle {mref}), err {err:.2e}")
-            assert err <= 1e-5
+            assert err <= 1e-5 and max_element(g[v].ravel(), root @ W[v].ravel()) <= 10 * 1e-5
             if precision == "fp64":
                 assert it[v] == mref and abs(eps[v] - eps_ref) <= 1e-9 * max(eps_ref, 1e-30)
         # each vector's result as the single-vector solve
@@ -169,4 +169,4 @@ def test_lanczos_multi_tolerance_per_vector(ctx, c1):
             for v in range(5):
                 one, m1, _, _ = ctx.lanczos(P, dev(W[v]), 1e-6)
                 assert m1 == it[v]
-                assert rel2(g[v], host(one)) <= 1e-12
+                assert close(g[v], host(one), 1e-12)

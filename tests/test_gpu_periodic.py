@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import forces, integrator, mobility
-from tests.gpu_util import dev, host, rel2, require_gpu
+from tests.gpu_util import max_element, close, dev, host, rel2, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -47,14 +47,14 @@ def test_periodic_product_matches_oracle(ctx, n, sym):
             ctx.set_tuning(precision, symmetric=sym)
             u = host(ctx.matvec(dev(pos), dev(F), None if torque is None else dev(torque),
                                 precision))
-            assert rel2(u, ref) <= tol, (n, sym, precision, torque is None)
+            assert close(u, ref, tol), (n, sym, precision, torque is None)
 
 
 def test_periodic_forces_match_oracle(ctx):
     pos = _boxed(300, 9)
     ref = forces.forces(pos, 1.0, 1.0, 0.1, -1.0, box=BOX)
     f = host(ctx.forces(dev(pos), -1.0, 1.0, 0.1))
-    assert rel2(f, ref) <= 1e-12
+    assert close(f, ref, 1e-12)
 
 
 def test_periodic_step_matches_oracle(ctx):
@@ -70,8 +70,8 @@ def test_periodic_step_matches_oracle(ctx):
                                       lanczos_tol=1e-300, lanczos_max_iter=6, u0=1.0, b=0.1,
                                       box=BOX)
     assert it == m == 6
-    assert rel2(host(state.pos) - pos, new - pos) <= 1e-10
-    assert rel2(host(state.u_prev), u) <= 1e-12
+    assert close(host(state.pos) - pos, new - pos, 1e-10)
+    assert close(host(state.u_prev), u, 1e-12)
 
 
 def test_periodic_rejections(ctx):
@@ -101,7 +101,7 @@ def test_periodic_forces_small_box(ctx):
                                rng.uniform(1.05, 2.5, 40)])
         ref = forces.forces(pos, 1.0, 1.0, 0.1, -1.0, box=small_box)
         f = host(c.forces(dev(pos), -1.0, 1.0, 0.1))
-        assert rel2(f, ref) <= 1e-12
+        assert close(f, ref, 1e-12)
     finally:
         c.close()
 
@@ -134,7 +134,7 @@ def test_periodic_product_several_tiles():
                     u = host(c.matvec(dev(pos), dev(F), None if torque is None else dev(torque),
                                       precision))[rows]
                     err = rel2(u, ref)
-                    assert err <= tol, (tpt, sym, precision, torque is None, err)
+                    assert err <= tol and max_element(u, ref) <= 10 * tol, (tpt, sym, precision, torque is None, err)
     finally:
         c.close()
 
@@ -158,6 +158,6 @@ def test_periodic_full_size_row_sampled():
             c.autotune(P, None, precision)
             err = rel2(host(c.matvec(P, F, None, precision))[rows], ref)
             print(f"periodic sheet64k {precision}: rel2 = {err:.3e} over {len(rows)} rows")
-            assert err <= tol
+            assert err <= tol and max_element(host(c.matvec(P, F, None, precision))[rows], ref) <= 10 * tol
     finally:
         c.close()
