@@ -105,6 +105,26 @@ int rpb_mobility_matvec(rpb_ctx *ctx, const rpb_params *p, int64_t n, const doub
                         const double *force, const double *torque, double *vel_out,
                         rpb_stream_t stream);
 
+/* The same whole-system product for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc).  It calls no
+ * hipMalloc, hipFree or other allocating routine: every intermediate (packed geometry, packed
+ * sources, partial sums of the ordered pair kernel over source chunks) lives in a 32 MiB
+ * static device array that each GPU the library runs on holds until the process ends
+ * (resolved once per device by rpb_create).  It also never synchronises the stream and does
+ * not check the positions (a NaN or Inf position gives a non-finite velocity, not
+ * RPB_ENONFINITE); the opt-in output check and timing records do not apply.
+ * Limit: the packed geometry and sources plus one source chunk of partial sums must fit,
+ * about (32 + 48 + 24) n bytes in float64 and (28 + 24 + 24) n in mixed precision, so n up to
+ * about 322,000 (RPB_FP64) or 441,000 (RPB_MIXED); larger n returns RPB_EINVAL.  Below the limit the
+ * sources are split into as many chunks (workgroups) as the launch shape asks for and fit.
+ * The result agrees with rpb_mobility_matvec to rounding (another summation order).
+ * All calls on one GPU share its array, which keeps the last call's contents: calls that
+ * overlap in time on one GPU (several streams or host threads) race and must be serialised
+ * by the caller.  Arguments and other errors as for rpb_mobility_matvec. */
+int rpb_mobility_matvec_noalloc(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                                const double *force, const double *torque, double *vel_out,
+                                rpb_stream_t stream);
+
 /* Rows [row_begin, row_end) of the same product (all n spheres are sources).  vel_out
  * then holds (row_end - row_begin) rows: the per-GPU share of a row-sharded product.  Row
  * ranges take the ordered kernel (target tiles x source chunks, chunking fixed by n), so

@@ -30,6 +30,7 @@ EXPORTS = (
     "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
     "rpb_step_graph_destroy", "rpb_get_tuning", "rpb_set_tuning", "rpb_autotune",
     "rpb_mobility_matvec_multi", "lanczos_sqrt_apply_multi", "rpb_output_check_enable",
+    "rpb_mobility_matvec_noalloc",
 )
 
 
@@ -99,6 +100,7 @@ def load(path: str = LIB_PATH):
         "rpb_version": (C.c_char_p, []),
         "rpb_mobility_matvec": (C.c_int, [P, pp, I64, P, P, P, P, P]),
         "rpb_mobility_matvec_rows": (C.c_int, [P, pp, I64, P, P, P, I64, I64, P, P]),
+        "rpb_mobility_matvec_noalloc": (C.c_int, [P, pp, I64, P, P, P, P, P]),
         "lanczos_sqrt_apply": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, C.POINTER(C.c_int),
                                          C.POINTER(D), P]),
         "lanczos_sqrt_apply_precond": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P,
@@ -257,6 +259,25 @@ class Context:
             _vec3(out, "out", r1 - r0)
             st = self.lib.rpb_mobility_matvec_rows(self.h, C.byref(p), n, _ptr(pos), _ptr(force),
                                                    _ptr(torque), r0, r1, _ptr(out), _stream())
+        self._check(st)
+        return out
+
+    def matvec_noalloc(self, pos, force=None, torque=None, precision="fp64", out=None):
+        """U = M F + M_C T through the entry point that allocates nothing (its intermediates
+        live in the library's static per-device scratch array)."""
+        import torch
+        pos = _vec3(pos, "pos")
+        n = pos.shape[0]
+        if force is not None:
+            _vec3(force, "force", n)
+        if torque is not None:
+            _vec3(torque, "torque", n)
+        if out is None:
+            out = torch.empty_like(pos)
+        _vec3(out, "out", n)
+        p = self.params(precision)
+        st = self.lib.rpb_mobility_matvec_noalloc(self.h, C.byref(p), n, _ptr(pos), _ptr(force),
+                                                  _ptr(torque), _ptr(out), _stream())
         self._check(st)
         return out
 

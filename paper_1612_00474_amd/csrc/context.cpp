@@ -155,6 +155,11 @@ int rpb_create(int hip_device, rpb_ctx **out) {
     delete c;
     return RPB_ENOMEM;
   }
+  if (noalloc_setup(c, hip_device) != RPB_OK) {
+    (void)hipHostFree(c->host_pinned);
+    delete c;
+    return RPB_EDEVICE;
+  }
   *out = c;
   return RPB_OK;
 }

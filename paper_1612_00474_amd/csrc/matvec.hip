@@ -911,6 +911,22 @@ void with_variant(bool torque, int tpt, bool wall, bool periodic, Fn &&fn) {
 
 inline bool periodic(const rpb_params *p) { return p->lx > 0.0; }
 
+// H-weighted sources of packed geometry `g` into `buf` (6 n values of the pair precision).
+int pack_sources_into(rpb_ctx *ctx, const Packed &g, const double *force, const double *torque,
+                      void *buf, hipStream_t stream, const int *skip = nullptr) {
+  const int64_t n = g.n;
+  const bool f64 = g.precision == RPB_FP64;
+  const double *h = f64 ? geom_d(g).h : geom_f(g).h;
+  if (f64)
+    pack_vectors<double><<<blocks_for(n, 256), 256, 0, stream>>>(
+        n, h, force, torque, 1.0 / g.a, static_cast<double *>(buf), skip);
+  else
+    pack_vectors<float><<<blocks_for(n, 256), 256, 0, stream>>>(
+        n, h, force, torque, 1.0 / g.a, static_cast<float *>(buf), skip);
+  RPB_LAUNCHED(ctx);
+  return RPB_OK;
+}
+
 int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const double *torque,
                  void **src, hipStream_t stream, const int *skip = nullptr) {
   const int64_t n = g.n;
@@ -919,13 +935,59 @@ int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const doubl
   int st;
   *src = workspace(ctx, WS_SRC, size_t(6 * n) * esz, &st);
   if (!*src) return st;
+  return pack_sources_into(ctx, g, force, torque, *src, stream, skip);
+}
+
+// Source chunking of the ordered kernel: enough workgroups to fill the chip several times
+// over (target_wgs), at most max_chunks chunks, each a multiple of kBlock sources.  The
+// chunks depend on n only (not on the row range), so every target sums its sources in the
+// same order whichever rows are requested: row shards concatenate to the full product bitwise.
+inline int64_t ordered_chunk(int64_t n, int tpt, int target_wgs, int64_t max_chunks) {
+  const int64_t per_wg = int64_t(kBlock) * tpt;
+  const int64_t tiles_full = (n + per_wg - 1) / per_wg;
+  int64_t nchunks = std::max<int64_t>(1, (int64_t(target_wgs) + tiles_full - 1) / tiles_full);
+  nchunks = std::min(nchunks, std::max<int64_t>(1, max_chunks));
+  int64_t chunk = (n + nchunks - 1) / nchunks;
+  return std::max<int64_t>(kBlock, (chunk + kBlock - 1) / kBlock * kBlock);
+}
+
+// Ordered pair kernel over rows [row0, row0 + nrows) into `part` (nchunks x 3 x nrows
+// doubles), then the fixed-order reduction into vel.  `record` brackets the pair kernel with
+// the context's timing events.
+int ordered_product(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
+                    bool has_t, int tpt, int64_t chunk, int64_t row0, int64_t nrows,
+                    double *part, double *vel, hipStream_t stream, const int *skip, bool record) {
+  const int64_t n = g.n;
+  const bool f64 = g.precision == RPB_FP64;
+  const int64_t per_wg = int64_t(kBlock) * tpt;
+  const int64_t tiles = (nrows + per_wg - 1) / per_wg;
+  const int64_t nchunks = (n + chunk - 1) / chunk;
+  if (tiles > 0x7fffffff || nchunks > 65535)
+    return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
+  PairArgs args{n, row0, nrows, chunk, skip};
+  const dim3 grid{unsigned(tiles), unsigned(nchunks), 1u};
+  hipEvent_t t0 = nullptr;
+  if (record) RPB_TRY(timing_begin(ctx, stream, &t0));
+  with_variant(has_t, tpt, p->wall != 0, periodic(p), [&](auto T, auto P, auto W, auto B) {
+    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value, kB = decltype(B)::value;
+    constexpr int kP = decltype(P)::value;
+    if (f64)
+      pair_kernel_f64<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
+          args, geom_d(g), static_cast<const double *>(src),
+          make_pair_consts<double>(p->lx / p->a, p->ly / p->a), part);
+    else
+      pair_kernel_mixed<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
+          args, geom_f(g), static_cast<const float *>(src),
+          make_pair_consts<float>(p->lx / p->a, p->ly / p->a), part);
+  });
+  RPB_LAUNCHED(ctx);
+  if (record)
+    RPB_TRY(timing_end(ctx, stream, t0, double(nrows) * double(n),
+                       (f64 ? 0 : 2) + (has_t ? 1 : 0)));
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
-  if (f64)
-    pack_vectors<double><<<blocks_for(n, 256), 256, 0, stream>>>(
-        n, h, force, torque, 1.0 / g.a, static_cast<double *>(*src), skip);
-  else
-    pack_vectors<float><<<blocks_for(n, 256), 256, 0, stream>>>(
-        n, h, force, torque, 1.0 / g.a, static_cast<float *>(*src), skip);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
+  reduce_partials<<<blocks_for(nrows, 256), 256, 0, stream>>>(nrows, int(nchunks), part,
+                                                              h + row0, scale, vel, skip);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
@@ -1001,11 +1063,18 @@ int check_finite_end(rpb_ctx *ctx) {
   return RPB_OK;
 }
 
+size_t packed_geometry_bytes(int64_t n, int precision) { return geom_bytes(n, precision); }
+
 int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, Slot slot,
                   Packed *out, hipStream_t stream) {
   int st;
   void *buf = workspace(ctx, slot, geom_bytes(n, p->precision), &st);
   if (!buf) return st;
+  return pack_geometry_into(ctx, p, n, pos, buf, out, stream);
+}
+
+int pack_geometry_into(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                       void *buf, Packed *out, hipStream_t stream) {
   out->n = n;
   out->a = p->a;
   out->precision = p->precision;
@@ -1112,56 +1181,53 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   RPB_TRY(pack_sources(ctx, g, force, torque, &src, stream, skip));
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
 
-  // Source chunking: enough workgroups to fill the chip several times over.  The chunks
-  // depend on n only (not on the row range), so every target sums its sources in the same
-  // order whichever rows are requested: row shards concatenate to the full product bitwise.
   const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
   const int tpt = shape.tpt;
   if (row0 == 0 && nrows == n && shape.symmetric &&
       sym_partial_bytes(n, int64_t(kBlock) * tpt, sym_nsplit(n, int64_t(kBlock) * tpt)) <=
           kMaxSymPartialBytes)
     return matvec_symmetric(ctx, p, g, src, has_t, h, tpt, vel, stream, skip);
-  const int64_t per_wg = int64_t(kBlock) * tpt;
-  const int64_t tiles = (nrows + per_wg - 1) / per_wg;
-  const int64_t tiles_full = (n + per_wg - 1) / per_wg;
-  int64_t nchunks =
-      std::max<int64_t>(1, (int64_t(shape.target_wgs) + tiles_full - 1) / tiles_full);
-  int64_t chunk = (n + nchunks - 1) / nchunks;
-  chunk = std::max<int64_t>(kBlock, (chunk + kBlock - 1) / kBlock * kBlock);
-  nchunks = (n + chunk - 1) / chunk;
-  if (tiles > 0x7fffffff || nchunks > 65535)
-    return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
-
+  const int64_t chunk = ordered_chunk(n, tpt, shape.target_wgs, 65535);
+  const int64_t nchunks = (n + chunk - 1) / chunk;
   int st;
   double *part = static_cast<double *>(
       workspace(ctx, WS_PART, size_t(nchunks) * 3 * size_t(nrows) * sizeof(double), &st));
   if (!part) return st;
+  return ordered_product(ctx, p, g, src, has_t, tpt, chunk, row0, nrows, part, vel, stream, skip,
+                         true);
+}
 
-  PairArgs args{n, row0, nrows, chunk, skip};
-  const dim3 grid{unsigned(tiles), unsigned(nchunks), 1u};
-  hipEvent_t t0;
-  RPB_TRY(timing_begin(ctx, stream, &t0));
-  with_variant(has_t, tpt, p->wall != 0, periodic(p), [&](auto T, auto P, auto W, auto B) {
-    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value, kB = decltype(B)::value;
-    constexpr int kP = decltype(P)::value;
-    if (f64)
-      pair_kernel_f64<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
-          args, geom_d(g), static_cast<const double *>(src),
-          make_pair_consts<double>(p->lx / p->a, p->ly / p->a), part);
-    else
-      pair_kernel_mixed<kT, kP, kW, kB><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src),
-          make_pair_consts<float>(p->lx / p->a, p->ly / p->a), part);
-  });
-  RPB_LAUNCHED(ctx);
-  RPB_TRY(timing_end(ctx, stream, t0, double(nrows) * double(n),
-                     (f64 ? 0 : 2) + (has_t ? 1 : 0)));
+size_t noalloc_matvec_bytes(int64_t n, int precision, int64_t nchunks) {
+  const size_t esz = precision == RPB_FP64 ? sizeof(double) : sizeof(float);
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return up(geom_bytes(n, precision)) + up(size_t(6 * n) * esz) +
+         size_t(nchunks) * 3 * size_t(n) * sizeof(double);
+}
 
-  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
-  reduce_partials<<<blocks_for(nrows, 256), 256, 0, stream>>>(nrows, int(nchunks), part,
-                                                              h + row0, scale, vel, skip);
-  RPB_LAUNCHED(ctx);
-  return RPB_OK;
+int matvec_into(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                const double *force, const double *torque, double *vel, void *buf, size_t bytes,
+                hipStream_t stream) {
+  const int prec = p->precision;
+  const Shape &shape = ctx->tune.s[prec == RPB_FP64 ? RPB_FP64 : RPB_MIXED];
+  const size_t fixed = noalloc_matvec_bytes(n, prec, 0);
+  const size_t per_chunk = 3 * size_t(n) * sizeof(double);
+  if (fixed + per_chunk > bytes)
+    return fail(ctx, RPB_EINVAL,
+                "n = %lld needs %zu bytes of scratch with one source chunk; the scratch holds %zu",
+                (long long)n, fixed + per_chunk, bytes);
+  const int64_t chunk =
+      ordered_chunk(n, shape.tpt, shape.target_wgs, int64_t((bytes - fixed) / per_chunk));
+  char *base = static_cast<char *>(buf);
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  void *geom = base;
+  void *src = base + up(geom_bytes(n, prec));
+  double *part = reinterpret_cast<double *>(static_cast<char *>(src) +
+                                            up(size_t(6 * n) * (prec == RPB_FP64 ? 8 : 4)));
+  Packed g;
+  RPB_TRY(pack_geometry_into(ctx, p, n, pos, geom, &g, stream));
+  RPB_TRY(pack_sources_into(ctx, g, force, torque, src, stream));
+  return ordered_product(ctx, p, g, src, torque != nullptr, shape.tpt, chunk, 0, n, part, vel,
+                         stream, nullptr, false);
 }
 
 // ---- batched -----------------------------------------------------------------------------

@@ -174,6 +174,24 @@ struct Packed {
 int pack_geometry(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos, Slot slot,
                   Packed *out, hipStream_t stream);
 
+// The same packing into a caller-provided buffer of packed_geometry_bytes(n, precision).
+int pack_geometry_into(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                       void *buf, Packed *out, hipStream_t stream);
+size_t packed_geometry_bytes(int64_t n, int precision);
+
+// Whole-system U = M F + M_C T with every intermediate in the caller's device buffer `buf`
+// (`bytes` long): packed geometry, packed sources and the ordered kernel's partial sums, with
+// as many source chunks as fit (at most the tuned count).  No workspace, no position check, no
+// synchronisation and no timing record.  RPB_EINVAL when even one chunk does not fit;
+// noalloc_matvec_bytes(n, precision, c) is the size needed with c chunks.
+size_t noalloc_matvec_bytes(int64_t n, int precision, int64_t nchunks);
+int matvec_into(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
+                const double *force, const double *torque, double *vel, void *buf, size_t bytes,
+                hipStream_t stream);
+// Resolves the device address of the library's static scratch array on the current device
+// `device` (noalloc.hip); called once per device by rpb_create.
+int noalloc_setup(rpb_ctx *ctx, int device);
+
 // vel[r] for rows [row0, row0 + nrows) of U = M F + M_C T for packed geometry `g`.
 // force / torque are [n][3] float64 device arrays (nullable, not both).  `skip` (nullable)
 // is a device flag read by every kernel of the product when it runs: while it is nonzero
