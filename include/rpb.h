@@ -290,8 +290,8 @@ int sab_step_batched(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config *cf
  * (the symmetric tile-pair kernel, diagonal tiles as ordered pairs).  Forces only (no
  * torques), wall or free space, no pseudo-periodic box (RPB_EINVAL).  Each result agrees with
  * rpb_mobility_matvec on that vector to rounding (summation order differs).  The partial sums
- * take 3 n^2 / 8 bytes of device workspace per launch; beyond 32 GiB (n above about 300,000)
- * the call falls back to one single-vector product per vector. */
+ * of one launch are held to 512 MiB: larger systems walk the triangle of tile pairs in chunks,
+ * each followed by its reduction into vel, so the workspace stays bounded for any n. */
 int rpb_mobility_matvec_multi(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
                               int32_t nvec, const double *force, double *vel,
                               rpb_stream_t stream);
@@ -325,14 +325,17 @@ void rpb_step_graph_destroy(rpb_graph *g);
 /* Launch-shape tuning ---------------------------------------------------------------------
  *
  * One shape per precision.  Single-system products: tpt, targets per lane of the pair kernels
- * (1 or 2); target_wgs, workgroups the ordered kernel aims for when splitting the sources into
- * chunks; symmetric, whole-system products use the symmetric tile-pair kernel (M_ij = M_ji^T:
- * each unordered pair evaluated once, both directions applied; with torques both coupling
- * directions come from the shared geometry).  Row ranges (rpb_mobility_matvec_rows) always
- * take the ordered kernel, and so do systems whose symmetric partial sums would exceed 32 GiB
- * (3 n^2 / (256 tpt) doubles: above about 840,000 spheres at tpt = 2).  Batched products: batch_tpt (1 or 2); batch_symmetric, the
+ * (1, 2 or 4; 4 applies to the symmetric kernel, the ordered kernel then takes 2); target_wgs,
+ * workgroups the ordered kernel aims for when splitting the sources into chunks; symmetric,
+ * whole-system products use the symmetric tile-pair kernel (M_ij = M_ji^T: each unordered pair
+ * evaluated once, both directions applied; with torques both coupling directions come from the
+ * shared geometry).  The symmetric kernel's partial sums (float32 in mixed precision) are held to
+ * 512 MiB per launch: larger systems walk the triangle of tile pairs in several launches, so any n
+ * takes it.  Row ranges (rpb_mobility_matvec_rows) always take the ordered kernel.  Batched
+ * products: batch_tpt (1 or 2); batch_symmetric, the
  * persistent kernel works on (system, tile pair) items of the symmetric kernel instead of
- * (system, target tile, source chunk) items; batch_chunk, sources per ordered work item
+ * (system, target tile, source chunk) items (a batch whose symmetric partials would exceed 4 GiB
+ * takes the ordered items); batch_chunk, sources per ordered work item
  * (multiple of 256); batch_wgs, persistent workgroups.  rpb_autotune times the candidates for
  * p->precision on the given configuration (force-only products, `reps` launches each, HIP
  * events on `stream`); nsys = 1 tunes the single-system fields, nsys > 1 the batched ones.

@@ -143,13 +143,18 @@ int rpb_create(int hip_device, rpb_ctx **out) {
       }
     };
     Shape &sh = c->tune.s[q];
-    env("TPT", 1, 2, 1, &sh.tpt);
+    env("TPT", 1, 4, 1, &sh.tpt);
+    if (sh.tpt == 3) sh.tpt = 2;
     env("WGS", 1, 1 << 20, 1, &sh.target_wgs);
     env("CHUNK", 256, 1 << 20, 256, &sh.batch_chunk);
     env("BWGS", 1, 1 << 20, 1, &sh.batch_wgs);
     env("SYM", 0, 1, 1, &sh.symmetric);
     env("BTPT", 1, 2, 1, &sh.batch_tpt);
     env("BSYM", 0, 1, 1, &sh.batch_symmetric);
+  }
+  if (const char *v = getenv("RPB_CHUNK_KIB")) {   // partial-sum chunk limit, for experiments
+    const long long kib = atoll(v);
+    if (kib >= 1 && kib <= (1ll << 30)) c->chunk_bytes = size_t(kib) << 10;
   }
   if (hipHostMalloc(&c->host_pinned, kHostScratchBytes, hipHostMallocDefault) != hipSuccess) {
     delete c;

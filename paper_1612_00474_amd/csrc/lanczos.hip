@@ -204,24 +204,28 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 
 // Eigendecomposition of T_m by implicit QL with Wilkinson-type shifts (Bowdler, Martin,
 // Reinsch, Wilkinson 1968), then y_m = |w| Q L^{1/2} Q^T e_1, eps_m and the stop test.
-// One wavefront: lane k owns row k of the eigenvector matrix Z.  Every lane runs the same
-// scalar recurrence and stores the same values into the single LDS copy of (d, e); a
-// wavefront's LDS accesses complete in program order, so no barrier is needed until the
-// end, and the column rotations of Z touch only the lane's own row.
+// The first wavefront of the workgroup does the work: lane k owns row k of the eigenvector
+// matrix Z.  Every lane runs the same scalar recurrence and stores the same values into the
+// single LDS copy of (d, e); a wavefront's LDS accesses complete in program order, so no
+// barrier is needed until the end, and the column rotations of Z touch only the lane's own
+// row.  Every thread of the workgroup must call this (the other wavefronts only pass the
+// barriers).
 __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   __shared__ double Z[kMaxKrylov * 64];   // Z[col * 64 + row]
   __shared__ double Dg[kMaxKrylov];       // diagonal, becomes the eigenvalues
   __shared__ double Eg[kMaxKrylov];       // subdiagonal e[i] couples i and i + 1
   __shared__ double red[64];
   const int lane = threadIdx.x;
-  for (int c = 0; c < m; ++c) Z[c * 64 + lane] = (c == lane) ? 1.0 : 0.0;
+  const bool w0 = lane < 64;
+  if (w0)
+    for (int c = 0; c < m; ++c) Z[c * 64 + lane] = (c == lane) ? 1.0 : 0.0;
   if (lane < m) {
     Dg[lane] = st->alpha[lane];
     Eg[lane] = (lane < m - 1) ? st->beta[lane] : 0.0;
   }
   __syncthreads();
   int failed = 0;
-  for (int l = 0; l < m && !failed; ++l) {
+  for (int l = 0; l < m && !failed && w0; ++l) {
     int iter = 0;
     for (;;) {
       // smallest mm >= l whose e[mm] is negligible next to its diagonal neighbours (m - 1 if
@@ -288,14 +292,14 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
     }
   }
   __syncthreads();
-  // largest and smallest eigenvalue and largest |alpha|, reduced across the wavefront
+  // largest and smallest eigenvalue and largest |alpha|, reduced across the first wavefront
   double lmax = lane < m ? Dg[lane] : -DBL_MAX;
   double lmin = lane < m ? Dg[lane] : DBL_MAX;
   double amax = lane < m ? fabs(st->alpha[lane]) : 0.0;
   for (int off = 32; off > 0; off >>= 1) {
-    lmax = fmax(lmax, __shfl_xor(lmax, off));
-    lmin = fmin(lmin, __shfl_xor(lmin, off));
-    amax = fmax(amax, __shfl_xor(amax, off));
+    lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
+    lmin = fmin(lmin, __shfl_xor(lmin, off, 64));
+    amax = fmax(amax, __shfl_xor(amax, off, 64));
   }
   // y_m = |w| Q L^{1/2} Q^T e_1: lane r forms row r from the eigenvalues (identical in every
   // lane) and the first row of the eigenvector matrix
@@ -309,7 +313,7 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   // eps_m in the orthonormal Krylov basis
   const double yp = (lane < m - 1) ? st->yprev[lane] : 0.0;
   const double diff = (lane < m) ? (yr - yp) : 0.0;
-  red[lane] = diff * diff;
+  if (w0) red[lane] = diff * diff;
   __syncthreads();
   for (int s = 32; s > 0; s >>= 1) {
     if (lane < s) red[lane] += red[lane + s];
@@ -317,7 +321,7 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   }
   const double num = red[0];
   __syncthreads();
-  red[lane] = yp * yp;
+  if (w0) red[lane] = yp * yp;
   __syncthreads();
   for (int s = 32; s > 0; s >>= 1) {
     if (lane < s) red[lane] += red[lane + s];
@@ -368,6 +372,82 @@ __global__ void lz_reset(LzState *st) {
     st->m = 0;
     st->reason = 0;
   }
+}
+
+// Longest segment (3 n values of one system) that one workgroup takes through a whole Lanczos
+// iteration (lanczos_step_body); longer segments use the multi-workgroup reductions.
+constexpr int64_t kFusedSegment = 3 * 8192;
+
+// The vector work and the eigensolve of Lanczos iteration k for the segment [e0, e1) of the
+// vectors, by one workgroup, after the product u = M v_k: alpha_k = v_k . u; u -= alpha_k v_k +
+// beta_{k-1} v_{k-1}; the full re-orthogonalisation u -= V_k (V_k^T u); beta_k = |u|; the
+// eigensolve of T_k with its stop test (tridiag_body); and, unless the process stopped,
+// v_{k+1} = u / beta_k (when write_next).  The steps and their order are those of the separate
+// kernels; the sums are taken over the workgroup instead of in two stages, so small systems
+// need one launch per iteration instead of about ten.
+__device__ void lanczos_step_body(LzState *__restrict__ st, double *__restrict__ V,
+                                  double *__restrict__ u, int64_t m3, int64_t e0, int64_t e1,
+                                  int k, double tol, bool write_next) {
+  __shared__ double sh[kThreads];
+  __shared__ double hs[kMaxKrylov];
+  const int t = threadIdx.x;
+  const double *vk = V + int64_t(k - 1) * m3;
+  const double *vp = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
+  double acc = 0.0;
+  for (int64_t i = e0 + t; i < e1; i += kThreads) acc += vk[i] * u[i];
+  const double alpha = block_sum(acc, sh);
+  const double bprev = k > 1 ? st->beta[k - 2] : 0.0;
+  for (int64_t i = e0 + t; i < e1; i += kThreads) {
+    double x = u[i] - alpha * vk[i];
+    if (vp) x -= bprev * vp[i];
+    u[i] = x;   // each thread reads back only its own elements below
+  }
+  // h_j = V_j . u for j < k, eight basis vectors per pass
+  for (int j0 = 0; j0 < k; j0 += 8) {
+    const int nj = min(8, k - j0);
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = e0 + t; i < e1; i += kThreads) {
+      const double ui = u[i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nj) a[q] += V[int64_t(j0 + q) * m3 + i] * ui;
+    }
+    for (int q = 0; q < nj; ++q) {
+      const double r = block_sum(a[q], sh);
+      if (t == 0) hs[j0 + q] = r;
+    }
+  }
+  __syncthreads();
+  for (int64_t i = e0 + t; i < e1; i += kThreads) {
+    double proj = 0.0;
+    for (int j = 0; j < k; ++j) proj += hs[j] * V[int64_t(j) * m3 + i];
+    u[i] -= proj;
+  }
+  acc = 0.0;
+  for (int64_t i = e0 + t; i < e1; i += kThreads) acc += u[i] * u[i];
+  const double beta = sqrt(block_sum(acc, sh));
+  if (t == 0) {
+    st->alpha[k - 1] = alpha;
+    st->beta[k - 1] = beta;
+  }
+  if (t < k) st->h[t] = hs[t];
+  __syncthreads();
+  tridiag_body(k, tol, st);
+  __syncthreads();
+  if (write_next && st->reason == 0) {
+    double *next = V + int64_t(k) * m3;
+    for (int64_t i = e0 + t; i < e1; i += kThreads) next[i] = beta > 0.0 ? u[i] / beta : 0.0;
+  }
+}
+
+// Single system, the whole vector (3 n <= kFusedSegment).  A process that has stopped keeps its
+// state: an iteration enqueued after the stop returns at once.
+__global__ __launch_bounds__(kThreads) void lanczos_step(LzState *__restrict__ st,
+                                                         double *__restrict__ V,
+                                                         double *__restrict__ u, int64_t m3, int k,
+                                                         double tol, int write_next) {
+  if (st->reason != 0) return;
+  lanczos_step_body(st, V, u, m3, 0, m3, k, tol, write_next != 0);
 }
 
 // ---- batched Lanczos: one Krylov process per system, segments of the concatenated vectors ----
@@ -478,6 +558,17 @@ __global__ __launch_bounds__(64) void tridiag_sqrt_batched(SegView v, int m, dou
   if (v.done[s]) return;
   tridiag_body(m, tol, v.st + s);
   if (threadIdx.x == 0 && v.st[s].reason != 0) v.done[s] = 1;
+}
+
+// lanczos_step_body for every live system, one workgroup each (segments <= kFusedSegment).
+__global__ __launch_bounds__(kThreads) void seg_lanczos_step(SegView v, double *__restrict__ V,
+                                                             double *__restrict__ u, int64_t m3,
+                                                             int k, double tol, int write_next) {
+  const int s = blockIdx.x;
+  if (v.done[s]) return;
+  LzState *st = v.st + s;
+  lanczos_step_body(st, V, u, m3, 3 * v.offs[s], 3 * v.offs[s + 1], k, tol, write_next != 0);
+  if (threadIdx.x == 0 && st->reason != 0) v.done[s] = 1;
 }
 
 // out = V_m y_m per system (m = the system's own iteration count)
@@ -621,26 +712,31 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
     } else {
       RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream, stopped));
     }
-    RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
-    three_term<<<nblk(m3), kThreads, 0, stream>>>(m3, u, vm, vprev, &ls->alpha[k - 1],
-                                                   k > 1 ? &ls->beta[k - 2] : nullptr);
-    RPB_LAUNCHED(ctx);
-    {
-      const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
-      reorth_dots<<<grid, kThreads, 0, stream>>>(m3, V, u, part);
+    if (m3 <= kFusedSegment) {   // the whole iteration's vector work in one workgroup
+      lanczos_step<<<1, kThreads, 0, stream>>>(ls, V, u, m3, k, tol, k < max_iter);
       RPB_LAUNCHED(ctx);
-      reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
+    } else {
+      RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
+      three_term<<<nblk(m3), kThreads, 0, stream>>>(m3, u, vm, vprev, &ls->alpha[k - 1],
+                                                     k > 1 ? &ls->beta[k - 2] : nullptr);
       RPB_LAUNCHED(ctx);
-      reorth_update<<<nblk(m3), kThreads, 0, stream>>>(m3, k, V, ls->h, u);
+      {
+        const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
+        reorth_dots<<<grid, kThreads, 0, stream>>>(m3, V, u, part);
+        RPB_LAUNCHED(ctx);
+        reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
+        RPB_LAUNCHED(ctx);
+        reorth_update<<<nblk(m3), kThreads, 0, stream>>>(m3, k, V, ls->h, u);
+        RPB_LAUNCHED(ctx);
+      }
+      RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[k - 1], 1, stream));
+      tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls);
       RPB_LAUNCHED(ctx);
-    }
-    RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[k - 1], 1, stream));
-    tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls);
-    RPB_LAUNCHED(ctx);
-    if (k < max_iter) {
-      scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
-                                                           V + int64_t(k) * m3, ls);
-      RPB_LAUNCHED(ctx);
+      if (k < max_iter) {
+        scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
+                                                             V + int64_t(k) * m3, ls);
+        RPB_LAUNCHED(ctx);
+      }
     }
     RPB_TRY(lz_ring_post(ctx, ring, k & 1, &ls->eps, stream));
     // the status of the previous iteration (or of this one, after the last)
@@ -723,6 +819,9 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
   RPB_LAUNCHED(ctx);
   int *host_done = static_cast<int *>(host_scratch(ctx));
   const int *known = nullptr;   // host copy of the flags, once read
+  bool fused = true;            // every system small enough for one workgroup per iteration
+  for (int s = 0; s < nsys; ++s)
+    fused = fused && 3 * (b.host_offs[s + 1] - b.host_offs[s]) <= kFusedSegment;
   for (int k = 1; k <= max_iter; ++k) {
     double *vk = V + int64_t(k - 1) * m3;
     const double *vprev = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
@@ -738,25 +837,32 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
     } else {
       RPB_TRY(product(vk, v.done, known, u));
     }
-    RPB_TRY(seg_dot(vk, u, f_alpha + k - 1, 0));
-    seg_three_term<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, u, vk, vprev);
-    RPB_LAUNCHED(ctx);
-    seg_reorth_dots<<<dim3{unsigned(kSegBlocks), unsigned(k), ns}, kThreads, 0, stream>>>(
-        v, m3, k, V, u, part);
-    RPB_LAUNCHED(ctx);
-    seg_reorth_finish<<<ns, 64, 0, stream>>>(v, k, part);
-    RPB_LAUNCHED(ctx);
-    seg_reorth_update<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, V, u);
-    RPB_LAUNCHED(ctx);
-    RPB_TRY(seg_dot(u, u, f_beta + k - 1, 1));
-    tridiag_sqrt_batched<<<ns, 64, 0, stream>>>(v, k, tol);
-    RPB_LAUNCHED(ctx);
-    seg_all_done<<<1, 256, 0, stream>>>(v, nsys);
-    RPB_LAUNCHED(ctx);
-    if (k < max_iter) {
-      seg_scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(v, m3, u, f_beta + k - 1,
-                                                               V + int64_t(k) * m3);
+    if (fused) {   // every system's iteration in one workgroup
+      seg_lanczos_step<<<ns, kThreads, 0, stream>>>(v, V, u, m3, k, tol, k < max_iter);
       RPB_LAUNCHED(ctx);
+      seg_all_done<<<1, 256, 0, stream>>>(v, nsys);
+      RPB_LAUNCHED(ctx);
+    } else {
+      RPB_TRY(seg_dot(vk, u, f_alpha + k - 1, 0));
+      seg_three_term<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, u, vk, vprev);
+      RPB_LAUNCHED(ctx);
+      seg_reorth_dots<<<dim3{unsigned(kSegBlocks), unsigned(k), ns}, kThreads, 0, stream>>>(
+          v, m3, k, V, u, part);
+      RPB_LAUNCHED(ctx);
+      seg_reorth_finish<<<ns, 64, 0, stream>>>(v, k, part);
+      RPB_LAUNCHED(ctx);
+      seg_reorth_update<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, V, u);
+      RPB_LAUNCHED(ctx);
+      RPB_TRY(seg_dot(u, u, f_beta + k - 1, 1));
+      tridiag_sqrt_batched<<<ns, 64, 0, stream>>>(v, k, tol);
+      RPB_LAUNCHED(ctx);
+      seg_all_done<<<1, 256, 0, stream>>>(v, nsys);
+      RPB_LAUNCHED(ctx);
+      if (k < max_iter) {
+        seg_scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(v, m3, u, f_beta + k - 1,
+                                                                 V + int64_t(k) * m3);
+        RPB_LAUNCHED(ctx);
+      }
     }
     if (sync_each) {
       RPB_HIP(ctx, hipMemcpyAsync(host_done, v.done, size_t(nsys) * sizeof(int),

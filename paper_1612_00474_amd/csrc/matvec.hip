@@ -429,15 +429,18 @@ __device__ __forceinline__ void load_own(const Real *__restrict__ src, int64_t n
   }
 }
 
-// Tile pair (I, J), I <= J, of one system: `g`, `src` and `partial` already point at the
-// system's first sphere and first partial slot.  Every lane of the workgroup must call this.
+// Tile pair (I, J), I <= J, of linear index Lp, source part h, of one system: `g`, `src` and
+// `partial` already point at the system's first sphere and first partial; the slots follow
+// `pm`.  The mixed kernels store their partial sums as float32 (the compensated row sums and
+// the float64 column sums over the wavefronts, rounded once).  Every lane of the workgroup
+// must call this.
 template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
                                               const float *__restrict__ src,
                                               const PairConsts<float> &k,
-                                              double *__restrict__ partial, int64_t I, int64_t J,
-                                              int64_t h, LdsF<TORQUE> &L,
-                                              float (&col)[kWaves][kBlock][3]) {
+                                              float *__restrict__ partial, const PartMap &pm,
+                                              int64_t Lp, int64_t I, int64_t J, int64_t h,
+                                              LdsF<TORQUE> &L, float (&col)[kWaves][kBlock][3]) {
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t n = a.n;
@@ -455,7 +458,8 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
       if (first + local < n)
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          partial[sym_slot(a, I, I, d, local, h)] = double(T.s[q][d]) - double(T.c[q][d]);
+          partial[part_elem(pm, Lp, h, 0, d, local)] =
+              float(double(T.s[q][d]) - double(T.c[q][d]));
     }
     return;
   }
@@ -515,7 +519,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
         double v = 0.0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) v += double(col[w][tid][d]);
-        partial[sym_slot(a, J, I, d, l)] = v;
+        partial[part_elem(pm, Lp, pm.nsplit, 0, d, l)] = float(v);
       }
     }
   }
@@ -525,7 +529,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
     if (first + local < n)
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        partial[sym_slot(a, I, J, d, local, h)] = double(T.s[q][d]) - double(T.c[q][d]);
+        partial[part_elem(pm, Lp, h, 0, d, local)] = float(double(T.s[q][d]) - double(T.c[q][d]));
   }
 }
 
@@ -533,9 +537,9 @@ template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
                                               const double *__restrict__ src,
                                               const PairConsts<double> &k,
-                                              double *__restrict__ partial, int64_t I, int64_t J,
-                                              int64_t h, LdsD<TORQUE> &L,
-                                              double (&col)[kWaves][kBlock][3]) {
+                                              double *__restrict__ partial, const PartMap &pm,
+                                              int64_t Lp, int64_t I, int64_t J, int64_t h,
+                                              LdsD<TORQUE> &L, double (&col)[kWaves][kBlock][3]) {
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t n = a.n;
@@ -552,7 +556,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
       const int64_t local = q * kBlock + tid;
       if (first + local < n)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, I, d, local, h)] = T.u[q][d];
+        for (int d = 0; d < 3; ++d) partial[part_elem(pm, Lp, h, 0, d, local)] = T.u[q][d];
     }
     return;
   }
@@ -603,7 +607,7 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
         double v = 0.0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) v += col[w][tid][d];
-        partial[sym_slot(a, J, I, d, l)] = v;
+        partial[part_elem(pm, Lp, pm.nsplit, 0, d, l)] = v;
       }
     }
   }
@@ -612,26 +616,28 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
     const int64_t local = q * kBlock + tid;
     if (first + local < n)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) partial[sym_slot(a, I, J, d, local, h)] = T.u[q][d];
+      for (int d = 0; d < 3; ++d) partial[part_elem(pm, Lp, h, 0, d, local)] = T.u[q][d];
   }
 }
 
+// One workgroup per (tile pair, source part) of the chunk [pm.L0, pm.L0 + gridDim.x / nsplit).
 template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
-__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, GeomF g,
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, PartMap pm, GeomF g,
                                                                 const float *__restrict__ src,
                                                                 PairConsts<float> k,
-                                                                double *__restrict__ partial) {
+                                                                float *__restrict__ partial) {
   if (a.skip && *a.skip) return;
   __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
   int64_t I, J;
-  tri_decode(blockIdx.x / a.nsplit, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, blockIdx.x % a.nsplit,
-                                             L, col);
+  const int64_t Lp = pm.L0 + int64_t(blockIdx.x) / a.nsplit;
+  tri_decode(Lp, a.nt, I, J);
+  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, pm, Lp, I, J,
+                                             int64_t(blockIdx.x) % a.nsplit, L, col);
 }
 
 template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
-__global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g,
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, PartMap pm, GeomD g,
                                                               const double *__restrict__ src,
                                                               PairConsts<double> k,
                                                               double *__restrict__ partial) {
@@ -639,34 +645,27 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, GeomD g
   __shared__ LdsD<TORQUE> L;
   __shared__ double col[kWaves][kBlock][3];
   int64_t I, J;
-  tri_decode(blockIdx.x / a.nsplit, a.nt, I, J);
-  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, I, J, blockIdx.x % a.nsplit,
-                                             L, col);
+  const int64_t Lp = pm.L0 + int64_t(blockIdx.x) / a.nsplit;
+  tri_decode(Lp, a.nt, I, J);
+  sym_tile_pair<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, partial, pm, Lp, I, J,
+                                             int64_t(blockIdx.x) % a.nsplit, L, col);
 }
 
-// One thread per (component, row): four independent partial sums over the slots (P mod 4),
-// combined in a fixed order, so the memory system sees four loads in flight per thread.  With
-// source parts (nsplit > 1) the row side T <= P holds one slot per part.
-__global__ void reduce_partials_sym(SymArgs a, const double *__restrict__ partial,
-                                    const double *__restrict__ h, double scale,
-                                    double *__restrict__ vel) {
+// One thread per (component, row): the partials of the chunk [pm.L0, L1) added in a fixed
+// order (chunk_row_sum), written to vel on the first chunk and added to it on the others; after
+// the last chunk the sum is scaled by H_i / (8 pi eta a).
+template <typename Part>
+__global__ void reduce_sym_chunk(SymArgs a, PartMap pm, int64_t L1, int first, int last,
+                                 const Part *__restrict__ partial, const double *__restrict__ h,
+                                 double scale, double *__restrict__ vel) {
   if (a.skip && *a.skip) return;
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= 3 * a.n) return;
   const int d = int(e / a.n);
   const int64_t r = e - int64_t(d) * a.n;
-  const int64_t T = r / a.ts, local = r % a.ts;
-  const double *base = partial + sym_slot(a, T, 0, d, local);
-  const int64_t ph = 3 * a.ts;             // slot (T, P, h) to (T, P, h + 1)
-  const int64_t stride = a.nsplit * ph;    // slot (T, P, 0) to (T, P + 1, 0)
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t P = 0; P < a.nt; ++P) {
-    double v = base[P * stride];
-    if (P >= T)
-      for (int64_t q = 1; q < a.nsplit; ++q) v += base[P * stride + q * ph];
-    s[P & 3] += v;
-  }
-  vel[3 * r + d] = scale * h[r] * ((s[0] + s[1]) + (s[2] + s[3]));
+  double v = chunk_row_sum(partial, pm, a.nt, L1, r / a.ts, r % a.ts, 0, d);
+  if (!first) v += vel[3 * r + d];
+  vel[3 * r + d] = last ? scale * h[r] * v : v;
 }
 
 // ---- batched systems: persistent workgroups over a cost-ordered item list -------------------
@@ -784,17 +783,21 @@ __device__ __forceinline__ int next_sym_item(const SymBatchArgs &b, int *slot) {
 template <int TPT, bool TORQUE, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
     SymBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k,
-    double *__restrict__ partial) {
+    float *__restrict__ partial) {
   __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
   __shared__ int slot[1];
   if (b.all_done && *b.all_done) return;
+  const PartMap pm{0, b.nsplit, b.ts, 1};
   for (int it = next_sym_item(b, slot); it >= 0; it = next_sym_item(b, slot)) {
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
-    sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
-                               partial + b.part_base[w.x], w.y, w.z, w.w, L, col);
+    const SymArgs a = sym_args_of(b, w.x);
+    sym_tile_pair<TPT, TORQUE, WALL, false>(a, offset_geom(g, s0), src + s0, k,
+                                            partial + b.part_base[w.x], pm,
+                                            tri_start(w.y, a.nt) + w.z - w.y, w.y, w.z, w.w, L,
+                                            col);
   }
 }
 
@@ -806,17 +809,23 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
   __shared__ double col[kWaves][kBlock][3];
   __shared__ int slot[1];
   if (b.all_done && *b.all_done) return;
+  const PartMap pm{0, b.nsplit, b.ts, 1};
   for (int it = next_sym_item(b, slot); it >= 0; it = next_sym_item(b, slot)) {
     const int4 w = b.items[it];
     if (b.done && b.done[w.x]) continue;
     const int64_t s0 = b.offs[w.x];
-    sym_tile_pair<TPT, TORQUE, WALL, false>(sym_args_of(b, w.x), offset_geom(g, s0), src + s0, k,
-                               partial + b.part_base[w.x], w.y, w.z, w.w, L, col);
+    const SymArgs a = sym_args_of(b, w.x);
+    sym_tile_pair<TPT, TORQUE, WALL, false>(a, offset_geom(g, s0), src + s0, k,
+                                            partial + b.part_base[w.x], pm,
+                                            tri_start(w.y, a.nt) + w.z - w.y, w.y, w.z, w.w, L,
+                                            col);
   }
 }
 
+// System s's partials start at part_base[s] and cover its whole triangle (one chunk).
+template <typename Part>
 __global__ void reduce_partials_sym_batched(SymBatchArgs b, const int *__restrict__ sys_of,
-                                            const double *__restrict__ partial,
+                                            const Part *__restrict__ partial,
                                             const double *__restrict__ h, double scale,
                                             double *__restrict__ vel) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // (component, row)
@@ -827,18 +836,10 @@ __global__ void reduce_partials_sym_batched(SymBatchArgs b, const int *__restric
   if (b.done && b.done[s]) return;
   const SymArgs a = sym_args_of(b, s);
   const int64_t local = r - b.offs[s];
-  const int64_t T = local / a.ts;
-  const double *base = partial + b.part_base[s] + sym_slot(a, T, 0, d, local % a.ts);
-  const int64_t ph = 3 * a.ts;             // slot (T, P, h) to (T, P, h + 1)
-  const int64_t stride = a.nsplit * ph;    // slot (T, P, 0) to (T, P + 1, 0)
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t P = 0; P < a.nt; ++P) {
-    double v = base[P * stride];
-    if (P >= T)
-      for (int64_t q = 1; q < a.nsplit; ++q) v += base[P * stride + q * ph];
-    acc[P & 3] += v;
-  }
-  vel[3 * r + d] = scale * h[r] * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  const PartMap pm{0, b.nsplit, b.ts, 1};
+  vel[3 * r + d] = scale * h[r] *
+                   chunk_row_sum(partial + b.part_base[s], pm, a.nt, a.nt * (a.nt + 1) / 2,
+                                 local / a.ts, local % a.ts, 0, d);
 }
 
 __global__ void fill_sys_of(int nsys, const int64_t *__restrict__ offs, int *__restrict__ sys_of) {
@@ -1123,15 +1124,42 @@ inline int64_t sym_nsplit(int64_t n, int64_t ts) {
   return q;
 }
 
-// Partial buffer of the symmetric kernel, nt^2 nsplit slots of 3 ts doubles.  Larger systems
-// take the ordered kernel, whose partials grow as O(n).
-constexpr size_t kMaxSymPartialBytes = size_t(32) << 30;
-inline size_t sym_partial_bytes(int64_t n, int64_t ts, int64_t nsplit = 1) {
-  const int64_t nt = (n + ts - 1) / ts;
-  return size_t(nt) * size_t(nt) * size_t(nsplit) * 3 * size_t(ts) * sizeof(double);
+// Partials of one persistent batched launch of the symmetric kernel (every system's triangle at
+// once); larger batches take the ordered items.
+constexpr size_t kMaxBatchSymBytes = size_t(4) << 30;
+
+// Calls fn(torque, tpt, wall, periodic) for the symmetric kernel, which also takes 4 targets
+// per lane (tiles of 1,024 spheres).
+template <typename Fn>
+void with_sym_variant(bool torque, int tpt, bool wall, bool periodic, Fn &&fn) {
+  if (tpt == 4) {
+    using P4 = std::integral_constant<int, 4>;
+    auto by_box = [&](auto t, auto w) {
+      if (periodic)
+        fn(t, P4{}, w, std::true_type{});
+      else
+        fn(t, P4{}, w, std::false_type{});
+    };
+    auto by_wall = [&](auto t) {
+      if (wall)
+        by_box(t, std::true_type{});
+      else
+        by_box(t, std::false_type{});
+    };
+    if (torque)
+      by_wall(std::true_type{});
+    else
+      by_wall(std::false_type{});
+    return;
+  }
+  with_variant(torque, tpt, wall, periodic, fn);
 }
 
-// Whole-system product with one evaluation per unordered pair.
+// Whole-system product with one evaluation per unordered pair.  The triangle of tile pairs is
+// walked in chunks whose partials fit the context's limit (512 MiB: one chunk up to about
+// 150,000 spheres in mixed precision and 100,000 in float64 at 2 targets per lane), each
+// chunk's pair kernel followed by its reduction into vel, so the workspace stays bounded
+// whatever n.  The timing record spans the pair kernels of all chunks.
 int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
                      bool torque, const double *h, int tpt, double *vel, hipStream_t stream,
                      const int *skip) {
@@ -1141,32 +1169,44 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
   a.skip = skip;
   a.nt = (n + a.ts - 1) / a.ts;
   a.nsplit = sym_nsplit(n, a.ts);
-  if (a.nt * (a.nt + 1) / 2 * a.nsplit > 0x7fffffffll)
-    return fail(ctx, RPB_EINVAL, "problem too large for one launch (n = %lld)", (long long)n);
+  const int64_t pairs = a.nt * (a.nt + 1) / 2;
+  const size_t esz = f64 ? sizeof(double) : sizeof(float);
+  const int64_t per = chunk_pairs(pairs, a.nsplit, 1, a.ts, esz, ctx->chunk_bytes);
   int st;
-  double *part = static_cast<double *>(
-      workspace(ctx, WS_PART, sym_partial_bytes(n, a.ts, a.nsplit), &st));
+  void *part = workspace(ctx, WS_PART, size_t(part_elems(per, a.nsplit, 1, a.ts)) * esz, &st);
   if (!part) return st;
-  const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2 * a.nsplit);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
-  with_variant(torque, tpt, p->wall != 0, periodic(p), [&](auto T, auto P, auto W, auto B) {
-    constexpr bool kT = decltype(T)::value, kW = decltype(W)::value, kB = decltype(B)::value;
-    constexpr int kP = decltype(P)::value;
+  for (int64_t L0 = 0; L0 < pairs; L0 += per) {
+    const int64_t L1 = std::min(pairs, L0 + per);
+    const PartMap pm{L0, a.nsplit, a.ts, 1};
+    const unsigned grid = unsigned((L1 - L0) * a.nsplit);
+    with_sym_variant(torque, tpt, p->wall != 0, periodic(p), [&](auto T, auto P, auto W, auto B) {
+      constexpr bool kT = decltype(T)::value, kW = decltype(W)::value, kB = decltype(B)::value;
+      constexpr int kP = decltype(P)::value;
+      if (f64)
+        pair_kernel_f64_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
+            a, pm, geom_d(g), static_cast<const double *>(src),
+            make_pair_consts<double>(p->lx / p->a, p->ly / p->a), static_cast<double *>(part));
+      else
+        pair_kernel_mixed_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
+            a, pm, geom_f(g), static_cast<const float *>(src),
+            make_pair_consts<float>(p->lx / p->a, p->ly / p->a), static_cast<float *>(part));
+    });
+    RPB_LAUNCHED(ctx);
+    if (L1 == pairs)
+      RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n),
+                         (f64 ? 0 : 2) + (torque ? 1 : 0)));
+    const int first = L0 == 0, last = L1 == pairs;
     if (f64)
-      pair_kernel_f64_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
-          a, geom_d(g), static_cast<const double *>(src),
-          make_pair_consts<double>(p->lx / p->a, p->ly / p->a), part);
+      reduce_sym_chunk<double><<<blocks_for(3 * n, 256), 256, 0, stream>>>(
+          a, pm, L1, first, last, static_cast<const double *>(part), h, scale, vel);
     else
-      pair_kernel_mixed_sym<kP, kT, kW, kB><<<grid, kBlock, 0, stream>>>(
-          a, geom_f(g), static_cast<const float *>(src),
-          make_pair_consts<float>(p->lx / p->a, p->ly / p->a), part);
-  });
-  RPB_LAUNCHED(ctx);
-  RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n), (f64 ? 0 : 2) + (torque ? 1 : 0)));
-  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
-  reduce_partials_sym<<<blocks_for(3 * n, 256), 256, 0, stream>>>(a, part, h, scale, vel);
-  RPB_LAUNCHED(ctx);
+      reduce_sym_chunk<float><<<blocks_for(3 * n, 256), 256, 0, stream>>>(
+          a, pm, L1, first, last, static_cast<const float *>(part), h, scale, vel);
+    RPB_LAUNCHED(ctx);
+  }
   return RPB_OK;
 }
 
@@ -1182,11 +1222,9 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
 
   const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
-  const int tpt = shape.tpt;
-  if (row0 == 0 && nrows == n && shape.symmetric &&
-      sym_partial_bytes(n, int64_t(kBlock) * tpt, sym_nsplit(n, int64_t(kBlock) * tpt)) <=
-          kMaxSymPartialBytes)
-    return matvec_symmetric(ctx, p, g, src, has_t, h, tpt, vel, stream, skip);
+  if (row0 == 0 && nrows == n && shape.symmetric)
+    return matvec_symmetric(ctx, p, g, src, has_t, h, shape.tpt, vel, stream, skip);
+  const int tpt = std::min(shape.tpt, 2);   // the ordered kernel takes 1 or 2 targets per lane
   const int64_t chunk = ordered_chunk(n, tpt, shape.target_wgs, 65535);
   const int64_t nchunks = (n + chunk - 1) / chunk;
   int st;
@@ -1215,8 +1253,9 @@ int matvec_into(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
     return fail(ctx, RPB_EINVAL,
                 "n = %lld needs %zu bytes of scratch with one source chunk; the scratch holds %zu",
                 (long long)n, fixed + per_chunk, bytes);
+  const int tpt = std::min(shape.tpt, 2);   // the ordered kernel takes 1 or 2 targets per lane
   const int64_t chunk =
-      ordered_chunk(n, shape.tpt, shape.target_wgs, int64_t((bytes - fixed) / per_chunk));
+      ordered_chunk(n, tpt, shape.target_wgs, int64_t((bytes - fixed) / per_chunk));
   char *base = static_cast<char *>(buf);
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   void *geom = base;
@@ -1226,8 +1265,8 @@ int matvec_into(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
   Packed g;
   RPB_TRY(pack_geometry_into(ctx, p, n, pos, geom, &g, stream));
   RPB_TRY(pack_sources_into(ctx, g, force, torque, src, stream));
-  return ordered_product(ctx, p, g, src, torque != nullptr, shape.tpt, chunk, 0, n, part, vel,
-                         stream, nullptr, false);
+  return ordered_product(ctx, p, g, src, torque != nullptr, tpt, chunk, 0, n, part, vel, stream,
+                         nullptr, false);
 }
 
 // ---- batched -----------------------------------------------------------------------------
@@ -1255,9 +1294,15 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
       pairs += nt * (nt + 1) / 2;
     }
     while (pairs * b->nsplit < 4 * int64_t(b->wgs) && per / (2 * b->nsplit) >= 128) b->nsplit *= 2;
+    const size_t esz = precision == RPB_FP64 ? sizeof(double) : sizeof(float);
     size_t bytes = 0;
-    for (int s = 0; s < nsys; ++s) bytes += sym_partial_bytes(offs[s + 1] - offs[s], per, b->nsplit);
-    if (bytes > kMaxSymPartialBytes) {
+    for (int s = 0; s < nsys; ++s) {
+      const int64_t nt = (offs[s + 1] - offs[s] + per - 1) / per;
+      bytes += size_t(part_elems(nt * (nt + 1) / 2, b->nsplit, 1, per)) * esz;
+    }
+    // one persistent launch holds every system's partials: beyond the limit the batch takes
+    // the ordered items, whose partials grow as O(n)
+    if (bytes > kMaxBatchSymBytes) {
       b->symmetric = false;
       b->nsplit = 1;
     }
@@ -1275,7 +1320,7 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
     if (b->symmetric) {
       const int64_t nt = (ns + per - 1) / per;
       part_base[s] = part_elems;
-      part_elems += nt * nt * b->nsplit * 3 * per;
+      part_elems += rpb::part_elems(nt * (nt + 1) / 2, b->nsplit, 1, per);
       for (int64_t I = 0; I < nt; ++I)
         for (int64_t J = I; J < nt; ++J)
           for (int64_t q = 0; q < b->nsplit; ++q) {
@@ -1347,7 +1392,7 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
 namespace {
 
 int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Packed &g,
-                       const void *src, bool has_t, const int *done, int *counter, double *part,
+                       const void *src, bool has_t, const int *done, int *counter, void *part,
                        const double *h, double *vel, hipStream_t stream) {
   const int64_t n = g.n;
   const bool f64 = g.precision == RPB_FP64;
@@ -1368,16 +1413,21 @@ int matvec_batched_sym(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const 
     if (f64)
       pair_kernel_f64_sym_batched<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
           args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(),
-          part);
+          static_cast<double *>(part));
     else
       pair_kernel_mixed_sym_batched<kP, kT, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(), part);
+          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(),
+          static_cast<float *>(part));
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
-  reduce_partials_sym_batched<<<blocks_for(3 * n, 256), 256, 0, stream>>>(args, b.sys_of, part,
-                                                                          h, scale, vel);
+  if (f64)
+    reduce_partials_sym_batched<double><<<blocks_for(3 * n, 256), 256, 0, stream>>>(
+        args, b.sys_of, static_cast<const double *>(part), h, scale, vel);
+  else
+    reduce_partials_sym_batched<float><<<blocks_for(3 * n, 256), 256, 0, stream>>>(
+        args, b.sys_of, static_cast<const float *>(part), h, scale, vel);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }
@@ -1395,10 +1445,11 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
   RPB_TRY(pack_sources(ctx, g, force, torque, &src, stream));
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
   int st;
-  const size_t part_elems =
-      b.symmetric ? size_t(b.part_elems) : size_t(b.max_chunks) * 3 * size_t(n);
-  double *part = static_cast<double *>(
-      workspace(ctx, WS_PART, std::max<size_t>(1, part_elems) * sizeof(double), &st));
+  // symmetric items: float32 partials in mixed precision; ordered items: float64
+  const size_t part_bytes = b.symmetric
+                                ? size_t(b.part_elems) * (f64 ? sizeof(double) : sizeof(float))
+                                : size_t(b.max_chunks) * 3 * size_t(n) * sizeof(double);
+  void *part = workspace(ctx, WS_PART, std::max<size_t>(8, part_bytes), &st);
   if (!part) return st;
   char *small = static_cast<char *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
   if (!small) return st;
@@ -1410,6 +1461,7 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
 
   BatchArgs args{b.offs, b.items, b.nitems, counter, n, b.chunk, done,
                  done ? done + b.nsys : nullptr};
+  double *dpart = static_cast<double *>(part);
   const unsigned grid = unsigned(std::max(1, std::min(b.nitems, b.wgs)));
   double pairs = 0.0;
   for (int s = 0; s < b.nsys; ++s) {
@@ -1425,16 +1477,16 @@ int matvec_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &b, const Pack
     if (f64)
       pair_kernel_f64_batched<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
           args, geom_d(g), static_cast<const double *>(src), make_pair_consts<double>(),
-          part);
+          dpart);
     else
       pair_kernel_mixed_batched<kT, kP, kW><<<grid, kBlock, 0, stream>>>(
-          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(), part);
+          args, geom_f(g), static_cast<const float *>(src), make_pair_consts<float>(), dpart);
   });
   RPB_LAUNCHED(ctx);
   RPB_TRY(timing_end(ctx, stream, t0, pairs, 4 + (f64 ? 0 : 2) + (has_t ? 1 : 0)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   reduce_partials_batched<<<blocks_for(n, 256), 256, 0, stream>>>(n, b.sys_of, b.offs, b.chunk,
-                                                                 done, part, h, scale, vel);
+                                                                 done, dpart, h, scale, vel);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }

@@ -30,8 +30,9 @@ namespace rpb {
 namespace {
 
 constexpr int kMulti = 4;   // source vectors per launch of the plain multi-vector product
-// Largest partial buffer of one launch; larger systems use the single-vector product per vector.
-constexpr size_t kMaxMultiPartialBytes = size_t(32) << 30;
+// Partials of one persistent batched launch (every system's triangle at once); larger batches
+// take the single-vector batched products.
+constexpr size_t kMaxMultiBatchBytes = size_t(4) << 30;
 
 // Source rows of a launch of K vectors: forces of slots 0..K-1 (3 each), then, with TQ, the
 // torque of slot 0.
@@ -164,20 +165,15 @@ __device__ __forceinline__ void multi_step(const Lds &L, int j, bool valid, cons
                                  cs[1], cs[2]);
 }
 
-// partial[(((v nt + T) nt + P) 3 + comp) kBlock + local]: tile pair (T, P)'s sums for the rows
-// of tile T, vector slot v.
-__device__ __forceinline__ int64_t multi_slot(const SymArgs &a, int v, int64_t T, int64_t P,
-                                              int comp, int64_t local) {
-  return (((int64_t(v) * a.nt + T) * a.nt + P) * 3 + comp) * kBlock + local;
-}
-
-// Tile pair (I, J), I <= J.  Every lane of the workgroup must call this (it synchronises).
-template <int K, bool TQ, bool WALL, typename Real, typename Geom, typename Lds>
+// Tile pair (I, J), I <= J, of linear index Lp; its partials follow `pm` (one part, K
+// vectors per slot), float32 in mixed precision.  Every lane of the workgroup must call this
+// (it synchronises).
+template <int K, bool TQ, bool WALL, typename Real, typename Part, typename Geom, typename Lds>
 __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
                                                 const Real *__restrict__ src,
                                                 const PairConsts<Real> &k,
-                                                double *__restrict__ partial, int64_t I,
-                                                int64_t J, Lds &L) {
+                                                Part *__restrict__ partial, const PartMap &pm,
+                                                int64_t Lp, int64_t I, int64_t J, Lds &L) {
   constexpr int R = src_rows<K, TQ>();
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
@@ -242,7 +238,7 @@ __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
           double sum = 0.0;
 #pragma unroll
           for (int w = 0; w < kWaves; ++w) sum += double(L.col[w][e][s]);
-          partial[multi_slot(a, e / 3, J, I, e % 3, blk + s)] = sum;
+          partial[part_elem(pm, Lp, 1, e / 3, e % 3, blk + s)] = Part(sum);
         }
       }
       __syncthreads();
@@ -251,35 +247,40 @@ __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
   if (on)
 #pragma unroll
     for (int e = 0; e < 3 * K; ++e)
-      partial[multi_slot(a, e / 3, I, J, e % 3, tid)] = double(acc[e]);
+      partial[part_elem(pm, Lp, 0, e / 3, e % 3, tid)] = Part(acc[e]);
 }
 
+// One workgroup per tile pair of the chunk [pm.L0, pm.L0 + gridDim.x).
 template <int K, bool TQ, bool WALL>
-__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi(SymArgs a, GeomF g,
+__global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi(SymArgs a, PartMap pm, GeomF g,
                                                                   const float *__restrict__ src,
                                                                   PairConsts<float> k,
-                                                                  double *__restrict__ partial) {
+                                                                  float *__restrict__ partial) {
   __shared__ MultiLdsF<K, TQ> L;
   int64_t I, J;
-  tri_decode(blockIdx.x, a.nt, I, J);
-  multi_tile_pair<K, TQ, WALL>(a, g, src, k, partial, I, J, L);
+  const int64_t Lp = pm.L0 + int64_t(blockIdx.x);
+  tri_decode(Lp, a.nt, I, J);
+  multi_tile_pair<K, TQ, WALL>(a, g, src, k, partial, pm, Lp, I, J, L);
 }
 
 template <int K, bool TQ, bool WALL>
-__global__ __launch_bounds__(kBlock) void pair_kernel_f64_multi(SymArgs a, GeomD g,
+__global__ __launch_bounds__(kBlock) void pair_kernel_f64_multi(SymArgs a, PartMap pm, GeomD g,
                                                                 const double *__restrict__ src,
                                                                 PairConsts<double> k,
                                                                 double *__restrict__ partial) {
   __shared__ MultiLdsD<K, TQ> L;
   int64_t I, J;
-  tri_decode(blockIdx.x, a.nt, I, J);
-  multi_tile_pair<K, TQ, WALL>(a, g, src, k, partial, I, J, L);
+  const int64_t Lp = pm.L0 + int64_t(blockIdx.x);
+  tri_decode(Lp, a.nt, I, J);
+  multi_tile_pair<K, TQ, WALL>(a, g, src, k, partial, pm, Lp, I, J, L);
 }
 
-// One thread per (vector slot, component, row); four independent partial sums over the
-// slots (P mod 4), combined in a fixed order.  Slot v's result goes to out.p[v] ([n][3]).
-template <int K>
-__global__ void reduce_multi(SymArgs a, OutPtrs<K> out, const double *__restrict__ partial,
+// One thread per (vector slot, component, row): the chunk's partials added in a fixed order
+// (chunk_row_sum), written to out.p[v] ([n][3]) on the first chunk and added on the others,
+// scaled by H_i / (8 pi eta a) after the last.
+template <int K, typename Part>
+__global__ void reduce_multi(SymArgs a, PartMap pm, int64_t L1, int first, int last,
+                             OutPtrs<K> out, const Part *__restrict__ partial,
                              const double *__restrict__ h, double scale) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t per = 3 * a.n;
@@ -290,42 +291,31 @@ __global__ void reduce_multi(SymArgs a, OutPtrs<K> out, const double *__restrict
   const int64_t r = rem - int64_t(d) * a.n;
   double *dst = out.p[v];
   if (!dst) return;
-  const int64_t T = r / kBlock, local = r % kBlock;
-  const double *base = partial + multi_slot(a, v, T, 0, d, local);
-  const int64_t stride = 3 * kBlock;   // slot (T, P) to (T, P + 1)
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t P = 0;
-  for (; P + 4 <= a.nt; P += 4) {
-    s0 += base[P * stride];
-    s1 += base[(P + 1) * stride];
-    s2 += base[(P + 2) * stride];
-    s3 += base[(P + 3) * stride];
-  }
-  for (; P < a.nt; ++P) s0 += base[P * stride];
-  dst[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
+  double x = chunk_row_sum(partial, pm, a.nt, L1, r / kBlock, r % kBlock, v, d);
+  if (!first) x += dst[3 * r + d];
+  dst[3 * r + d] = last ? scale * h[r] * x : x;
 }
 
-size_t multi_partial_bytes(int K, int64_t nt) {
-  return size_t(K) * size_t(nt) * size_t(nt) * 3 * size_t(kBlock) * sizeof(double);
-}
-
-// One launch of K vectors: sources in.p[k] (slot 0 with torque `torque` when TQ), results to
-// out.p[k].
+// One product of K vectors: sources in.p[k] (slot 0 with torque `torque` when TQ), results to
+// out.p[k].  The triangle of tile pairs is walked in chunks whose partials fit the context's
+// limit,
+// each chunk's pair kernel followed by its reduction into the results, so the workspace stays
+// bounded whatever n.  The timing record spans the pair kernels of all chunks.
 template <int K, bool TQ>
 int multi_launch(rpb_ctx *ctx, const rpb_params *p, const Packed &g, SrcPtrs<K> in,
                  const double *torque, OutPtrs<K> out, hipStream_t stream) {
   const int64_t n = g.n;
   const bool f64 = g.precision == RPB_FP64;
   SymArgs a{n, kBlock, (n + kBlock - 1) / kBlock, n};
-  int st;
-  double *part =
-      static_cast<double *>(workspace(ctx, WS_PART, multi_partial_bytes(K, a.nt), &st));
-  if (!part) return st;
+  const int64_t pairs = a.nt * (a.nt + 1) / 2;
   const size_t esz = f64 ? sizeof(double) : sizeof(float);
+  const int64_t per_chunk = chunk_pairs(pairs, 1, K, kBlock, esz, ctx->chunk_bytes);
+  int st;
+  void *part = workspace(ctx, WS_PART, size_t(part_elems(per_chunk, 1, K, kBlock)) * esz, &st);
+  if (!part) return st;
   void *src = workspace(ctx, WS_SRC, size_t(src_rows<K, TQ>()) * size_t(n) * esz, &st);
   if (!src) return st;
   const double *h = f64 ? geom_d(g).h : geom_f(g).h;
-  const unsigned grid = unsigned(a.nt * (a.nt + 1) / 2);
   int used = 0;
   for (int s = 0; s < K; ++s) used += in.p[s] != nullptr || (s == 0 && TQ);
   const double *tq = TQ ? torque : nullptr;
@@ -336,38 +326,50 @@ int multi_launch(rpb_ctx *ctx, const rpb_params *p, const Packed &g, SrcPtrs<K> 
     pack_multi<K, float><<<blocks_for(n, 256), 256, 0, stream>>>(n, in, h, tq, 1.0 / g.a,
                                                                 static_cast<float *>(src));
   RPB_LAUNCHED(ctx);
+  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   hipEvent_t t0;
   RPB_TRY(timing_begin(ctx, stream, &t0));
   const bool wall = p->wall != 0;
-  if (f64) {
-    const auto k = make_pair_consts<double>();
-    const auto *s = static_cast<const double *>(src);
-    if (wall)
-      pair_kernel_f64_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
+  for (int64_t L0 = 0; L0 < pairs; L0 += per_chunk) {
+    const int64_t L1 = std::min(pairs, L0 + per_chunk);
+    const PartMap pm{L0, 1, kBlock, K};
+    const unsigned grid = unsigned(L1 - L0);
+    if (f64) {
+      const auto k = make_pair_consts<double>();
+      const auto *s = static_cast<const double *>(src);
+      auto *pt = static_cast<double *>(part);
+      if (wall)
+        pair_kernel_f64_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, pm, geom_d(g), s, k, pt);
+      else
+        pair_kernel_f64_multi<K, TQ, false><<<grid, kBlock, 0, stream>>>(a, pm, geom_d(g), s, k,
+                                                                        pt);
+    } else {
+      const auto k = make_pair_consts<float>();
+      const auto *s = static_cast<const float *>(src);
+      auto *pt = static_cast<float *>(part);
+      if (wall)
+        pair_kernel_mixed_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, pm, geom_f(g), s, k,
+                                                                         pt);
+      else
+        pair_kernel_mixed_multi<K, TQ, false><<<grid, kBlock, 0, stream>>>(a, pm, geom_f(g), s, k,
+                                                                          pt);
+    }
+    RPB_LAUNCHED(ctx);
+    if (L1 == pairs)
+      RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n) * used, 8 + (f64 ? 0 : 2)));
+    const int first = L0 == 0, last = L1 == pairs;
+    const unsigned rgrid = blocks_for(int64_t(K) * 3 * n, 256);
+    if (f64)
+      reduce_multi<K, double><<<rgrid, 256, 0, stream>>>(a, pm, L1, first, last, out,
+                                                         static_cast<const double *>(part), h,
+                                                         scale);
     else
-      pair_kernel_f64_multi<K, TQ, false><<<grid, kBlock, 0, stream>>>(a, geom_d(g), s, k, part);
-  } else {
-    const auto k = make_pair_consts<float>();
-    const auto *s = static_cast<const float *>(src);
-    if (wall)
-      pair_kernel_mixed_multi<K, TQ, true><<<grid, kBlock, 0, stream>>>(a, geom_f(g), s, k, part);
-    else
-      pair_kernel_mixed_multi<K, TQ, false><<<grid, kBlock, 0, stream>>>(a, geom_f(g), s, k,
-                                                                         part);
+      reduce_multi<K, float><<<rgrid, 256, 0, stream>>>(a, pm, L1, first, last, out,
+                                                        static_cast<const float *>(part), h,
+                                                        scale);
+    RPB_LAUNCHED(ctx);
   }
-  RPB_LAUNCHED(ctx);
-  RPB_TRY(timing_end(ctx, stream, t0, double(n) * double(n) * used, 8 + (f64 ? 0 : 2)));
-  const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
-  reduce_multi<K><<<blocks_for(int64_t(K) * 3 * n, 256), 256, 0, stream>>>(a, out, part, h,
-                                                                            scale);
-  RPB_LAUNCHED(ctx);
   return RPB_OK;
-}
-
-// One launch can hold the problem (grid and partial-buffer limits).
-bool multi_fits(int K, int64_t n) {
-  const int64_t nt = (n + kBlock - 1) / kBlock;
-  return nt * (nt + 1) / 2 <= 0x7fffffffll && multi_partial_bytes(K, nt) <= kMaxMultiPartialBytes;
 }
 
 // ---- batches of independent systems ------------------------------------------------------
@@ -382,7 +384,8 @@ struct MultiBatchArgs {
 };
 
 // Item and partial offsets of every system (one workgroup): system s has nt (nt + 1)/2 tile
-// pairs of the upper triangle and K nt^2 3 kBlock partial doubles, nt = ceil(n_s / kBlock).
+// pairs of the upper triangle and part_elems(nt (nt + 1)/2, 1, K, kBlock) partials,
+// nt = ceil(n_s / kBlock).
 __global__ __launch_bounds__(kBlock) void multi_batch_setup(int nsys, int K,
                                                             const int64_t *__restrict__ offs,
                                                             int64_t *__restrict__ cum,
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void multi_batch_setup(int nsys, int K,
   for (int s = s0; s < s1; ++s) {
     const int64_t nt = (offs[s + 1] - offs[s] + kBlock - 1) / kBlock;
     ci += nt * (nt + 1) / 2;
-    ce += int64_t(K) * nt * nt * 3 * kBlock;
+    ce += part_elems(nt * (nt + 1) / 2, 1, K, kBlock);
   }
   pi[tid] = ci;
   pe[tid] = ce;
@@ -420,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void multi_batch_setup(int nsys, int K,
     base[s] = ce;
     const int64_t nt = (offs[s + 1] - offs[s] + kBlock - 1) / kBlock;
     ci += nt * (nt + 1) / 2;
-    ce += int64_t(K) * nt * nt * 3 * kBlock;
+    ce += part_elems(nt * (nt + 1) / 2, 1, K, kBlock);
   }
   if (tid == 0) {
     cum[nsys] = pi[kBlock];
@@ -428,10 +431,11 @@ __global__ __launch_bounds__(kBlock) void multi_batch_setup(int nsys, int K,
   }
 }
 
-// Next work item of the workgroup: (system, I, J), or false once the list is exhausted.  Every
-// workgroup keeps pulling until the counter passes the item count, so every wave exits.
+// Next work item of the workgroup: (system, tile pair Lp = (I, J)), or false once the list is
+// exhausted.  Every workgroup keeps pulling until the counter passes the item count, so every
+// wave exits.
 __device__ __forceinline__ bool next_multi_item(const MultiBatchArgs &b, int *slot, int &sys,
-                                                int64_t &I, int64_t &J) {
+                                                int64_t &Lp, int64_t &I, int64_t &J) {
   __syncthreads();
   if (threadIdx.x == 0) slot[0] = atomicAdd(b.counter, 1);
   __syncthreads();
@@ -447,7 +451,8 @@ __device__ __forceinline__ bool next_multi_item(const MultiBatchArgs &b, int *sl
   }
   sys = lo;
   const int64_t nt = (b.offs[lo + 1] - b.offs[lo] + kBlock - 1) / kBlock;
-  tri_decode(it - b.cum[lo], nt, I, J);
+  Lp = it - b.cum[lo];
+  tri_decode(Lp, nt, I, J);
   return true;
 }
 
@@ -459,15 +464,16 @@ __device__ __forceinline__ SymArgs multi_args_of(const MultiBatchArgs &b, int s)
 template <int K, bool TQ, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi_batched(
     MultiBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k,
-    double *__restrict__ partial) {
+    float *__restrict__ partial) {
   __shared__ MultiLdsF<K, TQ> L;
   __shared__ int slot[1];
+  const PartMap pm{0, 1, kBlock, K};
   int s;
-  int64_t I, J;
-  while (next_multi_item(b, slot, s, I, J)) {
+  int64_t Lp, I, J;
+  while (next_multi_item(b, slot, s, Lp, I, J)) {
     const int64_t s0 = b.offs[s];
     multi_tile_pair<K, TQ, WALL>(multi_args_of(b, s), offset_geom(g, s0), src + s0, k,
-                                 partial + b.base[s], I, J, L);
+                                 partial + b.base[s], pm, Lp, I, J, L);
   }
 }
 
@@ -477,18 +483,19 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_multi_batched(
     double *__restrict__ partial) {
   __shared__ MultiLdsD<K, TQ> L;
   __shared__ int slot[1];
+  const PartMap pm{0, 1, kBlock, K};
   int s;
-  int64_t I, J;
-  while (next_multi_item(b, slot, s, I, J)) {
+  int64_t Lp, I, J;
+  while (next_multi_item(b, slot, s, Lp, I, J)) {
     const int64_t s0 = b.offs[s];
     multi_tile_pair<K, TQ, WALL>(multi_args_of(b, s), offset_geom(g, s0), src + s0, k,
-                                 partial + b.base[s], I, J, L);
+                                 partial + b.base[s], pm, Lp, I, J, L);
   }
 }
 
-template <int K>
+template <int K, typename Part>
 __global__ void reduce_multi_batched(MultiBatchArgs b, const int *__restrict__ sys_of,
-                                     OutPtrs<K> out, const double *__restrict__ partial,
+                                     OutPtrs<K> out, const Part *__restrict__ partial,
                                      const double *__restrict__ h, double scale) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t per = 3 * b.n;
@@ -502,25 +509,17 @@ __global__ void reduce_multi_batched(MultiBatchArgs b, const int *__restrict__ s
   const int s = sys_of[r];
   const SymArgs a = multi_args_of(b, s);
   const int64_t local = r - b.offs[s];
-  const double *p0 = partial + b.base[s] + multi_slot(a, v, local / kBlock, 0, d, local % kBlock);
-  const int64_t stride = 3 * kBlock;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t P = 0;
-  for (; P + 4 <= a.nt; P += 4) {
-    s0 += p0[P * stride];
-    s1 += p0[(P + 1) * stride];
-    s2 += p0[(P + 2) * stride];
-    s3 += p0[(P + 3) * stride];
-  }
-  for (; P < a.nt; ++P) s0 += p0[P * stride];
-  dst[3 * r + d] = scale * h[r] * ((s0 + s1) + (s2 + s3));
+  const PartMap pm{0, 1, kBlock, K};
+  dst[3 * r + d] = scale * h[r] *
+                   chunk_row_sum(partial + b.base[s], pm, a.nt, a.nt * (a.nt + 1) / 2,
+                                 local / kBlock, local % kBlock, v, d);
 }
 
-size_t multi_batch_partial_bytes(int K, const Batch &bt) {
+size_t multi_batch_partial_bytes(int K, const Batch &bt, size_t esz) {
   size_t bytes = 0;
   for (int s = 0; s < bt.nsys; ++s) {
     const int64_t nt = (bt.host_offs[s + 1] - bt.host_offs[s] + kBlock - 1) / kBlock;
-    bytes += size_t(K) * size_t(nt) * size_t(nt) * 3 * size_t(kBlock) * sizeof(double);
+    bytes += size_t(part_elems(nt * (nt + 1) / 2, 1, K, kBlock)) * esz;
   }
   return bytes;
 }
@@ -537,13 +536,6 @@ int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, c
   std::vector<int> ids;
   for (int v = 0; v < nvec; ++v)
     if (!done || !done[v]) ids.push_back(v);
-  if (!multi_fits(kMulti, n)) {
-    // too large for one launch: one single-vector product per vector
-    for (int v : ids)
-      RPB_TRY(matvec_packed(ctx, p, g, force + size_t(v) * 3 * n, nullptr, 0, n,
-                            vel + size_t(v) * 3 * n, stream));
-    return RPB_OK;
-  }
   for (size_t g0 = 0; g0 < ids.size(); g0 += kMulti) {
     SrcPtrs<kMulti> in;
     OutPtrs<kMulti> out;
@@ -558,9 +550,7 @@ int matvec_multi(rpb_ctx *ctx, const rpb_params *p, const Packed &g, int nvec, c
   return RPB_OK;
 }
 
-bool matvec_first_supported(const rpb_params *p, int64_t n) {
-  return p->lx <= 0.0 && n > 0 && multi_fits(3, n);
-}
+bool matvec_first_supported(const rpb_params *p, int64_t n) { return p->lx <= 0.0 && n > 0; }
 
 int matvec_first(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,
                  const double *torque, const double *w, const double *w3, double *u_force,
@@ -581,7 +571,9 @@ int matvec_first(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doubl
 
 bool matvec_first_batched_supported(const rpb_params *p, const Batch &bt) {
   return p->lx <= 0.0 && bt.n > 0 && bt.nsys > 0 &&
-         multi_batch_partial_bytes(2, bt) <= kMaxMultiPartialBytes;
+         multi_batch_partial_bytes(2, bt, p->precision == RPB_FP64 ? sizeof(double)
+                                                                   : sizeof(float)) <=
+             kMaxMultiBatchBytes;
 }
 
 int matvec_first_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, const Packed &g,
@@ -596,10 +588,10 @@ int matvec_first_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, con
   const size_t meta_bytes = size_t(2 * (bt.nsys + 1)) * sizeof(int64_t);
   int64_t *meta = static_cast<int64_t *>(workspace(ctx, WS_MBATCH, meta_bytes, &st));
   if (!meta) return st;
-  double *part = static_cast<double *>(
-      workspace(ctx, WS_PART, std::max<size_t>(8, multi_batch_partial_bytes(K, bt)), &st));
-  if (!part) return st;
   const size_t esz = f64 ? sizeof(double) : sizeof(float);
+  void *part = workspace(ctx, WS_PART, std::max<size_t>(8, multi_batch_partial_bytes(K, bt, esz)),
+                         &st);
+  if (!part) return st;
   const bool tq = torque != nullptr;
   void *src = workspace(ctx, WS_SRC, size_t(3 * K + 3) * size_t(n) * esz, &st);
   if (!src) return st;
@@ -629,21 +621,23 @@ int matvec_first_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, con
     if (f64) {
       const auto k = make_pair_consts<double>();
       const auto *s = static_cast<const double *>(src);
+      auto *pt = static_cast<double *>(part);
       if (wall)
         pair_kernel_f64_multi_batched<K, kTQ, true><<<grid, kBlock, 0, stream>>>(args, geom_d(g),
-                                                                                 s, k, part);
+                                                                                 s, k, pt);
       else
         pair_kernel_f64_multi_batched<K, kTQ, false><<<grid, kBlock, 0, stream>>>(
-            args, geom_d(g), s, k, part);
+            args, geom_d(g), s, k, pt);
     } else {
       const auto k = make_pair_consts<float>();
       const auto *s = static_cast<const float *>(src);
+      auto *pt = static_cast<float *>(part);
       if (wall)
         pair_kernel_mixed_multi_batched<K, kTQ, true><<<grid, kBlock, 0, stream>>>(
-            args, geom_f(g), s, k, part);
+            args, geom_f(g), s, k, pt);
       else
         pair_kernel_mixed_multi_batched<K, kTQ, false><<<grid, kBlock, 0, stream>>>(
-            args, geom_f(g), s, k, part);
+            args, geom_f(g), s, k, pt);
     }
   };
   if (tq)
@@ -659,8 +653,12 @@ int matvec_first_batched(rpb_ctx *ctx, const rpb_params *p, const Batch &bt, con
   RPB_TRY(timing_end(ctx, stream, t0, K * pairs, 8 + (f64 ? 0 : 2)));
   const double scale = 1.0 / (8.0 * M_PI * p->eta * p->a);
   const OutPtrs<K> out{{u_force, u_w}};
-  reduce_multi_batched<K><<<blocks_for(int64_t(K) * 3 * n, 256), 256, 0, stream>>>(
-      args, bt.sys_of, out, part, h, scale);
+  if (f64)
+    reduce_multi_batched<K, double><<<blocks_for(int64_t(K) * 3 * n, 256), 256, 0, stream>>>(
+        args, bt.sys_of, out, static_cast<const double *>(part), h, scale);
+  else
+    reduce_multi_batched<K, float><<<blocks_for(int64_t(K) * 3 * n, 256), 256, 0, stream>>>(
+        args, bt.sys_of, out, static_cast<const float *>(part), h, scale);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }

@@ -74,29 +74,103 @@ __device__ __forceinline__ double wave_rol1(double v) {
                               static_cast<long long>(static_cast<unsigned>(lo)));
 }
 
-// slot (T, P, h) of the symmetric partial array:
-// partial[(((T * nt + P) * nsplit + h) * 3 + comp) * ts + local].  Tile T's rows get the sums
-// over source part h of tile P in slot (T, P, h) when T <= P, and the column sums of the
-// tile pair (P, T) in slot (T, P, 0) when T > P.
-__device__ __forceinline__ int64_t sym_slot(const SymArgs &a, int64_t T, int64_t P, int comp,
-                                            int64_t local, int64_t h = 0) {
-  return (((T * a.nt + P) * a.nsplit + h) * 3 + comp) * a.ts + local;
-}
-
 constexpr int kWaves = kBlock / 64;
 
-// Tile pair (I, J), I <= J, of linear index L = I nt - I (I - 1) / 2 + (J - I): row I of the
-// upper triangle holds nt - I pairs.  Workgroups walk the triangle row by row.
+// Tile pairs (I, J), I <= J, of the upper triangle in row-major order: pair (I, J) has linear
+// index L = tri_start(I) + J - I, row I holding nt - I pairs.
+__host__ __device__ __forceinline__ int64_t tri_start(int64_t r, int64_t nt) {
+  return r * nt - r * (r - 1) / 2;
+}
+
+// (I, J) of linear index L.  Workgroups walk the triangle row by row.
 __device__ __forceinline__ void tri_decode(int64_t L, int64_t nt, int64_t &I, int64_t &J) {
   const double b = double(2 * nt + 1);
   int64_t i = int64_t((b - sqrt(b * b - 8.0 * double(L))) * 0.5);
-  auto start = [nt](int64_t r) { return r * nt - r * (r - 1) / 2; };
   if (i < 0) i = 0;
   if (i > nt - 1) i = nt - 1;
-  while (i > 0 && start(i) > L) --i;
-  while (i + 1 < nt && start(i + 1) <= L) ++i;
+  while (i > 0 && tri_start(i, nt) > L) --i;
+  while (i + 1 < nt && tri_start(i + 1, nt) <= L) ++i;
   I = i;
-  J = i + (L - start(i));
+  J = i + (L - tri_start(i, nt));
+}
+
+// Partial sums of the symmetric tile-pair kernels.  One launch covers the tile pairs of linear
+// index L in [L0, L1) (a chunk of the triangle; the whole triangle when it fits the workspace
+// limit).  Pair q = L - L0 owns nsplit + 1 slots: slot q (nsplit + 1) + h holds the sums for
+// the rows of tile I over source part h of tile J (h < nsplit), slot q (nsplit + 1) + nsplit
+// the sums for the rows of tile J over tile I (I < J only; each part writes its own rows of
+// it).  A slot holds V vectors x 3 components x ts rows.
+struct PartMap {
+  int64_t L0;       // first pair of the chunk
+  int64_t nsplit;   // source parts per tile pair
+  int64_t ts;       // rows per tile
+  int V;            // vectors per slot
+};
+
+__host__ __device__ __forceinline__ int64_t part_elem(const PartMap &m, int64_t L, int64_t sub,
+                                                      int v, int comp, int64_t local) {
+  return ((((L - m.L0) * (m.nsplit + 1) + sub) * m.V + v) * 3 + comp) * m.ts + local;
+}
+
+// Elements of the partial buffer of pairs [L0, L1).
+__host__ __device__ __forceinline__ int64_t part_elems(int64_t pairs, int64_t nsplit, int V,
+                                                       int64_t ts) {
+  return pairs * (nsplit + 1) * V * 3 * ts;
+}
+
+// Sum, in a fixed order, of every partial of row `local` of tile T (component c, vector v)
+// that the pairs [L0, L1) wrote: first the column slots of pairs (I, T), I < T, in increasing I,
+// then the row slots of pairs (T, J), J >= T, in increasing J (parts in increasing h).  Four
+// running sums keep several loads in flight.  L(I, T) increases with I, so the pairs (I, T) of
+// the chunk form one range of I, found by bisection.
+template <typename Part>
+__device__ __forceinline__ double chunk_row_sum(const Part *__restrict__ p, const PartMap &m,
+                                                int64_t nt, int64_t L1, int64_t T, int64_t local,
+                                                int v, int c) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int k = 0;
+  auto Lcol = [&](int64_t I) { return tri_start(I, nt) + T - I; };
+  int64_t lo = 0, hi = T;
+  while (lo < hi) {   // first I with L(I, T) >= L0
+    const int64_t mid = (lo + hi) / 2;
+    if (Lcol(mid) >= m.L0)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int64_t i0 = lo;
+  hi = T;
+  while (lo < hi) {   // first I with L(I, T) >= L1
+    const int64_t mid = (lo + hi) / 2;
+    if (Lcol(mid) >= L1)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  for (int64_t I = i0; I < lo; ++I)
+    s[k++ & 3] += double(p[part_elem(m, Lcol(I), m.nsplit, v, c, local)]);
+  const int64_t st = tri_start(T, nt);
+  const int64_t j0 = T + (m.L0 > st ? m.L0 - st : 0);
+  const int64_t j1 = T + (L1 - st < nt - T ? (L1 > st ? L1 - st : 0) : nt - T);
+  for (int64_t J = j0; J < j1; ++J) {
+    const int64_t L = st + J - T;
+    double x = double(p[part_elem(m, L, 0, v, c, local)]);
+    for (int64_t h = 1; h < m.nsplit; ++h) x += double(p[part_elem(m, L, h, v, c, local)]);
+    s[k++ & 3] += x;
+  }
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// Chunks of the triangle: at most `limit` bytes of partials per launch (the context's chunk
+// limit, kMaxChunkBytes unless overridden), equal numbers of pairs per chunk.
+inline int64_t chunk_pairs(int64_t pairs, int64_t nsplit, int V, int64_t ts, size_t esz,
+                           size_t limit) {
+  const size_t per = size_t(part_elems(1, nsplit, V, ts)) * esz;
+  int64_t fit = int64_t(limit / per);
+  if (fit < 1) fit = 1;
+  if (fit > 0x7fffffffll / nsplit) fit = 0x7fffffffll / nsplit;
+  const int64_t nchunks = (pairs + fit - 1) / fit;
+  return (pairs + nchunks - 1) / nchunks;   // equal chunks
 }
 
 inline unsigned blocks_for(int64_t n, int threads) {

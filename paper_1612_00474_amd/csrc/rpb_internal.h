@@ -44,6 +44,9 @@ enum Slot {
   WS_NSLOTS
 };
 
+// Default limit of the partial sums of one launch of the symmetric tile-pair kernels.
+constexpr size_t kMaxChunkBytes = size_t(512) << 20;
+
 // Layout of the WS_SMALL slot.
 constexpr size_t kSmallBytes = 1 << 16;
 constexpr size_t kSmallWorkCounter = 8192;          // int: work counter of persistent kernels
@@ -76,6 +79,9 @@ struct Tuning {
 
 struct rpb_ctx {
   int device = 0;
+  // partials of one chunk of the symmetric tile-pair kernels (the triangle of tile pairs is
+  // walked in chunks of at most this many bytes); RPB_CHUNK_KIB overrides it
+  size_t chunk_bytes = rpb::kMaxChunkBytes;
   rpb::Tuning tune;
   std::map<std::tuple<int, int, int>, rpb::Tuning> tune_cache;   // (precision, batched, log2 n)
   std::string err;
@@ -218,7 +224,7 @@ struct Batch {
   bool symmetric = false;        // items are (system, I, J, part) of the symmetric kernel
   int nsplit = 1;                // source parts per symmetric tile pair
   int64_t *part_base = nullptr;  // device, nsys entries: each system's first partial slot
-  int64_t part_elems = 0;        // partial doubles of the symmetric layout
+  int64_t part_elems = 0;        // partial elements of the symmetric layout (float32 in mixed precision)
 };
 
 int check_offsets(rpb_ctx *ctx, int32_t nsys, const int64_t *offs);

@@ -75,7 +75,7 @@ int rpb_set_tuning(rpb_ctx *ctx, const rpb_tuning *t) {
   const rpb_shape *src[2] = {&t->fp64, &t->mixed};
   for (int q = 0; q < 2; ++q) {
     const rpb_shape &v = *src[q];
-    if ((v.tpt != 1 && v.tpt != 2) || v.target_wgs < 1 || v.target_wgs > (1 << 20) ||
+    if ((v.tpt != 1 && v.tpt != 2 && v.tpt != 4) || v.target_wgs < 1 || v.target_wgs > (1 << 20) ||
         v.batch_chunk < 256 || v.batch_chunk % 256 != 0 || v.batch_chunk > (1 << 20) ||
         v.batch_wgs < 1 || v.batch_wgs > (1 << 20) || (v.symmetric != 0 && v.symmetric != 1) ||
         (v.batch_tpt != 1 && v.batch_tpt != 2) ||
@@ -143,6 +143,12 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
           cands.push_back(c);
         }
       }
+    }
+    if (!batched) {   // 4 targets per lane: tiles of 1,024 spheres, symmetric kernel only
+      Shape c = base;
+      c.tpt = 4;
+      c.symmetric = 1;
+      cands.push_back(c);
     }
     int rc = RPB_OK;
     for (const Shape &sh : cands) {

@@ -175,7 +175,7 @@ def test_error_paths(ctx, c1):
 
 
 @pytest.mark.parametrize("torque", [False, True])
-@pytest.mark.parametrize("tpt", [1, 2])
+@pytest.mark.parametrize("tpt", [1, 2, 4])
 @pytest.mark.parametrize("n", [2, 63, 64, 65, 300, 513, 1100])
 def test_symmetric_kernel_matches_oracle_and_ordered(ctx, n, tpt, torque):
     # whole-system products take the symmetric tile-pair kernel (each unordered pair evaluated
