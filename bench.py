@@ -13,9 +13,9 @@ The ``roofline`` object prices the dominant kernel (the float32 pair kernel) aga
 float32 vector-ALU peak with the operation count of the algorithm it runs (one evaluation
 per unordered pair, applied in both directions); the logical count (every ordered pair
 charged in full) and the arithmetic the hardware counters saw issued sit beside it.
-``batched`` times the 64-system mixed batch (one hipGraph launch per step) and ``fp64_sheet16k``
-the float64 step at N = 16,384.  ``cpu_baseline`` times the FP64 CPU oracle over the host's
-cores on bounded samples.
+``batched`` times the 64-system mixed batch (one hipGraph launch per step), ``fp64_sheet16k``
+and ``fp64_sheet256`` the float64 steps at N = 16,384 and N = 256 (eager and graph-captured).
+``cpu_baseline`` times the FP64 CPU oracle over the host's cores on bounded samples.
 """
 from __future__ import annotations
 
@@ -166,6 +166,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="headline workload only (no batched / float64 sub-benchmarks)")
     ap.add_argument("--cpu-rows", type=int, default=24, help="C3 sample rows per CPU worker")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="time the steps only (no product, multi-vector or periodic rates): "
+                         "for kernel traces of the step")
     return ap.parse_args()
 
 
@@ -388,11 +391,37 @@ def run_batched(ctx, w, steps, warmup):
     }
 
 
-def run_fp64_sheet(ctx_cls, steps, warmup):
-    """Float64 steps of the 16,384-sphere sheet (its own context and tuned shape)."""
+def run_graph_steps(ctx, w, pos0, steps, warmup, budget):
+    """The same single-system step captured in a hipGraph (the batched step with one system:
+    device-side Lanczos stop, `budget` iterations enqueued, no host synchronisation)."""
+    import numpy as np
+    import torch
+    kw = dict(dt=w.dt, delta=w.delta, lanczos_tol=w.lanczos_tol, lanczos_max_iter=budget,
+              rfd_precision="fp64", f_grav_z=w.f_grav_z, torque=w.torque,
+              steric_u0=w.steric_u0, steric_b=w.steric_b, seed=0, precision=w.precision)
+    P = pos0.clone()
+    U = torch.zeros_like(P)
+    graph = ctx.step_graph(P, U, np.array([0, w.n], dtype=np.int64), 0, False, **kw)
+    for _ in range(warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    _, iters, _, _ = graph.status()
+    graph.close()
+    return {"steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+            "lanczos_budget": budget, "lanczos_iters_last_step": int(iters[0])}
+
+
+def run_fp64_sheet(ctx_cls, name, steps, warmup, budget):
+    """Float64 steps of one sheet (its own context and tuned shape): eager single-system steps
+    (the host reads each Lanczos status) and the graph-captured step."""
     import torch
     from paper_1612_00474_amd import workloads as wl
-    w = wl.WORKLOADS["sheet16k_fp64"]
+    w = wl.WORKLOADS[name]
     inp = wl.make_inputs(w, 0)
     pos0 = torch.as_tensor(inp["pos"]).cuda()
     ctx = ctx_cls(0, a=w.a, eta=w.eta, kT=w.kT)
@@ -400,13 +429,15 @@ def run_fp64_sheet(ctx_cls, steps, warmup):
     elapsed, iters, clocks = run_single_steps(ctx, w, pos0, steps, warmup, "fp64")
     kinds = read_kinds(ctx, {"fp64": bool(shape["symmetric"]), "mixed": True}, [w.n])
     ctx.timing(False)
+    graph = run_graph_steps(ctx, w, pos0, steps, warmup, budget)
     ctx.close()
     dom = kinds.get("fp64_force")
     products = sum(1 + m + 2 for m in iters)
-    return {"workload": w.name, "n": w.n, "precision": "fp64", "steps": steps, "warmup": warmup,
+    return {"workload": w.name, "n": w.n, "precision": "fp64", "lanczos_tol": w.lanczos_tol,
+            "steps": steps, "warmup": warmup,
             "steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
             "pairs_per_s": products * float(w.n) ** 2 / elapsed, "lanczos_iters": iters,
-            "launch_shape": shape, "pair_kernels": kinds, "gpu_clock": clocks,
+            "graph": graph, "launch_shape": shape, "pair_kernels": kinds, "gpu_clock": clocks,
             "roofline": None if dom is None else {
                 "bound": "alu", "achieved": dom["tflops_alg"], "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": dom["tflops_alg"] / PEAK_FP64_TFLOPS,
@@ -447,6 +478,15 @@ def main():
     # ---- launch shapes from the tuner (timed on this configuration, cached per size) -------
     shapes = {prec_: ctx.autotune(pos0, None, prec_)[0] for prec_ in ("mixed", "fp64")}
     sym = {p_: bool(s["symmetric"]) for p_, s in shapes.items()}
+
+    if args.steps_only:
+        elapsed, timed_iters, clock = run_single_steps(ctx, w, pos0, args.steps, args.warmup, prec)
+        ctx.close()
+        print(json.dumps({"workload": w.name, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": 1e3 * elapsed / args.steps,
+                          "steps_per_s": args.steps / elapsed, "lanczos_iters": timed_iters,
+                          "launch_shapes": shapes, "gpu_clock": clock}))
+        return
 
     # ---- kernel-only product throughput, mixed and float64 (pair kernel, HIP events) ----
     def kernel_rate(precision, reps=3):
@@ -590,7 +630,9 @@ def main():
         b.pop("_pairs_step")
         b.pop("sizes")
         line["batched"] = b
-        line["fp64_sheet16k"] = run_fp64_sheet(Context, max(args.steps, 10), args.warmup)
+        line["fp64_sheet16k"] = run_fp64_sheet(Context, "sheet16k_fp64", max(args.steps, 10),
+                                               args.warmup, 16)
+        line["fp64_sheet256"] = run_fp64_sheet(Context, "sheet256_rsa", 50, 5, 32)
     line["cpu_baseline"] = cpu
     print(json.dumps(line))
 

@@ -284,8 +284,9 @@ struct PairArgs {
 template <bool TORQUE, int TPT, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g,
                                                           const double *__restrict__ src,
-                                                          PairConsts<double> k,
+                                                          PairConsts<double> k_arg,
                                                           double *__restrict__ partial) {
+  const PairConsts<double> k = vgpr_consts(k_arg);
   if (args.skip && *args.skip) return;
   __shared__ LdsD<TORQUE> L;
   TargetsD<TPT> T;
@@ -301,8 +302,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64(PairArgs args, GeomD g
 template <bool TORQUE, int TPT, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed(PairArgs args, GeomF g,
                                                             const float *__restrict__ src,
-                                                            PairConsts<float> k,
+                                                            PairConsts<float> k_arg,
                                                             double *__restrict__ partial) {
+  const PairConsts<float> k = vgpr_consts(k_arg);
   if (args.skip && *args.skip) return;
   __shared__ LdsF<TORQUE> L;
   TargetsF<TPT> T;
@@ -624,8 +626,9 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
 template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, PartMap pm, GeomF g,
                                                                 const float *__restrict__ src,
-                                                                PairConsts<float> k,
+                                                                PairConsts<float> k_arg,
                                                                 float *__restrict__ partial) {
+  const PairConsts<float> k = vgpr_consts(k_arg);
   if (a.skip && *a.skip) return;
   __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
@@ -639,8 +642,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym(SymArgs a, PartM
 template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, PartMap pm, GeomD g,
                                                               const double *__restrict__ src,
-                                                              PairConsts<double> k,
+                                                              PairConsts<double> k_arg,
                                                               double *__restrict__ partial) {
+  const PairConsts<double> k = vgpr_consts(k_arg);
   if (a.skip && *a.skip) return;
   __shared__ LdsD<TORQUE> L;
   __shared__ double col[kWaves][kBlock][3];
@@ -694,8 +698,9 @@ __device__ __forceinline__ int next_item(const BatchArgs &b, int *slot) {
 template <bool TORQUE, int TPT, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_batched(BatchArgs b, GeomD g,
                                                                   const double *__restrict__ src,
-                                                                  PairConsts<double> k,
+                                                                  PairConsts<double> k_arg,
                                                                   double *__restrict__ partial) {
+  const PairConsts<double> k = vgpr_consts(k_arg);
   __shared__ LdsD<TORQUE> L;
   __shared__ int slot[1];
   if (b.all_done && *b.all_done) return;
@@ -715,8 +720,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_batched(BatchArgs b, G
 template <bool TORQUE, int TPT, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_batched(BatchArgs b, GeomF g,
                                                                     const float *__restrict__ src,
-                                                                    PairConsts<float> k,
+                                                                    PairConsts<float> k_arg,
                                                                     double *__restrict__ partial) {
+  const PairConsts<float> k = vgpr_consts(k_arg);
   __shared__ LdsF<TORQUE> L;
   __shared__ int slot[1];
   if (b.all_done && *b.all_done) return;
@@ -782,8 +788,9 @@ __device__ __forceinline__ int next_sym_item(const SymBatchArgs &b, int *slot) {
 
 template <int TPT, bool TORQUE, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
-    SymBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k,
+    SymBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k_arg,
     float *__restrict__ partial) {
+  const PairConsts<float> k = vgpr_consts(k_arg);
   __shared__ LdsF<TORQUE> L;
   __shared__ float col[kWaves][kBlock][3];
   __shared__ int slot[1];
@@ -803,8 +810,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_sym_batched(
 
 template <int TPT, bool TORQUE, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym_batched(
-    SymBatchArgs b, GeomD g, const double *__restrict__ src, PairConsts<double> k,
+    SymBatchArgs b, GeomD g, const double *__restrict__ src, PairConsts<double> k_arg,
     double *__restrict__ partial) {
+  const PairConsts<double> k = vgpr_consts(k_arg);
   __shared__ LdsD<TORQUE> L;
   __shared__ double col[kWaves][kBlock][3];
   __shared__ int slot[1];
@@ -1115,12 +1123,17 @@ int block_diag_scale(rpb_ctx *ctx, const rpb_params *p, const Packed &g, double 
 }
 
 // Small systems have few tile pairs: their sources are split into parts (each of at least
-// 128 spheres, one workgroup per part) until the grid has about kSplitWorkgroups workgroups.
+// 128 spheres, one workgroup per part) until the grid has about kSplitWorkgroups workgroups;
+// systems of one or a few tiles go on splitting, down to parts of 8 sources, until there are
+// at least kMinWorkgroups (a 256-sphere system is one tile pair: 2 to 4 workgroups otherwise).
 constexpr int64_t kSplitWorkgroups = 4096;
+constexpr int64_t kMinWorkgroups = 64;
 inline int64_t sym_nsplit(int64_t n, int64_t ts) {
   const int64_t nt = (n + ts - 1) / ts;
+  const int64_t pairs = nt * (nt + 1) / 2;
   int64_t q = 1;
-  while (nt * (nt + 1) / 2 * q < kSplitWorkgroups && ts / (2 * q) >= 128) q *= 2;
+  while (pairs * q < kSplitWorkgroups && ts / (2 * q) >= 128) q *= 2;
+  while (pairs * q < kMinWorkgroups && ts / (2 * q) >= 8) q *= 2;
   return q;
 }
 
@@ -1294,6 +1307,7 @@ int prepare_batch(rpb_ctx *ctx, int32_t nsys, const int64_t *offs, int precision
       pairs += nt * (nt + 1) / 2;
     }
     while (pairs * b->nsplit < 4 * int64_t(b->wgs) && per / (2 * b->nsplit) >= 128) b->nsplit *= 2;
+    while (pairs * b->nsplit < kMinWorkgroups && per / (2 * b->nsplit) >= 8) b->nsplit *= 2;
     const size_t esz = precision == RPB_FP64 ? sizeof(double) : sizeof(float);
     size_t bytes = 0;
     for (int s = 0; s < nsys; ++s) {

@@ -161,7 +161,7 @@ __device__ __forceinline__ void multi_step(const Lds &L, int j, bool valid, cons
                           own[3 * v + 2], acc[3 * v], acc[3 * v + 1], acc[3 * v + 2], cs[3 * v],
                           cs[3 * v + 1], cs[3 * v + 2]);
   if (TQ)
-    sym_apply_torque<Real, WALL>(c, t.z, f + 3 * K, own + 3 * K, acc[0], acc[1], acc[2], cs[0],
+    sym_apply_torque<Real, WALL>(c, k, t.z, f + 3 * K, own + 3 * K, acc[0], acc[1], acc[2], cs[0],
                                  cs[1], cs[2]);
 }
 
@@ -206,7 +206,7 @@ __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
         const Real tq[3] = {L.f[3 * K][j], L.f[3 * K + 1][j], L.f[3 * K + 2][j]};
         const Real none[3] = {Real(0), Real(0), Real(0)};
         Real px = Real(0), py = Real(0), pz = Real(0);
-        sym_apply_torque<Real, WALL>(c, t.z, tq, none, acc[0], acc[1], acc[2], px, py, pz);
+        sym_apply_torque<Real, WALL>(c, k, t.z, tq, none, acc[0], acc[1], acc[2], px, py, pz);
       }
     }
   } else {
@@ -254,8 +254,9 @@ __device__ __forceinline__ void multi_tile_pair(const SymArgs &a, const Geom &g,
 template <int K, bool TQ, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi(SymArgs a, PartMap pm, GeomF g,
                                                                   const float *__restrict__ src,
-                                                                  PairConsts<float> k,
+                                                                  PairConsts<float> k_arg,
                                                                   float *__restrict__ partial) {
+  const PairConsts<float> k = vgpr_consts(k_arg);
   __shared__ MultiLdsF<K, TQ> L;
   int64_t I, J;
   const int64_t Lp = pm.L0 + int64_t(blockIdx.x);
@@ -266,8 +267,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi(SymArgs a, Par
 template <int K, bool TQ, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_multi(SymArgs a, PartMap pm, GeomD g,
                                                                 const double *__restrict__ src,
-                                                                PairConsts<double> k,
+                                                                PairConsts<double> k_arg,
                                                                 double *__restrict__ partial) {
+  const PairConsts<double> k = vgpr_consts(k_arg);
   __shared__ MultiLdsD<K, TQ> L;
   int64_t I, J;
   const int64_t Lp = pm.L0 + int64_t(blockIdx.x);
@@ -463,8 +465,9 @@ __device__ __forceinline__ SymArgs multi_args_of(const MultiBatchArgs &b, int s)
 
 template <int K, bool TQ, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi_batched(
-    MultiBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k,
+    MultiBatchArgs b, GeomF g, const float *__restrict__ src, PairConsts<float> k_arg,
     float *__restrict__ partial) {
+  const PairConsts<float> k = vgpr_consts(k_arg);
   __shared__ MultiLdsF<K, TQ> L;
   __shared__ int slot[1];
   const PartMap pm{0, 1, kBlock, K};
@@ -479,8 +482,9 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_mixed_multi_batched(
 
 template <int K, bool TQ, bool WALL>
 __global__ __launch_bounds__(kBlock) void pair_kernel_f64_multi_batched(
-    MultiBatchArgs b, GeomD g, const double *__restrict__ src, PairConsts<double> k,
+    MultiBatchArgs b, GeomD g, const double *__restrict__ src, PairConsts<double> k_arg,
     double *__restrict__ partial) {
+  const PairConsts<double> k = vgpr_consts(k_arg);
   __shared__ MultiLdsD<K, TQ> L;
   __shared__ int slot[1];
   const PartMap pm{0, 1, kBlock, K};

@@ -120,7 +120,8 @@ __host__ __device__ __forceinline__ int64_t part_elems(int64_t pairs, int64_t ns
 
 // Sum, in a fixed order, of every partial of row `local` of tile T (component c, vector v)
 // that the pairs [L0, L1) wrote: first the column slots of pairs (I, T), I < T, in increasing I,
-// then the row slots of pairs (T, J), J >= T, in increasing J (parts in increasing h).  Four
+// then the row slots of pairs (T, J), J >= T, in increasing J (the parts of each pair summed
+// in four interleaved sums, h mod 4, combined in a fixed order).  Four
 // running sums keep several loads in flight.  L(I, T) increases with I, so the pairs (I, T) of
 // the chunk form one range of I, found by bisection.
 template <typename Part>
@@ -154,9 +155,11 @@ __device__ __forceinline__ double chunk_row_sum(const Part *__restrict__ p, cons
   const int64_t j1 = T + (L1 - st < nt - T ? (L1 > st ? L1 - st : 0) : nt - T);
   for (int64_t J = j0; J < j1; ++J) {
     const int64_t L = st + J - T;
-    double x = double(p[part_elem(m, L, 0, v, c, local)]);
-    for (int64_t h = 1; h < m.nsplit; ++h) x += double(p[part_elem(m, L, h, v, c, local)]);
-    s[k++ & 3] += x;
+    // the parts of the pair in four running sums (h mod 4), so that many parts (small systems
+    // split into up to 128) keep several loads in flight
+    double x[4] = {double(p[part_elem(m, L, 0, v, c, local)]), 0.0, 0.0, 0.0};
+    for (int64_t h = 1; h < m.nsplit; ++h) x[h & 3] += double(p[part_elem(m, L, h, v, c, local)]);
+    s[k++ & 3] += (x[0] + x[1]) + (x[2] + x[3]);
   }
   return (s[0] + s[1]) + (s[2] + s[3]);
 }

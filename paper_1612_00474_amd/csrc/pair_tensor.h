@@ -51,10 +51,15 @@ namespace rpb {
 // Lengths are in units of the sphere radius a (the packed geometry is divided by a), so the
 // tensors take a = 1: M(r; a) = M(r/a; 1)/a and M_C(r; a) = M_C(r/a; 1)/a^2, and the caller
 // applies 1/(8 pi eta a) per target and divides the torques by a.
+// The closed forms' non-trivial constants travel with the box lengths: the kernels copy them
+// into vector registers once (vgpr_consts), because a float32 vector operation that reads a
+// scalar register or a 32-bit literal issues at about half the rate of one that reads vector
+// registers only (measured on gfx950), and the pair code is bound by that issue rate.
 template <typename Real>
 struct PairConsts {
   Real lx, ly;      // pseudo-periodic box in units of a (used by the PERIODIC kernels only)
   Real ilx, ily;    // 1/lx, 1/ly
+  Real c2_3, c8_3, c10_3, c20_3, c70_3, c5, c6, c10, c12, c20;   // 2/3, 8/3, ..., 20
 };
 
 // Overlap branch (r < 2, units of a): cI = 4/3 - (3/8) r, cRR = (1/8)/r, cT = 1/2 - (3/16) r.
@@ -72,7 +77,45 @@ __host__ __device__ inline PairConsts<Real> make_pair_consts(double lx = 0.0, do
   k.ly = Real(ly);
   k.ilx = lx > 0.0 ? Real(1.0 / lx) : Real(0);
   k.ily = ly > 0.0 ? Real(1.0 / ly) : Real(0);
+  k.c2_3 = Real(2.0 / 3.0);
+  k.c8_3 = Real(8.0 / 3.0);
+  k.c10_3 = Real(10.0 / 3.0);
+  k.c20_3 = Real(20.0 / 3.0);
+  k.c70_3 = Real(70.0 / 3.0);
+  k.c5 = Real(5);
+  k.c6 = Real(6);
+  k.c10 = Real(10);
+  k.c12 = Real(12);
+  k.c20 = Real(20);
   return k;
+}
+
+// A zero the compiler cannot see through, held in a vector register.
+__device__ __forceinline__ float opaque_zero(float) {
+  float z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+__device__ __forceinline__ double opaque_zero(double) { return double(opaque_zero(0.0f)); }
+
+// The constants of `k` in vector registers (each plus an opaque zero: the same values, but the
+// pair code's multiplications by them then read vector registers only).  Called once per
+// kernel, outside the pair loops.
+template <typename Real>
+__device__ __forceinline__ PairConsts<Real> vgpr_consts(const PairConsts<Real> &k) {
+  const Real z = opaque_zero(Real(0));
+  PairConsts<Real> v = k;
+  v.c2_3 = k.c2_3 + z;
+  v.c8_3 = k.c8_3 + z;
+  v.c10_3 = k.c10_3 + z;
+  v.c20_3 = k.c20_3 + z;
+  v.c70_3 = k.c70_3 + z;
+  v.c5 = k.c5 + z;
+  v.c6 = k.c6 + z;
+  v.c10 = k.c10 + z;
+  v.c12 = k.c12 + z;
+  v.c20 = k.c20 + z;
+  return v;
 }
 
 // 1/sqrt(x) for x > 0.
@@ -107,7 +150,7 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
     const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
     const Real s = ir2;
-    cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
+    cI = invr * (Real(1) + k.c2_3 * s);
     cT = invr * ir2;
     cRR = cT * (Real(1) - Real(2) * s);
   } else {
@@ -115,7 +158,7 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
     if (r2 >= Real(kFourA2)) {
       const Real ir2 = invr * invr;
       const Real s = ir2;
-      cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
+      cI = invr * (Real(1) + k.c2_3 * s);
       cT = invr * ir2;
       cRR = cT * (Real(1) - Real(2) * s);
     } else {
@@ -151,15 +194,15 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
   const Real ez2 = ez * ez;
   const Real hme = hh - ez;
   const Real t = hh * hme;
-  const Real p = X * (Real(2) - Real(10.0 / 3.0) * X);
-  const Real q = Real(20.0 / 3.0) * Y;
+  const Real p = X * (Real(2) - k.c10_3 * X);
+  const Real q = k.c20_3 * Y;
   const Real hh2x = Real(2) * hh;
-  const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
-  const Real m1 = ez2 * (q - Real(5) * p);   // shared by c2 and c3 (10p - 2q = -2(q - 5p))
-  const Real c2 = m1 + (Real(-6) * t + (p - Real(1)));
-  const Real c3 = ez * ((q - Real(2) * p) + Real(-2) * m1) + (Real(12) * (ez * t) + hh2x);
+  const Real c1 = ez2 * p + (Real(2) * t + (-k.c2_3 * (X - Y) - Real(1)));
+  const Real m1 = ez2 * (q - k.c5 * p);   // shared by c2 and c3 (10p - 2q = -2(q - 5p))
+  const Real c2 = m1 + (-k.c6 * t + (p - Real(1)));
+  const Real c3 = ez * ((q - Real(2) * p) + Real(-2) * m1) + (k.c12 * (ez * t) + hh2x);
   const Real c4 = hh2x - ez * q;
-  const Real c5 = Y * (Real(20) * ez2 - Real(8.0 / 3.0)) - Real(4) * (hh * hh + X * ez2);
+  const Real c5 = Y * (k.c20 * ez2 - k.c8_3) - Real(4) * (hh * hh + X * ez2);
 
   // apply to the force
   const Real rhoF = dx * fx + dy * fy;
@@ -185,7 +228,7 @@ __device__ __forceinline__ void pair_velocity(Real dx, Real dy, Real zi, Real zj
     const Real al = iR3 - cT;                        // coefficient of kv
     const Real xez = X * ez;
     const Real d2 = Real(2) * xez + hh2x;
-    const Real d3 = Real(10) * xez + Real(6) * hme;
+    const Real d3 = k.c10 * xez + k.c6 * hme;
     const Real s = -(kz * iR);                       // (e x z) . T
     const Real be = cT * dz + (iR2 * d2 - iR3 * Rz);  // coefficient of (ty, -tx, 0)
     const Real ga = iR3 * (s * d3);                  // coefficient of rho
@@ -237,7 +280,7 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
     const Real invr = rsqrt_r(r2);
     const Real ir2 = invr * invr;
     const Real s = ir2;
-    cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
+    cI = invr * (Real(1) + k.c2_3 * s);
     if (TORQUE) {
       cT = invr * ir2;
       cRR = cT * (Real(1) - Real(2) * s);
@@ -249,7 +292,7 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
     if (r2 >= Real(kFourA2)) {
       const Real ir2 = invr * invr;
       const Real s = ir2;
-      cI = invr * (Real(1) + Real(2.0 / 3.0) * s);
+      cI = invr * (Real(1) + k.c2_3 * s);
       if (TORQUE) {
         cT = invr * ir2;
         cRR = cT * (Real(1) - Real(2) * s);
@@ -286,15 +329,15 @@ __device__ __forceinline__ void sym_coefficients(Real dx, Real dy, Real zi, Real
   const Real hh = zj * iR;
   const Real ez2 = ez * ez;
   const Real t = hh * (hh - ez);
-  const Real p = X * (Real(2) - Real(10.0 / 3.0) * X);
-  const Real q = Real(20.0 / 3.0) * Y;
-  const Real m = ez2 * (q - Real(5) * p);
-  const Real c1 = ez2 * p + (Real(2) * t + (Real(-2.0 / 3.0) * (X - Y) - Real(1)));
-  const Real g = m + (Real(-6) * t + p);
+  const Real p = X * (Real(2) - k.c10_3 * X);
+  const Real q = k.c20_3 * Y;
+  const Real m = ez2 * (q - k.c5 * p);
+  const Real c1 = ez2 * p + (Real(2) * t + (-k.c2_3 * (X - Y) - Real(1)));
+  const Real g = m + (-k.c6 * t + p);
   const Real u = ez * (g - q);
   const Real h2e = Real(2) * hh - ez;
-  const Real bx = ez2 * ((Real(6) * t - m) + (Real(70.0 / 3.0) * Y - (Real(6) * X + Real(1)))) -
-                  (Real(4) * t + Real(8.0 / 3.0) * Y);
+  const Real bx = ez2 * ((k.c6 * t - m) + (k.c70_3 * Y - (k.c6 * X + Real(1)))) -
+                  (Real(4) * t + k.c8_3 * Y);
   c.A = cI + iR * c1;
   const Real iR3 = iR * iR2;
   const Real crdz = cRR * dz;
@@ -360,9 +403,9 @@ __device__ __forceinline__ void sym_apply(const SymCoef<Real> &c, Real fx, Real 
 // height hh = z~_j/|R| replaced by z~_i/|R|, so everything else (|R|, e_z, X, the unbounded
 // coefficient) is shared.
 template <typename Real, bool WALL>
-__device__ __forceinline__ void sym_apply_torque(const SymCoef<Real> &c, Real zi, const Real *tq,
-                                                 const Real *uq, Real &ox, Real &oy, Real &oz,
-                                                 Real &px, Real &py, Real &pz) {
+__device__ __forceinline__ void sym_apply_torque(const SymCoef<Real> &c, const PairConsts<Real> &k,
+                                                 Real zi, const Real *tq, const Real *uq, Real &ox,
+                                                 Real &oy, Real &oz, Real &px, Real &py, Real &pz) {
   const Real dx = c.dx, dy = c.dy, dz = c.dz, cT = c.cT;
   if (!WALL) {   // cT T_j x r into o, cT T_i x (-r) into p
     ox += cT * (tq[1] * dz - tq[2] * dy);
@@ -379,10 +422,10 @@ __device__ __forceinline__ void sym_apply_torque(const SymCoef<Real> &c, Real zi
   const Real al = iR3 - cT;                 // coefficient of k (both directions)
   const Real xez = X * ez;
   const Real be0 = iR2 * (Real(2) * xez) - iR3 * Rz;
-  const Real d30 = Real(10) * xez - Real(6) * ez;
+  const Real d30 = k.c10 * xez - k.c6 * ez;
   const Real wz = d30 * ez - Real(2) * X;   // with the image-height part added per direction
   const Real iR2x2 = Real(2) * iR2;
-  const Real ez6 = Real(6) * ez;
+  const Real ez6 = k.c6 * ez;
   // Per direction, with k = (r_x, r_y, 0) x T = (r_y T_z, -r_x T_z, K):
   //   u_x,y += al k_x,y + be (T_y, -T_x) + ga (r_x, r_y),   u_z += K (al - (wz + 6 h e_z)/|R|^3),
   //   be = 2h/|R|^2 + be0 + cT r_z,   ga = -K (d30 + 6h)/|R|^4,   h = image height / |R|.
@@ -392,7 +435,7 @@ __device__ __forceinline__ void sym_apply_torque(const SymCoef<Real> &c, Real zi
     const Real K = dx * ty - dy * tx;
     const Real P = al * tz;
     const Real be = iR2x2 * hh + (cT * dz + be0);
-    const Real ga = -K * (iR4 * (Real(6) * hh + d30));
+    const Real ga = -K * (iR4 * (k.c6 * hh + d30));
     const Real cz = al - iR3 * (hh * ez6 + wz);
     ox += P * dy;
     ox += be * ty;
@@ -408,7 +451,7 @@ __device__ __forceinline__ void sym_apply_torque(const SymCoef<Real> &c, Real zi
     const Real K = dy * tx - dx * ty;
     const Real P = al * tz;
     const Real be = iR2x2 * hi + (be0 - cT * dz);
-    const Real ga = -K * (iR4 * (Real(6) * hi + d30));
+    const Real ga = -K * (iR4 * (k.c6 * hi + d30));
     const Real cz = al - iR3 * (hi * ez6 + wz);
     px -= P * dy;
     px += be * ty;
@@ -457,7 +500,7 @@ __device__ __forceinline__ void pair_velocity_sym(Real dx, Real dy, Real zi, Rea
   SymCoef<Real> c;
   sym_coefficients<Real, FAR_ONLY, TORQUE, WALL>(dx, dy, zi, zj, k, c);
   sym_apply<Real, WALL>(c, fx, fy, fz, gx, gy, gz, ox, oy, oz, px, py, pz);
-  if (TORQUE) sym_apply_torque<Real, WALL>(c, zi, tq, uq, ox, oy, oz, px, py, pz);
+  if (TORQUE) sym_apply_torque<Real, WALL>(c, k, zi, tq, uq, ox, oy, oz, px, py, pz);
 }
 
 __device__ __forceinline__ float round_nearest(float x) { return __builtin_rintf(x); }
