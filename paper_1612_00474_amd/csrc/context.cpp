@@ -160,6 +160,11 @@ int rpb_create(int hip_device, rpb_ctx **out) {
     delete c;
     return RPB_ENOMEM;
   }
+  if (hipHostGetDevicePointer(&c->host_pinned_dev, c->host_pinned, 0) != hipSuccess) {
+    (void)hipHostFree(c->host_pinned);
+    delete c;
+    return RPB_EDEVICE;
+  }
   if (noalloc_setup(c, hip_device) != RPB_OK) {
     (void)hipHostFree(c->host_pinned);
     delete c;

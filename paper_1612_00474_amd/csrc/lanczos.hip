@@ -64,6 +64,11 @@ static_assert(sizeof(LzRingSlot) == sizeof(double) + 2 * sizeof(int) &&
 LzRing *lz_ring(rpb_ctx *ctx) {
   return reinterpret_cast<LzRing *>(static_cast<char *>(host_scratch(ctx)) + kHostLzRingOffset);
 }
+// The ring as kernels address it.
+LzRing *lz_ring_dev(rpb_ctx *ctx) {
+  return reinterpret_cast<LzRing *>(static_cast<char *>(host_scratch_dev(ctx)) +
+                                    kHostLzRingOffset);
+}
 
 // Waits for every ring copy still in flight (a previous call's last copy may target a slot
 // this call is about to reuse, possibly from another stream).
@@ -76,11 +81,10 @@ int lz_ring_fence(rpb_ctx *ctx) {
   return RPB_OK;
 }
 
-// Enqueues the copy of the status words into ring slot q and marks it with event q.
-int lz_ring_post(rpb_ctx *ctx, LzRing *ring, int q, const double *status, hipStream_t stream) {
+// Marks ring slot q with event q: the iteration's last status-writing kernel (lanczos_step or
+// tridiag_sqrt, which store the status words into the slot) precedes it on the stream.
+int lz_ring_post(rpb_ctx *ctx, int q, hipStream_t stream) {
   if (!ctx->lz_ev[q]) RPB_HIP(ctx, hipEventCreateWithFlags(&ctx->lz_ev[q], hipEventDisableTiming));
-  RPB_HIP(ctx, hipMemcpyAsync(&ring->slot[q], status, sizeof(LzRingSlot), hipMemcpyDeviceToHost,
-                              stream));
   RPB_HIP(ctx, hipEventRecord(ctx->lz_ev[q], stream));
   ctx->lz_live[q] = true;
   return RPB_OK;
@@ -207,25 +211,25 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 // The first wavefront of the workgroup does the work: lane k owns row k of the eigenvector
 // matrix Z.  Every lane runs the same scalar recurrence and stores the same values into the
 // single LDS copy of (d, e); a wavefront's LDS accesses complete in program order, so no
-// barrier is needed until the end, and the column rotations of Z touch only the lane's own
-// row.  Every thread of the workgroup must call this (the other wavefronts only pass the
-// barriers).
+// barrier is needed, and the column rotations of Z touch only the lane's own row.  The other
+// wavefronts of the workgroup return at once; the caller synchronises before it reads the
+// state.
 __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   __shared__ double Z[kMaxKrylov * 64];   // Z[col * 64 + row]
   __shared__ double Dg[kMaxKrylov];       // diagonal, becomes the eigenvalues
   __shared__ double Eg[kMaxKrylov];       // subdiagonal e[i] couples i and i + 1
-  __shared__ double red[64];
+  __shared__ double Rz[kMaxKrylov];       // sqrt(lambda_k) z_k[0]
   const int lane = threadIdx.x;
-  const bool w0 = lane < 64;
-  if (w0)
-    for (int c = 0; c < m; ++c) Z[c * 64 + lane] = (c == lane) ? 1.0 : 0.0;
+  if (lane >= 64) return;
+  // rows m..63 of Z stay zero (no column c < m has its 1 there), so the rotations need no
+  // guard on the lane
+  for (int c = 0; c < m; ++c) Z[c * 64 + lane] = (c == lane) ? 1.0 : 0.0;
   if (lane < m) {
     Dg[lane] = st->alpha[lane];
     Eg[lane] = (lane < m - 1) ? st->beta[lane] : 0.0;
   }
-  __syncthreads();
   int failed = 0;
-  for (int l = 0; l < m && !failed && w0; ++l) {
+  for (int l = 0; l < m && !failed; ++l) {
     int iter = 0;
     for (;;) {
       // smallest mm >= l whose e[mm] is negligible next to its diagonal neighbours (m - 1 if
@@ -247,26 +251,27 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
       double g = (Dg[(l + 1)] - dl) / (2.0 * el);
       double r = sqrt(g * g + 1.0);
       g = Dg[mm] - dl + el / (g + copysign(r, g));
-      // One sweep of plane rotations from (mm - 1, mm) down to (l, l + 1).  d[i + 1] (not yet
-      // rewritten in this sweep) and column i + 1 of this lane's row of Z are carried in
-      // registers from one rotation to the next, so the LDS loads of e[i], d[i] and column i
-      // do not wait on the previous rotation's stores.  The rotation is formed from
-      // 1/sqrt(f^2 + g^2): r = h2 / sqrt(h2), s = f / r, c = g / r.
+      // One sweep of plane rotations from (mm - 1, mm) down to (l, l + 1).  Rotation i writes
+      // e[i + 1], d[i + 1] and column i + 1 and reads e[i], d[i] and column i, which no
+      // rotation of the sweep writes: so the operands of rotation i - 1 are loaded while
+      // rotation i computes, and d[i + 1] and this lane's entry of column i + 1 are carried in
+      // registers.  The rotation is formed from 1/sqrt(f^2 + g^2): r = h2 / sqrt(h2),
+      // s = f / r, c = g / r.
       double s = 1.0, c = 1.0, p = 0.0;
       bool underflow = false;
       double dhi = Dg[mm];
-      double zhi = (lane < m) ? Z[mm * 64 + lane] : 0.0;
+      double zhi = Z[mm * 64 + lane];
+      double ei = Eg[mm - 1], di = Dg[mm - 1], zi = Z[(mm - 1) * 64 + lane];
       for (int i = mm - 1; i >= l; --i) {
-        const double ei = Eg[i];
-        const double di = Dg[i];
-        const double zi = (lane < m) ? Z[i * 64 + lane] : 0.0;
+        const int nx = i > l ? i - 1 : i;
+        const double en = Eg[nx], dn = Dg[nx], zn = Z[nx * 64 + lane];
         const double f = s * ei;
         const double b = c * ei;
         const double h2 = f * f + g * g;
         if (h2 == 0.0) {
           Eg[(i + 1)] = 0.0;
           Dg[(i + 1)] = dhi - p;
-          if (lane < m) Z[(i + 1) * 64 + lane] = zhi;
+          Z[(i + 1) * 64 + lane] = zhi;
           Eg[mm] = 0.0;
           underflow = true;
           break;
@@ -280,19 +285,21 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
         p = s * r;
         Dg[(i + 1)] = g + p;
         g = c * r - b;
-        if (lane < m) Z[(i + 1) * 64 + lane] = s * zi + c * zhi;
+        Z[(i + 1) * 64 + lane] = s * zi + c * zhi;
         zhi = c * zi - s * zhi;
         dhi = di;
+        ei = en;
+        di = dn;
+        zi = zn;
       }
       if (underflow) continue;
-      if (lane < m) Z[l * 64 + lane] = zhi;
+      Z[l * 64 + lane] = zhi;
       Dg[l] = dhi - p;
       Eg[l] = g;
       Eg[mm] = 0.0;
     }
   }
-  __syncthreads();
-  // largest and smallest eigenvalue and largest |alpha|, reduced across the first wavefront
+  // largest and smallest eigenvalue and largest |alpha|, reduced across the wavefront
   double lmax = lane < m ? Dg[lane] : -DBL_MAX;
   double lmin = lane < m ? Dg[lane] : DBL_MAX;
   double amax = lane < m ? fabs(st->alpha[lane]) : 0.0;
@@ -301,34 +308,22 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
     lmin = fmin(lmin, __shfl_xor(lmin, off, 64));
     amax = fmax(amax, __shfl_xor(amax, off, 64));
   }
-  // y_m = |w| Q L^{1/2} Q^T e_1: lane r forms row r from the eigenvalues (identical in every
-  // lane) and the first row of the eigenvector matrix
+  // y_m = |w| Q L^{1/2} Q^T e_1: lane k forms sqrt(lambda_k) z_k[0], then lane r sums row r
+  if (lane < m) Rz[lane] = sqrt(fmax(Dg[lane], 0.0)) * Z[lane * 64 + 0];
   const double wn = st->wnorm;
   double yr = 0.0;
   if (lane < m) {
-    for (int k = 0; k < m; ++k)
-      yr += sqrt(fmax(Dg[k], 0.0)) * Z[k * 64 + 0] * Z[k * 64 + lane];
+    for (int k = 0; k < m; ++k) yr += Rz[k] * Z[k * 64 + lane];
     yr *= wn;
   }
   // eps_m in the orthonormal Krylov basis
   const double yp = (lane < m - 1) ? st->yprev[lane] : 0.0;
   const double diff = (lane < m) ? (yr - yp) : 0.0;
-  if (w0) red[lane] = diff * diff;
-  __syncthreads();
-  for (int s = 32; s > 0; s >>= 1) {
-    if (lane < s) red[lane] += red[lane + s];
-    __syncthreads();
+  double num = diff * diff, den = yp * yp;
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_xor(num, off, 64);
+    den += __shfl_xor(den, off, 64);
   }
-  const double num = red[0];
-  __syncthreads();
-  if (w0) red[lane] = yp * yp;
-  __syncthreads();
-  for (int s = 32; s > 0; s >>= 1) {
-    if (lane < s) red[lane] += red[lane + s];
-    __syncthreads();
-  }
-  const double den = red[0];
-  __syncthreads();
   if (lane < m) {
     st->y[lane] = yr;
     st->yprev[lane] = yr;
@@ -350,11 +345,21 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
   }
 }
 
+// Status words of the iteration into the host's ring slot (pinned host memory, written by the
+// kernel so that no copy needs enqueuing), by one thread after the state is final.
+__device__ __forceinline__ void post_status(const LzState *__restrict__ st, LzRingSlot *slot) {
+  slot->eps = st->eps;
+  slot->m = st->m;
+  slot->reason = st->reason;
+  __threadfence_system();
+}
+
 // A process that has stopped (reason != 0) keeps its state: an iteration enqueued after the
-// stop leaves y, eps, m and reason as they are.
-__global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st) {
-  if (st->reason != 0) return;
-  tridiag_body(m, tol, st);
+// stop leaves y, eps, m and reason as they are (and posts them again).
+__global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st,
+                                                   LzRingSlot *slot) {
+  if (st->reason == 0) tridiag_body(m, tol, st);
+  if (threadIdx.x == 0) post_status(st, slot);
 }
 
 __global__ void lz_reset(LzState *st) {
@@ -469,14 +474,17 @@ __device__ void lanczos_step_body(LzState *__restrict__ st, double *__restrict__
   }
 }
 
-// Single system, the whole vector (3 n <= kFusedSegment).  A process that has stopped keeps its
-// state: an iteration enqueued after the stop returns at once.
+// Single system, the whole vector (3 n <= kFusedSegment), then the status into the host's ring
+// slot.  A process that has stopped keeps its state: an iteration enqueued after the stop only
+// posts the status again.  (Every thread reads the same reason: it is written only after the
+// workgroup's first barrier.)
 __global__ __launch_bounds__(kThreads) void lanczos_step(LzState *__restrict__ st,
                                                          double *__restrict__ V,
                                                          double *__restrict__ u, int64_t m3, int k,
-                                                         double tol, int write_next) {
-  if (st->reason != 0) return;
-  lanczos_step_body(st, V, u, m3, 0, m3, k, tol, write_next != 0);
+                                                         double tol, int write_next,
+                                                         LzRingSlot *slot) {
+  if (st->reason == 0) lanczos_step_body(st, V, u, m3, 0, m3, k, tol, write_next != 0);
+  if (threadIdx.x == 0) post_status(st, slot);
 }
 
 // ---- batched Lanczos: one Krylov process per system, segments of the concatenated vectors ----
@@ -712,6 +720,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   // only u, V's next column and entries of alpha and beta past the last iteration.
   RPB_TRY(lz_ring_fence(ctx));
   LzRing *ring = lz_ring(ctx);
+  LzRing *ring_dev = lz_ring_dev(ctx);
   const int *stopped = &ls->reason;
 
   lz_reset<<<1, 64, 0, stream>>>(ls);
@@ -742,7 +751,8 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
       RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream, stopped));
     }
     if (m3 <= kFusedSegment) {   // the whole iteration's vector work in one workgroup
-      lanczos_step<<<1, kThreads, 0, stream>>>(ls, V, u, m3, k, tol, k < max_iter);
+      lanczos_step<<<1, kThreads, 0, stream>>>(ls, V, u, m3, k, tol, k < max_iter,
+                                                  &ring_dev->slot[k & 1]);
       RPB_LAUNCHED(ctx);
     } else {
       RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
@@ -759,7 +769,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
         RPB_LAUNCHED(ctx);
       }
       RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[k - 1], 1, stream));
-      tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls);
+      tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls, &ring_dev->slot[k & 1]);
       RPB_LAUNCHED(ctx);
       if (k < max_iter) {
         scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
@@ -767,7 +777,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
         RPB_LAUNCHED(ctx);
       }
     }
-    RPB_TRY(lz_ring_post(ctx, ring, k & 1, &ls->eps, stream));
+    RPB_TRY(lz_ring_post(ctx, k & 1, stream));
     // the status of the previous iteration (or of this one, after the last)
     for (int q = k > 1 ? k - 1 : k; q <= k; ++q) {
       if (q == k && k < max_iter) break;

@@ -655,19 +655,30 @@ __global__ __launch_bounds__(kBlock) void pair_kernel_f64_sym(SymArgs a, PartMap
                                              int64_t(blockIdx.x) % a.nsplit, L, col);
 }
 
-// One thread per (component, row): the partials of the chunk [pm.L0, L1) added in a fixed
-// order (chunk_row_sum), written to vel on the first chunk and added to it on the others; after
-// the last chunk the sum is scaled by H_i / (8 pi eta a).
+// kRedGroups threads per (component, row), 64 rows per workgroup (one wavefront per group):
+// the partials of the chunk [pm.L0, L1) dealt over the groups (chunk_row_sum_dealt) and the
+// group sums added in a fixed order, written to vel on the first chunk and added to it on the
+// others; after the last chunk the sum is scaled by H_i / (8 pi eta a).
+constexpr int kRedGroups = 8;
+
 template <typename Part>
-__global__ void reduce_sym_chunk(SymArgs a, PartMap pm, int64_t L1, int first, int last,
-                                 const Part *__restrict__ partial, const double *__restrict__ h,
-                                 double scale, double *__restrict__ vel) {
+__global__ __launch_bounds__(64 * kRedGroups) void reduce_sym_chunk(
+    SymArgs a, PartMap pm, int64_t L1, int first, int last, const Part *__restrict__ partial,
+    const double *__restrict__ h, double scale, double *__restrict__ vel) {
+  __shared__ double sh[kRedGroups * 64];
   if (a.skip && *a.skip) return;
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= 3 * a.n) return;
-  const int d = int(e / a.n);
-  const int64_t r = e - int64_t(d) * a.n;
-  double v = chunk_row_sum(partial, pm, a.nt, L1, r / a.ts, r % a.ts, 0, d);
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t e = int64_t(blockIdx.x) * 64 + lane;
+  const bool live = e < 3 * a.n;
+  const int d = live ? int(e / a.n) : 0;
+  const int64_t r = live ? e - int64_t(d) * a.n : 0;
+  sh[grp * 64 + lane] =
+      live ? chunk_row_sum_dealt(partial, pm, a.nt, L1, r / a.ts, r % a.ts, d, grp, kRedGroups)
+           : 0.0;
+  __syncthreads();
+  if (grp != 0 || !live) return;
+  double v = sh[lane];
+  for (int q = 1; q < kRedGroups; ++q) v += sh[q * 64 + lane];
   if (!first) v += vel[3 * r + d];
   vel[3 * r + d] = last ? scale * h[r] * v : v;
 }
@@ -1213,10 +1224,10 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
                          (f64 ? 0 : 2) + (torque ? 1 : 0)));
     const int first = L0 == 0, last = L1 == pairs;
     if (f64)
-      reduce_sym_chunk<double><<<blocks_for(3 * n, 256), 256, 0, stream>>>(
+      reduce_sym_chunk<double><<<blocks_for(3 * n, 64), 64 * kRedGroups, 0, stream>>>(
           a, pm, L1, first, last, static_cast<const double *>(part), h, scale, vel);
     else
-      reduce_sym_chunk<float><<<blocks_for(3 * n, 256), 256, 0, stream>>>(
+      reduce_sym_chunk<float><<<blocks_for(3 * n, 64), 64 * kRedGroups, 0, stream>>>(
           a, pm, L1, first, last, static_cast<const float *>(part), h, scale, vel);
     RPB_LAUNCHED(ctx);
   }

@@ -164,6 +164,57 @@ __device__ __forceinline__ double chunk_row_sum(const Part *__restrict__ p, cons
   return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
+// The same partials as chunk_row_sum for one vector, shared by G threads: the slots, in the
+// order of chunk_row_sum (column slots of pairs (I, T) in increasing I, then the parts h of the
+// row slots of pairs (T, J) in increasing J and h), are dealt to the G threads in turn; thread g
+// adds slots g + (4 j + q) G into running sum q, four loads in flight, and returns
+// (s_0 + s_1) + (s_2 + s_3).  The caller adds the G results in a fixed order.
+template <typename Part>
+__device__ __forceinline__ double chunk_row_sum_dealt(const Part *__restrict__ p,
+                                                      const PartMap &m, int64_t nt, int64_t L1,
+                                                      int64_t T, int64_t local, int c, int g,
+                                                      int G) {
+  auto Lcol = [&](int64_t I) { return tri_start(I, nt) + T - I; };
+  int64_t lo = 0, hi = T;
+  while (lo < hi) {   // first I with L(I, T) >= L0
+    const int64_t mid = (lo + hi) / 2;
+    if (Lcol(mid) >= m.L0)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int64_t i0 = lo;
+  hi = T;
+  while (lo < hi) {   // first I with L(I, T) >= L1
+    const int64_t mid = (lo + hi) / 2;
+    if (Lcol(mid) >= L1)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int ncol = int(lo - i0);
+  const int64_t st = tri_start(T, nt);
+  const int64_t j0 = T + (m.L0 > st ? m.L0 - st : 0);
+  const int64_t j1 = T + (L1 - st < nt - T ? (L1 > st ? L1 - st : 0) : nt - T);
+  const int ns = int(m.nsplit);
+  const int nslots = ncol + int(j1 - j0) * ns;
+  auto slot = [&](int q) -> double {   // value of slot q < nslots
+    if (q < ncol) return double(p[part_elem(m, Lcol(i0 + q), m.nsplit, 0, c, local)]);
+    const int t = q - ncol;
+    const int64_t J = j0 + t / ns;
+    return double(p[part_elem(m, st + J - T, t % ns, 0, c, local)]);
+  };
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int q = g; q < nslots; q += 4 * G) {
+    double x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = q + r * G < nslots ? slot(q + r * G) : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s[r] += x[r];
+  }
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 // Chunks of the triangle: at most `limit` bytes of partials per launch (the context's chunk
 // limit, kMaxChunkBytes unless overridden), equal numbers of pairs per chunk.
 inline int64_t chunk_pairs(int64_t pairs, int64_t nsplit, int V, int64_t ts, size_t esz,

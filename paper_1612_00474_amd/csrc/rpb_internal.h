@@ -87,6 +87,7 @@ struct rpb_ctx {
   std::string err;
   rpb::DevBuf ws[rpb::WS_NSLOTS];
   void *host_pinned = nullptr;          // small pinned host buffer for device scalars
+  void *host_pinned_dev = nullptr;      // the same buffer as kernels address it
   void *batch_host = nullptr;           // pinned staging of batched offsets / work items
   size_t batch_host_bytes = 0;
   // pair-kernel timing
@@ -121,6 +122,7 @@ constexpr size_t kHostScratchBytes = 1 << 17;
 constexpr size_t kHostLzRingOffset = kHostScratchBytes / 2;
 constexpr size_t kHostFiniteOffset = kHostLzRingOffset + 1024;   // deferred position check
 inline void *host_scratch(rpb_ctx *ctx) { return ctx->host_pinned; }
+inline void *host_scratch_dev(rpb_ctx *ctx) { return ctx->host_pinned_dev; }
 
 #define RPB_HIP(ctx, call)                                                              \
   do {                                                                                  \
