@@ -198,122 +198,314 @@ __global__ void basis_combine(int64_t m, int nvec, const double *__restrict__ V,
   out[i] = acc;
 }
 
-// 1/sqrt(x) for x > 0: hardware estimate, then one third-order Newton step on
-// e = 1 - x y^2, y (1 + e/2 + 3e^2/8) = y (1 - e)^{-1/2} + O(e^3).
-__device__ __forceinline__ double rsqrt_f64(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double e = __builtin_fma(-x * y, y, 1.0);
-  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
-}
+// Eigendecomposition of T_{m-1} kept from one iteration to the next (the eigensolve of T_m
+// updates it): eigenvalues in increasing order and the eigenvector matrix, row-major.
+struct LzEig {
+  double lam[kMaxKrylov];
+  double Q[kMaxKrylov * kMaxKrylov];   // Q[row * kMaxKrylov + col]
+};
 
-// Eigendecomposition of T_m by implicit QL with Wilkinson-type shifts (Bowdler, Martin,
-// Reinsch, Wilkinson 1968), then y_m = |w| Q L^{1/2} Q^T e_1, eps_m and the stop test.
-// The first wavefront of the workgroup does the work: lane k owns row k of the eigenvector
-// matrix Z.  Every lane runs the same scalar recurrence and stores the same values into the
-// single LDS copy of (d, e); a wavefront's LDS accesses complete in program order, so no
-// barrier is needed, and the column rotations of Z touch only the lane's own row.  The other
-// wavefronts of the workgroup return at once; the caller synchronises before it reads the
-// state.
-__device__ void tridiag_body(int m, double tol, LzState *__restrict__ st) {
-  __shared__ double Z[kMaxKrylov * 64];   // Z[col * 64 + row]
-  __shared__ double Dg[kMaxKrylov];       // diagonal, becomes the eigenvalues
-  __shared__ double Eg[kMaxKrylov];       // subdiagonal e[i] couples i and i + 1
-  __shared__ double Rz[kMaxKrylov];       // sqrt(lambda_k) z_k[0]
-  const int lane = threadIdx.x;
-  if (lane >= 64) return;
-  // rows m..63 of Z stay zero (no column c < m has its 1 there), so the rotations need no
-  // guard on the lane
-  for (int c = 0; c < m; ++c) Z[c * 64 + lane] = (c == lane) ? 1.0 : 0.0;
-  if (lane < m) {
-    Dg[lane] = st->alpha[lane];
-    Eg[lane] = (lane < m - 1) ? st->beta[lane] : 0.0;
-  }
-  int failed = 0;
-  for (int l = 0; l < m && !failed; ++l) {
-    int iter = 0;
-    for (;;) {
-      // smallest mm >= l whose e[mm] is negligible next to its diagonal neighbours (m - 1 if
-      // none): every lane tests one index and the wavefront takes the lowest hit
-      bool small = false;
-      if (lane >= l && lane < m - 1) {
-        const double dd = fabs(Dg[lane]) + fabs(Dg[lane + 1]);
-        small = fabs(Eg[lane]) + dd == dd;
-      }
-      const unsigned long long hits = __ballot(small);
-      const int mm = hits ? __builtin_ctzll(hits) : m - 1;
-      if (mm == l) break;
-      if (++iter > 60) {
-        failed = 1;
-        break;
-      }
-      const double dl = Dg[l];
-      const double el = Eg[l];
-      double g = (Dg[(l + 1)] - dl) / (2.0 * el);
-      double r = sqrt(g * g + 1.0);
-      g = Dg[mm] - dl + el / (g + copysign(r, g));
-      // One sweep of plane rotations from (mm - 1, mm) down to (l, l + 1).  Rotation i writes
-      // e[i + 1], d[i + 1] and column i + 1 and reads e[i], d[i] and column i, which no
-      // rotation of the sweep writes: so the operands of rotation i - 1 are loaded while
-      // rotation i computes, and d[i + 1] and this lane's entry of column i + 1 are carried in
-      // registers.  The rotation is formed from 1/sqrt(f^2 + g^2): r = h2 / sqrt(h2),
-      // s = f / r, c = g / r.
-      double s = 1.0, c = 1.0, p = 0.0;
-      bool underflow = false;
-      double dhi = Dg[mm];
-      double zhi = Z[mm * 64 + lane];
-      double ei = Eg[mm - 1], di = Dg[mm - 1], zi = Z[(mm - 1) * 64 + lane];
-      for (int i = mm - 1; i >= l; --i) {
-        const int nx = i > l ? i - 1 : i;
-        const double en = Eg[nx], dn = Dg[nx], zn = Z[nx * 64 + lane];
-        const double f = s * ei;
-        const double b = c * ei;
-        const double h2 = f * f + g * g;
-        if (h2 == 0.0) {
-          Eg[(i + 1)] = 0.0;
-          Dg[(i + 1)] = dhi - p;
-          Z[(i + 1) * 64 + lane] = zhi;
-          Eg[mm] = 0.0;
-          underflow = true;
-          break;
-        }
-        const double inv = rsqrt_f64(h2);
-        Eg[(i + 1)] = h2 * inv;
-        s = f * inv;
-        c = g * inv;
-        g = dhi - p;
-        r = (di - g) * s + 2.0 * c * b;
-        p = s * r;
-        Dg[(i + 1)] = g + p;
-        g = c * r - b;
-        Z[(i + 1) * 64 + lane] = s * zi + c * zhi;
-        zhi = c * zi - s * zhi;
-        dhi = di;
-        ei = en;
-        di = dn;
-        zi = zn;
-      }
-      if (underflow) continue;
-      Z[l * 64 + lane] = zhi;
-      Dg[l] = dhi - p;
-      Eg[l] = g;
-      Eg[mm] = 0.0;
+constexpr int kMaxRootIter = 64;   // secular-equation iterations per root before giving up
+
+// Root i (0 <= i <= p) of the secular equation of an arrowhead matrix with diagonal d (p
+// distinct values, increasing), border z (no zero) and corner a:
+//   f(mu) = a - mu - sum_j z_j^2 / (d_j - mu),
+// decreasing between consecutive poles, so that root i lies in (d_{i-1}, d_i) (d_{-1} = -inf,
+// d_p = +inf; the outer roots lie within |z| of d or a).  The root is kept as
+// mu = d_K + tau about the nearer pole K, with d_j - mu formed as (d_j - d_K) - tau, so that it
+// keeps full relative accuracy in its distance to the pole.  Each step solves the model
+// c + b tau + z_K^2 / tau = 0 (the pole K exact, the other terms linearised at the current tau:
+// a quadratic with one root on each side of 0, the one on the side of the root is taken),
+// safeguarded by bisection of the bracket; stops when |f| is within the rounding error of
+// its terms.  Returns false when it does not stop within kMaxRootIter steps.
+__device__ __forceinline__ bool secular_root(int i, int p, const double *__restrict__ d,
+                             const double *__restrict__ z2, double a, double znorm, int &K,
+                             double &tau) {
+  double lo, hi;
+  if (i == 0) {
+    K = 0;
+    lo = fmin(d[0], a) - znorm - d[0];
+    hi = 0.0;
+  } else if (i == p) {
+    K = p - 1;
+    lo = 0.0;
+    hi = fmax(d[p - 1], a) + znorm - d[p - 1];
+  } else {
+    const double mid = 0.5 * (d[i - 1] + d[i]);
+    double f = a - mid;
+    for (int j = 0; j < p; ++j) f -= z2[j] / (d[j] - mid);
+    if (f > 0.0) {   // the root lies above the midpoint: nearer pole d_i
+      K = i;
+      lo = mid - d[i];
+      hi = 0.0;
+    } else {
+      K = i - 1;
+      lo = 0.0;
+      hi = mid - d[i - 1];
     }
   }
-  // largest and smallest eigenvalue and largest |alpha|, reduced across the wavefront
-  double lmax = lane < m ? Dg[lane] : -DBL_MAX;
-  double lmin = lane < m ? Dg[lane] : DBL_MAX;
-  double amax = lane < m ? fabs(st->alpha[lane]) : 0.0;
-  for (int off = 32; off > 0; off >>= 1) {
-    lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
-    lmin = fmin(lmin, __shfl_xor(lmin, off, 64));
-    amax = fmax(amax, __shfl_xor(amax, off, 64));
+  const double dK = d[K], a0 = a - dK, zK2 = z2[K];
+  const bool above = K == i - 1;   // the root lies above its pole (tau > 0)
+  tau = 0.5 * (lo + hi);
+  for (int it = 0; it < kMaxRootIter; ++it) {
+    double f = a0 - tau, R = 0.0, Rp = 0.0, mag = fabs(a0) + fabs(tau);
+    for (int j = 0; j < p; ++j) {
+      const double den = (d[j] - dK) - tau;
+      const double inv = 1.0 / den;
+      const double w = z2[j] * inv;
+      f -= w;
+      mag += fabs(w);
+      if (j != K) {
+        R += w;
+        Rp += w * inv;
+      }
+    }
+    if (fabs(f) <= 4.0 * DBL_EPSILON * mag) return true;
+    if (f > 0.0)
+      lo = tau;
+    else
+      hi = tau;
+    const double b = -1.0 - Rp;           // slope of the linearised part
+    const double c = (a0 - tau - R) - b * tau;
+    const double disc = sqrt(c * c - 4.0 * b * zK2);
+    double t;
+    if (above)
+      t = c <= 0.0 ? 2.0 * zK2 / (disc - c) : (c + disc) / (-2.0 * b);
+    else
+      t = c <= 0.0 ? (disc - c) / (2.0 * b) : 2.0 * zK2 / (-c - disc);
+    if (!(t >= lo && t <= hi)) t = 0.5 * (lo + hi);
+    if (fabs(t - tau) <= 2.0 * DBL_EPSILON * fabs(t)) {
+      tau = t;
+      return true;
+    }
+    tau = t;
   }
-  // y_m = |w| Q L^{1/2} Q^T e_1: lane k forms sqrt(lambda_k) z_k[0], then lane r sums row r
-  if (lane < m) Rz[lane] = sqrt(fmax(Dg[lane], 0.0)) * Z[lane * 64 + 0];
+  return false;
+}
+
+// Eigendecomposition of T_m from that of T_{m-1} (in eig, replaced by T_m's).  In the basis of
+// T_{m-1}'s eigenvectors and e_m, T_m is an arrowhead matrix: diagonal lambda, border
+// z = beta_{m-1} (last row of Q), corner alpha_m.  Its eigenproblem is solved as in the
+// divide-and-conquer method (Cuppen 1981; Gu and Eisenstat 1995):
+//   - deflation: a border entry below tol (8 eps |T|) leaves its lambda an eigenvalue; two
+//     lambdas closer than tol / (c s) are rotated so that one border entry vanishes;
+//   - the p + 1 roots of the secular equation of the rest, one lane each (secular_root);
+//   - a border recomputed from the roots, z^_j^2 = prod_i |d_j - mu_i| / prod_{l != j}
+//     |d_j - d_l| (the border for which the computed roots are exact), which keeps the
+//     eigenvectors u_i = (z^_j / (d_j - mu_i), -1) / norm orthogonal to working accuracy;
+//   - new eigenvectors [Q 0; 0 1] U and the eigenvalues sorted increasingly.
+// Every thread of the workgroup calls this; the first wavefront (one lane per eigenvalue, m <=
+// 64) does the scalar work and the workgroup forms the product.  Returns 1 (every thread)
+// when a root iteration did not stop or an eigenvalue is not finite.
+__device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restrict__ eig) {
+  __shared__ double Qs[kMaxKrylov * kMaxKrylov];   // old Q (rows < m - 1), rotated
+  __shared__ double U[kMaxKrylov * kMaxKrylov];    // U[i * 64 + j]: eigenvector i, entry j
+  __shared__ double dd[kMaxKrylov], zz[kMaxKrylov], dn[kMaxKrylov], z2n[kMaxKrylov];
+  __shared__ double zh[kMaxKrylov], tau_s[kMaxKrylov], val[kMaxKrylov];
+  __shared__ double rot_c[kMaxKrylov], rot_s[kMaxKrylov];
+  __shared__ int K_s[kMaxKrylov], nd_s[kMaxKrylov], df_s[kMaxKrylov], rank_s[kMaxKrylov];
+  __shared__ int rot_p[kMaxKrylov], rot_j[kMaxKrylov];
+  __shared__ int info[4];   // p, number of deflated, number of rotations, failure
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63;
+  const bool w0 = tid < 64;
+  if (m == 1) {
+    if (tid == 0) {
+      eig->lam[0] = st->alpha[0];
+      eig->Q[0] = 1.0;
+    }
+    __syncthreads();
+    return 0;
+  }
+  const int n1 = m - 1;
+  const double alpha = st->alpha[m - 1], beta = st->beta[m - 2];
+  for (int e = tid; e < n1 * n1; e += nthr) {
+    const int r = e / n1, c = e - r * n1;
+    Qs[r * 64 + c] = eig->Q[r * kMaxKrylov + c];
+  }
+  if (w0) {
+    if (lane < n1) {
+      dd[lane] = eig->lam[lane];
+      zz[lane] = beta * eig->Q[(n1 - 1) * kMaxKrylov + lane];
+    }
+    // deflation tolerance from |T_m| <= max(|lambda|, |alpha|) + |beta|
+    double amax = lane < n1 ? fabs(eig->lam[lane]) : 0.0;
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    const double tol = 8.0 * DBL_EPSILON * (fmax(amax, fabs(alpha)) + fabs(beta));
+    // the wavefront's LDS accesses complete in order: dd and zz are visible below
+    const double zj = lane < n1 ? zz[lane] : 0.0;
+    unsigned long long keep = __ballot(lane < n1 && fabs(zj) > tol);
+    // a kept entry and the kept entry before it that would rotate into one (parallel test;
+    // the rotations themselves are taken in order, below, only when some pair qualifies)
+    bool close = false;
+    if ((keep >> lane) & 1ull) {
+      const unsigned long long below = keep & ((1ull << lane) - 1ull);
+      if (below) {
+        const int q = 63 - __builtin_clzll(below);
+        const double zq = zz[q], r = sqrt(zq * zq + zj * zj);
+        close = fabs((zj / r) * (zq / r) * (dd[lane] - dd[q])) <= tol;
+      }
+    }
+    int nrot = 0;
+    if (__ballot(close)) {
+      // in order over the entries, every lane alike: a kept entry q followed by a kept j
+      // whose rotation deflates q
+      keep = 0;
+      int prev = -1;
+      for (int j = 0; j < n1; ++j) {
+        const double zjj = zz[j];
+        if (!(fabs(zjj) > tol)) continue;
+        if (prev >= 0) {
+          const double zp = zz[prev], r = sqrt(zp * zp + zjj * zjj);
+          const double c = zjj / r, sn = zp / r;
+          if (fabs(c * sn * (dd[j] - dd[prev])) <= tol) {
+            const double dp = dd[prev], dj = dd[j];
+            if (lane == 0) {
+              dd[prev] = c * c * dp + sn * sn * dj;
+              dd[j] = sn * sn * dp + c * c * dj;
+              zz[prev] = 0.0;
+              zz[j] = r;
+              rot_p[nrot] = prev;
+              rot_j[nrot] = j;
+              rot_c[nrot] = c;
+              rot_s[nrot] = sn;
+            }
+            ++nrot;
+            keep &= ~(1ull << prev);
+          }
+        }
+        keep |= 1ull << j;
+        prev = j;
+      }
+    }
+    const int p = __popcll(keep);
+    const unsigned long long lower = (1ull << lane) - 1ull;
+    if (lane < n1) {
+      if ((keep >> lane) & 1ull) {
+        const int q = __popcll(keep & lower);
+        dn[q] = dd[lane];
+        z2n[q] = zz[lane] * zz[lane];
+        nd_s[q] = lane;
+      } else {
+        df_s[__popcll(~keep & lower)] = lane;
+      }
+    }
+    if (lane == 0) {
+      info[0] = p;
+      info[1] = n1 - p;
+      info[2] = nrot;
+    }
+  }
+  __syncthreads();
+  const int p = info[0], ndf = info[1], nrot = info[2];
+  // the deflating rotations on the columns of the old Q, in order
+  for (int q = 0; q < nrot; ++q) {
+    const int a = rot_p[q], b = rot_j[q];
+    const double c = rot_c[q], sn = rot_s[q];
+    for (int r = tid; r < n1; r += nthr) {
+      const double qa = Qs[r * 64 + a], qb = Qs[r * 64 + b];
+      Qs[r * 64 + a] = c * qa - sn * qb;
+      Qs[r * 64 + b] = sn * qa + c * qb;
+    }
+    __syncthreads();
+  }
+  if (w0) {
+    int bad = 0;
+    if (lane <= p) {
+      // the roots (with p = 0 the arrowhead is alpha alone)
+      int K = -1;
+      double tau = 0.0;
+      if (p > 0) {
+        double zn2 = 0.0;
+        for (int j = 0; j < p; ++j) zn2 += z2n[j];
+        bad = !secular_root(lane, p, dn, z2n, alpha, sqrt(zn2), K, tau);
+      }
+      K_s[lane] = K;
+      tau_s[lane] = tau;
+      val[lane] = K >= 0 ? dn[K] + tau : alpha;
+    } else if (lane < m) {
+      val[lane] = dd[df_s[lane - p - 1]];
+    }
+    // the recomputed border: the numerator's roots paired with the denominator's poles
+    if (lane < p) {
+      const double dj = dn[lane];
+      double prod = 1.0;
+      for (int i = 0; i <= p; ++i) {
+        prod *= fabs((dj - dn[K_s[i]]) - tau_s[i]);
+        if (i < p && i != lane) prod /= fabs(dj - dn[i]);
+      }
+      zh[lane] = sqrt(prod);   // its sign: that of the border entry, which z2n does not keep
+      const double zs = zz[nd_s[lane]];
+      if (zs < 0.0) zh[lane] = -zh[lane];
+    }
+    // eigenvector lane of the arrowhead (entries 0..p-1 on the kept lambdas, p on e_m)
+    if (lane <= p) {
+      double nrm = 1.0;
+      if (p > 0) {
+        const int K = K_s[lane];
+        const double dK = dn[K], tau = tau_s[lane];
+        for (int j = 0; j < p; ++j) {
+          const double x = zh[j] / ((dn[j] - dK) - tau);
+          U[lane * 64 + j] = x;
+          nrm += x * x;
+        }
+      }
+      const double inv = 1.0 / sqrt(nrm);
+      for (int j = 0; j < p; ++j) U[lane * 64 + j] *= inv;
+      U[lane * 64 + p] = -inv;
+    }
+    // rank of every eigenvalue (ties by index)
+    if (lane < m) {
+      const double v = val[lane];
+      int r = 0;
+      for (int e = 0; e < m; ++e) {
+        const double ve = val[e];
+        r += (ve < v || (ve == v && e < lane)) ? 1 : 0;
+      }
+      rank_s[lane] = r;
+      eig->lam[r] = v;
+      bad |= !isfinite(v);
+    }
+    bad = __ballot(bad) != 0ull;
+    if (lane == 0) info[3] = bad;
+  }
+  __syncthreads();
+  // new eigenvectors: column rank(e) of Q_m, rows 0..m-1
+  for (int x = tid; x < m * m; x += nthr) {
+    const int e = x / m, r = x - e * m;
+    double v;
+    if (e <= p) {
+      if (r < n1) {
+        v = 0.0;
+        for (int j = 0; j < p; ++j) v += Qs[r * 64 + nd_s[j]] * U[e * 64 + j];
+      } else {
+        v = U[e * 64 + p];
+      }
+    } else {
+      v = r < n1 ? Qs[r * 64 + df_s[e - p - 1]] : 0.0;
+    }
+    eig->Q[r * kMaxKrylov + rank_s[e]] = v;
+  }
+  __syncthreads();
+  return info[3];
+}
+
+// Eigendecomposition of T_m (eig_update), then y_m = |w| Q L^{1/2} Q^T e_1, eps_m and the stop
+// test.  Every thread of the workgroup calls this; the first wavefront forms y_m and the status.
+__device__ void tridiag_body(int m, double tol, LzState *__restrict__ st, LzEig *__restrict__ eig) {
+  __shared__ double Rz[kMaxKrylov];   // sqrt(lambda_k) q_k[0]
+  const int failed = eig_update(m, st, eig);
+  const int lane = threadIdx.x;
+  if (lane >= 64) return;
+  const double lmin = eig->lam[0], lmax = eig->lam[m - 1];
+  double amax = lane < m ? fabs(st->alpha[lane]) : 0.0;
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  // y_m = |w| Q L^{1/2} Q^T e_1: lane k forms sqrt(lambda_k) q_k[0], then lane r sums row r
+  if (lane < m) Rz[lane] = sqrt(fmax(eig->lam[lane], 0.0)) * eig->Q[lane];
   const double wn = st->wnorm;
   double yr = 0.0;
   if (lane < m) {
-    for (int k = 0; k < m; ++k) yr += Rz[k] * Z[k * 64 + lane];
+    for (int k = 0; k < m; ++k) yr += Rz[k] * eig->Q[lane * kMaxKrylov + k];
     yr *= wn;
   }
   // eps_m in the orthonormal Krylov basis
@@ -357,8 +549,8 @@ __device__ __forceinline__ void post_status(const LzState *__restrict__ st, LzRi
 // A process that has stopped (reason != 0) keeps its state: an iteration enqueued after the
 // stop leaves y, eps, m and reason as they are (and posts them again).
 __global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st,
-                                                   LzRingSlot *slot) {
-  if (st->reason == 0) tridiag_body(m, tol, st);
+                                                   LzEig *__restrict__ eig, LzRingSlot *slot) {
+  if (st->reason == 0) tridiag_body(m, tol, st, eig);
   if (threadIdx.x == 0) post_status(st, slot);
 }
 
@@ -414,9 +606,9 @@ __device__ __forceinline__ void group_sums(double (&v)[NV], double *sh) {
   __syncthreads();
 }
 
-__device__ void lanczos_step_body(LzState *__restrict__ st, double *__restrict__ V,
-                                  double *__restrict__ u, int64_t m3, int64_t e0, int64_t e1,
-                                  int k, double tol, bool write_next) {
+__device__ void lanczos_step_body(LzState *__restrict__ st, LzEig *__restrict__ eig,
+                                  double *__restrict__ V, double *__restrict__ u, int64_t m3,
+                                  int64_t e0, int64_t e1, int k, double tol, bool write_next) {
   __shared__ double sh[8 * (kThreads / 64)];
   __shared__ double hs[kMaxKrylov];
   const int t = threadIdx.x;
@@ -466,7 +658,7 @@ __device__ void lanczos_step_body(LzState *__restrict__ st, double *__restrict__
   }
   if (t < k) st->h[t] = hs[t];
   __syncthreads();
-  tridiag_body(k, tol, st);
+  tridiag_body(k, tol, st, eig);
   __syncthreads();
   if (write_next && st->reason == 0) {
     double *next = V + int64_t(k) * m3;
@@ -479,11 +671,12 @@ __device__ void lanczos_step_body(LzState *__restrict__ st, double *__restrict__
 // posts the status again.  (Every thread reads the same reason: it is written only after the
 // workgroup's first barrier.)
 __global__ __launch_bounds__(kThreads) void lanczos_step(LzState *__restrict__ st,
+                                                         LzEig *__restrict__ eig,
                                                          double *__restrict__ V,
                                                          double *__restrict__ u, int64_t m3, int k,
                                                          double tol, int write_next,
                                                          LzRingSlot *slot) {
-  if (st->reason == 0) lanczos_step_body(st, V, u, m3, 0, m3, k, tol, write_next != 0);
+  if (st->reason == 0) lanczos_step_body(st, eig, V, u, m3, 0, m3, k, tol, write_next != 0);
   if (threadIdx.x == 0) post_status(st, slot);
 }
 
@@ -500,6 +693,7 @@ struct SegView {
   const int *sys_of;      // sphere -> system (device)
   LzState *st;            // nsys states
   int *done;              // nsys flags
+  LzEig *eig;             // nsys eigendecompositions
 };
 
 // part[s * kSegBlocks + b] = partial dot of a and b over system s
@@ -593,7 +787,7 @@ __global__ void seg_reorth_update(SegView v, int64_t m, int nvec, const double *
 __global__ __launch_bounds__(64) void tridiag_sqrt_batched(SegView v, int m, double tol) {
   const int s = blockIdx.x;
   if (v.done[s]) return;
-  tridiag_body(m, tol, v.st + s);
+  tridiag_body(m, tol, v.st + s, v.eig + s);
   if (threadIdx.x == 0 && v.st[s].reason != 0) v.done[s] = 1;
 }
 
@@ -604,7 +798,8 @@ __global__ __launch_bounds__(kThreads) void seg_lanczos_step(SegView v, double *
   const int s = blockIdx.x;
   if (v.done[s]) return;
   LzState *st = v.st + s;
-  lanczos_step_body(st, V, u, m3, 3 * v.offs[s], 3 * v.offs[s + 1], k, tol, write_next != 0);
+  lanczos_step_body(st, v.eig + s, V, u, m3, 3 * v.offs[s], 3 * v.offs[s + 1], k, tol,
+                    write_next != 0);
   if (threadIdx.x == 0 && st->reason != 0) v.done[s] = 1;
 }
 
@@ -713,6 +908,8 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   if (!part) return st;
   LzState *ls = static_cast<LzState *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
   if (!ls) return st;
+  LzEig *eig = static_cast<LzEig *>(workspace(ctx, WS_LZEIG, sizeof(LzEig), &st));
+  if (!eig) return st;
   // The host reads the status of iteration m only after iteration m + 1 has been enqueued,
   // so the device never idles while the host decides.  Every kernel of an iteration enqueued
   // after the stop leaves the result unchanged: the product's kernels return at once while
@@ -751,7 +948,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
       RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream, stopped));
     }
     if (m3 <= kFusedSegment) {   // the whole iteration's vector work in one workgroup
-      lanczos_step<<<1, kThreads, 0, stream>>>(ls, V, u, m3, k, tol, k < max_iter,
+      lanczos_step<<<1, kThreads, 0, stream>>>(ls, eig, V, u, m3, k, tol, k < max_iter,
                                                   &ring_dev->slot[k & 1]);
       RPB_LAUNCHED(ctx);
     } else {
@@ -769,7 +966,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
         RPB_LAUNCHED(ctx);
       }
       RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[k - 1], 1, stream));
-      tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls, &ring_dev->slot[k & 1]);
+      tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls, eig, &ring_dev->slot[k & 1]);
       RPB_LAUNCHED(ctx);
       if (k < max_iter) {
         scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
@@ -836,8 +1033,10 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
   char *lz = static_cast<char *>(
       workspace(ctx, WS_LZBATCH, status_off + size_t(nsys) * sizeof(LzStatus), &st));
   if (!lz) return st;
+  LzEig *eig = static_cast<LzEig *>(workspace(ctx, WS_LZEIG, size_t(nsys) * sizeof(LzEig), &st));
+  if (!eig) return st;
   SegView v{b.offs, b.sys_of, reinterpret_cast<LzState *>(lz),
-            reinterpret_cast<int *>(lz + states_bytes)};
+            reinterpret_cast<int *>(lz + states_bytes), eig};
   LzStatus *status_dev = reinterpret_cast<LzStatus *>(lz + status_off);
   const unsigned ns = unsigned(nsys);
   const int f_alpha = int(offsetof(LzState, alpha) / sizeof(double));

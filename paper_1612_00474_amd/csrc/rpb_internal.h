@@ -41,6 +41,7 @@ enum Slot {
   WS_PRECOND,       // block-diagonal preconditioner: L (3n) and a scaled vector (3n)
   WS_CELLS,         // steric cell list: cells, buckets, sorted lists, bucket counts and starts
   WS_MBATCH,        // batched multi-vector products: per-system item and partial offsets
+  WS_LZEIG,         // Lanczos: eigendecomposition of T_m per Krylov process
   WS_NSLOTS
 };
 
