@@ -138,8 +138,9 @@ int rpb_mobility_matvec_rows(rpb_ctx *ctx, const rpb_params *p, int64_t n, const
 /* Brownian increment ------------------------------------------------------------------
  *
  * out ~ M^{1/2} w by the Krylov/Lanczos method of Ando et al. (paper, Sec. II.C): m Lanczos
- * steps on K_m(M, w) with full re-orthogonalisation, T_m = Q L Q^T by an implicit-QL
- * eigensolve on the device, g_m = |w| V_m Q L^{1/2} Q^T e_1.  Stops at the first m >= 2
+ * steps on K_m(M, w) with full re-orthogonalisation, T_m = Q L Q^T on the device (updated
+ * each step from T_{m-1}'s eigendecomposition, as lanczos_tridiag_sqrt below),
+ * g_m = |w| V_m Q L^{1/2} Q^T e_1.  Stops at the first m >= 2
  * with eps_m = |g_m - g_{m-1}| / |g_{m-1}| < tol (evaluated in the orthonormal basis), or
  * when the Krylov space is invariant (exact result, RPB_OK), or at max_iter
  * (RPB_ENOCONV, out = g_max_iter).  Only M (not M_C) enters.
@@ -162,6 +163,20 @@ int lanczos_sqrt_apply(rpb_ctx *ctx, const rpb_params *p, int64_t n, const doubl
 int lanczos_sqrt_apply_precond(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *pos,
                                const double *w, double tol, int max_iter, double *out,
                                int *iters_out, double *eps_out, rpb_stream_t stream);
+
+/* The small dense step of the same method (Sec. II.C) on its own: for the symmetric
+ * tridiagonal T with diagonal alpha[0..m-1] and off-diagonal beta[0..m-2], the vectors
+ * y_k = wnorm T_k^{1/2} e_1 of its leading k x k blocks T_k, k = 1..m, in the order and by the
+ * device code of the Lanczos solves: T_k = Q L Q^T from the arrowhead matrix that T_{k-1}'s
+ * eigenvectors make of T_k (secular equation, one root per lane, deflation of negligible
+ * couplings, eigenvectors from the recomputed coupling of Gu and Eisenstat), then
+ * y_k = wnorm Q L^{1/2} Q^T e_1 with negative eigenvalues taken as zero.
+ * alpha, beta: host arrays (beta may be NULL when m = 1), finite; wnorm finite, >= 0.
+ * y_out: host array of m * m doubles, row k - 1 holding y_k in its first k entries and zeros
+ * after.  1 <= m <= 64.  Synchronises the stream.  RPB_EDEVICE if an eigenvalue iteration
+ * does not converge. */
+int lanczos_tridiag_sqrt(rpb_ctx *ctx, int32_t m, const double *alpha, const double *beta,
+                         double wnorm, double *y_out, rpb_stream_t stream);
 
 /* Stochastic drift --------------------------------------------------------------------
  *

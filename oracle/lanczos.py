@@ -20,6 +20,8 @@ the closed-form diagonal square root; the sample covariance of g over many W
 approaches M (fluctuation-dissipation, eq. BD).  The preconditioned variant at
 m = 3N equals L B^{1/2} W with (L B^{1/2})(L B^{1/2})^T = M, and its scale reproduces the
 wall self-mobility series.
+``tridiag_sqrt_e1`` matches the closed-form root of a 2 x 2 matrix, the diagonal case and
+scipy's Schur-based ``sqrtm`` of the dense T.
 """
 from __future__ import annotations
 
@@ -70,6 +72,18 @@ def lanczos_sqrt(apply_m, w, tol, max_iter=64, breakdown_rel=1e-14, notspd_rel=1
         V.append(u / beta)
         g_prev = g
     return g, max_iter, eps, "noconv"
+
+
+def tridiag_sqrt_e1(alpha, beta, wnorm=1.0):
+    """|w| T^{1/2} e_1 for the symmetric tridiagonal T with diagonal ``alpha`` and
+    off-diagonal ``beta`` (len(alpha) - 1 entries): the small dense step of Sec. II.C that
+    turns the Lanczos coefficients into the coordinates of g_m in the Krylov basis.  From the
+    eigendecomposition T = Q Lambda Q^T, negative eigenvalues clamped at zero as in
+    ``lanczos_sqrt``."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    lam, Q = scipy.linalg.eigh_tridiagonal(alpha, beta)
+    return wnorm * Q @ (np.sqrt(np.maximum(lam, 0.0)) * Q[0])
 
 
 def sqrtm_dense(M):

@@ -30,7 +30,7 @@ EXPORTS = (
     "rpb_step_graph_create", "rpb_step_graph_launch", "rpb_step_graph_status",
     "rpb_step_graph_destroy", "rpb_get_tuning", "rpb_set_tuning", "rpb_autotune",
     "rpb_mobility_matvec_multi", "lanczos_sqrt_apply_multi", "rpb_output_check_enable",
-    "rpb_mobility_matvec_noalloc",
+    "rpb_mobility_matvec_noalloc", "lanczos_tridiag_sqrt",
 )
 
 
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
                                          C.POINTER(D), P]),
         "lanczos_sqrt_apply_precond": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P,
                                                  C.POINTER(C.c_int), C.POINTER(D), P]),
+        "lanczos_tridiag_sqrt": (C.c_int, [P, C.c_int32, P, P, D, P, P]),
         "rfd_drift": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, P]),
         "rfd_drift_one_sided": (C.c_int, [P, pp, I64, P, P, D, C.c_int, P, P]),
         "rpb_forces": (C.c_int, [P, pp, I64, P, D, D, D, P, P]),
@@ -302,6 +303,22 @@ class Context:
             (RPB_ENOTSPD,) if allow_notspd else ())
         self._check(st, ok)
         return out, it.value, eps.value, st
+
+    def tridiag_sqrt(self, alpha, beta, wnorm=1.0):
+        """y_k = wnorm T_k^{1/2} e_1 for the leading blocks T_k (k = 1..m) of the symmetric
+        tridiagonal (alpha, beta); returns an (m, m) float64 array, row k - 1 holding y_k."""
+        import numpy as np
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64).ravel()
+        beta = np.ascontiguousarray(beta, dtype=np.float64).ravel()
+        m = alpha.size
+        if beta.size != max(m - 1, 0):
+            raise ValueError("beta must have len(alpha) - 1 entries")
+        out = np.zeros((m, m), dtype=np.float64)
+        st = self.lib.lanczos_tridiag_sqrt(self.h, m, alpha.ctypes.data,
+                                           beta.ctypes.data if beta.size else None,
+                                           float(wnorm), out.ctypes.data, _stream())
+        self._check(st)
+        return out
 
     def rfd(self, pos, w_tilde, delta, precision="fp64", rfd_precision="fp64", out=None,
             rfd_scheme="centred"):

@@ -81,8 +81,8 @@ int lz_ring_fence(rpb_ctx *ctx) {
   return RPB_OK;
 }
 
-// Marks ring slot q with event q: the iteration's last status-writing kernel (lanczos_step or
-// tridiag_sqrt, which store the status words into the slot) precedes it on the stream.
+// Marks ring slot q with event q: the iteration's status-writing kernel (lanczos_step or
+// beta_eig, which store the status words into the slot) precedes it on the stream.
 int lz_ring_post(rpb_ctx *ctx, int q, hipStream_t stream) {
   if (!ctx->lz_ev[q]) RPB_HIP(ctx, hipEventCreateWithFlags(&ctx->lz_ev[q], hipEventDisableTiming));
   RPB_HIP(ctx, hipEventRecord(ctx->lz_ev[q], stream));
@@ -110,27 +110,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
-__global__ __launch_bounds__(kThreads) void dot_partial(int64_t m, const double *__restrict__ a,
-                                                        const double *__restrict__ b,
-                                                        double *__restrict__ part) {
-  __shared__ double sh[kThreads];
-  double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
-       i += int64_t(gridDim.x) * kThreads)
-    acc += a[i] * b[i];
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
 
-// out = sum(part) (mode 0) or sqrt(sum(part)) (mode 1)
-__global__ __launch_bounds__(kThreads) void dot_finish(const double *__restrict__ part, int np,
-                                                       double *__restrict__ out, int mode) {
-  __shared__ double sh[kThreads];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[i];
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[0] = mode == 1 ? sqrt(s) : s;
-}
 
 __global__ void scale_by_inverse(int64_t m, const double *__restrict__ x,
                                  const double *__restrict__ d, double *__restrict__ y,
@@ -142,51 +122,9 @@ __global__ void scale_by_inverse(int64_t m, const double *__restrict__ x,
   y[i] = s > 0.0 ? x[i] / s : 0.0;
 }
 
-// u -= alpha v + beta vprev
-__global__ void three_term(int64_t m, double *__restrict__ u, const double *__restrict__ v,
-                           const double *__restrict__ vprev, const double *__restrict__ alpha,
-                           const double *__restrict__ beta) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double x = u[i] - alpha[0] * v[i];
-  if (vprev) x -= beta[0] * vprev[i];
-  u[i] = x;
-}
 
-// part[k * gridDim.x + b] = partial dot of V_k and u over block b's share
-__global__ __launch_bounds__(kThreads) void reorth_dots(int64_t m, const double *__restrict__ V,
-                                                        const double *__restrict__ u,
-                                                        double *__restrict__ part) {
-  __shared__ double sh[kThreads];
-  const int k = blockIdx.y;
-  const double *vk = V + int64_t(k) * m;
-  double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
-       i += int64_t(gridDim.x) * kThreads)
-    acc += vk[i] * u[i];
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[int64_t(k) * gridDim.x + blockIdx.x] = s;
-}
 
-// h[k] = sum of the np partials of V_k . u; one workgroup per basis vector k
-__global__ __launch_bounds__(kThreads) void reorth_finish(int np, const double *__restrict__ part,
-                                                          double *__restrict__ h) {
-  __shared__ double sh[kThreads];
-  const int k = blockIdx.x;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[int64_t(k) * np + i];
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) h[k] = s;
-}
 
-__global__ void reorth_update(int64_t m, int nvec, const double *__restrict__ V,
-                              const double *__restrict__ h, double *__restrict__ u) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double proj = 0.0;
-  for (int k = 0; k < nvec; ++k) proj += h[k] * V[int64_t(k) * m + i];
-  u[i] -= proj;
-}
 
 // out = V y (first nvec rows of V)
 __global__ void basis_combine(int64_t m, int nvec, const double *__restrict__ V,
@@ -546,14 +484,6 @@ __device__ __forceinline__ void post_status(const LzState *__restrict__ st, LzRi
   __threadfence_system();
 }
 
-// A process that has stopped (reason != 0) keeps its state: an iteration enqueued after the
-// stop leaves y, eps, m and reason as they are (and posts them again).
-__global__ __launch_bounds__(64) void tridiag_sqrt(int m, double tol, LzState *__restrict__ st,
-                                                   LzEig *__restrict__ eig, LzRingSlot *slot) {
-  if (st->reason == 0) tridiag_body(m, tol, st, eig);
-  if (threadIdx.x == 0) post_status(st, slot);
-}
-
 __global__ void lz_reset(LzState *st) {
   const int t = threadIdx.x;
   if (t < kMaxKrylov) {
@@ -569,6 +499,108 @@ __global__ void lz_reset(LzState *st) {
     st->m = 0;
     st->reason = 0;
   }
+}
+
+// ---- one Lanczos iteration of a single system in seven kernels (segments > kFusedSegment) ----
+//
+// Sums in two stages, kRedBlocks workgroup partials and their sum in a fixed order by one
+// workgroup (a last-arriving workgroup could take the second stage, but its device-scope
+// release fence writes back its XCD's L2 and cost more than the launch it saved).  The
+// three-term recurrence is applied where its result is read, and the second stage of |u|
+// shares its workgroup with the eigensolve.  The arithmetic and its order are those of one
+// kernel per step.
+
+__global__ __launch_bounds__(kThreads) void dot_partial(int64_t m, const double *__restrict__ a,
+                                                        const double *__restrict__ b,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kThreads)
+    acc += a[i] * b[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out = sum(part) (mode 0) or sqrt(sum(part)) (mode 1)
+__global__ __launch_bounds__(kThreads) void dot_finish(const double *__restrict__ part, int np,
+                                                       double *__restrict__ out, int mode) {
+  __shared__ double sh[kThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = mode == 1 ? sqrt(s) : s;
+}
+
+// part[j * gridDim.x + b] = partial of V_j . (u - alpha_k v_k - beta_{k-1} v_{k-1}) over
+// workgroup b's share (grid y: j < k); u is not modified.
+__global__ __launch_bounds__(kThreads) void reorth_dots_3t(
+    int64_t m, const double *__restrict__ V, const double *__restrict__ u,
+    const double *__restrict__ vk, const double *__restrict__ vprev,
+    const double *__restrict__ alpha, const double *__restrict__ beta,
+    double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int j = blockIdx.y;
+  const double *vj = V + int64_t(j) * m;
+  const double al = alpha[0], be = vprev ? beta[0] : 0.0;
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kThreads) {
+    double x = u[i] - al * vk[i];
+    if (vprev) x -= be * vprev[i];
+    acc += vj[i] * x;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = s;
+}
+
+// h[j] = sum of the np partials of V_j . u; one workgroup per basis vector j
+__global__ __launch_bounds__(kThreads) void reorth_finish(int np, const double *__restrict__ part,
+                                                          double *__restrict__ h) {
+  __shared__ double sh[kThreads];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[int64_t(j) * np + i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) h[j] = s;
+}
+
+// u <- u - alpha_k v_k - beta_{k-1} v_{k-1} - sum_j h_j V_j, and the workgroup partials of |u|^2
+__global__ __launch_bounds__(kThreads) void reorth_update_sq(
+    int64_t m, int k, const double *__restrict__ V, double *__restrict__ u,
+    const double *__restrict__ vk, const double *__restrict__ vprev,
+    const LzState *__restrict__ st, double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  const double al = st->alpha[k - 1], be = vprev ? st->beta[k - 2] : 0.0;
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * kThreads) {
+    double x = u[i] - al * vk[i];
+    if (vprev) x -= be * vprev[i];
+    double proj = 0.0;
+    for (int j = 0; j < k; ++j) proj += st->h[j] * V[int64_t(j) * m + i];
+    x -= proj;
+    u[i] = x;
+    acc += x * x;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// beta_k = sqrt(sum of the np partials), then the eigensolve of T_k with its stop test (unless
+// the process has stopped) and the status words into the host's ring slot.
+__global__ __launch_bounds__(kThreads) void beta_eig(int np, const double *__restrict__ part,
+                                                     int k, double tol, LzState *__restrict__ st,
+                                                     LzEig *__restrict__ eig, LzRingSlot *slot) {
+  __shared__ double sh[kThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) st->beta[k - 1] = sqrt(s);
+  __syncthreads();
+  // every thread reads the same reason: only tridiag_body writes it, after its barriers
+  if (st->reason == 0) tridiag_body(k, tol, st, eig);
+  if (threadIdx.x == 0) post_status(st, slot);
 }
 
 // Longest segment (3 n values of one system) that one workgroup takes through a whole Lanczos
@@ -733,31 +765,25 @@ __global__ void seg_scale_by_inverse(SegView v, int64_t m, const double *__restr
   y[i] = d > 0.0 ? x[i] / d : 0.0;
 }
 
-__global__ void seg_three_term(SegView v, int64_t m, int k, double *__restrict__ u,
-                               const double *__restrict__ vk, const double *__restrict__ vprev) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const int s = v.sys_of[i / 3];
-  if (v.done[s]) return;
-  double x = u[i] - v.st[s].alpha[k - 1] * vk[i];
-  if (vprev) x -= v.st[s].beta[k - 2] * vprev[i];
-  u[i] = x;
-}
-
-// part[(s * nvec + j) * kSegBlocks + b] = partial dot of V_j and u over system s
-__global__ __launch_bounds__(kThreads) void seg_reorth_dots(SegView v, int64_t m, int nvec,
-                                                            const double *__restrict__ V,
-                                                            const double *__restrict__ u,
-                                                            double *__restrict__ part) {
+// part[(s * nvec + j) * kSegBlocks + b] = partial dot of V_j and u - alpha_k v_k -
+// beta_{k-1} v_{k-1} over system s (the three-term recurrence applied where it is read; u is
+// not modified), nvec = k
+__global__ __launch_bounds__(kThreads) void seg_reorth_dots_3t(
+    SegView v, int64_t m, int nvec, const double *__restrict__ V, const double *__restrict__ u,
+    const double *__restrict__ vk, const double *__restrict__ vprev, double *__restrict__ part) {
   __shared__ double sh[kThreads];
   const int s = blockIdx.z, j = blockIdx.y;
   if (v.done[s]) return;
   const int64_t e0 = 3 * v.offs[s], e1 = 3 * v.offs[s + 1];
   const double *vj = V + int64_t(j) * m;
+  const double al = v.st[s].alpha[nvec - 1], be = vprev ? v.st[s].beta[nvec - 2] : 0.0;
   double acc = 0.0;
   for (int64_t i = e0 + int64_t(blockIdx.x) * kThreads + threadIdx.x; i < e1;
-       i += int64_t(kSegBlocks) * kThreads)
-    acc += vj[i] * u[i];
+       i += int64_t(kSegBlocks) * kThreads) {
+    double x = u[i] - al * vk[i];
+    if (vprev) x -= be * vprev[i];
+    acc += vj[i] * x;
+  }
   const double r = block_sum(acc, sh);
   if (threadIdx.x == 0) part[(int64_t(s) * nvec + j) * kSegBlocks + blockIdx.x] = r;
 }
@@ -773,22 +799,64 @@ __global__ __launch_bounds__(64) void seg_reorth_finish(SegView v, int nvec,
   }
 }
 
-__global__ void seg_reorth_update(SegView v, int64_t m, int nvec, const double *__restrict__ V,
-                                  double *__restrict__ u) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const int s = v.sys_of[i / 3];
+// u <- u - alpha_k v_k - beta_{k-1} v_{k-1} - sum_j h_j V_j on every live system, and
+// part[s * kSegBlocks + b] = the partial of |u|^2 over system s
+__global__ __launch_bounds__(kThreads) void seg_reorth_update_sq(
+    SegView v, int64_t m, int k, const double *__restrict__ V, double *__restrict__ u,
+    const double *__restrict__ vk, const double *__restrict__ vprev, double *__restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int s = blockIdx.y;
   if (v.done[s]) return;
-  double proj = 0.0;
-  for (int j = 0; j < nvec; ++j) proj += v.st[s].h[j] * V[int64_t(j) * m + i];
-  u[i] -= proj;
+  const int64_t e0 = 3 * v.offs[s], e1 = 3 * v.offs[s + 1];
+  const LzState &st = v.st[s];
+  const double al = st.alpha[k - 1], be = vprev ? st.beta[k - 2] : 0.0;
+  double acc = 0.0;
+  for (int64_t i = e0 + int64_t(blockIdx.x) * kThreads + threadIdx.x; i < e1;
+       i += int64_t(kSegBlocks) * kThreads) {
+    double x = u[i] - al * vk[i];
+    if (vprev) x -= be * vprev[i];
+    double proj = 0.0;
+    for (int j = 0; j < k; ++j) proj += st.h[j] * V[int64_t(j) * m + i];
+    x -= proj;
+    u[i] = x;
+    acc += x * x;
+  }
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[int64_t(s) * kSegBlocks + blockIdx.x] = r;
 }
 
-__global__ __launch_bounds__(64) void tridiag_sqrt_batched(SegView v, int m, double tol) {
+// beta_k = sqrt(sum of the system's kSegBlocks partials, in order), then the eigensolve of T_k
+// with its stop test; a stopped system is frozen.
+__global__ __launch_bounds__(64) void seg_beta_eig(SegView v, int m, double tol,
+                                                   const double *__restrict__ part) {
   const int s = blockIdx.x;
   if (v.done[s]) return;
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int b = 0; b < kSegBlocks; ++b) acc += part[int64_t(s) * kSegBlocks + b];
+    v.st[s].beta[m - 1] = sqrt(acc);
+  }
+  __syncthreads();
   tridiag_body(m, tol, v.st + s, v.eig + s);
   if (threadIdx.x == 0 && v.st[s].reason != 0) v.done[s] = 1;
+}
+
+// The eigensolve of T_1, T_2, ..., T_m in turn (as a Krylov process meets them), row k - 1 of
+// ys (m doubles) receiving y_k = |w| T_k^{1/2} e_1 (entries k..m-1 zero); fail[0] = 1 when an
+// eigensolve fails.  The stop tests are evaluated but do not stop the sequence.
+__global__ __launch_bounds__(64) void tridiag_sequence(int m, LzState *__restrict__ st,
+                                                       LzEig *__restrict__ eig,
+                                                       double *__restrict__ ys,
+                                                       int *__restrict__ fail) {
+  const int t = threadIdx.x;
+  if (t == 0) fail[0] = 0;
+  for (int k = 1; k <= m; ++k) {
+    tridiag_body(k, 0.0, st, eig);
+    __syncthreads();
+    if (t < m) ys[int64_t(k - 1) * m + t] = t < k ? st->y[t] : 0.0;
+    if (t == 0 && st->reason == 4) fail[0] = 1;
+    __syncthreads();
+  }
 }
 
 // lanczos_step_body for every live system, one workgroup each (segments <= kFusedSegment).
@@ -874,6 +942,7 @@ __global__ void multiply_by(int64_t m, double *x, const double *__restrict__ s) 
 
 inline unsigned nblk(int64_t m) { return unsigned((m + kThreads - 1) / kThreads); }
 
+
 int dot(rpb_ctx *ctx, int64_t m, const double *a, const double *b, double *part, double *out,
         int mode, hipStream_t stream) {
   dot_partial<<<kRedBlocks, kThreads, 0, stream>>>(m, a, b, part);
@@ -913,8 +982,9 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   // The host reads the status of iteration m only after iteration m + 1 has been enqueued,
   // so the device never idles while the host decides.  Every kernel of an iteration enqueued
   // after the stop leaves the result unchanged: the product's kernels return at once while
-  // ls->reason is nonzero, tridiag_sqrt keeps y, eps and reason, and the other kernels touch
-  // only u, V's next column and entries of alpha and beta past the last iteration.
+  // ls->reason is nonzero, the eigensolve is skipped (y, eps and reason stay), and the other
+  // kernels touch only u, h, V's next column and entries of alpha and beta past the last
+  // iteration.
   RPB_TRY(lz_ring_fence(ctx));
   LzRing *ring = lz_ring(ctx);
   LzRing *ring_dev = lz_ring_dev(ctx);
@@ -951,22 +1021,18 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
       lanczos_step<<<1, kThreads, 0, stream>>>(ls, eig, V, u, m3, k, tol, k < max_iter,
                                                   &ring_dev->slot[k & 1]);
       RPB_LAUNCHED(ctx);
-    } else {
+    } else {   // seven kernels (see dot_partial)
       RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
-      three_term<<<nblk(m3), kThreads, 0, stream>>>(m3, u, vm, vprev, &ls->alpha[k - 1],
-                                                     k > 1 ? &ls->beta[k - 2] : nullptr);
+      const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
+      reorth_dots_3t<<<grid, kThreads, 0, stream>>>(m3, V, u, vm, vprev, &ls->alpha[k - 1],
+                                                     k > 1 ? &ls->beta[k - 2] : nullptr, part);
       RPB_LAUNCHED(ctx);
-      {
-        const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
-        reorth_dots<<<grid, kThreads, 0, stream>>>(m3, V, u, part);
-        RPB_LAUNCHED(ctx);
-        reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
-        RPB_LAUNCHED(ctx);
-        reorth_update<<<nblk(m3), kThreads, 0, stream>>>(m3, k, V, ls->h, u);
-        RPB_LAUNCHED(ctx);
-      }
-      RPB_TRY(dot(ctx, m3, u, u, part, &ls->beta[k - 1], 1, stream));
-      tridiag_sqrt<<<1, 64, 0, stream>>>(k, tol, ls, eig, &ring_dev->slot[k & 1]);
+      reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
+      RPB_LAUNCHED(ctx);
+      reorth_update_sq<<<kRedBlocks, kThreads, 0, stream>>>(m3, k, V, u, vm, vprev, ls, part);
+      RPB_LAUNCHED(ctx);
+      beta_eig<<<1, kThreads, 0, stream>>>(kRedBlocks, part, k, tol, ls, eig,
+                                           &ring_dev->slot[k & 1]);
       RPB_LAUNCHED(ctx);
       if (k < max_iter) {
         scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
@@ -1082,17 +1148,15 @@ int lanczos_segments(rpb_ctx *ctx, const Batch &b, const double *L, double *t, c
       RPB_LAUNCHED(ctx);
     } else {
       RPB_TRY(seg_dot(vk, u, f_alpha + k - 1, 0));
-      seg_three_term<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, u, vk, vprev);
-      RPB_LAUNCHED(ctx);
-      seg_reorth_dots<<<dim3{unsigned(kSegBlocks), unsigned(k), ns}, kThreads, 0, stream>>>(
-          v, m3, k, V, u, part);
+      seg_reorth_dots_3t<<<dim3{unsigned(kSegBlocks), unsigned(k), ns}, kThreads, 0, stream>>>(
+          v, m3, k, V, u, vk, vprev, part);
       RPB_LAUNCHED(ctx);
       seg_reorth_finish<<<ns, 64, 0, stream>>>(v, k, part);
       RPB_LAUNCHED(ctx);
-      seg_reorth_update<<<nblk(m3), kThreads, 0, stream>>>(v, m3, k, V, u);
+      seg_reorth_update_sq<<<dim3{unsigned(kSegBlocks), ns, 1u}, kThreads, 0, stream>>>(
+          v, m3, k, V, u, vk, vprev, part);
       RPB_LAUNCHED(ctx);
-      RPB_TRY(seg_dot(u, u, f_beta + k - 1, 1));
-      tridiag_sqrt_batched<<<ns, 64, 0, stream>>>(v, k, tol);
+      seg_beta_eig<<<ns, 64, 0, stream>>>(v, k, tol, part);
       RPB_LAUNCHED(ctx);
       seg_all_done<<<1, 256, 0, stream>>>(v, nsys);
       RPB_LAUNCHED(ctx);
@@ -1306,4 +1370,43 @@ extern "C" int lanczos_sqrt_apply_multi(rpb_ctx *ctx, const rpb_params *p, int64
     if (eps_out) eps_out[s] = stat[s].eps;
   }
   return lanczos_status_code(ctx, stat, nvec);
+}
+
+extern "C" int lanczos_tridiag_sqrt(rpb_ctx *ctx, int32_t m, const double *alpha,
+                                    const double *beta, double wnorm, double *y_out,
+                                    rpb_stream_t stream_) {
+  if (!ctx) return RPB_EINVAL;
+  if (m < 1 || m > kMaxKrylov) return fail(ctx, RPB_EINVAL, "m must be in [1, %d]", kMaxKrylov);
+  if (!alpha || (m > 1 && !beta) || !y_out)
+    return fail(ctx, RPB_EINVAL, "alpha, beta and y_out must not be NULL");
+  if (!std::isfinite(wnorm) || wnorm < 0.0)
+    return fail(ctx, RPB_EINVAL, "wnorm must be finite and >= 0");
+  LzState h{};
+  for (int i = 0; i < m; ++i) {
+    if (!std::isfinite(alpha[i]) || (i < m - 1 && !std::isfinite(beta[i])))
+      return fail(ctx, RPB_EINVAL, "alpha and beta must be finite");
+    h.alpha[i] = alpha[i];
+    if (i < m - 1) h.beta[i] = beta[i];
+  }
+  h.wnorm = wnorm;
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  RPB_HIP(ctx, hipSetDevice(ctx->device));
+  int st;
+  LzState *ls = static_cast<LzState *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
+  if (!ls) return st;
+  LzEig *eig = static_cast<LzEig *>(workspace(ctx, WS_LZEIG, sizeof(LzEig), &st));
+  if (!eig) return st;
+  const size_t ybytes = size_t(m) * size_t(m) * sizeof(double);
+  char *buf = static_cast<char *>(workspace(ctx, WS_VEC_A, ybytes + sizeof(int), &st));
+  if (!buf) return st;
+  int *flag = reinterpret_cast<int *>(buf + ybytes);
+  RPB_HIP(ctx, hipMemcpyAsync(ls, &h, sizeof(LzState), hipMemcpyHostToDevice, stream));
+  tridiag_sequence<<<1, 64, 0, stream>>>(m, ls, eig, reinterpret_cast<double *>(buf), flag);
+  RPB_LAUNCHED(ctx);
+  int failed = 0;
+  RPB_HIP(ctx, hipMemcpyAsync(y_out, buf, ybytes, hipMemcpyDeviceToHost, stream));
+  RPB_HIP(ctx, hipMemcpyAsync(&failed, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RPB_HIP(ctx, hipStreamSynchronize(stream));
+  if (failed) return fail(ctx, RPB_EDEVICE, "tridiagonal eigensolve did not converge");
+  return RPB_OK;
 }

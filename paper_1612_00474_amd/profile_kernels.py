@@ -1,10 +1,12 @@
 """Kernel profiling driver (run under rocprofv3).
 
-Tunes the launch shapes on one synthetic sheet of N spheres (as the benchmark does), then
-launches one plain device-to-device copy of known size (to calibrate the HBM byte counters
-FETCH_SIZE / WRITE_SIZE against a kernel whose traffic is known) followed by `--reps`
-launches of each pair-kernel variant, of the multi-vector kernel (four vectors per launch)
-and of the steric force kernel.  Only the dispatches after the copy count:
+On one synthetic sheet of N spheres, launches one plain device-to-device copy of known size
+(to calibrate the HBM byte counters FETCH_SIZE / WRITE_SIZE against a kernel whose traffic is
+known) followed by `--reps` launches of every whole-system pair-kernel variant the tuner may
+pick (the symmetric kernel at 1, 2 and 4 targets per lane, force only and with a torque, both
+precisions; the shape is set explicitly, so every counter pass sees the same kernels), of the
+multi-vector kernel (four vectors per launch) and of the steric force kernel.  Only the
+dispatches after the copy count:
 
     rocprofv3 --kernel-trace --stats -d OUT -o run -- python -m paper_1612_00474_amd.profile_kernels
     rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch -- python -m paper_1612_00474_amd.profile_kernels
@@ -43,8 +45,6 @@ def main():
     F = torch.as_tensor(rng.standard_normal((args.n, 3))).cuda()
     T = torch.as_tensor(rng.standard_normal((args.n, 3))).cuda()
     ctx = Context(0)
-    offs = np.array([0, args.n], dtype=np.int64)
-    shapes = {prec: ctx.autotune(pos, offs, prec)[0] for prec in ("mixed", "fp64")}
     torch.cuda.synchronize()
 
     nelem = args.copy_mib * (1 << 20) // 8
@@ -55,10 +55,13 @@ def main():
 
     launches = []
     for precision in ("mixed", "fp64"):
-        for torque in (None, T):
-            for _ in range(args.reps):
-                ctx.matvec(pos, F, torque, precision)
-            launches.append({"precision": precision, "torque": torque is not None, "reps": args.reps})
+        for tpt in (1, 2, 4):
+            ctx.set_tuning(precision, tpt=tpt, symmetric=1)
+            for torque in (None, T):
+                for _ in range(args.reps):
+                    ctx.matvec(pos, F, torque, precision)
+                launches.append({"precision": precision, "tpt": tpt, "torque": torque is not None,
+                                 "reps": args.reps})
     FF = torch.as_tensor(rng.standard_normal((4, args.n, 3))).cuda()
     for precision in ("mixed", "fp64"):
         for _ in range(args.reps):
@@ -69,8 +72,7 @@ def main():
     launches.append({"kernel": "steric", "reps": args.reps})
     torch.cuda.synchronize()
     ctx.close()
-    print(json.dumps({"copy_bytes": nelem * 8, "n": args.n, "shapes": shapes,
-                      "launches": launches}))
+    print(json.dumps({"copy_bytes": nelem * 8, "n": args.n, "launches": launches}))
 
 
 if __name__ == "__main__":

@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import scipy.linalg
 import pytest
 
 from oracle import faxen, lanczos, mobility
@@ -127,3 +128,30 @@ def test_periodic_not_spd_fixture():
     assert lam[0] < -1e-3 * lam[-1]
     g, mo, eps, status = lanczos.lanczos_sqrt(lambda v: M @ v, w, 1e-300, 64)
     assert status == "notspd" and mo == m
+
+
+def test_tridiagonal_root_two_by_two_closed_form():
+    # sqrt of a 2 x 2 SPD matrix: (T + s I) / t with s = sqrt(det T), t = sqrt(tr T + 2 s)
+    a, c, b = 2.5, 0.7, 0.9
+    s = np.sqrt(a * c - b * b)
+    t = np.sqrt(a + c + 2.0 * s)
+    expect = 3.0 * np.array([a + s, b]) / t
+    np.testing.assert_allclose(lanczos.tridiag_sqrt_e1([a, c], [b], 3.0), expect, rtol=1e-14)
+
+
+def test_tridiagonal_root_of_a_diagonal_matrix():
+    # beta = 0: T^{1/2} e_1 = sqrt(alpha_0) e_1, whatever the other diagonal entries
+    y = lanczos.tridiag_sqrt_e1([4.0, 0.3, 9.0, 1e-3], [0.0, 0.0, 0.0], 2.0)
+    np.testing.assert_allclose(y, [4.0, 0.0, 0.0, 0.0], atol=1e-15)
+
+
+def test_tridiagonal_root_matches_schur_sqrtm():
+    rng = np.random.default_rng(11)
+    for n in (3, 17, 40):
+        alpha = 1.0 + rng.random(n)
+        beta = 0.3 * rng.standard_normal(n - 1)
+        T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+        assert np.linalg.eigvalsh(T).min() > 0.0
+        expect = 1.7 * scipy.linalg.sqrtm(T).real[:, 0]
+        np.testing.assert_allclose(lanczos.tridiag_sqrt_e1(alpha, beta, 1.7), expect, rtol=1e-12,
+                                   atol=1e-13)
