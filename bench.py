@@ -64,19 +64,10 @@ def alg_flops(sizes, symmetric, torque=False, nvec=1):
 
 
 def kernel_source_hash() -> str:
-    """sha256[:16] of the pair-kernel sources with comments and blank lines removed (so that
-    editing a comment does not void the recorded counters)."""
-    import hashlib
-    import re
-    csrc = os.path.join(ROOT, "paper_1612_00474_amd", "csrc")
-    h = hashlib.sha256()
-    for name in ("matvec.hip", "multi.hip", "pair_common.h", "pair_tensor.h"):
-        with open(os.path.join(csrc, name)) as f:
-            for line in f:
-                code = re.sub(r"//.*$", "", line).strip()
-                if code:
-                    h.update(code.encode() + b"\n")
-    return h.hexdigest()[:16]
+    """sha256[:16] of the pair-kernel sources, comments and blank lines removed (the key of the
+    committed counter summaries)."""
+    from paper_1612_00474_amd.profile_summary import kernel_source_hash as h
+    return h()
 
 
 def counter_record(fname: str, kernel: str, n: int = PROFILED_N):
