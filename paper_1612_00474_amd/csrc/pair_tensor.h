@@ -52,9 +52,10 @@ namespace rpb {
 // tensors take a = 1: M(r; a) = M(r/a; 1)/a and M_C(r; a) = M_C(r/a; 1)/a^2, and the caller
 // applies 1/(8 pi eta a) per target and divides the torques by a.
 // The closed forms' non-trivial constants travel with the box lengths: the kernels copy them
-// into vector registers once (vgpr_consts), because a float32 vector operation that reads a
-// scalar register or a 32-bit literal issues at about half the rate of one that reads vector
-// registers only (measured on gfx950), and the pair code is bound by that issue rate.
+// into vector registers once (vgpr_consts), because in an isolated loop a float32 vector
+// operation that reads a scalar register issued at about half the rate of one that reads
+// vector registers or a literal (measured on gfx950).  In the pair kernels the change was
+// within the run-to-run noise.
 template <typename Real>
 struct PairConsts {
   Real lx, ly;      // pseudo-periodic box in units of a (used by the PERIODIC kernels only)
