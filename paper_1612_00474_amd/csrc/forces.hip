@@ -329,56 +329,74 @@ __global__ void cells_gather(int64_t n, const int *__restrict__ list,
   scell[s] = q;
 }
 
-// One thread per target: the 27 neighbouring cells in a fixed order, each bucket's spheres
-// of that cell (and system) in index order; then the wall force and gravity.
+// kSterGroup adjacent lanes per target: lane g of the group takes the neighbouring cells
+// g, g + kSterGroup, ... of the 27 in a fixed order, each bucket's spheres of that cell (and
+// system) in index order; the group's sums are then added by a butterfly over its lanes (a
+// fixed order), and its first lane adds the wall force and gravity and writes.  Eight lanes per
+// target keep enough wavefronts in flight for small systems (256 spheres: one wavefront per CU
+// with one lane per target).
+constexpr int kSterGroup = 8;
+
 __global__ void steric_cells(int64_t n, const double *__restrict__ pos, CellArgs c,
                              const int4 *__restrict__ cell, const int *__restrict__ start,
                              const int *__restrict__ count, const double4 *__restrict__ spos,
                              const int4 *__restrict__ scell, const int *__restrict__ sys_of,
                              double a, double u0, double b, double f_grav_z, int wall,
                              double *__restrict__ force) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = gid / kSterGroup;
+  const int g = int(gid % kSterGroup);
+  const bool live = i < n;   // every lane of a group takes part in the butterfly
   const double d = 2.0 * a;
   const double cut = d + 40.0 * b;
   const double cut2 = cut * cut;
   const double fmax_ = u0 / b;
   const double inv_b = 1.0 / b;
-  const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-  const int4 me = cell[i];
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int oz = -1; oz <= 1; ++oz)
-    for (int oy = -1; oy <= 1; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        int3 q = make_int3(me.x + ox, me.y + oy, me.z + oz);
-        if (c.ncx > 0) {
-          q.x = (q.x + c.ncx) % c.ncx;
-          q.y = (q.y + c.ncy) % c.ncy;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (live) {
+    xi = pos[3 * i];
+    yi = pos[3 * i + 1];
+    zi = pos[3 * i + 2];
+    const int4 me = cell[i];
+    for (int o = g; o < 27; o += kSterGroup) {
+      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+      int3 q = make_int3(me.x + ox, me.y + oy, me.z + oz);
+      if (c.ncx > 0) {
+        q.x = (q.x + c.ncx) % c.ncx;
+        q.y = (q.y + c.ncy) % c.ncy;
+      }
+      const uint32_t h = bucket_of(q, me.w, c.mask);
+      const int s0 = start[h], s1 = s0 + count[h];
+      for (int s = s0; s < s1; ++s) {
+        const int4 cj = scell[s];   // (cell x, y, z, sphere index)
+        if (cj.x != q.x || cj.y != q.y || cj.z != q.z || cj.w == i) continue;
+        if (sys_of && sys_of[cj.w] != me.w) continue;
+        const double4 pj = spos[s];
+        double dx = xi - pj.x, dy = yi - pj.y;
+        const double dz = zi - pj.z;
+        if (c.lx > 0.0) {   // minimum image
+          dx -= c.lx * rint(dx / c.lx);
+          dy -= c.ly * rint(dy / c.ly);
         }
-        const uint32_t h = bucket_of(q, me.w, c.mask);
-        const int s0 = start[h], s1 = s0 + count[h];
-        for (int s = s0; s < s1; ++s) {
-          const int4 cj = scell[s];   // (cell x, y, z, sphere index)
-          if (cj.x != q.x || cj.y != q.y || cj.z != q.z || cj.w == i) continue;
-          if (sys_of && sys_of[cj.w] != me.w) continue;
-          const double4 pj = spos[s];
-          double dx = xi - pj.x, dy = yi - pj.y;
-          const double dz = zi - pj.z;
-          if (c.lx > 0.0) {   // minimum image
-            dx -= c.lx * rint(dx / c.lx);
-            dy -= c.ly * rint(dy / c.ly);
-          }
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < cut2 && r2 > 0.0) {
-            const double r = sqrt(r2);
-            const double fm = r < d ? fmax_ : fmax_ * exp(-(r - d) * inv_b);
-            const double sc = fm / r;
-            fx += sc * dx;
-            fy += sc * dy;
-            fz += sc * dz;
-          }
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < cut2 && r2 > 0.0) {
+          const double r = sqrt(r2);
+          const double fm = r < d ? fmax_ : fmax_ * exp(-(r - d) * inv_b);
+          const double sc = fm / r;
+          fx += sc * dx;
+          fy += sc * dy;
+          fz += sc * dz;
         }
       }
+    }
+  }
+  for (int off = 1; off < kSterGroup; off <<= 1) {
+    fx += __shfl_xor(fx, off, kSterGroup);
+    fy += __shfl_xor(fy, off, kSterGroup);
+    fz += __shfl_xor(fz, off, kSterGroup);
+  }
+  if (!live || g != 0) return;
   if (wall) fz += zi < a ? fmax_ : fmax_ * exp(-(zi - a) / b);
   fz += f_grav_z;
   force[3 * i] = fx;
@@ -450,8 +468,8 @@ int steric_cell_run(rpb_ctx *ctx, const rpb_params *p, int64_t n, const double *
   RPB_LAUNCHED(ctx);
   cells_gather<<<gn, kBlock, 0, stream>>>(n, list, pos, cell, spos, scell);
   RPB_LAUNCHED(ctx);
-  steric_cells<<<gn, kBlock, 0, stream>>>(n, pos, c, cell, start, count, spos, scell, sys_of,
-                                          p->a, u0, b, f_grav_z, p->wall, force);
+  steric_cells<<<unsigned((n * kSterGroup + kBlock - 1) / kBlock), kBlock, 0, stream>>>(
+      n, pos, c, cell, start, count, spos, scell, sys_of, p->a, u0, b, f_grav_z, p->wall, force);
   RPB_LAUNCHED(ctx);
   return RPB_OK;
 }

@@ -143,6 +143,17 @@ struct LzEig {
   double Q[kMaxKrylov * kMaxKrylov];   // Q[row * kMaxKrylov + col]
 };
 
+// 1/x: the hardware estimate refined by two Newton steps r <- r + r (1 - x r) (the error is
+// squared by each; the result is within an ulp or two of the rounded quotient), about half the
+// instructions of an IEEE division.  x finite and nonzero.
+__device__ __forceinline__ double rcp_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 constexpr int kMaxRootIter = 64;   // secular-equation iterations per root before giving up
 
 // Root i (0 <= i <= p) of the secular equation of an arrowhead matrix with diagonal d (p
@@ -171,7 +182,7 @@ __device__ __forceinline__ bool secular_root(int i, int p, const double *__restr
   } else {
     const double mid = 0.5 * (d[i - 1] + d[i]);
     double f = a - mid;
-    for (int j = 0; j < p; ++j) f -= z2[j] / (d[j] - mid);
+    for (int j = 0; j < p; ++j) f -= z2[j] * rcp_f64(d[j] - mid);
     if (f > 0.0) {   // the root lies above the midpoint: nearer pole d_i
       K = i;
       lo = mid - d[i];
@@ -189,7 +200,7 @@ __device__ __forceinline__ bool secular_root(int i, int p, const double *__restr
     double f = a0 - tau, R = 0.0, Rp = 0.0, mag = fabs(a0) + fabs(tau);
     for (int j = 0; j < p; ++j) {
       const double den = (d[j] - dK) - tau;
-      const double inv = 1.0 / den;
+      const double inv = rcp_f64(den);
       const double w = z2[j] * inv;
       f -= w;
       mag += fabs(w);
@@ -383,7 +394,7 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
         const int K = K_s[lane];
         const double dK = dn[K], tau = tau_s[lane];
         for (int j = 0; j < p; ++j) {
-          const double x = zh[j] / ((dn[j] - dK) - tau);
+          const double x = zh[j] * rcp_f64((dn[j] - dK) - tau);
           U[lane * 64 + j] = x;
           nrm += x * x;
         }

@@ -144,7 +144,8 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
         }
       }
     }
-    if (!batched) {   // 4 targets per lane: tiles of 1,024 spheres, symmetric kernel only
+    if (!batched && n >= 4 * 1024) {   // 4 targets per lane: tiles of 1,024 spheres, symmetric
+      // kernel only; on smaller systems most of a tile's lanes would idle
       Shape c = base;
       c.tpt = 4;
       c.symmetric = 1;
