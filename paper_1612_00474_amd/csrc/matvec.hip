@@ -431,6 +431,250 @@ __device__ __forceinline__ void load_own(const Real *__restrict__ src, int64_t n
   }
 }
 
+// ---- diagonal tile pairs: each unordered pair of the tile once -----------------------------
+//
+// A diagonal tile pair (I, I) with source part h (a multiple of 64 spheres) covers the pairs of
+// the tile's own spheres.  In 64-blocks: target block tb (q * 4 + wavefront) and source block
+// sb are taken in both directions when tb < sb, skipped when tb > sb (that block pair is taken
+// by the part holding tb's spheres as sources), and on the block diagonal tb = sb over rotation
+// steps 0..32 only: step k pairs lane l with source lane l + k, so steps 1..31 meet each pair of
+// the block once, step 32 meets the pairs (l, l + 32) twice (lanes below 32 keep them) and step 0
+// is the self pair, taken in one direction.  The column sums are rows of the same tile and are
+// added into the targets' own sums.
+
+// One rotation step of a diagonal tile (sym_step with a per-target-block mode: 0 skip, 1 both
+// directions, 2 the block diagonal).
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
+__device__ __forceinline__ void sym_step_diag(const LdsF<TORQUE> &L, int j, bool valid, int step,
+                                              const int (&mode)[TPT], const TargetsF<TPT> &T,
+                                              const float (&own)[TPT][6],
+                                              const PairConsts<float> &k, float (&acc)[TPT][3],
+                                              float (&cs)[3]) {
+  const int lane = threadIdx.x & 63;
+  const float xjh = L.xh[j], xjl = L.xl[j], yjh = L.yh[j], yjl = L.yl[j], zj = L.z[j];
+  const float f0 = L.f[0][j], f1 = L.f[1][j], f2 = L.f[2][j];
+  float t0[3] = {0.f, 0.f, 0.f};
+  if (TORQUE) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t0[c] = L.t[c][j];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    if (mode[q] == 0 || (mode[q] == 2 && step > 32)) continue;
+    const bool v = valid && !(mode[q] == 2 && step == 32 && lane >= 32);
+    const bool back = v && !(mode[q] == 2 && step == 0);
+    const float fx = v ? f0 : 0.f, fy = v ? f1 : 0.f, fz = v ? f2 : 0.f;
+    float tq[3], g[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tq[c] = v ? t0[c] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) g[c] = back ? own[q][c] : 0.f;
+    const float dx0 = (T.xh[q] - xjh) + (T.xl[q] - xjl);
+    const float dy0 = (T.yh[q] - yjh) + (T.yl[q] - yjl);
+    for_images<PERIODIC>(dx0, dy0, k, [&](float dx, float dy) {
+      const float dz = T.z[q] - zj;
+      if (dx * dx + dy * dy + dz * dz < float(kFourA2))
+        pair_velocity_sym<float, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, g[0], g[1],
+                                                      g[2], k, acc[q][0], acc[q][1], acc[q][2],
+                                                      cs[0], cs[1], cs[2], tq, g + 3);
+      else
+        pair_velocity_sym<float, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, g[0], g[1],
+                                                     g[2], k, acc[q][0], acc[q][1], acc[q][2],
+                                                     cs[0], cs[1], cs[2], tq, g + 3);
+    });
+  }
+}
+
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
+__device__ __forceinline__ void sym_step_diag(const LdsD<TORQUE> &L, int j, bool valid, int step,
+                                              const int (&mode)[TPT], const TargetsD<TPT> &T,
+                                              const double (&own)[TPT][6],
+                                              const PairConsts<double> &k, double (&acc)[TPT][3],
+                                              double (&cs)[3]) {
+  const int lane = threadIdx.x & 63;
+  const double xj = L.x[j], yj = L.y[j], zj = L.z[j];
+  const double f0 = L.f[0][j], f1 = L.f[1][j], f2 = L.f[2][j];
+  double t0[3] = {0.0, 0.0, 0.0};
+  if (TORQUE) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t0[c] = L.t[c][j];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) cs[c] = wave_rol1(cs[c]);
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    if (mode[q] == 0 || (mode[q] == 2 && step > 32)) continue;
+    const bool v = valid && !(mode[q] == 2 && step == 32 && lane >= 32);
+    const bool back = v && !(mode[q] == 2 && step == 0);
+    const double fx = v ? f0 : 0.0, fy = v ? f1 : 0.0, fz = v ? f2 : 0.0;
+    double tq[3], g[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) tq[c] = v ? t0[c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) g[c] = back ? own[q][c] : 0.0;
+    for_images<PERIODIC>(T.x[q] - xj, T.y[q] - yj, k, [&](double dx, double dy) {
+      const double dz = T.z[q] - zj;
+      if (dx * dx + dy * dy + dz * dz < kFourA2)
+        pair_velocity_sym<double, false, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, g[0],
+                                                       g[1], g[2], k, acc[q][0], acc[q][1],
+                                                       acc[q][2], cs[0], cs[1], cs[2], tq, g + 3);
+      else
+        pair_velocity_sym<double, true, TORQUE, WALL>(dx, dy, T.z[q], zj, fx, fy, fz, g[0], g[1],
+                                                      g[2], k, acc[q][0], acc[q][1], acc[q][2],
+                                                      cs[0], cs[1], cs[2], tq, g + 3);
+    });
+  }
+}
+
+// Mode of each of the lane's target blocks against source block sb (see above); returns the
+// number of rotation steps the block needs (64 if some target block takes both directions, 33
+// if only the block diagonal, 0 if none).
+template <int TPT>
+__device__ __forceinline__ int diag_modes(int sb, int (&mode)[TPT]) {
+  const int wave = threadIdx.x / 64;
+  int steps = 0;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int tb = q * (kBlock / 64) + wave;
+    mode[q] = tb < sb ? 1 : (tb == sb ? 2 : 0);
+    steps = max(steps, mode[q] == 1 ? 64 : (mode[q] == 2 ? 33 : 0));
+  }
+  return steps;
+}
+
+// Sources [jb, je) (part h of tile I, starting a multiple of 64 into the tile at jt) against the
+// tile's own targets, each unordered pair once; sums into T (row sums and the column sums of
+// these sources, which are rows of the same tile).
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
+__device__ __forceinline__ void sym_diag_tile(const SymArgs &a, const GeomF &g,
+                                              const float *__restrict__ src,
+                                              const PairConsts<float> &k, int64_t first,
+                                              int64_t jb, int64_t je, LdsF<TORQUE> &L,
+                                              float (&col)[kWaves][kBlock][3], TargetsF<TPT> &T) {
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  float own[TPT][6];
+  load_own<TPT>(src, a.n, a.stride, first, TORQUE, own);
+  for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
+    const int cnt = int(min<int64_t>(kBlock, je - t0));
+    __syncthreads();
+    if (tid < cnt) {
+      const int64_t j = t0 + tid;
+      L.xh[tid] = g.xh[j];
+      L.xl[tid] = g.xl[j];
+      L.yh[tid] = g.yh[j];
+      L.yl[tid] = g.yl[j];
+      L.z[tid] = g.z[j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        L.f[c][tid] = src[c * a.stride + j];
+        if (TORQUE) L.t[c][tid] = src[(3 + c) * a.stride + j];
+      }
+    }
+    __syncthreads();
+    float acc[TPT][3];
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.f;
+    const int off = int(t0 - first);   // the LDS tile's first source, within the tile
+    for (int blk = 0; blk < cnt; blk += 64) {
+      const int nb = min(64, cnt - blk);
+      int mode[TPT];
+      const int steps = diag_modes<TPT>((off + blk) / 64, mode);
+      float cs[3] = {0.f, 0.f, 0.f};
+      for (int step = 0; step < steps; ++step) {
+        const int sl = (lane + step) & 63;
+        sym_step_diag<TPT, TORQUE, WALL, PERIODIC>(L, blk + (sl < nb ? sl : 0), sl < nb, step,
+                                                   mode, T, own, k, acc, cs);
+      }
+      // after step s lane l holds the sums of source (l + s) mod 64
+      const int sl = (lane + (steps > 0 ? steps - 1 : 0)) & 63;
+      if (sl < nb) {
+        col[wave][blk + sl][0] = steps > 0 ? cs[0] : 0.f;
+        col[wave][blk + sl][1] = steps > 0 ? cs[1] : 0.f;
+        col[wave][blk + sl][2] = steps > 0 ? cs[2] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TPT; ++q)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) kahan_add(T.s[q][d], T.c[q][d], acc[q][d]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int idx = q * kBlock + tid - off;
+      if (idx >= 0 && idx < cnt)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          double v = 0.0;
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) v += double(col[w][idx][d]);
+          kahan_add(T.s[q][d], T.c[q][d], float(v));
+        }
+    }
+  }
+}
+
+template <int TPT, bool TORQUE, bool WALL, bool PERIODIC>
+__device__ __forceinline__ void sym_diag_tile(const SymArgs &a, const GeomD &g,
+                                              const double *__restrict__ src,
+                                              const PairConsts<double> &k, int64_t first,
+                                              int64_t jb, int64_t je, LdsD<TORQUE> &L,
+                                              double (&col)[kWaves][kBlock][3], TargetsD<TPT> &T) {
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  double own[TPT][6];
+  load_own<TPT>(src, a.n, a.stride, first, TORQUE, own);
+  for (int64_t t0 = jb; t0 < je; t0 += kBlock) {
+    const int cnt = int(min<int64_t>(kBlock, je - t0));
+    __syncthreads();
+    if (tid < cnt) {
+      const int64_t j = t0 + tid;
+      L.x[tid] = g.x[j];
+      L.y[tid] = g.y[j];
+      L.z[tid] = g.z[j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        L.f[c][tid] = src[c * a.stride + j];
+        if (TORQUE) L.t[c][tid] = src[(3 + c) * a.stride + j];
+      }
+    }
+    __syncthreads();
+    const int off = int(t0 - first);
+    for (int blk = 0; blk < cnt; blk += 64) {
+      const int nb = min(64, cnt - blk);
+      int mode[TPT];
+      const int steps = diag_modes<TPT>((off + blk) / 64, mode);
+      double cs[3] = {0.0, 0.0, 0.0};
+      for (int step = 0; step < steps; ++step) {
+        const int sl = (lane + step) & 63;
+        sym_step_diag<TPT, TORQUE, WALL, PERIODIC>(L, blk + (sl < nb ? sl : 0), sl < nb, step,
+                                                   mode, T, own, k, T.u, cs);
+      }
+      const int sl = (lane + (steps > 0 ? steps - 1 : 0)) & 63;
+      if (sl < nb) {
+        col[wave][blk + sl][0] = steps > 0 ? cs[0] : 0.0;
+        col[wave][blk + sl][1] = steps > 0 ? cs[1] : 0.0;
+        col[wave][blk + sl][2] = steps > 0 ? cs[2] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int idx = q * kBlock + tid - off;
+      if (idx >= 0 && idx < cnt)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          double v = 0.0;
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) v += col[w][idx][d];
+          T.u[q][d] += v;
+        }
+    }
+  }
+}
+
 // Tile pair (I, J), I <= J, of linear index Lp, source part h, of one system: `g`, `src` and
 // `partial` already point at the system's first sphere and first partial; the slots follow
 // `pm`.  The mixed kernels store their partial sums as float32 (the compensated row sums and
@@ -453,7 +697,10 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomF &g,
   const int64_t jt = J * a.ts, part = a.ts / a.nsplit;
   const int64_t jb = jt + h * part, je = min(n, jb + part);
   if (I == J) {
-    sources_mixed<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
+    if (part % 64 == 0)
+      sym_diag_tile<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, first, jb, je, L, col, T);
+    else
+      sources_mixed<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
@@ -552,7 +799,10 @@ __device__ __forceinline__ void sym_tile_pair(const SymArgs &a, const GeomD &g,
   const int64_t jt = J * a.ts, part = a.ts / a.nsplit;
   const int64_t jb = jt + h * part, je = min(n, jb + part);
   if (I == J) {
-    sources_f64<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
+    if (part % 64 == 0)
+      sym_diag_tile<TPT, TORQUE, WALL, PERIODIC>(a, g, src, k, first, jb, je, L, col, T);
+    else
+      sources_f64<TORQUE, TPT, WALL, PERIODIC>(g, src, a.stride, jb, je, k, L, T);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
       const int64_t local = q * kBlock + tid;
