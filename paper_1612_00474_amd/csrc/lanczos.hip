@@ -140,7 +140,7 @@ __global__ void basis_combine(int64_t m, int nvec, const double *__restrict__ V,
 // updates it): eigenvalues in increasing order and the eigenvector matrix, row-major.
 struct LzEig {
   double lam[kMaxKrylov];
-  double Q[kMaxKrylov * kMaxKrylov];   // Q[row * kMaxKrylov + col]
+  double Q[kMaxKrylov * kMaxKrylov];   // Q[col * kMaxKrylov + row] (column-major)
 };
 
 // 1/x: the hardware estimate refined by two Newton steps r <- r + r (1 - x r) (the error is
@@ -156,34 +156,94 @@ __device__ __forceinline__ double rcp_f64(double x) {
 
 constexpr int kMaxRootIter = 64;   // secular-equation iterations per root before giving up
 
-// Root i (0 <= i <= p) of the secular equation of an arrowhead matrix with diagonal d (p
-// distinct values, increasing), border z (no zero) and corner a:
+// The p + 1 roots of the secular equation of an arrowhead matrix with diagonal d (p distinct
+// values, increasing), border z (no zero; z2 = z^2) and corner a:
 //   f(mu) = a - mu - sum_j z_j^2 / (d_j - mu),
 // decreasing between consecutive poles, so that root i lies in (d_{i-1}, d_i) (d_{-1} = -inf,
-// d_p = +inf; the outer roots lie within |z| of d or a).  The root is kept as
-// mu = d_K + tau about the nearer pole K, with d_j - mu formed as (d_j - d_K) - tau, so that it
-// keeps full relative accuracy in its distance to the pole.  Each step solves the model
-// c + b tau + z_K^2 / tau = 0 (the pole K exact, the other terms linearised at the current tau:
-// a quadratic with one root on each side of 0, the one on the side of the root is taken),
-// safeguarded by bisection of the bracket; stops when |f| is within the rounding error of
-// its terms.  Returns false when it does not stop within kMaxRootIter steps.
-__device__ __forceinline__ bool secular_root(int i, int p, const double *__restrict__ d,
-                             const double *__restrict__ z2, double a, double znorm, int &K,
-                             double &tau) {
-  double lo, hi;
-  if (i == 0) {
-    K = 0;
-    lo = fmin(d[0], a) - znorm - d[0];
-    hi = 0.0;
-  } else if (i == p) {
-    K = p - 1;
-    lo = 0.0;
-    hi = fmax(d[p - 1], a) + znorm - d[p - 1];
-  } else {
-    const double mid = 0.5 * (d[i - 1] + d[i]);
-    double f = a - mid;
-    for (int j = 0; j < p; ++j) f -= z2[j] * rcp_f64(d[j] - mid);
-    if (f > 0.0) {   // the root lies above the midpoint: nearer pole d_i
+// d_p = +inf; the outer roots lie within |z| of d or a).  Root i is kept as mu = d_K + tau about
+// its nearer pole K (the sign of f at the midpoint of the interval decides), with d_j - mu
+// formed as (d_j - d_K) - tau, so that it keeps full relative accuracy in its distance to the
+// pole.  Each step solves the model c + b tau + z_K^2 / tau = 0 (the pole K exact, the other
+// terms linearised at the current tau: a quadratic with one root on each side of 0, the one on
+// the side of the root is taken), safeguarded by bisection of the bracket; a root stops when
+// |f| is within the rounding error of its terms, or when a step no longer moves it.
+// Lane i of every wavefront follows root i; wavefront w sums the terms j = w, w + W, ... and
+// the W partial sums are added in wavefront order through LDS, so every wavefront holds the
+// same totals and takes the same steps.  Every thread of the workgroup calls this (W <=
+// kThreads / 64); wavefront 0 writes K, tau, d_K and a failure flag (no stop within
+// kMaxRootIter steps) for each root (K = -1, tau = 0 when p = 0: the root is a itself).
+__device__ void secular_roots(int p, const double *__restrict__ d, const double *__restrict__ z2,
+                              double a, int *K_out, double *tau_out, double *dK_out,
+                              int *fail_out) {
+  constexpr int kMaxW = kThreads / 64;
+  __shared__ double part[2][kMaxW][4][64];
+  __shared__ int more_s[2][kMaxW];
+  const int w = int(threadIdx.x) / 64, i = int(threadIdx.x) & 63;
+  // the terms are split over the wavefronts only when there are enough of them to pay for
+  // the exchange (one barrier per step); otherwise the first wavefront takes them all
+  const int W = p >= 16 ? int(blockDim.x) / 64 : 1;
+  if (w >= W) return;   // wavefront-uniform; the caller's next barrier joins them again
+  const bool act = p > 0 && i <= p;
+  int buf = 0;
+  // sums over all terms of w_j, |w_j|, and, without j = K, of w_j and w_j / (d_j - mu), with
+  // w_j = z_j^2 / ((d_j - x0) - x1); with W > 1 also whether any wavefront reports `need`
+  auto sums = [&](double x0, double x1, int K, bool need, double (&tot)[4]) -> bool {
+    const bool any = __ballot(need) != 0ull;
+    if (W == 1 && !any) return false;   // alone, the wavefront stops before summing again
+    double f = 0.0, mag = 0.0, R = 0.0, Rp = 0.0;
+    if (act)
+      for (int j = w; j < p; j += W) {
+        const double inv = rcp_f64((d[j] - x0) - x1);
+        const double t = z2[j] * inv;
+        f += t;
+        mag += fabs(t);
+        if (j != K) {
+          R += t;
+          Rp += t * inv;
+        }
+      }
+    if (W == 1) {
+      tot[0] = f;
+      tot[1] = mag;
+      tot[2] = R;
+      tot[3] = Rp;
+      return any;
+    }
+    part[buf][w][0][i] = f;
+    part[buf][w][1][i] = mag;
+    part[buf][w][2][i] = R;
+    part[buf][w][3][i] = Rp;
+    if (i == 0) more_s[buf][w] = any ? 1 : 0;
+    __syncthreads();
+    bool more = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double v = part[buf][0][q][i];
+      for (int u = 1; u < W; ++u) v += part[buf][u][q][i];
+      tot[q] = v;
+    }
+    for (int u = 0; u < W; ++u) more = more || more_s[buf][u] != 0;
+    buf ^= 1;   // the next exchange uses the other buffer, so no second barrier is needed
+    return more;
+  };
+  double zn2 = 0.0;
+  for (int j = 0; j < p; ++j) zn2 += z2[j];
+  const double znorm = sqrt(zn2);
+  double tot[4];
+  int K = 0;
+  double lo = 0.0, hi = 0.0;
+  const double mid = (act && i > 0 && i < p) ? 0.5 * (d[i - 1] + d[i]) : 0.0;
+  if (p > 1) sums(mid, 0.0, -1, true, tot);
+  if (act) {
+    if (i == 0) {
+      K = 0;
+      lo = fmin(d[0], a) - znorm - d[0];
+      hi = 0.0;
+    } else if (i == p) {
+      K = p - 1;
+      lo = 0.0;
+      hi = fmax(d[p - 1], a) + znorm - d[p - 1];
+    } else if ((a - mid) - tot[0] > 0.0) {   // the root lies above the midpoint: pole d_i
       K = i;
       lo = mid - d[i];
       hi = 0.0;
@@ -193,29 +253,25 @@ __device__ __forceinline__ bool secular_root(int i, int p, const double *__restr
       hi = mid - d[i - 1];
     }
   }
-  const double dK = d[K], a0 = a - dK, zK2 = z2[K];
+  const double dK = act ? d[K] : 0.0, a0 = a - dK, zK2 = act ? z2[K] : 0.0;
   const bool above = K == i - 1;   // the root lies above its pole (tau > 0)
-  tau = 0.5 * (lo + hi);
-  for (int it = 0; it < kMaxRootIter; ++it) {
-    double f = a0 - tau, R = 0.0, Rp = 0.0, mag = fabs(a0) + fabs(tau);
-    for (int j = 0; j < p; ++j) {
-      const double den = (d[j] - dK) - tau;
-      const double inv = rcp_f64(den);
-      const double w = z2[j] * inv;
-      f -= w;
-      mag += fabs(w);
-      if (j != K) {
-        R += w;
-        Rp += w * inv;
-      }
+  double tau = 0.5 * (lo + hi);
+  bool done = !act, ok = !act;
+  // every wavefront of the exchange sees the same `more`, so all take the same number of steps
+  for (int it = 0; sums(dK, tau, K, !done, tot); ++it) {
+    if (done) continue;
+    const double f = (a0 - tau) - tot[0];
+    const double mag = (fabs(a0) + fabs(tau)) + tot[1];
+    if (fabs(f) <= 4.0 * DBL_EPSILON * mag) {
+      done = ok = true;
+      continue;
     }
-    if (fabs(f) <= 4.0 * DBL_EPSILON * mag) return true;
     if (f > 0.0)
       lo = tau;
     else
       hi = tau;
-    const double b = -1.0 - Rp;           // slope of the linearised part
-    const double c = (a0 - tau - R) - b * tau;
+    const double b = -1.0 - tot[3];           // slope of the linearised part
+    const double c = (a0 - tau - tot[2]) - b * tau;
     const double disc = sqrt(c * c - 4.0 * b * zK2);
     double t;
     if (above)
@@ -223,13 +279,16 @@ __device__ __forceinline__ bool secular_root(int i, int p, const double *__restr
     else
       t = c <= 0.0 ? (disc - c) / (2.0 * b) : 2.0 * zK2 / (-c - disc);
     if (!(t >= lo && t <= hi)) t = 0.5 * (lo + hi);
-    if (fabs(t - tau) <= 2.0 * DBL_EPSILON * fabs(t)) {
-      tau = t;
-      return true;
-    }
+    if (fabs(t - tau) <= 2.0 * DBL_EPSILON * fabs(t)) done = ok = true;
     tau = t;
+    if (it + 1 >= kMaxRootIter) done = true;
   }
-  return false;
+  if (w == 0 && i <= p) {
+    K_out[i] = act ? K : -1;
+    tau_out[i] = act ? tau : 0.0;
+    dK_out[i] = act ? dK : 0.0;
+    fail_out[i] = ok ? 0 : 1;
+  }
 }
 
 // Eigendecomposition of T_m from that of T_{m-1} (in eig, replaced by T_m's).  In the basis of
@@ -247,12 +306,16 @@ __device__ __forceinline__ bool secular_root(int i, int p, const double *__restr
 // 64) does the scalar work and the workgroup forms the product.  Returns 1 (every thread)
 // when a root iteration did not stop or an eigenvalue is not finite.
 __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restrict__ eig) {
-  __shared__ double Qs[kMaxKrylov * kMaxKrylov];   // old Q (rows < m - 1), rotated
-  __shared__ double U[kMaxKrylov * kMaxKrylov];    // U[i * 64 + j]: eigenvector i, entry j
+  // column-major (entry [row or component] fastest), so that the lanes of a wavefront, which
+  // take consecutive rows, touch consecutive LDS words
+  __shared__ double Qs[kMaxKrylov * kMaxKrylov];   // old Q (rows < m - 1), rotated: [col * 64 + row]
+  __shared__ double U[kMaxKrylov * kMaxKrylov];    // eigenvectors of the arrowhead: [j * 64 + i]
+  __shared__ double Qk[kMaxKrylov * kMaxKrylov];   // the kept columns of Qs, in order
   __shared__ double dd[kMaxKrylov], zz[kMaxKrylov], dn[kMaxKrylov], z2n[kMaxKrylov];
-  __shared__ double zh[kMaxKrylov], tau_s[kMaxKrylov], val[kMaxKrylov];
+  __shared__ double zh[kMaxKrylov], tau_s[kMaxKrylov], dK_s[kMaxKrylov], val[kMaxKrylov];
   __shared__ double rot_c[kMaxKrylov], rot_s[kMaxKrylov];
   __shared__ int K_s[kMaxKrylov], nd_s[kMaxKrylov], df_s[kMaxKrylov], rank_s[kMaxKrylov];
+  __shared__ int fail_s[kMaxKrylov];
   __shared__ int rot_p[kMaxKrylov], rot_j[kMaxKrylov];
   __shared__ int info[4];   // p, number of deflated, number of rotations, failure
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -269,13 +332,13 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
   const int n1 = m - 1;
   const double alpha = st->alpha[m - 1], beta = st->beta[m - 2];
   for (int e = tid; e < n1 * n1; e += nthr) {
-    const int r = e / n1, c = e - r * n1;
-    Qs[r * 64 + c] = eig->Q[r * kMaxKrylov + c];
+    const int c = e / n1, r = e - c * n1;
+    Qs[c * 64 + r] = eig->Q[c * kMaxKrylov + r];
   }
   if (w0) {
     if (lane < n1) {
       dd[lane] = eig->lam[lane];
-      zz[lane] = beta * eig->Q[(n1 - 1) * kMaxKrylov + lane];
+      zz[lane] = beta * eig->Q[lane * kMaxKrylov + (n1 - 1)];
     }
     // deflation tolerance from |T_m| <= max(|lambda|, |alpha|) + |beta|
     double amax = lane < n1 ? fabs(eig->lam[lane]) : 0.0;
@@ -352,26 +415,25 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
     const int a = rot_p[q], b = rot_j[q];
     const double c = rot_c[q], sn = rot_s[q];
     for (int r = tid; r < n1; r += nthr) {
-      const double qa = Qs[r * 64 + a], qb = Qs[r * 64 + b];
-      Qs[r * 64 + a] = c * qa - sn * qb;
-      Qs[r * 64 + b] = sn * qa + c * qb;
+      const double qa = Qs[a * 64 + r], qb = Qs[b * 64 + r];
+      Qs[a * 64 + r] = c * qa - sn * qb;
+      Qs[b * 64 + r] = sn * qa + c * qb;
     }
     __syncthreads();
   }
+  // the kept columns side by side for the product below (read after the next barrier)
+  for (int x = tid; x < p * n1; x += nthr) {
+    const int jj = x / n1, r = x - jj * n1;
+    Qk[jj * 64 + r] = Qs[nd_s[jj] * 64 + r];
+  }
+  // the roots (with p = 0 the arrowhead is alpha alone), by the whole workgroup
+  secular_roots(p, dn, z2n, alpha, K_s, tau_s, dK_s, fail_s);
   if (w0) {
     int bad = 0;
     if (lane <= p) {
-      // the roots (with p = 0 the arrowhead is alpha alone)
-      int K = -1;
-      double tau = 0.0;
-      if (p > 0) {
-        double zn2 = 0.0;
-        for (int j = 0; j < p; ++j) zn2 += z2n[j];
-        bad = !secular_root(lane, p, dn, z2n, alpha, sqrt(zn2), K, tau);
-      }
-      K_s[lane] = K;
-      tau_s[lane] = tau;
-      val[lane] = K >= 0 ? dn[K] + tau : alpha;
+      bad = fail_s[lane];
+      const int K = K_s[lane];
+      val[lane] = K >= 0 ? dK_s[lane] + tau_s[lane] : alpha;
     } else if (lane < m) {
       val[lane] = dd[df_s[lane - p - 1]];
     }
@@ -380,7 +442,7 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
       const double dj = dn[lane];
       double prod = 1.0;
       for (int i = 0; i <= p; ++i) {
-        prod *= fabs((dj - dn[K_s[i]]) - tau_s[i]);
+        prod *= fabs((dj - dK_s[i]) - tau_s[i]);
         if (i < p && i != lane) prod /= fabs(dj - dn[i]);
       }
       zh[lane] = sqrt(prod);   // its sign: that of the border entry, which z2n does not keep
@@ -395,13 +457,13 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
         const double dK = dn[K], tau = tau_s[lane];
         for (int j = 0; j < p; ++j) {
           const double x = zh[j] * rcp_f64((dn[j] - dK) - tau);
-          U[lane * 64 + j] = x;
+          U[j * 64 + lane] = x;
           nrm += x * x;
         }
       }
       const double inv = 1.0 / sqrt(nrm);
-      for (int j = 0; j < p; ++j) U[lane * 64 + j] *= inv;
-      U[lane * 64 + p] = -inv;
+      for (int j = 0; j < p; ++j) U[j * 64 + lane] *= inv;
+      U[p * 64 + lane] = -inv;
     }
     // rank of every eigenvalue (ties by index)
     if (lane < m) {
@@ -425,15 +487,21 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
     double v;
     if (e <= p) {
       if (r < n1) {
-        v = 0.0;
-        for (int j = 0; j < p; ++j) v += Qs[r * 64 + nd_s[j]] * U[e * 64 + j];
+        // four running sums keep several LDS loads in flight
+        double v4[4] = {0.0, 0.0, 0.0, 0.0};
+        int j = 0;
+        for (; j + 4 <= p; j += 4)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v4[q] += Qk[(j + q) * 64 + r] * U[(j + q) * 64 + e];
+        for (; j < p; ++j) v4[0] += Qk[j * 64 + r] * U[j * 64 + e];
+        v = (v4[0] + v4[1]) + (v4[2] + v4[3]);
       } else {
-        v = U[e * 64 + p];
+        v = U[p * 64 + e];
       }
     } else {
-      v = r < n1 ? Qs[r * 64 + df_s[e - p - 1]] : 0.0;
+      v = r < n1 ? Qs[df_s[e - p - 1] * 64 + r] : 0.0;
     }
-    eig->Q[r * kMaxKrylov + rank_s[e]] = v;
+    eig->Q[rank_s[e] * kMaxKrylov + r] = v;
   }
   __syncthreads();
   return info[3];
@@ -450,11 +518,11 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st, LzEig 
   double amax = lane < m ? fabs(st->alpha[lane]) : 0.0;
   for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
   // y_m = |w| Q L^{1/2} Q^T e_1: lane k forms sqrt(lambda_k) q_k[0], then lane r sums row r
-  if (lane < m) Rz[lane] = sqrt(fmax(eig->lam[lane], 0.0)) * eig->Q[lane];
+  if (lane < m) Rz[lane] = sqrt(fmax(eig->lam[lane], 0.0)) * eig->Q[lane * kMaxKrylov];
   const double wn = st->wnorm;
   double yr = 0.0;
   if (lane < m) {
-    for (int k = 0; k < m; ++k) yr += Rz[k] * eig->Q[lane * kMaxKrylov + k];
+    for (int k = 0; k < m; ++k) yr += Rz[k] * eig->Q[k * kMaxKrylov + lane];
     yr *= wn;
   }
   // eps_m in the orthonormal Krylov basis
