@@ -170,6 +170,14 @@ int rpb_create(int hip_device, rpb_ctx **out) {
     delete c;
     return RPB_EDEVICE;
   }
+  bool ok = hipStreamCreateWithFlags(&c->lz_stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&c->lz_join_ev, hipEventDisableTiming) == hipSuccess;
+  for (auto &e : c->lz_vec_ev)
+    ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    rpb_destroy(c);
+    return RPB_EDEVICE;
+  }
   *out = c;
   return RPB_OK;
 }
@@ -185,6 +193,10 @@ void rpb_destroy(rpb_ctx *ctx) {
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (auto e : ctx->lz_ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto e : ctx->lz_vec_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->lz_join_ev) (void)hipEventDestroy(ctx->lz_join_ev);
+  if (ctx->lz_stream) (void)hipStreamDestroy(ctx->lz_stream);
   if (ctx->fin_ev) (void)hipEventDestroy(ctx->fin_ev);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);

@@ -5,7 +5,7 @@
 //     u = M v_m;  alpha_m = v_m . u;  u -= alpha_m v_m + beta_{m-1} v_{m-1};
 //     u -= V_m (V_m^T u)                       (full re-orthogonalisation)
 //     beta_m = |u|
-//     T_m = Q L Q^T (implicit QL, one wavefront), y_m = |w| Q L^{1/2} Q^T e_1
+//     T_m = Q L Q^T (updated from T_{m-1}'s), y_m = |w| Q L^{1/2} Q^T e_1
 //     eps_m = |y_m - (y_{m-1}, 0)| / |y_{m-1}|  (= |g_m - g_{m-1}|/|g_{m-1}| for orthonormal V)
 //     stop if eps_m < tol (m >= 2), or beta_m ~ 0 (invariant Krylov space, exact result)
 //     v_{m+1} = u / beta_m
@@ -36,25 +36,27 @@ struct LzState {
   double yprev[kMaxKrylov];
   double h[kMaxKrylov];
   double wnorm;
-  double scratch;
+  int halt;       // set by the vector work once it has seen reason != 0 (read by the products)
+  int pad_;
   // status (read by the host every iteration)
   double eps;
   int m;
   int reason;     // 0 running, 1 converged, 2 breakdown, 3 not SPD, 4 eigensolve failed
 };
-static_assert(sizeof(LzState) % 8 == 0, "LzState is an array of doubles and two ints");
+static_assert(sizeof(LzState) % 8 == 0, "LzState is an array of doubles and pairs of ints");
 static_assert(sizeof(LzState) <= kSmallWorkCounter, "LzState must fit the start of the small slot");
 static_assert(size_t(kMaxBatchSystems) * sizeof(LzStatus) <= kHostLzRingOffset,
               "per-system records must stay below the status ring");
 
-// Host copies of the status words (eps, m, reason) of two consecutive iterations.
+// Host copies of the status words (eps, m, reason) of consecutive iterations, slot k mod
+// kLzRing for iteration k.
 struct LzRingSlot {
   double eps;
   int m;
   int reason;
 };
 struct LzRing {
-  LzRingSlot slot[2];
+  LzRingSlot slot[kLzRing];
 };
 static_assert(sizeof(LzRingSlot) == sizeof(double) + 2 * sizeof(int) &&
                   offsetof(LzState, reason) - offsetof(LzState, eps) ==
@@ -73,7 +75,7 @@ LzRing *lz_ring_dev(rpb_ctx *ctx) {
 // Waits for every ring copy still in flight (a previous call's last copy may target a slot
 // this call is about to reuse, possibly from another stream).
 int lz_ring_fence(rpb_ctx *ctx) {
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < kLzRing; ++q) {
     if (!ctx->lz_live[q]) continue;
     RPB_HIP(ctx, hipEventSynchronize(ctx->lz_ev[q]));
     ctx->lz_live[q] = false;
@@ -81,7 +83,7 @@ int lz_ring_fence(rpb_ctx *ctx) {
   return RPB_OK;
 }
 
-// Marks ring slot q with event q: the iteration's status-writing kernel (lanczos_step or
+// Marks ring slot q with event q: the iteration's status-writing kernel (lanczos_eig or
 // beta_eig, which store the status words into the slot) precedes it on the stream.
 int lz_ring_post(rpb_ctx *ctx, int q, hipStream_t stream) {
   if (!ctx->lz_ev[q]) RPB_HIP(ctx, hipEventCreateWithFlags(&ctx->lz_ev[q], hipEventDisableTiming));
@@ -191,17 +193,27 @@ __device__ void secular_roots(int p, const double *__restrict__ d, const double 
     const bool any = __ballot(need) != 0ull;
     if (W == 1 && !any) return false;   // alone, the wavefront stops before summing again
     double f = 0.0, mag = 0.0, R = 0.0, Rp = 0.0;
-    if (act)
-      for (int j = w; j < p; j += W) {
-        const double inv = rcp_f64((d[j] - x0) - x1);
-        const double t = z2[j] * inv;
-        f += t;
-        mag += fabs(t);
-        if (j != K) {
-          R += t;
-          Rp += t * inv;
-        }
+    auto term = [&](int j, double inv) {
+      const double t = z2[j] * inv;
+      f += t;
+      mag += fabs(t);
+      if (j != K) {
+        R += t;
+        Rp += t * inv;
       }
+    };
+    if (act) {
+      // four reciprocals in flight at a time; the sums still run in increasing j
+      int j = w;
+      for (; j + 3 * W < p; j += 4 * W) {
+        double inv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) inv[r] = rcp_f64((d[j + r * W] - x0) - x1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) term(j + r * W, inv[r]);
+      }
+      for (; j < p; j += W) term(j, rcp_f64((d[j] - x0) - x1));
+    }
     if (W == 1) {
       tot[0] = f;
       tot[1] = mag;
@@ -227,38 +239,54 @@ __device__ void secular_roots(int p, const double *__restrict__ d, const double 
     return more;
   };
   double zn2 = 0.0;
+#pragma unroll 4
   for (int j = 0; j < p; ++j) zn2 += z2[j];
   const double znorm = sqrt(zn2);
-  double tot[4];
+  // bracket and pole of every root, and the first evaluation: an interior root at the midpoint
+  // of its two poles (every term: the sign of f there picks the pole), an outer root half way
+  // into its bracket about its only pole
   int K = 0;
-  double lo = 0.0, hi = 0.0;
-  const double mid = (act && i > 0 && i < p) ? 0.5 * (d[i - 1] + d[i]) : 0.0;
-  if (p > 1) sums(mid, 0.0, -1, true, tot);
+  double lo = 0.0, hi = 0.0, x0 = 0.0, x1 = 0.0;
   if (act) {
     if (i == 0) {
       K = 0;
       lo = fmin(d[0], a) - znorm - d[0];
-      hi = 0.0;
+      x0 = d[0];
+      x1 = 0.5 * lo;
     } else if (i == p) {
       K = p - 1;
-      lo = 0.0;
       hi = fmax(d[p - 1], a) + znorm - d[p - 1];
-    } else if ((a - mid) - tot[0] > 0.0) {   // the root lies above the midpoint: pole d_i
+      x0 = d[p - 1];
+      x1 = 0.5 * hi;
+    } else {
+      K = -1;
+      x0 = 0.5 * (d[i - 1] + d[i]);
+    }
+  }
+  double tot[4];
+  sums(x0, x1, K, true, tot);
+  double tau = x1;
+  if (act && i > 0 && i < p) {
+    const double mid = x0;
+    if ((a - mid) - tot[0] > 0.0) {   // the root lies above the midpoint: pole d_i
       K = i;
       lo = mid - d[i];
-      hi = 0.0;
+      tau = lo;
     } else {
       K = i - 1;
-      lo = 0.0;
       hi = mid - d[i - 1];
+      tau = hi;
     }
+    // the sums without pole K, from those over every term
+    const double inv = 1.0 / (d[K] - mid), t = z2[K] * inv;
+    tot[2] -= t;
+    tot[3] -= t * inv;
   }
   const double dK = act ? d[K] : 0.0, a0 = a - dK, zK2 = act ? z2[K] : 0.0;
   const bool above = K == i - 1;   // the root lies above its pole (tau > 0)
-  double tau = 0.5 * (lo + hi);
   bool done = !act, ok = !act;
   // every wavefront of the exchange sees the same `more`, so all take the same number of steps
-  for (int it = 0; sums(dK, tau, K, !done, tot); ++it) {
+  for (int it = 0; it == 0 || sums(dK, tau, K, !done, tot); ++it) {
     if (done) continue;
     const double f = (a0 - tau) - tot[0];
     const double mag = (fabs(a0) + fabs(tau)) + tot[1];
@@ -273,11 +301,11 @@ __device__ void secular_roots(int p, const double *__restrict__ d, const double 
     const double b = -1.0 - tot[3];           // slope of the linearised part
     const double c = (a0 - tau - tot[2]) - b * tau;
     const double disc = sqrt(c * c - 4.0 * b * zK2);
-    double t;
-    if (above)
-      t = c <= 0.0 ? 2.0 * zK2 / (disc - c) : (c + disc) / (-2.0 * b);
-    else
-      t = c <= 0.0 ? (disc - c) / (2.0 * b) : 2.0 * zK2 / (-c - disc);
+    // the quadratic's root on the side of the pole, in the form without cancellation
+    const bool neg = c <= 0.0;
+    const double num = above ? (neg ? 2.0 * zK2 : c + disc) : (neg ? disc - c : 2.0 * zK2);
+    const double den = above ? (neg ? disc - c : -2.0 * b) : (neg ? 2.0 * b : -c - disc);
+    double t = num * rcp_f64(den);
     if (!(t >= lo && t <= hi)) t = 0.5 * (lo + hi);
     if (fabs(t - tau) <= 2.0 * DBL_EPSILON * fabs(t)) done = ok = true;
     tau = t;
@@ -440,10 +468,12 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
     // the recomputed border: the numerator's roots paired with the denominator's poles
     if (lane < p) {
       const double dj = dn[lane];
+      // each factor formed apart from the running product, so that only a multiply waits on it
       double prod = 1.0;
+#pragma unroll 4
       for (int i = 0; i <= p; ++i) {
-        prod *= fabs((dj - dK_s[i]) - tau_s[i]);
-        if (i < p && i != lane) prod /= fabs(dj - dn[i]);
+        const double num = fabs((dj - dK_s[i]) - tau_s[i]);
+        prod *= (i < p && i != lane) ? num * rcp_f64(fabs(dj - dn[i])) : num;
       }
       zh[lane] = sqrt(prod);   // its sign: that of the border entry, which z2n does not keep
       const double zs = zz[nd_s[lane]];
@@ -455,6 +485,7 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
       if (p > 0) {
         const int K = K_s[lane];
         const double dK = dn[K], tau = tau_s[lane];
+#pragma unroll 4
         for (int j = 0; j < p; ++j) {
           const double x = zh[j] * rcp_f64((dn[j] - dK) - tau);
           U[j * 64 + lane] = x;
@@ -462,6 +493,7 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
         }
       }
       const double inv = 1.0 / sqrt(nrm);
+#pragma unroll 4
       for (int j = 0; j < p; ++j) U[j * 64 + lane] *= inv;
       U[p * 64 + lane] = -inv;
     }
@@ -469,6 +501,7 @@ __device__ int eig_update(int m, const LzState *__restrict__ st, LzEig *__restri
     if (lane < m) {
       const double v = val[lane];
       int r = 0;
+#pragma unroll 8
       for (int e = 0; e < m; ++e) {
         const double ve = val[e];
         r += (ve < v || (ve == v && e < lane)) ? 1 : 0;
@@ -522,6 +555,7 @@ __device__ void tridiag_body(int m, double tol, LzState *__restrict__ st, LzEig 
   const double wn = st->wnorm;
   double yr = 0.0;
   if (lane < m) {
+#pragma unroll 4
     for (int k = 0; k < m; ++k) yr += Rz[k] * eig->Q[k * kMaxKrylov + lane];
     yr *= wn;
   }
@@ -574,6 +608,7 @@ __global__ void lz_reset(LzState *st) {
   }
   if (t == 0) {
     st->wnorm = 0.0;
+    st->halt = 0;
     st->eps = 0.0;
     st->m = 0;
     st->reason = 0;
@@ -717,9 +752,12 @@ __device__ __forceinline__ void group_sums(double (&v)[NV], double *sh) {
   __syncthreads();
 }
 
-__device__ void lanczos_step_body(LzState *__restrict__ st, LzEig *__restrict__ eig,
-                                  double *__restrict__ V, double *__restrict__ u, int64_t m3,
-                                  int64_t e0, int64_t e1, int k, double tol, bool write_next) {
+// The vector work (alpha_k, the recurrence, the re-orthogonalisation, beta_k; alpha, beta and
+// the projections h stored in st), leaving the unnormalised u; returns beta_k to every thread.
+__device__ __forceinline__ double lanczos_vec_body(LzState *__restrict__ st,
+                                                   const double *__restrict__ V,
+                                                   double *__restrict__ u, int64_t m3,
+                                                   int64_t e0, int64_t e1, int k) {
   __shared__ double sh[8 * (kThreads / 64)];
   __shared__ double hs[kMaxKrylov];
   const int t = threadIdx.x;
@@ -735,15 +773,19 @@ __device__ void lanczos_step_body(LzState *__restrict__ st, LzEig *__restrict__ 
     if (vp) x -= bprev * vp[i];
     u[i] = x;   // each thread reads back only its own elements below
   }
-  // h_j = V_j . u for j < k, eight basis vectors per pass
+  // h_j = V_j . u for j < k, eight basis vectors per pass (the eight loads issued together:
+  // past the last vector they reread it and add nothing)
   for (int j0 = 0; j0 < k; j0 += 8) {
     const int nj = min(8, k - j0);
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t i = e0 + t; i < e1; i += kThreads) {
       const double ui = u[i];
+      double vq[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) vq[q] = V[int64_t(min(j0 + q, k - 1)) * m3 + i];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q < nj) a[q] += V[int64_t(j0 + q) * m3 + i] * ui;
+        if (q < nj) a[q] += vq[q] * ui;
     }
     group_sums(a, sh);
     if (t < nj) {   // thread t keeps the t-th sum (every thread holds all eight)
@@ -756,6 +798,7 @@ __device__ void lanczos_step_body(LzState *__restrict__ st, LzEig *__restrict__ 
   __syncthreads();
   for (int64_t i = e0 + t; i < e1; i += kThreads) {
     double proj = 0.0;
+#pragma unroll 8
     for (int j = 0; j < k; ++j) proj += hs[j] * V[int64_t(j) * m3 + i];
     u[i] -= proj;
   }
@@ -768,26 +811,59 @@ __device__ void lanczos_step_body(LzState *__restrict__ st, LzEig *__restrict__ 
     st->beta[k - 1] = beta;
   }
   if (t < k) st->h[t] = hs[t];
+  return beta;
+}
+
+// v_{k+1} = u / beta_k on [e0, e1) (0 when beta_k = 0)
+__device__ __forceinline__ void lanczos_write_next(double *__restrict__ V,
+                                                   const double *__restrict__ u, int64_t m3,
+                                                   int64_t e0, int64_t e1, int k, double beta) {
+  double *next = V + int64_t(k) * m3;
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += kThreads)
+    next[i] = beta > 0.0 ? u[i] / beta : 0.0;
+}
+
+// The vector work and the eigensolve of Lanczos iteration k for the segment [e0, e1) of the
+// vectors, by one workgroup: lanczos_vec_body, the eigensolve of T_k with its stop test
+// (tridiag_body) and, unless the process stopped, v_{k+1} (when write_next).
+__device__ void lanczos_step_body(LzState *__restrict__ st, LzEig *__restrict__ eig,
+                                  double *__restrict__ V, double *__restrict__ u, int64_t m3,
+                                  int64_t e0, int64_t e1, int k, double tol, bool write_next) {
+  const double beta = lanczos_vec_body(st, V, u, m3, e0, e1, k);
   __syncthreads();
   tridiag_body(k, tol, st, eig);
   __syncthreads();
-  if (write_next && st->reason == 0) {
-    double *next = V + int64_t(k) * m3;
-    for (int64_t i = e0 + t; i < e1; i += kThreads) next[i] = beta > 0.0 ? u[i] / beta : 0.0;
-  }
+  if (write_next && st->reason == 0) lanczos_write_next(V, u, m3, e0, e1, k, beta);
 }
 
-// Single system, the whole vector (3 n <= kFusedSegment), then the status into the host's ring
-// slot.  A process that has stopped keeps its state: an iteration enqueued after the stop only
-// posts the status again.  (Every thread reads the same reason: it is written only after the
-// workgroup's first barrier.)
-__global__ __launch_bounds__(kThreads) void lanczos_step(LzState *__restrict__ st,
-                                                         LzEig *__restrict__ eig,
-                                                         double *__restrict__ V,
-                                                         double *__restrict__ u, int64_t m3, int k,
-                                                         double tol, int write_next,
-                                                         LzRingSlot *slot) {
-  if (st->reason == 0) lanczos_step_body(st, eig, V, u, m3, 0, m3, k, tol, write_next != 0);
+// Single system, the whole vector (3 n <= kFusedSegment): the vector work of iteration k and
+// v_{k+1}, with the eigensolve and stop test left to lanczos_eig on a second stream, which
+// runs beside the next product.  Until that stream reports a stop the recurrence runs on (the
+// iterations past the stop are never used); once the workgroup sees reason != 0 it only sets
+// st->halt, on which the products of later iterations return at once.  (reason is written by
+// the other stream meanwhile: one thread reads it and the workgroup follows that read.)
+__global__ __launch_bounds__(kThreads) void lanczos_vec(LzState *__restrict__ st,
+                                                        double *__restrict__ V,
+                                                        double *__restrict__ u, int64_t m3, int k,
+                                                        int write_next) {
+  __shared__ int stop_s;
+  if (threadIdx.x == 0) {
+    stop_s = __hip_atomic_load(&st->reason, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (stop_s) st->halt = 1;
+  }
+  __syncthreads();
+  if (stop_s) return;
+  const double beta = lanczos_vec_body(st, V, u, m3, 0, m3, k);
+  if (write_next) lanczos_write_next(V, u, m3, 0, m3, k, beta);
+}
+
+// The eigensolve of T_k and the stop test (skipped once the process has stopped: y, eps and
+// reason stay), then the status into the host's ring slot.  Only these kernels write reason,
+// one after another on their stream, so every thread reads the same value.
+__global__ __launch_bounds__(kThreads) void lanczos_eig(LzState *__restrict__ st,
+                                                        LzEig *__restrict__ eig, int k,
+                                                        double tol, LzRingSlot *slot) {
+  if (st->reason == 0) tridiag_body(k, tol, st, eig);
   if (threadIdx.x == 0) post_status(st, slot);
 }
 
@@ -1058,16 +1134,22 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   if (!ls) return st;
   LzEig *eig = static_cast<LzEig *>(workspace(ctx, WS_LZEIG, sizeof(LzEig), &st));
   if (!eig) return st;
-  // The host reads the status of iteration m only after iteration m + 1 has been enqueued,
-  // so the device never idles while the host decides.  Every kernel of an iteration enqueued
-  // after the stop leaves the result unchanged: the product's kernels return at once while
-  // ls->reason is nonzero, the eigensolve is skipped (y, eps and reason stay), and the other
-  // kernels touch only u, h, V's next column and entries of alpha and beta past the last
-  // iteration.
+  // The host reads the status of iteration m only after iterations up to m + lag have been
+  // enqueued, so the device never idles while the host decides.  Small systems (one workgroup
+  // per iteration) run the eigensolve and stop test of iteration k on a second stream beside
+  // the product of iteration k + 1 (lag 2); larger ones keep them in line on `stream` (lag 1),
+  // where an iteration the stop test has not yet cleared would cost a whole product.  Every
+  // kernel of an iteration past the stop leaves the result unchanged: it touches only u, h,
+  // V's next column, entries of alpha and beta past the last iteration and, once the stop is
+  // seen, the skip flag of the products (which then return at once); the eigensolve is
+  // skipped (y, eps and reason stay).
   RPB_TRY(lz_ring_fence(ctx));
   LzRing *ring = lz_ring(ctx);
   LzRing *ring_dev = lz_ring_dev(ctx);
-  const int *stopped = &ls->reason;
+  const bool fused = m3 <= kFusedSegment;
+  hipStream_t es = ctx->lz_stream;
+  const int lag = fused ? 2 : 1;
+  const int *stopped = fused ? &ls->halt : &ls->reason;
 
   lz_reset<<<1, 64, 0, stream>>>(ls);
   RPB_LAUNCHED(ctx);
@@ -1078,63 +1160,80 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   int m = 0;           // iterations whose result counts
   int reason = 0;
   double eps = 0.0;
-  size_t mark[2] = {0, 0};   // first timing record of each iteration in flight
+  size_t mark[kLzRing] = {};   // first timing record of each iteration in flight
   bool stop = false;
-  for (int k = 1; k <= max_iter && !stop; ++k) {
-    mark[k & 1] = ctx->ev_start.size();
-    double *vm = V + int64_t(k - 1) * m3;
-    const double *vprev = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
-    if (precond) {   // u = L^-1 M L^-1 vm
-      divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, vm, L, t);
-      RPB_LAUNCHED(ctx);
-      RPB_TRY(matvec_packed(ctx, p, g, t, nullptr, 0, n, u, stream, stopped));
-      divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
-      RPB_LAUNCHED(ctx);
-    } else if (k == 1 && mw) {   // M v_1 = (M w) / |w| from the caller's product
-      scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, mw, &ls->wnorm, u, nullptr);
-      RPB_LAUNCHED(ctx);
-    } else {
-      RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream, stopped));
-    }
-    if (m3 <= kFusedSegment) {   // the whole iteration's vector work in one workgroup
-      lanczos_step<<<1, kThreads, 0, stream>>>(ls, eig, V, u, m3, k, tol, k < max_iter,
-                                                  &ring_dev->slot[k & 1]);
-      RPB_LAUNCHED(ctx);
-    } else {   // seven kernels (see dot_partial)
-      RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
-      const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
-      reorth_dots_3t<<<grid, kThreads, 0, stream>>>(m3, V, u, vm, vprev, &ls->alpha[k - 1],
-                                                     k > 1 ? &ls->beta[k - 2] : nullptr, part);
-      RPB_LAUNCHED(ctx);
-      reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
-      RPB_LAUNCHED(ctx);
-      reorth_update_sq<<<kRedBlocks, kThreads, 0, stream>>>(m3, k, V, u, vm, vprev, ls, part);
-      RPB_LAUNCHED(ctx);
-      beta_eig<<<1, kThreads, 0, stream>>>(kRedBlocks, part, k, tol, ls, eig,
-                                           &ring_dev->slot[k & 1]);
-      RPB_LAUNCHED(ctx);
-      if (k < max_iter) {
-        scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
-                                                             V + int64_t(k) * m3, ls);
+  int next_q = 1;      // first iteration whose status the host has not read
+  auto iterate = [&]() -> int {
+    for (int k = 1; k <= max_iter && !stop; ++k) {
+      const int slot = k % kLzRing;
+      mark[slot] = ctx->ev_start.size();
+      double *vm = V + int64_t(k - 1) * m3;
+      const double *vprev = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
+      if (precond) {   // u = L^-1 M L^-1 vm
+        divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, vm, L, t);
         RPB_LAUNCHED(ctx);
+        RPB_TRY(matvec_packed(ctx, p, g, t, nullptr, 0, n, u, stream, stopped));
+        divide_by<<<nblk(m3), kThreads, 0, stream>>>(m3, u, L, u);
+        RPB_LAUNCHED(ctx);
+      } else if (k == 1 && mw) {   // M v_1 = (M w) / |w| from the caller's product
+        scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, mw, &ls->wnorm, u, nullptr);
+        RPB_LAUNCHED(ctx);
+      } else {
+        RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream, stopped));
+      }
+      if (fused) {   // the vector work in one workgroup; the eigensolve on the second stream
+        lanczos_vec<<<1, kThreads, 0, stream>>>(ls, V, u, m3, k, k < max_iter);
+        RPB_LAUNCHED(ctx);
+        RPB_HIP(ctx, hipEventRecord(ctx->lz_vec_ev[slot], stream));
+        RPB_HIP(ctx, hipStreamWaitEvent(es, ctx->lz_vec_ev[slot], 0));
+        lanczos_eig<<<1, kThreads, 0, es>>>(ls, eig, k, tol, &ring_dev->slot[slot]);
+        RPB_LAUNCHED(ctx);
+        RPB_TRY(lz_ring_post(ctx, slot, es));
+      } else {   // seven kernels (see dot_partial)
+        RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
+        const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
+        reorth_dots_3t<<<grid, kThreads, 0, stream>>>(m3, V, u, vm, vprev, &ls->alpha[k - 1],
+                                                       k > 1 ? &ls->beta[k - 2] : nullptr, part);
+        RPB_LAUNCHED(ctx);
+        reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
+        RPB_LAUNCHED(ctx);
+        reorth_update_sq<<<kRedBlocks, kThreads, 0, stream>>>(m3, k, V, u, vm, vprev, ls, part);
+        RPB_LAUNCHED(ctx);
+        beta_eig<<<1, kThreads, 0, stream>>>(kRedBlocks, part, k, tol, ls, eig,
+                                             &ring_dev->slot[slot]);
+        RPB_LAUNCHED(ctx);
+        if (k < max_iter) {
+          scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
+                                                               V + int64_t(k) * m3, ls);
+          RPB_LAUNCHED(ctx);
+        }
+        RPB_TRY(lz_ring_post(ctx, slot, stream));
+      }
+      // the statuses up to iteration k - lag (all of them after the last iteration)
+      const int qmax = k < max_iter ? k - lag : k;
+      for (; next_q <= qmax; ++next_q) {
+        const int q = next_q;
+        RPB_TRY(lz_ring_wait(ctx, q % kLzRing));
+        m = q;
+        reason = ring->slot[q % kLzRing].reason;
+        eps = ring->slot[q % kLzRing].eps;
+        if (reason != 0) {
+          // the iterations after q did no work that counts: drop their pair-kernel timing
+          // records (some may have run in full before the stop was seen, others not at all)
+          if (q < k) timing_discard(ctx, mark[(q + 1) % kLzRing]);
+          stop = true;
+          break;
+        }
       }
     }
-    RPB_TRY(lz_ring_post(ctx, k & 1, stream));
-    // the status of the previous iteration (or of this one, after the last)
-    for (int q = k > 1 ? k - 1 : k; q <= k; ++q) {
-      if (q == k && k < max_iter) break;
-      RPB_TRY(lz_ring_wait(ctx, q & 1));
-      m = q;
-      reason = ring->slot[q & 1].reason;
-      eps = ring->slot[q & 1].eps;
-      if (reason != 0) {
-        // iteration q + 1, if enqueued, did no work: drop its pair-kernel timing records
-        if (q < k) timing_discard(ctx, mark[k & 1]);
-        stop = true;
-        break;
-      }
-    }
+    return RPB_OK;
+  };
+  const int status = iterate();
+  if (fused) {   // the second stream's work, all of it, before anything later on `stream`
+    RPB_HIP(ctx, hipEventRecord(ctx->lz_join_ev, es));
+    RPB_HIP(ctx, hipStreamWaitEvent(stream, ctx->lz_join_ev, 0));
   }
+  if (status != RPB_OK) return status;
   basis_combine<<<nblk(m3), kThreads, 0, stream>>>(m3, m, V, ls->y, out);
   RPB_LAUNCHED(ctx);
   if (precond) {

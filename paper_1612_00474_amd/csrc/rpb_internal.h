@@ -45,6 +45,9 @@ enum Slot {
   WS_NSLOTS
 };
 
+// Slots of the Lanczos status ring: iterations whose status may be in flight at once.
+constexpr int kLzRing = 4;
+
 // Default limit of the partial sums of one launch of the symmetric tile-pair kernels.
 constexpr size_t kMaxChunkBytes = size_t(512) << 20;
 
@@ -97,10 +100,15 @@ struct rpb_ctx {
   std::vector<double> ev_pairs;
   std::vector<int> ev_kind;             // 2 * (precision == mixed) + (torque present)
   std::vector<hipEvent_t> ev_pool;
-  // Lanczos status ring (two slots in the upper half of the pinned scratch) and the events
-  // that mark each slot's copy as landed; `lz_live` is set while a copy may be in flight
-  hipEvent_t lz_ev[2] = {nullptr, nullptr};
-  bool lz_live[2] = {false, false};
+  // Lanczos status ring (rpb::kLzRing slots in the upper half of the pinned scratch) and the
+  // events that mark each slot's status as landed; `lz_live` is set while one may be in flight
+  hipEvent_t lz_ev[rpb::kLzRing] = {};
+  bool lz_live[rpb::kLzRing] = {};
+  // the second stream on which small systems run the Lanczos eigensolve and stop test beside
+  // the vector recurrence, and the events that order the two streams
+  hipStream_t lz_stream = nullptr;
+  hipEvent_t lz_vec_ev[rpb::kLzRing] = {};
+  hipEvent_t lz_join_ev = nullptr;
   // deferred position check (check_finite_begin / _end): its flag's copy and event
   hipEvent_t fin_ev = nullptr;
   bool fin_live = false;
