@@ -754,56 +754,112 @@ __device__ __forceinline__ void group_sums(double (&v)[NV], double *sh) {
 
 // The vector work (alpha_k, the recurrence, the re-orthogonalisation, beta_k; alpha, beta and
 // the projections h stored in st), leaving the unnormalised u; returns beta_k to every thread.
-__device__ __forceinline__ double lanczos_vec_body(LzState *__restrict__ st,
-                                                   const double *__restrict__ V,
-                                                   double *__restrict__ u, int64_t m3,
-                                                   int64_t e0, int64_t e1, int k) {
-  __shared__ double sh[8 * (kThreads / 64)];
+// The segment has at most kEpt values per thread (kFusedSegment in all), so each thread keeps
+// its values of u, v_k and v_{k-1} in registers, and each pass over the basis issues all its
+// loads at once; the sums and their order are those of one value at a time.
+constexpr int kMaxEpt = int(kFusedSegment / kThreads);
+static_assert(kFusedSegment % kThreads == 0, "whole values per thread");
+template <int kEpt>
+__device__ __forceinline__ double lanczos_vec_values(LzState *__restrict__ st,
+                                                     const double *__restrict__ V,
+                                                     double *__restrict__ u, int64_t m3,
+                                                     int64_t e0, int64_t e1, int k) {
+  constexpr int W = kThreads / 64;
+  __shared__ double sh[8 * W];
+  __shared__ double hsh[kMaxKrylov * W];   // wavefront sums of h_j: [j * W + wave]
   __shared__ double hs[kMaxKrylov];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const double *vk = V + int64_t(k - 1) * m3;
   const double *vp = k > 1 ? V + int64_t(k - 2) * m3 : nullptr;
+  // this thread's values: element e0 + t + r kThreads, r < kEpt (clamped loads past e1)
+  bool in[kEpt];
+  int64_t ix[kEpt];
+  double uu[kEpt], xv[kEpt];
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r) {
+    const int64_t i = e0 + t + int64_t(r) * kThreads;
+    in[r] = i < e1;
+    ix[r] = in[r] ? i : e0;
+  }
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r) uu[r] = u[ix[r]];
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r) xv[r] = vk[ix[r]];
   double acc[1] = {0.0};
-  for (int64_t i = e0 + t; i < e1; i += kThreads) acc[0] += vk[i] * u[i];
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r)
+    if (in[r]) acc[0] += xv[r] * uu[r];
   group_sums(acc, sh);
   const double alpha = acc[0];
   const double bprev = k > 1 ? st->beta[k - 2] : 0.0;
-  for (int64_t i = e0 + t; i < e1; i += kThreads) {
-    double x = u[i] - alpha * vk[i];
-    if (vp) x -= bprev * vp[i];
-    u[i] = x;   // each thread reads back only its own elements below
+  double pv[kEpt];
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r) pv[r] = vp ? vp[ix[r]] : 0.0;
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r) {
+    double x = uu[r] - alpha * xv[r];
+    if (vp) x -= bprev * pv[r];
+    uu[r] = x;
   }
-  // h_j = V_j . u for j < k, eight basis vectors per pass (the eight loads issued together:
-  // past the last vector they reread it and add nothing)
+  // h_j = V_j . u for j < k, eight basis vectors per pass (past the last vector the loads
+  // reread it and add nothing); each wavefront's sums go to LDS, added over the wavefronts
+  // in a fixed order after the last pass
   for (int j0 = 0; j0 < k; j0 += 8) {
     const int nj = min(8, k - j0);
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = e0 + t; i < e1; i += kThreads) {
-      const double ui = u[i];
-      double vq[8];
+    double vq[8][kEpt];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) vq[q] = V[int64_t(min(j0 + q, k - 1)) * m3 + i];
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int r = 0; r < kEpt; ++r) vq[q][r] = V[int64_t(min(j0 + q, k - 1)) * m3 + ix[r]];
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kEpt; ++r)
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q < nj) a[q] += vq[q] * ui;
-    }
-    group_sums(a, sh);
-    if (t < nj) {   // thread t keeps the t-th sum (every thread holds all eight)
-      double r = a[0];
+        if (in[r] && q < nj) a[q] += vq[q][r] * uu[r];
 #pragma unroll
-      for (int q = 1; q < 8; ++q) r = t == q ? a[q] : r;
-      hs[j0 + t] = r;
-    }
+    for (int q = 0; q < 8; ++q)
+      for (int off = 32; off > 0; off >>= 1) a[q] += __shfl_xor(a[q], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nj) hsh[(j0 + q) * W + wave] = a[q];
   }
   __syncthreads();
-  for (int64_t i = e0 + t; i < e1; i += kThreads) {
-    double proj = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < k; ++j) proj += hs[j] * V[int64_t(j) * m3 + i];
-    u[i] -= proj;
+  if (t < k) {
+    double r = hsh[t * W];
+    for (int w = 1; w < W; ++w) r += hsh[t * W + w];
+    hs[t] = r;
+  }
+  __syncthreads();
+  // u -= V_k h: per value the terms in increasing j, eight basis vectors' loads at a time
+  double proj[kEpt];
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r) proj[r] = 0.0;
+  for (int j0 = 0; j0 < k; j0 += 8) {
+    const int nj = min(8, k - j0);
+    double vq[8][kEpt];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int r = 0; r < kEpt; ++r) vq[q][r] = V[int64_t(min(j0 + q, k - 1)) * m3 + ix[r]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double hj = q < nj ? hs[j0 + q] : 0.0;
+#pragma unroll
+      for (int r = 0; r < kEpt; ++r)
+        if (q < nj) proj[r] += hj * vq[q][r];
+    }
   }
   acc[0] = 0.0;
-  for (int64_t i = e0 + t; i < e1; i += kThreads) acc[0] += u[i] * u[i];
+#pragma unroll
+  for (int r = 0; r < kEpt; ++r) {
+    uu[r] -= proj[r];
+    if (in[r]) {
+      u[ix[r]] = uu[r];
+      acc[0] += uu[r] * uu[r];
+    }
+  }
   group_sums(acc, sh);
   const double beta = sqrt(acc[0]);
   if (t == 0) {
@@ -812,6 +868,23 @@ __device__ __forceinline__ double lanczos_vec_body(LzState *__restrict__ st,
   }
   if (t < k) st->h[t] = hs[t];
   return beta;
+}
+
+// lanczos_vec_values with as many values per thread as the segment needs (workgroup-uniform)
+__device__ __forceinline__ double lanczos_vec_body(LzState *__restrict__ st,
+                                                   const double *__restrict__ V,
+                                                   double *__restrict__ u, int64_t m3,
+                                                   int64_t e0, int64_t e1, int k) {
+  static_assert(kMaxEpt == 6, "one case per count of values per thread");
+  switch (int((e1 - e0 + kThreads - 1) / kThreads)) {
+    case 0:
+    case 1: return lanczos_vec_values<1>(st, V, u, m3, e0, e1, k);
+    case 2: return lanczos_vec_values<2>(st, V, u, m3, e0, e1, k);
+    case 3: return lanczos_vec_values<3>(st, V, u, m3, e0, e1, k);
+    case 4: return lanczos_vec_values<4>(st, V, u, m3, e0, e1, k);
+    case 5: return lanczos_vec_values<5>(st, V, u, m3, e0, e1, k);
+    default: return lanczos_vec_values<6>(st, V, u, m3, e0, e1, k);
+  }
 }
 
 // v_{k+1} = u / beta_k on [e0, e1) (0 when beta_k = 0)

@@ -109,3 +109,18 @@ def test_invalid_arguments_are_rejected(ctx):
     a[3] = 1.0
     assert lib.lanczos_tridiag_sqrt(ctx.h, 5, a.ctypes.data, b.ctypes.data, -1.0,
                                     y.ctypes.data, None) == RPB_EINVAL
+
+
+def test_overflowing_coefficients_report_failure(ctx):
+    """Coefficients whose squares overflow float64: the secular-equation roots cannot settle
+    (every root loop is bounded), so the call reports the failure instead of returning
+    non-finite values, and the context stays usable."""
+    from paper_1612_00474_amd._lib import RPB_EDEVICE
+    lib = ctx.lib
+    a = np.array([1e300, 1e300])
+    b = np.array([1e300])
+    y = np.zeros(4)
+    assert lib.lanczos_tridiag_sqrt(ctx.h, 2, a.ctypes.data, b.ctypes.data, 1.0,
+                                    y.ctypes.data, None) == RPB_EDEVICE
+    got = ctx.tridiag_sqrt(np.array([2.5, 0.7]), np.array([0.9]), 3.0)
+    close(got[1], lanczos.tridiag_sqrt_e1(np.array([2.5, 0.7]), np.array([0.9]), 3.0), TOL)
