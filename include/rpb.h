@@ -16,6 +16,10 @@
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream).  Calls
  *    that must read device scalars (Lanczos convergence, validation flags)
  *    synchronise `stream` before returning; host out-parameters are valid on return.
+ *    The single-system Lanczos solves of small systems (3 n <= 1536) run their
+ *    eigensolve on a second stream owned by the context, beside the next product; before
+ *    returning they make `stream` wait for all of it, so work enqueued later on `stream`
+ *    is ordered after the whole solve.
  *  - Return value: RPB_OK (0) or a negative rpb_status.  rpb_last_error() then holds
  *    a message.  No C++ exception crosses this interface.
  *  - n == 0 is a no-op that returns RPB_OK.  RPB_EINVAL for n < 0, a NULL required
