@@ -167,9 +167,33 @@ def trace(trace_dir, top=25):
         print(f"| `{short(r['Name'])}` | {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.1f} | "
               f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
               f"{100.0 * float(r['TotalDurationNs']) / tot:.2f} |")
+    # kernel time per stream, and how much of it ran beside kernels of another stream
+    trace_rows = _rows(trace_dir, "*kernel_trace.csv")
+    per_stream = defaultdict(float)
+    spans = []
+    for r in trace_rows:
+        s0, s1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        per_stream[r.get("Stream_Id", "0")] += (s1 - s0) / 1e6
+        spans.append((s0, s1))
+    if len(per_stream) > 1:
+        spans.sort()
+        busy, cur0, cur1 = 0, None, None
+        for s0, s1 in spans:
+            if cur1 is None or s0 > cur1:
+                if cur1 is not None:
+                    busy += cur1 - cur0
+                cur0, cur1 = s0, s1
+            else:
+                cur1 = max(cur1, s1)
+        busy += cur1 - cur0
+        total = sum(per_stream.values())
+        print("\nKernel time per stream (ms): "
+              + ", ".join(f"stream {k}: {v:.2f}" for k, v in sorted(per_stream.items()))
+              + f"; time with at least one kernel running {busy / 1e6:.2f} ms, so "
+              f"{total - busy / 1e6:.2f} ms of kernel time ran beside another kernel.")
     # pair kernels: launches that did work apart from those that found a stop flag set
     by = defaultdict(list)
-    for r in _rows(trace_dir, "*kernel_trace.csv"):
+    for r in trace_rows:
         k = short(r["Kernel_Name"])
         if k.startswith("pair_kernel"):
             by[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
