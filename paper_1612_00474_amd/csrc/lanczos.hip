@@ -915,10 +915,15 @@ __device__ void lanczos_step_body(LzState *__restrict__ st, LzEig *__restrict__ 
 // iterations past the stop are never used); once the workgroup sees reason != 0 it only sets
 // st->halt, on which the products of later iterations return at once.  (reason is written by
 // the other stream meanwhile: one thread reads it and the workgroup follows that read.)
+// With src (nullable), v_{k+1} also goes into the next product's packed sources, as that
+// product's own packing would write them: src[c n + s] = Real(H_s v_{k+1}[3 s + c]) (hw: H).
+template <typename Real>
 __global__ __launch_bounds__(kThreads) void lanczos_vec(LzState *__restrict__ st,
                                                         double *__restrict__ V,
                                                         double *__restrict__ u, int64_t m3, int k,
-                                                        int write_next) {
+                                                        int write_next,
+                                                        const double *__restrict__ hw,
+                                                        Real *__restrict__ src) {
   __shared__ int stop_s;
   if (threadIdx.x == 0) {
     stop_s = __hip_atomic_load(&st->reason, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -927,7 +932,17 @@ __global__ __launch_bounds__(kThreads) void lanczos_vec(LzState *__restrict__ st
   __syncthreads();
   if (stop_s) return;
   const double beta = lanczos_vec_body(st, V, u, m3, 0, m3, k);
-  if (write_next) lanczos_write_next(V, u, m3, 0, m3, k, beta);
+  if (!write_next) return;
+  double *next = V + int64_t(k) * m3;
+  const int64_t n = m3 / 3;
+  for (int64_t i = threadIdx.x; i < m3; i += kThreads) {
+    const double x = beta > 0.0 ? u[i] / beta : 0.0;
+    next[i] = x;
+    if (src) {
+      const int64_t s = i / 3;
+      src[(i - 3 * s) * n + s] = Real(hw[s] * x);
+    }
+  }
 }
 
 // The eigensolve of T_k and the stop test (skipped once the process has stopped: y, eps and
@@ -1220,6 +1235,15 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   LzRing *ring = lz_ring(ctx);
   LzRing *ring_dev = lz_ring_dev(ctx);
   const bool fused = m3 <= kFusedSegment;
+  // small systems without the preconditioner: lanczos_vec packs v_{k+1} for the next product
+  const bool prepack = fused && !precond;
+  void *src = nullptr;
+  if (prepack) {
+    src = source_buffer(ctx, g, &st);
+    if (!src) return st;
+  }
+  const double *hw = prepack ? packed_weights(g) : nullptr;
+  const bool f64 = g.precision == RPB_FP64;
   hipStream_t es = ctx->lz_stream;
   const int lag = fused ? 2 : 1;
   const int *stopped = fused ? &ls->halt : &ls->reason;
@@ -1251,11 +1275,18 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
       } else if (k == 1 && mw) {   // M v_1 = (M w) / |w| from the caller's product
         scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, mw, &ls->wnorm, u, nullptr);
         RPB_LAUNCHED(ctx);
+      } else if (prepack && k > 1) {   // v_k packed by the previous iteration's lanczos_vec
+        RPB_TRY(matvec_prepacked(ctx, p, g, src, u, stream, stopped));
       } else {
         RPB_TRY(matvec_packed(ctx, p, g, vm, nullptr, 0, n, u, stream, stopped));
       }
       if (fused) {   // the vector work in one workgroup; the eigensolve on the second stream
-        lanczos_vec<<<1, kThreads, 0, stream>>>(ls, V, u, m3, k, k < max_iter);
+        if (f64)
+          lanczos_vec<double><<<1, kThreads, 0, stream>>>(
+              ls, V, u, m3, k, k < max_iter, hw, static_cast<double *>(src));
+        else
+          lanczos_vec<float><<<1, kThreads, 0, stream>>>(
+              ls, V, u, m3, k, k < max_iter, hw, static_cast<float *>(src));
         RPB_LAUNCHED(ctx);
         RPB_HIP(ctx, hipEventRecord(ctx->lz_vec_ev[slot], stream));
         RPB_HIP(ctx, hipStreamWaitEvent(es, ctx->lz_vec_ev[slot], 0));

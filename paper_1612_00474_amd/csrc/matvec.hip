@@ -1199,11 +1199,8 @@ int pack_sources_into(rpb_ctx *ctx, const Packed &g, const double *force, const 
 
 int pack_sources(rpb_ctx *ctx, const Packed &g, const double *force, const double *torque,
                  void **src, hipStream_t stream, const int *skip = nullptr) {
-  const int64_t n = g.n;
-  const bool f64 = g.precision == RPB_FP64;
-  const size_t esz = f64 ? sizeof(double) : sizeof(float);
   int st;
-  *src = workspace(ctx, WS_SRC, size_t(6 * n) * esz, &st);
+  *src = source_buffer(ctx, g, &st);
   if (!*src) return st;
   return pack_sources_into(ctx, g, force, torque, *src, stream, skip);
 }
@@ -1482,6 +1479,35 @@ int matvec_symmetric(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const v
     RPB_LAUNCHED(ctx);
   }
   return RPB_OK;
+}
+
+const double *packed_weights(const Packed &g) {
+  return g.precision == RPB_FP64 ? geom_d(g).h : geom_f(g).h;
+}
+
+void *source_buffer(rpb_ctx *ctx, const Packed &g, int *status) {
+  const size_t esz = g.precision == RPB_FP64 ? sizeof(double) : sizeof(float);
+  return workspace(ctx, WS_SRC, size_t(6 * g.n) * esz, status);
+}
+
+int matvec_prepacked(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
+                     double *vel, hipStream_t stream, const int *skip) {
+  const int64_t n = g.n;
+  if (n <= 0) return RPB_OK;
+  const bool f64 = g.precision == RPB_FP64;
+  const Shape &shape = ctx->tune.s[f64 ? RPB_FP64 : RPB_MIXED];
+  if (shape.symmetric)
+    return matvec_symmetric(ctx, p, g, src, false, packed_weights(g), shape.tpt, vel, stream,
+                            skip);
+  const int tpt = std::min(shape.tpt, 2);
+  const int64_t chunk = ordered_chunk(n, tpt, shape.target_wgs, 65535);
+  const int64_t nchunks = (n + chunk - 1) / chunk;
+  int st;
+  double *part = static_cast<double *>(
+      workspace(ctx, WS_PART, size_t(nchunks) * 3 * size_t(n) * sizeof(double), &st));
+  if (!part) return st;
+  return ordered_product(ctx, p, g, src, false, tpt, chunk, 0, n, part, vel, stream, skip,
+                         true);
 }
 
 int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *force,

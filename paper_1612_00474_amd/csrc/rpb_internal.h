@@ -217,6 +217,18 @@ int matvec_packed(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const doub
                   const double *torque, int64_t row0, int64_t nrows, double *vel,
                   hipStream_t stream, const int *skip = nullptr);
 
+// The H weights of packed geometry `g` (n float64 values on the device).
+const double *packed_weights(const Packed &g);
+// The buffer the products read their packed sources from: 6 n values of the pair precision
+// (float64 for RPB_FP64, float32 for RPB_MIXED), component-major: rows c = 0..2 hold the
+// H-weighted force, f[c * n + i] = H_i F_i,c (the product in float64, then rounded), rows
+// 3..5 the H-weighted torque divided by the radius.
+void *source_buffer(rpb_ctx *ctx, const Packed &g, int *status);
+// U = M F for the whole system from force sources already written into `src` (rows 0..2 of
+// source_buffer's layout; no torque), as matvec_packed would form them.
+int matvec_prepacked(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const void *src,
+                     double *vel, hipStream_t stream, const int *skip = nullptr);
+
 // ---- batched products (matvec.hip) -----------------------------------------------------
 
 // Work list of a batch of independent systems (built on the host, copied to the device).
