@@ -1228,9 +1228,9 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   // the product of iteration k + 1 (lag 2); larger ones keep them in line on `stream` (lag 1),
   // where an iteration the stop test has not yet cleared would cost a whole product.  Every
   // kernel of an iteration past the stop leaves the result unchanged: it touches only u, h,
-  // V's next column, entries of alpha and beta past the last iteration and, once the stop is
-  // seen, the skip flag of the products (which then return at once); the eigensolve is
-  // skipped (y, eps and reason stay).
+  // V's next column, the packed sources of the next product, entries of alpha and beta past
+  // the last iteration and, once the stop is seen, the skip flag of the products (which then
+  // return at once); the eigensolve is skipped (y, eps and reason stay).
   RPB_TRY(lz_ring_fence(ctx));
   LzRing *ring = lz_ring(ctx);
   LzRing *ring_dev = lz_ring_dev(ctx);
