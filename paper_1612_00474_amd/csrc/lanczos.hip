@@ -124,6 +124,23 @@ __global__ void scale_by_inverse(int64_t m, const double *__restrict__ x,
   y[i] = s > 0.0 ? x[i] / s : 0.0;
 }
 
+// scale_by_inverse for v_{k+1} = u / beta_k that also writes it into the next product's
+// packed sources, as that product's own packing would: src[c n + s] = Real(H_s y[3 s + c]).
+template <typename Real>
+__global__ void scale_by_inverse_packed(int64_t m, const double *__restrict__ x,
+                                        const double *__restrict__ d, double *__restrict__ y,
+                                        const LzState *__restrict__ st,
+                                        const double *__restrict__ hw, Real *__restrict__ src) {
+  if (st->reason != 0) return;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double s = d[0];
+  const double v = s > 0.0 ? x[i] / s : 0.0;
+  y[i] = v;
+  const int64_t n = m / 3, sp = i / 3;
+  src[(i - 3 * sp) * n + sp] = Real(hw[sp] * v);
+}
+
 
 
 
@@ -615,14 +632,15 @@ __global__ void lz_reset(LzState *st) {
   }
 }
 
-// ---- one Lanczos iteration of a single system in seven kernels (segments > kFusedSegment) ----
+// ---- one Lanczos iteration of a single system in six kernels (segments > kFusedSegment) ----
 //
 // Sums in two stages, kRedBlocks workgroup partials and their sum in a fixed order by one
 // workgroup (a last-arriving workgroup could take the second stage, but its device-scope
 // release fence writes back its XCD's L2 and cost more than the launch it saved).  The
-// three-term recurrence is applied where its result is read, and the second stage of |u|
-// shares its workgroup with the eigensolve.  The arithmetic and its order are those of one
-// kernel per step.
+// three-term recurrence is applied where its result is read; alpha's second stage is taken by
+// every workgroup of the re-orthogonalisation dots (the same sum in each), and the second
+// stage of |u| shares its workgroup with the eigensolve.  The arithmetic and its order are
+// those of one kernel per step.
 
 __global__ __launch_bounds__(kThreads) void dot_partial(int64_t m, const double *__restrict__ a,
                                                         const double *__restrict__ b,
@@ -647,16 +665,22 @@ __global__ __launch_bounds__(kThreads) void dot_finish(const double *__restrict_
 }
 
 // part[j * gridDim.x + b] = partial of V_j . (u - alpha_k v_k - beta_{k-1} v_{k-1}) over
-// workgroup b's share (grid y: j < k); u is not modified.
+// workgroup b's share (grid y: j < k); u is not modified.  alpha_k is the sum of the np
+// partials of v_k . u in apart, which every workgroup forms as dot_finish would (the same
+// value in each), and the first workgroup stores (alpha_out).
 __global__ __launch_bounds__(kThreads) void reorth_dots_3t(
     int64_t m, const double *__restrict__ V, const double *__restrict__ u,
     const double *__restrict__ vk, const double *__restrict__ vprev,
-    const double *__restrict__ alpha, const double *__restrict__ beta,
-    double *__restrict__ part) {
+    const double *__restrict__ apart, int np, double *__restrict__ alpha_out,
+    const double *__restrict__ beta, double *__restrict__ part) {
   __shared__ double sh[kThreads];
+  double a0 = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) a0 += apart[i];
+  const double al = block_sum(a0, sh);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) alpha_out[0] = al;
   const int j = blockIdx.y;
   const double *vj = V + int64_t(j) * m;
-  const double al = alpha[0], be = vprev ? beta[0] : 0.0;
+  const double be = vprev ? beta[0] : 0.0;
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < m;
        i += int64_t(gridDim.x) * kThreads) {
@@ -1216,7 +1240,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   double *u = static_cast<double *>(workspace(ctx, WS_VEC_A, size_t(m3) * sizeof(double), &st));
   if (!u) return st;
   double *part = static_cast<double *>(
-      workspace(ctx, WS_REDUCE, size_t(kRedBlocks) * kMaxKrylov * sizeof(double), &st));
+      workspace(ctx, WS_REDUCE, size_t(kRedBlocks) * (kMaxKrylov + 1) * sizeof(double), &st));
   if (!part) return st;
   LzState *ls = static_cast<LzState *>(workspace(ctx, WS_SMALL, kSmallBytes, &st));
   if (!ls) return st;
@@ -1235,8 +1259,9 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   LzRing *ring = lz_ring(ctx);
   LzRing *ring_dev = lz_ring_dev(ctx);
   const bool fused = m3 <= kFusedSegment;
-  // small systems without the preconditioner: lanczos_vec packs v_{k+1} for the next product
-  const bool prepack = fused && !precond;
+  // without the preconditioner the kernel that forms v_{k+1} also packs it for the next product
+  // (lanczos_vec, or scale_by_inverse_packed for larger systems)
+  const bool prepack = !precond;
   void *src = nullptr;
   if (prepack) {
     src = source_buffer(ctx, g, &st);
@@ -1293,10 +1318,13 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
         lanczos_eig<<<1, kThreads, 0, es>>>(ls, eig, k, tol, &ring_dev->slot[slot]);
         RPB_LAUNCHED(ctx);
         RPB_TRY(lz_ring_post(ctx, slot, es));
-      } else {   // seven kernels (see dot_partial)
-        RPB_TRY(dot(ctx, m3, vm, u, part, &ls->alpha[k - 1], 0, stream));
+      } else {   // six kernels (see dot_partial)
+        double *apart = part + int64_t(kRedBlocks) * kMaxKrylov;   // partials of v_k . u
+        dot_partial<<<kRedBlocks, kThreads, 0, stream>>>(m3, vm, u, apart);
+        RPB_LAUNCHED(ctx);
         const dim3 grid{unsigned(kRedBlocks), unsigned(k), 1u};
-        reorth_dots_3t<<<grid, kThreads, 0, stream>>>(m3, V, u, vm, vprev, &ls->alpha[k - 1],
+        reorth_dots_3t<<<grid, kThreads, 0, stream>>>(m3, V, u, vm, vprev, apart, kRedBlocks,
+                                                       &ls->alpha[k - 1],
                                                        k > 1 ? &ls->beta[k - 2] : nullptr, part);
         RPB_LAUNCHED(ctx);
         reorth_finish<<<unsigned(k), kThreads, 0, stream>>>(kRedBlocks, part, ls->h);
@@ -1307,8 +1335,16 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
                                              &ring_dev->slot[slot]);
         RPB_LAUNCHED(ctx);
         if (k < max_iter) {
-          scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1],
-                                                               V + int64_t(k) * m3, ls);
+          double *next = V + int64_t(k) * m3;
+          if (!prepack)
+            scale_by_inverse<<<nblk(m3), kThreads, 0, stream>>>(m3, u, &ls->beta[k - 1], next,
+                                                                 ls);
+          else if (f64)
+            scale_by_inverse_packed<double><<<nblk(m3), kThreads, 0, stream>>>(
+                m3, u, &ls->beta[k - 1], next, ls, hw, static_cast<double *>(src));
+          else
+            scale_by_inverse_packed<float><<<nblk(m3), kThreads, 0, stream>>>(
+                m3, u, &ls->beta[k - 1], next, ls, hw, static_cast<float *>(src));
           RPB_LAUNCHED(ctx);
         }
         RPB_TRY(lz_ring_post(ctx, slot, stream));
