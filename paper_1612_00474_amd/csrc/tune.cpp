@@ -119,6 +119,9 @@ int rpb_autotune(rpb_ctx *ctx, const rpb_params *p, int32_t nsys, const int64_t 
     Shape best = base;
     std::vector<Shape> cands;
     for (int tpt : {1, 2}) {
+      // a system within one tile of 256 targets (one per lane of a 256-lane workgroup): two
+      // targets per lane would leave half of each lane's targets empty
+      if (!batched && tpt == 2 && n <= 256) continue;
       if (batched) {
         for (int wgs : {1024, 2048, 4096}) {
           Shape c = base;
