@@ -240,3 +240,18 @@ def test_not_spd_is_reported(precision, tol):
         assert "negative Ritz value" in c.last_error()
     finally:
         c.close()
+
+
+def test_small_and_large_solves_alternate(ctx, c1, multi_tile):
+    # A 256-sphere solve runs its eigensolve on the context's second stream and a 1,100-sphere
+    # solve runs it in line; alternating the two on one context reproduces each bitwise (the
+    # status ring's slots and the streams' ordering carry nothing from one solve to the next).
+    import torch
+    inp, _ = c1
+    pos_l, _, w_l = multi_tile
+    cases = [(dev(inp["pos"]), dev(inp["w"])), (dev(pos_l), dev(w_l))]
+    first = [ctx.lanczos(P, W, 1e-5, allow_noconv=True) for P, W in cases]
+    for _ in range(3):
+        for (P, W), (g0, it0, eps0, _) in zip(cases, first):
+            g, it, eps, _ = ctx.lanczos(P, W, 1e-5, allow_noconv=True)
+            assert it == it0 and eps == eps0 and torch.equal(g, g0)
