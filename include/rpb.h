@@ -19,7 +19,9 @@
  *    The single-system Lanczos solves of small systems (3 n <= 1536) run their
  *    eigensolve on a second stream owned by the context, beside the next product; before
  *    returning they make `stream` wait for all of it, so work enqueued later on `stream`
- *    is ordered after the whole solve.
+ *    is ordered after the whole solve.  That stream's work is enqueued by a helper thread
+ *    that the context starts on the first such solve and rpb_destroy() stops; it makes HIP
+ *    calls on the context's device only while a solve is in progress.
  *  - Return value: RPB_OK (0) or a negative rpb_status.  rpb_last_error() then holds
  *    a message.  No C++ exception crosses this interface.
  *  - n == 0 is a no-op that returns RPB_OK.  RPB_EINVAL for n < 0, a NULL required

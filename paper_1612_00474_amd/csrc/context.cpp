@@ -184,6 +184,7 @@ int rpb_create(int hip_device, rpb_ctx **out) {
 
 void rpb_destroy(rpb_ctx *ctx) {
   if (!ctx) return;
+  lz_helper_destroy(ctx);
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (auto &b : ctx->ws)

@@ -15,7 +15,11 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <condition_variable>
 #include <cstddef>
+#include <deque>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "rpb_internal.h"
@@ -1221,6 +1225,134 @@ int dot(rpb_ctx *ctx, int64_t m, const double *a, const double *b, double *part,
 
 }  // namespace
 
+// One eigensolve of the second stream: wait for iteration k's vector work (event
+// lz_vec_ev[slot]), the eigensolve and stop test (lanczos_eig), then the status event of ring
+// slot `slot` (lz_ev[slot]).
+struct LzJob {
+  void *ls;          // LzState
+  void *eig;         // LzEig
+  void *ring_slot;   // LzRingSlot, device address
+  int k;
+  double tol;
+  int slot;
+};
+
+// The second stream's host calls of the small-system solves, issued by a thread of its own:
+// a cross-stream wait, a launch and an event record take ~15 us of host time per iteration,
+// which the calling thread spends on the next iteration's launches instead (the two threads'
+// calls overlap).  Jobs are issued in the order they are queued; `posted` counts those whose
+// calls have been issued (their status event then exists).
+struct LzHelper {
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv_job, cv_done;
+  std::deque<LzJob> jobs;
+  int64_t pushed = 0, posted = 0;
+  bool stop = false;
+  hipError_t err = hipSuccess;   // the first failed call, reported to the caller by lz_helper_wait
+  const char *what = nullptr;
+};
+
+namespace {
+
+void lz_helper_run(rpb_ctx *ctx, LzHelper *h) {
+  (void)hipSetDevice(ctx->device);
+  for (;;) {
+    LzJob j;
+    {
+      std::unique_lock<std::mutex> lk(h->mu);
+      h->cv_job.wait(lk, [&] { return h->stop || !h->jobs.empty(); });
+      if (h->jobs.empty()) return;   // stopped with nothing left to issue
+      j = h->jobs.front();
+      h->jobs.pop_front();
+    }
+    const char *what = "hipStreamWaitEvent";
+    hipError_t e = hipStreamWaitEvent(ctx->lz_stream, ctx->lz_vec_ev[j.slot], 0);
+    if (e == hipSuccess) {
+      lanczos_eig<<<1, kThreads, 0, ctx->lz_stream>>>(static_cast<LzState *>(j.ls),
+                                                      static_cast<LzEig *>(j.eig), j.k, j.tol,
+                                                      static_cast<LzRingSlot *>(j.ring_slot));
+      e = hipGetLastError();
+      what = "lanczos_eig launch";
+    }
+    if (e == hipSuccess) {
+      e = hipEventRecord(ctx->lz_ev[j.slot], ctx->lz_stream);
+      what = "hipEventRecord";
+    }
+    {
+      std::lock_guard<std::mutex> lk(h->mu);
+      if (e != hipSuccess && h->err == hipSuccess) {
+        h->err = e;
+        h->what = what;
+      }
+      ++h->posted;
+    }
+    h->cv_done.notify_all();
+  }
+}
+
+// The context's helper, started on first use (with the ring's status events).
+int lz_helper_get(rpb_ctx *ctx, LzHelper **out) {
+  if (!ctx->lz_helper) {
+    for (auto &e : ctx->lz_ev)
+      if (!e) RPB_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    LzHelper *h = new (std::nothrow) LzHelper();
+    if (!h) return fail(ctx, RPB_ENOMEM, "no memory for the Lanczos helper");
+    try {
+      h->th = std::thread(lz_helper_run, ctx, h);
+    } catch (...) {
+      delete h;
+      return fail(ctx, RPB_EDEVICE, "could not start the Lanczos helper thread");
+    }
+    ctx->lz_helper = h;
+  }
+  *out = ctx->lz_helper;
+  return RPB_OK;
+}
+
+// Queues a job; returns its sequence number.
+int64_t lz_helper_push(LzHelper *h, const LzJob &j) {
+  int64_t seq;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->jobs.push_back(j);
+    seq = ++h->pushed;
+  }
+  h->cv_job.notify_one();
+  return seq;
+}
+
+// Blocks until the jobs up to sequence number `seq` are issued; reports a failed call.
+int lz_helper_wait(rpb_ctx *ctx, LzHelper *h, int64_t seq) {
+  hipError_t e;
+  const char *what;
+  {
+    std::unique_lock<std::mutex> lk(h->mu);
+    h->cv_done.wait(lk, [&] { return h->posted >= seq; });
+    e = h->err;
+    what = h->what;
+    h->err = hipSuccess;
+  }
+  if (e != hipSuccess)
+    return fail(ctx, RPB_EDEVICE, "%s failed: %s (Lanczos helper)", what, hipGetErrorString(e));
+  return RPB_OK;
+}
+
+}  // namespace
+
+void lz_helper_destroy(rpb_ctx *ctx) {
+  LzHelper *h = ctx->lz_helper;
+  if (!h) return;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->stop = true;
+  }
+  h->cv_job.notify_all();
+  if (h->th.joinable()) h->th.join();
+  delete h;
+  ctx->lz_helper = nullptr;
+}
+
 int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double *w, double tol,
                 int max_iter, bool precond, double *out, int *iters, double *eps_out,
                 hipStream_t stream, const double *mw) {
@@ -1270,6 +1402,10 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
   const double *hw = prepack ? packed_weights(g) : nullptr;
   const bool f64 = g.precision == RPB_FP64;
   hipStream_t es = ctx->lz_stream;
+  LzHelper *helper = nullptr;   // issues the second stream's calls (small systems)
+  if (fused) RPB_TRY(lz_helper_get(ctx, &helper));
+  int64_t seq[kLzRing] = {};    // helper job of the iteration in each ring slot
+  int64_t last_seq = 0;
   const int lag = fused ? 2 : 1;
   const int *stopped = fused ? &ls->halt : &ls->reason;
 
@@ -1314,10 +1450,9 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
               ls, V, u, m3, k, k < max_iter, hw, static_cast<float *>(src));
         RPB_LAUNCHED(ctx);
         RPB_HIP(ctx, hipEventRecord(ctx->lz_vec_ev[slot], stream));
-        RPB_HIP(ctx, hipStreamWaitEvent(es, ctx->lz_vec_ev[slot], 0));
-        lanczos_eig<<<1, kThreads, 0, es>>>(ls, eig, k, tol, &ring_dev->slot[slot]);
-        RPB_LAUNCHED(ctx);
-        RPB_TRY(lz_ring_post(ctx, slot, es));
+        ctx->lz_live[slot] = true;   // the helper records lz_ev[slot] after its eigensolve
+        seq[slot] = last_seq =
+            lz_helper_push(helper, LzJob{ls, eig, &ring_dev->slot[slot], k, tol, slot});
       } else {   // six kernels (see dot_partial)
         double *apart = part + int64_t(kRedBlocks) * kMaxKrylov;   // partials of v_k . u
         dot_partial<<<kRedBlocks, kThreads, 0, stream>>>(m3, vm, u, apart);
@@ -1353,6 +1488,7 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
       const int qmax = k < max_iter ? k - lag : k;
       for (; next_q <= qmax; ++next_q) {
         const int q = next_q;
+        if (fused) RPB_TRY(lz_helper_wait(ctx, helper, seq[q % kLzRing]));
         RPB_TRY(lz_ring_wait(ctx, q % kLzRing));
         m = q;
         reason = ring->slot[q % kLzRing].reason;
@@ -1368,8 +1504,10 @@ int lanczos_run(rpb_ctx *ctx, const rpb_params *p, const Packed &g, const double
     }
     return RPB_OK;
   };
-  const int status = iterate();
+  int status = iterate();
   if (fused) {   // the second stream's work, all of it, before anything later on `stream`
+    const int hs = lz_helper_wait(ctx, helper, last_seq);
+    if (status == RPB_OK) status = hs;
     RPB_HIP(ctx, hipEventRecord(ctx->lz_join_ev, es));
     RPB_HIP(ctx, hipStreamWaitEvent(stream, ctx->lz_join_ev, 0));
   }

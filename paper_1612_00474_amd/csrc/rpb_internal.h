@@ -48,6 +48,11 @@ enum Slot {
 // Slots of the Lanczos status ring: iterations whose status may be in flight at once.
 constexpr int kLzRing = 4;
 
+// The host thread that issues the second stream's work of small-system Lanczos solves
+// (lanczos.hip); created on first use, stopped by lz_helper_destroy.
+struct LzHelper;
+void lz_helper_destroy(rpb_ctx *ctx);
+
 // Default limit of the partial sums of one launch of the symmetric tile-pair kernels.
 constexpr size_t kMaxChunkBytes = size_t(512) << 20;
 
@@ -109,6 +114,7 @@ struct rpb_ctx {
   hipStream_t lz_stream = nullptr;
   hipEvent_t lz_vec_ev[rpb::kLzRing] = {};
   hipEvent_t lz_join_ev = nullptr;
+  rpb::LzHelper *lz_helper = nullptr;   // issues the second stream's calls from its own thread
   // deferred position check (check_finite_begin / _end): its flag's copy and event
   hipEvent_t fin_ev = nullptr;
   bool fin_live = false;
