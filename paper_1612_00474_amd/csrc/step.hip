@@ -221,10 +221,13 @@ extern "C" int sab_step(rpb_ctx *ctx, const rpb_params *p, const rpb_sab_config 
   RPB_TRY(pack_geometry(ctx, p, n, state->pos, WS_GEOM, &geo, stream));
   // M F + M_C T, the first Lanczos product M W and, for the one-sided RFD in the step's own
   // precision, its product M W~ at q share the configuration: one launch evaluates each pair's
-  // coefficients once for all of them
+  // coefficients once for all of them.  That launch takes one workgroup per pair of 256-sphere
+  // tiles; a system of a few tiles leaves most of the device idle, so there the products run
+  // apart, each split over enough workgroups.
+  constexpr int64_t kJointMinN = 4 * 256;
   double *mw = nullptr, *mwt = nullptr;
   const bool one_sided = cfg->rfd_scheme == 1;
-  if (cfg->lanczos_precond == 0 && matvec_first_supported(p, n)) {
+  if (cfg->lanczos_precond == 0 && n > kJointMinN && matvec_first_supported(p, n)) {
     mw = static_cast<double *>(workspace(ctx, WS_VEC_B, nb, &st));
     if (!mw) return st;
     if (one_sided && cfg->rfd_precision == p->precision) {
